@@ -1,0 +1,189 @@
+/*
+ * pwdf.h -- C ABI of libpwdf: the long-range (reciprocal-space) Coulomb matrix
+ * of a periodic Gaussian basis by integral-direct planewave density fitting,
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Dinh, Rettig, Feng, Lee, "Efficient All-Electron Periodic
+ * Fourier-Transformed Coulomb Method", arXiv 2509.16460, section "Long-range
+ * contributions" (eq. "AFT for pair density" and the three-step contraction
+ * order that follows it), eq. "Ewald J" (second term), eq. "FT for D" and
+ * eq. "FT of J".  For every screened primitive pair (a in cell 0, b in cell L)
+ * the analytic Fourier transform F_abL(G) of the Gaussian product is formed on
+ * the fly and contracted with the real-space density:
+ *
+ *   D(L)     = sum_k w_k e^{ik.L} D(k)                       (w_k = 1/Nk)
+ *   rho(G)   = (1/Omega) sum_{(a,b,L)} D_ab(L) F_abL(G)
+ *   v(G)     = 4 pi exp(-|G|^2 / 4 omega^2) / |G|^2,  G != 0
+ *   J_ab(L)  = sum_G v(G) rho(-G) F_abL(G)
+ *   J(k)     = sum_L e^{ik.L} J(L)
+ *   E_J      = 1/2 Omega sum_G v(G) |rho(G)|^2 = 1/2 sum_k w_k sum D(k) J(k)
+ *
+ * G runs over {G = B n : 0 < |G| <= 2 omega sqrt(-ln eps_G)}, B = 2 pi A^-T
+ * (appendix "Cartesian coordinates and relative coordinates"); pairs are kept
+ * when the Gaussian-product prefactor exp(-a_a a_b/(a_a+a_b) |A-B-L|^2) is at
+ * least eps_pair (and |A-B-L| <= r_max when r_max > 0).
+ *
+ * Conventions
+ *   lattice   3x3 row-major, rows a1, a2, a3 (Bohr).  Omega = |det|.
+ *   basis     Cartesian shells, l <= 3; components in descending lexicographic
+ *             (lx,ly,lz) order; each primitive carries
+ *             N(l,a) = (2a/pi)^{3/4} (4a)^{l/2} / sqrt((2l-1)!!) times its
+ *             contraction coefficient.  nbf = sum over shells of (l+1)(l+2)/2.
+ *   k-mesh    Gamma-centred: k = sum_i (m_i/n_i) b_i, m_i = 0..n_i-1, index
+ *             (m1*n2 + m2)*n3 + m3.
+ *   D(k),J(k) complex128 interleaved (re, im), [ndm][nk][nbf][nbf] row-major;
+ *             D(L) pairs phi_mu in cell 0 with phi_nu in cell L.  Each D(k)
+ *             must be Hermitian; the result depends only on its Hermitian
+ *             part, and J(k) is Hermitian.
+ *
+ * Ownership and streams
+ *   The caller owns every input and output buffer; the library never frees or
+ *   retains them.  The library owns the context (plan and device workspaces),
+ *   allocated in pwdf_create; pwdf_build_j and pwdf_grad do not allocate.
+ *   Device calls only enqueue work on the given HIP stream (NULL: the null
+ *   stream); results are valid after the stream is synchronised.  One context
+ *   must not be used by two streams at once; distinct contexts are independent.
+ *
+ * Errors
+ *   Every call returns a pwdf_status; nothing aborts.  Arguments are validated
+ *   on the host before anything is enqueued; on failure nothing is enqueued and
+ *   pwdf_last_error(ctx) describes the problem (pwdf_last_error(NULL) reports
+ *   the last failed pwdf_create of the calling thread).  HIP runtime failures
+ *   map to PWDF_EDEVICE with the HIP error string.
+ */
+#ifndef PWDF_H
+#define PWDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pwdf_ctx pwdf_ctx;
+
+typedef enum {
+  PWDF_OK = 0,
+  PWDF_EINVAL = -1,       /* bad argument, shape or geometry */
+  PWDF_ENOMEM = -2,       /* host or device allocation failed */
+  PWDF_EDEVICE = -3,      /* HIP runtime error */
+  PWDF_EUNSUPPORTED = -4, /* l > 3, ndm > max_ndm, unsupported precision */
+  PWDF_ENONFINITE = -5,   /* non-finite input */
+  PWDF_ESTATE = -6        /* call out of order (e.g. gradient before any plan) */
+} pwdf_status;
+
+typedef enum {
+  PWDF_FP64 = 0,      /* every step in FP64 */
+  PWDF_FP32_MFMA = 1  /* pair-G tiles generated in FP32, contracted on FP32 MFMA,
+                         FP64 accumulation across pairs; phase sums, E-coefficient
+                         transforms and the energy stay FP64 */
+} pwdf_precision;
+
+typedef struct {
+  double eps_pair; /* pair screening on exp(-a_a a_b/p |A-B-L|^2); e.g. 1e-12 */
+  double eps_G;    /* G cutoff |G| <= 2 omega sqrt(-ln eps_G); e.g. 1e-12 */
+  double r_max;    /* centre-distance cap |A-B-L| <= r_max (Bohr); <= 0: off */
+} pwdf_screen;
+
+typedef struct {
+  int64_t npairs_by_class[16]; /* unique primitive pairs per (la,lb), index la*4+lb (la >= lb) */
+  int64_t nG;       /* |G set| (both G and -G); the kernels walk nG/2 of them */
+  int64_t npairs;   /* unique primitive pairs (a,b,L) ~ (b,a,-L) counted once */
+  int64_t nbf, nk, nimg, nblocks, nseg;
+  double pairG_evals; /* per build and density: 2 passes x npairs x nG/2 */
+  double t_us[8];     /* reserved */
+} pwdf_stats;
+
+/*
+ * Build the plan for one geometry: reciprocal lattice, G set (walked as lines
+ * in relative coordinates), screened unique primitive pairs sorted by class,
+ * phase tables, and every device workspace for up to max_ndm densities per
+ * call.  Passage: section "Long-range contributions" and section "Integral
+ * screening" (pair list), appendix "Cartesian coordinates and relative
+ * coordinates" (B, relative coordinates).
+ *   lattice[9]     host, row-major rows a1,a2,a3; det must be nonzero.
+ *   natm, xyz      host, natm x 3 Bohr; used as given (no wrapping).
+ *   nshell         number of shells; shell_atom/shell_l/shell_nprim host [nshell];
+ *                  0 <= shell_l <= 3; shell_nprim >= 1.
+ *   exps, coefs    host, sum(shell_nprim) primitives in shell order; exps > 0.
+ *   kmesh[3]       host, each >= 1.
+ *   omega          range-separation parameter > 0 (Bohr^-1).
+ *   screen         host; eps_pair, eps_G in (0, 1).
+ *   prec           PWDF_FP64 or PWDF_FP32_MFMA.
+ *   max_ndm        largest ndm accepted by later calls (>= 1).
+ *   device         HIP device ordinal.
+ * On success *out is a new context (free with pwdf_destroy).
+ */
+pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const double *xyz,
+                        int nshell, const int *shell_atom, const int *shell_l,
+                        const int *shell_nprim, const double *exps, const double *coefs,
+                        const int kmesh[3], double omega, const pwdf_screen *screen,
+                        pwdf_precision prec, int max_ndm, int device);
+
+/* Sizes and counts of the plan (host struct, filled). */
+pwdf_status pwdf_query(const pwdf_ctx *ctx, pwdf_stats *out);
+
+/* Host-only plan: validates the same arguments as pwdf_create, builds the G set
+ * and the unique screened pair list on the host (no device is touched) and
+ * fills *out.  Section "Integral screening" (pair list).  Errors as for
+ * pwdf_create; the message is read with pwdf_last_error(NULL). */
+pwdf_status pwdf_plan_stats(const double lattice[9], int natm, const double *xyz, int nshell,
+                            const int *shell_atom, const int *shell_l, const int *shell_nprim,
+                            const double *exps, const double *coefs, const int kmesh[3], double omega,
+                            const pwdf_screen *screen, pwdf_stats *out);
+
+/*
+ * Long-range J for ndm densities: D(k) -> D(L) on the pair support (eq. "FT for
+ * D"), per-pair density transform (algorithm "density matrix transformation"),
+ * rho(G) (algorithm "non-ortho rho eval"), V(G) and E_J, J from V (algorithm
+ * "non-ortho J eval"), back transform (algorithm "J matrix transformation")
+ * and J(L) -> J(k) (eq. "FT of J").
+ *   ndm   1 <= ndm <= max_ndm.
+ *   Dk    device, complex128 [ndm][nk][nbf][nbf], Hermitian per k; read only.
+ *   Jk    device, same layout; fully written (zeros off the pair support).
+ *   EJ    device, double [ndm]; written with E_J of each density.
+ *   stream  hipStream_t or NULL.
+ * Dk and Jk must not overlap.  Enqueue only.
+ */
+pwdf_status pwdf_build_j(pwdf_ctx *ctx, int ndm, const double *Dk, double *Jk, double *EJ,
+                         void *stream);
+
+/*
+ * rho(G) of the last computation path for diagnostics: runs the D(k) -> rho(G)
+ * part of pwdf_build_j for ndm densities and writes, for the nG/2 vectors of
+ * the half space the kernels walk (rho(-G) = conj rho(G)),
+ *   rhoG    device, complex128 [ndm][nG/2]
+ *   miller  host, int [nG/2][3] Miller indices n (G = B n) in the same order
+ *           (may be NULL).
+ * Synchronises the stream before returning (miller is filled on the host).
+ */
+pwdf_status pwdf_get_rhoG(pwdf_ctx *ctx, int ndm, const double *Dk, double *rhoG, int *miller,
+                          void *stream);
+
+/*
+ * Nuclear gradient dE_J/dR_A at fixed D(k), fixed pair list and fixed G set
+ * (derivative of the pair transform with respect to the Gaussian centres,
+ * eq. "cart gaussian function" and eq. "FT of cart Gaussians").
+ *   Dk    device, as in pwdf_build_j.
+ *   dEdR  device, double [ndm][natm][3], written.
+ *   EJ    device, double [ndm] or NULL; written with E_J when not NULL.
+ * The geometry is the one given to pwdf_create.
+ */
+pwdf_status pwdf_grad(pwdf_ctx *ctx, int ndm, const double *Dk, double *dEdR, double *EJ,
+                      void *stream);
+
+/* Pick launch shapes per class (segment length, chunking) by timing candidate
+ * shapes on the device; must run before any graph capture of pwdf_build_j.
+ * cache_path may be NULL (no persistence).  Synchronous. */
+pwdf_status pwdf_autotune(pwdf_ctx *ctx, int ndm, const char *cache_path);
+
+/* Message of the last failure on ctx (NULL: last failed pwdf_create of this thread). */
+const char *pwdf_last_error(const pwdf_ctx *ctx);
+
+/* Free the plan and all device workspaces; NULL is a no-op. */
+void pwdf_destroy(pwdf_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PWDF_H */

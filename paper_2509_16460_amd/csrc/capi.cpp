@@ -1,0 +1,415 @@
+// C ABI of libpwdf (declarations and contract: include/pwdf.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pwdf.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace pwdf;
+
+struct pwdf_ctx {
+  Plan plan;
+  Dev dev;
+  std::vector<void *> owned;  // device allocations
+  double *Escr = nullptr;     // [max_ndm] energies of diagnostic calls
+  std::string err;
+  int device = 0;
+  int max_ndm = 1;
+  pwdf_precision prec = PWDF_FP64;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+pwdf_status fail(pwdf_ctx *c, pwdf_status s, const std::string &m) {
+  if (c)
+    c->err = m;
+  else
+    g_create_err = m;
+  return s;
+}
+
+pwdf_status hip_fail(pwdf_ctx *c, hipError_t e, const char *where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(c, PWDF_EDEVICE, m);
+}
+
+template <class T>
+hipError_t upload(pwdf_ctx *c, const std::vector<T> &v, const T **out) {
+  void *p = nullptr;
+  size_t n = std::max<size_t>(1, v.size()) * sizeof(T);
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) return e;
+  c->owned.push_back(p);
+  if (!v.empty()) {
+    e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+  }
+  *out = (const T *)p;
+  return hipSuccess;
+}
+
+template <class T>
+hipError_t alloc(pwdf_ctx *c, size_t count, T **out) {
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(1, count) * sizeof(T));
+  if (e != hipSuccess) return e;
+  c->owned.push_back(p);
+  *out = (T *)p;
+  return hipSuccess;
+}
+
+void free_device(pwdf_ctx *c) {
+  for (void *p : c->owned) (void)hipFree(p);
+  c->owned.clear();
+}
+
+// Launch shapes: spread each pass over about `target` waves in proportion to
+// the class's pair-G work.
+void choose_shapes(const Plan &p, Dev &d, int target_waves) {
+  const int SEG = p.seg_len;
+  d.rho_bs = 64 * std::min(4, std::max(1, (p.nseg() + 63) / 64));
+  double wsum = 0.0, wL[kMaxLsum + 1];
+  for (int L = 0; L <= kMaxLsum; ++L) {
+    int np = p.L_p1[L] - p.L_p0[L];
+    wL[L] = np > 0 ? (double)np * (2.0 * L + 10.0 + (70.0 + nherm(L)) / SEG) : 0.0;
+    wsum += wL[L];
+  }
+  const int rho_waves_per_chunk = ((p.nseg() + d.rho_bs - 1) / d.rho_bs) * (d.rho_bs / 64);
+  int rows = 0;
+  int64_t yoff = 0;
+  for (int L = 0; L <= kMaxLsum; ++L) {
+    int np = p.L_p1[L] - p.L_p0[L];
+    d.rho_row0[L] = rows;
+    d.yhat_off[L] = yoff;
+    if (np <= 0) {
+      d.rho_chunks[L] = 0;
+      d.rho_ppc[L] = 1;
+      d.j_chunks[L] = 0;
+      d.j_spc[L] = 1;
+      continue;
+    }
+    double share = wL[L] / wsum;
+    int ch = (int)std::lround(target_waves * share / rho_waves_per_chunk);
+    ch = std::max(1, std::min(np, ch));
+    int ppc = (np + ch - 1) / ch;
+    ch = (np + ppc - 1) / ppc;
+    d.rho_chunks[L] = ch;
+    d.rho_ppc[L] = ppc;
+    rows += ch;
+    int jw = ((np + 255) / 256) * 4;
+    int jc = (int)std::lround(target_waves * share / jw);
+    jc = std::max(1, std::min(p.nseg(), jc));
+    int spc = (p.nseg() + jc - 1) / jc;
+    jc = (p.nseg() + spc - 1) / spc;
+    d.j_chunks[L] = jc;
+    d.j_spc[L] = spc;
+    yoff += (int64_t)jc * nherm(L) * np;
+  }
+  d.nrows = std::max(1, rows);
+  d.yhat_size = std::max<int64_t>(1, yoff);
+  d.nred_blocks = (p.nslot() + 255) / 256;
+}
+
+pwdf_status validate_ndm(pwdf_ctx *c, int ndm) {
+  if (ndm < 1) return fail(c, PWDF_EINVAL, "ndm must be >= 1");
+  if (ndm > c->max_ndm) return fail(c, PWDF_EUNSUPPORTED, "ndm exceeds max_ndm given to pwdf_create");
+  return PWDF_OK;
+}
+
+pwdf_status run_to_rho(pwdf_ctx *c, int ndm, const double *Dk, double *EJ, hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_phase_d(c->dev, Dk, ndm, st)) != hipSuccess) return hip_fail(c, e, "phase D");
+  if ((e = launch_transform(c->dev, ndm, st)) != hipSuccess) return hip_fail(c, e, "density transform");
+  if ((e = launch_rho(c->dev, ndm, st)) != hipSuccess) return hip_fail(c, e, "rho");
+  if ((e = launch_reduce(c->dev, ndm, EJ, st)) != hipSuccess) return hip_fail(c, e, "reduce");
+  return PWDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Argument checks shared by pwdf_create and pwdf_plan_stats; fills `in`.
+static pwdf_status make_input(PlanInput &in, const double lattice[9], int natm, const double *xyz, int nshell,
+                              const int *shell_atom, const int *shell_l, const int *shell_nprim,
+                              const double *exps, const double *coefs, const int kmesh[3], double omega,
+                              const pwdf_screen *screen) {
+  if (!lattice || !xyz || !shell_atom || !shell_l || !shell_nprim || !exps || !coefs || !kmesh || !screen)
+    return fail(nullptr, PWDF_EINVAL, "NULL input pointer");
+  if (natm < 1 || nshell < 1) return fail(nullptr, PWDF_EINVAL, "natm and nshell must be >= 1");
+  for (int s = 0; s < nshell; ++s)
+    if (shell_l[s] < 0 || shell_l[s] > kMaxL) return fail(nullptr, PWDF_EUNSUPPORTED, "shell l outside 0..3");
+  std::memcpy(in.lattice, lattice, sizeof(in.lattice));
+  in.natm = natm;
+  in.xyz.assign(xyz, xyz + 3 * natm);
+  in.nshell = nshell;
+  in.sh_atom.assign(shell_atom, shell_atom + nshell);
+  in.sh_l.assign(shell_l, shell_l + nshell);
+  in.sh_nprim.assign(shell_nprim, shell_nprim + nshell);
+  int nprim = 0;
+  for (int s = 0; s < nshell; ++s) {
+    if (shell_nprim[s] < 1) return fail(nullptr, PWDF_EINVAL, "shell_nprim must be >= 1");
+    nprim += shell_nprim[s];
+  }
+  in.exps.assign(exps, exps + nprim);
+  in.coefs.assign(coefs, coefs + nprim);
+  for (int i = 0; i < 3; ++i) in.kmesh[i] = kmesh[i];
+  in.omega = omega;
+  in.eps_pair = screen->eps_pair;
+  in.eps_G = screen->eps_G;
+  in.r_max = screen->r_max;
+  return PWDF_OK;
+}
+
+static void fill_stats(const Plan &p, pwdf_stats *out) {
+  std::memset(out, 0, sizeof(*out));
+  for (int cl = 0; cl < 16; ++cl) {
+    int b0 = p.cls_b0[cl], b1 = p.cls_b1[cl];
+    if (b1 > b0) out->npairs_by_class[cl] = p.blocks[b1 - 1].p1 - p.blocks[b0].p0;
+  }
+  out->nG = p.nG_full;
+  out->npairs = p.npairs();
+  out->nbf = p.nbf;
+  out->nk = p.nk;
+  out->nimg = p.nimg();
+  out->nblocks = (int64_t)p.blocks.size();
+  out->nseg = p.nseg();
+  out->pairG_evals = 2.0 * (double)p.npairs() * (double)(p.nG_full / 2);
+}
+
+pwdf_status pwdf_plan_stats(const double lattice[9], int natm, const double *xyz, int nshell, const int *shell_atom,
+                            const int *shell_l, const int *shell_nprim, const double *exps, const double *coefs,
+                            const int kmesh[3], double omega, const pwdf_screen *screen, pwdf_stats *out) {
+  if (!out) return fail(nullptr, PWDF_EINVAL, "out is NULL");
+  PlanInput in;
+  pwdf_status s = make_input(in, lattice, natm, xyz, nshell, shell_atom, shell_l, shell_nprim, exps, coefs, kmesh,
+                             omega, screen);
+  if (s != PWDF_OK) return s;
+  Plan p;
+  std::string why;
+  try {
+    why = build_plan(in, 8, p);
+  } catch (const std::bad_alloc &) {
+    return fail(nullptr, PWDF_ENOMEM, "host allocation failed while building the plan");
+  }
+  if (!why.empty()) return fail(nullptr, PWDF_EINVAL, why);
+  fill_stats(p, out);
+  return PWDF_OK;
+}
+
+pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const double *xyz, int nshell,
+                        const int *shell_atom, const int *shell_l, const int *shell_nprim, const double *exps,
+                        const double *coefs, const int kmesh[3], double omega, const pwdf_screen *screen,
+                        pwdf_precision prec, int max_ndm, int device) {
+  if (!out) return fail(nullptr, PWDF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_ndm < 1) return fail(nullptr, PWDF_EINVAL, "max_ndm must be >= 1");
+  if (prec != PWDF_FP64 && prec != PWDF_FP32_MFMA) return fail(nullptr, PWDF_EUNSUPPORTED, "unknown precision");
+  PlanInput in;
+  {
+    pwdf_status s = make_input(in, lattice, natm, xyz, nshell, shell_atom, shell_l, shell_nprim, exps, coefs, kmesh,
+                               omega, screen);
+    if (s != PWDF_OK) return s;
+  }
+
+  pwdf_ctx *c = new (std::nothrow) pwdf_ctx();
+  if (!c) return fail(nullptr, PWDF_ENOMEM, "host allocation failed");
+  std::string why;
+  try {
+    why = build_plan(in, 8, c->plan);
+  } catch (const std::bad_alloc &) {
+    delete c;
+    return fail(nullptr, PWDF_ENOMEM, "host allocation failed while building the plan");
+  }
+  if (!why.empty()) {
+    delete c;
+    return fail(nullptr, PWDF_EINVAL, why);
+  }
+  c->device = device;
+  c->max_ndm = max_ndm;
+  c->prec = prec;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) {
+    delete c;
+    return fail(nullptr, PWDF_EDEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
+  }
+  if (device < 0 || device >= ndev) {
+    delete c;
+    return fail(nullptr, PWDF_EINVAL, "device ordinal out of range");
+  }
+  if ((e = hipSetDevice(device)) != hipSuccess) {
+    delete c;
+    return fail(nullptr, PWDF_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  }
+  Plan &p = c->plan;
+  Dev &d = c->dev;
+  std::memset(&d, 0, sizeof(d));
+  d.nk = p.nk;
+  d.nbf = p.nbf;
+  d.nshell = in.nshell;
+  d.natm = in.natm;
+  d.nseg = p.nseg();
+  d.nslot = p.nslot();
+  d.seg_len = p.seg_len;
+  d.nelem = p.nelem;
+  d.vol = p.vol;
+  for (int i = 0; i < 16; ++i) {
+    d.cls_b0[i] = p.cls_b0[i];
+    d.cls_b1[i] = p.cls_b1[i];
+  }
+  for (int L = 0; L <= kMaxLsum; ++L) {
+    d.L_p0[L] = p.L_p0[L];
+    d.L_p1[L] = p.L_p1[L];
+    d.dhat_off[L] = p.dhat_off[L];
+  }
+  d.dhat_size = std::max<int64_t>(1, p.dhat_size);
+  choose_shapes(p, d, 4096);
+
+#define UP(vec, field)                                                  \
+  if ((e = upload(c, vec, &d.field)) != hipSuccess) {                   \
+    pwdf_status s_ = hip_fail(nullptr, e, "uploading " #field);         \
+    free_device(c);                                                     \
+    delete c;                                                           \
+    return s_;                                                          \
+  }
+  UP(p.segs, segs)
+  UP(p.slot_v, slot_v)
+  UP(p.hot, hot)
+  UP(p.aux, aux)
+  UP(p.blocks, blocks)
+  UP(p.elem_blk, elem_blk)
+  UP(in.sh_l, sh_l)
+  UP(in.sh_atom, sh_atom)
+  UP(p.sp_off, sp_off)
+  UP(p.sp_ent, sp_ent)
+  UP(p.bf_shell, bf_shell)
+  UP(p.bf_comp, bf_comp)
+  UP(p.ttab, ttab)
+#undef UP
+  {
+    const double *ph;
+    if ((e = upload(c, p.phD, &ph)) != hipSuccess) {
+      free_device(c);
+      delete c;
+      return hip_fail(nullptr, e, "uploading phase tables");
+    }
+    d.phD = (const double2 *)ph;
+    if ((e = upload(c, p.phJ, &ph)) != hipSuccess) {
+      free_device(c);
+      delete c;
+      return hip_fail(nullptr, e, "uploading phase tables");
+    }
+    d.phJ = (const double2 *)ph;
+  }
+  const size_t M = (size_t)max_ndm;
+#define AL(field, count)                                                \
+  if ((e = alloc(c, (count), &d.field)) != hipSuccess) {                \
+    free_device(c);                                                     \
+    delete c;                                                           \
+    return fail(nullptr, PWDF_ENOMEM, "device allocation failed: " #field); \
+  }
+  AL(Dblk, M * p.nelem)
+  AL(Jblk, M * p.nelem)
+  AL(dhat, M * d.dhat_size)
+  AL(yhat, M * d.yhat_size)
+  AL(part, M * d.nrows * d.nslot)
+  AL(rho, M * d.nslot)
+  AL(Vc, M * d.nslot)
+  AL(Epart, M * d.nred_blocks)
+#undef AL
+  if ((e = alloc(c, M, &c->Escr)) != hipSuccess) {
+    free_device(c);
+    delete c;
+    return fail(nullptr, PWDF_ENOMEM, "device allocation failed: energies");
+  }
+  *out = c;
+  return PWDF_OK;
+}
+
+pwdf_status pwdf_query(const pwdf_ctx *c, pwdf_stats *out) {
+  if (!c || !out) return PWDF_EINVAL;
+  fill_stats(c->plan, out);
+  return PWDF_OK;
+}
+
+pwdf_status pwdf_build_j(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, double *EJ, void *stream) {
+  if (!c) return PWDF_EINVAL;
+  pwdf_status s = validate_ndm(c, ndm);
+  if (s != PWDF_OK) return s;
+  if (!Dk || !Jk || !EJ) return fail(c, PWDF_EINVAL, "NULL buffer");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  if ((s = run_to_rho(c, ndm, Dk, EJ, st)) != PWDF_OK) return s;
+  if ((e = launch_jpass(c->dev, ndm, st)) != hipSuccess) return hip_fail(c, e, "J pass");
+  if ((e = launch_backtransform(c->dev, ndm, st)) != hipSuccess) return hip_fail(c, e, "back transform");
+  if ((e = launch_phase_j(c->dev, ndm, Jk, st)) != hipSuccess) return hip_fail(c, e, "phase J");
+  return PWDF_OK;
+}
+
+pwdf_status pwdf_get_rhoG(pwdf_ctx *c, int ndm, const double *Dk, double *rhoG, int *miller, void *stream) {
+  if (!c) return PWDF_EINVAL;
+  pwdf_status s = validate_ndm(c, ndm);
+  if (s != PWDF_OK) return s;
+  if (!Dk || !rhoG) return fail(c, PWDF_EINVAL, "NULL buffer");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  if ((s = run_to_rho(c, ndm, Dk, c->Escr, st)) != PWDF_OK) return s;
+  // gather the valid slots on the host side of the copy (small: nG/2 complex per density)
+  const Plan &p = c->plan;
+  const size_t nv = p.valid_slots.size();
+  std::vector<double2> full((size_t)ndm * p.nslot());
+  if ((e = hipMemcpyAsync(full.data(), c->dev.rho, full.size() * sizeof(double2), hipMemcpyDeviceToHost, st)) !=
+      hipSuccess)
+    return hip_fail(c, e, "copy rho");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "sync");
+  std::vector<double2> comp((size_t)ndm * nv);
+  for (int dm = 0; dm < ndm; ++dm)
+    for (size_t i = 0; i < nv; ++i) comp[dm * nv + i] = full[(size_t)dm * p.nslot() + p.valid_slots[i]];
+  if ((e = hipMemcpy(rhoG, comp.data(), comp.size() * sizeof(double2), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(c, e, "copy rhoG");
+  if (miller)
+    for (size_t i = 0; i < nv; ++i)
+      for (int x = 0; x < 3; ++x) miller[3 * i + x] = p.slot_miller[3 * (size_t)p.valid_slots[i] + x];
+  return PWDF_OK;
+}
+
+pwdf_status pwdf_grad(pwdf_ctx *c, int ndm, const double *Dk, double *dEdR, double *EJ, void *stream) {
+  (void)ndm;
+  (void)Dk;
+  (void)dEdR;
+  (void)EJ;
+  (void)stream;
+  if (!c) return PWDF_EINVAL;
+  return fail(c, PWDF_EUNSUPPORTED, "gradient not built yet");
+}
+
+pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
+  (void)ndm;
+  (void)cache_path;
+  if (!c) return PWDF_EINVAL;
+  return PWDF_OK;
+}
+
+const char *pwdf_last_error(const pwdf_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+void pwdf_destroy(pwdf_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  free_device(c);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// Device-side view of a plan and the kernel launchers of libpwdf.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pwdf_internal.h"
+
+namespace pwdf {
+
+// Plain struct of device pointers and launch shapes (copied by value into launchers).
+struct Dev {
+  // sizes
+  int nk, nbf, nshell, natm;
+  int nseg, nslot, seg_len;
+  int64_t nelem;
+  double vol;
+  // static plan data (device)
+  const SegDesc *segs;
+  const double *slot_v;
+  const PairHot *hot;
+  const PairAux *aux;
+  const BlockRec *blocks;
+  const int *elem_blk;
+  const int *sh_l;
+  const int *sh_atom;
+  const double2 *phD, *phJ;
+  const int *sp_off;
+  const GatherEnt *sp_ent;
+  const int *bf_shell, *bf_comp;
+  const double *ttab;
+  int cls_b0[16], cls_b1[16];
+  int L_p0[kMaxLsum + 1], L_p1[kMaxLsum + 1];
+  int64_t dhat_off[kMaxLsum + 1];
+  int64_t dhat_size;
+  // workspaces (device), sized for max_ndm densities
+  double *Dblk, *Jblk;     // [ndm][nelem]
+  double *dhat;            // [ndm][dhat_size]
+  double *yhat;            // [ndm][yhat_size]
+  double2 *part;           // [ndm][nrows][nslot]
+  double2 *rho, *Vc;       // [ndm][nslot]
+  double *Epart;           // [ndm][nred_blocks]
+  // launch shapes
+  int rho_bs;
+  int rho_chunks[kMaxLsum + 1], rho_ppc[kMaxLsum + 1], rho_row0[kMaxLsum + 1];
+  int nrows;
+  int j_chunks[kMaxLsum + 1], j_spc[kMaxLsum + 1];
+  int64_t yhat_off[kMaxLsum + 1];
+  int64_t yhat_size;
+  int nred_blocks;
+};
+
+hipError_t launch_phase_d(const Dev &d, const double *Dk, int ndm, hipStream_t st);
+hipError_t launch_transform(const Dev &d, int ndm, hipStream_t st);
+hipError_t launch_rho(const Dev &d, int ndm, hipStream_t st);
+hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st);
+hipError_t launch_jpass(const Dev &d, int ndm, hipStream_t st);
+hipError_t launch_backtransform(const Dev &d, int ndm, hipStream_t st);
+hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, hipStream_t st);
+
+}  // namespace pwdf

@@ -1,0 +1,696 @@
+// FP64 kernels of libpwdf for gfx950.
+//
+// Pipeline per density (section "Long-range contributions"):
+//   k_phase_d      D(k) -> D(L) on the unique pair blocks            (eq. "FT for D")
+//   k_transform    per primitive pair: D block x McMurchie-Davidson Hermite
+//                  coefficients -> Hermite coefficients -> relative-monomial
+//                  coefficients d_k                                  (algorithm "density matrix transformation")
+//   k_rho          rho(G) partial sums: lane = one segment of a G line, the
+//                  wave walks a chunk of pairs                       (algorithm "non-ortho rho eval")
+//   k_reduce       sum of partial rows, V(G) = v rho, energy partials (contraction step 2)
+//   k_jpass        lane = one pair, the wave walks a chunk of segments and
+//                  accumulates the relative-monomial moments of conj(V) F
+//                                                                    (algorithm "non-ortho J eval")
+//   k_backtransform moments -> Hermite -> Cartesian J block          (algorithm "J matrix transformation")
+//   k_phase_j      J(L) -> J(k), dense output                        (eq. "FT of J")
+//
+// Per pair and G the transform is
+//   F_abL(G) = C e^{-|G|^2/4p} e^{-iG.P} sum_t E^{ab}_t (-iG)^t
+// (Hermite expansion of the Gaussian product; the transform of the t-th
+// derivative of e^{-p x_P^2} with respect to P carries (-iG)^t), and with
+// G = B n the Cartesian monomials G^t are rewritten as relative monomials
+// n_u^a n_v^b n_w^c (appendix "Expansion of angular prefactor in relative
+// coordinate"), so along a line (n_v, n_w fixed) the polynomial is a
+// one-variable polynomial in n_u and the Gaussian/phase factor follows the
+// shift-term recurrence.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace pwdf {
+
+// ---------------------------------------------------------------------------
+// compile-time monomial tables: degree-ordered, descending lexicographic
+// ---------------------------------------------------------------------------
+template <int L>
+struct Monos {
+  int u[nherm(L)], v[nherm(L)], w[nherm(L)];
+  constexpr Monos() : u(), v(), w() {
+    int n = 0;
+    for (int d = 0; d <= L; ++d)
+      for (int a = d; a >= 0; --a)
+        for (int b = d - a; b >= 0; --b) {
+          u[n] = a;
+          v[n] = b;
+          w[n] = d - a - b;
+          ++n;
+        }
+  }
+};
+
+// Cartesian components of one shell, descending lexicographic (lx, ly, lz).
+template <int l>
+struct Carts {
+  int x[ncart(l)], y[ncart(l)], z[ncart(l)];
+  constexpr Carts() : x(), y(), z() {
+    int n = 0;
+    for (int a = l; a >= 0; --a)
+      for (int b = l - a; b >= 0; --b) {
+        x[n] = a;
+        y[n] = b;
+        z[n] = l - a - b;
+        ++n;
+      }
+  }
+};
+
+__host__ __device__ constexpr int mono_idx(int a, int b, int c) {
+  // index of (a,b,c) inside its degree block, descending lexicographic
+  int d = a + b + c;
+  int idx = 0;
+  for (int x = d; x > a; --x) idx += d - x + 1;
+  return idx + (d - a) - b;
+}
+
+// ---------------------------------------------------------------------------
+// McMurchie-Davidson Hermite coefficients along one axis:
+//   x_A^i x_B^j e^{-p x_P^2} = sum_t E[i][j][t] d^t/dP^t e^{-p x_P^2}
+//   E[i+1][j][t] = E[i][j][t-1]/(2p) + X_PA E[i][j][t] + (t+1) E[i][j][t+1]
+// ---------------------------------------------------------------------------
+template <int LA, int LB>
+__device__ __forceinline__ void md_axis(double inv2p, double xpa, double xpb,
+                                        double (&E)[LA + 1][LB + 1][LA + LB + 1]) {
+#pragma unroll
+  for (int i = 0; i <= LA; ++i)
+#pragma unroll
+    for (int j = 0; j <= LB; ++j)
+#pragma unroll
+      for (int t = 0; t <= LA + LB; ++t) E[i][j][t] = 0.0;
+  E[0][0][0] = 1.0;
+#pragma unroll
+  for (int i = 0; i <= LA; ++i)
+#pragma unroll
+    for (int j = 0; j <= LB; ++j) {
+      if (i == 0 && j == 0) continue;
+#pragma unroll
+      for (int t = 0; t <= i + j; ++t) {
+        double v;
+        if (i > 0) {
+          v = xpa * E[i - 1][j][t];
+          if (t > 0) v += inv2p * E[i - 1][j][t - 1];
+          if (t + 1 <= i - 1 + j) v += (t + 1) * E[i - 1][j][t + 1];
+        } else {
+          v = xpb * E[i][j - 1][t];
+          if (t > 0) v += inv2p * E[i][j - 1][t - 1];
+          if (t + 1 <= i + j - 1) v += (t + 1) * E[i][j - 1][t + 1];
+        }
+        E[i][j][t] = v;
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a1: D(k) -> D(L) on the unique blocks (real part; the Hermitian input makes
+// the imaginary part cancel between (a,b,L) and its mirror (b,a,-L)).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk, int nk, int nbf,
+                                                 int64_t nelem, const int *__restrict__ elem_blk,
+                                                 const BlockRec *__restrict__ blocks,
+                                                 const int *__restrict__ sh_l,
+                                                 const double2 *__restrict__ phD,
+                                                 double *__restrict__ Dblk) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int dm = blockIdx.y;
+  if (e >= nelem) return;
+  const BlockRec b = blocks[elem_blk[e]];
+  const int ncb = ncart(sh_l[b.sb]);
+  const int r = (int)(e - b.eoff);
+  const int mu = b.bfa + r / ncb, nu = b.bfb + r % ncb;
+  const size_t nn = (size_t)nbf * nbf;
+  const double2 *D = Dk + (size_t)dm * nk * nn + (size_t)mu * nbf + nu;
+  const double2 *ph = phD + (size_t)b.img * nk;
+  double acc = 0.0;
+  for (int k = 0; k < nk; ++k) {
+    double2 d = D[(size_t)k * nn];
+    double2 w = ph[k];
+    acc = fma(w.x, d.x, acc);
+    acc = fma(-w.y, d.y, acc);
+  }
+  Dblk[(size_t)dm * nelem + e] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// a2: per block of class (LA, LB): for every primitive pair
+//   D~_t = pref_rho sum_{a,b} D_ab E^x_{ax bx tx} E^y_{ay by ty} E^z_{az bz tz}
+//   d_k  = sigma_|k| sum_{|t| = |k|} T[t][k] D~_t,  sigma = (+,-,-,+)[|k| mod 4]
+// so that rho's polynomial along a line is sum_k d_k n^k with even |k| in the
+// real part and odd |k| in the imaginary part.
+// ---------------------------------------------------------------------------
+template <int LA, int LB>
+__global__ __launch_bounds__(64) void k_transform(const BlockRec *__restrict__ blocks, int b0, int b1,
+                                                  const PairAux *__restrict__ aux,
+                                                  const double *__restrict__ Dblk, int64_t nelem,
+                                                  const double *__restrict__ ttab,
+                                                  double *__restrict__ dhat, int64_t dhat_size,
+                                                  int64_t cls_off, int Lp0) {
+  constexpr int L = LA + LB;
+  constexpr int NT = nherm(L);
+  constexpr Carts<LA> CA{};
+  constexpr Carts<LB> CB{};
+  constexpr int NCA = ncart(LA), NCB = ncart(LB);
+  const int bi = b0 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int dm = blockIdx.y;
+  if (bi >= b1) return;
+  const BlockRec b = blocks[bi];
+  const double *D = Dblk + (size_t)dm * nelem + b.eoff;
+  double *out_base = dhat + (size_t)dm * dhat_size + cls_off;
+  for (int q = b.p0; q < b.p1; ++q) {
+    const PairAux x = aux[q];
+    const double inv2p = 0.5 / x.p;
+    double Ex[LA + 1][LB + 1][L + 1], Ey[LA + 1][LB + 1][L + 1], Ez[LA + 1][LB + 1][L + 1];
+    md_axis<LA, LB>(inv2p, x.xpa[0], x.xpb[0], Ex);
+    md_axis<LA, LB>(inv2p, x.xpa[1], x.xpb[1], Ey);
+    md_axis<LA, LB>(inv2p, x.xpa[2], x.xpb[2], Ez);
+    double Dt[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) Dt[t] = 0.0;
+#pragma unroll
+    for (int ia = 0; ia < NCA; ++ia)
+#pragma unroll
+      for (int ib = 0; ib < NCB; ++ib) {
+        const double dab = D[ia * NCB + ib] * x.pref_rho;
+        const int ax = CA.x[ia], ay = CA.y[ia], az = CA.z[ia];
+        const int bx = CB.x[ib], by = CB.y[ib], bz = CB.z[ib];
+#pragma unroll
+        for (int tx = 0; tx <= ax + bx; ++tx)
+#pragma unroll
+          for (int ty = 0; ty <= ay + by; ++ty) {
+            const double exy = dab * Ex[ax][bx][tx] * Ey[ay][by][ty];
+#pragma unroll
+            for (int tz = 0; tz <= az + bz; ++tz) {
+              const int t = deg_off(tx + ty + tz) + mono_idx(tx, ty, tz);
+              Dt[t] = fma(exy, Ez[az][bz][tz], Dt[t]);
+            }
+          }
+      }
+    double *out = out_base + (size_t)(q - Lp0) * NT;
+#pragma unroll
+    for (int d = 0; d <= L; ++d) {
+      const int nc = ncart(d);
+      const double *T = ttab + tblk_off(d);
+      const double sg = ((d & 3) == 1 || (d & 3) == 2) ? -1.0 : 1.0;
+#pragma unroll
+      for (int k = 0; k < nc; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < nc; ++t) s = fma(T[t * nc + k], Dt[deg_off(d) + t], s);
+        out[deg_off(d) + k] = sg * s;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a3: rho(G) partial sums.  Lane = one segment (SEG consecutive n_u of a line),
+// the wave walks pairs [p0, p1) of class L with wave-uniform pair data.
+//   rho(n) += S(n) P(n),   P(n_u) = sum_a C_a n_u^a  (Horner),
+//   C_a = sum_{b,c} d_{abc} n_v^b n_w^c  (real part from even a+b+c, imaginary
+//   from odd), S advanced by S <- S R, R <- q R.
+// ---------------------------------------------------------------------------
+template <int L, int SEG>
+__global__ __launch_bounds__(256) void k_rho(const SegDesc *__restrict__ segs, int nseg,
+                                             const PairHot *__restrict__ hot, int Lp0, int Lp1,
+                                             int pairs_per_chunk, const double *__restrict__ dhat,
+                                             int64_t dhat_size, int64_t cls_off,
+                                             double2 *__restrict__ part, int row0, int nrows, int nslot) {
+  constexpr int NT = nherm(L);
+  constexpr Monos<L> MT{};
+  const int seg = blockIdx.x * blockDim.x + threadIdx.x;
+  const int chunk = blockIdx.y;
+  const int dm = blockIdx.z;
+  const int p0 = Lp0 + chunk * pairs_per_chunk;
+  const int p1 = min(Lp1, p0 + pairs_per_chunk);
+  const bool active = seg < nseg;
+  SegDesc sd = segs[active ? seg : 0];
+  // monomials n_v^b n_w^c
+  double mv[L + 1], mw[L + 1];
+  mv[0] = 1.0;
+  mw[0] = 1.0;
+#pragma unroll
+  for (int b = 1; b <= L; ++b) {
+    mv[b] = mv[b - 1] * sd.nv;
+    mw[b] = mw[b - 1] * sd.nw;
+  }
+  double accr[SEG], acci[SEG];
+#pragma unroll
+  for (int s = 0; s < SEG; ++s) accr[s] = acci[s] = 0.0;
+  const double *dbase = dhat + (size_t)dm * dhat_size + cls_off;
+  const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
+  for (int p = p0; p < p1; ++p) {
+    const PairHot h = hot[p];
+    const double *d = dbase + (size_t)(p - Lp0) * NT;
+    double cr[L + 1], ci[L + 1];
+#pragma unroll
+    for (int a = 0; a <= L; ++a) cr[a] = ci[a] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      const int a = MT.u[k], b = MT.v[k], c = MT.w[k];
+      const double t = d[k] * (mv[b] * mw[c]);
+      if ((a + b + c) & 1)
+        ci[a] += t;
+      else
+        cr[a] += t;
+    }
+    const double e0 = exp(-sd.gq0 * h.inv4p);
+    const double eR = exp(-sd.dg0 * h.inv4p);
+    double ph = fma(nu0, h.fu, fma(nv, h.fv, nw * h.fw));
+    ph -= rint(ph);
+    double sn, cs;
+    sincospi(2.0 * ph, &sn, &cs);
+    double Sr = e0 * cs, Si = -e0 * sn;
+    double Rr = eR * h.cu, Ri = eR * h.su;
+    const double q = h.q;
+#pragma unroll
+    for (int s = 0; s < SEG; ++s) {
+      const double n = nu0 + s;
+      double Pr = cr[L], Pi = ci[L];
+#pragma unroll
+      for (int a = L - 1; a >= 0; --a) {
+        Pr = fma(Pr, n, cr[a]);
+        Pi = fma(Pi, n, ci[a]);
+      }
+      accr[s] = fma(Sr, Pr, fma(-Si, Pi, accr[s]));
+      acci[s] = fma(Sr, Pi, fma(Si, Pr, acci[s]));
+      const double tr = fma(Sr, Rr, -Si * Ri);
+      Si = fma(Sr, Ri, Si * Rr);
+      Sr = tr;
+      Rr *= q;
+      Ri *= q;
+    }
+  }
+  if (!active) return;
+  double2 *out = part + ((size_t)dm * nrows + row0 + chunk) * nslot + (size_t)seg * SEG;
+#pragma unroll
+  for (int s = 0; s < SEG; ++s) out[s] = make_double2(accr[s], acci[s]);
+}
+
+// ---------------------------------------------------------------------------
+// a4: rho = sum of partial rows (fixed order), V = v rho, stored conjugated for
+// the J pass; energy partial Omega sum v |rho|^2 per block (G half space).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ part, int nrows, int nslot,
+                                                const double *__restrict__ slot_v, double vol,
+                                                double2 *__restrict__ rho, double2 *__restrict__ Vc,
+                                                double *__restrict__ Epart) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int dm = blockIdx.y;
+  double e = 0.0;
+  if (g < nslot) {
+    const double2 *pp = part + (size_t)dm * nrows * nslot + g;
+    double r = 0.0, i = 0.0;
+    for (int row = 0; row < nrows; ++row) {
+      double2 x = pp[(size_t)row * nslot];
+      r += x.x;
+      i += x.y;
+    }
+    const double v = slot_v[g];
+    rho[(size_t)dm * nslot + g] = make_double2(r, i);
+    Vc[(size_t)dm * nslot + g] = make_double2(v * r, -v * i);
+    e = vol * v * (r * r + i * i);
+  }
+  __shared__ double sh[256];
+  sh[threadIdx.x] = e;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) Epart[(size_t)dm * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_energy(const double *__restrict__ Epart, int nparts,
+                                                double *__restrict__ EJ) {
+  const int dm = blockIdx.x;
+  double e = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) e += Epart[(size_t)dm * nparts + i];
+  __shared__ double sh[256];
+  sh[threadIdx.x] = e;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) EJ[dm] = sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// a5: J moments.  Lane = one pair of class L; the wave walks segments
+// [s0, s1) with wave-uniform segment data and conj(V):
+//   U(n) = conj V(n) S(n);  m_a = sum_{n_u} n_u^a U  along the segment;
+//   yhat_{abc} += n_v^b n_w^c (Re m_a if a+b+c even else Im m_a).
+// Padding slots carry V = 0.
+// ---------------------------------------------------------------------------
+template <int L, int SEG>
+__global__ __launch_bounds__(256) void k_jpass(const SegDesc *__restrict__ segs, int nseg,
+                                               int segs_per_chunk, const double2 *__restrict__ Vc,
+                                               int nslot, const PairHot *__restrict__ hot, int Lp0,
+                                               int Lp1, double *__restrict__ yhat, int64_t yhat_size,
+                                               int64_t ycls_off) {
+  constexpr int NT = nherm(L);
+  constexpr Monos<L> MT{};
+  const int np = Lp1 - Lp0;
+  const int pl = blockIdx.x * blockDim.x + threadIdx.x;
+  const int chunk = blockIdx.y;
+  const int dm = blockIdx.z;
+  const bool active = pl < np;
+  const PairHot h = hot[Lp0 + (active ? pl : 0)];
+  const int s0 = chunk * segs_per_chunk;
+  const int s1 = min(nseg, s0 + segs_per_chunk);
+  double y[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) y[k] = 0.0;
+  const double2 *V = Vc + (size_t)dm * nslot;
+  for (int sg = s0; sg < s1; ++sg) {
+    const SegDesc sd = segs[sg];
+    const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
+    const double e0 = exp(-sd.gq0 * h.inv4p);
+    const double eR = exp(-sd.dg0 * h.inv4p);
+    double ph = fma(nu0, h.fu, fma(nv, h.fv, nw * h.fw));
+    ph -= rint(ph);
+    double sn, cs;
+    sincospi(2.0 * ph, &sn, &cs);
+    double Sr = e0 * cs, Si = -e0 * sn;
+    double Rr = eR * h.cu, Ri = eR * h.su;
+    const double q = h.q;
+    double mr[L + 1], mi[L + 1];
+#pragma unroll
+    for (int a = 0; a <= L; ++a) mr[a] = mi[a] = 0.0;
+#pragma unroll
+    for (int s = 0; s < SEG; ++s) {
+      const double2 v = V[(size_t)sg * SEG + s];
+      const double Ur = fma(v.x, Sr, -v.y * Si);
+      const double Ui = fma(v.x, Si, v.y * Sr);
+      const double n = nu0 + s;
+      double pw = 1.0;
+#pragma unroll
+      for (int a = 0; a <= L; ++a) {
+        mr[a] = fma(pw, Ur, mr[a]);
+        mi[a] = fma(pw, Ui, mi[a]);
+        pw *= n;
+      }
+      const double tr = fma(Sr, Rr, -Si * Ri);
+      Si = fma(Sr, Ri, Si * Rr);
+      Sr = tr;
+      Rr *= q;
+      Ri *= q;
+    }
+    double mv[L + 1], mw[L + 1];
+    mv[0] = mw[0] = 1.0;
+#pragma unroll
+    for (int b = 1; b <= L; ++b) {
+      mv[b] = mv[b - 1] * nv;
+      mw[b] = mw[b - 1] * nw;
+    }
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      const int a = MT.u[k], b = MT.v[k], c = MT.w[k];
+      const double m = ((a + b + c) & 1) ? mi[a] : mr[a];
+      y[k] = fma(mv[b] * mw[c], m, y[k]);
+    }
+  }
+  if (!active) return;
+  double *out = yhat + (size_t)dm * yhat_size + ycls_off + (size_t)chunk * NT * np + pl;
+#pragma unroll
+  for (int k = 0; k < NT; ++k) out[(size_t)k * np] = y[k];
+}
+
+// ---------------------------------------------------------------------------
+// a6: per block of class (LA, LB): for every primitive pair
+//   y_k  = s_|k| sum_chunks yhat_k,  s = (+,+,-,-)[|k| mod 4]   (Re of (-i)^|k| Y_k)
+//   J~_t = sum_{|k| = |t|} T[t][k] y_k
+//   J_ab += pref_j sum_t E^{ab}_t J~_t
+// ---------------------------------------------------------------------------
+template <int LA, int LB>
+__global__ __launch_bounds__(64) void k_backtransform(const BlockRec *__restrict__ blocks, int b0, int b1,
+                                                      const PairAux *__restrict__ aux,
+                                                      const double *__restrict__ ttab,
+                                                      const double *__restrict__ yhat, int64_t yhat_size,
+                                                      int64_t ycls_off, int nchunks, int Lp0, int Lp1,
+                                                      double *__restrict__ Jblk, int64_t nelem) {
+  constexpr int L = LA + LB;
+  constexpr int NT = nherm(L);
+  constexpr Carts<LA> CA{};
+  constexpr Carts<LB> CB{};
+  constexpr int NCA = ncart(LA), NCB = ncart(LB);
+  const int bi = b0 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int dm = blockIdx.y;
+  if (bi >= b1) return;
+  const BlockRec b = blocks[bi];
+  const int np = Lp1 - Lp0;
+  double J[NCA * NCB];
+#pragma unroll
+  for (int e = 0; e < NCA * NCB; ++e) J[e] = 0.0;
+  for (int q = b.p0; q < b.p1; ++q) {
+    const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (q - Lp0);
+    double y[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      double s = 0.0;
+      for (int c = 0; c < nchunks; ++c) s += ys[((size_t)c * NT + k) * np];
+      y[k] = s;
+    }
+    double Jt[NT];
+#pragma unroll
+    for (int d = 0; d <= L; ++d) {
+      const int nc = ncart(d);
+      const double *T = ttab + tblk_off(d);
+      const double sg = ((d & 3) >= 2) ? -1.0 : 1.0;
+#pragma unroll
+      for (int t = 0; t < nc; ++t) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < nc; ++k) s = fma(T[t * nc + k], y[deg_off(d) + k], s);
+        Jt[deg_off(d) + t] = sg * s;
+      }
+    }
+    const PairAux x = aux[q];
+    const double inv2p = 0.5 / x.p;
+    double Ex[LA + 1][LB + 1][L + 1], Ey[LA + 1][LB + 1][L + 1], Ez[LA + 1][LB + 1][L + 1];
+    md_axis<LA, LB>(inv2p, x.xpa[0], x.xpb[0], Ex);
+    md_axis<LA, LB>(inv2p, x.xpa[1], x.xpb[1], Ey);
+    md_axis<LA, LB>(inv2p, x.xpa[2], x.xpb[2], Ez);
+#pragma unroll
+    for (int ia = 0; ia < NCA; ++ia)
+#pragma unroll
+      for (int ib = 0; ib < NCB; ++ib) {
+        const int ax = CA.x[ia], ay = CA.y[ia], az = CA.z[ia];
+        const int bx = CB.x[ib], by = CB.y[ib], bz = CB.z[ib];
+        double s = 0.0;
+#pragma unroll
+        for (int tx = 0; tx <= ax + bx; ++tx)
+#pragma unroll
+          for (int ty = 0; ty <= ay + by; ++ty) {
+            const double exy = Ex[ax][bx][tx] * Ey[ay][by][ty];
+#pragma unroll
+            for (int tz = 0; tz <= az + bz; ++tz) {
+              const int t = deg_off(tx + ty + tz) + mono_idx(tx, ty, tz);
+              s = fma(exy * Ez[az][bz][tz], Jt[t], s);
+            }
+          }
+        J[ia * NCB + ib] = fma(x.pref_j, s, J[ia * NCB + ib]);
+      }
+  }
+  double *out = Jblk + (size_t)dm * nelem + b.eoff;
+#pragma unroll
+  for (int e = 0; e < NCA * NCB; ++e) out[e] = J[e];
+}
+
+// ---------------------------------------------------------------------------
+// a7: J(k)_{mu nu} = sum over the gather list of (sa, sb):
+//   tr = 0: e^{ik.L_m} J_blk[a][b];  tr = 1: e^{-ik.L_m} J_blk[b][a]  (mirror block)
+// One thread per (k, mu, nu); nu fastest for coalesced stores.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_phase_j(const double *__restrict__ Jblk, int64_t nelem,
+                                                 const BlockRec *__restrict__ blocks,
+                                                 const int *__restrict__ sh_l,
+                                                 const int *__restrict__ bf_shell,
+                                                 const int *__restrict__ bf_comp,
+                                                 const int *__restrict__ sp_off,
+                                                 const GatherEnt *__restrict__ sp_ent, int nshell,
+                                                 const double2 *__restrict__ phJ, int nk, int nbf,
+                                                 double2 *__restrict__ Jk) {
+  const int nu = blockIdx.x * blockDim.x + threadIdx.x;
+  const int mu = blockIdx.y;
+  const int kz = blockIdx.z;
+  const int dm = kz / nk, k = kz % nk;
+  if (nu >= nbf) return;
+  const int sa = bf_shell[mu], sb = bf_shell[nu];
+  const int a = bf_comp[mu], bcomp = bf_comp[nu];
+  const double *J = Jblk + (size_t)dm * nelem;
+  double re = 0.0, im = 0.0;
+  const int e0 = sp_off[(size_t)sa * nshell + sb], e1 = sp_off[(size_t)sa * nshell + sb + 1];
+  for (int e = e0; e < e1; ++e) {
+    const GatherEnt g = sp_ent[e];
+    const BlockRec br = blocks[g.blk];
+    const double2 w = phJ[(size_t)g.img * nk + k];
+    double val;
+    double wi;
+    if (g.tr == 0) {
+      val = J[br.eoff + a * ncart(sh_l[br.sb]) + bcomp];
+      wi = w.y;
+    } else {
+      val = J[br.eoff + bcomp * ncart(sh_l[br.sb]) + a];
+      wi = -w.y;
+    }
+    re = fma(w.x, val, re);
+    im = fma(wi, val, im);
+  }
+  Jk[(((size_t)dm * nk + k) * nbf + mu) * nbf + nu] = make_double2(re, im);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+#define PWDF_CHECK_LAUNCH()                          \
+  do {                                               \
+    hipError_t e_ = hipGetLastError();               \
+    if (e_ != hipSuccess) return e_;                 \
+  } while (0)
+
+hipError_t launch_phase_d(const Dev &d, const double *Dk, int ndm, hipStream_t st) {
+  dim3 grid((unsigned)((d.nelem + 255) / 256), ndm);
+  hipLaunchKernelGGL(k_phase_d, grid, dim3(256), 0, st, (const double2 *)Dk, d.nk, d.nbf, d.nelem, d.elem_blk,
+                     d.blocks, d.sh_l, d.phD, d.Dblk);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+template <int LA, int LB>
+static hipError_t transform_one(const Dev &d, int ndm, hipStream_t st) {
+  const int c = LA * 4 + LB;
+  const int b0 = d.cls_b0[c], b1 = d.cls_b1[c];
+  if (b1 <= b0) return hipSuccess;
+  dim3 grid((unsigned)((b1 - b0 + 63) / 64), ndm);
+  hipLaunchKernelGGL((k_transform<LA, LB>), grid, dim3(64), 0, st, d.blocks, b0, b1, d.aux, d.Dblk, d.nelem,
+                     d.ttab, d.dhat, d.dhat_size, d.dhat_off[LA + LB], d.L_p0[LA + LB]);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+hipError_t launch_transform(const Dev &d, int ndm, hipStream_t st) {
+  hipError_t e;
+#define T1(A, B) \
+  if ((e = transform_one<A, B>(d, ndm, st)) != hipSuccess) return e;
+  T1(0, 0) T1(1, 0) T1(1, 1) T1(2, 0) T1(2, 1) T1(2, 2) T1(3, 0) T1(3, 1) T1(3, 2) T1(3, 3)
+#undef T1
+  return hipSuccess;
+}
+
+template <int L, int SEG>
+static hipError_t rho_one(const Dev &d, int ndm, hipStream_t st) {
+  const int np = d.L_p1[L] - d.L_p0[L];
+  if (np <= 0) return hipSuccess;
+  const int bs = d.rho_bs;
+  dim3 grid((unsigned)((d.nseg + bs - 1) / bs), d.rho_chunks[L], ndm);
+  hipLaunchKernelGGL((k_rho<L, SEG>), grid, dim3(bs), 0, st, d.segs, d.nseg, d.hot, d.L_p0[L], d.L_p1[L],
+                     d.rho_ppc[L], d.dhat, d.dhat_size, d.dhat_off[L], d.part, d.rho_row0[L], d.nrows, d.nslot);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+template <int SEG>
+static hipError_t rho_all(const Dev &d, int ndm, hipStream_t st) {
+  hipError_t e;
+  if ((e = rho_one<0, SEG>(d, ndm, st)) != hipSuccess) return e;
+  if ((e = rho_one<1, SEG>(d, ndm, st)) != hipSuccess) return e;
+  if ((e = rho_one<2, SEG>(d, ndm, st)) != hipSuccess) return e;
+  if ((e = rho_one<3, SEG>(d, ndm, st)) != hipSuccess) return e;
+  if ((e = rho_one<4, SEG>(d, ndm, st)) != hipSuccess) return e;
+  if ((e = rho_one<5, SEG>(d, ndm, st)) != hipSuccess) return e;
+  if ((e = rho_one<6, SEG>(d, ndm, st)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t launch_rho(const Dev &d, int ndm, hipStream_t st) {
+  switch (d.seg_len) {
+    case 4: return rho_all<4>(d, ndm, st);
+    case 8: return rho_all<8>(d, ndm, st);
+    case 16: return rho_all<16>(d, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st) {
+  dim3 grid((unsigned)d.nred_blocks, ndm);
+  hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, st, d.part, d.nrows, d.nslot, d.slot_v, d.vol, d.rho, d.Vc,
+                     d.Epart);
+  PWDF_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_energy, dim3(ndm), dim3(256), 0, st, d.Epart, d.nred_blocks, EJ);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+template <int L, int SEG>
+static hipError_t j_one(const Dev &d, int ndm, hipStream_t st) {
+  const int np = d.L_p1[L] - d.L_p0[L];
+  if (np <= 0) return hipSuccess;
+  dim3 grid((unsigned)((np + 255) / 256), d.j_chunks[L], ndm);
+  hipLaunchKernelGGL((k_jpass<L, SEG>), grid, dim3(256), 0, st, d.segs, d.nseg, d.j_spc[L], d.Vc, d.nslot, d.hot,
+                     d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size, d.yhat_off[L]);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+template <int SEG>
+static hipError_t j_all(const Dev &d, int ndm, hipStream_t st) {
+  hipError_t e;
+  if ((e = j_one<0, SEG>(d, ndm, st)) != hipSuccess) return e;
+  if ((e = j_one<1, SEG>(d, ndm, st)) != hipSuccess) return e;
+  if ((e = j_one<2, SEG>(d, ndm, st)) != hipSuccess) return e;
+  if ((e = j_one<3, SEG>(d, ndm, st)) != hipSuccess) return e;
+  if ((e = j_one<4, SEG>(d, ndm, st)) != hipSuccess) return e;
+  if ((e = j_one<5, SEG>(d, ndm, st)) != hipSuccess) return e;
+  if ((e = j_one<6, SEG>(d, ndm, st)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t launch_jpass(const Dev &d, int ndm, hipStream_t st) {
+  switch (d.seg_len) {
+    case 4: return j_all<4>(d, ndm, st);
+    case 8: return j_all<8>(d, ndm, st);
+    case 16: return j_all<16>(d, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int LA, int LB>
+static hipError_t back_one(const Dev &d, int ndm, hipStream_t st) {
+  const int c = LA * 4 + LB;
+  const int b0 = d.cls_b0[c], b1 = d.cls_b1[c];
+  if (b1 <= b0) return hipSuccess;
+  constexpr int L = LA + LB;
+  dim3 grid((unsigned)((b1 - b0 + 63) / 64), ndm);
+  hipLaunchKernelGGL((k_backtransform<LA, LB>), grid, dim3(64), 0, st, d.blocks, b0, b1, d.aux, d.ttab, d.yhat,
+                     d.yhat_size, d.yhat_off[L], d.j_chunks[L], d.L_p0[L], d.L_p1[L], d.Jblk, d.nelem);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+hipError_t launch_backtransform(const Dev &d, int ndm, hipStream_t st) {
+  hipError_t e;
+#define B1(A, B) \
+  if ((e = back_one<A, B>(d, ndm, st)) != hipSuccess) return e;
+  B1(0, 0) B1(1, 0) B1(1, 1) B1(2, 0) B1(2, 1) B1(2, 2) B1(3, 0) B1(3, 1) B1(3, 2) B1(3, 3)
+#undef B1
+  return hipSuccess;
+}
+
+hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, hipStream_t st) {
+  dim3 grid((unsigned)((d.nbf + 255) / 256), d.nbf, d.nk * ndm);
+  hipLaunchKernelGGL(k_phase_j, grid, dim3(256), 0, st, d.Jblk, d.nelem, d.blocks, d.sh_l, d.bf_shell, d.bf_comp,
+                     d.sp_off, d.sp_ent, d.nshell, d.phJ, d.nk, d.nbf, (double2 *)Jk);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+}  // namespace pwdf

@@ -1,0 +1,471 @@
+// Host plan of libpwdf (see plan.h).
+//
+// Passages: section "Long-range contributions" (what is computed per pair),
+// section "Integral screening" (pair list), appendix "Cartesian coordinates and
+// relative coordinates" (A, B, relative coordinates), appendix "Expansion of
+// angular prefactor in relative coordinate" (multinomial transform of
+// G_x^lx G_y^ly G_z^lz into relative monomials), eq. "FT for D" / "FT of J"
+// (phase tables).
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <tuple>
+
+namespace pwdf {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+double dfact(int n) {
+  double r = 1.0;
+  for (; n > 1; n -= 2) r *= n;
+  return r;
+}
+
+double gto_norm(int l, double a) {
+  return std::pow(2.0 * a / kPi, 0.75) * std::pow(4.0 * a, 0.5 * l) / std::sqrt(dfact(2 * l - 1));
+}
+
+bool lex_nonneg(const std::array<int, 3> &m) {
+  for (int i = 0; i < 3; ++i) {
+    if (m[i] > 0) return true;
+    if (m[i] < 0) return false;
+  }
+  return true;  // m == 0
+}
+
+// |G|^2 for Miller indices n in the original axes, as sum of squared Cartesian components.
+double g2_of(const Plan &p, const int n[3]) {
+  double s = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    double g = p.B[c][0] * n[0] + p.B[c][1] * n[1] + p.B[c][2] * n[2];
+    s += g * g;
+  }
+  return s;
+}
+
+// Index of a monomial (e0, e1, e2) of degree d in descending lexicographic order.
+int mono_index(int e0, int e1, int e2) {
+  int d = e0 + e1 + e2;
+  // components with first exponent > e0 come first: sum_{x=e0+1}^{d} (d - x + 1)
+  int idx = 0;
+  for (int x = d; x > e0; --x) idx += d - x + 1;
+  idx += (d - e0) - e1;
+  return idx;
+}
+
+}  // namespace
+
+void build_segments(Plan &p, int seg_len) {
+  p.seg_len = seg_len;
+  p.segs.clear();
+  p.slot_v.clear();
+  p.slot_miller.clear();
+  p.valid_slots.clear();
+  const double gcut2 = 4.0 * p.in.omega * p.in.omega * (-std::log(p.in.eps_G));
+  const double gcut = std::sqrt(gcut2);
+  int nmax[3];
+  for (int i = 0; i < 3; ++i) {
+    double alen = std::sqrt(p.A[0][i] * p.A[0][i] + p.A[1][i] * p.A[1][i] + p.A[2][i] * p.A[2][i]);
+    nmax[i] = (int)std::floor(gcut * alen / (2.0 * kPi)) + 1;
+  }
+  const int u = p.ax[0], v = p.ax[1], w = p.ax[2];
+  const double w4 = 4.0 * p.in.omega * p.in.omega;
+  int64_t count = 0;
+  for (int nw = 0; nw <= nmax[w]; ++nw)
+    for (int nv = -nmax[v]; nv <= nmax[v]; ++nv) {
+      if (nw == 0 && nv < 0) continue;  // half space: (nw > 0) or (nw = 0, nv > 0) or (0, 0, nu > 0)
+      int lo = 1 << 30, hi = -(1 << 30);
+      for (int nu = -nmax[u]; nu <= nmax[u]; ++nu) {
+        if (nw == 0 && nv == 0 && nu <= 0) continue;
+        int n[3];
+        n[u] = nu;
+        n[v] = nv;
+        n[w] = nw;
+        double g2 = g2_of(p, n);
+        if (g2 > 0.0 && g2 <= gcut2) {
+          lo = std::min(lo, nu);
+          hi = std::max(hi, nu);
+        }
+      }
+      if (lo > hi) continue;
+      for (int nu0 = lo; nu0 <= hi; nu0 += seg_len) {
+        SegDesc sd;
+        sd.nu0 = nu0;
+        sd.nv = nv;
+        sd.nw = nw;
+        sd.cnt = std::min(seg_len, hi - nu0 + 1);
+        double b = p.M[u][v] * nv + p.M[u][w] * nw;
+        double c = p.M[v][v] * nv * nv + 2.0 * p.M[v][w] * nv * nw + p.M[w][w] * nw * nw;
+        sd.gq0 = p.M[u][u] * nu0 * (double)nu0 + 2.0 * b * nu0 + c;
+        sd.dg0 = p.M[u][u] * (2.0 * nu0 + 1.0) + 2.0 * b;
+        int sidx = (int)p.segs.size();
+        p.segs.push_back(sd);
+        for (int s = 0; s < seg_len; ++s) {
+          int n[3] = {0, 0, 0};
+          double vg = 0.0;
+          if (s < sd.cnt) {
+            n[u] = nu0 + s;
+            n[v] = nv;
+            n[w] = nw;
+            double g2 = g2_of(p, n);
+            vg = 4.0 * kPi * std::exp(-g2 / w4) / g2;
+            p.valid_slots.push_back(sidx * seg_len + s);
+            ++count;
+          }
+          p.slot_v.push_back(vg);
+          for (int c3 = 0; c3 < 3; ++c3) p.slot_miller.push_back(n[c3]);
+        }
+      }
+    }
+  p.nG_full = 2 * count;
+}
+
+std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
+  p.in = in;
+  char msg[256];
+  // ---- validation
+  if (in.natm < 1) return "natm must be >= 1";
+  if (in.nshell < 1) return "nshell must be >= 1";
+  if (!(in.omega > 0.0) || !std::isfinite(in.omega)) return "omega must be finite and > 0";
+  if (!(in.eps_pair > 0.0 && in.eps_pair < 1.0)) return "eps_pair must be in (0,1)";
+  if (!(in.eps_G > 0.0 && in.eps_G < 1.0)) return "eps_G must be in (0,1)";
+  for (int i = 0; i < 3; ++i)
+    if (in.kmesh[i] < 1) return "kmesh entries must be >= 1";
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(in.lattice[i])) return "lattice is not finite";
+  for (double x : in.xyz)
+    if (!std::isfinite(x)) return "xyz is not finite";
+  int nprim_tot = 0;
+  for (int s = 0; s < in.nshell; ++s) {
+    if (in.sh_l[s] < 0 || in.sh_l[s] > kMaxL) {
+      std::snprintf(msg, sizeof msg, "shell %d: l=%d outside 0..%d", s, in.sh_l[s], kMaxL);
+      return msg;
+    }
+    if (in.sh_atom[s] < 0 || in.sh_atom[s] >= in.natm) {
+      std::snprintf(msg, sizeof msg, "shell %d: atom index %d out of range", s, in.sh_atom[s]);
+      return msg;
+    }
+    if (in.sh_nprim[s] < 1) return "shell_nprim must be >= 1";
+    nprim_tot += in.sh_nprim[s];
+  }
+  if ((int)in.exps.size() != nprim_tot || (int)in.coefs.size() != nprim_tot) return "primitive arrays size mismatch";
+  for (int i = 0; i < nprim_tot; ++i) {
+    if (!(in.exps[i] > 0.0) || !std::isfinite(in.exps[i])) return "exponents must be finite and > 0";
+    if (!std::isfinite(in.coefs[i])) return "coefficients must be finite";
+  }
+
+  // ---- geometry
+  for (int i = 0; i < 3; ++i)
+    for (int c = 0; c < 3; ++c) p.A[c][i] = in.lattice[3 * i + c];
+  const double(*A)[3] = p.A;
+  double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+               A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+  double scale = 1.0;
+  for (int i = 0; i < 9; ++i) scale = std::max(scale, std::fabs(in.lattice[i]));
+  if (!(std::fabs(det) > 1e-10 * scale * scale * scale)) return "lattice is singular";
+  p.vol = std::fabs(det);
+  double inv[3][3];
+  inv[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / det;
+  inv[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+  inv[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+  inv[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / det;
+  inv[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+  inv[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+  inv[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / det;
+  inv[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+  inv[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+  for (int c = 0; c < 3; ++c)
+    for (int i = 0; i < 3; ++i) p.B[c][i] = 2.0 * kPi * inv[i][c];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) p.M[i][j] = p.B[0][i] * p.B[0][j] + p.B[1][i] * p.B[1][j] + p.B[2][i] * p.B[2][j];
+  // line axis: the longest index range |a_i| (most G per line)
+  {
+    double len[3];
+    for (int i = 0; i < 3; ++i) len[i] = std::sqrt(A[0][i] * A[0][i] + A[1][i] * A[1][i] + A[2][i] * A[2][i]);
+    int u = 0;
+    for (int i = 1; i < 3; ++i)
+      if (len[i] > len[u] * (1 + 1e-12)) u = i;
+    p.ax[0] = u;
+    p.ax[1] = (u + 1) % 3 < (u + 2) % 3 ? (u + 1) % 3 : (u + 2) % 3;
+    p.ax[2] = 3 - u - p.ax[1];
+  }
+
+  // ---- basis offsets
+  p.sh_bf.assign(in.nshell + 1, 0);
+  p.sh_pr.assign(in.nshell + 1, 0);
+  for (int s = 0; s < in.nshell; ++s) {
+    p.sh_bf[s + 1] = p.sh_bf[s] + ncart(in.sh_l[s]);
+    p.sh_pr[s + 1] = p.sh_pr[s] + in.sh_nprim[s];
+  }
+  p.nbf = p.sh_bf[in.nshell];
+  p.nk = in.kmesh[0] * in.kmesh[1] * in.kmesh[2];
+  p.bf_shell.resize(p.nbf);
+  p.bf_comp.resize(p.nbf);
+  for (int s = 0; s < in.nshell; ++s)
+    for (int c = 0; c < ncart(in.sh_l[s]); ++c) {
+      p.bf_shell[p.sh_bf[s] + c] = s;
+      p.bf_comp[p.sh_bf[s] + c] = c;
+    }
+
+  build_segments(p, seg_len);
+  if (p.valid_slots.empty()) return "the G set is empty (increase omega or decrease eps_G)";
+
+  // ---- unique screened primitive pairs, grouped into (sa, sb, m) blocks
+  struct RawPair {
+    int ia, ib;
+  };
+  struct RawBlock {
+    int L, la, sa, sb;
+    std::array<int, 3> m;
+    std::vector<RawPair> prims;
+  };
+  std::vector<RawBlock> raw;
+  const double lneps = -std::log(in.eps_pair);
+  for (int sa = 0; sa < in.nshell; ++sa)
+    for (int sb = 0; sb < in.nshell; ++sb) {
+      int la = in.sh_l[sa], lb = in.sh_l[sb];
+      // one representative of (a,b,L) ~ (b,a,-L): la > lb, or la == lb and sa <= sb
+      if (la < lb || (la == lb && sa > sb)) continue;
+      const double *RA = &in.xyz[3 * in.sh_atom[sa]];
+      const double *RB = &in.xyz[3 * in.sh_atom[sb]];
+      double d[3] = {RA[0] - RB[0], RA[1] - RB[1], RA[2] - RB[2]};
+      std::map<std::array<int, 3>, std::vector<RawPair>> bym;
+      for (int ia = p.sh_pr[sa]; ia < p.sh_pr[sa + 1]; ++ia)
+        for (int ib = p.sh_pr[sb]; ib < p.sh_pr[sb + 1]; ++ib) {
+          double aa = in.exps[ia], ab = in.exps[ib];
+          double mu = aa * ab / (aa + ab);
+          double R = std::sqrt(lneps / mu);
+          if (in.r_max > 0 && in.r_max < R) R = in.r_max;
+          int lo[3], hi[3];
+          for (int i = 0; i < 3; ++i) {
+            double bd = p.B[0][i] * d[0] + p.B[1][i] * d[1] + p.B[2][i] * d[2];
+            double bn = std::sqrt(p.B[0][i] * p.B[0][i] + p.B[1][i] * p.B[1][i] + p.B[2][i] * p.B[2][i]);
+            lo[i] = (int)std::floor((bd - bn * R) / (2.0 * kPi)) - 1;
+            hi[i] = (int)std::ceil((bd + bn * R) / (2.0 * kPi)) + 1;
+          }
+          for (int m0 = lo[0]; m0 <= hi[0]; ++m0)
+            for (int m1 = lo[1]; m1 <= hi[1]; ++m1)
+              for (int m2 = lo[2]; m2 <= hi[2]; ++m2) {
+                std::array<int, 3> m = {m0, m1, m2};
+                if (sa == sb && !lex_nonneg(m)) continue;
+                double r2 = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                  double L = A[c][0] * m0 + A[c][1] * m1 + A[c][2] * m2;
+                  double x = d[c] - L;
+                  r2 += x * x;
+                }
+                if (!(std::exp(-mu * r2) >= in.eps_pair)) continue;
+                if (in.r_max > 0 && std::sqrt(r2) > in.r_max) continue;
+                bym[m].push_back({ia, ib});
+              }
+        }
+      for (auto &kv : bym) raw.push_back({la + lb, la, sa, sb, kv.first, std::move(kv.second)});
+    }
+  if (raw.empty()) return "no pair survives screening";
+  std::stable_sort(raw.begin(), raw.end(), [](const RawBlock &x, const RawBlock &y) {
+    return std::tie(x.L, x.la, x.sa, x.sb, x.m) < std::tie(y.L, y.la, y.sa, y.sb, y.m);
+  });
+
+  std::map<std::array<int, 3>, int> img_index;
+  p.blocks.clear();
+  p.hot.clear();
+  p.aux.clear();
+  for (int c = 0; c < 16; ++c) p.cls_b0[c] = p.cls_b1[c] = 0;
+  for (int L = 0; L <= kMaxLsum; ++L) p.L_p0[L] = p.L_p1[L] = 0;
+  int64_t eoff = 0;
+  for (const RawBlock &rb : raw) {
+    auto it = img_index.find(rb.m);
+    int img;
+    if (it == img_index.end()) {
+      img = (int)p.imgs.size();
+      img_index[rb.m] = img;
+      p.imgs.push_back(rb.m);
+    } else {
+      img = it->second;
+    }
+    BlockRec br;
+    br.sa = rb.sa;
+    br.sb = rb.sb;
+    br.img = img;
+    br.p0 = (int)p.hot.size();
+    br.bfa = p.sh_bf[rb.sa];
+    br.bfb = p.sh_bf[rb.sb];
+    bool diag = (rb.sa == rb.sb) && rb.m[0] == 0 && rb.m[1] == 0 && rb.m[2] == 0;
+    br.w2 = diag ? 0 : 1;
+    br.eoff = eoff;
+    int la = in.sh_l[rb.sa], lb = in.sh_l[rb.sb];
+    eoff += (int64_t)ncart(la) * ncart(lb);
+    const double *RA = &in.xyz[3 * in.sh_atom[rb.sa]];
+    const double *RB0 = &in.xyz[3 * in.sh_atom[rb.sb]];
+    double RB[3];
+    for (int c = 0; c < 3; ++c) RB[c] = RB0[c] + A[c][0] * rb.m[0] + A[c][1] * rb.m[1] + A[c][2] * rb.m[2];
+    for (const RawPair &pr : rb.prims) {
+      double aa = in.exps[pr.ia], ab = in.exps[pr.ib];
+      double pp = aa + ab;
+      double P[3], r2 = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        P[c] = (aa * RA[c] + ab * RB[c]) / pp;
+        r2 += (RA[c] - RB[c]) * (RA[c] - RB[c]);
+      }
+      double K = std::exp(-aa * ab / pp * r2);
+      double C = in.coefs[pr.ia] * in.coefs[pr.ib] * gto_norm(la, aa) * gto_norm(lb, ab) * K * std::pow(kPi / pp, 1.5);
+      PairAux x;
+      x.p = pp;
+      for (int c = 0; c < 3; ++c) {
+        x.xpa[c] = P[c] - RA[c];
+        x.xpb[c] = P[c] - RB[c];
+      }
+      x.pref_rho = (diag ? 1.0 : 2.0) * C / p.vol;
+      x.pref_j = 2.0 * C;
+      x.pad = 0.0;
+      PairHot h;
+      double f[3];
+      for (int i = 0; i < 3; ++i) {
+        double t = (p.B[0][i] * P[0] + p.B[1][i] * P[1] + p.B[2][i] * P[2]) / (2.0 * kPi);
+        f[i] = t - std::nearbyint(t);
+      }
+      h.inv4p = 0.25 / pp;
+      h.fu = f[p.ax[0]];
+      h.fv = f[p.ax[1]];
+      h.fw = f[p.ax[2]];
+      h.cu = std::cos(2.0 * kPi * h.fu);
+      h.su = -std::sin(2.0 * kPi * h.fu);
+      h.q = std::exp(-p.M[p.ax[0]][p.ax[0]] / (2.0 * pp));
+      h.pad = 0.0;
+      p.hot.push_back(h);
+      p.aux.push_back(x);
+    }
+    br.p1 = (int)p.hot.size();
+    p.blocks.push_back(br);
+  }
+  p.nelem = eoff;
+  // class ranges (blocks are sorted by (L, la) so classes are contiguous)
+  for (int c = 0; c < 16; ++c) {
+    p.cls_b0[c] = 0;
+    p.cls_b1[c] = 0;
+  }
+  {
+    int b = 0, nb = (int)p.blocks.size();
+    while (b < nb) {
+      int la = in.sh_l[p.blocks[b].sa], lb = in.sh_l[p.blocks[b].sb];
+      int e = b;
+      while (e < nb && in.sh_l[p.blocks[e].sa] == la && in.sh_l[p.blocks[e].sb] == lb) ++e;
+      p.cls_b0[la * 4 + lb] = b;
+      p.cls_b1[la * 4 + lb] = e;
+      b = e;
+    }
+  }
+  for (int L = 0; L <= kMaxLsum; ++L) {
+    p.L_p0[L] = p.L_p1[L] = 0;
+  }
+  {
+    int64_t off = 0;
+    for (int L = 0; L <= 2 * kMaxL; ++L) {
+      int p0 = -1, p1 = -1;
+      for (int la = 0; la <= kMaxL; ++la) {
+        int lb = L - la;
+        if (lb < 0 || lb > la) continue;
+        int c = la * 4 + lb;
+        if (p.cls_b1[c] <= p.cls_b0[c]) continue;
+        int q0 = p.blocks[p.cls_b0[c]].p0, q1 = p.blocks[p.cls_b1[c] - 1].p1;
+        p0 = p0 < 0 ? q0 : std::min(p0, q0);
+        p1 = p1 < 0 ? q1 : std::max(p1, q1);
+      }
+      if (p0 < 0) p0 = p1 = 0;
+      p.L_p0[L] = p0;
+      p.L_p1[L] = p1;
+      p.dhat_off[L] = off;
+      off += (int64_t)(p1 - p0) * nherm(L);
+    }
+    p.dhat_off[kMaxLsum] = off;
+    p.dhat_size = off;
+  }
+  p.elem_blk.resize(p.nelem);
+  for (int b = 0; b < (int)p.blocks.size(); ++b) {
+    const BlockRec &br = p.blocks[b];
+    int n = ncart(in.sh_l[br.sa]) * ncart(in.sh_l[br.sb]);
+    for (int e = 0; e < n; ++e) p.elem_blk[br.eoff + e] = b;
+  }
+
+  // ---- phase tables
+  int nimg = (int)p.imgs.size();
+  p.phD.assign((size_t)nimg * p.nk * 2, 0.0);
+  p.phJ.assign((size_t)nimg * p.nk * 2, 0.0);
+  for (int i = 0; i < nimg; ++i)
+    for (int k = 0; k < p.nk; ++k) {
+      int km[3];
+      km[2] = k % in.kmesh[2];
+      km[1] = (k / in.kmesh[2]) % in.kmesh[1];
+      km[0] = k / (in.kmesh[2] * in.kmesh[1]);
+      // reduce the integer phase exactly before converting: k.L/2pi = sum_i km_i m_i / n_i
+      double t = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        long r = ((long)km[d] * p.imgs[i][d]) % in.kmesh[d];
+        t += (double)r / in.kmesh[d];
+      }
+      t -= std::nearbyint(t);
+      double c = std::cos(2.0 * kPi * t), s = std::sin(2.0 * kPi * t);
+      size_t o = ((size_t)i * p.nk + k) * 2;
+      p.phJ[o] = c;
+      p.phJ[o + 1] = s;
+      p.phD[o] = c / p.nk;
+      p.phD[o + 1] = s / p.nk;
+    }
+
+  // ---- J(k) gather lists per ordered shell pair
+  {
+    int ns = in.nshell;
+    std::vector<std::vector<GatherEnt>> lists((size_t)ns * ns);
+    for (int b = 0; b < (int)p.blocks.size(); ++b) {
+      const BlockRec &br = p.blocks[b];
+      lists[(size_t)br.sa * ns + br.sb].push_back({b, br.img, 0, 0});
+      if (br.w2) lists[(size_t)br.sb * ns + br.sa].push_back({b, br.img, 1, 0});
+    }
+    p.sp_off.assign((size_t)ns * ns + 1, 0);
+    p.sp_ent.clear();
+    for (size_t i = 0; i < lists.size(); ++i) {
+      p.sp_off[i] = (int)p.sp_ent.size();
+      for (auto &e : lists[i]) p.sp_ent.push_back(e);
+    }
+    p.sp_off[lists.size()] = (int)p.sp_ent.size();
+  }
+
+  // ---- Hermite -> relative monomial transform per degree:
+  // G_x^tx G_y^ty G_z^tz = sum_k T[t][k] n_u^ku n_v^kv n_w^kw, G_c = sum_j B[c][ax[j]] n_(ax j)
+  p.ttab.assign(kTTableSize, 0.0);
+  for (int d = 0; d <= kMaxLsum; ++d) {
+    int nc = ncart(d);
+    int t = 0;
+    for (int tx = d; tx >= 0; --tx)
+      for (int ty = d - tx; ty >= 0; --ty, ++t) {
+        int tz = d - tx - ty;
+        // polynomial as map (e0,e1,e2) -> coefficient
+        std::map<std::array<int, 3>, double> poly;
+        poly[{0, 0, 0}] = 1.0;
+        int tc[3] = {tx, ty, tz};
+        for (int c = 0; c < 3; ++c)
+          for (int r = 0; r < tc[c]; ++r) {
+            std::map<std::array<int, 3>, double> np;
+            for (auto &kv : poly)
+              for (int j = 0; j < 3; ++j) {
+                std::array<int, 3> e = kv.first;
+                e[j] += 1;
+                np[e] += kv.second * p.B[c][p.ax[j]];
+              }
+            poly.swap(np);
+          }
+        for (auto &kv : poly) {
+          int k = mono_index(kv.first[0], kv.first[1], kv.first[2]);
+          p.ttab[tblk_off(d) + t * nc + k] = kv.second;
+        }
+      }
+  }
+  return "";
+}
+
+}  // namespace pwdf

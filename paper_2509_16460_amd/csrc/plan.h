@@ -1,0 +1,72 @@
+// Host-side plan of libpwdf: everything that depends on the geometry, the basis
+// and the k-mesh but not on the density.
+#pragma once
+#include <array>
+#include <string>
+#include <vector>
+
+#include "pwdf_internal.h"
+
+namespace pwdf {
+
+struct PlanInput {
+  double lattice[9];
+  int natm;
+  std::vector<double> xyz;
+  int nshell;
+  std::vector<int> sh_atom, sh_l, sh_nprim;
+  std::vector<double> exps, coefs;
+  int kmesh[3];
+  double omega, eps_pair, eps_G, r_max;
+};
+
+struct Plan {
+  PlanInput in;
+  // geometry: A[c][i] = component c of a_i; B = 2 pi A^-T; M = B^T B
+  double A[3][3], B[3][3], M[3][3], vol;
+  int ax[3];  // relative axes in (u, v, w) order: u is the line axis
+  // basis
+  std::vector<int> sh_bf, sh_pr;
+  int nbf = 0, nk = 0;
+  std::vector<int> bf_shell, bf_comp;
+  // reciprocal space: segments of lines, padded to seg_len slots each
+  int seg_len = 8;
+  std::vector<SegDesc> segs;
+  std::vector<double> slot_v;       // v(G) per slot, 0 on padding
+  std::vector<int> slot_miller;     // [nslot][3] in the original axis order (padding: 0,0,0)
+  std::vector<int> valid_slots;     // slots holding a G, in walk order
+  int64_t nG_full = 0;              // |G set| including -G
+  // lattice images of the pair list
+  std::vector<std::array<int, 3>> imgs;
+  // unique blocks and primitive pairs, sorted by (L = la+lb, la, sa, sb, m)
+  std::vector<BlockRec> blocks;
+  std::vector<PairHot> hot;
+  std::vector<PairAux> aux;
+  int cls_b0[16], cls_b1[16];  // block range of class (la, lb), index la*4 + lb
+  int L_p0[kMaxLsum + 1], L_p1[kMaxLsum + 1];  // pair range of class L
+  int64_t dhat_off[kMaxLsum + 1];             // offset of class L in a per-density coefficient array
+  int64_t dhat_size = 0;
+  int64_t nelem = 0;                          // sum over blocks of ncart(la) ncart(lb)
+  std::vector<int> elem_blk;                  // element -> block
+  // phase tables [nimg][nk] complex: w_k e^{ik.L} and e^{ik.L}
+  std::vector<double> phD, phJ;
+  // J(k) gather lists per ordered shell pair
+  std::vector<int> sp_off;
+  std::vector<GatherEnt> sp_ent;
+  // block-diagonal Hermite -> relative-monomial transform (degree blocks), and
+  // the sign of (-i)^{|k|} folded into the rho coefficients / J moments
+  std::vector<double> ttab;
+
+  int nseg() const { return (int)segs.size(); }
+  int nslot() const { return (int)segs.size() * seg_len; }
+  int npairs() const { return (int)hot.size(); }
+  int nimg() const { return (int)imgs.size(); }
+};
+
+// Validates and builds; returns an empty string on success, else the reason.
+std::string build_plan(const PlanInput &in, int seg_len, Plan &out);
+
+// Rebuild only the reciprocal-space segments for another segment length.
+void build_segments(Plan &p, int seg_len);
+
+}  // namespace pwdf

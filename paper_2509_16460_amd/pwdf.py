@@ -1,0 +1,223 @@
+"""Python binding of libpwdf (the C ABI in include/pwdf.h).
+
+Argument marshalling only: every step of the long-range J build runs in the HIP
+kernels of libpwdf.so.  PyTorch supplies device memory and the current HIP
+stream.  If the library is missing this module raises at import of the
+library; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libpwdf.so")
+
+PWDF_FP64 = 0
+PWDF_FP32_MFMA = 1
+
+_STATUS = {0: "PWDF_OK", -1: "PWDF_EINVAL", -2: "PWDF_ENOMEM", -3: "PWDF_EDEVICE",
+           -4: "PWDF_EUNSUPPORTED", -5: "PWDF_ENONFINITE", -6: "PWDF_ESTATE"}
+
+EXPORTED = ["pwdf_create", "pwdf_query", "pwdf_build_j", "pwdf_get_rhoG", "pwdf_grad",
+            "pwdf_autotune", "pwdf_last_error", "pwdf_destroy", "pwdf_plan_stats"]
+
+
+class PwdfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Screen(ctypes.Structure):
+    _fields_ = [("eps_pair", ctypes.c_double), ("eps_G", ctypes.c_double), ("r_max", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("npairs_by_class", ctypes.c_int64 * 16), ("nG", ctypes.c_int64), ("npairs", ctypes.c_int64),
+                ("nbf", ctypes.c_int64), ("nk", ctypes.c_int64), ("nimg", ctypes.c_int64),
+                ("nblocks", ctypes.c_int64), ("nseg", ctypes.c_int64), ("pairG_evals", ctypes.c_double),
+                ("t_us", ctypes.c_double * 8)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("npairs_by_class", "t_us")}
+        d["npairs_by_class"] = {f"{c // 4}{c % 4}": int(self.npairs_by_class[c]) for c in range(16)
+                                if self.npairs_by_class[c]}
+        return d
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError(f"libpwdf.so is not built ({LIBPATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIBPATH)
+        vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        L.pwdf_create.restype = ctypes.c_int
+        L.pwdf_create.argtypes = [ctypes.POINTER(vp), dp, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, dp, dp, ip,
+                                  ctypes.c_double, ctypes.POINTER(Screen), ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.pwdf_plan_stats.restype = ctypes.c_int
+        L.pwdf_plan_stats.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, dp, dp, ip,
+                                      ctypes.c_double, ctypes.POINTER(Screen), ctypes.POINTER(Stats)]
+        L.pwdf_query.restype = ctypes.c_int
+        L.pwdf_query.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.pwdf_build_j.restype = ctypes.c_int
+        L.pwdf_build_j.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+        L.pwdf_get_rhoG.restype = ctypes.c_int
+        L.pwdf_get_rhoG.argtypes = [vp, ctypes.c_int, vp, vp, ip, vp]
+        L.pwdf_grad.restype = ctypes.c_int
+        L.pwdf_grad.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+        L.pwdf_autotune.restype = ctypes.c_int
+        L.pwdf_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p]
+        L.pwdf_last_error.restype = ctypes.c_char_p
+        L.pwdf_last_error.argtypes = [vp]
+        L.pwdf_destroy.restype = None
+        L.pwdf_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _basis_arrays(prob):
+    return dict(
+        lat=np.ascontiguousarray(prob.lattice, dtype=np.float64).ravel(),
+        xyz=np.ascontiguousarray(prob.xyz, dtype=np.float64).ravel(),
+        sa=np.ascontiguousarray(prob.shell_atom, dtype=np.int32),
+        sl=np.ascontiguousarray(prob.shell_l, dtype=np.int32),
+        sn=np.ascontiguousarray(prob.shell_nprim, dtype=np.int32),
+        ex=np.ascontiguousarray(prob.exps, dtype=np.float64),
+        co=np.ascontiguousarray(prob.coefs, dtype=np.float64),
+        km=np.ascontiguousarray(prob.kmesh, dtype=np.int32),
+    )
+
+
+def plan_stats(prob) -> dict:
+    """Host-only plan sizes (no device needed)."""
+    a = _basis_arrays(prob)
+    st = Stats()
+    scr = Screen(prob.eps_pair, prob.eps_G, prob.r_max)
+    rc = lib().pwdf_plan_stats(_dp(a["lat"]), prob.natm, _dp(a["xyz"]), prob.nshell, _ip(a["sa"]), _ip(a["sl"]),
+                               _ip(a["sn"]), _dp(a["ex"]), _dp(a["co"]), _ip(a["km"]), float(prob.omega),
+                               ctypes.byref(scr), ctypes.byref(st))
+    if rc != 0:
+        raise PwdfError(rc, lib().pwdf_last_error(None).decode())
+    return st.as_dict()
+
+
+class LongRangeJ:
+    """One plan (geometry, basis, k-mesh, omega) on one device."""
+
+    def __init__(self, prob, precision: int = PWDF_FP64, max_ndm: int = 1, device: int = 0):
+        self.prob = prob
+        self.precision = precision
+        self.max_ndm = max_ndm
+        self.device = device
+        a = _basis_arrays(prob)
+        self._keep = a
+        scr = Screen(prob.eps_pair, prob.eps_G, prob.r_max)
+        h = ctypes.c_void_p()
+        rc = lib().pwdf_create(ctypes.byref(h), _dp(a["lat"]), prob.natm, _dp(a["xyz"]), prob.nshell, _ip(a["sa"]),
+                               _ip(a["sl"]), _ip(a["sn"]), _dp(a["ex"]), _dp(a["co"]), _ip(a["km"]),
+                               float(prob.omega), ctypes.byref(scr), int(precision), int(max_ndm), int(device))
+        if rc != 0:
+            raise PwdfError(rc, lib().pwdf_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pwdf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, rc):
+        raise PwdfError(rc, lib().pwdf_last_error(self._h).decode())
+
+    def stats(self) -> dict:
+        st = Stats()
+        rc = lib().pwdf_query(self._h, ctypes.byref(st))
+        if rc != 0:
+            self._err(rc)
+        return st.as_dict()
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        s = torch.cuda.current_stream() if stream is None else stream
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def _check_D(self, Dk):
+        import torch
+        p = self.prob
+        if Dk.dtype != torch.complex128 or not Dk.is_cuda or not Dk.is_contiguous():
+            raise ValueError("Dk must be a contiguous complex128 CUDA tensor")
+        if Dk.dim() == 3:
+            Dk = Dk.unsqueeze(0)
+        if tuple(Dk.shape[1:]) != (p.nk, p.nbf, p.nbf):
+            raise ValueError(f"Dk shape {tuple(Dk.shape)} != [ndm, {p.nk}, {p.nbf}, {p.nbf}]")
+        return Dk
+
+    def build_j(self, Dk, Jk=None, EJ=None, stream=None):
+        """Dk: complex128 [ndm][nk][nbf][nbf] (or [nk][nbf][nbf]) on the device.
+        Returns (Jk, EJ) device tensors; enqueued on `stream` (default: current)."""
+        import torch
+        Dk = self._check_D(Dk)
+        ndm = Dk.shape[0]
+        if Jk is None:
+            Jk = torch.empty_like(Dk)
+        if EJ is None:
+            EJ = torch.empty(ndm, dtype=torch.float64, device=Dk.device)
+        rc = lib().pwdf_build_j(self._h, ndm, ctypes.c_void_p(Dk.data_ptr()), ctypes.c_void_p(Jk.data_ptr()),
+                                ctypes.c_void_p(EJ.data_ptr()), self._stream(stream))
+        if rc != 0:
+            self._err(rc)
+        return Jk, EJ
+
+    def get_rhoG(self, Dk, stream=None):
+        """rho(G) on the half space the kernels walk, and the Miller indices (host)."""
+        import torch
+        Dk = self._check_D(Dk)
+        ndm = Dk.shape[0]
+        nh = self.stats()["nG"] // 2
+        rho = torch.empty((ndm, nh), dtype=torch.complex128, device=Dk.device)
+        miller = np.zeros((nh, 3), dtype=np.int32)
+        rc = lib().pwdf_get_rhoG(self._h, ndm, ctypes.c_void_p(Dk.data_ptr()), ctypes.c_void_p(rho.data_ptr()),
+                                 _ip(miller), self._stream(stream))
+        if rc != 0:
+            self._err(rc)
+        return rho, miller
+
+    def grad(self, Dk, stream=None):
+        """dE_J/dR [ndm][natm][3] and E_J [ndm] (device tensors)."""
+        import torch
+        Dk = self._check_D(Dk)
+        ndm = Dk.shape[0]
+        g = torch.empty((ndm, self.prob.natm, 3), dtype=torch.float64, device=Dk.device)
+        EJ = torch.empty(ndm, dtype=torch.float64, device=Dk.device)
+        rc = lib().pwdf_grad(self._h, ndm, ctypes.c_void_p(Dk.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                             ctypes.c_void_p(EJ.data_ptr()), self._stream(stream))
+        if rc != 0:
+            self._err(rc)
+        return g, EJ
+
+    def autotune(self, ndm: int = 1, cache_path: Optional[str] = None):
+        rc = lib().pwdf_autotune(self._h, int(ndm), cache_path.encode() if cache_path else None)
+        if rc != 0:
+            self._err(rc)
