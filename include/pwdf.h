@@ -177,6 +177,24 @@ pwdf_status pwdf_grad(pwdf_ctx *ctx, int ndm, const double *Dk, double *dEdR, do
  * cache_path may be NULL (no persistence).  Synchronous. */
 pwdf_status pwdf_autotune(pwdf_ctx *ctx, int ndm, const char *cache_path);
 
+/* Diagnostics: per-launch HIP-event timing on the caller's stream.
+ * pwdf_profile_enable(ctx, 1) resets the counters and brackets every later
+ * kernel launch of ctx with a pair of events on the stream it runs on
+ * (creating events as needed, so keep it off under graph capture);
+ * pwdf_profile_read synchronises on the recorded events and returns, per
+ * kernel name, the launch count, the summed milliseconds and the summed work
+ * units (pair-G evaluations for rho_L* / jpass_L*, complex multiply-adds for
+ * phase_d, outputs for phase_j, primitive pairs for transform / back).
+ * out may be NULL to query the count; *n receives the number of names. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double ms;
+  double units;
+} pwdf_kprof;
+pwdf_status pwdf_profile_enable(pwdf_ctx *ctx, int on);
+pwdf_status pwdf_profile_read(pwdf_ctx *ctx, pwdf_kprof *out, int max, int *n);
+
 /* Message of the last failure on ctx (NULL: last failed pwdf_create of this thread). */
 const char *pwdf_last_error(const pwdf_ctx *ctx);
 

@@ -15,8 +15,25 @@
 
 using namespace pwdf;
 
+// Per-launch HIP-event timing (diagnostic mode, off by default).
+struct ProfRec {
+  int id;
+  hipEvent_t a, b;
+  double units;
+};
+struct ProfAgg {
+  int64_t launches = 0;
+  double ms = 0.0, units = 0.0;
+};
+
 struct pwdf_ctx {
   Plan plan;
+  bool prof_on = false;
+  std::vector<ProfRec> prof_recs;
+  std::vector<hipEvent_t> prof_pool;
+  size_t prof_next = 0;
+  std::vector<std::string> prof_names;
+  std::vector<ProfAgg> prof_agg;
   Dev dev;
   std::vector<void *> owned;  // device allocations
   double *Escr = nullptr;     // [max_ndm] energies of diagnostic calls
@@ -126,12 +143,97 @@ pwdf_status validate_ndm(pwdf_ctx *c, int ndm) {
   return PWDF_OK;
 }
 
+int prof_id(pwdf_ctx *c, const std::string &name) {
+  for (size_t i = 0; i < c->prof_names.size(); ++i)
+    if (c->prof_names[i] == name) return (int)i;
+  c->prof_names.push_back(name);
+  c->prof_agg.emplace_back();
+  return (int)c->prof_names.size() - 1;
+}
+
+hipEvent_t prof_event(pwdf_ctx *c) {
+  if (c->prof_next == c->prof_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->prof_pool.push_back(e);
+  }
+  return c->prof_pool[c->prof_next++];
+}
+
+// Runs one launch; in profiling mode brackets it with events on the same stream.
+template <class F>
+pwdf_status step(pwdf_ctx *c, const char *name, double units, hipStream_t st, F &&launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (c->prof_on) {
+    a = prof_event(c);
+    b = prof_event(c);
+    if (a) (void)hipEventRecord(a, st);
+  }
+  hipError_t e = launch();
+  if (e != hipSuccess) return hip_fail(c, e, name);
+  if (c->prof_on && a && b) {
+    (void)hipEventRecord(b, st);
+    c->prof_recs.push_back({prof_id(c, name), a, b, units});
+  }
+  return PWDF_OK;
+}
+
+int np_L(const Plan &p, int L) { return p.L_p1[L] - p.L_p0[L]; }
+
 pwdf_status run_to_rho(pwdf_ctx *c, int ndm, const double *Dk, double *EJ, hipStream_t st) {
-  hipError_t e;
-  if ((e = launch_phase_d(c->dev, Dk, ndm, st)) != hipSuccess) return hip_fail(c, e, "phase D");
-  if ((e = launch_transform(c->dev, ndm, st)) != hipSuccess) return hip_fail(c, e, "density transform");
-  if ((e = launch_rho(c->dev, ndm, st)) != hipSuccess) return hip_fail(c, e, "rho");
-  if ((e = launch_reduce(c->dev, ndm, EJ, st)) != hipSuccess) return hip_fail(c, e, "reduce");
+  const Plan &p = c->plan;
+  const Dev &d = c->dev;
+  const double nGh = (double)(p.nG_full / 2);
+  pwdf_status s;
+  if ((s = step(c, "phase_d", (double)p.nelem * p.nk * ndm, st, [&] { return launch_phase_d(d, Dk, ndm, st); })) !=
+      PWDF_OK)
+    return s;
+  char name[32];
+  for (int la = 0; la <= kMaxL; ++la)
+    for (int lb = 0; lb <= la; ++lb) {
+      int cl = la * 4 + lb;
+      if (p.cls_b1[cl] <= p.cls_b0[cl]) continue;
+      std::snprintf(name, sizeof name, "transform_%d%d", la, lb);
+      double units = (double)(p.blocks[p.cls_b1[cl] - 1].p1 - p.blocks[p.cls_b0[cl]].p0) * ndm;
+      if ((s = step(c, name, units, st, [&] { return launch_transform_cls(d, la, lb, ndm, st); })) != PWDF_OK)
+        return s;
+    }
+  for (int L = 0; L <= 2 * kMaxL; ++L) {
+    if (np_L(p, L) <= 0) continue;
+    std::snprintf(name, sizeof name, "rho_L%d", L);
+    if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, st, [&] { return launch_rho_L(d, L, ndm, st); })) !=
+        PWDF_OK)
+      return s;
+  }
+  if ((s = step(c, "reduce", (double)p.nslot() * ndm, st, [&] { return launch_reduce(d, ndm, EJ, st); })) != PWDF_OK)
+    return s;
+  return PWDF_OK;
+}
+
+pwdf_status run_from_V(pwdf_ctx *c, int ndm, double *Jk, hipStream_t st) {
+  const Plan &p = c->plan;
+  const Dev &d = c->dev;
+  const double nGh = (double)(p.nG_full / 2);
+  pwdf_status s;
+  char name[32];
+  for (int L = 0; L <= 2 * kMaxL; ++L) {
+    if (np_L(p, L) <= 0) continue;
+    std::snprintf(name, sizeof name, "jpass_L%d", L);
+    if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, st, [&] { return launch_jpass_L(d, L, ndm, st); })) !=
+        PWDF_OK)
+      return s;
+  }
+  for (int la = 0; la <= kMaxL; ++la)
+    for (int lb = 0; lb <= la; ++lb) {
+      int cl = la * 4 + lb;
+      if (p.cls_b1[cl] <= p.cls_b0[cl]) continue;
+      std::snprintf(name, sizeof name, "back_%d%d", la, lb);
+      double units = (double)(p.blocks[p.cls_b1[cl] - 1].p1 - p.blocks[p.cls_b0[cl]].p0) * ndm;
+      if ((s = step(c, name, units, st, [&] { return launch_back_cls(d, la, lb, ndm, st); })) != PWDF_OK) return s;
+    }
+  if ((s = step(c, "phase_j", (double)p.nk * p.nbf * (double)p.nbf * ndm, st,
+                [&] { return launch_phase_j(d, ndm, Jk, st); })) != PWDF_OK)
+    return s;
   return PWDF_OK;
 }
 
@@ -352,10 +454,7 @@ pwdf_status pwdf_build_j(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, dou
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   if ((s = run_to_rho(c, ndm, Dk, EJ, st)) != PWDF_OK) return s;
-  if ((e = launch_jpass(c->dev, ndm, st)) != hipSuccess) return hip_fail(c, e, "J pass");
-  if ((e = launch_backtransform(c->dev, ndm, st)) != hipSuccess) return hip_fail(c, e, "back transform");
-  if ((e = launch_phase_j(c->dev, ndm, Jk, st)) != hipSuccess) return hip_fail(c, e, "phase J");
-  return PWDF_OK;
+  return run_from_V(c, ndm, Jk, st);
 }
 
 pwdf_status pwdf_get_rhoG(pwdf_ctx *c, int ndm, const double *Dk, double *rhoG, int *miller, void *stream) {
@@ -403,11 +502,53 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
   return PWDF_OK;
 }
 
+pwdf_status pwdf_profile_enable(pwdf_ctx *c, int on) {
+  if (!c) return PWDF_EINVAL;
+  c->prof_on = on != 0;
+  c->prof_recs.clear();
+  c->prof_next = 0;
+  for (auto &a : c->prof_agg) a = ProfAgg();
+  return PWDF_OK;
+}
+
+pwdf_status pwdf_profile_read(pwdf_ctx *c, pwdf_kprof *out, int max, int *n) {
+  if (!c || !n) return PWDF_EINVAL;
+  (void)hipSetDevice(c->device);
+  for (const ProfRec &r : c->prof_recs) {
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e != hipSuccess) return hip_fail(c, e, "profile read");
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return hip_fail(c, e, "profile read");
+    ProfAgg &g = c->prof_agg[r.id];
+    g.launches += 1;
+    g.ms += ms;
+    g.units += r.units;
+  }
+  c->prof_recs.clear();
+  c->prof_next = 0;
+  int k = 0;
+  for (size_t i = 0; i < c->prof_names.size(); ++i) {
+    if (c->prof_agg[i].launches == 0) continue;
+    if (out && k < max) {
+      std::memset(&out[k], 0, sizeof(out[k]));
+      std::snprintf(out[k].name, sizeof(out[k].name), "%s", c->prof_names[i].c_str());
+      out[k].launches = c->prof_agg[i].launches;
+      out[k].ms = c->prof_agg[i].ms;
+      out[k].units = c->prof_agg[i].units;
+    }
+    ++k;
+  }
+  *n = k;
+  return PWDF_OK;
+}
+
 const char *pwdf_last_error(const pwdf_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
 void pwdf_destroy(pwdf_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
   free_device(c);
   delete c;
 }

@@ -49,11 +49,11 @@ struct Dev {
 };
 
 hipError_t launch_phase_d(const Dev &d, const double *Dk, int ndm, hipStream_t st);
-hipError_t launch_transform(const Dev &d, int ndm, hipStream_t st);
-hipError_t launch_rho(const Dev &d, int ndm, hipStream_t st);
+hipError_t launch_transform_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st);
+hipError_t launch_rho_L(const Dev &d, int L, int ndm, hipStream_t st);
 hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st);
-hipError_t launch_jpass(const Dev &d, int ndm, hipStream_t st);
-hipError_t launch_backtransform(const Dev &d, int ndm, hipStream_t st);
+hipError_t launch_jpass_L(const Dev &d, int L, int ndm, hipStream_t st);
+hipError_t launch_back_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st);
 hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, hipStream_t st);
 
 }  // namespace pwdf

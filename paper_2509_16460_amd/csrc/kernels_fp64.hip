@@ -577,13 +577,20 @@ static hipError_t transform_one(const Dev &d, int ndm, hipStream_t st) {
   return hipSuccess;
 }
 
-hipError_t launch_transform(const Dev &d, int ndm, hipStream_t st) {
-  hipError_t e;
-#define T1(A, B) \
-  if ((e = transform_one<A, B>(d, ndm, st)) != hipSuccess) return e;
-  T1(0, 0) T1(1, 0) T1(1, 1) T1(2, 0) T1(2, 1) T1(2, 2) T1(3, 0) T1(3, 1) T1(3, 2) T1(3, 3)
-#undef T1
-  return hipSuccess;
+hipError_t launch_transform_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st) {
+  switch (la * 4 + lb) {
+    case 0: return transform_one<0, 0>(d, ndm, st);
+    case 4: return transform_one<1, 0>(d, ndm, st);
+    case 5: return transform_one<1, 1>(d, ndm, st);
+    case 8: return transform_one<2, 0>(d, ndm, st);
+    case 9: return transform_one<2, 1>(d, ndm, st);
+    case 10: return transform_one<2, 2>(d, ndm, st);
+    case 12: return transform_one<3, 0>(d, ndm, st);
+    case 13: return transform_one<3, 1>(d, ndm, st);
+    case 14: return transform_one<3, 2>(d, ndm, st);
+    case 15: return transform_one<3, 3>(d, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int L, int SEG>
@@ -599,23 +606,24 @@ static hipError_t rho_one(const Dev &d, int ndm, hipStream_t st) {
 }
 
 template <int SEG>
-static hipError_t rho_all(const Dev &d, int ndm, hipStream_t st) {
-  hipError_t e;
-  if ((e = rho_one<0, SEG>(d, ndm, st)) != hipSuccess) return e;
-  if ((e = rho_one<1, SEG>(d, ndm, st)) != hipSuccess) return e;
-  if ((e = rho_one<2, SEG>(d, ndm, st)) != hipSuccess) return e;
-  if ((e = rho_one<3, SEG>(d, ndm, st)) != hipSuccess) return e;
-  if ((e = rho_one<4, SEG>(d, ndm, st)) != hipSuccess) return e;
-  if ((e = rho_one<5, SEG>(d, ndm, st)) != hipSuccess) return e;
-  if ((e = rho_one<6, SEG>(d, ndm, st)) != hipSuccess) return e;
-  return hipSuccess;
+static hipError_t rho_L(const Dev &d, int L, int ndm, hipStream_t st) {
+  switch (L) {
+    case 0: return rho_one<0, SEG>(d, ndm, st);
+    case 1: return rho_one<1, SEG>(d, ndm, st);
+    case 2: return rho_one<2, SEG>(d, ndm, st);
+    case 3: return rho_one<3, SEG>(d, ndm, st);
+    case 4: return rho_one<4, SEG>(d, ndm, st);
+    case 5: return rho_one<5, SEG>(d, ndm, st);
+    case 6: return rho_one<6, SEG>(d, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-hipError_t launch_rho(const Dev &d, int ndm, hipStream_t st) {
+hipError_t launch_rho_L(const Dev &d, int L, int ndm, hipStream_t st) {
   switch (d.seg_len) {
-    case 4: return rho_all<4>(d, ndm, st);
-    case 8: return rho_all<8>(d, ndm, st);
-    case 16: return rho_all<16>(d, ndm, st);
+    case 4: return rho_L<4>(d, L, ndm, st);
+    case 8: return rho_L<8>(d, L, ndm, st);
+    case 16: return rho_L<16>(d, L, ndm, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -642,23 +650,24 @@ static hipError_t j_one(const Dev &d, int ndm, hipStream_t st) {
 }
 
 template <int SEG>
-static hipError_t j_all(const Dev &d, int ndm, hipStream_t st) {
-  hipError_t e;
-  if ((e = j_one<0, SEG>(d, ndm, st)) != hipSuccess) return e;
-  if ((e = j_one<1, SEG>(d, ndm, st)) != hipSuccess) return e;
-  if ((e = j_one<2, SEG>(d, ndm, st)) != hipSuccess) return e;
-  if ((e = j_one<3, SEG>(d, ndm, st)) != hipSuccess) return e;
-  if ((e = j_one<4, SEG>(d, ndm, st)) != hipSuccess) return e;
-  if ((e = j_one<5, SEG>(d, ndm, st)) != hipSuccess) return e;
-  if ((e = j_one<6, SEG>(d, ndm, st)) != hipSuccess) return e;
-  return hipSuccess;
+static hipError_t j_L(const Dev &d, int L, int ndm, hipStream_t st) {
+  switch (L) {
+    case 0: return j_one<0, SEG>(d, ndm, st);
+    case 1: return j_one<1, SEG>(d, ndm, st);
+    case 2: return j_one<2, SEG>(d, ndm, st);
+    case 3: return j_one<3, SEG>(d, ndm, st);
+    case 4: return j_one<4, SEG>(d, ndm, st);
+    case 5: return j_one<5, SEG>(d, ndm, st);
+    case 6: return j_one<6, SEG>(d, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-hipError_t launch_jpass(const Dev &d, int ndm, hipStream_t st) {
+hipError_t launch_jpass_L(const Dev &d, int L, int ndm, hipStream_t st) {
   switch (d.seg_len) {
-    case 4: return j_all<4>(d, ndm, st);
-    case 8: return j_all<8>(d, ndm, st);
-    case 16: return j_all<16>(d, ndm, st);
+    case 4: return j_L<4>(d, L, ndm, st);
+    case 8: return j_L<8>(d, L, ndm, st);
+    case 16: return j_L<16>(d, L, ndm, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -676,13 +685,20 @@ static hipError_t back_one(const Dev &d, int ndm, hipStream_t st) {
   return hipSuccess;
 }
 
-hipError_t launch_backtransform(const Dev &d, int ndm, hipStream_t st) {
-  hipError_t e;
-#define B1(A, B) \
-  if ((e = back_one<A, B>(d, ndm, st)) != hipSuccess) return e;
-  B1(0, 0) B1(1, 0) B1(1, 1) B1(2, 0) B1(2, 1) B1(2, 2) B1(3, 0) B1(3, 1) B1(3, 2) B1(3, 3)
-#undef B1
-  return hipSuccess;
+hipError_t launch_back_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st) {
+  switch (la * 4 + lb) {
+    case 0: return back_one<0, 0>(d, ndm, st);
+    case 4: return back_one<1, 0>(d, ndm, st);
+    case 5: return back_one<1, 1>(d, ndm, st);
+    case 8: return back_one<2, 0>(d, ndm, st);
+    case 9: return back_one<2, 1>(d, ndm, st);
+    case 10: return back_one<2, 2>(d, ndm, st);
+    case 12: return back_one<3, 0>(d, ndm, st);
+    case 13: return back_one<3, 1>(d, ndm, st);
+    case 14: return back_one<3, 2>(d, ndm, st);
+    case 15: return back_one<3, 3>(d, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, hipStream_t st) {

@@ -23,7 +23,8 @@ _STATUS = {0: "PWDF_OK", -1: "PWDF_EINVAL", -2: "PWDF_ENOMEM", -3: "PWDF_EDEVICE
            -4: "PWDF_EUNSUPPORTED", -5: "PWDF_ENONFINITE", -6: "PWDF_ESTATE"}
 
 EXPORTED = ["pwdf_create", "pwdf_query", "pwdf_build_j", "pwdf_get_rhoG", "pwdf_grad",
-            "pwdf_autotune", "pwdf_last_error", "pwdf_destroy", "pwdf_plan_stats"]
+            "pwdf_autotune", "pwdf_last_error", "pwdf_destroy", "pwdf_plan_stats",
+            "pwdf_profile_enable", "pwdf_profile_read"]
 
 
 class PwdfError(RuntimeError):
@@ -47,6 +48,11 @@ class Stats(ctypes.Structure):
         d["npairs_by_class"] = {f"{c // 4}{c % 4}": int(self.npairs_by_class[c]) for c in range(16)
                                 if self.npairs_by_class[c]}
         return d
+
+
+class KProf(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("units", ctypes.c_double)]
 
 
 _lib = None
@@ -75,6 +81,10 @@ def lib():
         L.pwdf_grad.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
         L.pwdf_autotune.restype = ctypes.c_int
         L.pwdf_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p]
+        L.pwdf_profile_enable.restype = ctypes.c_int
+        L.pwdf_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.pwdf_profile_read.restype = ctypes.c_int
+        L.pwdf_profile_read.argtypes = [vp, ctypes.POINTER(KProf), ctypes.c_int, ip]
         L.pwdf_last_error.restype = ctypes.c_char_p
         L.pwdf_last_error.argtypes = [vp]
         L.pwdf_destroy.restype = None
@@ -216,6 +226,24 @@ class LongRangeJ:
         if rc != 0:
             self._err(rc)
         return g, EJ
+
+    def profile_enable(self, on: bool = True):
+        rc = lib().pwdf_profile_enable(self._h, 1 if on else 0)
+        if rc != 0:
+            self._err(rc)
+
+    def profile_read(self) -> dict:
+        """{kernel name: {"launches", "ms", "units"}} accumulated since profile_enable."""
+        n = ctypes.c_int(0)
+        rc = lib().pwdf_profile_read(self._h, None, 0, ctypes.byref(n))
+        if rc != 0:
+            self._err(rc)
+        arr = (KProf * max(1, n.value))()
+        rc = lib().pwdf_profile_read(self._h, arr, n.value, ctypes.byref(n))
+        if rc != 0:
+            self._err(rc)
+        return {arr[i].name.decode(): dict(launches=int(arr[i].launches), ms=float(arr[i].ms),
+                                           units=float(arr[i].units)) for i in range(n.value)}
 
     def autotune(self, ndm: int = 1, cache_path: Optional[str] = None):
         rc = lib().pwdf_autotune(self._h, int(ndm), cache_path.encode() if cache_path else None)

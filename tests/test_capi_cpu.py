@@ -1,0 +1,124 @@
+"""C ABI checks that need no GPU: symbols, host-side validation, host plan.
+
+The plan counts are compared with the oracle's own enumeration of the G set
+and of the full pair list (every (a,b,L) and its mirror (b,a,-L)); the
+library keeps one representative per mirror pair, so full = 2 unique - diag.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_16460_amd import pwdf, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "pwdf.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pwdf_[A-Za-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(pwdf.LIBPATH)
+    names = declared_functions()
+    assert "pwdf_build_j" in names and "pwdf_create" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(pwdf.EXPORTED) == set(names)
+
+
+def n_diag_pairs(prob):
+    # primitive pairs of the (s, s, L=0) blocks: nprim^2 per shell
+    return int(np.sum(prob.shell_nprim.astype(np.int64) ** 2))
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 4, 5])
+def test_plan_matches_oracle_enumeration(cfg):
+    prob = synth.config_problem(cfg)
+    s = pwdf.plan_stats(prob)
+    o = O.sizes(prob)
+    assert s["nG"] == o["nG"]
+    assert 2 * s["npairs"] - n_diag_pairs(prob) == o["npairs"]
+    assert s["nbf"] == o["nbf"] and s["nk"] == o["nk"]
+
+
+def test_plan_contracted_and_rmax():
+    p = synth.small_problem(kind="c", seed=3, kmesh=(2, 1, 1), lmax=2, natm=3, r_max=6.0, nper=2)
+    # make the first shell a two-primitive contraction
+    p = p.with_(shell_nprim=np.concatenate([[2], p.shell_nprim[2:]]).astype(np.int32),
+                shell_atom=np.concatenate([[p.shell_atom[0]], p.shell_atom[2:]]).astype(np.int32),
+                shell_l=np.concatenate([[p.shell_l[0]], p.shell_l[2:]]).astype(np.int32))
+    s = pwdf.plan_stats(p)
+    o = O.sizes(p)
+    assert s["nG"] == o["nG"]
+    assert 2 * s["npairs"] - n_diag_pairs(p) == o["npairs"]
+
+
+def bad(prob, **kw):
+    return prob.with_(**kw)
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (dict(omega=0.0), "PWDF_EINVAL"),
+    (dict(omega=float("nan")), "PWDF_EINVAL"),
+    (dict(eps_pair=0.0), "PWDF_EINVAL"),
+    (dict(eps_G=1.5), "PWDF_EINVAL"),
+    (dict(kmesh=(0, 1, 1)), "PWDF_EINVAL"),
+    (dict(lattice=np.array([[1.0, 0, 0], [2.0, 0, 0], [0, 0, 1.0]])), "PWDF_EINVAL"),
+    (dict(shell_l=None), "PWDF_EUNSUPPORTED"),
+    (dict(exps=None), "PWDF_EINVAL"),
+    (dict(shell_atom=None), "PWDF_EINVAL"),
+])
+def test_host_validation(mutate, status):
+    prob = synth.small_problem(kind="v", seed=4, lmax=1, natm=2)
+    if "shell_l" in mutate:
+        sl = prob.shell_l.copy()
+        sl[0] = 4
+        mutate = dict(shell_l=sl)
+    if "exps" in mutate:
+        ex = prob.exps.copy()
+        ex[1] = -1.0
+        mutate = dict(exps=ex)
+    if "shell_atom" in mutate:
+        sa = prob.shell_atom.copy()
+        sa[0] = 7
+        mutate = dict(shell_atom=sa)
+    with pytest.raises(pwdf.PwdfError) as ei:
+        pwdf.plan_stats(bad(prob, **mutate))
+    assert status in str(ei.value)
+    # the same argument is rejected by pwdf_create before any device is touched
+    with pytest.raises(pwdf.PwdfError) as ei2:
+        pwdf.LongRangeJ(bad(prob, **mutate))
+    assert status in str(ei2.value)
+
+
+def test_create_null_and_ndm_arguments():
+    L = pwdf.lib()
+    h = ctypes.c_void_p()
+    scr = pwdf.Screen(1e-12, 1e-12, 0.0)
+    rc = L.pwdf_create(ctypes.byref(h), None, 1, None, 1, None, None, None, None, None, None, 0.5,
+                       ctypes.byref(scr), 0, 1, 0)
+    assert rc == -1 and b"NULL" in L.pwdf_last_error(None)
+    prob = synth.small_problem(kind="n", seed=4, lmax=1, natm=2)
+    with pytest.raises(pwdf.PwdfError, match="max_ndm"):
+        pwdf.LongRangeJ(prob, max_ndm=0)
+    with pytest.raises(pwdf.PwdfError, match="PWDF_EUNSUPPORTED"):
+        pwdf.LongRangeJ(prob, precision=7)
+    # NULL context is rejected by every entry point; destroy(NULL) is a no-op
+    assert L.pwdf_build_j(None, 1, None, None, None, None) == -1
+    assert L.pwdf_grad(None, 1, None, None, None, None) == -1
+    L.pwdf_destroy(None)
+
+
+def test_create_without_device_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    prob = synth.small_problem(kind="d", seed=4, lmax=1, natm=2)
+    with pytest.raises(pwdf.PwdfError, match="PWDF_EDEVICE"):
+        pwdf.LongRangeJ(prob)
