@@ -94,14 +94,14 @@ void free_device(pwdf_ctx *c) {
 // the class's pair-G work.
 void choose_shapes(const Plan &p, Dev &d, int target_waves) {
   const int SEG = p.seg_len;
-  d.rho_bs = 64 * std::min(4, std::max(1, (p.nseg() + 63) / 64));
+  d.rho_bs = 256;  // 64 segments x 4 waves sharing them
   double wsum = 0.0, wL[kMaxLsum + 1];
   for (int L = 0; L <= kMaxLsum; ++L) {
     int np = p.L_p1[L] - p.L_p0[L];
     wL[L] = np > 0 ? (double)np * (2.0 * L + 10.0 + (70.0 + nherm(L)) / SEG) : 0.0;
     wsum += wL[L];
   }
-  const int rho_waves_per_chunk = ((p.nseg() + d.rho_bs - 1) / d.rho_bs) * (d.rho_bs / 64);
+  const int rho_waves_per_chunk = ((p.nseg() + 63) / 64) * 4;
   int rows = 0;
   int64_t yoff = 0;
   for (int L = 0; L <= kMaxLsum; ++L) {
@@ -133,8 +133,11 @@ void choose_shapes(const Plan &p, Dev &d, int target_waves) {
     yoff += (int64_t)jc * nherm(L) * np;
   }
   d.nrows = std::max(1, rows);
+  d.ngroups = std::min(d.nrows, 64);
+  d.rows_per_group = (d.nrows + d.ngroups - 1) / d.ngroups;
+  d.ngroups = (d.nrows + d.rows_per_group - 1) / d.rows_per_group;
   d.yhat_size = std::max<int64_t>(1, yoff);
-  d.nred_blocks = (p.nslot() + 255) / 256;
+  d.nred_blocks = (p.nslot() + 3) / 4;
 }
 
 pwdf_status validate_ndm(pwdf_ctx *c, int ndm) {
@@ -231,6 +234,8 @@ pwdf_status run_from_V(pwdf_ctx *c, int ndm, double *Jk, hipStream_t st) {
       double units = (double)(p.blocks[p.cls_b1[cl] - 1].p1 - p.blocks[p.cls_b0[cl]].p0) * ndm;
       if ((s = step(c, name, units, st, [&] { return launch_back_cls(d, la, lb, ndm, st); })) != PWDF_OK) return s;
     }
+  if ((s = step(c, "fold_j", (double)p.eJ.size() * ndm, st, [&] { return launch_fold_j(d, ndm, st); })) != PWDF_OK)
+    return s;
   if ((s = step(c, "phase_j", (double)p.nk * p.nbf * (double)p.nbf * ndm, st,
                 [&] { return launch_phase_j(d, ndm, Jk, st); })) != PWDF_OK)
     return s;
@@ -337,6 +342,11 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
     delete c;
     return fail(nullptr, PWDF_EINVAL, why);
   }
+  // the phase kernels stage (n1+n2+n3) lcm(n) phases and the k-point list in LDS
+  if (c->plan.ptab.size() / 2 > 1024 || c->plan.nk > 512) {
+    delete c;
+    return fail(nullptr, PWDF_EUNSUPPORTED, "k-mesh too large: need (n1+n2+n3)*lcm(n1,n2,n3) <= 1024 and Nk <= 512");
+  }
   c->device = device;
   c->max_ndm = max_ndm;
   c->prec = prec;
@@ -376,6 +386,8 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
     d.dhat_off[L] = p.dhat_off[L];
   }
   d.dhat_size = std::max<int64_t>(1, p.dhat_size);
+  d.nsegJ = (int)p.sJ_code.size();
+  d.nsegD = (int)p.sD_code.size();
   choose_shapes(p, d, 4096);
 
 #define UP(vec, field)                                                  \
@@ -397,6 +409,14 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
   UP(p.sp_ent, sp_ent)
   UP(p.bf_shell, bf_shell)
   UP(p.bf_comp, bf_comp)
+  UP(p.sJ_off, sJ_off)
+  UP(p.sJ_code, sJ_code)
+  UP(p.sJ_e0, sJ_e0)
+  UP(p.eJ, eJ)
+  UP(p.sD_el, sD_el)
+  UP(p.sD_code, sD_code)
+  UP(p.sD_e0, sD_e0)
+  UP(p.eD, eD)
   UP(p.ttab, ttab)
 #undef UP
   {
@@ -413,6 +433,21 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
       return hip_fail(nullptr, e, "uploading phase tables");
     }
     d.phJ = (const double2 *)ph;
+    const int *ent;
+    const double *pt;
+    if ((e = upload(c, p.ptab, &pt)) != hipSuccess) {
+      free_device(c);
+      delete c;
+      return hip_fail(nullptr, e, "uploading phase table");
+    }
+    d.ptab = (const double2 *)pt;
+    d.ptab_len = (int)(p.ptab.size() / 2);
+    if ((e = upload(c, p.kvec, &ent)) != hipSuccess) {
+      free_device(c);
+      delete c;
+      return hip_fail(nullptr, e, "uploading k table");
+    }
+    d.kvec = (const int4 *)ent;
   }
   const size_t M = (size_t)max_ndm;
 #define AL(field, count)                                                \
@@ -426,9 +461,11 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
   AL(dhat, M * d.dhat_size)
   AL(yhat, M * d.yhat_size)
   AL(part, M * d.nrows * d.nslot)
+  AL(part2, M * d.ngroups * d.nslot)
   AL(rho, M * d.nslot)
   AL(Vc, M * d.nslot)
   AL(Epart, M * d.nred_blocks)
+  AL(Jfold, M * (size_t)std::max(1, d.nsegJ))
 #undef AL
   if ((e = alloc(c, M, &c->Escr)) != hipSuccess) {
     free_device(c);

@@ -26,6 +26,14 @@ struct Dev {
   const int *sp_off;
   const GatherEnt *sp_ent;
   const int *bf_shell, *bf_comp;
+  // phase sums by Born-von Karman class (see plan.h)
+  int nsegJ, nsegD;
+  const int *sJ_off, *sJ_code, *sJ_e0, *eJ;
+  const int *sD_el, *sD_code, *sD_e0, *eD;
+  double *Jfold;                 // [ndm][nsegJ]
+  const double2 *ptab;           // e^{2 pi i t / N}
+  const int4 *kvec;              // (k1, k2, k3, 0)
+  int ptab_len;
   const double *ttab;
   int cls_b0[16], cls_b1[16];
   int L_p0[kMaxLsum + 1], L_p1[kMaxLsum + 1];
@@ -36,12 +44,14 @@ struct Dev {
   double *dhat;            // [ndm][dhat_size]
   double *yhat;            // [ndm][yhat_size]
   double2 *part;           // [ndm][nrows][nslot]
+  double2 *part2;          // [ndm][ngroups][nslot]
   double2 *rho, *Vc;       // [ndm][nslot]
   double *Epart;           // [ndm][nred_blocks]
   // launch shapes
   int rho_bs;
   int rho_chunks[kMaxLsum + 1], rho_ppc[kMaxLsum + 1], rho_row0[kMaxLsum + 1];
   int nrows;
+  int ngroups, rows_per_group;  // first stage of the row reduction
   int j_chunks[kMaxLsum + 1], j_spc[kMaxLsum + 1];
   int64_t yhat_off[kMaxLsum + 1];
   int64_t yhat_size;
@@ -54,6 +64,7 @@ hipError_t launch_rho_L(const Dev &d, int L, int ndm, hipStream_t st);
 hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st);
 hipError_t launch_jpass_L(const Dev &d, int L, int ndm, hipStream_t st);
 hipError_t launch_back_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st);
+hipError_t launch_fold_j(const Dev &d, int ndm, hipStream_t st);
 hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, hipStream_t st);
 
 }  // namespace pwdf

@@ -110,33 +110,41 @@ __device__ __forceinline__ void md_axis(double inv2p, double xpa, double xpb,
 }
 
 // ---------------------------------------------------------------------------
-// a1: D(k) -> D(L) on the unique blocks (real part; the Hermitian input makes
-// the imaginary part cancel between (a,b,L) and its mirror (b,a,-L)).
+// Phase factors of the k <-> L sums: for the k-point (k1,k2,k3) of an
+// n1 x n2 x n3 mesh and the image m, k.L/2pi = sum_i k_i m_i / n_i, an integer
+// multiple t of 1/N (N = lcm of the n_i).  An image enters only through its
+// Born-von Karman class c_i = (m_i mod n_i) N / n_i, so t = k1 c1 + k2 c2 + k3 c3
+// and the phase is ptab[t] = e^{2 pi i t / N} (t < (n1+n2+n3) N, no reduction).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk, int nk, int nbf,
-                                                 int64_t nelem, const int *__restrict__ elem_blk,
-                                                 const BlockRec *__restrict__ blocks,
-                                                 const int *__restrict__ sh_l,
-                                                 const double2 *__restrict__ phD,
-                                                 double *__restrict__ Dblk) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int dm = blockIdx.y;
-  if (e >= nelem) return;
-  const BlockRec b = blocks[elem_blk[e]];
-  const int ncb = ncart(sh_l[b.sb]);
-  const int r = (int)(e - b.eoff);
-  const int mu = b.bfa + r / ncb, nu = b.bfb + r % ncb;
+__device__ __forceinline__ int phase_index(int4 kv, int code) {
+  return kv.x * (code & 1023) + kv.y * ((code >> 10) & 1023) + kv.z * (code >> 20);
+}
+
+// a1: D(k) -> D(L) on the unique blocks (real part: the Hermitian input makes
+// the imaginary part cancel between (a,b,L) and its mirror (b,a,-L)).  One thread
+// per (matrix element, BvK class) segment: D_c = Re sum_k w_k e^{ik.L} D(k)[mu][nu]
+// is the same for every image of the class and is written to each of them.
+__global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk, int nk, int nbf, int nsegD,
+                                                 const int *__restrict__ sD_el, const int *__restrict__ sD_code,
+                                                 const int *__restrict__ sD_e0, const int *__restrict__ eD,
+                                                 const double2 *__restrict__ ptab, const int4 *__restrict__ kvec,
+                                                 double wk, double *__restrict__ Dblk, int64_t nelem) {
+  const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+  const int dm = blockIdx.y;
+  if (sg >= nsegD) return;
+  const int code = sD_code[sg];
   const size_t nn = (size_t)nbf * nbf;
-  const double2 *D = Dk + (size_t)dm * nk * nn + (size_t)mu * nbf + nu;
-  const double2 *ph = phD + (size_t)b.img * nk;
+  const double2 *D = Dk + (size_t)dm * nk * nn + sD_el[sg];
   double acc = 0.0;
   for (int k = 0; k < nk; ++k) {
-    double2 d = D[(size_t)k * nn];
-    double2 w = ph[k];
+    const double2 w = ptab[phase_index(kvec[k], code)];
+    const double2 d = D[(size_t)k * nn];
     acc = fma(w.x, d.x, acc);
     acc = fma(-w.y, d.y, acc);
   }
-  Dblk[(size_t)dm * nelem + e] = acc;
+  acc *= wk;
+  double *out = Dblk + (size_t)dm * nelem;
+  for (int i = sD_e0[sg]; i < sD_e0[sg + 1]; ++i) out[eD[i]] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -211,28 +219,41 @@ __global__ __launch_bounds__(64) void k_transform(const BlockRec *__restrict__ b
 }
 
 // ---------------------------------------------------------------------------
-// a3: rho(G) partial sums.  Lane = one segment (SEG consecutive n_u of a line),
-// the wave walks pairs [p0, p1) of class L with wave-uniform pair data.
+// a3: rho(G) partial sums.  Lane = one segment (SEG consecutive n_u of a line);
+// the W waves of a workgroup share 64 segments and split a chunk of pairs of
+// class L.  Pair records are staged in LDS tile by tile (wave-uniform reads).
 //   rho(n) += S(n) P(n),   P(n_u) = sum_a C_a n_u^a  (Horner),
 //   C_a = sum_{b,c} d_{abc} n_v^b n_w^c  (real part from even a+b+c, imaginary
 //   from odd), S advanced by S <- S R, R <- q R.
+// The W partial sums are added in LDS (fixed order) into one row per workgroup.
 // ---------------------------------------------------------------------------
-template <int L, int SEG>
-__global__ __launch_bounds__(256) void k_rho(const SegDesc *__restrict__ segs, int nseg,
-                                             const PairHot *__restrict__ hot, int Lp0, int Lp1,
-                                             int pairs_per_chunk, const double *__restrict__ dhat,
-                                             int64_t dhat_size, int64_t cls_off,
-                                             double2 *__restrict__ part, int row0, int nrows, int nslot) {
+template <int L>
+struct RhoTile {
+  static constexpr int NT = nherm(L);
+  static constexpr int REC = 8 + NT;  // PairHot (8 doubles) + coefficients
+  static constexpr int TP = NT <= 20 ? 64 : 32;
+};
+
+template <int L, int SEG, int W>
+__global__ __launch_bounds__(64 * W) void k_rho(const SegDesc *__restrict__ segs, int nseg,
+                                                const PairHot *__restrict__ hot, int Lp0, int Lp1,
+                                                int pairs_per_chunk, const double *__restrict__ dhat,
+                                                int64_t dhat_size, int64_t cls_off,
+                                                double2 *__restrict__ part, int row0, int nrows, int nslot) {
   constexpr int NT = nherm(L);
+  constexpr int REC = RhoTile<L>::REC;
+  constexpr int TP = RhoTile<L>::TP;
   constexpr Monos<L> MT{};
-  const int seg = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double sp[TP * REC];
+  __shared__ double2 red[(W > 1 ? W - 1 : 1) * 64 * SEG];
+  const int lane = threadIdx.x, w = threadIdx.y, tid = w * 64 + lane;
+  const int seg = blockIdx.x * 64 + lane;
   const int chunk = blockIdx.y;
   const int dm = blockIdx.z;
   const int p0 = Lp0 + chunk * pairs_per_chunk;
   const int p1 = min(Lp1, p0 + pairs_per_chunk);
   const bool active = seg < nseg;
-  SegDesc sd = segs[active ? seg : 0];
-  // monomials n_v^b n_w^c
+  const SegDesc sd = segs[active ? seg : 0];
   double mv[L + 1], mw[L + 1];
   mv[0] = 1.0;
   mw[0] = 1.0;
@@ -246,47 +267,73 @@ __global__ __launch_bounds__(256) void k_rho(const SegDesc *__restrict__ segs, i
   for (int s = 0; s < SEG; ++s) accr[s] = acci[s] = 0.0;
   const double *dbase = dhat + (size_t)dm * dhat_size + cls_off;
   const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
-  for (int p = p0; p < p1; ++p) {
-    const PairHot h = hot[p];
-    const double *d = dbase + (size_t)(p - Lp0) * NT;
-    double cr[L + 1], ci[L + 1];
-#pragma unroll
-    for (int a = 0; a <= L; ++a) cr[a] = ci[a] = 0.0;
-#pragma unroll
-    for (int k = 0; k < NT; ++k) {
-      const int a = MT.u[k], b = MT.v[k], c = MT.w[k];
-      const double t = d[k] * (mv[b] * mw[c]);
-      if ((a + b + c) & 1)
-        ci[a] += t;
-      else
-        cr[a] += t;
+  for (int t0 = p0; t0 < p1; t0 += TP) {
+    const int nt = min(TP, p1 - t0);
+    __syncthreads();
+    for (int i = tid; i < nt * REC; i += 64 * W) {
+      const int pi = i / REC, f = i - pi * REC;
+      sp[i] = f < 8 ? reinterpret_cast<const double *>(hot + t0 + pi)[f]
+                    : dbase[(size_t)(t0 + pi - Lp0) * NT + (f - 8)];
     }
-    const double e0 = exp(-sd.gq0 * h.inv4p);
-    const double eR = exp(-sd.dg0 * h.inv4p);
-    double ph = fma(nu0, h.fu, fma(nv, h.fv, nw * h.fw));
-    ph -= rint(ph);
-    double sn, cs;
-    sincospi(2.0 * ph, &sn, &cs);
-    double Sr = e0 * cs, Si = -e0 * sn;
-    double Rr = eR * h.cu, Ri = eR * h.su;
-    const double q = h.q;
+    __syncthreads();
+    for (int j = w; j < nt; j += W) {
+      const double *r = sp + j * REC;
+      const double inv4p = r[0], fu = r[1], fv = r[2], fw = r[3], cu = r[4], su = r[5], q = r[6];
+      const double *d = r + 8;
+      double cr[L + 1], ci[L + 1];
 #pragma unroll
-    for (int s = 0; s < SEG; ++s) {
-      const double n = nu0 + s;
-      double Pr = cr[L], Pi = ci[L];
+      for (int a = 0; a <= L; ++a) cr[a] = ci[a] = 0.0;
 #pragma unroll
-      for (int a = L - 1; a >= 0; --a) {
-        Pr = fma(Pr, n, cr[a]);
-        Pi = fma(Pi, n, ci[a]);
+      for (int k = 0; k < NT; ++k) {
+        const int a = MT.u[k], b = MT.v[k], c = MT.w[k];
+        const double t = d[k] * (mv[b] * mw[c]);
+        if ((a + b + c) & 1)
+          ci[a] += t;
+        else
+          cr[a] += t;
       }
-      accr[s] = fma(Sr, Pr, fma(-Si, Pi, accr[s]));
-      acci[s] = fma(Sr, Pi, fma(Si, Pr, acci[s]));
-      const double tr = fma(Sr, Rr, -Si * Ri);
-      Si = fma(Sr, Ri, Si * Rr);
-      Sr = tr;
-      Rr *= q;
-      Ri *= q;
+      const double e0 = exp(-sd.gq0 * inv4p);
+      const double eR = exp(-sd.dg0 * inv4p);
+      double ph = fma(nu0, fu, fma(nv, fv, nw * fw));
+      ph -= rint(ph);
+      double sn, cs;
+      sincospi(2.0 * ph, &sn, &cs);
+      double Sr = e0 * cs, Si = -e0 * sn;
+      double Rr = eR * cu, Ri = eR * su;
+#pragma unroll
+      for (int s = 0; s < SEG; ++s) {
+        const double n = nu0 + s;
+        double Pr = cr[L], Pi = ci[L];
+#pragma unroll
+        for (int a = L - 1; a >= 0; --a) {
+          Pr = fma(Pr, n, cr[a]);
+          Pi = fma(Pi, n, ci[a]);
+        }
+        accr[s] = fma(Sr, Pr, fma(-Si, Pi, accr[s]));
+        acci[s] = fma(Sr, Pi, fma(Si, Pr, acci[s]));
+        const double tr = fma(Sr, Rr, -Si * Ri);
+        Si = fma(Sr, Ri, Si * Rr);
+        Sr = tr;
+        Rr *= q;
+        Ri *= q;
+      }
     }
+  }
+  if (W > 1) {
+    if (w > 0) {
+#pragma unroll
+      for (int s = 0; s < SEG; ++s) red[((w - 1) * SEG + s) * 64 + lane] = make_double2(accr[s], acci[s]);
+    }
+    __syncthreads();
+    if (w > 0) return;
+#pragma unroll
+    for (int v = 1; v < W; ++v)
+#pragma unroll
+      for (int s = 0; s < SEG; ++s) {
+        const double2 x = red[((v - 1) * SEG + s) * 64 + lane];
+        accr[s] += x.x;
+        acci[s] += x.y;
+      }
   }
   if (!active) return;
   double2 *out = part + ((size_t)dm * nrows + row0 + chunk) * nslot + (size_t)seg * SEG;
@@ -295,37 +342,61 @@ __global__ __launch_bounds__(256) void k_rho(const SegDesc *__restrict__ segs, i
 }
 
 // ---------------------------------------------------------------------------
-// a4: rho = sum of partial rows (fixed order), V = v rho, stored conjugated for
-// the J pass; energy partial Omega sum v |rho|^2 per block (G half space).
+// a4: rho = sum of the partial rows in a fixed order (two stages: groups of
+// rows, then the groups), V = v rho stored conjugated for the J pass, and the
+// energy partials Omega sum v |rho|^2 per block (G half space).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ part, int nrows, int nslot,
+__global__ __launch_bounds__(256) void k_reduce_rows(const double2 *__restrict__ part, int nrows, int nslot,
+                                                     int rows_per_group, double2 *__restrict__ part2,
+                                                     int ngroups) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int grp = blockIdx.y;
+  const int dm = blockIdx.z;
+  if (g >= nslot) return;
+  const int r0 = grp * rows_per_group, r1 = min(nrows, r0 + rows_per_group);
+  const double2 *pp = part + (size_t)dm * nrows * nslot + g;
+  double r = 0.0, i = 0.0;
+  for (int row = r0; row < r1; ++row) {
+    const double2 x = pp[(size_t)row * nslot];
+    r += x.x;
+    i += x.y;
+  }
+  part2[((size_t)dm * ngroups + grp) * nslot + g] = make_double2(r, i);
+}
+
+// Second stage: 4 slots per workgroup, one wave per slot; lane r holds group r
+// (ngroups <= 64) and a fixed xor-butterfly adds them.
+__global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ part2, int ngroups, int nslot,
                                                 const double *__restrict__ slot_v, double vol,
                                                 double2 *__restrict__ rho, double2 *__restrict__ Vc,
                                                 double *__restrict__ Epart) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = blockIdx.x * 4 + wv;
   const int dm = blockIdx.y;
-  double e = 0.0;
-  if (g < nslot) {
-    const double2 *pp = part + (size_t)dm * nrows * nslot + g;
-    double r = 0.0, i = 0.0;
-    for (int row = 0; row < nrows; ++row) {
-      double2 x = pp[(size_t)row * nslot];
-      r += x.x;
-      i += x.y;
+  double r = 0.0, i = 0.0;
+  if (g < nslot && lane < ngroups) {
+    const double2 x = part2[((size_t)dm * ngroups + lane) * nslot + g];
+    r = x.x;
+    i = x.y;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    r += __shfl_xor(r, off, 64);
+    i += __shfl_xor(i, off, 64);
+  }
+  __shared__ double sh[4];
+  if (lane == 0) {
+    double e = 0.0;
+    if (g < nslot) {
+      const double v = slot_v[g];
+      rho[(size_t)dm * nslot + g] = make_double2(r, i);
+      Vc[(size_t)dm * nslot + g] = make_double2(v * r, -v * i);
+      e = vol * v * (r * r + i * i);
     }
-    const double v = slot_v[g];
-    rho[(size_t)dm * nslot + g] = make_double2(r, i);
-    Vc[(size_t)dm * nslot + g] = make_double2(v * r, -v * i);
-    e = vol * v * (r * r + i * i);
+    sh[wv] = e;
   }
-  __shared__ double sh[256];
-  sh[threadIdx.x] = e;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) Epart[(size_t)dm * gridDim.x + blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) Epart[(size_t)dm * gridDim.x + blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
 __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ Epart, int nparts,
@@ -357,7 +428,10 @@ __global__ __launch_bounds__(256) void k_jpass(const SegDesc *__restrict__ segs,
                                                int Lp1, double *__restrict__ yhat, int64_t yhat_size,
                                                int64_t ycls_off) {
   constexpr int NT = nherm(L);
+  constexpr int TS = 32;  // segments per LDS tile
   constexpr Monos<L> MT{};
+  __shared__ SegDesc ss[TS];
+  __shared__ double2 sv[TS * SEG];
   const int np = Lp1 - Lp0;
   const int pl = blockIdx.x * blockDim.x + threadIdx.x;
   const int chunk = blockIdx.y;
@@ -370,52 +444,59 @@ __global__ __launch_bounds__(256) void k_jpass(const SegDesc *__restrict__ segs,
 #pragma unroll
   for (int k = 0; k < NT; ++k) y[k] = 0.0;
   const double2 *V = Vc + (size_t)dm * nslot;
-  for (int sg = s0; sg < s1; ++sg) {
-    const SegDesc sd = segs[sg];
-    const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
-    const double e0 = exp(-sd.gq0 * h.inv4p);
-    const double eR = exp(-sd.dg0 * h.inv4p);
-    double ph = fma(nu0, h.fu, fma(nv, h.fv, nw * h.fw));
-    ph -= rint(ph);
-    double sn, cs;
-    sincospi(2.0 * ph, &sn, &cs);
-    double Sr = e0 * cs, Si = -e0 * sn;
-    double Rr = eR * h.cu, Ri = eR * h.su;
-    const double q = h.q;
-    double mr[L + 1], mi[L + 1];
+  for (int t0 = s0; t0 < s1; t0 += TS) {
+    const int nt = min(TS, s1 - t0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nt * SEG; i += blockDim.x) sv[i] = V[(size_t)t0 * SEG + i];
+    if ((int)threadIdx.x < nt) ss[threadIdx.x] = segs[t0 + threadIdx.x];
+    __syncthreads();
+    for (int j = 0; j < nt; ++j) {
+      const SegDesc sd = ss[j];
+      const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
+      const double e0 = exp(-sd.gq0 * h.inv4p);
+      const double eR = exp(-sd.dg0 * h.inv4p);
+      double ph = fma(nu0, h.fu, fma(nv, h.fv, nw * h.fw));
+      ph -= rint(ph);
+      double sn, cs;
+      sincospi(2.0 * ph, &sn, &cs);
+      double Sr = e0 * cs, Si = -e0 * sn;
+      double Rr = eR * h.cu, Ri = eR * h.su;
+      const double q = h.q;
+      double mr[L + 1], mi[L + 1];
 #pragma unroll
-    for (int a = 0; a <= L; ++a) mr[a] = mi[a] = 0.0;
+      for (int a = 0; a <= L; ++a) mr[a] = mi[a] = 0.0;
 #pragma unroll
-    for (int s = 0; s < SEG; ++s) {
-      const double2 v = V[(size_t)sg * SEG + s];
-      const double Ur = fma(v.x, Sr, -v.y * Si);
-      const double Ui = fma(v.x, Si, v.y * Sr);
-      const double n = nu0 + s;
-      double pw = 1.0;
+      for (int s = 0; s < SEG; ++s) {
+        const double2 v = sv[j * SEG + s];
+        const double Ur = fma(v.x, Sr, -v.y * Si);
+        const double Ui = fma(v.x, Si, v.y * Sr);
+        const double n = nu0 + s;
+        double pw = 1.0;
 #pragma unroll
-      for (int a = 0; a <= L; ++a) {
-        mr[a] = fma(pw, Ur, mr[a]);
-        mi[a] = fma(pw, Ui, mi[a]);
-        pw *= n;
+        for (int a = 0; a <= L; ++a) {
+          mr[a] = fma(pw, Ur, mr[a]);
+          mi[a] = fma(pw, Ui, mi[a]);
+          pw *= n;
+        }
+        const double tr = fma(Sr, Rr, -Si * Ri);
+        Si = fma(Sr, Ri, Si * Rr);
+        Sr = tr;
+        Rr *= q;
+        Ri *= q;
       }
-      const double tr = fma(Sr, Rr, -Si * Ri);
-      Si = fma(Sr, Ri, Si * Rr);
-      Sr = tr;
-      Rr *= q;
-      Ri *= q;
-    }
-    double mv[L + 1], mw[L + 1];
-    mv[0] = mw[0] = 1.0;
+      double mv[L + 1], mw[L + 1];
+      mv[0] = mw[0] = 1.0;
 #pragma unroll
-    for (int b = 1; b <= L; ++b) {
-      mv[b] = mv[b - 1] * nv;
-      mw[b] = mw[b - 1] * nw;
-    }
+      for (int b = 1; b <= L; ++b) {
+        mv[b] = mv[b - 1] * nv;
+        mw[b] = mw[b - 1] * nw;
+      }
 #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-      const int a = MT.u[k], b = MT.v[k], c = MT.w[k];
-      const double m = ((a + b + c) & 1) ? mi[a] : mr[a];
-      y[k] = fma(mv[b] * mw[c], m, y[k]);
+      for (int k = 0; k < NT; ++k) {
+        const int a = MT.u[k], b = MT.v[k], c = MT.w[k];
+        const double m = ((a + b + c) & 1) ? mi[a] : mr[a];
+        y[k] = fma(mv[b] * mw[c], m, y[k]);
+      }
     }
   }
   if (!active) return;
@@ -506,46 +587,79 @@ __global__ __launch_bounds__(64) void k_backtransform(const BlockRec *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// a7: J(k)_{mu nu} = sum over the gather list of (sa, sb):
-//   tr = 0: e^{ik.L_m} J_blk[a][b];  tr = 1: e^{-ik.L_m} J_blk[b][a]  (mirror block)
-// One thread per (k, mu, nu); nu fastest for coalesced stores.
+// a7: J(L) -> J(k).  First the blocks of every matrix element are summed per
+// BvK class (k_fold_j, one thread per (element, class) segment, fixed order);
+// then J(k)_{mu nu} = sum over the element's classes of e^{2 pi i t/N} J_c
+// (k_phase_j, one thread per (k, mu, nu), at most Nk terms each).  Mirror
+// entries (b,a,-L) were given the class of -m and the transposed element.  Every
+// output is written (zeros off the support), coalesced over nu.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_phase_j(const double *__restrict__ Jblk, int64_t nelem,
-                                                 const BlockRec *__restrict__ blocks,
-                                                 const int *__restrict__ sh_l,
-                                                 const int *__restrict__ bf_shell,
-                                                 const int *__restrict__ bf_comp,
-                                                 const int *__restrict__ sp_off,
-                                                 const GatherEnt *__restrict__ sp_ent, int nshell,
-                                                 const double2 *__restrict__ phJ, int nk, int nbf,
-                                                 double2 *__restrict__ Jk) {
-  const int nu = blockIdx.x * blockDim.x + threadIdx.x;
-  const int mu = blockIdx.y;
-  const int kz = blockIdx.z;
-  const int dm = kz / nk, k = kz % nk;
-  if (nu >= nbf) return;
-  const int sa = bf_shell[mu], sb = bf_shell[nu];
-  const int a = bf_comp[mu], bcomp = bf_comp[nu];
+__global__ __launch_bounds__(256) void k_fold_j(const double *__restrict__ Jblk, int64_t nelem, int nsegJ,
+                                                const int *__restrict__ sJ_e0, const int *__restrict__ eJ,
+                                                double *__restrict__ Jfold) {
+  const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+  const int dm = blockIdx.y;
+  if (sg >= nsegJ) return;
   const double *J = Jblk + (size_t)dm * nelem;
-  double re = 0.0, im = 0.0;
-  const int e0 = sp_off[(size_t)sa * nshell + sb], e1 = sp_off[(size_t)sa * nshell + sb + 1];
-  for (int e = e0; e < e1; ++e) {
-    const GatherEnt g = sp_ent[e];
-    const BlockRec br = blocks[g.blk];
-    const double2 w = phJ[(size_t)g.img * nk + k];
-    double val;
-    double wi;
-    if (g.tr == 0) {
-      val = J[br.eoff + a * ncart(sh_l[br.sb]) + bcomp];
-      wi = w.y;
-    } else {
-      val = J[br.eoff + bcomp * ncart(sh_l[br.sb]) + a];
-      wi = -w.y;
+  double s = 0.0;
+  for (int i = sJ_e0[sg]; i < sJ_e0[sg + 1]; ++i) s += J[eJ[i]];
+  Jfold[(size_t)dm * nsegJ + sg] = s;
+}
+
+// One wave per matrix element, lanes = k-points (64 at a time): the element's
+// class segments are loaded once, one per lane, and broadcast lane by lane.  A
+// workgroup computes a tile of WAVES x EPW consecutive nu for one mu into LDS,
+// then writes each k-row of the tile as one contiguous run.
+template <int WAVES, int EPW>
+__global__ __launch_bounds__(64 * WAVES) void k_phase_j(const double *__restrict__ Jfold, int nsegJ,
+                                                        const int *__restrict__ sJ_off,
+                                                        const int *__restrict__ sJ_code,
+                                                        const double2 *__restrict__ ptab,
+                                                        const int4 *__restrict__ kvec, int nk, int nbf,
+                                                        double2 *__restrict__ Jk) {
+  constexpr int TW = WAVES * EPW;  // tile width in nu
+  __shared__ double2 tile[64 * TW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int mu = blockIdx.y, dm = blockIdx.z;
+  const int nu_t = blockIdx.x * TW;
+  const int tw = min(TW, nbf - nu_t);
+  const size_t nn = (size_t)nbf * nbf;
+  const double *Jf = Jfold + (size_t)dm * nsegJ;
+  for (int kb = 0; kb < nk; kb += 64) {
+    const int kc = min(64, nk - kb);
+    const int k = kb + lane;
+    const int4 kv = kvec[k < nk ? k : nk - 1];
+    for (int e = 0; e < EPW; ++e) {
+      const int j = w * EPW + e;
+      if (j >= tw) break;
+      const size_t el = (size_t)mu * nbf + nu_t + j;
+      const int s0 = sJ_off[el], s1 = sJ_off[el + 1];
+      double re = 0.0, im = 0.0;
+      for (int b0 = s0; b0 < s1; b0 += 64) {
+        const int nb = min(64, s1 - b0);
+        int mycode = 0;
+        double myv = 0.0;
+        if (lane < nb) {
+          mycode = sJ_code[b0 + lane];
+          myv = Jf[b0 + lane];
+        }
+        for (int i = 0; i < nb; ++i) {
+          const int code = __shfl(mycode, i, 64);
+          const double v = __shfl(myv, i, 64);
+          const double2 ph = ptab[phase_index(kv, code)];
+          re = fma(ph.x, v, re);
+          im = fma(ph.y, v, im);
+        }
+      }
+      tile[lane * TW + j] = make_double2(re, im);
     }
-    re = fma(w.x, val, re);
-    im = fma(wi, val, im);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kc * TW; i += 64 * WAVES) {
+      const int kk = i / TW, j = i - kk * TW;
+      if (j < tw) Jk[((size_t)dm * nk + kb + kk) * nn + (size_t)mu * nbf + nu_t + j] = tile[kk * TW + j];
+    }
+    __syncthreads();
   }
-  Jk[(((size_t)dm * nk + k) * nbf + mu) * nbf + nu] = make_double2(re, im);
 }
 
 // ---------------------------------------------------------------------------
@@ -558,9 +672,10 @@ __global__ __launch_bounds__(256) void k_phase_j(const double *__restrict__ Jblk
   } while (0)
 
 hipError_t launch_phase_d(const Dev &d, const double *Dk, int ndm, hipStream_t st) {
-  dim3 grid((unsigned)((d.nelem + 255) / 256), ndm);
-  hipLaunchKernelGGL(k_phase_d, grid, dim3(256), 0, st, (const double2 *)Dk, d.nk, d.nbf, d.nelem, d.elem_blk,
-                     d.blocks, d.sh_l, d.phD, d.Dblk);
+  if (d.nsegD <= 0) return hipSuccess;
+  dim3 grid((unsigned)((d.nsegD + 255) / 256), ndm);
+  hipLaunchKernelGGL(k_phase_d, grid, dim3(256), 0, st, (const double2 *)Dk, d.nk, d.nbf, d.nsegD, d.sD_el,
+                     d.sD_code, d.sD_e0, d.eD, d.ptab, d.kvec, 1.0 / d.nk, d.Dblk, d.nelem);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -597,9 +712,9 @@ template <int L, int SEG>
 static hipError_t rho_one(const Dev &d, int ndm, hipStream_t st) {
   const int np = d.L_p1[L] - d.L_p0[L];
   if (np <= 0) return hipSuccess;
-  const int bs = d.rho_bs;
-  dim3 grid((unsigned)((d.nseg + bs - 1) / bs), d.rho_chunks[L], ndm);
-  hipLaunchKernelGGL((k_rho<L, SEG>), grid, dim3(bs), 0, st, d.segs, d.nseg, d.hot, d.L_p0[L], d.L_p1[L],
+  constexpr int W = 4;
+  dim3 grid((unsigned)((d.nseg + 63) / 64), d.rho_chunks[L], ndm);
+  hipLaunchKernelGGL((k_rho<L, SEG, W>), grid, dim3(64, W), 0, st, d.segs, d.nseg, d.hot, d.L_p0[L], d.L_p1[L],
                      d.rho_ppc[L], d.dhat, d.dhat_size, d.dhat_off[L], d.part, d.rho_row0[L], d.nrows, d.nslot);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
@@ -629,8 +744,12 @@ hipError_t launch_rho_L(const Dev &d, int L, int ndm, hipStream_t st) {
 }
 
 hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st) {
+  dim3 g1((unsigned)((d.nslot + 255) / 256), d.ngroups, ndm);
+  hipLaunchKernelGGL(k_reduce_rows, g1, dim3(256), 0, st, d.part, d.nrows, d.nslot, d.rows_per_group, d.part2,
+                     d.ngroups);
+  PWDF_CHECK_LAUNCH();
   dim3 grid((unsigned)d.nred_blocks, ndm);
-  hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, st, d.part, d.nrows, d.nslot, d.slot_v, d.vol, d.rho, d.Vc,
+  hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, st, d.part2, d.ngroups, d.nslot, d.slot_v, d.vol, d.rho, d.Vc,
                      d.Epart);
   PWDF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_energy, dim3(ndm), dim3(256), 0, st, d.Epart, d.nred_blocks, EJ);
@@ -701,10 +820,20 @@ hipError_t launch_back_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st
   }
 }
 
+hipError_t launch_fold_j(const Dev &d, int ndm, hipStream_t st) {
+  if (d.nsegJ > 0) {
+    dim3 g1((unsigned)((d.nsegJ + 255) / 256), ndm);
+    hipLaunchKernelGGL(k_fold_j, g1, dim3(256), 0, st, d.Jblk, d.nelem, d.nsegJ, d.sJ_e0, d.eJ, d.Jfold);
+    PWDF_CHECK_LAUNCH();
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, hipStream_t st) {
-  dim3 grid((unsigned)((d.nbf + 255) / 256), d.nbf, d.nk * ndm);
-  hipLaunchKernelGGL(k_phase_j, grid, dim3(256), 0, st, d.Jblk, d.nelem, d.blocks, d.sh_l, d.bf_shell, d.bf_comp,
-                     d.sp_off, d.sp_ent, d.nshell, d.phJ, d.nk, d.nbf, (double2 *)Jk);
+  constexpr int WAVES = 4, EPW = 8;
+  dim3 grid((unsigned)((d.nbf + WAVES * EPW - 1) / (WAVES * EPW)), d.nbf, ndm);
+  hipLaunchKernelGGL((k_phase_j<WAVES, EPW>), grid, dim3(64 * WAVES), 0, st, d.Jfold, d.nsegJ, d.sJ_off, d.sJ_code,
+                     d.ptab, d.kvec, d.nk, d.nbf, (double2 *)Jk);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }

@@ -433,6 +433,89 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
       for (auto &e : lists[i]) p.sp_ent.push_back(e);
     }
     p.sp_off[lists.size()] = (int)p.sp_ent.size();
+    // per element lists with integer phase codes
+    auto gcd = [](int x, int y) {
+      while (y) {
+        int t = x % y;
+        x = y;
+        y = t;
+      }
+      return x;
+    };
+    int N = 1;
+    for (int i = 0; i < 3; ++i) N = N / gcd(N, in.kmesh[i]) * in.kmesh[i];
+    p.phN = N;
+    const int T = (in.kmesh[0] + in.kmesh[1] + in.kmesh[2]) * N;
+    p.ptab.resize(2 * (size_t)T);
+    for (int t = 0; t < T; ++t) {
+      int r = t % N;  // exact reduction before the transcendental
+      p.ptab[2 * t] = std::cos(2.0 * kPi * r / N);
+      p.ptab[2 * t + 1] = std::sin(2.0 * kPi * r / N);
+    }
+    p.kvec.resize(4 * (size_t)p.nk);
+    for (int k = 0; k < p.nk; ++k) {
+      p.kvec[4 * k + 2] = k % in.kmesh[2];
+      p.kvec[4 * k + 1] = (k / in.kmesh[2]) % in.kmesh[1];
+      p.kvec[4 * k + 0] = k / (in.kmesh[2] * in.kmesh[1]);
+      p.kvec[4 * k + 3] = 0;
+    }
+    // class code of image m (sign s = +1) or of -m (s = -1)
+    auto code_of = [&](const std::array<int, 3> &m, int s) {
+      int c[3];
+      for (int d = 0; d < 3; ++d) {
+        int n = in.kmesh[d];
+        c[d] = ((((s * m[d]) % n) + n) % n) * (N / n);
+      }
+      return c[0] | (c[1] << 10) | (c[2] << 20);
+    };
+    const int nbf = p.nbf;
+    p.sJ_off.assign((size_t)nbf * nbf + 1, 0);
+    p.sJ_code.clear();
+    p.sJ_e0.clear();
+    p.eJ.clear();
+    p.sD_el.clear();
+    p.sD_code.clear();
+    p.sD_e0.clear();
+    p.eD.clear();
+    std::vector<std::pair<int, int>> ents, dents;  // (code, element offset)
+    for (int mu = 0; mu < nbf; ++mu)
+      for (int nu = 0; nu < nbf; ++nu) {
+        size_t e = (size_t)mu * nbf + nu;
+        p.sJ_off[e] = (int)p.sJ_code.size();
+        int sa = p.bf_shell[mu], sb = p.bf_shell[nu];
+        int a = p.bf_comp[mu], b = p.bf_comp[nu];
+        ents.clear();
+        dents.clear();
+        for (int i = p.sp_off[(size_t)sa * ns + sb]; i < p.sp_off[(size_t)sa * ns + sb + 1]; ++i) {
+          const GatherEnt &g = p.sp_ent[i];
+          const BlockRec &br = p.blocks[g.blk];
+          int ncb = ncart(in.sh_l[br.sb]);
+          int64_t joff = br.eoff + (g.tr ? (int64_t)b * ncb + a : (int64_t)a * ncb + b);
+          int code = code_of(p.imgs[g.img], g.tr ? -1 : 1);
+          ents.push_back({code, (int)joff});
+          if (!g.tr) dents.push_back({code, (int)joff});
+        }
+        std::sort(ents.begin(), ents.end());
+        std::sort(dents.begin(), dents.end());
+        for (size_t i = 0; i < ents.size(); ++i) {
+          if (i == 0 || ents[i].first != ents[i - 1].first) {
+            p.sJ_code.push_back(ents[i].first);
+            p.sJ_e0.push_back((int)p.eJ.size());
+          }
+          p.eJ.push_back(ents[i].second);
+        }
+        for (size_t i = 0; i < dents.size(); ++i) {
+          if (i == 0 || dents[i].first != dents[i - 1].first) {
+            p.sD_el.push_back((int)e);
+            p.sD_code.push_back(dents[i].first);
+            p.sD_e0.push_back((int)p.eD.size());
+          }
+          p.eD.push_back(dents[i].second);
+        }
+      }
+    p.sJ_off[(size_t)nbf * nbf] = (int)p.sJ_code.size();
+    p.sJ_e0.push_back((int)p.eJ.size());
+    p.sD_e0.push_back((int)p.eD.size());
   }
 
   // ---- Hermite -> relative monomial transform per degree:

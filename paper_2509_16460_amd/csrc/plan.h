@@ -53,6 +53,22 @@ struct Plan {
   // J(k) gather lists per ordered shell pair
   std::vector<int> sp_off;
   std::vector<GatherEnt> sp_ent;
+  // Phase sums by Born-von Karman class.  e^{ik.L} depends on the image m only
+  // through c_i = (m_i mod n_i) N / n_i (N = lcm(n1, n2, n3)): for the k-point
+  // (k1, k2, k3), k.L / 2 pi = (k1 c1 + k2 c2 + k3 c3) / N.  The block entries of
+  // every matrix element (mu, nu) are grouped into segments of equal class
+  // (code = c1 | c2 << 10 | c3 << 20), at most Nk per element:
+  //   J side: all entries (mirror entries carry the class of -m and the
+  //           transposed element offset), segments ordered by element;
+  //   D side: direct entries only (each block element once).
+  std::vector<int> sJ_off;          // [nbf*nbf + 1] first J segment of each element
+  std::vector<int> sJ_code, sJ_e0;  // per J segment: class code; first entry ([nsegJ + 1])
+  std::vector<int> eJ;              // per J entry: element offset in Jblk
+  std::vector<int> sD_el, sD_code, sD_e0;  // per D segment: element, class code, first entry
+  std::vector<int> eD;                      // per D entry: element offset in Dblk
+  int phN = 1;                        // N
+  std::vector<double> ptab;           // e^{2 pi i t / N}, t = 0 .. (n1+n2+n3) N - 1
+  std::vector<int> kvec;              // (k1, k2, k3, 0) per k-point
   // block-diagonal Hermite -> relative-monomial transform (degree blocks), and
   // the sign of (-i)^{|k|} folded into the rho coefficients / J moments
   std::vector<double> ttab;
