@@ -203,9 +203,10 @@ pwdf_status run_to_rho(pwdf_ctx *c, int ndm, const double *Dk, double *EJ, hipSt
     }
   for (int L = 0; L <= 2 * kMaxL; ++L) {
     if (np_L(p, L) <= 0) continue;
-    std::snprintf(name, sizeof name, "rho_L%d", L);
-    if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, st, [&] { return launch_rho_L(d, L, ndm, st); })) !=
-        PWDF_OK)
+    std::snprintf(name, sizeof name, d.fp32 ? "rho_mfma_L%d" : "rho_L%d", L);
+    if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, st, [&] {
+           return d.fp32 ? launch_rho_mfma_L(d, L, ndm, st) : launch_rho_L(d, L, ndm, st);
+         })) != PWDF_OK)
       return s;
   }
   if ((s = step(c, "reduce", (double)p.nslot() * ndm, st, [&] { return launch_reduce(d, ndm, EJ, st); })) != PWDF_OK)
@@ -219,11 +220,15 @@ pwdf_status run_from_V(pwdf_ctx *c, int ndm, double *Jk, hipStream_t st) {
   const double nGh = (double)(p.nG_full / 2);
   pwdf_status s;
   char name[32];
+  if (d.fp32 && (s = step(c, "wprep", (double)p.nslot() * ndm, st, [&] { return launch_wprep(d, ndm, st); })) !=
+                    PWDF_OK)
+    return s;
   for (int L = 0; L <= 2 * kMaxL; ++L) {
     if (np_L(p, L) <= 0) continue;
-    std::snprintf(name, sizeof name, "jpass_L%d", L);
-    if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, st, [&] { return launch_jpass_L(d, L, ndm, st); })) !=
-        PWDF_OK)
+    std::snprintf(name, sizeof name, d.fp32 ? "jpass_mfma_L%d" : "jpass_L%d", L);
+    if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, st, [&] {
+           return d.fp32 ? launch_jpass_mfma_L(d, L, ndm, st) : launch_jpass_L(d, L, ndm, st);
+         })) != PWDF_OK)
       return s;
   }
   for (int la = 0; la <= kMaxL; ++la)
@@ -387,6 +392,28 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
   }
   d.dhat_size = std::max<int64_t>(1, p.dhat_size);
   d.nsegJ = (int)p.sJ_code.size();
+  d.fp32 = prec == PWDF_FP32_MFMA ? 1 : 0;
+  if (d.fp32) {
+    if (max_ndm > 16) {
+      delete c;
+      return fail(nullptr, PWDF_EUNSUPPORTED, "the FP32-MFMA form takes at most 16 densities per call");
+    }
+    d.ndmp = 1;
+    while (d.ndmp < max_ndm) d.ndmp *= 2;
+    int64_t off = 0;
+    int lmax = 0;
+    for (int L = 0; L <= kMaxLsum; ++L) {
+      int npl = p.L_p1[L] - p.L_p0[L];
+      d.ncols32[L] = ((nherm(L) * d.ndmp + 15) / 16) * 16;
+      d.d32_off[L] = off;
+      if (npl > 0) {
+        off += (int64_t)npl * d.ncols32[L];
+        lmax = L;
+      }
+    }
+    d.ncolsW = d.ncols32[lmax];
+    d.d32_off[kMaxLsum] = off;
+  }
   d.nsegD = (int)p.sD_code.size();
   choose_shapes(p, d, 4096);
 
@@ -466,6 +493,16 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
   AL(Vc, M * d.nslot)
   AL(Epart, M * d.nred_blocks)
   AL(Jfold, M * (size_t)std::max(1, d.nsegJ))
+  if (d.fp32) {
+    AL(dh32, (size_t)std::max<int64_t>(1, d.d32_off[kMaxLsum]))
+    AL(wre, (size_t)d.nslot * d.ncolsW)
+    AL(wim, (size_t)d.nslot * d.ncolsW)
+    if ((e = hipMemset(d.dh32, 0, sizeof(float) * std::max<int64_t>(1, d.d32_off[kMaxLsum]))) != hipSuccess) {
+      free_device(c);
+      delete c;
+      return hip_fail(nullptr, e, "clearing operand buffer");
+    }
+  }
 #undef AL
   if ((e = alloc(c, M, &c->Escr)) != hipSuccess) {
     free_device(c);

@@ -47,6 +47,16 @@ struct Dev {
   double2 *part2;          // [ndm][ngroups][nslot]
   double2 *rho, *Vc;       // [ndm][nslot]
   double *Epart;           // [ndm][nred_blocks]
+  // FP32-MFMA form: operands [pair][k * ndmp + dm] per class (columns padded to
+  // 16), W'[slot][k * ndmp + dm] for the J pass; ndmp = densities padded to a
+  // power of two (<= 16)
+  int fp32;
+  int ndmp;
+  float *dh32;
+  int64_t d32_off[kMaxLsum + 1];
+  int ncols32[kMaxLsum + 1];
+  float *wre, *wim;
+  int ncolsW;
   // launch shapes
   int rho_bs;
   int rho_chunks[kMaxLsum + 1], rho_ppc[kMaxLsum + 1], rho_row0[kMaxLsum + 1];
@@ -58,6 +68,9 @@ struct Dev {
   int nred_blocks;
 };
 
+hipError_t launch_rho_mfma_L(const Dev &d, int L, int ndm, hipStream_t st);
+hipError_t launch_wprep(const Dev &d, int ndm, hipStream_t st);
+hipError_t launch_jpass_mfma_L(const Dev &d, int L, int ndm, hipStream_t st);
 hipError_t launch_phase_d(const Dev &d, const double *Dk, int ndm, hipStream_t st);
 hipError_t launch_transform_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st);
 hipError_t launch_rho_L(const Dev &d, int L, int ndm, hipStream_t st);

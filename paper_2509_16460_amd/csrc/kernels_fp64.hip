@@ -25,52 +25,10 @@
 // shift-term recurrence.
 #include <hip/hip_runtime.h>
 
+#include "kernel_common.h"
 #include "kernels.h"
 
 namespace pwdf {
-
-// ---------------------------------------------------------------------------
-// compile-time monomial tables: degree-ordered, descending lexicographic
-// ---------------------------------------------------------------------------
-template <int L>
-struct Monos {
-  int u[nherm(L)], v[nherm(L)], w[nherm(L)];
-  constexpr Monos() : u(), v(), w() {
-    int n = 0;
-    for (int d = 0; d <= L; ++d)
-      for (int a = d; a >= 0; --a)
-        for (int b = d - a; b >= 0; --b) {
-          u[n] = a;
-          v[n] = b;
-          w[n] = d - a - b;
-          ++n;
-        }
-  }
-};
-
-// Cartesian components of one shell, descending lexicographic (lx, ly, lz).
-template <int l>
-struct Carts {
-  int x[ncart(l)], y[ncart(l)], z[ncart(l)];
-  constexpr Carts() : x(), y(), z() {
-    int n = 0;
-    for (int a = l; a >= 0; --a)
-      for (int b = l - a; b >= 0; --b) {
-        x[n] = a;
-        y[n] = b;
-        z[n] = l - a - b;
-        ++n;
-      }
-  }
-};
-
-__host__ __device__ constexpr int mono_idx(int a, int b, int c) {
-  // index of (a,b,c) inside its degree block, descending lexicographic
-  int d = a + b + c;
-  int idx = 0;
-  for (int x = d; x > a; --x) idx += d - x + 1;
-  return idx + (d - a) - b;
-}
 
 // ---------------------------------------------------------------------------
 // McMurchie-Davidson Hermite coefficients along one axis:
@@ -160,7 +118,8 @@ __global__ __launch_bounds__(64) void k_transform(const BlockRec *__restrict__ b
                                                   const double *__restrict__ Dblk, int64_t nelem,
                                                   const double *__restrict__ ttab,
                                                   double *__restrict__ dhat, int64_t dhat_size,
-                                                  int64_t cls_off, int Lp0) {
+                                                  int64_t cls_off, int Lp0, float *__restrict__ dh32,
+                                                  int64_t d32_off, int ncols, int ndmp) {
   constexpr int L = LA + LB;
   constexpr int NT = nherm(L);
   constexpr Carts<LA> CA{};
@@ -213,6 +172,8 @@ __global__ __launch_bounds__(64) void k_transform(const BlockRec *__restrict__ b
 #pragma unroll
         for (int t = 0; t < nc; ++t) s = fma(T[t * nc + k], Dt[deg_off(d) + t], s);
         out[deg_off(d) + k] = sg * s;
+        // FP32 operand of the MFMA form: [pair][k * ndmp + dm]
+        if (dh32) dh32[d32_off + (size_t)(q - Lp0) * ncols + (deg_off(d) + k) * ndmp + dm] = (float)(sg * s);
       }
     }
   }
@@ -687,7 +648,8 @@ static hipError_t transform_one(const Dev &d, int ndm, hipStream_t st) {
   if (b1 <= b0) return hipSuccess;
   dim3 grid((unsigned)((b1 - b0 + 63) / 64), ndm);
   hipLaunchKernelGGL((k_transform<LA, LB>), grid, dim3(64), 0, st, d.blocks, b0, b1, d.aux, d.Dblk, d.nelem,
-                     d.ttab, d.dhat, d.dhat_size, d.dhat_off[LA + LB], d.L_p0[LA + LB]);
+                     d.ttab, d.dhat, d.dhat_size, d.dhat_off[LA + LB], d.L_p0[LA + LB], d.dh32,
+                     d.d32_off[LA + LB], d.ncols32[LA + LB], d.ndmp);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }

@@ -1,0 +1,71 @@
+"""FP32-MFMA form vs the FP64 oracle / FP64 path (needs an MI355X).
+
+Targets of the precision form: |E_J - E_J(oracle)| <= 1e-7 Eh and
+max |J(k) - J(k)(oracle)| <= 1e-8 on the cubic Gamma cell (2 atoms, 4s2p per
+atom).  Batched calls must give, density by density, the same result as
+single-density FP32 calls to FP32 rounding, and stay within the relative error
+the FP32 operands allow against the FP64 path on every class up to (3,3).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_16460_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def pw():
+    from paper_2509_16460_amd import pwdf
+    return pwdf
+
+
+def run(prob, D, prec, max_ndm=None):
+    ndm = D.shape[0]
+    ctx = pw().LongRangeJ(prob, precision=prec, max_ndm=max_ndm or ndm)
+    J, E = ctx.build_j(torch.from_numpy(np.ascontiguousarray(D)).cuda())
+    torch.cuda.synchronize()
+    return J.cpu().numpy(), E.cpu().numpy()
+
+
+def test_cubic_gamma_fp32_targets():
+    p = synth.config_problem(3)
+    D = synth.make_density(p, 1000)
+    ref = O.build_j(p, D, want_rho=False)
+    J, E = run(p, D[None], pw().PWDF_FP32_MFMA)
+    dE = abs(E[0] - ref["E_G"])
+    dJ = np.max(np.abs(J[0] - ref["J"]))
+    print(f"cubic Gamma FP32-MFMA: E_J={E[0]:.12f} dE={dE:.3e} max|dJ|={dJ:.3e} (max|J|={np.max(np.abs(ref['J'])):.3e})",
+          flush=True)
+    assert dE <= 1e-7
+    assert dJ <= 1e-8
+
+
+@pytest.mark.parametrize("name,lmax,kmesh,natm", [("sp", 1, (2, 1, 1), 2), ("spd", 2, (1, 2, 2), 2),
+                                                  ("spdf", 3, (1, 1, 1), 2)])
+def test_fp32_vs_fp64_classes(name, lmax, kmesh, natm):
+    p = synth.small_problem(kind=name, seed=60 + lmax, kmesh=kmesh, lmax=lmax, natm=natm, lo=0.25, hi=30.0)
+    D = synth.make_density(p, 61)[None]
+    J64, E64 = run(p, D, pw().PWDF_FP64)
+    J32, E32 = run(p, D, pw().PWDF_FP32_MFMA)
+    relE = abs(E32[0] - E64[0]) / abs(E64[0])
+    relJ = np.max(np.abs(J32 - J64)) / np.max(np.abs(J64))
+    print(f"{name}: relE={relE:.2e} relJ={relJ:.2e}", flush=True)
+    assert relE <= 2e-6 and relJ <= 2e-5
+
+
+@pytest.mark.parametrize("ndm", [3, 16])
+def test_fp32_batched_equals_single(ndm):
+    p = synth.small_problem(kind="b", seed=70, kmesh=(2, 1, 1), lmax=2, natm=2, lo=0.25, hi=20.0)
+    D = np.stack([synth.make_density(p, 700 + i) for i in range(ndm)])
+    Jb, Eb = run(p, D, pw().PWDF_FP32_MFMA)
+    J64, E64 = run(p, D, pw().PWDF_FP64)
+    for i in (0, ndm - 1):
+        Js, Es = run(p, D[i:i + 1], pw().PWDF_FP32_MFMA)
+        assert abs(Eb[i] - Es[0]) <= 1e-6 * abs(Es[0])
+        assert np.max(np.abs(Jb[i] - Js[0])) <= 1e-5 * np.max(np.abs(Js[0]))
+    relE = np.max(np.abs(Eb - E64) / np.abs(E64))
+    relJ = np.max(np.abs(Jb - J64)) / np.max(np.abs(J64))
+    print(f"batched ndm={ndm}: relE={relE:.2e} relJ={relJ:.2e}", flush=True)
+    assert relE <= 2e-6 and relJ <= 2e-5
