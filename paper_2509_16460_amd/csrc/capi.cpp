@@ -132,6 +132,14 @@ void choose_shapes(const Plan &p, Dev &d, int target_waves) {
     d.j_spc[L] = spc;
     yoff += (int64_t)jc * nherm(L) * np;
   }
+  // force moments of degree L+1 over the class-L pairs, same segment chunks as J
+  int64_t foff = 0;
+  for (int L = 0; L <= kMaxLsum; ++L) {
+    int np = p.L_p1[L] - p.L_p0[L];
+    d.yF_off[L] = foff;
+    if (np > 0 && L < kMaxLsum) foff += (int64_t)d.j_chunks[L] * nherm(L + 1) * np;
+  }
+  d.yF_size = std::max<int64_t>(1, foff);
   d.nrows = std::max(1, rows);
   d.ngroups = std::min(d.nrows, 64);
   d.rows_per_group = (d.nrows + d.ngroups - 1) / d.ngroups;
@@ -493,6 +501,28 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
   AL(Vc, M * d.nslot)
   AL(Epart, M * d.nred_blocks)
   AL(Jfold, M * (size_t)std::max(1, d.nsegJ))
+  AL(yF, M * d.yF_size)
+  d.nblocks = (int)p.blocks.size();
+  AL(gblk, M * (size_t)d.nblocks * 6)
+  {
+    // per atom: (block * 6 + 0) for shell a on the atom, (block * 6 + 3) for shell b
+    std::vector<std::vector<int>> per(in.natm);
+    for (int b = 0; b < d.nblocks; ++b) {
+      per[in.sh_atom[p.blocks[b].sa]].push_back(b * 6);
+      per[in.sh_atom[p.blocks[b].sb]].push_back(b * 6 + 3);
+    }
+    std::vector<int> off(in.natm + 1, 0), ent;
+    for (int a = 0; a < in.natm; ++a) {
+      off[a] = (int)ent.size();
+      ent.insert(ent.end(), per[a].begin(), per[a].end());
+    }
+    off[in.natm] = (int)ent.size();
+    if ((e = upload(c, off, &d.atom_off)) != hipSuccess || (e = upload(c, ent, &d.atom_ent)) != hipSuccess) {
+      free_device(c);
+      delete c;
+      return hip_fail(nullptr, e, "uploading atom lists");
+    }
+  }
   if (d.fp32) {
     AL(dh32, (size_t)std::max<int64_t>(1, d.d32_off[kMaxLsum]))
     AL(wre, (size_t)d.nslot * d.ncolsW)
@@ -560,13 +590,37 @@ pwdf_status pwdf_get_rhoG(pwdf_ctx *c, int ndm, const double *Dk, double *rhoG, 
 }
 
 pwdf_status pwdf_grad(pwdf_ctx *c, int ndm, const double *Dk, double *dEdR, double *EJ, void *stream) {
-  (void)ndm;
-  (void)Dk;
-  (void)dEdR;
-  (void)EJ;
-  (void)stream;
   if (!c) return PWDF_EINVAL;
-  return fail(c, PWDF_EUNSUPPORTED, "gradient not built yet");
+  pwdf_status s = validate_ndm(c, ndm);
+  if (s != PWDF_OK) return s;
+  if (!Dk || !dEdR) return fail(c, PWDF_EINVAL, "NULL buffer");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  // energy path (rho, V) in the context's precision; the adjoint moments and the
+  // centre-derivative contraction run in FP64
+  if ((s = run_to_rho(c, ndm, Dk, EJ ? EJ : c->Escr, st)) != PWDF_OK) return s;
+  const Plan &p = c->plan;
+  const Dev &d = c->dev;
+  const double nGh = (double)(p.nG_full / 2);
+  char name[32];
+  for (int L = 0; L <= 2 * kMaxL; ++L) {
+    if (np_L(p, L) <= 0) continue;
+    std::snprintf(name, sizeof name, "jforce_L%d", L);
+    if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, st, [&] { return launch_jpass_force_L(d, L, ndm, st); })) !=
+        PWDF_OK)
+      return s;
+  }
+  for (int la = 0; la <= kMaxL; ++la)
+    for (int lb = 0; lb <= la; ++lb) {
+      int cl = la * 4 + lb;
+      if (p.cls_b1[cl] <= p.cls_b0[cl]) continue;
+      std::snprintf(name, sizeof name, "fback_%d%d", la, lb);
+      double units = (double)(p.blocks[p.cls_b1[cl] - 1].p1 - p.blocks[p.cls_b0[cl]].p0) * ndm;
+      if ((s = step(c, name, units, st, [&] { return launch_force_back_cls(d, la, lb, ndm, st); })) != PWDF_OK)
+        return s;
+    }
+  return step(c, "force_atoms", (double)d.natm * 3 * ndm, st, [&] { return launch_force_atoms(d, ndm, dEdR, st); });
 }
 
 pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {

@@ -47,4 +47,41 @@ __host__ __device__ constexpr int mono_idx(int a, int b, int c) {
   return idx + (d - a) - b;
 }
 
+// ---------------------------------------------------------------------------
+// McMurchie-Davidson Hermite coefficients along one axis:
+//   x_A^i x_B^j e^{-p x_P^2} = sum_t E[i][j][t] d^t/dP^t e^{-p x_P^2}
+//   E[i+1][j][t] = E[i][j][t-1]/(2p) + X_PA E[i][j][t] + (t+1) E[i][j][t+1]
+// ---------------------------------------------------------------------------
+template <int LA, int LB>
+__device__ __forceinline__ void md_axis(double inv2p, double xpa, double xpb,
+                                        double (&E)[LA + 1][LB + 1][LA + LB + 1]) {
+#pragma unroll
+  for (int i = 0; i <= LA; ++i)
+#pragma unroll
+    for (int j = 0; j <= LB; ++j)
+#pragma unroll
+      for (int t = 0; t <= LA + LB; ++t) E[i][j][t] = 0.0;
+  E[0][0][0] = 1.0;
+#pragma unroll
+  for (int i = 0; i <= LA; ++i)
+#pragma unroll
+    for (int j = 0; j <= LB; ++j) {
+      if (i == 0 && j == 0) continue;
+#pragma unroll
+      for (int t = 0; t <= i + j; ++t) {
+        double v;
+        if (i > 0) {
+          v = xpa * E[i - 1][j][t];
+          if (t > 0) v += inv2p * E[i - 1][j][t - 1];
+          if (t + 1 <= i - 1 + j) v += (t + 1) * E[i - 1][j][t + 1];
+        } else {
+          v = xpb * E[i][j - 1][t];
+          if (t > 0) v += inv2p * E[i][j - 1][t - 1];
+          if (t + 1 <= i + j - 1) v += (t + 1) * E[i][j - 1][t + 1];
+        }
+        E[i][j][t] = v;
+      }
+    }
+}
+
 }  // namespace pwdf

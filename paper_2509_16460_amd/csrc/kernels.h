@@ -57,6 +57,14 @@ struct Dev {
   int ncols32[kMaxLsum + 1];
   float *wre, *wim;
   int ncolsW;
+  // gradient: moments of degree L+1 per class, per-block centre gradients,
+  // per-atom lists of (block, 0 = shell a / 3 = shell b)
+  double *yF;
+  int64_t yF_off[kMaxLsum + 1];
+  int64_t yF_size;
+  double *gblk;              // [ndm][nblocks][6]
+  int nblocks;
+  const int *atom_off, *atom_ent;
   // launch shapes
   int rho_bs;
   int rho_chunks[kMaxLsum + 1], rho_ppc[kMaxLsum + 1], rho_row0[kMaxLsum + 1];
@@ -78,6 +86,9 @@ hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st);
 hipError_t launch_jpass_L(const Dev &d, int L, int ndm, hipStream_t st);
 hipError_t launch_back_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st);
 hipError_t launch_fold_j(const Dev &d, int ndm, hipStream_t st);
+hipError_t launch_jpass_force_L(const Dev &d, int L, int ndm, hipStream_t st);
+hipError_t launch_force_back_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st);
+hipError_t launch_force_atoms(const Dev &d, int ndm, double *dEdR, hipStream_t st);
 hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, hipStream_t st);
 
 }  // namespace pwdf

@@ -31,43 +31,6 @@
 namespace pwdf {
 
 // ---------------------------------------------------------------------------
-// McMurchie-Davidson Hermite coefficients along one axis:
-//   x_A^i x_B^j e^{-p x_P^2} = sum_t E[i][j][t] d^t/dP^t e^{-p x_P^2}
-//   E[i+1][j][t] = E[i][j][t-1]/(2p) + X_PA E[i][j][t] + (t+1) E[i][j][t+1]
-// ---------------------------------------------------------------------------
-template <int LA, int LB>
-__device__ __forceinline__ void md_axis(double inv2p, double xpa, double xpb,
-                                        double (&E)[LA + 1][LB + 1][LA + LB + 1]) {
-#pragma unroll
-  for (int i = 0; i <= LA; ++i)
-#pragma unroll
-    for (int j = 0; j <= LB; ++j)
-#pragma unroll
-      for (int t = 0; t <= LA + LB; ++t) E[i][j][t] = 0.0;
-  E[0][0][0] = 1.0;
-#pragma unroll
-  for (int i = 0; i <= LA; ++i)
-#pragma unroll
-    for (int j = 0; j <= LB; ++j) {
-      if (i == 0 && j == 0) continue;
-#pragma unroll
-      for (int t = 0; t <= i + j; ++t) {
-        double v;
-        if (i > 0) {
-          v = xpa * E[i - 1][j][t];
-          if (t > 0) v += inv2p * E[i - 1][j][t - 1];
-          if (t + 1 <= i - 1 + j) v += (t + 1) * E[i - 1][j][t + 1];
-        } else {
-          v = xpb * E[i][j - 1][t];
-          if (t > 0) v += inv2p * E[i][j - 1][t - 1];
-          if (t + 1 <= i + j - 1) v += (t + 1) * E[i][j - 1][t + 1];
-        }
-        E[i][j][t] = v;
-      }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Phase factors of the k <-> L sums: for the k-point (k1,k2,k3) of an
 // n1 x n2 x n3 mesh and the image m, k.L/2pi = sum_i k_i m_i / n_i, an integer
 // multiple t of 1/N (N = lcm of the n_i).  An image enters only through its
@@ -749,6 +712,43 @@ hipError_t launch_jpass_L(const Dev &d, int L, int ndm, hipStream_t st) {
     case 4: return j_L<4>(d, L, ndm, st);
     case 8: return j_L<8>(d, L, ndm, st);
     case 16: return j_L<16>(d, L, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Moments of degree <= L+1 for the pairs of class L (centre derivatives raise
+// one Cartesian exponent on the same Gaussian product): the J-pass kernel of
+// degree L+1 run over class-L pairs, into the force moment buffer.
+template <int L, int SEG>
+static hipError_t jforce_one(const Dev &d, int ndm, hipStream_t st) {
+  const int np = d.L_p1[L] - d.L_p0[L];
+  if (np <= 0) return hipSuccess;
+  dim3 grid((unsigned)((np + 255) / 256), d.j_chunks[L], ndm);
+  hipLaunchKernelGGL((k_jpass<L + 1, SEG>), grid, dim3(256), 0, st, d.segs, d.nseg, d.j_spc[L], d.Vc, d.nslot, d.hot,
+                     d.L_p0[L], d.L_p1[L], d.yF, d.yF_size, d.yF_off[L]);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+template <int SEG>
+static hipError_t jforce_L(const Dev &d, int L, int ndm, hipStream_t st) {
+  switch (L) {
+    case 0: return jforce_one<0, SEG>(d, ndm, st);
+    case 1: return jforce_one<1, SEG>(d, ndm, st);
+    case 2: return jforce_one<2, SEG>(d, ndm, st);
+    case 3: return jforce_one<3, SEG>(d, ndm, st);
+    case 4: return jforce_one<4, SEG>(d, ndm, st);
+    case 5: return jforce_one<5, SEG>(d, ndm, st);
+    case 6: return jforce_one<6, SEG>(d, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_jpass_force_L(const Dev &d, int L, int ndm, hipStream_t st) {
+  switch (d.seg_len) {
+    case 4: return jforce_L<4>(d, L, ndm, st);
+    case 8: return jforce_L<8>(d, L, ndm, st);
+    case 16: return jforce_L<16>(d, L, ndm, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -322,6 +322,9 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
       }
       x.pref_rho = (diag ? 1.0 : 2.0) * C / p.vol;
       x.pref_j = 2.0 * C;
+      x.alpha_a = aa;
+      x.alpha_b = ab;
+      x.w = diag ? 1.0 : 2.0;
       x.pad = 0.0;
       PairHot h;
       double f[3];

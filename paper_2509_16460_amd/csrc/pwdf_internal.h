@@ -51,6 +51,8 @@ struct PairAux {
   double xpa[3], xpb[3];  // P - A, P - (B + L)
   double pref_rho;        // w c_a c_b N_a N_b K (pi/p)^{3/2} / Omega   (w = 1 on the diagonal block, 2 otherwise)
   double pref_j;          // 2 c_a c_b N_a N_b K (pi/p)^{3/2}            (factor 2: G half space)
+  double alpha_a, alpha_b;  // primitive exponents (centre derivatives)
+  double w;                 // 1 on the diagonal block (s, s, 0), 2 otherwise
   double pad;
 };
 

@@ -249,3 +249,59 @@ class LongRangeJ:
         rc = lib().pwdf_autotune(self._h, int(ndm), cache_path.encode() if cache_path else None)
         if rc != 0:
             self._err(rc)
+
+
+def _autograd_function():
+    import torch
+
+    class LongRangeJEnergy(torch.autograd.Function):
+        """E_J[ndm] = LongRangeJEnergy.apply(Dk, xyz, plan).
+
+        Dk: complex128 [ndm][nk][nbf][nbf] on the device; xyz: float64 [natm][3]
+        (must equal the geometry the plan was built for: the pair list and G set
+        stay those of the plan, as in the gradient definition at fixed pair list).
+        backward: dE/dD(k) = w_k conj J(k) (torch's convention for complex inputs,
+        from the symmetric bilinear form E = 1/2 sum_k w_k sum D(k) J(k)) and
+        dE/dR from the adjoint kernels of pwdf_grad.
+        """
+
+        @staticmethod
+        def forward(ctx, Dk, xyz, plan):
+            ref = np.asarray(plan.prob.xyz, dtype=np.float64)
+            got = xyz.detach().to("cpu", torch.float64).numpy()
+            if got.shape != ref.shape or not np.array_equal(got, ref):
+                raise ValueError("xyz differs from the geometry of the plan; build a new LongRangeJ")
+            Jk, EJ = plan.build_j(Dk)
+            ctx.save_for_backward(Dk, Jk)
+            ctx.plan = plan
+            ctx.xyz_meta = (xyz.device, xyz.dtype)
+            return EJ
+
+        @staticmethod
+        def backward(ctx, gE):
+            Dk, Jk = ctx.saved_tensors
+            plan = ctx.plan
+            grad_D = grad_x = None
+            gE = gE.to(torch.float64)
+            if ctx.needs_input_grad[0]:
+                w = 1.0 / plan.prob.nk
+                grad_D = (gE.view(-1, 1, 1, 1) * w) * Jk.conj()
+                if Dk.dim() == 3:
+                    grad_D = grad_D[0]
+            if ctx.needs_input_grad[1]:
+                g, _ = plan.grad(Dk)
+                grad_x = (gE.view(-1, 1, 1) * g).sum(0).to(ctx.xyz_meta[0], ctx.xyz_meta[1])
+            return grad_D, grad_x, None
+
+    return LongRangeJEnergy
+
+
+_LRJE = None
+
+
+def long_range_energy(Dk, xyz, plan):
+    """Differentiable E_J (see LongRangeJEnergy)."""
+    global _LRJE
+    if _LRJE is None:
+        _LRJE = _autograd_function()
+    return _LRJE.apply(Dk, xyz, plan)
