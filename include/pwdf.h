@@ -41,8 +41,13 @@
  *   retains them.  The library owns the context (plan and device workspaces),
  *   allocated in pwdf_create; pwdf_build_j and pwdf_grad do not allocate.
  *   Device calls only enqueue work on the given HIP stream (NULL: the null
- *   stream); results are valid after the stream is synchronised.  One context
- *   must not be used by two streams at once; distinct contexts are independent.
+ *   stream); results are valid after the stream is synchronised.  Independent
+ *   per-class launches inside one call fan out over internal streams of the
+ *   context (default priority) and join back into the given stream before the
+ *   next dependent step, so stream order is preserved.  One context must not be
+ *   used by two streams at once: calls on one context that overlap in time
+ *   (different streams, or a graph replay racing an eager call) race on its
+ *   workspaces.  Distinct contexts are independent.
  *
  * Errors
  *   Every call returns a pwdf_status; nothing aborts.  Arguments are validated
@@ -92,6 +97,7 @@ typedef struct {
   int64_t nbf, nk, nimg, nblocks, nseg;
   double pairG_evals; /* per build and density: 2 passes x npairs x nG/2 */
   double t_us[8];     /* reserved */
+  int64_t seg_len;    /* line-segment length of the current launch shapes (pwdf_query) */
 } pwdf_stats;
 
 /*
@@ -149,6 +155,20 @@ pwdf_status pwdf_build_j(pwdf_ctx *ctx, int ndm, const double *Dk, double *Jk, d
                          void *stream);
 
 /*
+ * pwdf_build_j replayed as a HIP graph: the first call with a given
+ * (ndm, Dk, Jk, EJ) captures the whole launch sequence (fork/join branches
+ * included) on an internal stream, instantiates it and keeps it in the context;
+ * this and later calls with the same arguments launch the instantiated graph on
+ * `stream` (one launch instead of ~30).  Results equal those of pwdf_build_j
+ * bit for bit (same kernels, same shapes).  A call with other arguments,
+ * pwdf_autotune or pwdf_destroy drops the cached graph.  The graph holds kernel
+ * launches and event dependencies only (no memset or copy nodes).
+ * Errors: as pwdf_build_j; PWDF_ESTATE while profiling is enabled.
+ */
+pwdf_status pwdf_build_j_graph(pwdf_ctx *ctx, int ndm, const double *Dk, double *Jk, double *EJ,
+                               void *stream);
+
+/*
  * rho(G) of the last computation path for diagnostics: runs the D(k) -> rho(G)
  * part of pwdf_build_j for ndm densities and writes, for the nG/2 vectors of
  * the half space the kernels walk (rho(-G) = conj rho(G)),
@@ -172,9 +192,19 @@ pwdf_status pwdf_get_rhoG(pwdf_ctx *ctx, int ndm, const double *Dk, double *rhoG
 pwdf_status pwdf_grad(pwdf_ctx *ctx, int ndm, const double *Dk, double *dEdR, double *EJ,
                       void *stream);
 
-/* Pick launch shapes per class (segment length, chunking) by timing candidate
- * shapes on the device; must run before any graph capture of pwdf_build_j.
- * cache_path may be NULL (no persistence).  Synchronous. */
+/* Pick launch shapes by timing candidates on the device for ndm densities:
+ * first the line-segment length (4, 8, 16 points; 4, 8 for the FP32-MFMA form)
+ * by the time of the pair-G passes, then per angular class L a multiplier
+ * (1/4 .. 4) of the default number of pair chunks of the rho pass and of
+ * segment chunks of the J pass, each class keeping its fastest.  Timing runs on
+ * an internal stream over zero D(L) and does not touch caller buffers.  The
+ * device workspaces are rebuilt for the chosen shapes (this call allocates),
+ * a cached graph is dropped and profiling counters are reset.  Results of later
+ * calls agree with the untuned ones to rounding (summation order changes).
+ * cache_path: text file of "key seg_len mrho[0..7] mj[0..7]" lines keyed by
+ * arch, precision, nG, pair count, nbf, nk and ndm; an entry found there is
+ * applied without timing, a new result is appended.  NULL: no persistence.
+ * Synchronous. */
 pwdf_status pwdf_autotune(pwdf_ctx *ctx, int ndm, const char *cache_path);
 
 /* Diagnostics: per-launch HIP-event timing on the caller's stream.

@@ -26,8 +26,31 @@ struct ProfAgg {
   double ms = 0.0, units = 0.0;
 };
 
+// Launch-shape choice: segment length and, per class L, multipliers of the
+// default wave targets of the rho and J passes (chunk counts follow from them).
+struct Tune {
+  int seg_len = 8;
+  double mrho[kMaxLsum + 1];
+  double mj[kMaxLsum + 1];
+  Tune() {
+    for (int L = 0; L <= kMaxLsum; ++L) mrho[L] = mj[L] = 1.0;
+  }
+};
+
+constexpr int kAux = 4;  // internal streams for independent per-class launches
+
+struct GraphCache {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int ndm = 0;
+  const void *Dk = nullptr;
+  void *Jk = nullptr, *EJ = nullptr;
+};
+
 struct pwdf_ctx {
   Plan plan;
+  PlanInput in;
+  Tune tune;
   bool prof_on = false;
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> prof_pool;
@@ -35,8 +58,12 @@ struct pwdf_ctx {
   std::vector<std::string> prof_names;
   std::vector<ProfAgg> prof_agg;
   Dev dev;
-  std::vector<void *> owned;  // device allocations
+  std::vector<void *> owned;  // device allocations of the current setup
   double *Escr = nullptr;     // [max_ndm] energies of diagnostic calls
+  hipStream_t aux[kAux] = {};
+  hipStream_t cap = nullptr;  // capture / tuning stream
+  hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
+  GraphCache gc;
   std::string err;
   int device = 0;
   int max_ndm = 1;
@@ -90,10 +117,17 @@ void free_device(pwdf_ctx *c) {
   c->owned.clear();
 }
 
-// Launch shapes: spread each pass over about `target` waves in proportion to
-// the class's pair-G work.
-void choose_shapes(const Plan &p, Dev &d, int target_waves) {
+void drop_graph(pwdf_ctx *c) {
+  if (c->gc.exec) (void)hipGraphExecDestroy(c->gc.exec);
+  if (c->gc.graph) (void)hipGraphDestroy(c->gc.graph);
+  c->gc = GraphCache();
+}
+
+// Launch shapes: spread each pass over about 4096 waves in proportion to the
+// class's pair-G work, scaled per class by the tune multipliers.
+void choose_shapes(const Plan &p, Dev &d, const Tune &tn) {
   const int SEG = p.seg_len;
+  const double target = 4096.0;
   d.rho_bs = 256;  // 64 segments x 4 waves sharing them
   double wsum = 0.0, wL[kMaxLsum + 1];
   for (int L = 0; L <= kMaxLsum; ++L) {
@@ -116,7 +150,7 @@ void choose_shapes(const Plan &p, Dev &d, int target_waves) {
       continue;
     }
     double share = wL[L] / wsum;
-    int ch = (int)std::lround(target_waves * share / rho_waves_per_chunk);
+    int ch = (int)std::lround(target * share * tn.mrho[L] / rho_waves_per_chunk);
     ch = std::max(1, std::min(np, ch));
     int ppc = (np + ch - 1) / ch;
     ch = (np + ppc - 1) / ppc;
@@ -124,7 +158,7 @@ void choose_shapes(const Plan &p, Dev &d, int target_waves) {
     d.rho_ppc[L] = ppc;
     rows += ch;
     int jw = ((np + 255) / 256) * 4;
-    int jc = (int)std::lround(target_waves * share / jw);
+    int jc = (int)std::lround(target * share * tn.mj[L] / jw);
     jc = std::max(1, std::min(p.nseg(), jc));
     int spc = (p.nseg() + jc - 1) / jc;
     jc = (p.nseg() + spc - 1) / spc;
@@ -146,6 +180,139 @@ void choose_shapes(const Plan &p, Dev &d, int target_waves) {
   d.ngroups = (d.nrows + d.rows_per_group - 1) / d.rows_per_group;
   d.yhat_size = std::max<int64_t>(1, yoff);
   d.nred_blocks = (p.nslot() + 3) / 4;
+}
+
+// (Re)builds the device view of the plan: uploads and workspaces for the current
+// segment length and tune.  Frees the previous setup first.
+pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
+  drop_graph(c);
+  free_device(c);
+  c->tune = tn;
+  Plan &p = c->plan;
+  const PlanInput &in = c->in;
+  Dev &d = c->dev;
+  std::memset(&d, 0, sizeof(d));
+  d.nk = p.nk;
+  d.nbf = p.nbf;
+  d.nshell = in.nshell;
+  d.natm = in.natm;
+  d.nseg = p.nseg();
+  d.nslot = p.nslot();
+  d.seg_len = p.seg_len;
+  d.nelem = p.nelem;
+  d.vol = p.vol;
+  for (int i = 0; i < 16; ++i) {
+    d.cls_b0[i] = p.cls_b0[i];
+    d.cls_b1[i] = p.cls_b1[i];
+  }
+  for (int L = 0; L <= kMaxLsum; ++L) {
+    d.L_p0[L] = p.L_p0[L];
+    d.L_p1[L] = p.L_p1[L];
+    d.dhat_off[L] = p.dhat_off[L];
+  }
+  d.dhat_size = std::max<int64_t>(1, p.dhat_size);
+  d.nsegJ = (int)p.sJ_code.size();
+  d.nsegD = (int)p.sD_code.size();
+  d.fp32 = c->prec == PWDF_FP32_MFMA ? 1 : 0;
+  if (d.fp32) {
+    d.ndmp = 1;
+    while (d.ndmp < c->max_ndm) d.ndmp *= 2;
+    int64_t off = 0;
+    int lmax = 0;
+    for (int L = 0; L <= kMaxLsum; ++L) {
+      int npl = p.L_p1[L] - p.L_p0[L];
+      d.ncols32[L] = ((nherm(L) * d.ndmp + 15) / 16) * 16;
+      d.d32_off[L] = off;
+      if (npl > 0) {
+        off += (int64_t)npl * d.ncols32[L];
+        lmax = L;
+      }
+    }
+    d.ncolsW = d.ncols32[lmax];
+    d.d32_off[kMaxLsum] = off;
+  }
+  choose_shapes(p, d, tn);
+
+  hipError_t e;
+#define UP(vec, field) \
+  if ((e = upload(c, vec, &d.field)) != hipSuccess) return hip_fail(c, e, "uploading " #field);
+  UP(p.segs, segs)
+  UP(p.slot_v, slot_v)
+  UP(p.hot, hot)
+  UP(p.aux, aux)
+  UP(p.blocks, blocks)
+  UP(p.elem_blk, elem_blk)
+  UP(in.sh_l, sh_l)
+  UP(in.sh_atom, sh_atom)
+  UP(p.sp_off, sp_off)
+  UP(p.sp_ent, sp_ent)
+  UP(p.bf_shell, bf_shell)
+  UP(p.bf_comp, bf_comp)
+  UP(p.sJ_off, sJ_off)
+  UP(p.sJ_code, sJ_code)
+  UP(p.sJ_e0, sJ_e0)
+  UP(p.eJ, eJ)
+  UP(p.sD_el, sD_el)
+  UP(p.sD_code, sD_code)
+  UP(p.sD_e0, sD_e0)
+  UP(p.eD, eD)
+  UP(p.ttab, ttab)
+#undef UP
+  {
+    const double *ph;
+    if ((e = upload(c, p.phD, &ph)) != hipSuccess) return hip_fail(c, e, "uploading phase tables");
+    d.phD = (const double2 *)ph;
+    if ((e = upload(c, p.phJ, &ph)) != hipSuccess) return hip_fail(c, e, "uploading phase tables");
+    d.phJ = (const double2 *)ph;
+    if ((e = upload(c, p.ptab, &ph)) != hipSuccess) return hip_fail(c, e, "uploading phase table");
+    d.ptab = (const double2 *)ph;
+    d.ptab_len = (int)(p.ptab.size() / 2);
+    const int *ent;
+    if ((e = upload(c, p.kvec, &ent)) != hipSuccess) return hip_fail(c, e, "uploading k table");
+    d.kvec = (const int4 *)ent;
+  }
+  const size_t M = (size_t)c->max_ndm;
+#define AL(field, count) \
+  if ((e = alloc(c, (count), &d.field)) != hipSuccess) return fail(c, PWDF_ENOMEM, "device allocation failed: " #field);
+  AL(Dblk, M * p.nelem)
+  AL(Jblk, M * p.nelem)
+  AL(dhat, M * d.dhat_size)
+  AL(yhat, M * d.yhat_size)
+  AL(part, M * d.nrows * d.nslot)
+  AL(part2, M * d.ngroups * d.nslot)
+  AL(rho, M * d.nslot)
+  AL(Vc, M * d.nslot)
+  AL(Epart, M * d.nred_blocks)
+  AL(Jfold, M * (size_t)std::max(1, d.nsegJ))
+  AL(yF, M * d.yF_size)
+  d.nblocks = (int)p.blocks.size();
+  AL(gblk, M * (size_t)d.nblocks * 6)
+  if (d.fp32) {
+    AL(dh32, (size_t)std::max<int64_t>(1, d.d32_off[kMaxLsum]))
+    AL(wre, (size_t)d.nslot * d.ncolsW)
+    AL(wim, (size_t)d.nslot * d.ncolsW)
+    if ((e = hipMemset(d.dh32, 0, sizeof(float) * std::max<int64_t>(1, d.d32_off[kMaxLsum]))) != hipSuccess)
+      return hip_fail(c, e, "clearing operand buffer");
+  }
+#undef AL
+  {
+    // per atom: (block * 6 + 0) for shell a on the atom, (block * 6 + 3) for shell b
+    std::vector<std::vector<int>> per(in.natm);
+    for (int b = 0; b < d.nblocks; ++b) {
+      per[in.sh_atom[p.blocks[b].sa]].push_back(b * 6);
+      per[in.sh_atom[p.blocks[b].sb]].push_back(b * 6 + 3);
+    }
+    std::vector<int> off(in.natm + 1, 0), ent;
+    for (int a = 0; a < in.natm; ++a) {
+      off[a] = (int)ent.size();
+      ent.insert(ent.end(), per[a].begin(), per[a].end());
+    }
+    off[in.natm] = (int)ent.size();
+    if ((e = upload(c, off, &d.atom_off)) != hipSuccess || (e = upload(c, ent, &d.atom_ent)) != hipSuccess)
+      return hip_fail(c, e, "uploading atom lists");
+  }
+  if ((e = alloc(c, M, &c->Escr)) != hipSuccess) return fail(c, PWDF_ENOMEM, "device allocation failed: energies");
+  return PWDF_OK;
 }
 
 pwdf_status validate_ndm(pwdf_ctx *c, int ndm) {
@@ -189,40 +356,85 @@ pwdf_status step(pwdf_ctx *c, const char *name, double units, hipStream_t st, F 
   return PWDF_OK;
 }
 
+// Fork/join of independent per-class launches over the internal streams (they
+// write disjoint rows / blocks).  In profiling mode everything stays on `st`.
+struct Fork {
+  pwdf_ctx *c;
+  hipStream_t st;
+  bool on;
+  int next = 0;
+  Fork(pwdf_ctx *c_, hipStream_t st_) : c(c_), st(st_), on(!c_->prof_on && c_->aux[0] != nullptr) {
+    if (!on) return;
+    (void)hipEventRecord(c->ev_fork, st);
+    for (int i = 0; i < kAux; ++i) (void)hipStreamWaitEvent(c->aux[i], c->ev_fork, 0);
+  }
+  hipStream_t stream() { return on ? c->aux[next++ % kAux] : st; }
+  hipError_t join() {
+    if (!on) return hipSuccess;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < kAux; ++i) {
+      if ((e = hipEventRecord(c->ev_join[i], c->aux[i])) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(st, c->ev_join[i], 0)) != hipSuccess) return e;
+    }
+    return e;
+  }
+};
+
 int np_L(const Plan &p, int L) { return p.L_p1[L] - p.L_p0[L]; }
 
-pwdf_status run_to_rho(pwdf_ctx *c, int ndm, const double *Dk, double *EJ, hipStream_t st) {
+double cls_pairs(const Plan &p, int cl) {
+  return (double)(p.blocks[p.cls_b1[cl] - 1].p1 - p.blocks[p.cls_b0[cl]].p0);
+}
+
+// transform .. reduce (Dblk already holds D(L)); EJ device [ndm]
+pwdf_status run_mid_rho(pwdf_ctx *c, int ndm, double *EJ, hipStream_t st) {
   const Plan &p = c->plan;
   const Dev &d = c->dev;
   const double nGh = (double)(p.nG_full / 2);
   pwdf_status s;
+  char name[32];
+  {
+    Fork f(c, st);
+    for (int la = 0; la <= kMaxL; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        int cl = la * 4 + lb;
+        if (p.cls_b1[cl] <= p.cls_b0[cl]) continue;
+        std::snprintf(name, sizeof name, "transform_%d%d", la, lb);
+        hipStream_t ss = f.stream();
+        if ((s = step(c, name, cls_pairs(p, cl) * ndm, ss, [&] { return launch_transform_cls(d, la, lb, ndm, ss); })) !=
+            PWDF_OK)
+          return s;
+      }
+    if (hipError_t e = f.join()) return hip_fail(c, e, "join");
+  }
+  {
+    Fork f(c, st);
+    for (int L = 0; L <= 2 * kMaxL; ++L) {
+      if (np_L(p, L) <= 0) continue;
+      std::snprintf(name, sizeof name, d.fp32 ? "rho_mfma_L%d" : "rho_L%d", L);
+      hipStream_t ss = f.stream();
+      if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, ss, [&] {
+             return d.fp32 ? launch_rho_mfma_L(d, L, ndm, ss) : launch_rho_L(d, L, ndm, ss);
+           })) != PWDF_OK)
+        return s;
+    }
+    if (hipError_t e = f.join()) return hip_fail(c, e, "join");
+  }
+  return step(c, "reduce", (double)p.nslot() * ndm, st, [&] { return launch_reduce(d, ndm, EJ, st); });
+}
+
+pwdf_status run_to_rho(pwdf_ctx *c, int ndm, const double *Dk, double *EJ, hipStream_t st) {
+  const Plan &p = c->plan;
+  const Dev &d = c->dev;
+  pwdf_status s;
   if ((s = step(c, "phase_d", (double)p.nelem * p.nk * ndm, st, [&] { return launch_phase_d(d, Dk, ndm, st); })) !=
       PWDF_OK)
     return s;
-  char name[32];
-  for (int la = 0; la <= kMaxL; ++la)
-    for (int lb = 0; lb <= la; ++lb) {
-      int cl = la * 4 + lb;
-      if (p.cls_b1[cl] <= p.cls_b0[cl]) continue;
-      std::snprintf(name, sizeof name, "transform_%d%d", la, lb);
-      double units = (double)(p.blocks[p.cls_b1[cl] - 1].p1 - p.blocks[p.cls_b0[cl]].p0) * ndm;
-      if ((s = step(c, name, units, st, [&] { return launch_transform_cls(d, la, lb, ndm, st); })) != PWDF_OK)
-        return s;
-    }
-  for (int L = 0; L <= 2 * kMaxL; ++L) {
-    if (np_L(p, L) <= 0) continue;
-    std::snprintf(name, sizeof name, d.fp32 ? "rho_mfma_L%d" : "rho_L%d", L);
-    if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, st, [&] {
-           return d.fp32 ? launch_rho_mfma_L(d, L, ndm, st) : launch_rho_L(d, L, ndm, st);
-         })) != PWDF_OK)
-      return s;
-  }
-  if ((s = step(c, "reduce", (double)p.nslot() * ndm, st, [&] { return launch_reduce(d, ndm, EJ, st); })) != PWDF_OK)
-    return s;
-  return PWDF_OK;
+  return run_mid_rho(c, ndm, EJ, st);
 }
 
-pwdf_status run_from_V(pwdf_ctx *c, int ndm, double *Jk, hipStream_t st) {
+// (wprep) .. back transform: Jblk from V
+pwdf_status run_mid_j(pwdf_ctx *c, int ndm, hipStream_t st) {
   const Plan &p = c->plan;
   const Dev &d = c->dev;
   const double nGh = (double)(p.nG_full / 2);
@@ -231,28 +443,51 @@ pwdf_status run_from_V(pwdf_ctx *c, int ndm, double *Jk, hipStream_t st) {
   if (d.fp32 && (s = step(c, "wprep", (double)p.nslot() * ndm, st, [&] { return launch_wprep(d, ndm, st); })) !=
                     PWDF_OK)
     return s;
-  for (int L = 0; L <= 2 * kMaxL; ++L) {
-    if (np_L(p, L) <= 0) continue;
-    std::snprintf(name, sizeof name, d.fp32 ? "jpass_mfma_L%d" : "jpass_L%d", L);
-    if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, st, [&] {
-           return d.fp32 ? launch_jpass_mfma_L(d, L, ndm, st) : launch_jpass_L(d, L, ndm, st);
-         })) != PWDF_OK)
-      return s;
-  }
-  for (int la = 0; la <= kMaxL; ++la)
-    for (int lb = 0; lb <= la; ++lb) {
-      int cl = la * 4 + lb;
-      if (p.cls_b1[cl] <= p.cls_b0[cl]) continue;
-      std::snprintf(name, sizeof name, "back_%d%d", la, lb);
-      double units = (double)(p.blocks[p.cls_b1[cl] - 1].p1 - p.blocks[p.cls_b0[cl]].p0) * ndm;
-      if ((s = step(c, name, units, st, [&] { return launch_back_cls(d, la, lb, ndm, st); })) != PWDF_OK) return s;
+  {
+    Fork f(c, st);
+    for (int L = 0; L <= 2 * kMaxL; ++L) {
+      if (np_L(p, L) <= 0) continue;
+      std::snprintf(name, sizeof name, d.fp32 ? "jpass_mfma_L%d" : "jpass_L%d", L);
+      hipStream_t ss = f.stream();
+      if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, ss, [&] {
+             return d.fp32 ? launch_jpass_mfma_L(d, L, ndm, ss) : launch_jpass_L(d, L, ndm, ss);
+           })) != PWDF_OK)
+        return s;
     }
+    if (hipError_t e = f.join()) return hip_fail(c, e, "join");
+  }
+  {
+    Fork f(c, st);
+    for (int la = 0; la <= kMaxL; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        int cl = la * 4 + lb;
+        if (p.cls_b1[cl] <= p.cls_b0[cl]) continue;
+        std::snprintf(name, sizeof name, "back_%d%d", la, lb);
+        hipStream_t ss = f.stream();
+        if ((s = step(c, name, cls_pairs(p, cl) * ndm, ss, [&] { return launch_back_cls(d, la, lb, ndm, ss); })) !=
+            PWDF_OK)
+          return s;
+      }
+    if (hipError_t e = f.join()) return hip_fail(c, e, "join");
+  }
+  return PWDF_OK;
+}
+
+pwdf_status run_from_V(pwdf_ctx *c, int ndm, double *Jk, hipStream_t st) {
+  const Plan &p = c->plan;
+  const Dev &d = c->dev;
+  pwdf_status s;
+  if ((s = run_mid_j(c, ndm, st)) != PWDF_OK) return s;
   if ((s = step(c, "fold_j", (double)p.eJ.size() * ndm, st, [&] { return launch_fold_j(d, ndm, st); })) != PWDF_OK)
     return s;
-  if ((s = step(c, "phase_j", (double)p.nk * p.nbf * (double)p.nbf * ndm, st,
-                [&] { return launch_phase_j(d, ndm, Jk, st); })) != PWDF_OK)
-    return s;
-  return PWDF_OK;
+  return step(c, "phase_j", (double)p.nk * p.nbf * (double)p.nbf * ndm, st,
+              [&] { return launch_phase_j(d, ndm, Jk, st); });
+}
+
+pwdf_status enqueue_build(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, double *EJ, hipStream_t st) {
+  pwdf_status s;
+  if ((s = run_to_rho(c, ndm, Dk, EJ, st)) != PWDF_OK) return s;
+  return run_from_V(c, ndm, Jk, st);
 }
 
 }  // namespace
@@ -305,6 +540,7 @@ static void fill_stats(const Plan &p, pwdf_stats *out) {
   out->nblocks = (int64_t)p.blocks.size();
   out->nseg = p.nseg();
   out->pairG_evals = 2.0 * (double)p.npairs() * (double)(p.nG_full / 2);
+  out->seg_len = p.seg_len;
 }
 
 pwdf_status pwdf_plan_stats(const double lattice[9], int natm, const double *xyz, int nshell, const int *shell_atom,
@@ -327,6 +563,8 @@ pwdf_status pwdf_plan_stats(const double lattice[9], int natm, const double *xyz
   return PWDF_OK;
 }
 
+void pwdf_destroy(pwdf_ctx *c);
+
 pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const double *xyz, int nshell,
                         const int *shell_atom, const int *shell_l, const int *shell_nprim, const double *exps,
                         const double *coefs, const int kmesh[3], double omega, const pwdf_screen *screen,
@@ -335,18 +573,21 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
   *out = nullptr;
   if (max_ndm < 1) return fail(nullptr, PWDF_EINVAL, "max_ndm must be >= 1");
   if (prec != PWDF_FP64 && prec != PWDF_FP32_MFMA) return fail(nullptr, PWDF_EUNSUPPORTED, "unknown precision");
-  PlanInput in;
-  {
-    pwdf_status s = make_input(in, lattice, natm, xyz, nshell, shell_atom, shell_l, shell_nprim, exps, coefs, kmesh,
-                               omega, screen);
-    if (s != PWDF_OK) return s;
-  }
-
+  if (prec == PWDF_FP32_MFMA && max_ndm > 16)
+    return fail(nullptr, PWDF_EUNSUPPORTED, "the FP32-MFMA form takes at most 16 densities per call");
   pwdf_ctx *c = new (std::nothrow) pwdf_ctx();
   if (!c) return fail(nullptr, PWDF_ENOMEM, "host allocation failed");
+  {
+    pwdf_status s = make_input(c->in, lattice, natm, xyz, nshell, shell_atom, shell_l, shell_nprim, exps, coefs,
+                               kmesh, omega, screen);
+    if (s != PWDF_OK) {
+      delete c;
+      return s;
+    }
+  }
   std::string why;
   try {
-    why = build_plan(in, 8, c->plan);
+    why = build_plan(c->in, 8, c->plan);
   } catch (const std::bad_alloc &) {
     delete c;
     return fail(nullptr, PWDF_ENOMEM, "host allocation failed while building the plan");
@@ -377,167 +618,21 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
     delete c;
     return fail(nullptr, PWDF_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
   }
-  Plan &p = c->plan;
-  Dev &d = c->dev;
-  std::memset(&d, 0, sizeof(d));
-  d.nk = p.nk;
-  d.nbf = p.nbf;
-  d.nshell = in.nshell;
-  d.natm = in.natm;
-  d.nseg = p.nseg();
-  d.nslot = p.nslot();
-  d.seg_len = p.seg_len;
-  d.nelem = p.nelem;
-  d.vol = p.vol;
-  for (int i = 0; i < 16; ++i) {
-    d.cls_b0[i] = p.cls_b0[i];
-    d.cls_b1[i] = p.cls_b1[i];
+  // internal streams (default priority) and fork/join events
+  bool ok = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; ok && i < kAux; ++i)
+    ok = hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&c->ev_join[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    pwdf_destroy(c);
+    return fail(nullptr, PWDF_EDEVICE, "creating internal streams");
   }
-  for (int L = 0; L <= kMaxLsum; ++L) {
-    d.L_p0[L] = p.L_p0[L];
-    d.L_p1[L] = p.L_p1[L];
-    d.dhat_off[L] = p.dhat_off[L];
-  }
-  d.dhat_size = std::max<int64_t>(1, p.dhat_size);
-  d.nsegJ = (int)p.sJ_code.size();
-  d.fp32 = prec == PWDF_FP32_MFMA ? 1 : 0;
-  if (d.fp32) {
-    if (max_ndm > 16) {
-      delete c;
-      return fail(nullptr, PWDF_EUNSUPPORTED, "the FP32-MFMA form takes at most 16 densities per call");
-    }
-    d.ndmp = 1;
-    while (d.ndmp < max_ndm) d.ndmp *= 2;
-    int64_t off = 0;
-    int lmax = 0;
-    for (int L = 0; L <= kMaxLsum; ++L) {
-      int npl = p.L_p1[L] - p.L_p0[L];
-      d.ncols32[L] = ((nherm(L) * d.ndmp + 15) / 16) * 16;
-      d.d32_off[L] = off;
-      if (npl > 0) {
-        off += (int64_t)npl * d.ncols32[L];
-        lmax = L;
-      }
-    }
-    d.ncolsW = d.ncols32[lmax];
-    d.d32_off[kMaxLsum] = off;
-  }
-  d.nsegD = (int)p.sD_code.size();
-  choose_shapes(p, d, 4096);
-
-#define UP(vec, field)                                                  \
-  if ((e = upload(c, vec, &d.field)) != hipSuccess) {                   \
-    pwdf_status s_ = hip_fail(nullptr, e, "uploading " #field);         \
-    free_device(c);                                                     \
-    delete c;                                                           \
-    return s_;                                                          \
-  }
-  UP(p.segs, segs)
-  UP(p.slot_v, slot_v)
-  UP(p.hot, hot)
-  UP(p.aux, aux)
-  UP(p.blocks, blocks)
-  UP(p.elem_blk, elem_blk)
-  UP(in.sh_l, sh_l)
-  UP(in.sh_atom, sh_atom)
-  UP(p.sp_off, sp_off)
-  UP(p.sp_ent, sp_ent)
-  UP(p.bf_shell, bf_shell)
-  UP(p.bf_comp, bf_comp)
-  UP(p.sJ_off, sJ_off)
-  UP(p.sJ_code, sJ_code)
-  UP(p.sJ_e0, sJ_e0)
-  UP(p.eJ, eJ)
-  UP(p.sD_el, sD_el)
-  UP(p.sD_code, sD_code)
-  UP(p.sD_e0, sD_e0)
-  UP(p.eD, eD)
-  UP(p.ttab, ttab)
-#undef UP
-  {
-    const double *ph;
-    if ((e = upload(c, p.phD, &ph)) != hipSuccess) {
-      free_device(c);
-      delete c;
-      return hip_fail(nullptr, e, "uploading phase tables");
-    }
-    d.phD = (const double2 *)ph;
-    if ((e = upload(c, p.phJ, &ph)) != hipSuccess) {
-      free_device(c);
-      delete c;
-      return hip_fail(nullptr, e, "uploading phase tables");
-    }
-    d.phJ = (const double2 *)ph;
-    const int *ent;
-    const double *pt;
-    if ((e = upload(c, p.ptab, &pt)) != hipSuccess) {
-      free_device(c);
-      delete c;
-      return hip_fail(nullptr, e, "uploading phase table");
-    }
-    d.ptab = (const double2 *)pt;
-    d.ptab_len = (int)(p.ptab.size() / 2);
-    if ((e = upload(c, p.kvec, &ent)) != hipSuccess) {
-      free_device(c);
-      delete c;
-      return hip_fail(nullptr, e, "uploading k table");
-    }
-    d.kvec = (const int4 *)ent;
-  }
-  const size_t M = (size_t)max_ndm;
-#define AL(field, count)                                                \
-  if ((e = alloc(c, (count), &d.field)) != hipSuccess) {                \
-    free_device(c);                                                     \
-    delete c;                                                           \
-    return fail(nullptr, PWDF_ENOMEM, "device allocation failed: " #field); \
-  }
-  AL(Dblk, M * p.nelem)
-  AL(Jblk, M * p.nelem)
-  AL(dhat, M * d.dhat_size)
-  AL(yhat, M * d.yhat_size)
-  AL(part, M * d.nrows * d.nslot)
-  AL(part2, M * d.ngroups * d.nslot)
-  AL(rho, M * d.nslot)
-  AL(Vc, M * d.nslot)
-  AL(Epart, M * d.nred_blocks)
-  AL(Jfold, M * (size_t)std::max(1, d.nsegJ))
-  AL(yF, M * d.yF_size)
-  d.nblocks = (int)p.blocks.size();
-  AL(gblk, M * (size_t)d.nblocks * 6)
-  {
-    // per atom: (block * 6 + 0) for shell a on the atom, (block * 6 + 3) for shell b
-    std::vector<std::vector<int>> per(in.natm);
-    for (int b = 0; b < d.nblocks; ++b) {
-      per[in.sh_atom[p.blocks[b].sa]].push_back(b * 6);
-      per[in.sh_atom[p.blocks[b].sb]].push_back(b * 6 + 3);
-    }
-    std::vector<int> off(in.natm + 1, 0), ent;
-    for (int a = 0; a < in.natm; ++a) {
-      off[a] = (int)ent.size();
-      ent.insert(ent.end(), per[a].begin(), per[a].end());
-    }
-    off[in.natm] = (int)ent.size();
-    if ((e = upload(c, off, &d.atom_off)) != hipSuccess || (e = upload(c, ent, &d.atom_ent)) != hipSuccess) {
-      free_device(c);
-      delete c;
-      return hip_fail(nullptr, e, "uploading atom lists");
-    }
-  }
-  if (d.fp32) {
-    AL(dh32, (size_t)std::max<int64_t>(1, d.d32_off[kMaxLsum]))
-    AL(wre, (size_t)d.nslot * d.ncolsW)
-    AL(wim, (size_t)d.nslot * d.ncolsW)
-    if ((e = hipMemset(d.dh32, 0, sizeof(float) * std::max<int64_t>(1, d.d32_off[kMaxLsum]))) != hipSuccess) {
-      free_device(c);
-      delete c;
-      return hip_fail(nullptr, e, "clearing operand buffer");
-    }
-  }
-#undef AL
-  if ((e = alloc(c, M, &c->Escr)) != hipSuccess) {
-    free_device(c);
-    delete c;
-    return fail(nullptr, PWDF_ENOMEM, "device allocation failed: energies");
+  pwdf_status s = setup_device(c, Tune());
+  if (s != PWDF_OK) {
+    std::string m = c->err;
+    pwdf_destroy(c);
+    return fail(nullptr, s, m);
   }
   *out = c;
   return PWDF_OK;
@@ -546,6 +641,7 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
 pwdf_status pwdf_query(const pwdf_ctx *c, pwdf_stats *out) {
   if (!c || !out) return PWDF_EINVAL;
   fill_stats(c->plan, out);
+  out->seg_len = c->plan.seg_len;
   return PWDF_OK;
 }
 
@@ -554,11 +650,47 @@ pwdf_status pwdf_build_j(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, dou
   pwdf_status s = validate_ndm(c, ndm);
   if (s != PWDF_OK) return s;
   if (!Dk || !Jk || !EJ) return fail(c, PWDF_EINVAL, "NULL buffer");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  return enqueue_build(c, ndm, Dk, Jk, EJ, (hipStream_t)stream);
+}
+
+pwdf_status pwdf_build_j_graph(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, double *EJ, void *stream) {
+  if (!c) return PWDF_EINVAL;
+  pwdf_status s = validate_ndm(c, ndm);
+  if (s != PWDF_OK) return s;
+  if (!Dk || !Jk || !EJ) return fail(c, PWDF_EINVAL, "NULL buffer");
+  if (c->prof_on) return fail(c, PWDF_ESTATE, "graph replay is not available in profiling mode");
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-  if ((s = run_to_rho(c, ndm, Dk, EJ, st)) != PWDF_OK) return s;
-  return run_from_V(c, ndm, Jk, st);
+  GraphCache &g = c->gc;
+  if (!(g.exec && g.ndm == ndm && g.Dk == Dk && g.Jk == Jk && g.EJ == EJ)) {
+    drop_graph(c);
+    if ((e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(c, e, "begin capture");
+    s = enqueue_build(c, ndm, Dk, Jk, EJ, c->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->cap, &graph);
+    if (s != PWDF_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e2 != hipSuccess) return hip_fail(c, e2, "end capture");
+    hipGraphExec_t exec = nullptr;
+    if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(c, e, "graph instantiate");
+    }
+    g.graph = graph;
+    g.exec = exec;
+    g.ndm = ndm;
+    g.Dk = Dk;
+    g.Jk = Jk;
+    g.EJ = EJ;
+  }
+  if ((e = hipGraphLaunch(g.exec, st)) != hipSuccess) return hip_fail(c, e, "graph launch");
+  return PWDF_OK;
 }
 
 pwdf_status pwdf_get_rhoG(pwdf_ctx *c, int ndm, const double *Dk, double *rhoG, int *miller, void *stream) {
@@ -604,29 +736,203 @@ pwdf_status pwdf_grad(pwdf_ctx *c, int ndm, const double *Dk, double *dEdR, doub
   const Dev &d = c->dev;
   const double nGh = (double)(p.nG_full / 2);
   char name[32];
-  for (int L = 0; L <= 2 * kMaxL; ++L) {
-    if (np_L(p, L) <= 0) continue;
-    std::snprintf(name, sizeof name, "jforce_L%d", L);
-    if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, st, [&] { return launch_jpass_force_L(d, L, ndm, st); })) !=
-        PWDF_OK)
-      return s;
-  }
-  for (int la = 0; la <= kMaxL; ++la)
-    for (int lb = 0; lb <= la; ++lb) {
-      int cl = la * 4 + lb;
-      if (p.cls_b1[cl] <= p.cls_b0[cl]) continue;
-      std::snprintf(name, sizeof name, "fback_%d%d", la, lb);
-      double units = (double)(p.blocks[p.cls_b1[cl] - 1].p1 - p.blocks[p.cls_b0[cl]].p0) * ndm;
-      if ((s = step(c, name, units, st, [&] { return launch_force_back_cls(d, la, lb, ndm, st); })) != PWDF_OK)
+  {
+    Fork f(c, st);
+    for (int L = 0; L <= 2 * kMaxL; ++L) {
+      if (np_L(p, L) <= 0) continue;
+      std::snprintf(name, sizeof name, "jforce_L%d", L);
+      hipStream_t ss = f.stream();
+      if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, ss,
+                    [&] { return launch_jpass_force_L(d, L, ndm, ss); })) != PWDF_OK)
         return s;
     }
+    if ((e = f.join()) != hipSuccess) return hip_fail(c, e, "join");
+  }
+  {
+    Fork f(c, st);
+    for (int la = 0; la <= kMaxL; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        int cl = la * 4 + lb;
+        if (p.cls_b1[cl] <= p.cls_b0[cl]) continue;
+        std::snprintf(name, sizeof name, "fback_%d%d", la, lb);
+        hipStream_t ss = f.stream();
+        if ((s = step(c, name, cls_pairs(p, cl) * ndm, ss,
+                      [&] { return launch_force_back_cls(d, la, lb, ndm, ss); })) != PWDF_OK)
+          return s;
+      }
+    if ((e = f.join()) != hipSuccess) return hip_fail(c, e, "join");
+  }
   return step(c, "force_atoms", (double)d.natm * 3 * ndm, st, [&] { return launch_force_atoms(d, ndm, dEdR, st); });
 }
 
+// ---------------------------------------------------------------------------
+// autotuning
+// ---------------------------------------------------------------------------
+
+static std::string tune_key(const pwdf_ctx *c, int ndm) {
+  char k[256];
+  std::snprintf(k, sizeof k, "gfx950|%s|nG=%lld|pairs=%d|nbf=%d|nk=%d|ndm=%d", c->prec == PWDF_FP64 ? "fp64" : "fp32",
+                (long long)c->plan.nG_full, c->plan.npairs(), c->plan.nbf, c->plan.nk, ndm);
+  return k;
+}
+
+static bool load_tune(const char *path, const std::string &key, Tune &t) {
+  if (!path) return false;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[2048];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    char kbuf[512];
+    int seg;
+    int n = 0;
+    if (std::sscanf(line, "%511s %d%n", kbuf, &seg, &n) < 2 || key != kbuf) continue;
+    Tune u;
+    u.seg_len = seg;
+    const char *q = line + n;
+    bool good = true;
+    for (int L = 0; L <= kMaxLsum && good; ++L) {
+      int m = 0;
+      good = std::sscanf(q, "%lf%n", &u.mrho[L], &m) == 1;
+      q += m;
+    }
+    for (int L = 0; L <= kMaxLsum && good; ++L) {
+      int m = 0;
+      good = std::sscanf(q, "%lf%n", &u.mj[L], &m) == 1;
+      q += m;
+    }
+    if (good) {
+      t = u;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+static void save_tune(const char *path, const std::string &key, const Tune &t) {
+  if (!path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d", key.c_str(), t.seg_len);
+  for (int L = 0; L <= kMaxLsum; ++L) std::fprintf(f, " %.6g", t.mrho[L]);
+  for (int L = 0; L <= kMaxLsum; ++L) std::fprintf(f, " %.6g", t.mj[L]);
+  std::fprintf(f, "\n");
+  std::fclose(f);
+}
+
+// Per-kernel milliseconds of the tunable part (transform .. back transform), one
+// warm-up and `reps` profiled repetitions on the tuning stream.
+static pwdf_status time_tunable(pwdf_ctx *c, int ndm, int reps, std::vector<std::pair<std::string, double>> &out,
+                                double &total) {
+  pwdf_status s;
+  hipError_t e;
+  if ((e = hipMemsetAsync(c->dev.Dblk, 0, sizeof(double) * (size_t)ndm * c->plan.nelem, c->cap)) != hipSuccess)
+    return hip_fail(c, e, "tune clear");
+  if ((s = run_mid_rho(c, ndm, c->Escr, c->cap)) != PWDF_OK) return s;
+  if ((s = run_mid_j(c, ndm, c->cap)) != PWDF_OK) return s;
+  if ((e = hipStreamSynchronize(c->cap)) != hipSuccess) return hip_fail(c, e, "tune sync");
+  c->prof_on = true;
+  c->prof_recs.clear();
+  c->prof_next = 0;
+  for (auto &a : c->prof_agg) a = ProfAgg();
+  for (int r = 0; r < reps; ++r) {
+    if ((s = run_mid_rho(c, ndm, c->Escr, c->cap)) != PWDF_OK) break;
+    if ((s = run_mid_j(c, ndm, c->cap)) != PWDF_OK) break;
+  }
+  c->prof_on = false;
+  if (s != PWDF_OK) return s;
+  total = 0.0;
+  out.clear();
+  for (const ProfRec &r : c->prof_recs) {
+    if ((e = hipEventSynchronize(r.b)) != hipSuccess) return hip_fail(c, e, "tune events");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    total += ms / reps;
+    bool hit = false;
+    for (auto &kv : out)
+      if (kv.first == c->prof_names[r.id]) {
+        kv.second += ms / reps;
+        hit = true;
+      }
+    if (!hit) out.push_back({c->prof_names[r.id], ms / reps});
+  }
+  c->prof_recs.clear();
+  c->prof_next = 0;
+  return PWDF_OK;
+}
+
+static double kernel_ms(const std::vector<std::pair<std::string, double>> &v, const std::string &name) {
+  for (auto &kv : v)
+    if (kv.first == name) return kv.second;
+  return 0.0;
+}
+
 pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
-  (void)ndm;
-  (void)cache_path;
   if (!c) return PWDF_EINVAL;
+  pwdf_status s = validate_ndm(c, ndm);
+  if (s != PWDF_OK) return s;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  // the workspaces are rebuilt below: nothing may still be running on them
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+  const std::string key = tune_key(c, ndm);
+  Tune best;
+  if (load_tune(cache_path, key, best)) {
+    if (best.seg_len != c->plan.seg_len) build_segments(c->plan, best.seg_len);
+    return setup_device(c, best);
+  }
+  const bool was_prof = c->prof_on;
+  // 1. segment length
+  std::vector<int> segs = c->prec == PWDF_FP32_MFMA ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 16};
+  double best_t = 1e300;
+  std::vector<std::pair<std::string, double>> per;
+  for (int sl : segs) {
+    build_segments(c->plan, sl);
+    Tune t;
+    t.seg_len = sl;
+    if ((s = setup_device(c, t)) != PWDF_OK) return s;
+    double tot = 0.0;
+    if ((s = time_tunable(c, ndm, 3, per, tot)) != PWDF_OK) return s;
+    if (tot < best_t) {
+      best_t = tot;
+      best = t;
+    }
+  }
+  // 2. per-class chunk multipliers at the chosen segment length
+  build_segments(c->plan, best.seg_len);
+  const double mults[] = {0.25, 0.5, 1.0, 2.0, 4.0};
+  double brho[kMaxLsum + 1], bj[kMaxLsum + 1];
+  for (int L = 0; L <= kMaxLsum; ++L) brho[L] = bj[L] = 1e300;
+  const char *rn = c->prec == PWDF_FP32_MFMA ? "rho_mfma_L%d" : "rho_L%d";
+  const char *jn = c->prec == PWDF_FP32_MFMA ? "jpass_mfma_L%d" : "jpass_L%d";
+  Tune cand = best;
+  for (double m : mults) {
+    Tune t = best;
+    for (int L = 0; L <= kMaxLsum; ++L) t.mrho[L] = t.mj[L] = m;
+    if ((s = setup_device(c, t)) != PWDF_OK) return s;
+    double tot = 0.0;
+    if ((s = time_tunable(c, ndm, 3, per, tot)) != PWDF_OK) return s;
+    char name[32];
+    for (int L = 0; L <= 2 * kMaxL; ++L) {
+      if (np_L(c->plan, L) <= 0) continue;
+      std::snprintf(name, sizeof name, rn, L);
+      double tr = kernel_ms(per, name);
+      std::snprintf(name, sizeof name, jn, L);
+      double tj = kernel_ms(per, name);
+      if (tr < brho[L]) {
+        brho[L] = tr;
+        cand.mrho[L] = m;
+      }
+      if (tj < bj[L]) {
+        bj[L] = tj;
+        cand.mj[L] = m;
+      }
+    }
+  }
+  c->prof_on = was_prof;
+  if ((s = setup_device(c, cand)) != PWDF_OK) return s;
+  save_tune(cache_path, key, cand);
   return PWDF_OK;
 }
 
@@ -676,7 +982,17 @@ const char *pwdf_last_error(const pwdf_ctx *c) { return c ? c->err.c_str() : g_c
 void pwdf_destroy(pwdf_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  for (int i = 0; i < kAux; ++i)
+    if (c->aux[i]) (void)hipStreamSynchronize(c->aux[i]);
+  if (c->cap) (void)hipStreamSynchronize(c->cap);
+  drop_graph(c);
   for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
+  for (int i = 0; i < kAux; ++i) {
+    if (c->aux[i]) (void)hipStreamDestroy(c->aux[i]);
+    if (c->ev_join[i]) (void)hipEventDestroy(c->ev_join[i]);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   free_device(c);
   delete c;
 }

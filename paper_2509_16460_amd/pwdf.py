@@ -22,7 +22,7 @@ PWDF_FP32_MFMA = 1
 _STATUS = {0: "PWDF_OK", -1: "PWDF_EINVAL", -2: "PWDF_ENOMEM", -3: "PWDF_EDEVICE",
            -4: "PWDF_EUNSUPPORTED", -5: "PWDF_ENONFINITE", -6: "PWDF_ESTATE"}
 
-EXPORTED = ["pwdf_create", "pwdf_query", "pwdf_build_j", "pwdf_get_rhoG", "pwdf_grad",
+EXPORTED = ["pwdf_create", "pwdf_query", "pwdf_build_j", "pwdf_build_j_graph", "pwdf_get_rhoG", "pwdf_grad",
             "pwdf_autotune", "pwdf_last_error", "pwdf_destroy", "pwdf_plan_stats",
             "pwdf_profile_enable", "pwdf_profile_read"]
 
@@ -41,7 +41,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("npairs_by_class", ctypes.c_int64 * 16), ("nG", ctypes.c_int64), ("npairs", ctypes.c_int64),
                 ("nbf", ctypes.c_int64), ("nk", ctypes.c_int64), ("nimg", ctypes.c_int64),
                 ("nblocks", ctypes.c_int64), ("nseg", ctypes.c_int64), ("pairG_evals", ctypes.c_double),
-                ("t_us", ctypes.c_double * 8)]
+                ("t_us", ctypes.c_double * 8), ("seg_len", ctypes.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("npairs_by_class", "t_us")}
@@ -75,6 +75,8 @@ def lib():
         L.pwdf_query.argtypes = [vp, ctypes.POINTER(Stats)]
         L.pwdf_build_j.restype = ctypes.c_int
         L.pwdf_build_j.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+        L.pwdf_build_j_graph.restype = ctypes.c_int
+        L.pwdf_build_j_graph.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
         L.pwdf_get_rhoG.restype = ctypes.c_int
         L.pwdf_get_rhoG.argtypes = [vp, ctypes.c_int, vp, vp, ip, vp]
         L.pwdf_grad.restype = ctypes.c_int
@@ -184,9 +186,11 @@ class LongRangeJ:
             raise ValueError(f"Dk shape {tuple(Dk.shape)} != [ndm, {p.nk}, {p.nbf}, {p.nbf}]")
         return Dk
 
-    def build_j(self, Dk, Jk=None, EJ=None, stream=None):
+    def build_j(self, Dk, Jk=None, EJ=None, stream=None, graph=False):
         """Dk: complex128 [ndm][nk][nbf][nbf] (or [nk][nbf][nbf]) on the device.
-        Returns (Jk, EJ) device tensors; enqueued on `stream` (default: current)."""
+        Returns (Jk, EJ) device tensors; enqueued on `stream` (default: current).
+        graph=True goes through pwdf_build_j_graph (captured once per set of
+        buffers, then replayed): pass the same Jk / EJ tensors on every call."""
         import torch
         Dk = self._check_D(Dk)
         ndm = Dk.shape[0]
@@ -194,8 +198,9 @@ class LongRangeJ:
             Jk = torch.empty_like(Dk)
         if EJ is None:
             EJ = torch.empty(ndm, dtype=torch.float64, device=Dk.device)
-        rc = lib().pwdf_build_j(self._h, ndm, ctypes.c_void_p(Dk.data_ptr()), ctypes.c_void_p(Jk.data_ptr()),
-                                ctypes.c_void_p(EJ.data_ptr()), self._stream(stream))
+        fn = lib().pwdf_build_j_graph if graph else lib().pwdf_build_j
+        rc = fn(self._h, ndm, ctypes.c_void_p(Dk.data_ptr()), ctypes.c_void_p(Jk.data_ptr()),
+                ctypes.c_void_p(EJ.data_ptr()), self._stream(stream))
         if rc != 0:
             self._err(rc)
         return Jk, EJ

@@ -1,0 +1,135 @@
+"""Launch runtime of the HIP path (needs an MI355X).
+
+* fork/join over the context's internal streams is deterministic: two eager
+  calls, and an eager call with profiling on (everything on one stream), give
+  bit-identical J(k) and E_J;
+* pwdf_build_j_graph: the captured graph, replayed several times with other
+  eager work and new D(k) contents between replays, reproduces the eager result
+  of each density bit for bit (same kernels, same shapes, no memset nodes);
+* pwdf_autotune: the tuned context still meets the FP64 bar against the oracle,
+  writes a cache entry, and a second context applies the cached shapes without
+  timing (same segment length, bit-identical results to the first tuned one).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_16460_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def pw():
+    from paper_2509_16460_amd import pwdf
+    return pwdf
+
+
+def problem():
+    return synth.small_problem(kind="runtime", seed=61, kmesh=(2, 1, 2), lmax=3, natm=2, lo=0.3, hi=18.0)
+
+
+def dev(D):
+    return torch.from_numpy(np.ascontiguousarray(D[None] if D.ndim == 3 else D)).cuda()
+
+
+def test_fork_join_deterministic():
+    p = problem()
+    D = synth.make_density(p, 611)
+    ctx = pw().LongRangeJ(p, max_ndm=1)
+    J1, E1 = ctx.build_j(dev(D))
+    J2, E2 = ctx.build_j(dev(D))
+    ctx.profile_enable(True)
+    J3, E3 = ctx.build_j(dev(D))
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    torch.cuda.synchronize()
+    assert torch.equal(J1, J2) and torch.equal(E1, E2)
+    assert torch.equal(J1, J3) and torch.equal(E1, E3)
+    assert any(k.startswith("rho_L") for k in prof) and "phase_j" in prof
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32_mfma"])
+def test_graph_replay_matches_eager(prec):
+    p = problem()
+    ndm = 2
+    ctx = pw().LongRangeJ(p, precision=prec, max_ndm=ndm)
+    other = pw().LongRangeJ(p, precision=prec, max_ndm=1)
+    dens = [np.stack([synth.make_density(p, 620 + 2 * r), synth.make_density(p, 621 + 2 * r)]) for r in range(4)]
+    Dbuf = dev(dens[0])
+    Jg = torch.empty_like(Dbuf)
+    Eg = torch.empty(ndm, dtype=torch.float64, device="cuda")
+    for r, D in enumerate(dens):
+        Dbuf.copy_(dev(D))
+        ctx.build_j(Dbuf, Jg, Eg, graph=True)
+        torch.cuda.synchronize()
+        Jr, Er = Jg.clone(), Eg.clone()
+        # eager work of the program between replays: another context and torch ops
+        Jo, _ = other.build_j(dev(D[0]))
+        (Jo.abs() * 2).sum().item()
+        # eager reference on the same context, separate output buffers
+        Je, Ee = ctx.build_j(dev(D))
+        torch.cuda.synchronize()
+        print(f"prec={prec} replay {r}: max|dJ|={float((Jr - Je).abs().max()):.1e}", flush=True)
+        assert torch.equal(Jr, Je), f"replay {r}: J differs from the eager call"
+        assert torch.equal(Er, Ee), f"replay {r}: E_J differs from the eager call"
+        assert torch.equal(Jo[0], Je[0])
+
+
+def test_graph_recaptures_on_new_buffers():
+    p = problem()
+    ctx = pw().LongRangeJ(p, max_ndm=1)
+    D = synth.make_density(p, 630)
+    Ja, Ea = ctx.build_j(dev(D), graph=True)
+    Jb, Eb = ctx.build_j(dev(D), graph=True)  # new buffers: captured again
+    Je, Ee = ctx.build_j(dev(D))
+    torch.cuda.synchronize()
+    assert torch.equal(Ja, Je) and torch.equal(Jb, Je) and torch.equal(Ea, Ee) and torch.equal(Eb, Ee)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32_mfma"])
+def test_autotune_parity_and_cache(prec, tmp_path):
+    p = problem()
+    D = synth.make_density(p, 640)
+    ref = O.build_j(p, D, want_J=True, want_rho=False)
+    ctx = pw().LongRangeJ(p, precision=prec, max_ndm=1)
+    J0, E0 = ctx.build_j(dev(D))
+    cache = str(tmp_path / "tune.txt")
+    ctx.autotune(1, cache)
+    seg = ctx.stats()["seg_len"]
+    J1, E1 = ctx.build_j(dev(D))
+    torch.cuda.synchronize()
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and int(lines[0].split()[1]) == int(seg)
+    e_tol, j_tol = (1e-10, 1e-11) if prec == 0 else (1e-6, 1e-6)
+    dE = abs(float(E1.cpu()[0]) - ref["E_G"])
+    dJ = float(np.max(np.abs(J1.cpu().numpy()[0] - ref["J"])))
+    print(f"prec={prec} seg={seg} dE={dE:.2e} dJ={dJ:.2e}", flush=True)
+    assert dE <= e_tol and dJ <= j_tol
+    if prec == 0:
+        assert float((J1 - J0).abs().max()) <= 1e-13
+    # a second context takes the cached shapes without timing
+    ctx2 = pw().LongRangeJ(p, precision=prec, max_ndm=1)
+    ctx2.autotune(1, cache)
+    assert ctx2.stats()["seg_len"] == seg
+    J2, E2 = ctx2.build_j(dev(D))
+    torch.cuda.synchronize()
+    assert torch.equal(J1, J2) and torch.equal(E1, E2)
+    assert len(open(cache).read().strip().splitlines()) == 1
+
+
+def test_autotune_full_diamond_cell():
+    """Diamond 8-atom cell, 4x4x4 mesh: tuned FP64 path vs untuned (summation order only)."""
+    p = synth.config_problem(2)
+    D = synth.make_density(p, 2000)
+    ctx = pw().LongRangeJ(p, max_ndm=1)
+    J0, E0 = ctx.build_j(dev(D))
+    ctx.autotune(1, None)
+    J1, E1 = ctx.build_j(dev(D))
+    Jg, Eg = ctx.build_j(dev(D), graph=True)
+    torch.cuda.synchronize()
+    dJ = float((J1 - J0).abs().max())
+    dE = abs(float(E1.cpu()[0]) - float(E0.cpu()[0]))
+    print(f"diamond tuned seg={ctx.stats()['seg_len']} dE={dE:.2e} dJ={dJ:.2e}", flush=True)
+    assert dE <= 1e-11 and dJ <= 1e-12
+    assert torch.equal(Jg, J1) and torch.equal(Eg, E1)
