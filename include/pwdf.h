@@ -112,7 +112,8 @@ typedef struct {
  *   nshell         number of shells; shell_atom/shell_l/shell_nprim host [nshell];
  *                  0 <= shell_l <= 3; shell_nprim >= 1.
  *   exps, coefs    host, sum(shell_nprim) primitives in shell order; exps > 0.
- *   kmesh[3]       host, each >= 1.
+ *   kmesh[3]       host, each >= 1, with (n1+n2+n3) lcm(n1,n2,n3) <= 1024
+ *                  (PWDF_EUNSUPPORTED otherwise: the phase table lives in LDS).
  *   omega          range-separation parameter > 0 (Bohr^-1).
  *   screen         host; eps_pair, eps_G in (0, 1).
  *   prec           PWDF_FP64 or PWDF_FP32_MFMA.
@@ -213,8 +214,9 @@ pwdf_status pwdf_autotune(pwdf_ctx *ctx, int ndm, const char *cache_path);
  * (creating events as needed, so keep it off under graph capture);
  * pwdf_profile_read synchronises on the recorded events and returns, per
  * kernel name, the launch count, the summed milliseconds and the summed work
- * units (pair-G evaluations for rho_L* / jpass_L*, complex multiply-adds for
- * phase_d, outputs for phase_j, primitive pairs for transform / back).
+ * units (pair-G evaluations for rho_L* / jpass_L*, D(k) values read for
+ * phase_d (elements on the pair support x Nk), J(k) values written for phase_j,
+ * primitive pairs for transform / back).
  * out may be NULL to query the count; *n receives the number of names. */
 typedef struct {
   char name[32];

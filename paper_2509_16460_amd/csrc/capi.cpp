@@ -213,6 +213,8 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   d.dhat_size = std::max<int64_t>(1, p.dhat_size);
   d.nsegJ = (int)p.sJ_code.size();
   d.nsegD = (int)p.sD_code.size();
+  for (int i = 0; i < 3; ++i) d.kmesh[i] = in.kmesh[i];
+  d.nheavyJ = (int)p.heavyJ.size();
   d.fp32 = c->prec == PWDF_FP32_MFMA ? 1 : 0;
   if (d.fp32) {
     d.ndmp = 1;
@@ -253,6 +255,7 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   UP(p.sJ_e0, sJ_e0)
   UP(p.eJ, eJ)
   UP(p.sD_el, sD_el)
+  UP(p.heavyJ, heavyJ)
   UP(p.sD_code, sD_code)
   UP(p.sD_e0, sD_e0)
   UP(p.eD, eD)
@@ -267,9 +270,6 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
     if ((e = upload(c, p.ptab, &ph)) != hipSuccess) return hip_fail(c, e, "uploading phase table");
     d.ptab = (const double2 *)ph;
     d.ptab_len = (int)(p.ptab.size() / 2);
-    const int *ent;
-    if ((e = upload(c, p.kvec, &ent)) != hipSuccess) return hip_fail(c, e, "uploading k table");
-    d.kvec = (const int4 *)ent;
   }
   const size_t M = (size_t)c->max_ndm;
 #define AL(field, count) \
@@ -427,7 +427,8 @@ pwdf_status run_to_rho(pwdf_ctx *c, int ndm, const double *Dk, double *EJ, hipSt
   const Plan &p = c->plan;
   const Dev &d = c->dev;
   pwdf_status s;
-  if ((s = step(c, "phase_d", (double)p.nelem * p.nk * ndm, st, [&] { return launch_phase_d(d, Dk, ndm, st); })) !=
+  if ((s = step(c, "phase_d", (double)p.nD_support * p.nk * ndm, st,
+                [&] { return launch_phase_d(d, Dk, ndm, st); })) !=
       PWDF_OK)
     return s;
   return run_mid_rho(c, ndm, EJ, st);
@@ -480,8 +481,21 @@ pwdf_status run_from_V(pwdf_ctx *c, int ndm, double *Jk, hipStream_t st) {
   if ((s = run_mid_j(c, ndm, st)) != PWDF_OK) return s;
   if ((s = step(c, "fold_j", (double)p.eJ.size() * ndm, st, [&] { return launch_fold_j(d, ndm, st); })) != PWDF_OK)
     return s;
-  return step(c, "phase_j", (double)p.nk * p.nbf * (double)p.nbf * ndm, st,
-              [&] { return launch_phase_j(d, ndm, Jk, st); });
+  // light and heavy elements write disjoint parts of J(k)
+  Fork f(c, st);
+  hipStream_t s1 = f.stream();
+  const double nh = (double)p.heavyJ.size();
+  if ((s = step(c, "phase_j", ((double)p.nbf * p.nbf - nh) * p.nk * ndm, s1,
+                [&] { return launch_phase_j(d, ndm, Jk, s1); })) != PWDF_OK)
+    return s;
+  if (nh > 0) {
+    hipStream_t s2 = f.stream();
+    if ((s = step(c, "phase_j_heavy", nh * p.nk * ndm, s2, [&] { return launch_phase_j_heavy(d, ndm, Jk, s2); })) !=
+        PWDF_OK)
+      return s;
+  }
+  if (hipError_t e = f.join()) return hip_fail(c, e, "join");
+  return PWDF_OK;
 }
 
 pwdf_status enqueue_build(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, double *EJ, hipStream_t st) {
@@ -596,10 +610,10 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
     delete c;
     return fail(nullptr, PWDF_EINVAL, why);
   }
-  // the phase kernels stage (n1+n2+n3) lcm(n) phases and the k-point list in LDS
-  if (c->plan.ptab.size() / 2 > 1024 || c->plan.nk > 512) {
+  // the phase kernels stage the (n1+n2+n3) lcm(n1,n2,n3) phases in LDS
+  if (c->plan.ptab.size() / 2 > 1024) {
     delete c;
-    return fail(nullptr, PWDF_EUNSUPPORTED, "k-mesh too large: need (n1+n2+n3)*lcm(n1,n2,n3) <= 1024 and Nk <= 512");
+    return fail(nullptr, PWDF_EUNSUPPORTED, "k-mesh too large: need (n1+n2+n3)*lcm(n1,n2,n3) <= 1024");
   }
   c->device = device;
   c->max_ndm = max_ndm;

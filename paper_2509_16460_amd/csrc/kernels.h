@@ -30,10 +30,12 @@ struct Dev {
   int nsegJ, nsegD;
   const int *sJ_off, *sJ_code, *sJ_e0, *eJ;
   const int *sD_el, *sD_code, *sD_e0, *eD;
+  const int *heavyJ;             // elements with more than kPhaseLight J classes
+  int nheavyJ;
   double *Jfold;                 // [ndm][nsegJ]
   const double2 *ptab;           // e^{2 pi i t / N}
-  const int4 *kvec;              // (k1, k2, k3, 0)
   int ptab_len;
+  int kmesh[3];                  // k-point k = (k1 n2 + k2) n3 + k3
   const double *ttab;
   int cls_b0[16], cls_b1[16];
   int L_p0[kMaxLsum + 1], L_p1[kMaxLsum + 1];
@@ -90,5 +92,6 @@ hipError_t launch_jpass_force_L(const Dev &d, int L, int ndm, hipStream_t st);
 hipError_t launch_force_back_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st);
 hipError_t launch_force_atoms(const Dev &d, int ndm, double *dEdR, hipStream_t st);
 hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, hipStream_t st);
+hipError_t launch_phase_j_heavy(const Dev &d, int ndm, double *Jk, hipStream_t st);
 
 }  // namespace pwdf

@@ -36,36 +36,61 @@ namespace pwdf {
 // multiple t of 1/N (N = lcm of the n_i).  An image enters only through its
 // Born-von Karman class c_i = (m_i mod n_i) N / n_i, so t = k1 c1 + k2 c2 + k3 c3
 // and the phase is ptab[t] = e^{2 pi i t / N} (t < (n1+n2+n3) N, no reduction).
+// Class codes pack (c1, c2, c3) as c1 | c2 << 10 | c3 << 20; k-points are
+// walked in the order k = (k1 n2 + k2) n3 + k3.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int phase_index(int4 kv, int code) {
-  return kv.x * (code & 1023) + kv.y * ((code >> 10) & 1023) + kv.z * (code >> 20);
-}
 
 // a1: D(k) -> D(L) on the unique blocks (real part: the Hermitian input makes
 // the imaginary part cancel between (a,b,L) and its mirror (b,a,-L)).  One thread
-// per (matrix element, BvK class) segment: D_c = Re sum_k w_k e^{ik.L} D(k)[mu][nu]
-// is the same for every image of the class and is written to each of them.
-__global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk, int nk, int nbf, int nsegD,
-                                                 const int *__restrict__ sD_el, const int *__restrict__ sD_code,
-                                                 const int *__restrict__ sD_e0, const int *__restrict__ eD,
-                                                 const double2 *__restrict__ ptab, const int4 *__restrict__ kvec,
-                                                 double wk, double *__restrict__ Dblk, int64_t nelem) {
+// per (matrix element, BvK class) segment, segments ordered by element so that
+// the lanes of a wave read neighbouring elements of D(k) (kU loads in flight);
+// D_c = Re sum_k w_k e^{ik.L} D(k)[mu][nu] is the same for every image of the
+// class and is written to each of them.
+constexpr int kU = 8;
+
+__device__ __forceinline__ void next_k(int &k1, int &k2, int &k3, int n2, int n3) {
+  if (++k3 == n3) {
+    k3 = 0;
+    if (++k2 == n2) {
+      k2 = 0;
+      ++k1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk, int nk, int nbf, int n2, int n3,
+                                                 int nsegD, const int *__restrict__ sD_el,
+                                                 const int *__restrict__ sD_code, const int *__restrict__ sD_e0,
+                                                 const int *__restrict__ eD, const double2 *__restrict__ ptab,
+                                                 int ptab_len, double wk, double *__restrict__ Dblk, int64_t nelem) {
+  __shared__ double2 sph[kPtabMax];
+  for (int i = threadIdx.x; i < ptab_len; i += blockDim.x) sph[i] = ptab[i];
+  __syncthreads();
   const int sg = blockIdx.x * blockDim.x + threadIdx.x;
   const int dm = blockIdx.y;
   if (sg >= nsegD) return;
+  const int64_t nn = (int64_t)nbf * nbf;
   const int code = sD_code[sg];
-  const size_t nn = (size_t)nbf * nbf;
+  const int c1 = code & 1023, c2 = (code >> 10) & 1023, c3 = code >> 20;
   const double2 *D = Dk + (size_t)dm * nk * nn + sD_el[sg];
   double acc = 0.0;
-  for (int k = 0; k < nk; ++k) {
-    const double2 w = ptab[phase_index(kvec[k], code)];
-    const double2 d = D[(size_t)k * nn];
-    acc = fma(w.x, d.x, acc);
-    acc = fma(-w.y, d.y, acc);
+  int k1 = 0, k2 = 0, k3 = 0;
+  for (int kb = 0; kb < nk; kb += kU) {
+    double2 d[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) d[u] = kb + u < nk ? D[(size_t)(kb + u) * nn] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (kb + u < nk) {
+        const double2 w = sph[k1 * c1 + k2 * c2 + k3 * c3];
+        acc = fma(w.x, d[u].x, fma(-w.y, d[u].y, acc));
+        next_k(k1, k2, k3, n2, n3);
+      }
+    }
   }
-  acc *= wk;
+  const double v = acc * wk;
   double *out = Dblk + (size_t)dm * nelem;
-  for (int i = sD_e0[sg]; i < sD_e0[sg + 1]; ++i) out[eD[i]] = acc;
+  for (int j = sD_e0[sg]; j < sD_e0[sg + 1]; ++j) out[eD[j]] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -514,9 +539,10 @@ __global__ __launch_bounds__(64) void k_backtransform(const BlockRec *__restrict
 // a7: J(L) -> J(k).  First the blocks of every matrix element are summed per
 // BvK class (k_fold_j, one thread per (element, class) segment, fixed order);
 // then J(k)_{mu nu} = sum over the element's classes of e^{2 pi i t/N} J_c
-// (k_phase_j, one thread per (k, mu, nu), at most Nk terms each).  Mirror
-// entries (b,a,-L) were given the class of -m and the transposed element.  Every
-// output is written (zeros off the support), coalesced over nu.
+// (k_phase_j, one thread per element, all k).  Mirror entries (b,a,-L) were
+// given the class of -m and the transposed element.  Every output is written
+// (zeros off the support); for each k the threads of a wave write consecutive
+// elements of one row of J(k).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_fold_j(const double *__restrict__ Jblk, int64_t nelem, int nsegJ,
                                                 const int *__restrict__ sJ_e0, const int *__restrict__ eJ,
@@ -530,59 +556,91 @@ __global__ __launch_bounds__(256) void k_fold_j(const double *__restrict__ Jblk,
   Jfold[(size_t)dm * nsegJ + sg] = s;
 }
 
-// One wave per matrix element, lanes = k-points (64 at a time): the element's
-// class segments are loaded once, one per lane, and broadcast lane by lane.  A
-// workgroup computes a tile of WAVES x EPW consecutive nu for one mu into LDS,
-// then writes each k-row of the tile as one contiguous run.
-template <int WAVES, int EPW>
-__global__ __launch_bounds__(64 * WAVES) void k_phase_j(const double *__restrict__ Jfold, int nsegJ,
-                                                        const int *__restrict__ sJ_off,
-                                                        const int *__restrict__ sJ_code,
-                                                        const double2 *__restrict__ ptab,
-                                                        const int4 *__restrict__ kvec, int nk, int nbf,
-                                                        double2 *__restrict__ Jk) {
-  constexpr int TW = WAVES * EPW;  // tile width in nu
-  __shared__ double2 tile[64 * TW];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int mu = blockIdx.y, dm = blockIdx.z;
-  const int nu_t = blockIdx.x * TW;
-  const int tw = min(TW, nbf - nu_t);
-  const size_t nn = (size_t)nbf * nbf;
+// Light elements (at most kPhaseLight classes, zeros included): one thread per
+// element, codes and values in registers; for each k the threads of a wave
+// write consecutive elements of one row of J(k).
+__global__ __launch_bounds__(256) void k_phase_j(const double *__restrict__ Jfold, int nsegJ,
+                                                 const int *__restrict__ sJ_off, const int *__restrict__ sJ_code,
+                                                 const double2 *__restrict__ ptab, int ptab_len, int nk, int n2,
+                                                 int n3, int nbf, double2 *__restrict__ Jk) {
+  __shared__ double2 sph[kPtabMax];
+  for (int i = threadIdx.x; i < ptab_len; i += blockDim.x) sph[i] = ptab[i];
+  __syncthreads();
+  const int64_t nn = (int64_t)nbf * nbf;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int dm = blockIdx.y;
+  if (e >= nn) return;
+  const int s0 = sJ_off[e];
+  const int n = sJ_off[e + 1] - s0;
+  if (n > kPhaseLight) return;
   const double *Jf = Jfold + (size_t)dm * nsegJ;
-  for (int kb = 0; kb < nk; kb += 64) {
-    const int kc = min(64, nk - kb);
-    const int k = kb + lane;
-    const int4 kv = kvec[k < nk ? k : nk - 1];
-    for (int e = 0; e < EPW; ++e) {
-      const int j = w * EPW + e;
-      if (j >= tw) break;
-      const size_t el = (size_t)mu * nbf + nu_t + j;
-      const int s0 = sJ_off[el], s1 = sJ_off[el + 1];
-      double re = 0.0, im = 0.0;
-      for (int b0 = s0; b0 < s1; b0 += 64) {
-        const int nb = min(64, s1 - b0);
-        int mycode = 0;
-        double myv = 0.0;
-        if (lane < nb) {
-          mycode = sJ_code[b0 + lane];
-          myv = Jf[b0 + lane];
-        }
-        for (int i = 0; i < nb; ++i) {
-          const int code = __shfl(mycode, i, 64);
-          const double v = __shfl(myv, i, 64);
-          const double2 ph = ptab[phase_index(kv, code)];
-          re = fma(ph.x, v, re);
-          im = fma(ph.y, v, im);
-        }
+  double2 *out = Jk + (size_t)dm * nk * nn + e;
+  int c1[kPhaseLight], c2[kPhaseLight], c3[kPhaseLight];
+  double v[kPhaseLight];
+#pragma unroll
+  for (int i = 0; i < kPhaseLight; ++i) {
+    const int code = i < n ? sJ_code[s0 + i] : 0;
+    c1[i] = code & 1023;
+    c2[i] = (code >> 10) & 1023;
+    c3[i] = code >> 20;
+    v[i] = i < n ? Jf[s0 + i] : 0.0;
+  }
+  int k1 = 0, k2 = 0, k3 = 0;
+  for (int k = 0; k < nk; ++k) {
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int i = 0; i < kPhaseLight; ++i) {
+      if (i < n) {
+        const double2 w = sph[k1 * c1[i] + k2 * c2[i] + k3 * c3[i]];
+        re = fma(w.x, v[i], re);
+        im = fma(w.y, v[i], im);
       }
-      tile[lane * TW + j] = make_double2(re, im);
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kc * TW; i += 64 * WAVES) {
-      const int kk = i / TW, j = i - kk * TW;
-      if (j < tw) Jk[((size_t)dm * nk + kb + kk) * nn + (size_t)mu * nbf + nu_t + j] = tile[kk * TW + j];
+    out[(size_t)k * nn] = make_double2(re, im);
+    next_k(k1, k2, k3, n2, n3);
+  }
+}
+
+// Heavy elements: one wave per element, lanes = k-points (64 at a time), the
+// element's classes loaded 64 at a time and broadcast lane by lane.
+__global__ __launch_bounds__(256) void k_phase_j_heavy(const double *__restrict__ Jfold, int nsegJ,
+                                                       const int *__restrict__ heavy, int nheavy,
+                                                       const int *__restrict__ sJ_off,
+                                                       const int *__restrict__ sJ_code,
+                                                       const double2 *__restrict__ ptab, int ptab_len, int nk,
+                                                       int n2, int n3, int nbf, double2 *__restrict__ Jk) {
+  __shared__ double2 sph[kPtabMax];
+  for (int i = threadIdx.x; i < ptab_len; i += blockDim.x) sph[i] = ptab[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int h = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int dm = blockIdx.y;
+  if (h >= nheavy) return;
+  const int64_t nn = (int64_t)nbf * nbf;
+  const int64_t e = heavy[h];
+  const int s0 = sJ_off[e], s1 = sJ_off[e + 1];
+  const double *Jf = Jfold + (size_t)dm * nsegJ;
+  double2 *out = Jk + (size_t)dm * nk * nn + e;
+  const int n23 = n2 * n3;
+  for (int kb = 0; kb < nk; kb += 64) {
+    const int k = kb + lane;
+    const int kk = k < nk ? k : 0;
+    const int k1 = kk / n23, r = kk - k1 * n23;
+    const int k2 = r / n3, k3 = r - k2 * n3;
+    double re = 0.0, im = 0.0;
+    for (int cb = s0; cb < s1; cb += 64) {
+      const int nb = min(64, s1 - cb);
+      const int mycode = lane < nb ? sJ_code[cb + lane] : 0;
+      const double myv = lane < nb ? Jf[cb + lane] : 0.0;
+      for (int i = 0; i < nb; ++i) {
+        const int code = __shfl(mycode, i, 64);
+        const double x = __shfl(myv, i, 64);
+        const double2 w = sph[k1 * (code & 1023) + k2 * ((code >> 10) & 1023) + k3 * (code >> 20)];
+        re = fma(w.x, x, re);
+        im = fma(w.y, x, im);
+      }
     }
-    __syncthreads();
+    if (k < nk) out[(size_t)k * nn] = make_double2(re, im);
   }
 }
 
@@ -597,9 +655,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_phase_j(const double *__restrict
 
 hipError_t launch_phase_d(const Dev &d, const double *Dk, int ndm, hipStream_t st) {
   if (d.nsegD <= 0) return hipSuccess;
+  if (d.ptab_len > kPtabMax) return hipErrorInvalidValue;
   dim3 grid((unsigned)((d.nsegD + 255) / 256), ndm);
-  hipLaunchKernelGGL(k_phase_d, grid, dim3(256), 0, st, (const double2 *)Dk, d.nk, d.nbf, d.nsegD, d.sD_el,
-                     d.sD_code, d.sD_e0, d.eD, d.ptab, d.kvec, 1.0 / d.nk, d.Dblk, d.nelem);
+  hipLaunchKernelGGL(k_phase_d, grid, dim3(256), 0, st, (const double2 *)Dk, d.nk, d.nbf, d.kmesh[1], d.kmesh[2],
+                     d.nsegD, d.sD_el, d.sD_code, d.sD_e0, d.eD, d.ptab, d.ptab_len, 1.0 / d.nk, d.Dblk, d.nelem);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -792,10 +851,21 @@ hipError_t launch_fold_j(const Dev &d, int ndm, hipStream_t st) {
 }
 
 hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, hipStream_t st) {
-  constexpr int WAVES = 4, EPW = 8;
-  dim3 grid((unsigned)((d.nbf + WAVES * EPW - 1) / (WAVES * EPW)), d.nbf, ndm);
-  hipLaunchKernelGGL((k_phase_j<WAVES, EPW>), grid, dim3(64 * WAVES), 0, st, d.Jfold, d.nsegJ, d.sJ_off, d.sJ_code,
-                     d.ptab, d.kvec, d.nk, d.nbf, (double2 *)Jk);
+  if (d.ptab_len > kPtabMax) return hipErrorInvalidValue;
+  const int64_t nn = (int64_t)d.nbf * d.nbf;
+  dim3 grid((unsigned)((nn + 255) / 256), ndm);
+  hipLaunchKernelGGL(k_phase_j, grid, dim3(256), 0, st, d.Jfold, d.nsegJ, d.sJ_off, d.sJ_code, d.ptab, d.ptab_len,
+                     d.nk, d.kmesh[1], d.kmesh[2], d.nbf, (double2 *)Jk);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+hipError_t launch_phase_j_heavy(const Dev &d, int ndm, double *Jk, hipStream_t st) {
+  if (d.nheavyJ <= 0) return hipSuccess;
+  if (d.ptab_len > kPtabMax) return hipErrorInvalidValue;
+  dim3 gh((unsigned)((d.nheavyJ + 3) / 4), ndm);
+  hipLaunchKernelGGL(k_phase_j_heavy, gh, dim3(256), 0, st, d.Jfold, d.nsegJ, d.heavyJ, d.nheavyJ, d.sJ_off, d.sJ_code,
+                     d.ptab, d.ptab_len, d.nk, d.kmesh[1], d.kmesh[2], d.nbf, (double2 *)Jk);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }

@@ -455,13 +455,6 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
       p.ptab[2 * t] = std::cos(2.0 * kPi * r / N);
       p.ptab[2 * t + 1] = std::sin(2.0 * kPi * r / N);
     }
-    p.kvec.resize(4 * (size_t)p.nk);
-    for (int k = 0; k < p.nk; ++k) {
-      p.kvec[4 * k + 2] = k % in.kmesh[2];
-      p.kvec[4 * k + 1] = (k / in.kmesh[2]) % in.kmesh[1];
-      p.kvec[4 * k + 0] = k / (in.kmesh[2] * in.kmesh[1]);
-      p.kvec[4 * k + 3] = 0;
-    }
     // class code of image m (sign s = +1) or of -m (s = -1)
     auto code_of = [&](const std::array<int, 3> &m, int s) {
       int c[3];
@@ -473,10 +466,12 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
     };
     const int nbf = p.nbf;
     p.sJ_off.assign((size_t)nbf * nbf + 1, 0);
+    p.nD_support = 0;
+    p.heavyJ.clear();
+    p.sD_el.clear();
     p.sJ_code.clear();
     p.sJ_e0.clear();
     p.eJ.clear();
-    p.sD_el.clear();
     p.sD_code.clear();
     p.sD_e0.clear();
     p.eD.clear();
@@ -515,6 +510,8 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
           }
           p.eD.push_back(dents[i].second);
         }
+        if (!dents.empty()) ++p.nD_support;
+        if ((int)p.sJ_code.size() - p.sJ_off[e] > kPhaseLight) p.heavyJ.push_back((int)e);
       }
     p.sJ_off[(size_t)nbf * nbf] = (int)p.sJ_code.size();
     p.sJ_e0.push_back((int)p.eJ.size());

@@ -65,10 +65,13 @@ struct Plan {
   std::vector<int> sJ_code, sJ_e0;  // per J segment: class code; first entry ([nsegJ + 1])
   std::vector<int> eJ;              // per J entry: element offset in Jblk
   std::vector<int> sD_el, sD_code, sD_e0;  // per D segment: element, class code, first entry
+  int64_t nD_support = 0;                  // elements with at least one D segment
+  // elements with more than kPhaseLight J classes, summed one wave per element
+  // (the others one thread per element)
+  std::vector<int> heavyJ;
   std::vector<int> eD;                      // per D entry: element offset in Dblk
   int phN = 1;                        // N
   std::vector<double> ptab;           // e^{2 pi i t / N}, t = 0 .. (n1+n2+n3) N - 1
-  std::vector<int> kvec;              // (k1, k2, k3, 0) per k-point
   // block-diagonal Hermite -> relative-monomial transform (degree blocks), and
   // the sign of (-i)^{|k|} folded into the rho coefficients / J moments
   std::vector<double> ttab;

@@ -29,6 +29,12 @@ __host__ __device__ constexpr int tblk_off(int d) {
 }
 constexpr int kTTableSize = tblk_off(kMaxLsum + 1);
 
+// Phase sums: matrix elements with at most kPhaseLight Born-von Karman classes
+// are summed by one thread with the classes in registers; heavier elements by
+// one wave.  The phase table e^{2 pi i t/N} lives in LDS (at most kPtabMax).
+constexpr int kPhaseLight = 8;
+constexpr int kPtabMax = 1024;
+
 // One segment of a G line: cnt <= SEG valid points n_u = nu0 .. nu0+cnt-1.
 struct SegDesc {
   int nu0, nv, nw, cnt;

@@ -52,6 +52,11 @@ def case(name):
         p = synth.small_problem(kind=name, seed=35, kmesh=(3, 1, 1), lmax=3, natm=3, lo=0.25, hi=40.0)
     elif name == "contracted_k212":
         p = contracted_problem()
+    elif name == "diffuse_k553":
+        # small dense cell with very diffuse shells: more than 64 BvK classes per
+        # matrix element and 75 k-points (wave-per-element phase sums, chunked)
+        lat = np.array([[3.1, 0.0, 0.0], [0.2, 3.3, 0.0], [-0.3, 0.4, 2.9]])
+        p = synth.small_problem(kind=name, seed=37, kmesh=(5, 5, 3), lattice=lat, lmax=1, natm=2, lo=0.02, hi=4.0)
     elif name == "cubic2_gamma":
         p = synth.config_problem(1)
     else:
@@ -61,7 +66,7 @@ def case(name):
 
 
 SMALL = ["s_only_gamma", "sp_k221", "spd_k123", "spdf_gamma", "spdf_k311_3atoms", "contracted_k212",
-         "cubic2_gamma"]
+         "diffuse_k553", "cubic2_gamma"]
 
 
 def run(prob, Dk, prec=0):
