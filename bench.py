@@ -1,22 +1,24 @@
 #!/usr/bin/env python
 """Long-range J benchmark on one MI355X.
 
-One step = one long-range J build (D(k) in HBM -> J(k) and E_J in HBM): phase sum
-D(k) -> D(L), per-pair transforms, rho(G), V(G) and E_J, J from V, back
-transform and J(L) -> J(k), for the 8-atom diamond-like cell with 10s6p3d
-uncontracted shells per atom on a 4x4x4 k-mesh (omega 0.4, screening 1e-12).
+One step = one long-range J build for one density (D(k) in HBM -> J(k) and E_J
+in HBM): phase sum D(k) -> D(L), per-pair transforms, rho(G), V(G) and E_J, J
+from V, back transform and J(L) -> J(k).  Workload: the 8-atom diamond-like
+cell (a = 6.74 Bohr) with 10s6p3d uncontracted shells per atom on a 4x4x4
+Gamma-centred k-mesh, omega 0.4, screening 1e-12, FP64.
 
-Prints one JSON line.  `value` is J builds/s from a region timed with
-torch.cuda.synchronize() on both sides; an equally long second region runs
-with per-launch HIP events (library profiling mode, events on the launch
-stream) and gives each kernel's average duration for the roofline entry.  The
-FP64 CPU oracle is timed on the host cores on the same workload as the
-baseline.
+`value` is J builds/s of the FP64 form, launched as the captured graph
+(pwdf_build_j_graph) after an untimed autotune, from a region timed with
+torch.cuda.synchronize() on both sides.  A second region of the same steps runs
+with per-launch HIP events (library profiling mode: events on the stream each
+kernel is launched on, launches serialised) and gives each kernel's average
+duration for the roofline entry.  The same line reports the FP32-MFMA form and
+16-density batches of both forms on the same workload, with their errors, and
+the FP64 CPU oracle timed on the host cores as the baseline.
 """
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -25,51 +27,56 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "long-range J builds/s + pair-G evals/s, FP32-MFMA vs FP64 at <=1e-7 Eh"
-PEAK = {"fp64_valu_tflops": 78.6, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
-KERNEL_SOURCES = ["paper_2509_16460_amd/csrc/kernels_fp64.hip"]
+PEAK = {"fp64_valu_tflops": 78.6, "hbm_gbs": 8000.0}
+CSRC = os.path.join(ROOT, "paper_2509_16460_amd", "csrc")
+WORKLOAD = "diamond8_10s6p3d_k444_w0.4"
 
 
 def kernel_source_hash():
+    """Hash of every kernel and launch source: counter data older than this is stale."""
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def flops_per_unit(name):
-    """Algorithmic flops per unique (pair, G, density) of one pass in the
-    factored form: an (L+1)-term complex multiply-add along the line plus the
-    separable exponential/phase product, 8(L+1) + 4."""
-    if name.startswith("rho_L") or name.startswith("jpass_L"):
-        L = int(name.split("_L")[1])
-        return 8 * (L + 1) + 4
+    """Algorithmic flops per unique (pair, G, density) of one pass in the factored
+    form: an (L+1)-term complex multiply-add along the line plus the separable
+    exponential/phase product, 8(L+1) + 4."""
+    for pre in ("rho_L", "jpass_L"):
+        if name.startswith(pre):
+            L = int(name[len(pre):])
+            return 8 * (L + 1) + 4
     return None
 
 
-def roofline_entry(name, rec, plan_stats, ndm, traffic):
+def bytes_per_unit(name):
+    """Algorithmic HBM bytes per work unit of the phase kernels: one complex128
+    value of J(k) written (phase_j, phase_j_heavy) or of D(k) read on the pair
+    support (phase_d)."""
+    return 16.0 if name in ("phase_j", "phase_j_heavy", "phase_d") else None
+
+
+def roofline_entry(name, rec, traffic):
     avg_s = rec["ms"] / rec["launches"] * 1e-3
-    per_launch_units = rec["units"] / rec["launches"]
-    fpu = flops_per_unit(name)
-    if fpu is not None:
-        achieved = per_launch_units * fpu / avg_s / 1e12
-        peak = PEAK["fp64_valu_tflops"]
-        return {"kernel": name, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": traffic, "avg_launch_us": avg_s * 1e6,
-                "units_per_launch": per_launch_units, "flops_per_unit": fpu}
-    if name == "phase_j":
-        nk, nbf = plan_stats["nk"], plan_stats["nbf"]
-        nbytes = per_launch_units * 16.0  # dense complex128 J(k) written
-    elif name == "phase_d":
-        nbytes = per_launch_units * 16.0  # complex128 D(k) read on the pair support
+    units = rec["units"] / rec["launches"]
+    fpu, bpu = flops_per_unit(name), bytes_per_unit(name)
+    ent = {"kernel": name, "avg_launch_us": avg_s * 1e6, "units_per_launch": units}
+    if bpu is not None:
+        ach = units * bpu / avg_s / 1e9
+        ent.update(bound="hbm", achieved=ach, peak=PEAK["hbm_gbs"], unit="GB/s", frac=ach / PEAK["hbm_gbs"],
+                   traffic=traffic, bytes_per_unit=bpu, algorithmic_bytes_per_launch=units * bpu)
+    elif fpu is not None:
+        ach = units * fpu / avg_s / 1e12
+        ent.update(bound="alu", achieved=ach, peak=PEAK["fp64_valu_tflops"], unit="TFLOP/s",
+                   frac=ach / PEAK["fp64_valu_tflops"], traffic=traffic, flops_per_unit=fpu)
     else:
-        nbytes = None
-    if nbytes is None:
-        return {"kernel": name, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
-                "traffic": traffic, "avg_launch_us": avg_s * 1e6}
-    achieved = nbytes / avg_s / 1e9
-    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-            "frac": achieved / PEAK["hbm_gbs"], "traffic": traffic, "avg_launch_us": avg_s * 1e6}
+        ent.update(bound="alu", achieved=None, peak=None, unit=None, frac=None, traffic=traffic)
+    return ent
 
 
 def load_traffic(kernel):
@@ -86,38 +93,49 @@ def load_traffic(kernel):
     if rec.get("source_hash") != kernel_source_hash():
         return None
     ent = rec.get("kernels", {}).get(kernel)
-    if not ent:
-        return None
-    return ent.get("hbm_bytes_per_launch")
+    return None if not ent else ent.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(prob, D, min_s=10.0, max_runs=8):
     from oracle import oracle as O
     cores = len(os.sched_getaffinity(0))
-    O.build_j(prob, D, want_rho=False, nthreads=cores)  # load + warm caches (untimed)
     runs, t0 = 0, time.perf_counter()
     ref = None
     while True:
-        ref = O.build_j(prob, D, want_rho=False, nthreads=cores)
+        r = O.build_j(prob, D, want_rho=False, nthreads=cores)
+        ref = ref or r
         runs += 1
         el = time.perf_counter() - t0
         if el >= min_s or runs >= max_runs:
             break
     return ({"value": runs / el, "unit": "J builds/s", "cores": cores, "kind": "oracle",
-             "sample": f"{runs} full FP64 oracle J builds of the same workload ({el:.1f} s)"}, ref)
+             "sample": f"{runs} full FP64 oracle J builds of the same workload, one density ({el:.1f} s)"}, ref)
+
+
+def timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP32-MFMA and batched measurements")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not supported"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; runs on several GPUs are not "
+                                   "supported (the long-range J build of one cell runs on one device)"}))
         sys.exit(2)
 
     import numpy as np
@@ -128,6 +146,7 @@ def main():
     prob = synth.config_problem(2)
     D = synth.make_density(prob, 2000)
     ctx = pwdf.LongRangeJ(prob, precision=pwdf.PWDF_FP64, max_ndm=1)
+    ctx.autotune(1, None)
     st = ctx.stats()
     Dt = torch.from_numpy(D[None]).cuda()
     Jk = torch.empty_like(Dt)
@@ -141,30 +160,26 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    for _ in range(args.warmup):
-        ctx.build_j(Dt, Jk, EJ)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.build_j(Dt, Jk, EJ)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) / args.steps * 1e3
+    # timed region: graph replay of the whole build
+    ms = timed(torch, lambda: ctx.build_j(Dt, Jk, EJ, graph=True), args.steps, args.warmup)
+    ms_eager = timed(torch, lambda: ctx.build_j(Dt, Jk, EJ), args.steps, 1)
+    J64 = Jk.clone()
+    E64 = float(EJ.cpu()[0])
 
-    # second region: same steps with per-launch HIP events on the launch stream
+    # profiled region: per-launch events, launches serialised on one stream
     ctx.profile_enable(True)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
     for _ in range(args.steps):
         ctx.build_j(Dt, Jk, EJ)
     torch.cuda.synchronize()
-    t3 = time.perf_counter()
     prof = ctx.profile_read()
     ctx.profile_enable(False)
-    dominant = max(prof, key=lambda k: prof[k]["ms"])
-    roof = roofline_entry(dominant, prof[dominant], st, 1, load_traffic(dominant))
-    kernels = {k: {"launches": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3,
-                   "share": v["ms"] / sum(x["ms"] for x in prof.values())} for k, v in prof.items()}
+    dominant = max(prof, key=lambda k: prof[k]["ms"] / prof[k]["launches"])
+    roof = roofline_entry(dominant, prof[dominant], load_traffic(dominant))
+    tot = sum(x["ms"] for x in prof.values())
+    kernels = {k: {"launches": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3, "share": v["ms"] / tot}
+               for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+    second = [roofline_entry(k, prof[k], load_traffic(k)) for k in kernels
+              if k != dominant and (flops_per_unit(k) or bytes_per_unit(k))][:4]
 
     builds_per_s = 1e3 / ms
     pairG = st["pairG_evals"]
@@ -181,22 +196,59 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "diamond8_k444_fp64", "atoms": prob.natm, "nbf": prob.nbf, "nk": prob.nk,
+        "config": {"workload": WORKLOAD, "atoms": prob.natm, "nbf": prob.nbf, "nk": prob.nk,
                    "omega": prob.omega, "nG": st["nG"], "unique_pairs": st["npairs"], "ndm": 1,
-                   "precision": "fp64"},
+                   "precision": "fp64", "launch": "graph replay, autotuned", "seg_len": st["seg_len"]},
         "pair_G_evals_per_s": pairG * builds_per_s,
         "pair_G_evals_per_build": pairG,
-        "ms_per_step_profiled": (t3 - t2) / args.steps * 1e3,
+        "ms_per_step_eager": ms_eager,
         "roofline": roof,
+        "roofline_next": second,
         "kernels": kernels,
-        "E_J": float(EJ.cpu()[0]),
+        "E_J": E64,
     }
+
+    if not args.no_extras:
+        # FP32-MFMA form, one density
+        c32 = pwdf.LongRangeJ(prob, precision=pwdf.PWDF_FP32_MFMA, max_ndm=1)
+        c32.autotune(1, None)
+        J32 = torch.empty_like(Dt)
+        E32 = torch.empty(1, dtype=torch.float64, device="cuda")
+        ms32 = timed(torch, lambda: c32.build_j(Dt, J32, E32, graph=True), args.steps, args.warmup)
+        fp32 = {"builds_per_s": 1e3 / ms32, "ms_per_build": ms32, "speedup_vs_fp64": ms / ms32,
+                "E_J": float(E32.cpu()[0]), "seg_len": c32.stats()["seg_len"]}
+        del c32
+        # 16-density batches (distinct densities), per-density throughput
+        ndm = 16
+        Db = torch.from_numpy(synth.make_densities(prob, ndm)).cuda()
+        Jb = torch.empty_like(Db)
+        Eb = torch.empty(ndm, dtype=torch.float64, device="cuda")
+        batched = {}
+        res = {}
+        for name, prec in (("fp64", pwdf.PWDF_FP64), ("fp32_mfma", pwdf.PWDF_FP32_MFMA)):
+            cb = pwdf.LongRangeJ(prob, precision=prec, max_ndm=ndm)
+            cb.autotune(ndm, None)
+            msb = timed(torch, lambda: cb.build_j(Db, Jb, Eb, graph=True), max(5, args.steps // 5), 2)
+            res[name] = (Jb.clone(), Eb.clone())
+            batched[name] = {"ndm": ndm, "ms_per_batch": msb, "density_builds_per_s": ndm * 1e3 / msb,
+                             "speedup_vs_fp64_single": ndm * ms / msb}
+            del cb
+        dJb = float((res["fp32_mfma"][0] - res["fp64"][0]).abs().max())
+        dEb = float((res["fp32_mfma"][1] - res["fp64"][1]).abs().max())
+        batched["fp32_mfma"]["max_abs_dJ_vs_fp64_gpu"] = dJb
+        batched["fp32_mfma"]["max_abs_dE_vs_fp64_gpu"] = dEb
+        out["fp32_mfma"] = fp32
+        out["batched"] = batched
+        del Db, Jb, Eb, res
+
     if not args.no_cpu_baseline:
         base, ref = cpu_baseline(prob, D)
         out["cpu_baseline"] = base
-        Jh = Jk.cpu().numpy()[0]
-        out["parity_vs_oracle"] = {"dE_J": abs(out["E_J"] - ref["E_G"]),
-                                   "max_abs_dJ": float(np.max(np.abs(Jh - ref["J"])))}
+        out["parity_vs_oracle"] = {"dE_J": abs(E64 - ref["E_G"]),
+                                   "max_abs_dJ": float(np.max(np.abs(J64.cpu().numpy()[0] - ref["J"])))}
+        if "fp32_mfma" in out:
+            out["fp32_mfma"]["dE_J_vs_oracle"] = abs(out["fp32_mfma"]["E_J"] - ref["E_G"])
+            out["fp32_mfma"]["max_abs_dJ_vs_oracle"] = float(np.max(np.abs(J32.cpu().numpy()[0] - ref["J"])))
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))

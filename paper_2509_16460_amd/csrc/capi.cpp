@@ -123,17 +123,26 @@ void drop_graph(pwdf_ctx *c) {
   c->gc = GraphCache();
 }
 
-// Launch shapes: spread each pass over about 4096 waves in proportion to the
-// class's pair-G work, scaled per class by the tune multipliers.
+// Launch shapes: spread each pass over about 4096 waves so that every wave of
+// every class does about the same work (the classes of one pass run
+// concurrently).  rho: lane = segment, a class is split into pair chunks.
+// J: lane = pair, a class is split into segment chunks; a wave costs the same
+// whether or not all 64 pairs are present, so the J weights count padded lanes.
+// Per pair and point the cost is about 2L + 10 operations plus the segment start
+// (two exponentials, one sincos, the NT coefficients) spread over SEG points.
+// The tune multipliers scale the chunk counts per class.
 void choose_shapes(const Plan &p, Dev &d, const Tune &tn) {
   const int SEG = p.seg_len;
   const double target = 4096.0;
   d.rho_bs = 256;  // 64 segments x 4 waves sharing them
-  double wsum = 0.0, wL[kMaxLsum + 1];
+  double wsumR = 0.0, wsumJ = 0.0, wR[kMaxLsum + 1], wJ[kMaxLsum + 1];
   for (int L = 0; L <= kMaxLsum; ++L) {
-    int np = p.L_p1[L] - p.L_p0[L];
-    wL[L] = np > 0 ? (double)np * (2.0 * L + 10.0 + (70.0 + nherm(L)) / SEG) : 0.0;
-    wsum += wL[L];
+    const int np = p.L_p1[L] - p.L_p0[L];
+    const double cost = 2.0 * L + 10.0 + (70.0 + nherm(L)) / SEG;
+    wR[L] = np > 0 ? (double)np * cost : 0.0;
+    wJ[L] = np > 0 ? (double)((np + 63) / 64) * 64.0 * cost : 0.0;
+    wsumR += wR[L];
+    wsumJ += wJ[L];
   }
   const int rho_waves_per_chunk = ((p.nseg() + 63) / 64) * 4;
   int rows = 0;
@@ -149,16 +158,15 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn) {
       d.j_spc[L] = 1;
       continue;
     }
-    double share = wL[L] / wsum;
-    int ch = (int)std::lround(target * share * tn.mrho[L] / rho_waves_per_chunk);
+    int ch = (int)std::lround(target * (wR[L] / wsumR) * tn.mrho[L] / rho_waves_per_chunk);
     ch = std::max(1, std::min(np, ch));
     int ppc = (np + ch - 1) / ch;
     ch = (np + ppc - 1) / ppc;
     d.rho_chunks[L] = ch;
     d.rho_ppc[L] = ppc;
     rows += ch;
-    int jw = ((np + 255) / 256) * 4;
-    int jc = (int)std::lround(target * share * tn.mj[L] / jw);
+    const int jw = (np + 63) / 64;  // active waves per segment chunk
+    int jc = (int)std::lround(target * (wJ[L] / wsumJ) * tn.mj[L] / jw);
     jc = std::max(1, std::min(p.nseg(), jc));
     int spc = (p.nseg() + jc - 1) / jc;
     jc = (p.nseg() + spc - 1) / spc;
@@ -876,6 +884,29 @@ static pwdf_status time_tunable(pwdf_ctx *c, int ndm, int reps, std::vector<std:
   return PWDF_OK;
 }
 
+// Wall time per repetition of the tunable part with the per-class launches
+// running concurrently (as in pwdf_build_j), events on the tuning stream.
+static pwdf_status time_total(pwdf_ctx *c, int ndm, int reps, double &ms_out) {
+  pwdf_status s;
+  hipError_t e;
+  if ((e = hipMemsetAsync(c->dev.Dblk, 0, sizeof(double) * (size_t)ndm * c->plan.nelem, c->cap)) != hipSuccess)
+    return hip_fail(c, e, "tune clear");
+  hipEvent_t a = prof_event(c), b = prof_event(c);
+  if (!a || !b) return fail(c, PWDF_EDEVICE, "tune events");
+  for (int r = -1; r < reps; ++r) {  // r = -1: warm-up
+    if (r == 0 && (e = hipEventRecord(a, c->cap)) != hipSuccess) return hip_fail(c, e, "tune events");
+    if ((s = run_mid_rho(c, ndm, c->Escr, c->cap)) != PWDF_OK) return s;
+    if ((s = run_mid_j(c, ndm, c->cap)) != PWDF_OK) return s;
+  }
+  if ((e = hipEventRecord(b, c->cap)) != hipSuccess || (e = hipEventSynchronize(b)) != hipSuccess)
+    return hip_fail(c, e, "tune events");
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  c->prof_next = 0;
+  ms_out = ms / reps;
+  return PWDF_OK;
+}
+
 static double kernel_ms(const std::vector<std::pair<std::string, double>> &v, const std::string &name) {
   for (auto &kv : v)
     if (kv.first == name) return kv.second;
@@ -897,23 +928,24 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
     return setup_device(c, best);
   }
   const bool was_prof = c->prof_on;
-  // 1. segment length
+  c->prof_on = false;
+  // 1. segment length, by the concurrent wall time of the tunable part
   std::vector<int> segs = c->prec == PWDF_FP32_MFMA ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 16};
   double best_t = 1e300;
-  std::vector<std::pair<std::string, double>> per;
   for (int sl : segs) {
     build_segments(c->plan, sl);
     Tune t;
     t.seg_len = sl;
     if ((s = setup_device(c, t)) != PWDF_OK) return s;
-    double tot = 0.0;
-    if ((s = time_tunable(c, ndm, 3, per, tot)) != PWDF_OK) return s;
-    if (tot < best_t) {
-      best_t = tot;
+    double ms = 0.0;
+    if ((s = time_total(c, ndm, 5, ms)) != PWDF_OK) return s;
+    if (ms < best_t) {
+      best_t = ms;
       best = t;
     }
   }
-  // 2. per-class chunk multipliers at the chosen segment length
+  // 2. per-class chunk multipliers at that segment length: each class keeps the
+  // multiplier with its shortest kernel (timed one launch at a time)
   build_segments(c->plan, best.seg_len);
   const double mults[] = {0.25, 0.5, 1.0, 2.0, 4.0};
   double brho[kMaxLsum + 1], bj[kMaxLsum + 1];
@@ -921,6 +953,7 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
   const char *rn = c->prec == PWDF_FP32_MFMA ? "rho_mfma_L%d" : "rho_L%d";
   const char *jn = c->prec == PWDF_FP32_MFMA ? "jpass_mfma_L%d" : "jpass_L%d";
   Tune cand = best;
+  std::vector<std::pair<std::string, double>> per;
   for (double m : mults) {
     Tune t = best;
     for (int L = 0; L <= kMaxLsum; ++L) t.mrho[L] = t.mj[L] = m;
@@ -944,8 +977,15 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
       }
     }
   }
-  c->prof_on = was_prof;
+  // 3. keep the per-class choice only if it also wins when the classes overlap
   if ((s = setup_device(c, cand)) != PWDF_OK) return s;
+  double t_cand = 0.0;
+  if ((s = time_total(c, ndm, 5, t_cand)) != PWDF_OK) return s;
+  if (t_cand > best_t) {
+    cand = best;
+    if ((s = setup_device(c, cand)) != PWDF_OK) return s;
+  }
+  c->prof_on = was_prof;
   save_tune(cache_path, key, cand);
   return PWDF_OK;
 }

@@ -536,6 +536,200 @@ __global__ __launch_bounds__(64) void k_backtransform(const BlockRec *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// a2 / a6 for high angular classes: one wave per block.  The thread-per-block
+// kernels above keep the three E tables, the Hermite vector and the Cartesian
+// block of one pair in registers; for L = la + lb >= 4 that is several hundred
+// doubles per lane and the few pairs of such classes end up as one long serial
+// chain.  Here lanes 0..2 build the E table of one axis each into LDS and the
+// wave then works lane-parallel over Hermite indices t, monomials k or
+// Cartesian elements (ia, ib).
+// ---------------------------------------------------------------------------
+template <int LA, int LB>
+struct WaveTabs {
+  static constexpr int L = LA + LB;
+  static constexpr int NT = nherm(L);
+  static constexpr int NCA = ncart(LA), NCB = ncart(LB);
+  static constexpr int NE = (LA + 1) * (LB + 1) * (L + 1);  // one axis: E[i][j][t]
+  static constexpr int eidx(int i, int j, int t) { return (i * (LB + 1) + j) * (L + 1) + t; }
+};
+
+// (tx, ty, tz) of Hermite index t in the degree-ordered list (runtime inverse).
+__device__ __forceinline__ void herm_of(int t, int &tx, int &ty, int &tz) {
+  int d = 0;
+  while (deg_off(d + 1) <= t) ++d;
+  int r = t - deg_off(d);
+  int a = d;
+  while (r > d - a) {
+    r -= d - a + 1;
+    --a;
+  }
+  tx = a;
+  ty = d - a - r;
+  tz = d - tx - ty;
+}
+
+// Cartesian component ic of shell l (descending lexicographic), runtime.
+__device__ __forceinline__ void cart_of(int l, int ic, int &x, int &y, int &z) {
+  int a = l, r = ic;
+  while (r > l - a) {
+    r -= l - a + 1;
+    --a;
+  }
+  x = a;
+  y = l - a - r;
+  z = l - x - y;
+}
+
+template <int LA, int LB>
+__device__ __forceinline__ void wave_etabs(const PairAux &x, double *sE) {
+  using W = WaveTabs<LA, LB>;
+  const int lane = threadIdx.x;
+  if (lane < 3) {
+    const double xa = lane == 0 ? x.xpa[0] : (lane == 1 ? x.xpa[1] : x.xpa[2]);
+    const double xb = lane == 0 ? x.xpb[0] : (lane == 1 ? x.xpb[1] : x.xpb[2]);
+    double E[LA + 1][LB + 1][W::L + 1];
+    md_axis<LA, LB>(0.5 / x.p, xa, xb, E);
+#pragma unroll
+    for (int i = 0; i <= LA; ++i)
+#pragma unroll
+      for (int j = 0; j <= LB; ++j)
+#pragma unroll
+        for (int t = 0; t <= W::L; ++t) sE[lane * W::NE + W::eidx(i, j, t)] = E[i][j][t];
+  }
+}
+
+template <int LA, int LB>
+__global__ __launch_bounds__(64) void k_transform_w(const BlockRec *__restrict__ blocks, int b0,
+                                                    const PairAux *__restrict__ aux,
+                                                    const double *__restrict__ Dblk, int64_t nelem,
+                                                    const double *__restrict__ ttab, double *__restrict__ dhat,
+                                                    int64_t dhat_size, int64_t cls_off, int Lp0,
+                                                    float *__restrict__ dh32, int64_t d32_off, int ncols, int ndmp) {
+  using W = WaveTabs<LA, LB>;
+  constexpr int L = W::L, NT = W::NT, NCA = W::NCA, NCB = W::NCB, NE = W::NE;
+  constexpr Carts<LA> CA{};
+  constexpr Carts<LB> CB{};
+  __shared__ double sE[3 * NE];
+  __shared__ double sD[NCA * NCB];
+  __shared__ double sH[NT];
+  const int lane = threadIdx.x;
+  const BlockRec b = blocks[b0 + blockIdx.x];
+  const int dm = blockIdx.y;
+  for (int e = lane; e < NCA * NCB; e += 64) sD[e] = Dblk[(size_t)dm * nelem + b.eoff + e];
+  double *out_base = dhat + (size_t)dm * dhat_size + cls_off;
+  for (int q = b.p0; q < b.p1; ++q) {
+    const PairAux x = aux[q];
+    __syncthreads();
+    wave_etabs<LA, LB>(x, sE);
+    __syncthreads();
+    for (int t = lane; t < NT; t += 64) {
+      int tx, ty, tz;
+      herm_of(t, tx, ty, tz);
+      double s = 0.0;
+#pragma unroll
+      for (int ia = 0; ia < NCA; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < NCB; ++ib) {
+          const double ex = sE[W::eidx(CA.x[ia], CB.x[ib], 0) + tx];
+          const double ey = sE[NE + W::eidx(CA.y[ia], CB.y[ib], 0) + ty];
+          const double ez = sE[2 * NE + W::eidx(CA.z[ia], CB.z[ib], 0) + tz];
+          s = fma(sD[ia * NCB + ib] * ex, ey * ez, s);
+        }
+      sH[t] = s * x.pref_rho;
+    }
+    __syncthreads();
+    double *out = out_base + (size_t)(q - Lp0) * NT;
+    for (int k = lane; k < NT; k += 64) {
+      int d = 0;
+      while (deg_off(d + 1) <= k) ++d;
+      const int nc = ncart(d), r = k - deg_off(d);
+      const double *T = ttab + tblk_off(d);
+      const double sg = ((d & 3) == 1 || (d & 3) == 2) ? -1.0 : 1.0;
+      double s = 0.0;
+      for (int t = 0; t < nc; ++t) s = fma(T[t * nc + r], sH[deg_off(d) + t], s);
+      out[k] = sg * s;
+      if (dh32) dh32[d32_off + (size_t)(q - Lp0) * ncols + k * ndmp + dm] = (float)(sg * s);
+    }
+  }
+}
+
+template <int LA, int LB>
+__global__ __launch_bounds__(64) void k_back_w(const BlockRec *__restrict__ blocks, int b0,
+                                               const PairAux *__restrict__ aux, const double *__restrict__ ttab,
+                                               const double *__restrict__ yhat, int64_t yhat_size, int64_t ycls_off,
+                                               int nchunks, int Lp0, int Lp1, double *__restrict__ Jblk,
+                                               int64_t nelem) {
+  using W = WaveTabs<LA, LB>;
+  constexpr int L = W::L, NT = W::NT, NCA = W::NCA, NCB = W::NCB, NE = W::NE;
+  constexpr int NEL = NCA * NCB;
+  constexpr int ROUNDS = (NEL + 63) / 64;
+  __shared__ double sE[3 * NE];
+  __shared__ double sY[NT];
+  __shared__ double sJ[NT];
+  __shared__ int sIdx[(L + 1) * (L + 1) * (L + 1)];
+  const int lane = threadIdx.x;
+  const BlockRec b = blocks[b0 + blockIdx.x];
+  const int dm = blockIdx.y;
+  const int np = Lp1 - Lp0;
+  for (int t = lane; t < NT; t += 64) {
+    int tx, ty, tz;
+    herm_of(t, tx, ty, tz);
+    sIdx[(tx * (L + 1) + ty) * (L + 1) + tz] = t;
+  }
+  double acc[ROUNDS];
+  int ax[ROUNDS], ay[ROUNDS], az[ROUNDS], bx[ROUNDS], by[ROUNDS], bz[ROUNDS];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    acc[r] = 0.0;
+    const int e = min(lane + 64 * r, NEL - 1);
+    cart_of(LA, e / NCB, ax[r], ay[r], az[r]);
+    cart_of(LB, e % NCB, bx[r], by[r], bz[r]);
+  }
+  for (int q = b.p0; q < b.p1; ++q) {
+    const PairAux x = aux[q];
+    __syncthreads();
+    const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (q - Lp0);
+    for (int k = lane; k < NT; k += 64) {
+      double s = 0.0;
+      for (int c = 0; c < nchunks; ++c) s += ys[((size_t)c * NT + k) * np];
+      sY[k] = s;
+    }
+    wave_etabs<LA, LB>(x, sE);
+    __syncthreads();
+    for (int t = lane; t < NT; t += 64) {
+      int d = 0;
+      while (deg_off(d + 1) <= t) ++d;
+      const int nc = ncart(d), r = t - deg_off(d);
+      const double *T = ttab + tblk_off(d);
+      const double sg = ((d & 3) >= 2) ? -1.0 : 1.0;
+      double s = 0.0;
+      for (int k = 0; k < nc; ++k) s = fma(T[r * nc + k], sY[deg_off(d) + k], s);
+      sJ[t] = sg * s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+      if (lane + 64 * r < NEL) {
+        double s = 0.0;
+        for (int tx = 0; tx <= ax[r] + bx[r]; ++tx) {
+          const double ex = sE[W::eidx(ax[r], bx[r], tx)];
+          for (int ty = 0; ty <= ay[r] + by[r]; ++ty) {
+            const double exy = ex * sE[NE + W::eidx(ay[r], by[r], ty)];
+            for (int tz = 0; tz <= az[r] + bz[r]; ++tz)
+              s = fma(exy * sE[2 * NE + W::eidx(az[r], bz[r], tz)], sJ[sIdx[(tx * (L + 1) + ty) * (L + 1) + tz]], s);
+          }
+        }
+        acc[r] = fma(x.pref_j, s, acc[r]);
+      }
+    }
+  }
+  double *out = Jblk + (size_t)dm * nelem + b.eoff;
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r)
+    if (lane + 64 * r < NEL) out[lane + 64 * r] = acc[r];
+}
+
+// ---------------------------------------------------------------------------
 // a7: J(L) -> J(k).  First the blocks of every matrix element are summed per
 // BvK class (k_fold_j, one thread per (element, class) segment, fixed order);
 // then J(k)_{mu nu} = sum over the element's classes of e^{2 pi i t/N} J_c
@@ -663,11 +857,23 @@ hipError_t launch_phase_d(const Dev &d, const double *Dk, int ndm, hipStream_t s
   return hipSuccess;
 }
 
+// Wave-per-block kernels for the heavy classes: L >= 4 always, L = 3 while the
+// class is small enough that one thread per block leaves most of the chip idle.
+static bool wave_per_block(int L, int nblocks) { return L >= 4 || (L == 3 && nblocks < 16384); }
+
 template <int LA, int LB>
 static hipError_t transform_one(const Dev &d, int ndm, hipStream_t st) {
   const int c = LA * 4 + LB;
   const int b0 = d.cls_b0[c], b1 = d.cls_b1[c];
   if (b1 <= b0) return hipSuccess;
+  if (wave_per_block(LA + LB, b1 - b0)) {
+    dim3 grid((unsigned)(b1 - b0), ndm);
+    hipLaunchKernelGGL((k_transform_w<LA, LB>), grid, dim3(64), 0, st, d.blocks, b0, d.aux, d.Dblk, d.nelem, d.ttab,
+                       d.dhat, d.dhat_size, d.dhat_off[LA + LB], d.L_p0[LA + LB], d.dh32, d.d32_off[LA + LB],
+                       d.ncols32[LA + LB], d.ndmp);
+    PWDF_CHECK_LAUNCH();
+    return hipSuccess;
+  }
   dim3 grid((unsigned)((b1 - b0 + 63) / 64), ndm);
   hipLaunchKernelGGL((k_transform<LA, LB>), grid, dim3(64), 0, st, d.blocks, b0, b1, d.aux, d.Dblk, d.nelem,
                      d.ttab, d.dhat, d.dhat_size, d.dhat_off[LA + LB], d.L_p0[LA + LB], d.dh32,
@@ -818,6 +1024,13 @@ static hipError_t back_one(const Dev &d, int ndm, hipStream_t st) {
   const int b0 = d.cls_b0[c], b1 = d.cls_b1[c];
   if (b1 <= b0) return hipSuccess;
   constexpr int L = LA + LB;
+  if (wave_per_block(L, b1 - b0)) {
+    dim3 grid((unsigned)(b1 - b0), ndm);
+    hipLaunchKernelGGL((k_back_w<LA, LB>), grid, dim3(64), 0, st, d.blocks, b0, d.aux, d.ttab, d.yhat, d.yhat_size,
+                       d.yhat_off[L], d.j_chunks[L], d.L_p0[L], d.L_p1[L], d.Jblk, d.nelem);
+    PWDF_CHECK_LAUNCH();
+    return hipSuccess;
+  }
   dim3 grid((unsigned)((b1 - b0 + 63) / 64), ndm);
   hipLaunchKernelGGL((k_backtransform<LA, LB>), grid, dim3(64), 0, st, d.blocks, b0, b1, d.aux, d.ttab, d.yhat,
                      d.yhat_size, d.yhat_off[L], d.j_chunks[L], d.L_p0[L], d.L_p1[L], d.Jblk, d.nelem);
