@@ -44,10 +44,15 @@ def kernel_source_hash():
 
 
 def flops_per_unit(name):
-    """Algorithmic flops per unique (pair, G, density) of one pass in the factored
-    form: an (L+1)-term complex multiply-add along the line plus the separable
-    exponential/phase product, 8(L+1) + 4."""
-    for pre in ("rho_L", "jpass_L"):
+    """Algorithmic flops per work unit of the pair-G kernels.  The FP64 pair-G
+    launches (rho_lo/hi, jpass_lo/hi) count their units in flops already: 8(L+1)+4
+    per unique (pair, G of the half space, density) of class L in the factored
+    form (an (L+1)-term complex multiply-add along the line plus the separable
+    exponential/phase product).  The per-class FP32 launches count pair-G
+    evaluations."""
+    if name in ("rho_lo", "rho_hi", "jpass_lo", "jpass_hi"):
+        return 1.0
+    for pre in ("rho_mfma_L", "jpass_mfma_L"):
         if name.startswith(pre):
             L = int(name[len(pre):])
             return 8 * (L + 1) + 4

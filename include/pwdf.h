@@ -214,7 +214,9 @@ pwdf_status pwdf_autotune(pwdf_ctx *ctx, int ndm, const char *cache_path);
  * (creating events as needed, so keep it off under graph capture);
  * pwdf_profile_read synchronises on the recorded events and returns, per
  * kernel name, the launch count, the summed milliseconds and the summed work
- * units (pair-G evaluations for rho_L* / jpass_L*, D(k) values read for
+ * units (algorithmic flops for the FP64 pair-G launches rho_lo/hi and
+ * jpass_lo/hi, 8(L+1)+4 per unique pair, G of the half space and density;
+ * pair-G evaluations for the FP32 launches rho_mfma_L* / jpass_mfma_L*; D(k) values read for
  * phase_d (elements on the pair support x Nk), J(k) values written for phase_j,
  * primitive pairs for transform / back).
  * out may be NULL to query the count; *n receives the number of names. */

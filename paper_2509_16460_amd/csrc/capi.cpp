@@ -390,6 +390,16 @@ struct Fork {
 
 int np_L(const Plan &p, int L) { return p.L_p1[L] - p.L_p0[L]; }
 
+// Algorithmic flops of one pair-G pass over the classes L in [L0, L1]: 8(L+1)+4
+// per (unique pair, G of the half space, density) in the factored form.
+double pass_flops(const Plan &p, int L0, int L1, int ndm) {
+  double f = 0.0;
+  for (int L = L0; L <= L1; ++L) f += (double)np_L(p, L) * (double)(p.nG_full / 2) * (8.0 * (L + 1) + 4.0);
+  return f * ndm;
+}
+
+double total_pairs(const Plan &p) { return (double)p.npairs(); }
+
 double cls_pairs(const Plan &p, int cl) {
   return (double)(p.blocks[p.cls_b1[cl] - 1].p1 - p.blocks[p.cls_b0[cl]].p0);
 }
@@ -401,29 +411,27 @@ pwdf_status run_mid_rho(pwdf_ctx *c, int ndm, double *EJ, hipStream_t st) {
   const double nGh = (double)(p.nG_full / 2);
   pwdf_status s;
   char name[32];
-  {
-    Fork f(c, st);
-    for (int la = 0; la <= kMaxL; ++la)
-      for (int lb = 0; lb <= la; ++lb) {
-        int cl = la * 4 + lb;
-        if (p.cls_b1[cl] <= p.cls_b0[cl]) continue;
-        std::snprintf(name, sizeof name, "transform_%d%d", la, lb);
-        hipStream_t ss = f.stream();
-        if ((s = step(c, name, cls_pairs(p, cl) * ndm, ss, [&] { return launch_transform_cls(d, la, lb, ndm, ss); })) !=
-            PWDF_OK)
-          return s;
-      }
-    if (hipError_t e = f.join()) return hip_fail(c, e, "join");
-  }
-  {
+  if ((s = step(c, "transform", total_pairs(p) * ndm, st, [&] { return launch_transform_all(d, ndm, st); })) !=
+      PWDF_OK)
+    return s;
+  if (d.fp32) {
     Fork f(c, st);
     for (int L = 0; L <= 2 * kMaxL; ++L) {
       if (np_L(p, L) <= 0) continue;
-      std::snprintf(name, sizeof name, d.fp32 ? "rho_mfma_L%d" : "rho_L%d", L);
+      std::snprintf(name, sizeof name, "rho_mfma_L%d", L);
       hipStream_t ss = f.stream();
-      if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, ss, [&] {
-             return d.fp32 ? launch_rho_mfma_L(d, L, ndm, ss) : launch_rho_L(d, L, ndm, ss);
-           })) != PWDF_OK)
+      if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, ss, [&] { return launch_rho_mfma_L(d, L, ndm, ss); })) !=
+          PWDF_OK)
+        return s;
+    }
+    if (hipError_t e = f.join()) return hip_fail(c, e, "join");
+  } else {
+    Fork f(c, st);
+    for (int g = 0; g < 2; ++g) {
+      if (!jpass_group_nonempty(d, g)) continue;
+      hipStream_t ss = f.stream();
+      if ((s = step(c, g ? "rho_hi" : "rho_lo", pass_flops(p, g ? 3 : 0, g ? 2 * kMaxL : 2, ndm), ss,
+                    [&] { return launch_rho_group(d, g, ndm, ss); })) != PWDF_OK)
         return s;
     }
     if (hipError_t e = f.join()) return hip_fail(c, e, "join");
@@ -436,50 +444,56 @@ pwdf_status run_to_rho(pwdf_ctx *c, int ndm, const double *Dk, double *EJ, hipSt
   const Dev &d = c->dev;
   pwdf_status s;
   if ((s = step(c, "phase_d", (double)p.nD_support * p.nk * ndm, st,
-                [&] { return launch_phase_d(d, Dk, ndm, st); })) !=
-      PWDF_OK)
+                [&] { return launch_phase_d(d, Dk, ndm, st); })) != PWDF_OK)
     return s;
   return run_mid_rho(c, ndm, EJ, st);
+}
+
+// J moments of both class groups (FP64) or per class (FP32-MFMA); force = true
+// gives the degree L+1 moments of the gradient
+pwdf_status run_moments(pwdf_ctx *c, int ndm, bool force, hipStream_t st) {
+  const Plan &p = c->plan;
+  const Dev &d = c->dev;
+  const double nGh = (double)(p.nG_full / 2);
+  pwdf_status s;
+  char name[32];
+  Fork f(c, st);
+  if (d.fp32 && !force) {
+    for (int L = 0; L <= 2 * kMaxL; ++L) {
+      if (np_L(p, L) <= 0) continue;
+      std::snprintf(name, sizeof name, "jpass_mfma_L%d", L);
+      hipStream_t ss = f.stream();
+      if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, ss,
+                    [&] { return launch_jpass_mfma_L(d, L, ndm, ss); })) != PWDF_OK)
+        return s;
+    }
+  } else {
+    for (int g = 0; g < 2; ++g) {
+      if (!jpass_group_nonempty(d, g)) continue;
+      hipStream_t ss = f.stream();
+      // force moments cost one degree more than the class's J moments
+      const double fl = force ? pass_flops(p, g ? 3 : 0, g ? 2 * kMaxL : 2, ndm) +
+                                    8.0 * nGh * ndm * (g ? np_L(p, 3) + np_L(p, 4) + np_L(p, 5) + np_L(p, 6)
+                                                         : np_L(p, 0) + np_L(p, 1) + np_L(p, 2))
+                              : pass_flops(p, g ? 3 : 0, g ? 2 * kMaxL : 2, ndm);
+      const char *nm = force ? (g ? "jforce_hi" : "jforce_lo") : (g ? "jpass_hi" : "jpass_lo");
+      if ((s = step(c, nm, fl, ss, [&] { return launch_jpass_group(d, g, force, ndm, ss); })) != PWDF_OK) return s;
+    }
+  }
+  if (hipError_t e = f.join()) return hip_fail(c, e, "join");
+  return PWDF_OK;
 }
 
 // (wprep) .. back transform: Jblk from V
 pwdf_status run_mid_j(pwdf_ctx *c, int ndm, hipStream_t st) {
   const Plan &p = c->plan;
   const Dev &d = c->dev;
-  const double nGh = (double)(p.nG_full / 2);
   pwdf_status s;
-  char name[32];
   if (d.fp32 && (s = step(c, "wprep", (double)p.nslot() * ndm, st, [&] { return launch_wprep(d, ndm, st); })) !=
                     PWDF_OK)
     return s;
-  {
-    Fork f(c, st);
-    for (int L = 0; L <= 2 * kMaxL; ++L) {
-      if (np_L(p, L) <= 0) continue;
-      std::snprintf(name, sizeof name, d.fp32 ? "jpass_mfma_L%d" : "jpass_L%d", L);
-      hipStream_t ss = f.stream();
-      if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, ss, [&] {
-             return d.fp32 ? launch_jpass_mfma_L(d, L, ndm, ss) : launch_jpass_L(d, L, ndm, ss);
-           })) != PWDF_OK)
-        return s;
-    }
-    if (hipError_t e = f.join()) return hip_fail(c, e, "join");
-  }
-  {
-    Fork f(c, st);
-    for (int la = 0; la <= kMaxL; ++la)
-      for (int lb = 0; lb <= la; ++lb) {
-        int cl = la * 4 + lb;
-        if (p.cls_b1[cl] <= p.cls_b0[cl]) continue;
-        std::snprintf(name, sizeof name, "back_%d%d", la, lb);
-        hipStream_t ss = f.stream();
-        if ((s = step(c, name, cls_pairs(p, cl) * ndm, ss, [&] { return launch_back_cls(d, la, lb, ndm, ss); })) !=
-            PWDF_OK)
-          return s;
-      }
-    if (hipError_t e = f.join()) return hip_fail(c, e, "join");
-  }
-  return PWDF_OK;
+  if ((s = run_moments(c, ndm, false, st)) != PWDF_OK) return s;
+  return step(c, "back", total_pairs(p) * ndm, st, [&] { return launch_back_all(d, ndm, st); });
 }
 
 pwdf_status run_from_V(pwdf_ctx *c, int ndm, double *Jk, hipStream_t st) {
@@ -489,21 +503,8 @@ pwdf_status run_from_V(pwdf_ctx *c, int ndm, double *Jk, hipStream_t st) {
   if ((s = run_mid_j(c, ndm, st)) != PWDF_OK) return s;
   if ((s = step(c, "fold_j", (double)p.eJ.size() * ndm, st, [&] { return launch_fold_j(d, ndm, st); })) != PWDF_OK)
     return s;
-  // light and heavy elements write disjoint parts of J(k)
-  Fork f(c, st);
-  hipStream_t s1 = f.stream();
-  const double nh = (double)p.heavyJ.size();
-  if ((s = step(c, "phase_j", ((double)p.nbf * p.nbf - nh) * p.nk * ndm, s1,
-                [&] { return launch_phase_j(d, ndm, Jk, s1); })) != PWDF_OK)
-    return s;
-  if (nh > 0) {
-    hipStream_t s2 = f.stream();
-    if ((s = step(c, "phase_j_heavy", nh * p.nk * ndm, s2, [&] { return launch_phase_j_heavy(d, ndm, Jk, s2); })) !=
-        PWDF_OK)
-      return s;
-  }
-  if (hipError_t e = f.join()) return hip_fail(c, e, "join");
-  return PWDF_OK;
+  return step(c, "phase_j", (double)p.nk * p.nbf * (double)p.nbf * ndm, st,
+              [&] { return launch_phase_j(d, ndm, Jk, st); });
 }
 
 pwdf_status enqueue_build(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, double *EJ, hipStream_t st) {
@@ -756,20 +757,8 @@ pwdf_status pwdf_grad(pwdf_ctx *c, int ndm, const double *Dk, double *dEdR, doub
   if ((s = run_to_rho(c, ndm, Dk, EJ ? EJ : c->Escr, st)) != PWDF_OK) return s;
   const Plan &p = c->plan;
   const Dev &d = c->dev;
-  const double nGh = (double)(p.nG_full / 2);
   char name[32];
-  {
-    Fork f(c, st);
-    for (int L = 0; L <= 2 * kMaxL; ++L) {
-      if (np_L(p, L) <= 0) continue;
-      std::snprintf(name, sizeof name, "jforce_L%d", L);
-      hipStream_t ss = f.stream();
-      if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, ss,
-                    [&] { return launch_jpass_force_L(d, L, ndm, ss); })) != PWDF_OK)
-        return s;
-    }
-    if ((e = f.join()) != hipSuccess) return hip_fail(c, e, "join");
-  }
+  if ((s = run_moments(c, ndm, true, st)) != PWDF_OK) return s;
   {
     Fork f(c, st);
     for (int la = 0; la <= kMaxL; ++la)
@@ -944,47 +933,60 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
       best = t;
     }
   }
-  // 2. per-class chunk multipliers at that segment length: each class keeps the
-  // multiplier with its shortest kernel (timed one launch at a time)
+  // 2. chunk counts of the pair-G passes scaled together, by concurrent wall time
   build_segments(c->plan, best.seg_len);
-  const double mults[] = {0.25, 0.5, 1.0, 2.0, 4.0};
-  double brho[kMaxLsum + 1], bj[kMaxLsum + 1];
-  for (int L = 0; L <= kMaxLsum; ++L) brho[L] = bj[L] = 1e300;
-  const char *rn = c->prec == PWDF_FP32_MFMA ? "rho_mfma_L%d" : "rho_L%d";
-  const char *jn = c->prec == PWDF_FP32_MFMA ? "jpass_mfma_L%d" : "jpass_L%d";
-  Tune cand = best;
-  std::vector<std::pair<std::string, double>> per;
-  for (double m : mults) {
+  for (double m : {0.5, 2.0}) {
     Tune t = best;
     for (int L = 0; L <= kMaxLsum; ++L) t.mrho[L] = t.mj[L] = m;
     if ((s = setup_device(c, t)) != PWDF_OK) return s;
-    double tot = 0.0;
-    if ((s = time_tunable(c, ndm, 3, per, tot)) != PWDF_OK) return s;
-    char name[32];
-    for (int L = 0; L <= 2 * kMaxL; ++L) {
-      if (np_L(c->plan, L) <= 0) continue;
-      std::snprintf(name, sizeof name, rn, L);
-      double tr = kernel_ms(per, name);
-      std::snprintf(name, sizeof name, jn, L);
-      double tj = kernel_ms(per, name);
-      if (tr < brho[L]) {
-        brho[L] = tr;
-        cand.mrho[L] = m;
-      }
-      if (tj < bj[L]) {
-        bj[L] = tj;
-        cand.mj[L] = m;
-      }
+    double ms = 0.0;
+    if ((s = time_total(c, ndm, 5, ms)) != PWDF_OK) return s;
+    if (ms < best_t) {
+      best_t = ms;
+      best = t;
     }
   }
-  // 3. keep the per-class choice only if it also wins when the classes overlap
-  if ((s = setup_device(c, cand)) != PWDF_OK) return s;
-  double t_cand = 0.0;
-  if ((s = time_total(c, ndm, 5, t_cand)) != PWDF_OK) return s;
-  if (t_cand > best_t) {
-    cand = best;
+  Tune cand = best;
+  // 3. FP32-MFMA form (one launch per class): each class keeps the multiplier
+  // with its shortest kernel, timed one launch at a time, and the result is kept
+  // only if it also wins when the classes overlap
+  if (c->prec == PWDF_FP32_MFMA) {
+    const double mults[] = {0.25, 0.5, 1.0, 2.0, 4.0};
+    double brho[kMaxLsum + 1], bj[kMaxLsum + 1];
+    for (int L = 0; L <= kMaxLsum; ++L) brho[L] = bj[L] = 1e300;
+    std::vector<std::pair<std::string, double>> per;
+    for (double m : mults) {
+      Tune t = best;
+      for (int L = 0; L <= kMaxLsum; ++L) {
+        t.mrho[L] *= m;
+        t.mj[L] *= m;
+      }
+      if ((s = setup_device(c, t)) != PWDF_OK) return s;
+      double tot = 0.0;
+      if ((s = time_tunable(c, ndm, 3, per, tot)) != PWDF_OK) return s;
+      char name[32];
+      for (int L = 0; L <= 2 * kMaxL; ++L) {
+        if (np_L(c->plan, L) <= 0) continue;
+        std::snprintf(name, sizeof name, "rho_mfma_L%d", L);
+        const double tr = kernel_ms(per, name);
+        std::snprintf(name, sizeof name, "jpass_mfma_L%d", L);
+        const double tj = kernel_ms(per, name);
+        if (tr < brho[L]) {
+          brho[L] = tr;
+          cand.mrho[L] = t.mrho[L];
+        }
+        if (tj < bj[L]) {
+          bj[L] = tj;
+          cand.mj[L] = t.mj[L];
+        }
+      }
+    }
     if ((s = setup_device(c, cand)) != PWDF_OK) return s;
+    double t_cand = 0.0;
+    if ((s = time_total(c, ndm, 5, t_cand)) != PWDF_OK) return s;
+    if (t_cand > best_t) cand = best;
   }
+  if ((s = setup_device(c, cand)) != PWDF_OK) return s;
   c->prof_on = was_prof;
   save_tune(cache_path, key, cand);
   return PWDF_OK;

@@ -101,22 +101,20 @@ __global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk,
 // real part and odd |k| in the imaginary part.
 // ---------------------------------------------------------------------------
 template <int LA, int LB>
-__global__ __launch_bounds__(64) void k_transform(const BlockRec *__restrict__ blocks, int b0, int b1,
-                                                  const PairAux *__restrict__ aux,
-                                                  const double *__restrict__ Dblk, int64_t nelem,
-                                                  const double *__restrict__ ttab,
-                                                  double *__restrict__ dhat, int64_t dhat_size,
-                                                  int64_t cls_off, int Lp0, float *__restrict__ dh32,
-                                                  int64_t d32_off, int ncols, int ndmp) {
+__device__ __forceinline__ void transform_thread(const Dev &dv, int bi, int dm) {
   constexpr int L = LA + LB;
   constexpr int NT = nherm(L);
   constexpr Carts<LA> CA{};
   constexpr Carts<LB> CB{};
   constexpr int NCA = ncart(LA), NCB = ncart(LB);
-  const int bi = b0 + blockIdx.x * blockDim.x + threadIdx.x;
-  const int dm = blockIdx.y;
-  if (bi >= b1) return;
-  const BlockRec b = blocks[bi];
+  const PairAux *__restrict__ aux = dv.aux;
+  const double *__restrict__ Dblk = dv.Dblk;
+  const double *__restrict__ ttab = dv.ttab;
+  double *__restrict__ dhat = dv.dhat;
+  float *__restrict__ dh32 = dv.dh32;
+  const int64_t nelem = dv.nelem, dhat_size = dv.dhat_size, cls_off = dv.dhat_off[L], d32_off = dv.d32_off[L];
+  const int Lp0 = dv.L_p0[L], ncols = dv.ncols32[L], ndmp = dv.ndmp;
+  const BlockRec b = dv.blocks[bi];
   const double *D = Dblk + (size_t)dm * nelem + b.eoff;
   double *out_base = dhat + (size_t)dm * dhat_size + cls_off;
   for (int q = b.p0; q < b.p1; ++q) {
@@ -184,21 +182,21 @@ struct RhoTile {
 };
 
 template <int L, int SEG, int W>
-__global__ __launch_bounds__(64 * W) void k_rho(const SegDesc *__restrict__ segs, int nseg,
-                                                const PairHot *__restrict__ hot, int Lp0, int Lp1,
-                                                int pairs_per_chunk, const double *__restrict__ dhat,
-                                                int64_t dhat_size, int64_t cls_off,
-                                                double2 *__restrict__ part, int row0, int nrows, int nslot) {
+__device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int dm, double *__restrict__ sp,
+                                          double2 *__restrict__ red) {
   constexpr int NT = nherm(L);
   constexpr int REC = RhoTile<L>::REC;
   constexpr int TP = RhoTile<L>::TP;
   constexpr Monos<L> MT{};
-  __shared__ double sp[TP * REC];
-  __shared__ double2 red[(W > 1 ? W - 1 : 1) * 64 * SEG];
+  const SegDesc *__restrict__ segs = dv.segs;
+  const PairHot *__restrict__ hot = dv.hot;
+  const double *__restrict__ dhat = dv.dhat;
+  double2 *__restrict__ part = dv.part;
+  const int nseg = dv.nseg, Lp0 = dv.L_p0[L], Lp1 = dv.L_p1[L], pairs_per_chunk = dv.rho_ppc[L];
+  const int row0 = dv.rho_row0[L], nrows = dv.nrows, nslot = dv.nslot;
+  const int64_t dhat_size = dv.dhat_size, cls_off = dv.dhat_off[L];
   const int lane = threadIdx.x, w = threadIdx.y, tid = w * 64 + lane;
-  const int seg = blockIdx.x * 64 + lane;
-  const int chunk = blockIdx.y;
-  const int dm = blockIdx.z;
+  const int seg = sgi * 64 + lane;
   const int p0 = Lp0 + chunk * pairs_per_chunk;
   const int p1 = min(Lp1, p0 + pairs_per_chunk);
   const bool active = seg < nseg;
@@ -370,21 +368,20 @@ __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ Epart
 //   yhat_{abc} += n_v^b n_w^c (Re m_a if a+b+c even else Im m_a).
 // Padding slots carry V = 0.
 // ---------------------------------------------------------------------------
+constexpr int kJTile = 32;  // segments per LDS tile of the J pass
+
 template <int L, int SEG>
-__global__ __launch_bounds__(256) void k_jpass(const SegDesc *__restrict__ segs, int nseg,
-                                               int segs_per_chunk, const double2 *__restrict__ Vc,
-                                               int nslot, const PairHot *__restrict__ hot, int Lp0,
-                                               int Lp1, double *__restrict__ yhat, int64_t yhat_size,
-                                               int64_t ycls_off) {
+__device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, int nseg, int segs_per_chunk,
+                                            const double2 *__restrict__ Vc, int nslot,
+                                            const PairHot *__restrict__ hot, int Lp0, int Lp1,
+                                            double *__restrict__ yhat, int64_t yhat_size, int64_t ycls_off, int pb,
+                                            int chunk, int dm, SegDesc *__restrict__ ss,
+                                            double2 *__restrict__ sv) {
   constexpr int NT = nherm(L);
-  constexpr int TS = 32;  // segments per LDS tile
+  constexpr int TS = kJTile;
   constexpr Monos<L> MT{};
-  __shared__ SegDesc ss[TS];
-  __shared__ double2 sv[TS * SEG];
   const int np = Lp1 - Lp0;
-  const int pl = blockIdx.x * blockDim.x + threadIdx.x;
-  const int chunk = blockIdx.y;
-  const int dm = blockIdx.z;
+  const int pl = pb * blockDim.x + threadIdx.x;
   const bool active = pl < np;
   const PairHot h = hot[Lp0 + (active ? pl : 0)];
   const int s0 = chunk * segs_per_chunk;
@@ -461,21 +458,19 @@ __global__ __launch_bounds__(256) void k_jpass(const SegDesc *__restrict__ segs,
 //   J_ab += pref_j sum_t E^{ab}_t J~_t
 // ---------------------------------------------------------------------------
 template <int LA, int LB>
-__global__ __launch_bounds__(64) void k_backtransform(const BlockRec *__restrict__ blocks, int b0, int b1,
-                                                      const PairAux *__restrict__ aux,
-                                                      const double *__restrict__ ttab,
-                                                      const double *__restrict__ yhat, int64_t yhat_size,
-                                                      int64_t ycls_off, int nchunks, int Lp0, int Lp1,
-                                                      double *__restrict__ Jblk, int64_t nelem) {
+__device__ __forceinline__ void back_thread(const Dev &dv, int bi, int dm) {
   constexpr int L = LA + LB;
   constexpr int NT = nherm(L);
   constexpr Carts<LA> CA{};
   constexpr Carts<LB> CB{};
   constexpr int NCA = ncart(LA), NCB = ncart(LB);
-  const int bi = b0 + blockIdx.x * blockDim.x + threadIdx.x;
-  const int dm = blockIdx.y;
-  if (bi >= b1) return;
-  const BlockRec b = blocks[bi];
+  const PairAux *__restrict__ aux = dv.aux;
+  const double *__restrict__ ttab = dv.ttab;
+  const double *__restrict__ yhat = dv.yhat;
+  double *__restrict__ Jblk = dv.Jblk;
+  const int64_t yhat_size = dv.yhat_size, ycls_off = dv.yhat_off[L], nelem = dv.nelem;
+  const int nchunks = dv.j_chunks[L], Lp0 = dv.L_p0[L], Lp1 = dv.L_p1[L];
+  const BlockRec b = dv.blocks[bi];
   const int np = Lp1 - Lp0;
   double J[NCA * NCB];
 #pragma unroll
@@ -551,6 +546,9 @@ struct WaveTabs {
   static constexpr int NCA = ncart(LA), NCB = ncart(LB);
   static constexpr int NE = (LA + 1) * (LB + 1) * (L + 1);  // one axis: E[i][j][t]
   static constexpr int eidx(int i, int j, int t) { return (i * (LB + 1) + j) * (L + 1) + t; }
+  // LDS doubles of the wave-per-block transform and back-transform
+  static constexpr int kTransformLds = 3 * NE + NCA * NCB + NT;
+  static constexpr int kBackLds = 3 * NE + 2 * NT + ((L + 1) * (L + 1) * (L + 1) + 1) / 2;
 };
 
 // (tx, ty, tz) of Hermite index t in the degree-ordered list (runtime inverse).
@@ -599,22 +597,23 @@ __device__ __forceinline__ void wave_etabs(const PairAux &x, double *sE) {
 }
 
 template <int LA, int LB>
-__global__ __launch_bounds__(64) void k_transform_w(const BlockRec *__restrict__ blocks, int b0,
-                                                    const PairAux *__restrict__ aux,
-                                                    const double *__restrict__ Dblk, int64_t nelem,
-                                                    const double *__restrict__ ttab, double *__restrict__ dhat,
-                                                    int64_t dhat_size, int64_t cls_off, int Lp0,
-                                                    float *__restrict__ dh32, int64_t d32_off, int ncols, int ndmp) {
+__device__ __forceinline__ void transform_wave(const Dev &dv, int bi, int dm, double *__restrict__ lds) {
   using W = WaveTabs<LA, LB>;
   constexpr int L = W::L, NT = W::NT, NCA = W::NCA, NCB = W::NCB, NE = W::NE;
   constexpr Carts<LA> CA{};
   constexpr Carts<LB> CB{};
-  __shared__ double sE[3 * NE];
-  __shared__ double sD[NCA * NCB];
-  __shared__ double sH[NT];
+  const PairAux *__restrict__ aux = dv.aux;
+  const double *__restrict__ Dblk = dv.Dblk;
+  const double *__restrict__ ttab = dv.ttab;
+  double *__restrict__ dhat = dv.dhat;
+  float *__restrict__ dh32 = dv.dh32;
+  const int64_t nelem = dv.nelem, dhat_size = dv.dhat_size, cls_off = dv.dhat_off[L], d32_off = dv.d32_off[L];
+  const int Lp0 = dv.L_p0[L], ncols = dv.ncols32[L], ndmp = dv.ndmp;
+  double *sE = lds;
+  double *sD = sE + 3 * NE;
+  double *sH = sD + NCA * NCB;
   const int lane = threadIdx.x;
-  const BlockRec b = blocks[b0 + blockIdx.x];
-  const int dm = blockIdx.y;
+  const BlockRec b = dv.blocks[bi];
   for (int e = lane; e < NCA * NCB; e += 64) sD[e] = Dblk[(size_t)dm * nelem + b.eoff + e];
   double *out_base = dhat + (size_t)dm * dhat_size + cls_off;
   for (int q = b.p0; q < b.p1; ++q) {
@@ -654,22 +653,23 @@ __global__ __launch_bounds__(64) void k_transform_w(const BlockRec *__restrict__
 }
 
 template <int LA, int LB>
-__global__ __launch_bounds__(64) void k_back_w(const BlockRec *__restrict__ blocks, int b0,
-                                               const PairAux *__restrict__ aux, const double *__restrict__ ttab,
-                                               const double *__restrict__ yhat, int64_t yhat_size, int64_t ycls_off,
-                                               int nchunks, int Lp0, int Lp1, double *__restrict__ Jblk,
-                                               int64_t nelem) {
+__device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double *__restrict__ lds) {
   using W = WaveTabs<LA, LB>;
   constexpr int L = W::L, NT = W::NT, NCA = W::NCA, NCB = W::NCB, NE = W::NE;
   constexpr int NEL = NCA * NCB;
   constexpr int ROUNDS = (NEL + 63) / 64;
-  __shared__ double sE[3 * NE];
-  __shared__ double sY[NT];
-  __shared__ double sJ[NT];
-  __shared__ int sIdx[(L + 1) * (L + 1) * (L + 1)];
+  const PairAux *__restrict__ aux = dv.aux;
+  const double *__restrict__ ttab = dv.ttab;
+  const double *__restrict__ yhat = dv.yhat;
+  double *__restrict__ Jblk = dv.Jblk;
+  const int64_t yhat_size = dv.yhat_size, ycls_off = dv.yhat_off[L], nelem = dv.nelem;
+  const int nchunks = dv.j_chunks[L], Lp0 = dv.L_p0[L], Lp1 = dv.L_p1[L];
+  double *sE = lds;
+  double *sY = sE + 3 * NE;
+  double *sJ = sY + NT;
+  int *sIdx = reinterpret_cast<int *>(sJ + NT);
   const int lane = threadIdx.x;
-  const BlockRec b = blocks[b0 + blockIdx.x];
-  const int dm = blockIdx.y;
+  const BlockRec b = dv.blocks[bi];
   const int np = Lp1 - Lp0;
   for (int t = lane; t < NT; t += 64) {
     int tx, ty, tz;
@@ -752,23 +752,49 @@ __global__ __launch_bounds__(256) void k_fold_j(const double *__restrict__ Jblk,
 
 // Light elements (at most kPhaseLight classes, zeros included): one thread per
 // element, codes and values in registers; for each k the threads of a wave
-// write consecutive elements of one row of J(k).
-__global__ __launch_bounds__(256) void k_phase_j(const double *__restrict__ Jfold, int nsegJ,
-                                                 const int *__restrict__ sJ_off, const int *__restrict__ sJ_code,
-                                                 const double2 *__restrict__ ptab, int ptab_len, int nk, int n2,
-                                                 int n3, int nbf, double2 *__restrict__ Jk) {
-  __shared__ double2 sph[kPtabMax];
-  for (int i = threadIdx.x; i < ptab_len; i += blockDim.x) sph[i] = ptab[i];
-  __syncthreads();
+// write consecutive elements of one row of J(k).  The body is chosen by the
+// wave's largest class count (lanes with fewer classes carry zero values), the
+// phase offsets advance by one add per class and k, and all NC table reads of a
+// k-point are issued before their multiply-adds.
+template <int NC>
+__device__ __forceinline__ void phase_j_body(const double2 *__restrict__ sph, const int *c1, const int *c2,
+                                             const int *c3, const double *v, int n1, int n2, int n3, size_t nn,
+                                             double2 *__restrict__ out) {
+  size_t ko = 0;
+  for (int k1 = 0; k1 < n1; ++k1)
+    for (int k2 = 0; k2 < n2; ++k2) {
+      int t[NC];
+#pragma unroll
+      for (int i = 0; i < NC; ++i) t[i] = k1 * c1[i] + k2 * c2[i];
+      for (int k3 = 0; k3 < n3; ++k3, ko += nn) {
+        double2 w[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) w[i] = sph[t[i]];
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+          re = fma(w[i].x, v[i], re);
+          im = fma(w[i].y, v[i], im);
+          t[i] += c3[i];
+        }
+        out[ko] = make_double2(re, im);
+      }
+    }
+}
+
+__device__ __forceinline__ void phase_j_light(const double2 *__restrict__ sph, const double *__restrict__ Jfold,
+                                              int nsegJ, const int *__restrict__ sJ_off,
+                                              const int *__restrict__ sJ_code, int nk, int n1, int n2, int n3,
+                                              int nbf, double2 *__restrict__ Jk, int64_t e0, int dm) {
   const int64_t nn = (int64_t)nbf * nbf;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int dm = blockIdx.y;
-  if (e >= nn) return;
+  // lanes past the end and heavy elements take part with no classes and store nothing
+  const bool inb = e0 < nn;
+  const int64_t e = inb ? e0 : nn - 1;
   const int s0 = sJ_off[e];
-  const int n = sJ_off[e + 1] - s0;
-  if (n > kPhaseLight) return;
+  int n = sJ_off[e + 1] - s0;
+  const bool mine = inb && n <= kPhaseLight;
+  if (!mine) n = 0;
   const double *Jf = Jfold + (size_t)dm * nsegJ;
-  double2 *out = Jk + (size_t)dm * nk * nn + e;
   int c1[kPhaseLight], c2[kPhaseLight], c3[kPhaseLight];
   double v[kPhaseLight];
 #pragma unroll
@@ -779,36 +805,33 @@ __global__ __launch_bounds__(256) void k_phase_j(const double *__restrict__ Jfol
     c3[i] = code >> 20;
     v[i] = i < n ? Jf[s0 + i] : 0.0;
   }
-  int k1 = 0, k2 = 0, k3 = 0;
-  for (int k = 0; k < nk; ++k) {
-    double re = 0.0, im = 0.0;
+  int nmax = n;
 #pragma unroll
-    for (int i = 0; i < kPhaseLight; ++i) {
-      if (i < n) {
-        const double2 w = sph[k1 * c1[i] + k2 * c2[i] + k3 * c3[i]];
-        re = fma(w.x, v[i], re);
-        im = fma(w.y, v[i], im);
-      }
-    }
-    out[(size_t)k * nn] = make_double2(re, im);
-    next_k(k1, k2, k3, n2, n3);
+  for (int off = 32; off > 0; off >>= 1) nmax = max(nmax, __shfl_xor(nmax, off, 64));
+  if (!mine) return;
+  double2 *out = Jk + (size_t)dm * nk * nn + e;
+  if (nmax == 0) {
+    for (int k = 0; k < nk; ++k) out[(size_t)k * nn] = make_double2(0.0, 0.0);
+  } else if (nmax == 1) {
+    phase_j_body<1>(sph, c1, c2, c3, v, n1, n2, n3, (size_t)nn, out);
+  } else if (nmax == 2) {
+    phase_j_body<2>(sph, c1, c2, c3, v, n1, n2, n3, (size_t)nn, out);
+  } else if (nmax <= 4) {
+    phase_j_body<4>(sph, c1, c2, c3, v, n1, n2, n3, (size_t)nn, out);
+  } else {
+    phase_j_body<kPhaseLight>(sph, c1, c2, c3, v, n1, n2, n3, (size_t)nn, out);
   }
 }
 
 // Heavy elements: one wave per element, lanes = k-points (64 at a time), the
-// element's classes loaded 64 at a time and broadcast lane by lane.
-__global__ __launch_bounds__(256) void k_phase_j_heavy(const double *__restrict__ Jfold, int nsegJ,
-                                                       const int *__restrict__ heavy, int nheavy,
-                                                       const int *__restrict__ sJ_off,
-                                                       const int *__restrict__ sJ_code,
-                                                       const double2 *__restrict__ ptab, int ptab_len, int nk,
-                                                       int n2, int n3, int nbf, double2 *__restrict__ Jk) {
-  __shared__ double2 sph[kPtabMax];
-  for (int i = threadIdx.x; i < ptab_len; i += blockDim.x) sph[i] = ptab[i];
-  __syncthreads();
+// element's classes loaded 64 at a time and broadcast lane by lane, four per
+// step so that their table reads overlap.
+__device__ __forceinline__ void phase_j_heavy(const double2 *__restrict__ sph, const double *__restrict__ Jfold,
+                                              int nsegJ, const int *__restrict__ heavy, int nheavy,
+                                              const int *__restrict__ sJ_off, const int *__restrict__ sJ_code,
+                                              int nk, int n2, int n3, int nbf, double2 *__restrict__ Jk, int h,
+                                              int dm) {
   const int lane = threadIdx.x & 63;
-  const int h = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int dm = blockIdx.y;
   if (h >= nheavy) return;
   const int64_t nn = (int64_t)nbf * nbf;
   const int64_t e = heavy[h];
@@ -826,16 +849,202 @@ __global__ __launch_bounds__(256) void k_phase_j_heavy(const double *__restrict_
       const int nb = min(64, s1 - cb);
       const int mycode = lane < nb ? sJ_code[cb + lane] : 0;
       const double myv = lane < nb ? Jf[cb + lane] : 0.0;
-      for (int i = 0; i < nb; ++i) {
-        const int code = __shfl(mycode, i, 64);
-        const double x = __shfl(myv, i, 64);
-        const double2 w = sph[k1 * (code & 1023) + k2 * ((code >> 10) & 1023) + k3 * (code >> 20)];
-        re = fma(w.x, x, re);
-        im = fma(w.y, x, im);
+      // lanes past nb hold code 0 and value 0: rounding nb up to 4 adds zeros
+      for (int i = 0; i < nb; i += 4) {
+        int code[4];
+        double x[4];
+        double2 w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          code[u] = __shfl(mycode, i + u, 64);
+          x[u] = __shfl(myv, i + u, 64);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          w[u] = sph[k1 * (code[u] & 1023) + k2 * ((code[u] >> 10) & 1023) + k3 * (code[u] >> 20)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          re = fma(w[u].x, x[u], re);
+          im = fma(w[u].y, x[u], im);
+        }
       }
     }
     if (k < nk) out[(size_t)k * nn] = make_double2(re, im);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Fused launches.  Every pass launches the blocks of all its classes at once: a
+// class table maps ranges of blockIdx.x to a class and its per-class body, so
+// the classes fill the chip together and a build issues about ten launches.
+// ---------------------------------------------------------------------------
+struct ClassTab {
+  int n;              // entries
+  int first[17];      // first flattened block of each entry; first[n] = total
+  int cls[16];        // class: la * 4 + lb (transform, back) or L (rho, J)
+  int mode[16];       // transform / back: 1 = one wave per block, 0 = one thread per block
+  int gx[16];         // rho: segment groups; J: pair blocks (the other index is the chunk)
+};
+
+__device__ __forceinline__ int tab_entry(const ClassTab &t, int b) {
+  int i = 0;
+  while (i + 1 < t.n && b >= t.first[i + 1]) ++i;
+  return i;
+}
+
+template <int LA, int LB>
+constexpr int wave_lds() {
+  return WaveTabs<LA, LB>::kBackLds > WaveTabs<LA, LB>::kTransformLds ? WaveTabs<LA, LB>::kBackLds
+                                                                       : WaveTabs<LA, LB>::kTransformLds;
+}
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kWaveLds = cmax(cmax(cmax(wave_lds<2, 1>(), wave_lds<3, 0>()), cmax(wave_lds<2, 2>(), wave_lds<3, 1>())),
+                              cmax(wave_lds<3, 2>(), wave_lds<3, 3>()));
+
+// Wave-per-block bodies for the heavy classes: L >= 4 always, L = 3 while the
+// class is small enough that one thread per block leaves most of the chip idle.
+static bool wave_per_block(int L, int nblocks) { return L >= 4 || (L == 3 && nblocks < 16384); }
+
+#define PWDF_CLASS_SWITCH_THREAD(F, ...)      \
+  switch (cl) {                               \
+    case 0: F<0, 0>(__VA_ARGS__); break;      \
+    case 4: F<1, 0>(__VA_ARGS__); break;      \
+    case 5: F<1, 1>(__VA_ARGS__); break;      \
+    case 8: F<2, 0>(__VA_ARGS__); break;      \
+    case 9: F<2, 1>(__VA_ARGS__); break;      \
+    case 12: F<3, 0>(__VA_ARGS__); break;     \
+    default: break;                           \
+  }
+#define PWDF_CLASS_SWITCH_WAVE(F, ...)        \
+  switch (cl) {                               \
+    case 9: F<2, 1>(__VA_ARGS__); break;      \
+    case 12: F<3, 0>(__VA_ARGS__); break;     \
+    case 10: F<2, 2>(__VA_ARGS__); break;     \
+    case 13: F<3, 1>(__VA_ARGS__); break;     \
+    case 14: F<3, 2>(__VA_ARGS__); break;     \
+    case 15: F<3, 3>(__VA_ARGS__); break;     \
+    default: break;                           \
+  }
+
+__global__ __launch_bounds__(64) void k_transform_all(const Dev dv, const ClassTab tab) {
+  __shared__ double lds[kWaveLds];
+  const int i = tab_entry(tab, blockIdx.x);
+  const int local = blockIdx.x - tab.first[i];
+  const int cl = tab.cls[i];
+  const int dm = blockIdx.y;
+  if (tab.mode[i]) {
+    PWDF_CLASS_SWITCH_WAVE(transform_wave, dv, dv.cls_b0[cl] + local, dm, lds)
+  } else {
+    const int bi = dv.cls_b0[cl] + local * 64 + threadIdx.x;
+    if (bi >= dv.cls_b1[cl]) return;
+    PWDF_CLASS_SWITCH_THREAD(transform_thread, dv, bi, dm)
+  }
+}
+
+__global__ __launch_bounds__(64) void k_back_all(const Dev dv, const ClassTab tab) {
+  __shared__ double lds[kWaveLds];
+  const int i = tab_entry(tab, blockIdx.x);
+  const int local = blockIdx.x - tab.first[i];
+  const int cl = tab.cls[i];
+  const int dm = blockIdx.y;
+  if (tab.mode[i]) {
+    PWDF_CLASS_SWITCH_WAVE(back_wave, dv, dv.cls_b0[cl] + local, dm, lds)
+  } else {
+    const int bi = dv.cls_b0[cl] + local * 64 + threadIdx.x;
+    if (bi >= dv.cls_b1[cl]) return;
+    PWDF_CLASS_SWITCH_THREAD(back_thread, dv, bi, dm)
+  }
+}
+
+template <int L>
+constexpr int rho_sp_doubles() {
+  return RhoTile<L>::TP * RhoTile<L>::REC;
+}
+constexpr int kRhoSp = cmax(cmax(cmax(rho_sp_doubles<0>(), rho_sp_doubles<1>()), cmax(rho_sp_doubles<2>(), rho_sp_doubles<3>())),
+                            cmax(cmax(rho_sp_doubles<4>(), rho_sp_doubles<5>()), rho_sp_doubles<6>()));
+
+// rho of the classes L in [L0, L1] (low and high groups as for the J pass: the
+// Horner coefficients and monomials of class L set the register footprint).
+template <int SEG, int L0, int L1>
+__global__ __launch_bounds__(256) void k_rho_all(const Dev dv, const ClassTab tab) {
+  constexpr int W = 4;
+  __shared__ double sp[kRhoSp];
+  __shared__ double2 red[(W - 1) * 64 * SEG];
+  const int i = tab_entry(tab, blockIdx.x);
+  const int local = blockIdx.x - tab.first[i];
+  const int nsg = tab.gx[i];
+  const int sgi = local % nsg, chunk = local / nsg;
+  const int dm = blockIdx.y;
+#define PWDF_RCASE(LL) \
+  case LL:             \
+    if (LL >= L0 && LL <= L1) rho_block<(LL >= L0 && LL <= L1 ? LL : L0), SEG, W>(dv, sgi, chunk, dm, sp, red); \
+    break;
+  switch (tab.cls[i]) {
+    PWDF_RCASE(0)
+    PWDF_RCASE(1)
+    PWDF_RCASE(2)
+    PWDF_RCASE(3)
+    PWDF_RCASE(4)
+    PWDF_RCASE(5)
+    PWDF_RCASE(6)
+    default: break;
+  }
+#undef PWDF_RCASE
+}
+
+// J moments of the classes L in [L0, L1] (degree L + DEG: DEG = 1 gives the force
+// moments of the class-L pairs).  Classes are split into a low and a high group
+// because the moment count NT(L) sets the register footprint of the launch.
+template <int SEG, int DEG, int L0, int L1>
+__global__ __launch_bounds__(256) void k_jpass_all(const Dev dv, const ClassTab tab) {
+  __shared__ SegDesc ss[kJTile];
+  __shared__ double2 sv[kJTile * SEG];
+  const int i = tab_entry(tab, blockIdx.x);
+  const int local = blockIdx.x - tab.first[i];
+  const int npb = tab.gx[i];
+  const int pb = local % npb, chunk = local / npb;
+  const int dm = blockIdx.y;
+  const int L = tab.cls[i];
+  double *y = DEG ? dv.yF : dv.yhat;
+  const int64_t ysz = DEG ? dv.yF_size : dv.yhat_size;
+  const int64_t yoff = DEG ? dv.yF_off[L] : dv.yhat_off[L];
+#define PWDF_JCASE(LL)                                                                                          \
+  case LL:                                                                                                      \
+    if (LL >= L0 && LL <= L1)                                                                                   \
+      jpass_block<(LL >= L0 && LL <= L1 ? LL + DEG : 0), SEG>(dv.segs, dv.nseg, dv.j_spc[LL], dv.Vc, dv.nslot, \
+                                                                dv.hot, dv.L_p0[LL], dv.L_p1[LL], y, ysz, yoff, pb, \
+                                                                chunk, dm, ss, sv);                             \
+    break;
+  switch (L) {
+    PWDF_JCASE(0)
+    PWDF_JCASE(1)
+    PWDF_JCASE(2)
+    PWDF_JCASE(3)
+    PWDF_JCASE(4)
+    PWDF_JCASE(5)
+    PWDF_JCASE(6)
+    default: break;
+  }
+#undef PWDF_JCASE
+}
+
+// J(L) -> J(k): blocks [0, nlight) take 256 elements each (light path), the rest
+// four heavy elements each (one wave per element).
+__global__ __launch_bounds__(256) void k_phase_j_all(const double *__restrict__ Jfold, int nsegJ,
+                                                     const int *__restrict__ sJ_off, const int *__restrict__ sJ_code,
+                                                     const int *__restrict__ heavy, int nheavy, int nlight,
+                                                     const double2 *__restrict__ ptab, int ptab_len, int nk, int n1,
+                                                     int n2, int n3, int nbf, double2 *__restrict__ Jk) {
+  __shared__ double2 sph[kPtabMax];
+  for (int i = threadIdx.x; i < ptab_len; i += blockDim.x) sph[i] = ptab[i];
+  __syncthreads();
+  const int dm = blockIdx.y;
+  if ((int)blockIdx.x < nlight)
+    phase_j_light(sph, Jfold, nsegJ, sJ_off, sJ_code, nk, n1, n2, n3, nbf, Jk,
+                  (int64_t)blockIdx.x * blockDim.x + threadIdx.x, dm);
+  else
+    phase_j_heavy(sph, Jfold, nsegJ, heavy, nheavy, sJ_off, sJ_code, nk, n2, n3, nbf, Jk,
+                  (blockIdx.x - nlight) * 4 + (threadIdx.x >> 6), dm);
 }
 
 // ---------------------------------------------------------------------------
@@ -857,201 +1066,110 @@ hipError_t launch_phase_d(const Dev &d, const double *Dk, int ndm, hipStream_t s
   return hipSuccess;
 }
 
-// Wave-per-block kernels for the heavy classes: L >= 4 always, L = 3 while the
-// class is small enough that one thread per block leaves most of the chip idle.
-static bool wave_per_block(int L, int nblocks) { return L >= 4 || (L == 3 && nblocks < 16384); }
+static void add_entry(ClassTab &t, int cls, int mode, int gx, int nblocks) {
+  if (t.n == 0) t.first[0] = 0;
+  t.cls[t.n] = cls;
+  t.mode[t.n] = mode;
+  t.gx[t.n] = gx;
+  t.first[t.n + 1] = t.first[t.n] + nblocks;
+  ++t.n;
+}
 
-template <int LA, int LB>
-static hipError_t transform_one(const Dev &d, int ndm, hipStream_t st) {
-  const int c = LA * 4 + LB;
-  const int b0 = d.cls_b0[c], b1 = d.cls_b1[c];
-  if (b1 <= b0) return hipSuccess;
-  if (wave_per_block(LA + LB, b1 - b0)) {
-    dim3 grid((unsigned)(b1 - b0), ndm);
-    hipLaunchKernelGGL((k_transform_w<LA, LB>), grid, dim3(64), 0, st, d.blocks, b0, d.aux, d.Dblk, d.nelem, d.ttab,
-                       d.dhat, d.dhat_size, d.dhat_off[LA + LB], d.L_p0[LA + LB], d.dh32, d.d32_off[LA + LB],
-                       d.ncols32[LA + LB], d.ndmp);
-    PWDF_CHECK_LAUNCH();
-    return hipSuccess;
-  }
-  dim3 grid((unsigned)((b1 - b0 + 63) / 64), ndm);
-  hipLaunchKernelGGL((k_transform<LA, LB>), grid, dim3(64), 0, st, d.blocks, b0, b1, d.aux, d.Dblk, d.nelem,
-                     d.ttab, d.dhat, d.dhat_size, d.dhat_off[LA + LB], d.L_p0[LA + LB], d.dh32,
-                     d.d32_off[LA + LB], d.ncols32[LA + LB], d.ndmp);
+// transform / back: one entry per non-empty class (la, lb)
+static ClassTab pair_class_tab(const Dev &d) {
+  ClassTab t{};
+  for (int la = 0; la <= kMaxL; ++la)
+    for (int lb = 0; lb <= la; ++lb) {
+      const int cl = la * 4 + lb, nb = d.cls_b1[cl] - d.cls_b0[cl];
+      if (nb <= 0) continue;
+      const bool wave = wave_per_block(la + lb, nb);
+      add_entry(t, cl, wave ? 1 : 0, 0, wave ? nb : (nb + 63) / 64);
+    }
+  return t;
+}
+
+hipError_t launch_transform_all(const Dev &d, int ndm, hipStream_t st) {
+  const ClassTab t = pair_class_tab(d);
+  if (t.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transform_all, dim3((unsigned)t.first[t.n], ndm), dim3(64), 0, st, d, t);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }
 
-hipError_t launch_transform_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st) {
-  switch (la * 4 + lb) {
-    case 0: return transform_one<0, 0>(d, ndm, st);
-    case 4: return transform_one<1, 0>(d, ndm, st);
-    case 5: return transform_one<1, 1>(d, ndm, st);
-    case 8: return transform_one<2, 0>(d, ndm, st);
-    case 9: return transform_one<2, 1>(d, ndm, st);
-    case 10: return transform_one<2, 2>(d, ndm, st);
-    case 12: return transform_one<3, 0>(d, ndm, st);
-    case 13: return transform_one<3, 1>(d, ndm, st);
-    case 14: return transform_one<3, 2>(d, ndm, st);
-    case 15: return transform_one<3, 3>(d, ndm, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int L, int SEG>
-static hipError_t rho_one(const Dev &d, int ndm, hipStream_t st) {
-  const int np = d.L_p1[L] - d.L_p0[L];
-  if (np <= 0) return hipSuccess;
-  constexpr int W = 4;
-  dim3 grid((unsigned)((d.nseg + 63) / 64), d.rho_chunks[L], ndm);
-  hipLaunchKernelGGL((k_rho<L, SEG, W>), grid, dim3(64, W), 0, st, d.segs, d.nseg, d.hot, d.L_p0[L], d.L_p1[L],
-                     d.rho_ppc[L], d.dhat, d.dhat_size, d.dhat_off[L], d.part, d.rho_row0[L], d.nrows, d.nslot);
+hipError_t launch_back_all(const Dev &d, int ndm, hipStream_t st) {
+  const ClassTab t = pair_class_tab(d);
+  if (t.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_back_all, dim3((unsigned)t.first[t.n], ndm), dim3(64), 0, st, d, t);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }
+
+// Class groups of the pair-G passes: [0, kJSplit] and [kJSplit + 1, 6].
+constexpr int kJSplit = 2;
 
 template <int SEG>
-static hipError_t rho_L(const Dev &d, int L, int ndm, hipStream_t st) {
-  switch (L) {
-    case 0: return rho_one<0, SEG>(d, ndm, st);
-    case 1: return rho_one<1, SEG>(d, ndm, st);
-    case 2: return rho_one<2, SEG>(d, ndm, st);
-    case 3: return rho_one<3, SEG>(d, ndm, st);
-    case 4: return rho_one<4, SEG>(d, ndm, st);
-    case 5: return rho_one<5, SEG>(d, ndm, st);
-    case 6: return rho_one<6, SEG>(d, ndm, st);
-    default: return hipErrorInvalidValue;
-  }
+static hipError_t rho_group(const Dev &d, int ndm, hipStream_t st, int group) {
+  ClassTab t{};
+  const int nsg = (d.nseg + 63) / 64;
+  const int La = group == 0 ? 0 : kJSplit + 1, Lb = group == 0 ? kJSplit : 2 * kMaxL;
+  for (int L = La; L <= Lb; ++L)
+    if (d.L_p1[L] > d.L_p0[L]) add_entry(t, L, 0, nsg, nsg * d.rho_chunks[L]);
+  if (t.n == 0) return hipSuccess;
+  dim3 grid((unsigned)t.first[t.n], ndm), block(64, 4);
+  if (group == 0)
+    hipLaunchKernelGGL((k_rho_all<SEG, 0, kJSplit>), grid, block, 0, st, d, t);
+  else
+    hipLaunchKernelGGL((k_rho_all<SEG, kJSplit + 1, 2 * kMaxL>), grid, block, 0, st, d, t);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
 }
 
-hipError_t launch_rho_L(const Dev &d, int L, int ndm, hipStream_t st) {
+hipError_t launch_rho_group(const Dev &d, int group, int ndm, hipStream_t st) {
   switch (d.seg_len) {
-    case 4: return rho_L<4>(d, L, ndm, st);
-    case 8: return rho_L<8>(d, L, ndm, st);
-    case 16: return rho_L<16>(d, L, ndm, st);
+    case 4: return rho_group<4>(d, ndm, st, group);
+    case 8: return rho_group<8>(d, ndm, st, group);
+    case 16: return rho_group<16>(d, ndm, st, group);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st) {
-  dim3 g1((unsigned)((d.nslot + 255) / 256), d.ngroups, ndm);
-  hipLaunchKernelGGL(k_reduce_rows, g1, dim3(256), 0, st, d.part, d.nrows, d.nslot, d.rows_per_group, d.part2,
-                     d.ngroups);
-  PWDF_CHECK_LAUNCH();
-  dim3 grid((unsigned)d.nred_blocks, ndm);
-  hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, st, d.part2, d.ngroups, d.nslot, d.slot_v, d.vol, d.rho, d.Vc,
-                     d.Epart);
-  PWDF_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_energy, dim3(ndm), dim3(256), 0, st, d.Epart, d.nred_blocks, EJ);
-  PWDF_CHECK_LAUNCH();
-  return hipSuccess;
-}
-
-template <int L, int SEG>
-static hipError_t j_one(const Dev &d, int ndm, hipStream_t st) {
-  const int np = d.L_p1[L] - d.L_p0[L];
-  if (np <= 0) return hipSuccess;
-  dim3 grid((unsigned)((np + 255) / 256), d.j_chunks[L], ndm);
-  hipLaunchKernelGGL((k_jpass<L, SEG>), grid, dim3(256), 0, st, d.segs, d.nseg, d.j_spc[L], d.Vc, d.nslot, d.hot,
-                     d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size, d.yhat_off[L]);
+template <int SEG, int DEG>
+static hipError_t jpass_groups(const Dev &d, int ndm, hipStream_t st, int group) {
+  ClassTab t{};
+  const int La = group == 0 ? 0 : kJSplit + 1, Lb = group == 0 ? kJSplit : 2 * kMaxL;
+  for (int L = La; L <= Lb; ++L) {
+    const int np = d.L_p1[L] - d.L_p0[L];
+    if (np <= 0) continue;
+    const int npb = (np + 255) / 256;
+    add_entry(t, L, 0, npb, npb * d.j_chunks[L]);
+  }
+  if (t.n == 0) return hipSuccess;
+  dim3 grid((unsigned)t.first[t.n], ndm);
+  if (group == 0)
+    hipLaunchKernelGGL((k_jpass_all<SEG, DEG, 0, kJSplit>), grid, dim3(256), 0, st, d, t);
+  else
+    hipLaunchKernelGGL((k_jpass_all<SEG, DEG, kJSplit + 1, 2 * kMaxL>), grid, dim3(256), 0, st, d, t);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }
 
-template <int SEG>
-static hipError_t j_L(const Dev &d, int L, int ndm, hipStream_t st) {
-  switch (L) {
-    case 0: return j_one<0, SEG>(d, ndm, st);
-    case 1: return j_one<1, SEG>(d, ndm, st);
-    case 2: return j_one<2, SEG>(d, ndm, st);
-    case 3: return j_one<3, SEG>(d, ndm, st);
-    case 4: return j_one<4, SEG>(d, ndm, st);
-    case 5: return j_one<5, SEG>(d, ndm, st);
-    case 6: return j_one<6, SEG>(d, ndm, st);
+hipError_t launch_jpass_group(const Dev &d, int group, bool force, int ndm, hipStream_t st) {
+  switch (d.seg_len * 2 + (force ? 1 : 0)) {
+    case 8: return jpass_groups<4, 0>(d, ndm, st, group);
+    case 9: return jpass_groups<4, 1>(d, ndm, st, group);
+    case 16: return jpass_groups<8, 0>(d, ndm, st, group);
+    case 17: return jpass_groups<8, 1>(d, ndm, st, group);
+    case 32: return jpass_groups<16, 0>(d, ndm, st, group);
+    case 33: return jpass_groups<16, 1>(d, ndm, st, group);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_jpass_L(const Dev &d, int L, int ndm, hipStream_t st) {
-  switch (d.seg_len) {
-    case 4: return j_L<4>(d, L, ndm, st);
-    case 8: return j_L<8>(d, L, ndm, st);
-    case 16: return j_L<16>(d, L, ndm, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-// Moments of degree <= L+1 for the pairs of class L (centre derivatives raise
-// one Cartesian exponent on the same Gaussian product): the J-pass kernel of
-// degree L+1 run over class-L pairs, into the force moment buffer.
-template <int L, int SEG>
-static hipError_t jforce_one(const Dev &d, int ndm, hipStream_t st) {
-  const int np = d.L_p1[L] - d.L_p0[L];
-  if (np <= 0) return hipSuccess;
-  dim3 grid((unsigned)((np + 255) / 256), d.j_chunks[L], ndm);
-  hipLaunchKernelGGL((k_jpass<L + 1, SEG>), grid, dim3(256), 0, st, d.segs, d.nseg, d.j_spc[L], d.Vc, d.nslot, d.hot,
-                     d.L_p0[L], d.L_p1[L], d.yF, d.yF_size, d.yF_off[L]);
-  PWDF_CHECK_LAUNCH();
-  return hipSuccess;
-}
-
-template <int SEG>
-static hipError_t jforce_L(const Dev &d, int L, int ndm, hipStream_t st) {
-  switch (L) {
-    case 0: return jforce_one<0, SEG>(d, ndm, st);
-    case 1: return jforce_one<1, SEG>(d, ndm, st);
-    case 2: return jforce_one<2, SEG>(d, ndm, st);
-    case 3: return jforce_one<3, SEG>(d, ndm, st);
-    case 4: return jforce_one<4, SEG>(d, ndm, st);
-    case 5: return jforce_one<5, SEG>(d, ndm, st);
-    case 6: return jforce_one<6, SEG>(d, ndm, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_jpass_force_L(const Dev &d, int L, int ndm, hipStream_t st) {
-  switch (d.seg_len) {
-    case 4: return jforce_L<4>(d, L, ndm, st);
-    case 8: return jforce_L<8>(d, L, ndm, st);
-    case 16: return jforce_L<16>(d, L, ndm, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int LA, int LB>
-static hipError_t back_one(const Dev &d, int ndm, hipStream_t st) {
-  const int c = LA * 4 + LB;
-  const int b0 = d.cls_b0[c], b1 = d.cls_b1[c];
-  if (b1 <= b0) return hipSuccess;
-  constexpr int L = LA + LB;
-  if (wave_per_block(L, b1 - b0)) {
-    dim3 grid((unsigned)(b1 - b0), ndm);
-    hipLaunchKernelGGL((k_back_w<LA, LB>), grid, dim3(64), 0, st, d.blocks, b0, d.aux, d.ttab, d.yhat, d.yhat_size,
-                       d.yhat_off[L], d.j_chunks[L], d.L_p0[L], d.L_p1[L], d.Jblk, d.nelem);
-    PWDF_CHECK_LAUNCH();
-    return hipSuccess;
-  }
-  dim3 grid((unsigned)((b1 - b0 + 63) / 64), ndm);
-  hipLaunchKernelGGL((k_backtransform<LA, LB>), grid, dim3(64), 0, st, d.blocks, b0, b1, d.aux, d.ttab, d.yhat,
-                     d.yhat_size, d.yhat_off[L], d.j_chunks[L], d.L_p0[L], d.L_p1[L], d.Jblk, d.nelem);
-  PWDF_CHECK_LAUNCH();
-  return hipSuccess;
-}
-
-hipError_t launch_back_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st) {
-  switch (la * 4 + lb) {
-    case 0: return back_one<0, 0>(d, ndm, st);
-    case 4: return back_one<1, 0>(d, ndm, st);
-    case 5: return back_one<1, 1>(d, ndm, st);
-    case 8: return back_one<2, 0>(d, ndm, st);
-    case 9: return back_one<2, 1>(d, ndm, st);
-    case 10: return back_one<2, 2>(d, ndm, st);
-    case 12: return back_one<3, 0>(d, ndm, st);
-    case 13: return back_one<3, 1>(d, ndm, st);
-    case 14: return back_one<3, 2>(d, ndm, st);
-    case 15: return back_one<3, 3>(d, ndm, st);
-    default: return hipErrorInvalidValue;
-  }
+bool jpass_group_nonempty(const Dev &d, int group) {
+  const int La = group == 0 ? 0 : kJSplit + 1, Lb = group == 0 ? kJSplit : 2 * kMaxL;
+  for (int L = La; L <= Lb; ++L)
+    if (d.L_p1[L] > d.L_p0[L]) return true;
+  return false;
 }
 
 hipError_t launch_fold_j(const Dev &d, int ndm, hipStream_t st) {
@@ -1066,19 +1184,26 @@ hipError_t launch_fold_j(const Dev &d, int ndm, hipStream_t st) {
 hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, hipStream_t st) {
   if (d.ptab_len > kPtabMax) return hipErrorInvalidValue;
   const int64_t nn = (int64_t)d.nbf * d.nbf;
-  dim3 grid((unsigned)((nn + 255) / 256), ndm);
-  hipLaunchKernelGGL(k_phase_j, grid, dim3(256), 0, st, d.Jfold, d.nsegJ, d.sJ_off, d.sJ_code, d.ptab, d.ptab_len,
-                     d.nk, d.kmesh[1], d.kmesh[2], d.nbf, (double2 *)Jk);
+  const int nlight = (int)((nn + 255) / 256);
+  const int nheavy_blocks = (d.nheavyJ + 3) / 4;
+  dim3 grid((unsigned)(nlight + nheavy_blocks), ndm);
+  hipLaunchKernelGGL(k_phase_j_all, grid, dim3(256), 0, st, d.Jfold, d.nsegJ, d.sJ_off, d.sJ_code, d.heavyJ,
+                     d.nheavyJ, nlight, d.ptab, d.ptab_len, d.nk, d.kmesh[0], d.kmesh[1], d.kmesh[2], d.nbf,
+                     (double2 *)Jk);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }
 
-hipError_t launch_phase_j_heavy(const Dev &d, int ndm, double *Jk, hipStream_t st) {
-  if (d.nheavyJ <= 0) return hipSuccess;
-  if (d.ptab_len > kPtabMax) return hipErrorInvalidValue;
-  dim3 gh((unsigned)((d.nheavyJ + 3) / 4), ndm);
-  hipLaunchKernelGGL(k_phase_j_heavy, gh, dim3(256), 0, st, d.Jfold, d.nsegJ, d.heavyJ, d.nheavyJ, d.sJ_off, d.sJ_code,
-                     d.ptab, d.ptab_len, d.nk, d.kmesh[1], d.kmesh[2], d.nbf, (double2 *)Jk);
+hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st) {
+  dim3 g1((unsigned)((d.nslot + 255) / 256), d.ngroups, ndm);
+  hipLaunchKernelGGL(k_reduce_rows, g1, dim3(256), 0, st, d.part, d.nrows, d.nslot, d.rows_per_group, d.part2,
+                     d.ngroups);
+  PWDF_CHECK_LAUNCH();
+  dim3 g2((unsigned)d.nred_blocks, ndm);
+  hipLaunchKernelGGL(k_reduce, g2, dim3(256), 0, st, d.part2, d.ngroups, d.nslot, d.slot_v, d.vol, d.rho, d.Vc,
+                     d.Epart);
+  PWDF_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_energy, dim3(ndm), dim3(256), 0, st, d.Epart, d.nred_blocks, EJ);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }
