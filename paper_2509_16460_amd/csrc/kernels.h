@@ -85,6 +85,7 @@ hipError_t launch_jpass_mfma_L(const Dev &d, int L, int ndm, hipStream_t st);
 // FP64 path: one launch per pass over all classes
 hipError_t launch_phase_d(const Dev &d, const double *Dk, int ndm, hipStream_t st);
 hipError_t launch_transform_all(const Dev &d, int ndm, hipStream_t st);
+hipError_t launch_back_all(const Dev &d, int ndm, hipStream_t st);
 // rho of the class group 0 (L <= 2) or 1 (L >= 3)
 hipError_t launch_rho_group(const Dev &d, int group, int ndm, hipStream_t st);
 hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st);
@@ -92,7 +93,6 @@ hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st);
 // class group 0 (L <= 2) or 1 (L >= 3)
 hipError_t launch_jpass_group(const Dev &d, int group, bool force, int ndm, hipStream_t st);
 bool jpass_group_nonempty(const Dev &d, int group);
-hipError_t launch_back_all(const Dev &d, int ndm, hipStream_t st);
 hipError_t launch_fold_j(const Dev &d, int ndm, hipStream_t st);
 hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, hipStream_t st);
 // gradient

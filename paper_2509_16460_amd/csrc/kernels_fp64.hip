@@ -547,7 +547,7 @@ struct WaveTabs {
   static constexpr int NE = (LA + 1) * (LB + 1) * (L + 1);  // one axis: E[i][j][t]
   static constexpr int eidx(int i, int j, int t) { return (i * (LB + 1) + j) * (L + 1) + t; }
   // LDS doubles of the wave-per-block transform and back-transform
-  static constexpr int kTransformLds = 3 * NE + NCA * NCB + NT;
+  static constexpr int kTransformLds = 3 * NE + NCA * NCB + NT + (3 * NCA * NCB + 1) / 2;
   static constexpr int kBackLds = 3 * NE + 2 * NT + ((L + 1) * (L + 1) * (L + 1) + 1) / 2;
 };
 
@@ -578,22 +578,69 @@ __device__ __forceinline__ void cart_of(int l, int ic, int &x, int &y, int &z) {
   z = l - x - y;
 }
 
+// E table of one axis written column by column into E[i][j][t] (LDS), with the
+// recurrence of md_axis: only the column E[0][j] and the current E[i][j] live
+// in registers.  Entries t > i + j are written as zeros.
 template <int LA, int LB>
-__device__ __forceinline__ void wave_etabs(const PairAux &x, double *sE) {
+__device__ __forceinline__ void md_axis_lds(double inv2p, double xpa, double xpb, double *E) {
+  using W = WaveTabs<LA, LB>;
+  constexpr int L = LA + LB;
+  double c0[L + 1];
+#pragma unroll
+  for (int t = 0; t <= L; ++t) c0[t] = t == 0 ? 1.0 : 0.0;
+#pragma unroll
+  for (int j = 0; j <= LB; ++j) {
+    if (j > 0) {
+      double n[L + 1];
+#pragma unroll
+      for (int t = 0; t <= L; ++t) {
+        double v = 0.0;
+        if (t <= j) {
+          v = xpb * c0[t];
+          if (t > 0) v += inv2p * c0[t - 1];
+          if (t + 1 <= j - 1) v += (t + 1) * c0[t + 1];
+        }
+        n[t] = v;
+      }
+#pragma unroll
+      for (int t = 0; t <= L; ++t) c0[t] = n[t];
+    }
+    double cur[L + 1];
+#pragma unroll
+    for (int t = 0; t <= L; ++t) {
+      cur[t] = c0[t];
+      E[W::eidx(0, j, t)] = cur[t];
+    }
+#pragma unroll
+    for (int i = 1; i <= LA; ++i) {
+      double n[L + 1];
+#pragma unroll
+      for (int t = 0; t <= L; ++t) {
+        double v = 0.0;
+        if (t <= i + j) {
+          v = xpa * cur[t];
+          if (t > 0) v += inv2p * cur[t - 1];
+          if (t + 1 <= i - 1 + j) v += (t + 1) * cur[t + 1];
+        }
+        n[t] = v;
+      }
+#pragma unroll
+      for (int t = 0; t <= L; ++t) {
+        cur[t] = n[t];
+        E[W::eidx(i, j, t)] = cur[t];
+      }
+    }
+  }
+}
+
+// Lanes 0..2 build the E table of axis x, y, z (read straight from the pair
+// record in global memory: a lane-indexed field of a local copy would go
+// through scratch).
+template <int LA, int LB>
+__device__ __forceinline__ void wave_etabs(const PairAux *__restrict__ xq, double *sE) {
   using W = WaveTabs<LA, LB>;
   const int lane = threadIdx.x;
-  if (lane < 3) {
-    const double xa = lane == 0 ? x.xpa[0] : (lane == 1 ? x.xpa[1] : x.xpa[2]);
-    const double xb = lane == 0 ? x.xpb[0] : (lane == 1 ? x.xpb[1] : x.xpb[2]);
-    double E[LA + 1][LB + 1][W::L + 1];
-    md_axis<LA, LB>(0.5 / x.p, xa, xb, E);
-#pragma unroll
-    for (int i = 0; i <= LA; ++i)
-#pragma unroll
-      for (int j = 0; j <= LB; ++j)
-#pragma unroll
-        for (int t = 0; t <= W::L; ++t) sE[lane * W::NE + W::eidx(i, j, t)] = E[i][j][t];
-  }
+  if (lane < 3) md_axis_lds<LA, LB>(0.5 / xq->p, xq->xpa[lane], xq->xpb[lane], sE + lane * W::NE);
 }
 
 template <int LA, int LB>
@@ -612,28 +659,33 @@ __device__ __forceinline__ void transform_wave(const Dev &dv, int bi, int dm, do
   double *sE = lds;
   double *sD = sE + 3 * NE;
   double *sH = sD + NCA * NCB;
+  int3 *sOff = reinterpret_cast<int3 *>(sH + NT);  // E-table offsets of element (ia, ib) per axis
   const int lane = threadIdx.x;
   const BlockRec b = dv.blocks[bi];
+  for (int e = lane; e < NCA * NCB; e += 64) {
+    int ax, ay, az, bx, by, bz;
+    cart_of(LA, e / NCB, ax, ay, az);
+    cart_of(LB, e % NCB, bx, by, bz);
+    sOff[e] = make_int3(W::eidx(ax, bx, 0), NE + W::eidx(ay, by, 0), 2 * NE + W::eidx(az, bz, 0));
+  }
   for (int e = lane; e < NCA * NCB; e += 64) sD[e] = Dblk[(size_t)dm * nelem + b.eoff + e];
   double *out_base = dhat + (size_t)dm * dhat_size + cls_off;
   for (int q = b.p0; q < b.p1; ++q) {
     const PairAux x = aux[q];
     __syncthreads();
-    wave_etabs<LA, LB>(x, sE);
+    wave_etabs<LA, LB>(aux + q, sE);
     __syncthreads();
     for (int t = lane; t < NT; t += 64) {
       int tx, ty, tz;
       herm_of(t, tx, ty, tz);
       double s = 0.0;
-#pragma unroll
-      for (int ia = 0; ia < NCA; ++ia)
-#pragma unroll
-        for (int ib = 0; ib < NCB; ++ib) {
-          const double ex = sE[W::eidx(CA.x[ia], CB.x[ib], 0) + tx];
-          const double ey = sE[NE + W::eidx(CA.y[ia], CB.y[ib], 0) + ty];
-          const double ez = sE[2 * NE + W::eidx(CA.z[ia], CB.z[ib], 0) + tz];
-          s = fma(sD[ia * NCB + ib] * ex, ey * ez, s);
-        }
+      // element (ia, ib) in a runtime loop, four at a time: a fully unrolled loop
+      // lets the scheduler hoist every LDS read and the register count explodes
+#pragma unroll 4
+      for (int e = 0; e < NCA * NCB; ++e) {
+        const int3 o = sOff[e];
+        s = fma(sD[e] * sE[o.x + tx], sE[o.y + ty] * sE[o.z + tz], s);
+      }
       sH[t] = s * x.pref_rho;
     }
     __syncthreads();
@@ -694,7 +746,7 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
       for (int c = 0; c < nchunks; ++c) s += ys[((size_t)c * NT + k) * np];
       sY[k] = s;
     }
-    wave_etabs<LA, LB>(x, sE);
+    wave_etabs<LA, LB>(aux + q, sE);
     __syncthreads();
     for (int t = lane; t < NT; t += 64) {
       int d = 0;
@@ -750,6 +802,8 @@ __global__ __launch_bounds__(256) void k_fold_j(const double *__restrict__ Jblk,
   Jfold[(size_t)dm * nsegJ + sg] = s;
 }
 
+__device__ __forceinline__ void store_jk(double2 *p, double re, double im) { *p = make_double2(re, im); }
+
 // Light elements (at most kPhaseLight classes, zeros included): one thread per
 // element, codes and values in registers; for each k the threads of a wave
 // write consecutive elements of one row of J(k).  The body is chosen by the
@@ -777,7 +831,7 @@ __device__ __forceinline__ void phase_j_body(const double2 *__restrict__ sph, co
           im = fma(w[i].y, v[i], im);
           t[i] += c3[i];
         }
-        out[ko] = make_double2(re, im);
+        store_jk(out + ko, re, im);
       }
     }
 }
@@ -811,7 +865,7 @@ __device__ __forceinline__ void phase_j_light(const double2 *__restrict__ sph, c
   if (!mine) return;
   double2 *out = Jk + (size_t)dm * nk * nn + e;
   if (nmax == 0) {
-    for (int k = 0; k < nk; ++k) out[(size_t)k * nn] = make_double2(0.0, 0.0);
+    for (int k = 0; k < nk; ++k) store_jk(out + (size_t)k * nn, 0.0, 0.0);
   } else if (nmax == 1) {
     phase_j_body<1>(sph, c1, c2, c3, v, n1, n2, n3, (size_t)nn, out);
   } else if (nmax == 2) {
@@ -869,7 +923,7 @@ __device__ __forceinline__ void phase_j_heavy(const double2 *__restrict__ sph, c
         }
       }
     }
-    if (k < nk) out[(size_t)k * nn] = make_double2(re, im);
+    if (k < nk) store_jk(out + (size_t)k * nn, re, im);
   }
 }
 
@@ -901,9 +955,10 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int kWaveLds = cmax(cmax(cmax(wave_lds<2, 1>(), wave_lds<3, 0>()), cmax(wave_lds<2, 2>(), wave_lds<3, 1>())),
                               cmax(wave_lds<3, 2>(), wave_lds<3, 3>()));
 
-// Wave-per-block bodies for the heavy classes: L >= 4 always, L = 3 while the
-// class is small enough that one thread per block leaves most of the chip idle.
-static bool wave_per_block(int L, int nblocks) { return L >= 4 || (L == 3 && nblocks < 16384); }
+// Wave-per-block bodies for the classes with L = la + lb >= 3: their per-lane
+// tables (E coefficients, Hermite and Cartesian vectors) would hold hundreds
+// of registers in a thread-per-block body.
+static bool wave_per_block(int L) { return L >= 3; }
 
 #define PWDF_CLASS_SWITCH_THREAD(F, ...)      \
   switch (cl) {                               \
@@ -911,8 +966,6 @@ static bool wave_per_block(int L, int nblocks) { return L >= 4 || (L == 3 && nbl
     case 4: F<1, 0>(__VA_ARGS__); break;      \
     case 5: F<1, 1>(__VA_ARGS__); break;      \
     case 8: F<2, 0>(__VA_ARGS__); break;      \
-    case 9: F<2, 1>(__VA_ARGS__); break;      \
-    case 12: F<3, 0>(__VA_ARGS__); break;     \
     default: break;                           \
   }
 #define PWDF_CLASS_SWITCH_WAVE(F, ...)        \
@@ -1082,8 +1135,8 @@ static ClassTab pair_class_tab(const Dev &d) {
     for (int lb = 0; lb <= la; ++lb) {
       const int cl = la * 4 + lb, nb = d.cls_b1[cl] - d.cls_b0[cl];
       if (nb <= 0) continue;
-      const bool wave = wave_per_block(la + lb, nb);
-      add_entry(t, cl, wave ? 1 : 0, 0, wave ? nb : (nb + 63) / 64);
+      const int wave = wave_per_block(la + lb) ? 1 : 0;
+      add_entry(t, cl, wave, 0, wave ? nb : (nb + 63) / 64);
     }
   return t;
 }
