@@ -25,6 +25,8 @@
 // shift-term recurrence.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "kernel_common.h"
 #include "kernels.h"
 
@@ -181,13 +183,71 @@ struct RhoTile {
   static constexpr int TP = NT <= 20 ? 64 : 32;
 };
 
+// Contributions of NP pairs (LDS records r[p]: PairHot then the NT coefficients)
+// to the SEG points of one segment.
+template <int L, int SEG, int NP>
+__device__ __forceinline__ void rho_pairs(const double *const (&r)[NP], const SegDesc &sd,
+                                          const double (&mv)[L + 1], const double (&mw)[L + 1],
+                                          double (&accr)[SEG], double (&acci)[SEG]) {
+  constexpr int NT = nherm(L);
+  constexpr Monos<L> MT{};
+  const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
+  double cr[NP][L + 1], ci[NP][L + 1], Sr[NP], Si[NP], Rr[NP], Ri[NP], q[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const double inv4p = r[p][0], fu = r[p][1], fv = r[p][2], fw = r[p][3];
+    const double *d = r[p] + 8;
+#pragma unroll
+    for (int a = 0; a <= L; ++a) cr[p][a] = ci[p][a] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      const int a = MT.u[k], b = MT.v[k], c = MT.w[k];
+      const double t = d[k] * (mv[b] * mw[c]);
+      if ((a + b + c) & 1)
+        ci[p][a] += t;
+      else
+        cr[p][a] += t;
+    }
+    const double e0 = exp(-sd.gq0 * inv4p);
+    const double eR = exp(-sd.dg0 * inv4p);
+    double ph = fma(nu0, fu, fma(nv, fv, nw * fw));
+    ph -= rint(ph);
+    double sn, cs;
+    sincospi(2.0 * ph, &sn, &cs);
+    Sr[p] = e0 * cs;
+    Si[p] = -e0 * sn;
+    Rr[p] = eR * r[p][4];
+    Ri[p] = eR * r[p][5];
+    q[p] = r[p][6];
+  }
+#pragma unroll
+  for (int s = 0; s < SEG; ++s) {
+    const double n = nu0 + s;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      double Pr = cr[p][L], Pi = ci[p][L];
+#pragma unroll
+      for (int a = L - 1; a >= 0; --a) {
+        Pr = fma(Pr, n, cr[p][a]);
+        Pi = fma(Pi, n, ci[p][a]);
+      }
+      accr[s] = fma(Sr[p], Pr, fma(-Si[p], Pi, accr[s]));
+      acci[s] = fma(Sr[p], Pi, fma(Si[p], Pr, acci[s]));
+      const double tr = fma(Sr[p], Rr[p], -Si[p] * Ri[p]);
+      Si[p] = fma(Sr[p], Ri[p], Si[p] * Rr[p]);
+      Sr[p] = tr;
+      Rr[p] *= q[p];
+      Ri[p] *= q[p];
+    }
+  }
+}
+
 template <int L, int SEG, int W>
 __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int dm, double *__restrict__ sp,
                                           double2 *__restrict__ red) {
   constexpr int NT = nherm(L);
   constexpr int REC = RhoTile<L>::REC;
   constexpr int TP = RhoTile<L>::TP;
-  constexpr Monos<L> MT{};
   const SegDesc *__restrict__ segs = dv.segs;
   const PairHot *__restrict__ hot = dv.hot;
   const double *__restrict__ dhat = dv.dhat;
@@ -213,7 +273,6 @@ __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int
 #pragma unroll
   for (int s = 0; s < SEG; ++s) accr[s] = acci[s] = 0.0;
   const double *dbase = dhat + (size_t)dm * dhat_size + cls_off;
-  const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
   for (int t0 = p0; t0 < p1; t0 += TP) {
     const int nt = min(TP, p1 - t0);
     __syncthreads();
@@ -224,46 +283,8 @@ __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int
     }
     __syncthreads();
     for (int j = w; j < nt; j += W) {
-      const double *r = sp + j * REC;
-      const double inv4p = r[0], fu = r[1], fv = r[2], fw = r[3], cu = r[4], su = r[5], q = r[6];
-      const double *d = r + 8;
-      double cr[L + 1], ci[L + 1];
-#pragma unroll
-      for (int a = 0; a <= L; ++a) cr[a] = ci[a] = 0.0;
-#pragma unroll
-      for (int k = 0; k < NT; ++k) {
-        const int a = MT.u[k], b = MT.v[k], c = MT.w[k];
-        const double t = d[k] * (mv[b] * mw[c]);
-        if ((a + b + c) & 1)
-          ci[a] += t;
-        else
-          cr[a] += t;
-      }
-      const double e0 = exp(-sd.gq0 * inv4p);
-      const double eR = exp(-sd.dg0 * inv4p);
-      double ph = fma(nu0, fu, fma(nv, fv, nw * fw));
-      ph -= rint(ph);
-      double sn, cs;
-      sincospi(2.0 * ph, &sn, &cs);
-      double Sr = e0 * cs, Si = -e0 * sn;
-      double Rr = eR * cu, Ri = eR * su;
-#pragma unroll
-      for (int s = 0; s < SEG; ++s) {
-        const double n = nu0 + s;
-        double Pr = cr[L], Pi = ci[L];
-#pragma unroll
-        for (int a = L - 1; a >= 0; --a) {
-          Pr = fma(Pr, n, cr[a]);
-          Pi = fma(Pi, n, ci[a]);
-        }
-        accr[s] = fma(Sr, Pr, fma(-Si, Pi, accr[s]));
-        acci[s] = fma(Sr, Pi, fma(Si, Pr, acci[s]));
-        const double tr = fma(Sr, Rr, -Si * Ri);
-        Si = fma(Sr, Ri, Si * Rr);
-        Sr = tr;
-        Rr *= q;
-        Ri *= q;
-      }
+      const double *rr[1] = {sp + j * REC};
+      rho_pairs<L, SEG, 1>(rr, sd, mv, mw, accr, acci);
     }
   }
   if (W > 1) {
@@ -390,6 +411,13 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
 #pragma unroll
   for (int k = 0; k < NT; ++k) y[k] = 0.0;
   const double2 *V = Vc + (size_t)dm * nslot;
+  // S, R of the walk; a segment that continues the previous one on the same line
+  // (same n_v, n_w, n_u0 = previous n_u0 + SEG) starts from where the recurrence
+  // stopped, so only the first segment of each line costs the exponentials and
+  // the sincos (the test is wave-uniform: segments come from LDS)
+  double Sr = 0.0, Si = 0.0, Rr = 0.0, Ri = 0.0;
+  int pnv = INT_MIN, pnw = INT_MIN, pnext = INT_MIN;
+  const double q = h.q;
   for (int t0 = s0; t0 < s1; t0 += TS) {
     const int nt = min(TS, s1 - t0);
     __syncthreads();
@@ -399,15 +427,21 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
     for (int j = 0; j < nt; ++j) {
       const SegDesc sd = ss[j];
       const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
-      const double e0 = exp(-sd.gq0 * h.inv4p);
-      const double eR = exp(-sd.dg0 * h.inv4p);
-      double ph = fma(nu0, h.fu, fma(nv, h.fv, nw * h.fw));
-      ph -= rint(ph);
-      double sn, cs;
-      sincospi(2.0 * ph, &sn, &cs);
-      double Sr = e0 * cs, Si = -e0 * sn;
-      double Rr = eR * h.cu, Ri = eR * h.su;
-      const double q = h.q;
+      if (!(sd.nv == pnv && sd.nw == pnw && sd.nu0 == pnext)) {
+        const double e0 = exp(-sd.gq0 * h.inv4p);
+        const double eR = exp(-sd.dg0 * h.inv4p);
+        double ph = fma(nu0, h.fu, fma(nv, h.fv, nw * h.fw));
+        ph -= rint(ph);
+        double sn, cs;
+        sincospi(2.0 * ph, &sn, &cs);
+        Sr = e0 * cs;
+        Si = -e0 * sn;
+        Rr = eR * h.cu;
+        Ri = eR * h.su;
+      }
+      pnv = sd.nv;
+      pnw = sd.nw;
+      pnext = sd.nu0 + SEG;
       double mr[L + 1], mi[L + 1];
 #pragma unroll
       for (int a = 0; a <= L; ++a) mr[a] = mi[a] = 0.0;
