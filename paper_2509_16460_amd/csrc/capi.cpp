@@ -131,9 +131,13 @@ void drop_graph(pwdf_ctx *c) {
 // Per pair and point the cost is about 2L + 10 operations plus the segment start
 // (two exponentials, one sincos, the NT coefficients) spread over SEG points.
 // The tune multipliers scale the chunk counts per class.
-void choose_shapes(const Plan &p, Dev &d, const Tune &tn) {
+void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
   const int SEG = p.seg_len;
   const double target = 4096.0;
+  // the low-L classes share S across d.ndb densities per block (at most 32 / SEG,
+  // chosen at launch); chunk counts are those of one density block (a batch
+  // adds blocks along the density axis of the grid)
+  d.ndb = max_ndm >= 4 ? 4 : (max_ndm >= 2 ? 2 : 1);
   d.rho_bs = 256;  // 64 segments x 4 waves sharing them
   double wsumR = 0.0, wsumJ = 0.0, wR[kMaxLsum + 1], wJ[kMaxLsum + 1];
   for (int L = 0; L <= kMaxLsum; ++L) {
@@ -241,7 +245,7 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
     d.ncolsW = d.ncols32[lmax];
     d.d32_off[kMaxLsum] = off;
   }
-  choose_shapes(p, d, tn);
+  choose_shapes(p, d, tn, c->max_ndm);
 
   hipError_t e;
 #define UP(vec, field) \

@@ -68,6 +68,7 @@ struct Dev {
   int nblocks;
   const int *atom_off, *atom_ent;
   // launch shapes
+  int ndb;  // densities per block of the low-L pair-G launches (1, 2 or 4)
   int rho_bs;
   int rho_chunks[kMaxLsum + 1], rho_ppc[kMaxLsum + 1], rho_row0[kMaxLsum + 1];
   int nrows;

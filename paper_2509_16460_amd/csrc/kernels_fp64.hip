@@ -25,6 +25,7 @@
 // shift-term recurrence.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 
 #include "kernel_common.h"
@@ -183,70 +184,70 @@ struct RhoTile {
   static constexpr int TP = NT <= 20 ? 64 : 32;
 };
 
-// Contributions of NP pairs (LDS records r[p]: PairHot then the NT coefficients)
-// to the SEG points of one segment.
-template <int L, int SEG, int NP>
-__device__ __forceinline__ void rho_pairs(const double *const (&r)[NP], const SegDesc &sd,
-                                          const double (&mv)[L + 1], const double (&mw)[L + 1],
-                                          double (&accr)[SEG], double (&acci)[SEG]) {
+// Contributions of one pair (LDS record r: PairHot, then NT coefficients for each
+// of NDB densities) to the SEG points of one segment.  The Gaussian/phase factor
+// S is generated once and shared by the densities; each density keeps its own
+// accumulators, filled in the same pair order as a one-density call.
+template <int L, int SEG, int NDB>
+__device__ __forceinline__ void rho_pair(const double *__restrict__ r, const SegDesc &sd, const double (&mv)[L + 1],
+                                         const double (&mw)[L + 1], double (&accr)[NDB][SEG],
+                                         double (&acci)[NDB][SEG]) {
   constexpr int NT = nherm(L);
   constexpr Monos<L> MT{};
   const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
-  double cr[NP][L + 1], ci[NP][L + 1], Sr[NP], Si[NP], Rr[NP], Ri[NP], q[NP];
+  const double inv4p = r[0], fu = r[1], fv = r[2], fw = r[3];
+  double cr[NDB][L + 1], ci[NDB][L + 1];
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    const double inv4p = r[p][0], fu = r[p][1], fv = r[p][2], fw = r[p][3];
-    const double *d = r[p] + 8;
+  for (int b = 0; b < NDB; ++b) {
+    const double *d = r + 8 + b * NT;
 #pragma unroll
-    for (int a = 0; a <= L; ++a) cr[p][a] = ci[p][a] = 0.0;
+    for (int a = 0; a <= L; ++a) cr[b][a] = ci[b][a] = 0.0;
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
-      const int a = MT.u[k], b = MT.v[k], c = MT.w[k];
-      const double t = d[k] * (mv[b] * mw[c]);
-      if ((a + b + c) & 1)
-        ci[p][a] += t;
+      const int a = MT.u[k], bb = MT.v[k], c = MT.w[k];
+      const double t = d[k] * (mv[bb] * mw[c]);
+      if ((a + bb + c) & 1)
+        ci[b][a] += t;
       else
-        cr[p][a] += t;
+        cr[b][a] += t;
     }
-    const double e0 = exp(-sd.gq0 * inv4p);
-    const double eR = exp(-sd.dg0 * inv4p);
-    double ph = fma(nu0, fu, fma(nv, fv, nw * fw));
-    ph -= rint(ph);
-    double sn, cs;
-    sincospi(2.0 * ph, &sn, &cs);
-    Sr[p] = e0 * cs;
-    Si[p] = -e0 * sn;
-    Rr[p] = eR * r[p][4];
-    Ri[p] = eR * r[p][5];
-    q[p] = r[p][6];
   }
+  const double e0 = exp(-sd.gq0 * inv4p);
+  const double eR = exp(-sd.dg0 * inv4p);
+  double ph = fma(nu0, fu, fma(nv, fv, nw * fw));
+  ph -= rint(ph);
+  double sn, cs;
+  sincospi(2.0 * ph, &sn, &cs);
+  double Sr = e0 * cs, Si = -e0 * sn;
+  double Rr = eR * r[4], Ri = eR * r[5];
+  const double q = r[6];
 #pragma unroll
   for (int s = 0; s < SEG; ++s) {
     const double n = nu0 + s;
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      double Pr = cr[p][L], Pi = ci[p][L];
+    for (int b = 0; b < NDB; ++b) {
+      double Pr = cr[b][L], Pi = ci[b][L];
 #pragma unroll
       for (int a = L - 1; a >= 0; --a) {
-        Pr = fma(Pr, n, cr[p][a]);
-        Pi = fma(Pi, n, ci[p][a]);
+        Pr = fma(Pr, n, cr[b][a]);
+        Pi = fma(Pi, n, ci[b][a]);
       }
-      accr[s] = fma(Sr[p], Pr, fma(-Si[p], Pi, accr[s]));
-      acci[s] = fma(Sr[p], Pi, fma(Si[p], Pr, acci[s]));
-      const double tr = fma(Sr[p], Rr[p], -Si[p] * Ri[p]);
-      Si[p] = fma(Sr[p], Ri[p], Si[p] * Rr[p]);
-      Sr[p] = tr;
-      Rr[p] *= q[p];
-      Ri[p] *= q[p];
+      accr[b][s] = fma(Sr, Pr, fma(-Si, Pi, accr[b][s]));
+      acci[b][s] = fma(Sr, Pi, fma(Si, Pr, acci[b][s]));
     }
+    const double tr = fma(Sr, Rr, -Si * Ri);
+    Si = fma(Sr, Ri, Si * Rr);
+    Sr = tr;
+    Rr *= q;
+    Ri *= q;
   }
 }
 
-template <int L, int SEG, int W>
-__device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int dm, double *__restrict__ sp,
+template <int L, int SEG, int W, int NDB>
+__device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int db, int ndm, double *__restrict__ sp,
                                           double2 *__restrict__ red) {
   constexpr int NT = nherm(L);
-  constexpr int REC = RhoTile<L>::REC;
+  constexpr int REC = 8 + NT * NDB;
   constexpr int TP = RhoTile<L>::TP;
   const SegDesc *__restrict__ segs = dv.segs;
   const PairHot *__restrict__ hot = dv.hot;
@@ -269,44 +270,62 @@ __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int
     mv[b] = mv[b - 1] * sd.nv;
     mw[b] = mw[b - 1] * sd.nw;
   }
-  double accr[SEG], acci[SEG];
+  double accr[NDB][SEG], acci[NDB][SEG];
 #pragma unroll
-  for (int s = 0; s < SEG; ++s) accr[s] = acci[s] = 0.0;
-  const double *dbase = dhat + (size_t)dm * dhat_size + cls_off;
+  for (int b = 0; b < NDB; ++b)
+#pragma unroll
+    for (int s = 0; s < SEG; ++s) accr[b][s] = acci[b][s] = 0.0;
+  const int dm0 = db * NDB;
   for (int t0 = p0; t0 < p1; t0 += TP) {
     const int nt = min(TP, p1 - t0);
     __syncthreads();
+    // pair records: PairHot, then the coefficients of densities dm0 .. dm0+NDB-1
+    // (zeros past ndm)
     for (int i = tid; i < nt * REC; i += 64 * W) {
       const int pi = i / REC, f = i - pi * REC;
-      sp[i] = f < 8 ? reinterpret_cast<const double *>(hot + t0 + pi)[f]
-                    : dbase[(size_t)(t0 + pi - Lp0) * NT + (f - 8)];
-    }
-    __syncthreads();
-    for (int j = w; j < nt; j += W) {
-      const double *rr[1] = {sp + j * REC};
-      rho_pairs<L, SEG, 1>(rr, sd, mv, mw, accr, acci);
-    }
-  }
-  if (W > 1) {
-    if (w > 0) {
-#pragma unroll
-      for (int s = 0; s < SEG; ++s) red[((w - 1) * SEG + s) * 64 + lane] = make_double2(accr[s], acci[s]);
-    }
-    __syncthreads();
-    if (w > 0) return;
-#pragma unroll
-    for (int v = 1; v < W; ++v)
-#pragma unroll
-      for (int s = 0; s < SEG; ++s) {
-        const double2 x = red[((v - 1) * SEG + s) * 64 + lane];
-        accr[s] += x.x;
-        acci[s] += x.y;
+      double v;
+      if (f < 8) {
+        v = reinterpret_cast<const double *>(hot + t0 + pi)[f];
+      } else {
+        const int b = (f - 8) / NT, k = (f - 8) - b * NT;
+        v = dm0 + b < ndm ? dhat[(size_t)(dm0 + b) * dhat_size + cls_off + (size_t)(t0 + pi - Lp0) * NT + k] : 0.0;
       }
+      sp[i] = v;
+    }
+    __syncthreads();
+    for (int j = w; j < nt; j += W) rho_pair<L, SEG, NDB>(sp + j * REC, sd, mv, mw, accr, acci);
+  }
+  // the W waves' partial sums are added in LDS in fixed order, one density at a time
+  if (W > 1) {
+#pragma unroll
+    for (int b = 0; b < NDB; ++b) {
+      if (w > 0) {
+#pragma unroll
+        for (int s = 0; s < SEG; ++s) red[((w - 1) * SEG + s) * 64 + lane] = make_double2(accr[b][s], acci[b][s]);
+      }
+      __syncthreads();
+      if (w == 0) {
+#pragma unroll
+        for (int v = 1; v < W; ++v)
+#pragma unroll
+          for (int s = 0; s < SEG; ++s) {
+            const double2 x = red[((v - 1) * SEG + s) * 64 + lane];
+            accr[b][s] += x.x;
+            acci[b][s] += x.y;
+          }
+      }
+      __syncthreads();
+    }
+    if (w > 0) return;
   }
   if (!active) return;
-  double2 *out = part + ((size_t)dm * nrows + row0 + chunk) * nslot + (size_t)seg * SEG;
 #pragma unroll
-  for (int s = 0; s < SEG; ++s) out[s] = make_double2(accr[s], acci[s]);
+  for (int b = 0; b < NDB; ++b) {
+    if (dm0 + b >= ndm) break;
+    double2 *out = part + ((size_t)(dm0 + b) * nrows + row0 + chunk) * nslot + (size_t)seg * SEG;
+#pragma unroll
+    for (int s = 0; s < SEG; ++s) out[s] = make_double2(accr[b][s], acci[b][s]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -391,12 +410,14 @@ __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ Epart
 // ---------------------------------------------------------------------------
 constexpr int kJTile = 32;  // segments per LDS tile of the J pass
 
-template <int L, int SEG>
+// J moments of one pair per lane for NDB densities (dm0 .. dm0+NDB-1, those past
+// ndm skipped): S is generated once per point and shared by the densities.
+template <int L, int SEG, int NDB>
 __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, int nseg, int segs_per_chunk,
                                             const double2 *__restrict__ Vc, int nslot,
                                             const PairHot *__restrict__ hot, int Lp0, int Lp1,
                                             double *__restrict__ yhat, int64_t yhat_size, int64_t ycls_off, int pb,
-                                            int chunk, int dm, SegDesc *__restrict__ ss,
+                                            int chunk, int dm0, int ndm, SegDesc *__restrict__ ss,
                                             double2 *__restrict__ sv) {
   constexpr int NT = nherm(L);
   constexpr int TS = kJTile;
@@ -407,10 +428,11 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
   const PairHot h = hot[Lp0 + (active ? pl : 0)];
   const int s0 = chunk * segs_per_chunk;
   const int s1 = min(nseg, s0 + segs_per_chunk);
-  double y[NT];
+  double y[NDB][NT];
 #pragma unroll
-  for (int k = 0; k < NT; ++k) y[k] = 0.0;
-  const double2 *V = Vc + (size_t)dm * nslot;
+  for (int b = 0; b < NDB; ++b)
+#pragma unroll
+    for (int k = 0; k < NT; ++k) y[b][k] = 0.0;
   // S, R of the walk; a segment that continues the previous one on the same line
   // (same n_v, n_w, n_u0 = previous n_u0 + SEG) starts from where the recurrence
   // stopped, so only the first segment of each line costs the exponentials and
@@ -421,7 +443,12 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
   for (int t0 = s0; t0 < s1; t0 += TS) {
     const int nt = min(TS, s1 - t0);
     __syncthreads();
-    for (int i = threadIdx.x; i < nt * SEG; i += blockDim.x) sv[i] = V[(size_t)t0 * SEG + i];
+    // conj V of the tile's slots for each density (zeros past ndm), [b][slot]
+    for (int i = threadIdx.x; i < NDB * nt * SEG; i += blockDim.x) {
+      const int b = i / (nt * SEG), r = i - b * (nt * SEG);
+      sv[b * TS * SEG + r] =
+          dm0 + b < ndm ? Vc[(size_t)(dm0 + b) * nslot + (size_t)t0 * SEG + r] : make_double2(0.0, 0.0);
+    }
     if ((int)threadIdx.x < nt) ss[threadIdx.x] = segs[t0 + threadIdx.x];
     __syncthreads();
     for (int j = 0; j < nt; ++j) {
@@ -442,21 +469,26 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
       pnv = sd.nv;
       pnw = sd.nw;
       pnext = sd.nu0 + SEG;
-      double mr[L + 1], mi[L + 1];
+      double mr[NDB][L + 1], mi[NDB][L + 1];
 #pragma unroll
-      for (int a = 0; a <= L; ++a) mr[a] = mi[a] = 0.0;
+      for (int b = 0; b < NDB; ++b)
+#pragma unroll
+        for (int a = 0; a <= L; ++a) mr[b][a] = mi[b][a] = 0.0;
 #pragma unroll
       for (int s = 0; s < SEG; ++s) {
-        const double2 v = sv[j * SEG + s];
-        const double Ur = fma(v.x, Sr, -v.y * Si);
-        const double Ui = fma(v.x, Si, v.y * Sr);
         const double n = nu0 + s;
-        double pw = 1.0;
 #pragma unroll
-        for (int a = 0; a <= L; ++a) {
-          mr[a] = fma(pw, Ur, mr[a]);
-          mi[a] = fma(pw, Ui, mi[a]);
-          pw *= n;
+        for (int b = 0; b < NDB; ++b) {
+          const double2 v = sv[b * TS * SEG + j * SEG + s];
+          const double Ur = fma(v.x, Sr, -v.y * Si);
+          const double Ui = fma(v.x, Si, v.y * Sr);
+          double pw = 1.0;
+#pragma unroll
+          for (int a = 0; a <= L; ++a) {
+            mr[b][a] = fma(pw, Ur, mr[b][a]);
+            mi[b][a] = fma(pw, Ui, mi[b][a]);
+            pw *= n;
+          }
         }
         const double tr = fma(Sr, Rr, -Si * Ri);
         Si = fma(Sr, Ri, Si * Rr);
@@ -467,22 +499,28 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
       double mv[L + 1], mw[L + 1];
       mv[0] = mw[0] = 1.0;
 #pragma unroll
-      for (int b = 1; b <= L; ++b) {
-        mv[b] = mv[b - 1] * nv;
-        mw[b] = mw[b - 1] * nw;
+      for (int c = 1; c <= L; ++c) {
+        mv[c] = mv[c - 1] * nv;
+        mw[c] = mw[c - 1] * nw;
       }
 #pragma unroll
-      for (int k = 0; k < NT; ++k) {
-        const int a = MT.u[k], b = MT.v[k], c = MT.w[k];
-        const double m = ((a + b + c) & 1) ? mi[a] : mr[a];
-        y[k] = fma(mv[b] * mw[c], m, y[k]);
-      }
+      for (int b = 0; b < NDB; ++b)
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+          const int a = MT.u[k], bb = MT.v[k], c = MT.w[k];
+          const double m = ((a + bb + c) & 1) ? mi[b][a] : mr[b][a];
+          y[b][k] = fma(mv[bb] * mw[c], m, y[b][k]);
+        }
     }
   }
   if (!active) return;
-  double *out = yhat + (size_t)dm * yhat_size + ycls_off + (size_t)chunk * NT * np + pl;
 #pragma unroll
-  for (int k = 0; k < NT; ++k) out[(size_t)k * np] = y[k];
+  for (int b = 0; b < NDB; ++b) {
+    if (dm0 + b >= ndm) break;
+    double *out = yhat + (size_t)(dm0 + b) * yhat_size + ycls_off + (size_t)chunk * NT * np + pl;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) out[(size_t)k * np] = y[b][k];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1043,28 +1081,33 @@ __global__ __launch_bounds__(64) void k_back_all(const Dev dv, const ClassTab ta
   }
 }
 
-template <int L>
+template <int L, int NDB>
 constexpr int rho_sp_doubles() {
-  return RhoTile<L>::TP * RhoTile<L>::REC;
+  return RhoTile<L>::TP * (8 + nherm(L) * NDB);
 }
-constexpr int kRhoSp = cmax(cmax(cmax(rho_sp_doubles<0>(), rho_sp_doubles<1>()), cmax(rho_sp_doubles<2>(), rho_sp_doubles<3>())),
-                            cmax(cmax(rho_sp_doubles<4>(), rho_sp_doubles<5>()), rho_sp_doubles<6>()));
+// LDS of the fused rho launch: pair records of the largest class of the group
+template <int L0, int L1, int NDB>
+constexpr int rho_sp_max() {
+  return L0 > L1 ? 0 : cmax(rho_sp_doubles<L0, NDB>(), rho_sp_max<(L0 < L1 ? L0 + 1 : L1 + 1), L1, NDB>());
+}
 
-// rho of the classes L in [L0, L1] (low and high groups as for the J pass: the
-// Horner coefficients and monomials of class L set the register footprint).
-template <int SEG, int L0, int L1>
-__global__ __launch_bounds__(256) void k_rho_all(const Dev dv, const ClassTab tab) {
+// rho of the classes L in [L0, L1] for NDB densities per block (blockIdx.y is the
+// density block).  Low and high groups as for the J pass: the Horner
+// coefficients and monomials of class L set the register footprint.
+template <int SEG, int L0, int L1, int NDB>
+__global__ __launch_bounds__(256) void k_rho_all(const Dev dv, const ClassTab tab, int ndm) {
   constexpr int W = 4;
-  __shared__ double sp[kRhoSp];
+  __shared__ double sp[rho_sp_max<L0, L1, NDB>()];
   __shared__ double2 red[(W - 1) * 64 * SEG];
   const int i = tab_entry(tab, blockIdx.x);
   const int local = blockIdx.x - tab.first[i];
   const int nsg = tab.gx[i];
   const int sgi = local % nsg, chunk = local / nsg;
-  const int dm = blockIdx.y;
-#define PWDF_RCASE(LL) \
-  case LL:             \
-    if (LL >= L0 && LL <= L1) rho_block<(LL >= L0 && LL <= L1 ? LL : L0), SEG, W>(dv, sgi, chunk, dm, sp, red); \
+  const int db = blockIdx.y;
+#define PWDF_RCASE(LL)                                                                                      \
+  case LL:                                                                                                  \
+    if (LL >= L0 && LL <= L1)                                                                               \
+      rho_block<(LL >= L0 && LL <= L1 ? LL : L0), SEG, W, NDB>(dv, sgi, chunk, db, ndm, sp, red);           \
     break;
   switch (tab.cls[i]) {
     PWDF_RCASE(0)
@@ -1080,27 +1123,28 @@ __global__ __launch_bounds__(256) void k_rho_all(const Dev dv, const ClassTab ta
 }
 
 // J moments of the classes L in [L0, L1] (degree L + DEG: DEG = 1 gives the force
-// moments of the class-L pairs).  Classes are split into a low and a high group
-// because the moment count NT(L) sets the register footprint of the launch.
-template <int SEG, int DEG, int L0, int L1>
-__global__ __launch_bounds__(256) void k_jpass_all(const Dev dv, const ClassTab tab) {
+// moments of the class-L pairs), NDB densities per block (blockIdx.y).  Classes
+// are split into a low and a high group because the moment count NT(L) sets the
+// register footprint of the launch.
+template <int SEG, int DEG, int L0, int L1, int NDB>
+__global__ __launch_bounds__(256) void k_jpass_all(const Dev dv, const ClassTab tab, int ndm) {
   __shared__ SegDesc ss[kJTile];
-  __shared__ double2 sv[kJTile * SEG];
+  __shared__ double2 sv[NDB * kJTile * SEG];
   const int i = tab_entry(tab, blockIdx.x);
   const int local = blockIdx.x - tab.first[i];
   const int npb = tab.gx[i];
   const int pb = local % npb, chunk = local / npb;
-  const int dm = blockIdx.y;
+  const int dm0 = blockIdx.y * NDB;
   const int L = tab.cls[i];
   double *y = DEG ? dv.yF : dv.yhat;
   const int64_t ysz = DEG ? dv.yF_size : dv.yhat_size;
   const int64_t yoff = DEG ? dv.yF_off[L] : dv.yhat_off[L];
-#define PWDF_JCASE(LL)                                                                                          \
-  case LL:                                                                                                      \
-    if (LL >= L0 && LL <= L1)                                                                                   \
-      jpass_block<(LL >= L0 && LL <= L1 ? LL + DEG : 0), SEG>(dv.segs, dv.nseg, dv.j_spc[LL], dv.Vc, dv.nslot, \
-                                                                dv.hot, dv.L_p0[LL], dv.L_p1[LL], y, ysz, yoff, pb, \
-                                                                chunk, dm, ss, sv);                             \
+#define PWDF_JCASE(LL)                                                                                         \
+  case LL:                                                                                                     \
+    if (LL >= L0 && LL <= L1)                                                                                  \
+      jpass_block<(LL >= L0 && LL <= L1 ? LL + DEG : 0), SEG, NDB>(dv.segs, dv.nseg, dv.j_spc[LL], dv.Vc,      \
+                                                                     dv.nslot, dv.hot, dv.L_p0[LL], dv.L_p1[LL], \
+                                                                     y, ysz, yoff, pb, chunk, dm0, ndm, ss, sv); \
     break;
   switch (L) {
     PWDF_JCASE(0)
@@ -1194,6 +1238,25 @@ hipError_t launch_back_all(const Dev &d, int ndm, hipStream_t st) {
 // Class groups of the pair-G passes: [0, kJSplit] and [kJSplit + 1, 6].
 constexpr int kJSplit = 2;
 
+// Densities per block of the low class group (S shared by them): d.ndb, at most
+// 32 / SEG so that the per-density accumulators stay within the register file.
+// The high group takes one density per block.
+static int group_ndb(const Dev &d, int group) {
+  if (group != 0) return 1;
+  return std::min(d.ndb, 32 / d.seg_len);
+}
+
+template <int SEG, int NDB>
+static hipError_t rho_launch(const Dev &d, const ClassTab &t, int ndm, hipStream_t st, int group) {
+  dim3 grid((unsigned)t.first[t.n], (unsigned)((ndm + NDB - 1) / NDB)), block(64, 4);
+  if (group == 0)
+    hipLaunchKernelGGL((k_rho_all<SEG, 0, kJSplit, NDB>), grid, block, 0, st, d, t, ndm);
+  else
+    hipLaunchKernelGGL((k_rho_all<SEG, kJSplit + 1, 2 * kMaxL, 1>), grid, block, 0, st, d, t, ndm);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
 template <int SEG>
 static hipError_t rho_group(const Dev &d, int ndm, hipStream_t st, int group) {
   ClassTab t{};
@@ -1202,13 +1265,14 @@ static hipError_t rho_group(const Dev &d, int ndm, hipStream_t st, int group) {
   for (int L = La; L <= Lb; ++L)
     if (d.L_p1[L] > d.L_p0[L]) add_entry(t, L, 0, nsg, nsg * d.rho_chunks[L]);
   if (t.n == 0) return hipSuccess;
-  dim3 grid((unsigned)t.first[t.n], ndm), block(64, 4);
-  if (group == 0)
-    hipLaunchKernelGGL((k_rho_all<SEG, 0, kJSplit>), grid, block, 0, st, d, t);
-  else
-    hipLaunchKernelGGL((k_rho_all<SEG, kJSplit + 1, 2 * kMaxL>), grid, block, 0, st, d, t);
-  PWDF_CHECK_LAUNCH();
-  return hipSuccess;
+  switch (group_ndb(d, group)) {
+    case 1: return rho_launch<SEG, 1>(d, t, ndm, st, group);
+    case 2: return rho_launch<SEG, 2>(d, t, ndm, st, group);
+    case 4:
+      if constexpr (SEG <= 8) return rho_launch<SEG, 4>(d, t, ndm, st, group);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_rho_group(const Dev &d, int group, int ndm, hipStream_t st) {
@@ -1218,6 +1282,17 @@ hipError_t launch_rho_group(const Dev &d, int group, int ndm, hipStream_t st) {
     case 16: return rho_group<16>(d, ndm, st, group);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int SEG, int DEG, int NDB>
+static hipError_t jpass_launch(const Dev &d, const ClassTab &t, int ndm, hipStream_t st, int group) {
+  dim3 grid((unsigned)t.first[t.n], (unsigned)((ndm + NDB - 1) / NDB));
+  if (group == 0)
+    hipLaunchKernelGGL((k_jpass_all<SEG, DEG, 0, kJSplit, NDB>), grid, dim3(256), 0, st, d, t, ndm);
+  else
+    hipLaunchKernelGGL((k_jpass_all<SEG, DEG, kJSplit + 1, 2 * kMaxL, 1>), grid, dim3(256), 0, st, d, t, ndm);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
 }
 
 template <int SEG, int DEG>
@@ -1231,13 +1306,14 @@ static hipError_t jpass_groups(const Dev &d, int ndm, hipStream_t st, int group)
     add_entry(t, L, 0, npb, npb * d.j_chunks[L]);
   }
   if (t.n == 0) return hipSuccess;
-  dim3 grid((unsigned)t.first[t.n], ndm);
-  if (group == 0)
-    hipLaunchKernelGGL((k_jpass_all<SEG, DEG, 0, kJSplit>), grid, dim3(256), 0, st, d, t);
-  else
-    hipLaunchKernelGGL((k_jpass_all<SEG, DEG, kJSplit + 1, 2 * kMaxL>), grid, dim3(256), 0, st, d, t);
-  PWDF_CHECK_LAUNCH();
-  return hipSuccess;
+  switch (group_ndb(d, group)) {
+    case 1: return jpass_launch<SEG, DEG, 1>(d, t, ndm, st, group);
+    case 2: return jpass_launch<SEG, DEG, 2>(d, t, ndm, st, group);
+    case 4:
+      if constexpr (SEG <= 8) return jpass_launch<SEG, DEG, 4>(d, t, ndm, st, group);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_jpass_group(const Dev &d, int group, bool force, int ndm, hipStream_t st) {

@@ -143,3 +143,23 @@ def test_kpoint_config_parity():
     print(f"E_J gpu={E[0]:.15f} oracle={ref['E_G']:.15f}", flush=True)
     assert abs(E[0] - ref["E_G"]) <= E_TOL
     assert np.max(np.abs(J[0] - ref["J"])) <= J_TOL
+
+
+@pytest.mark.parametrize("name", ["spd_k123", "spdf_k311_3atoms"])
+def test_fp64_batch_matches_single(name, oracle_cache):
+    """Six densities in one call (density blocks of 4 in the low-L pair-G kernels
+    and in J(L) -> J(k), the second block partial): every density equals its
+    one-density result bit for bit (same operations in the same order), and the
+    first one meets the FP64 bar against the oracle."""
+    p, D, ref = oracle_of(oracle_cache, name)
+    dens = np.stack([D] + [synth.make_density(p, 700 + i) for i in range(5)])
+    ctx6 = pw().LongRangeJ(p, max_ndm=6)
+    J6, E6 = ctx6.build_j(torch.from_numpy(dens).cuda())
+    ctx1 = pw().LongRangeJ(p, max_ndm=1)
+    for i in range(6):
+        J1, E1 = ctx1.build_j(torch.from_numpy(dens[i:i + 1]).cuda())
+        torch.cuda.synchronize()
+        assert torch.equal(J6[i], J1[0]), f"density {i}: J differs from the one-density call"
+        assert torch.equal(E6[i], E1[0]), f"density {i}: E_J differs from the one-density call"
+    assert abs(float(E6[0].cpu()) - ref["E_G"]) <= E_TOL
+    assert np.max(np.abs(J6[0].cpu().numpy() - ref["J"])) <= J_TOL
