@@ -119,7 +119,9 @@ typedef struct {
  *   prec           PWDF_FP64 or PWDF_FP32_MFMA.
  *   max_ndm        largest ndm accepted by later calls (>= 1).
  *   device         HIP device ordinal.
- * On success *out is a new context (free with pwdf_destroy).
+ * On success *out is a new context (free with pwdf_destroy).  PWDF_EINVAL also
+ * when no G vector lies in the cutoff sphere (0 < |G| <= Gcut); the screened
+ * pair list always holds at least the on-site pairs (K = 1).
  */
 pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const double *xyz,
                         int nshell, const int *shell_atom, const int *shell_l,

@@ -148,7 +148,9 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
     wsumR += wR[L];
     wsumJ += wJ[L];
   }
-  const int rho_waves_per_chunk = ((p.nseg() + 63) / 64) * 4;
+  const int rho_waves_per_chunk = std::max(4, ((p.nseg() + 63) / 64) * 4);
+  wsumR = std::max(wsumR, 1.0);  // no pairs: every class is skipped below
+  wsumJ = std::max(wsumJ, 1.0);
   int rows = 0;
   int64_t yoff = 0;
   for (int L = 0; L <= kMaxLsum; ++L) {
@@ -172,8 +174,8 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
     const int jw = (np + 63) / 64;  // active waves per segment chunk
     int jc = (int)std::lround(target * (wJ[L] / wsumJ) * tn.mj[L] / jw);
     jc = std::max(1, std::min(p.nseg(), jc));
-    int spc = (p.nseg() + jc - 1) / jc;
-    jc = (p.nseg() + spc - 1) / spc;
+    int spc = std::max(1, (p.nseg() + jc - 1) / jc);
+    jc = (p.nseg() + spc - 1) / spc;  // 0 when the G set is empty
     d.j_chunks[L] = jc;
     d.j_spc[L] = spc;
     yoff += (int64_t)jc * nherm(L) * np;

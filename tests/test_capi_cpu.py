@@ -69,6 +69,7 @@ def bad(prob, **kw):
     (dict(omega=float("nan")), "PWDF_EINVAL"),
     (dict(eps_pair=0.0), "PWDF_EINVAL"),
     (dict(eps_G=1.5), "PWDF_EINVAL"),
+    (dict(eps_G=0.9999), "PWDF_EINVAL"),  # cutoff sphere holds no G vector
     (dict(kmesh=(0, 1, 1)), "PWDF_EINVAL"),
     (dict(lattice=np.array([[1.0, 0, 0], [2.0, 0, 0], [0, 0, 1.0]])), "PWDF_EINVAL"),
     (dict(shell_l=None), "PWDF_EUNSUPPORTED"),
