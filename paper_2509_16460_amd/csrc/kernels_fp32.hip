@@ -39,13 +39,18 @@ __device__ __forceinline__ double ipow(double x, int e) {
 
 // ---------------------------------------------------------------------------
 // rho, K = pairs.  A workgroup = 4 waves = 64 segments (16 per wave as the MFMA
-// rows); lane (r16 = l%16, g4 = l/16) generates S for segment r16 of its wave and
-// pair g4 of each group of four, for all T points of the segment (one MFMA
-// accumulator tile per point).  One N-tile (16 columns of (k, dm)) at a time;
-// after the pair chunk the FP64 epilogue contracts the columns with n^k
-// (times i for odd |k|) and adds lanes of equal density.
+// rows).  The chunk's pairs are staged in LDS in tiles of kQTile pairs (record
+// and the coefficient columns of the current N-tile group).  Lane
+// (r16 = l%16, g4 = l/16) generates S for segment r16 of its wave and pair g4 of
+// each group of four, for all T points of the segment, once per N-tile group,
+// and feeds NTG N-tiles (16 columns of (k, dm) each) with it: one MFMA
+// accumulator tile per (N-tile, point).  After the chunk the FP64 epilogue
+// contracts each N-tile's columns with n^k (times i for odd |k|) and adds the
+// lanes of equal density.
 // ---------------------------------------------------------------------------
-template <int L, int T>
+constexpr int kQTile = 64;  // pairs per LDS tile of the rho pass
+
+template <int L, int T, int NTG>
 __global__ __launch_bounds__(256) void k_rho_mfma(const SegDesc *__restrict__ segs, int nseg,
                                                   const PairHot *__restrict__ hot, int Lp0, int Lp1, int ppc,
                                                   const float *__restrict__ dh32, int64_t d32_off, int ncols,
@@ -53,7 +58,10 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const SegDesc *__restrict__ se
                                                   int nrows, int nslot) {
   constexpr int NT = nherm(L);
   constexpr Monos<L> MT{};
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ PairHot sh[kQTile];
+  __shared__ float sc[kQTile * NTG * 16];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, g4 = lane >> 4;
   const int chunk = blockIdx.y;
   const int p0 = Lp0 + chunk * ppc, p1 = min(Lp1, p0 + ppc);
@@ -63,84 +71,125 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const SegDesc *__restrict__ se
   const float *dcls = dh32 + d32_off;
   const int ntiles = ncols >> 4;
 
-  double accr[T][4], acci[T][4];
+  // lanes r16 < ndm write density r16 of the wave's rows; each N-tile group adds
+  // its epilogue into the chunk's partial row (same lane, same addresses: no race)
+  double2 *out = part + ((size_t)min(r16, ndm - 1) * nrows + row0 + chunk) * nslot;
+  for (int ng = 0; ng < ntiles; ng += NTG) {
+    const int ntg = min(NTG, ntiles - ng);
+    f4 are[NTG][T], aim[NTG][T];
 #pragma unroll
-  for (int t = 0; t < T; ++t)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) accr[t][i] = acci[t][i] = 0.0;
-
-  for (int nt = 0; nt < ntiles; ++nt) {
-    f4 are[T], aim[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      are[t] = f4{0.f, 0.f, 0.f, 0.f};
-      aim[t] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-    for (int q0 = p0; q0 < p1; q0 += 4) {
-      const int q = q0 + g4;
-      const bool vq = q < p1;
-      const PairHot h = hot[vq ? q : p0];
-      const float b = vq ? dcls[(size_t)(q - Lp0) * ncols + nt * 16 + r16] : 0.f;
-      const double e0 = exp(-sdA.gq0 * h.inv4p);
-      const double eR = exp(-sdA.dg0 * h.inv4p);
-      double ph = fma((double)sdA.nu0, h.fu, fma((double)sdA.nv, h.fv, (double)sdA.nw * h.fw));
-      ph -= rint(ph);
-      double sn, cs;
-      sincospi(2.0 * ph, &sn, &cs);
-      double Sr = e0 * cs, Si = -e0 * sn;
-      double Rr = eR * h.cu, Ri = eR * h.su;
+    for (int n = 0; n < NTG; ++n)
 #pragma unroll
       for (int t = 0; t < T; ++t) {
-        are[t] = mfma4((float)Sr, b, are[t]);
-        aim[t] = mfma4((float)Si, b, aim[t]);
-        const double tr = fma(Sr, Rr, -Si * Ri);
-        Si = fma(Sr, Ri, Si * Rr);
-        Sr = tr;
-        Rr *= h.q;
-        Ri *= h.q;
+        are[n][t] = f4{0.f, 0.f, 0.f, 0.f};
+        aim[n][t] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+    for (int t0 = p0; t0 < p1; t0 += kQTile) {
+      const int nq = min(kQTile, p1 - t0);
+      __syncthreads();
+      for (int i = tid; i < nq; i += 256) sh[i] = hot[t0 + i];
+      // coefficient columns [ng*16, (ng+ntg)*16) of the tile's pairs
+      for (int i = tid; i < nq * NTG * 16; i += 256) {
+        const int q = i / (NTG * 16), c = i - q * (NTG * 16);
+        sc[i] = c < ntg * 16 ? dcls[(size_t)(t0 + q - Lp0) * ncols + ng * 16 + c] : 0.f;
+      }
+      __syncthreads();
+      for (int q0 = 0; q0 < nq; q0 += 4) {
+        const int q = q0 + g4;
+        const bool vq = q < nq;
+        const PairHot h = sh[vq ? q : 0];
+        float Sre[T], Sim[T];
+        {
+          const double e0 = exp(-sdA.gq0 * h.inv4p);
+          const double eR = exp(-sdA.dg0 * h.inv4p);
+          double ph = fma((double)sdA.nu0, h.fu, fma((double)sdA.nv, h.fv, (double)sdA.nw * h.fw));
+          ph -= rint(ph);
+          double sn, cs;
+          sincospi(2.0 * ph, &sn, &cs);
+          double Sr = e0 * cs, Si = -e0 * sn;
+          double Rr = eR * h.cu, Ri = eR * h.su;
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            Sre[t] = (float)Sr;
+            Sim[t] = (float)Si;
+            const double tr = fma(Sr, Rr, -Si * Ri);
+            Si = fma(Sr, Ri, Si * Rr);
+            Sr = tr;
+            Rr *= h.q;
+            Ri *= h.q;
+          }
+        }
+#pragma unroll
+        for (int n = 0; n < NTG; ++n) {
+          if (n < ntg) {
+            const float b = vq ? sc[q * (NTG * 16) + n * 16 + r16] : 0.f;
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+              are[n][t] = mfma4(Sre[t], b, are[n][t]);
+              aim[n][t] = mfma4(Sim[t], b, aim[n][t]);
+            }
+          }
+        }
       }
     }
-    // epilogue of this N-tile: lane holds R[segment 4*g4+i][column r16] at point t
-    const int c = nt * 16 + r16;
-    const int k = c / ndmp;
-    const bool vk = k < NT;
-    const int ka = vk ? MT.u[k] : 0, kb = vk ? MT.v[k] : 0, kc = vk ? MT.w[k] : 0;
+    // epilogue of this N-tile group: lane holds R[segment 4*g4+i][column r16] at point t
+    double accr[T][4], acci[T][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int sr = seg0 + 4 * g4 + i;
-      const SegDesc sd = segs[sr < nseg ? sr : nseg - 1];
-      const double mvw = ipow((double)sd.nv, kb) * ipow((double)sd.nw, kc);
+    for (int t = 0; t < T; ++t)
 #pragma unroll
-      for (int t = 0; t < T; ++t) {
-        const double mono = vk ? ipow((double)(sd.nu0 + t), ka) * mvw : 0.0;
-        // d_k carries sigma_|k| already (real part from even |k|, imaginary from odd):
-        // the column contributes R for even |k| and i R for odd |k|
-        double cr = (double)are[t][i], ci = (double)aim[t][i];
-        if ((ka + kb + kc) & 1) {
-          const double tr = -ci;
-          ci = cr;
-          cr = tr;
+      for (int i = 0; i < 4; ++i) accr[t][i] = acci[t][i] = 0.0;
+#pragma unroll
+    for (int n = 0; n < NTG; ++n) {
+      if (n >= ntg) break;
+      const int c = (ng + n) * 16 + r16;
+      const int k = c / ndmp;
+      const bool vk = k < NT;
+      const int ka = vk ? MT.u[k] : 0, kb = vk ? MT.v[k] : 0, kc = vk ? MT.w[k] : 0;
+      const bool odd = (ka + kb + kc) & 1;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int sr = seg0 + 4 * g4 + i;
+        const SegDesc sd = segs[sr < nseg ? sr : nseg - 1];
+        const double mvw = ipow((double)sd.nv, kb) * ipow((double)sd.nw, kc);
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const double mono = vk ? ipow((double)(sd.nu0 + t), ka) * mvw : 0.0;
+          // d_k carries sigma_|k| already (real part from even |k|, imaginary from odd):
+          // the column contributes R for even |k| and i R for odd |k|
+          double cr = (double)are[n][t][i], ci = (double)aim[n][t][i];
+          if (odd) {
+            const double tr = -ci;
+            ci = cr;
+            cr = tr;
+          }
+          cr *= mono;
+          ci *= mono;
+          for (int off = ndmp; off < 16; off <<= 1) {
+            cr += __shfl_xor(cr, off, 64);
+            ci += __shfl_xor(ci, off, 64);
+          }
+          accr[t][i] += cr;
+          acci[t][i] += ci;
         }
-        cr *= mono;
-        ci *= mono;
-        for (int off = ndmp; off < 16; off <<= 1) {
-          cr += __shfl_xor(cr, off, 64);
-          ci += __shfl_xor(ci, off, 64);
-        }
-        accr[t][i] += cr;
-        acci[t][i] += ci;
       }
     }
-  }
-  // lanes r16 < ndm hold density r16
-  if (r16 >= ndm) return;
-  double2 *out = part + ((size_t)r16 * nrows + row0 + chunk) * nslot;
+    if (r16 < ndm) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int sr = seg0 + 4 * g4 + i;
-    if (sr >= nseg) continue;
+      for (int i = 0; i < 4; ++i) {
+        const int sr = seg0 + 4 * g4 + i;
+        if (sr >= nseg) continue;
 #pragma unroll
-    for (int t = 0; t < T; ++t) out[(size_t)sr * T + t] = make_double2(accr[t][i], acci[t][i]);
+        for (int t = 0; t < T; ++t) {
+          double2 v = make_double2(accr[t][i], acci[t][i]);
+          if (ng > 0) {
+            const double2 o = out[(size_t)sr * T + t];
+            v.x += o.x;
+            v.y += o.y;
+          }
+          out[(size_t)sr * T + t] = v;
+        }
+      }
+    }
   }
 }
 
@@ -266,9 +315,16 @@ static hipError_t rho_mfma_one(const Dev &d, int ndm, hipStream_t st) {
   const int np = d.L_p1[L] - d.L_p0[L];
   if (np <= 0) return hipSuccess;
   dim3 grid((unsigned)((d.nseg + 63) / 64), d.rho_chunks[L]);
-  hipLaunchKernelGGL((k_rho_mfma<L, T>), grid, dim3(256), 0, st, d.segs, d.nseg, d.hot, d.L_p0[L], d.L_p1[L],
-                     d.rho_ppc[L], d.dh32, d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.part, d.rho_row0[L], d.nrows,
-                     d.nslot);
+  // N-tiles per S generation: all of them when there is one, else as many as the
+  // accumulator budget allows
+  if (d.ncols32[L] == 16)
+    hipLaunchKernelGGL((k_rho_mfma<L, T, 1>), grid, dim3(256), 0, st, d.segs, d.nseg, d.hot, d.L_p0[L], d.L_p1[L],
+                       d.rho_ppc[L], d.dh32, d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.part, d.rho_row0[L],
+                       d.nrows, d.nslot);
+  else
+    hipLaunchKernelGGL((k_rho_mfma<L, T, (T <= 4 ? 4 : 2)>), grid, dim3(256), 0, st, d.segs, d.nseg, d.hot, d.L_p0[L],
+                       d.L_p1[L], d.rho_ppc[L], d.dh32, d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.part,
+                       d.rho_row0[L], d.nrows, d.nslot);
   PWDF_CHECK_LAUNCH32();
   return hipSuccess;
 }
