@@ -196,17 +196,22 @@ pwdf_status pwdf_grad(pwdf_ctx *ctx, int ndm, const double *Dk, double *dEdR, do
                       void *stream);
 
 /* Pick launch shapes by timing candidates on the device for ndm densities:
- * first the line-segment length (4, 8, 16 points; 4, 8 for the FP32-MFMA form)
- * by the time of the pair-G passes, then per angular class L a multiplier
- * (1/4 .. 4) of the default number of pair chunks of the rho pass and of
- * segment chunks of the J pass, each class keeping its fastest.  Timing runs on
+ * first the line-segment length (4, 5, 8 or 16 points; 4 or 8 for the FP32-MFMA
+ * form), then a common multiplier (1/2 or 2) of the default number of pair
+ * chunks of the rho pass and of segment chunks of the J pass, both by the wall
+ * time of the pair-G passes with their launches overlapping as in a build.  The
+ * FP32-MFMA form (one launch per angular class L) then lets each class keep the
+ * multiplier (1/4 .. 4) of its shortest launch, and keeps that result only if
+ * it also wins with the launches overlapping.  Timing runs on
  * an internal stream over zero D(L) and does not touch caller buffers.  The
  * device workspaces are rebuilt for the chosen shapes (this call allocates),
  * a cached graph is dropped and profiling counters are reset.  Results of later
  * calls agree with the untuned ones to rounding (summation order changes).
  * cache_path: text file of "key seg_len mrho[0..7] mj[0..7]" lines keyed by
  * arch, precision, nG, pair count, nbf, nk and ndm; an entry found there is
- * applied without timing, a new result is appended.  NULL: no persistence.
+ * applied without timing (PWDF_EINVAL if its segment length is not one listed
+ * above for the context's form), a new result is appended.  NULL: no
+ * persistence.
  * Synchronous. */
 pwdf_status pwdf_autotune(pwdf_ctx *ctx, int ndm, const char *cache_path);
 

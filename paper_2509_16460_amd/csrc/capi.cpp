@@ -793,6 +793,11 @@ static std::string tune_key(const pwdf_ctx *c, int ndm) {
   return k;
 }
 
+// Segment lengths the kernels are built for, per precision form.
+static std::vector<int> seg_lengths(int prec) {
+  return prec == PWDF_FP32_MFMA ? std::vector<int>{4, 8} : std::vector<int>{4, 5, 8, 16};
+}
+
 static bool load_tune(const char *path, const std::string &key, Tune &t) {
   if (!path) return false;
   FILE *f = std::fopen(path, "r");
@@ -919,13 +924,16 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
   const std::string key = tune_key(c, ndm);
   Tune best;
   if (load_tune(cache_path, key, best)) {
+    const std::vector<int> ok = seg_lengths(c->prec);
+    if (std::find(ok.begin(), ok.end(), best.seg_len) == ok.end())
+      return fail(c, PWDF_EINVAL, "tune cache: segment length not supported");
     if (best.seg_len != c->plan.seg_len) build_segments(c->plan, best.seg_len);
     return setup_device(c, best);
   }
   const bool was_prof = c->prof_on;
   c->prof_on = false;
   // 1. segment length, by the concurrent wall time of the tunable part
-  std::vector<int> segs = c->prec == PWDF_FP32_MFMA ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 16};
+  const std::vector<int> segs = seg_lengths(c->prec);
   double best_t = 1e300;
   for (int sl : segs) {
     build_segments(c->plan, sl);

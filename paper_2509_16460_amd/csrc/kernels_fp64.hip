@@ -1278,6 +1278,7 @@ static hipError_t rho_group(const Dev &d, int ndm, hipStream_t st, int group) {
 hipError_t launch_rho_group(const Dev &d, int group, int ndm, hipStream_t st) {
   switch (d.seg_len) {
     case 4: return rho_group<4>(d, ndm, st, group);
+    case 5: return rho_group<5>(d, ndm, st, group);
     case 8: return rho_group<8>(d, ndm, st, group);
     case 16: return rho_group<16>(d, ndm, st, group);
     default: return hipErrorInvalidValue;
@@ -1320,6 +1321,8 @@ hipError_t launch_jpass_group(const Dev &d, int group, bool force, int ndm, hipS
   switch (d.seg_len * 2 + (force ? 1 : 0)) {
     case 8: return jpass_groups<4, 0>(d, ndm, st, group);
     case 9: return jpass_groups<4, 1>(d, ndm, st, group);
+    case 10: return jpass_groups<5, 0>(d, ndm, st, group);
+    case 11: return jpass_groups<5, 1>(d, ndm, st, group);
     case 16: return jpass_groups<8, 0>(d, ndm, st, group);
     case 17: return jpass_groups<8, 1>(d, ndm, st, group);
     case 32: return jpass_groups<16, 0>(d, ndm, st, group);

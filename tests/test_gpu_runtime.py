@@ -133,3 +133,35 @@ def test_autotune_full_diamond_cell():
     print(f"diamond tuned seg={ctx.stats()['seg_len']} dE={dE:.2e} dJ={dJ:.2e}", flush=True)
     assert dE <= 1e-11 and dJ <= 1e-12
     assert torch.equal(Jg, J1) and torch.equal(Eg, E1)
+
+
+@pytest.mark.parametrize("prec,segs", [(0, (4, 5, 8, 16)), (1, (4, 8))], ids=["fp64", "fp32_mfma"])
+def test_every_segment_length_matches_oracle(prec, segs, tmp_path):
+    """Each segment length the kernels are built for, forced through a tune-cache
+    entry (applied without timing), against the oracle; a length the kernels are
+    not built for is rejected."""
+    p = synth.small_problem(kind="segs", seed=71, kmesh=(2, 2, 1), lmax=2, natm=2, lo=0.2, hi=12.0)
+    D = synth.make_density(p, 710)
+    ref = O.build_j(p, D, want_J=True, want_rho=False)
+    probe = pw().LongRangeJ(p, precision=prec, max_ndm=1)
+    cache = tmp_path / "tune.txt"
+    probe.autotune(1, str(cache))
+    key = cache.read_text().split()[0]
+    ones = " ".join(["1"] * 16)
+    e_tol, j_tol = (1e-10, 1e-11) if prec == 0 else (1e-6, 1e-6)
+    for seg in segs:
+        cache.write_text(f"{key} {seg} {ones}\n")
+        ctx = pw().LongRangeJ(p, precision=prec, max_ndm=1)
+        ctx.autotune(1, str(cache))
+        assert ctx.stats()["seg_len"] == seg
+        J, E = ctx.build_j(dev(D))
+        torch.cuda.synchronize()
+        dE = abs(float(E.cpu()[0]) - ref["E_G"])
+        dJ = float(np.max(np.abs(J.cpu().numpy()[0] - ref["J"])))
+        print(f"prec={prec} seg={seg} nseg={ctx.stats()['nseg']} dE={dE:.2e} dJ={dJ:.2e}", flush=True)
+        assert dE <= e_tol and dJ <= j_tol
+    cache.write_text(f"{key} 7 {ones}\n")
+    ctx = pw().LongRangeJ(p, precision=prec, max_ndm=1)
+    with pytest.raises(pw().PwdfError) as ei:
+        ctx.autotune(1, str(cache))
+    assert ei.value.status == -1
