@@ -98,6 +98,8 @@ typedef struct {
   double pairG_evals; /* per build and density: 2 passes x npairs x nG/2 */
   double t_us[8];     /* reserved */
   int64_t seg_len;    /* line-segment length of the current launch shapes (pwdf_query) */
+  int64_t fork;       /* 1: independent launches of a pass overlap on internal streams;
+                         0: they follow each other on the caller's stream (pwdf_query) */
 } pwdf_stats;
 
 /*
@@ -162,7 +164,7 @@ pwdf_status pwdf_build_j(pwdf_ctx *ctx, int ndm, const double *Dk, double *Jk, d
  * (ndm, Dk, Jk, EJ) captures the whole launch sequence (fork/join branches
  * included) on an internal stream, instantiates it and keeps it in the context;
  * this and later calls with the same arguments launch the instantiated graph on
- * `stream` (one launch instead of ~30).  Results equal those of pwdf_build_j
+ * `stream` (one launch instead of about a dozen kernel launches).  Results equal those of pwdf_build_j
  * bit for bit (same kernels, same shapes).  A call with other arguments,
  * pwdf_autotune or pwdf_destroy drops the cached graph.  The graph holds kernel
  * launches and event dependencies only (no memset or copy nodes).
@@ -199,15 +201,19 @@ pwdf_status pwdf_grad(pwdf_ctx *ctx, int ndm, const double *Dk, double *dEdR, do
  * first the line-segment length (4, 5, 8 or 16 points; 4 or 8 for the FP32-MFMA
  * form), then a common multiplier (1/2 or 2) of the default number of pair
  * chunks of the rho pass and of segment chunks of the J pass, both by the wall
- * time of the pair-G passes with their launches overlapping as in a build.  The
- * FP32-MFMA form (one launch per angular class L) then lets each class keep the
- * multiplier (1/4 .. 4) of its shortest launch, and keeps that result only if
- * it also wins with the launches overlapping.  Timing runs on
+ * time of the transform .. back-transform launches captured as a graph and
+ * replayed.  The FP32-MFMA form (one launch per angular class L) then lets each
+ * class keep the multiplier (1/4 .. 4) of its shortest launch, and keeps that
+ * result only if it also wins replayed as a graph.  Last, the independent
+ * launches of a pass either overlap on the internal streams or follow each
+ * other on the caller's stream, whichever replays faster (pwdf_stats.fork).
+ * Timing runs on
  * an internal stream over zero D(L) and does not touch caller buffers.  The
  * device workspaces are rebuilt for the chosen shapes (this call allocates),
  * a cached graph is dropped and profiling counters are reset.  Results of later
  * calls agree with the untuned ones to rounding (summation order changes).
- * cache_path: text file of "key seg_len mrho[0..7] mj[0..7]" lines keyed by
+ * cache_path: text file of "key seg_len mrho[0..7] mj[0..7] fork" lines (fork
+ * may be absent: 1) keyed by
  * arch, precision, nG, pair count, nbf, nk and ndm; an entry found there is
  * applied without timing (PWDF_EINVAL if its segment length is not one listed
  * above for the context's form), a new result is appended.  NULL: no

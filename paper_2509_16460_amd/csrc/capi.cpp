@@ -26,12 +26,15 @@ struct ProfAgg {
   double ms = 0.0, units = 0.0;
 };
 
-// Launch-shape choice: segment length and, per class L, multipliers of the
-// default wave targets of the rho and J passes (chunk counts follow from them).
+// Launch-shape choice: segment length, per class L multipliers of the default
+// wave targets of the rho and J passes (chunk counts follow from them), and
+// whether independent launches of one pass fan out over the internal streams
+// (fork = 1) or follow each other on the caller's stream (fork = 0).
 struct Tune {
   int seg_len = 8;
   double mrho[kMaxLsum + 1];
   double mj[kMaxLsum + 1];
+  int fork = 1;
   Tune() {
     for (int L = 0; L <= kMaxLsum; ++L) mrho[L] = mj[L] = 1.0;
   }
@@ -371,13 +374,15 @@ pwdf_status step(pwdf_ctx *c, const char *name, double units, hipStream_t st, F 
 }
 
 // Fork/join of independent per-class launches over the internal streams (they
-// write disjoint rows / blocks).  In profiling mode everything stays on `st`.
+// write disjoint rows / blocks).  In profiling mode, and when the tune says so,
+// everything stays on `st`.
 struct Fork {
   pwdf_ctx *c;
   hipStream_t st;
   bool on;
   int next = 0;
-  Fork(pwdf_ctx *c_, hipStream_t st_) : c(c_), st(st_), on(!c_->prof_on && c_->aux[0] != nullptr) {
+  Fork(pwdf_ctx *c_, hipStream_t st_)
+      : c(c_), st(st_), on(!c_->prof_on && c_->tune.fork && c_->aux[0] != nullptr) {
     if (!on) return;
     (void)hipEventRecord(c->ev_fork, st);
     for (int i = 0; i < kAux; ++i) (void)hipStreamWaitEvent(c->aux[i], c->ev_fork, 0);
@@ -570,6 +575,7 @@ static void fill_stats(const Plan &p, pwdf_stats *out) {
   out->nseg = p.nseg();
   out->pairG_evals = 2.0 * (double)p.npairs() * (double)(p.nG_full / 2);
   out->seg_len = p.seg_len;
+  out->fork = 1;
 }
 
 pwdf_status pwdf_plan_stats(const double lattice[9], int natm, const double *xyz, int nshell, const int *shell_atom,
@@ -671,6 +677,7 @@ pwdf_status pwdf_query(const pwdf_ctx *c, pwdf_stats *out) {
   if (!c || !out) return PWDF_EINVAL;
   fill_stats(c->plan, out);
   out->seg_len = c->plan.seg_len;
+  out->fork = c->tune.fork;
   return PWDF_OK;
 }
 
@@ -824,6 +831,8 @@ static bool load_tune(const char *path, const std::string &key, Tune &t) {
       q += m;
     }
     if (good) {
+      int f = 1;
+      if (std::sscanf(q, "%d", &f) == 1) u.fork = f != 0;
       t = u;
       found = true;
     }
@@ -839,7 +848,7 @@ static void save_tune(const char *path, const std::string &key, const Tune &t) {
   std::fprintf(f, "%s %d", key.c_str(), t.seg_len);
   for (int L = 0; L <= kMaxLsum; ++L) std::fprintf(f, " %.6g", t.mrho[L]);
   for (int L = 0; L <= kMaxLsum; ++L) std::fprintf(f, " %.6g", t.mj[L]);
-  std::fprintf(f, "\n");
+  std::fprintf(f, " %d\n", t.fork);
   std::fclose(f);
 }
 
@@ -884,25 +893,45 @@ static pwdf_status time_tunable(pwdf_ctx *c, int ndm, int reps, std::vector<std:
   return PWDF_OK;
 }
 
-// Wall time per repetition of the tunable part with the per-class launches
-// running concurrently (as in pwdf_build_j), events on the tuning stream.
+// Wall time per repetition of the tunable part (transform .. back transform) as
+// a graph replayed on the tuning stream, the launches of one pass overlapping
+// as the tune's fork setting makes them in a build.
 static pwdf_status time_total(pwdf_ctx *c, int ndm, int reps, double &ms_out) {
   pwdf_status s;
   hipError_t e;
   if ((e = hipMemsetAsync(c->dev.Dblk, 0, sizeof(double) * (size_t)ndm * c->plan.nelem, c->cap)) != hipSuccess)
     return hip_fail(c, e, "tune clear");
-  hipEvent_t a = prof_event(c), b = prof_event(c);
-  if (!a || !b) return fail(c, PWDF_EDEVICE, "tune events");
-  for (int r = -1; r < reps; ++r) {  // r = -1: warm-up
-    if (r == 0 && (e = hipEventRecord(a, c->cap)) != hipSuccess) return hip_fail(c, e, "tune events");
-    if ((s = run_mid_rho(c, ndm, c->Escr, c->cap)) != PWDF_OK) return s;
-    if ((s = run_mid_j(c, ndm, c->cap)) != PWDF_OK) return s;
+  if ((e = hipStreamSynchronize(c->cap)) != hipSuccess) return hip_fail(c, e, "tune sync");
+  if ((e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return hip_fail(c, e, "tune capture");
+  s = run_mid_rho(c, ndm, c->Escr, c->cap);
+  if (s == PWDF_OK) s = run_mid_j(c, ndm, c->cap);
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->cap, &graph);
+  if (s != PWDF_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
   }
-  if ((e = hipEventRecord(b, c->cap)) != hipSuccess || (e = hipEventSynchronize(b)) != hipSuccess)
-    return hip_fail(c, e, "tune events");
+  if (e2 != hipSuccess) return hip_fail(c, e2, "tune capture");
+  hipGraphExec_t exec = nullptr;
+  if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(c, e, "tune graph");
+  }
+  hipEvent_t a = prof_event(c), b = prof_event(c);
+  if (!a || !b) e = hipErrorOutOfMemory;
+  for (int r = -1; r < reps && e == hipSuccess; ++r) {  // r = -1: warm-up
+    if (r == 0) e = hipEventRecord(a, c->cap);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, c->cap);
+  }
+  if (e == hipSuccess) e = hipEventRecord(b, c->cap);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
   float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, a, b);
+  if (e == hipSuccess) (void)hipEventElapsedTime(&ms, a, b);
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
   c->prof_next = 0;
+  if (e != hipSuccess) return hip_fail(c, e, "tune timing");
   ms_out = ms / reps;
   return PWDF_OK;
 }
@@ -932,34 +961,56 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
   }
   const bool was_prof = c->prof_on;
   c->prof_on = false;
-  // 1. segment length, by the concurrent wall time of the tunable part
+  // Each candidate: the workspaces set up for it, two timings of graph replays,
+  // the shorter kept.
+  auto measure = [&](const Tune &t, double &ms) -> pwdf_status {
+    if (t.seg_len != c->plan.seg_len) build_segments(c->plan, t.seg_len);
+    pwdf_status r = setup_device(c, t);
+    double a = 0.0, b = 0.0;
+    if (r == PWDF_OK) r = time_total(c, ndm, 5, a);
+    if (r == PWDF_OK) r = time_total(c, ndm, 5, b);
+    ms = std::min(a, b);
+    return r;
+  };
+  // 1. segment length: a warm-up, then two passes over the candidates (the
+  // second in reverse order, so that neither end is favoured by clocks still
+  // settling), each candidate keeping its shortest time
   const std::vector<int> segs = seg_lengths(c->prec);
-  double best_t = 1e300;
-  for (int sl : segs) {
-    build_segments(c->plan, sl);
+  std::vector<double> tseg(segs.size(), 1e300);
+  {
     Tune t;
-    t.seg_len = sl;
-    if ((s = setup_device(c, t)) != PWDF_OK) return s;
+    t.seg_len = segs.back();
     double ms = 0.0;
-    if ((s = time_total(c, ndm, 5, ms)) != PWDF_OK) return s;
-    if (ms < best_t) {
-      best_t = ms;
-      best = t;
-    }
+    if ((s = measure(t, ms)) != PWDF_OK) return s;
   }
-  // 2. chunk counts of the pair-G passes scaled together, by concurrent wall time
-  build_segments(c->plan, best.seg_len);
+  for (int pass = 0; pass < 2; ++pass)
+    for (size_t i = 0; i < segs.size(); ++i) {
+      const size_t j = pass ? segs.size() - 1 - i : i;
+      Tune t;
+      t.seg_len = segs[j];
+      double ms = 0.0;
+      if ((s = measure(t, ms)) != PWDF_OK) return s;
+      tseg[j] = std::min(tseg[j], ms);
+    }
+  double best_t = 1e300;
+  for (size_t j = 0; j < segs.size(); ++j)
+    if (tseg[j] < best_t) {
+      best_t = tseg[j];
+      best = Tune();
+      best.seg_len = segs[j];
+    }
+  // 2. chunk counts of the pair-G passes scaled together
   for (double m : {0.5, 2.0}) {
     Tune t = best;
     for (int L = 0; L <= kMaxLsum; ++L) t.mrho[L] = t.mj[L] = m;
-    if ((s = setup_device(c, t)) != PWDF_OK) return s;
     double ms = 0.0;
-    if ((s = time_total(c, ndm, 5, ms)) != PWDF_OK) return s;
+    if ((s = measure(t, ms)) != PWDF_OK) return s;
     if (ms < best_t) {
       best_t = ms;
       best = t;
     }
   }
+  if (best.seg_len != c->plan.seg_len) build_segments(c->plan, best.seg_len);
   Tune cand = best;
   // 3. FP32-MFMA form (one launch per class): each class keeps the multiplier
   // with its shortest kernel, timed one launch at a time, and the result is kept
@@ -1000,7 +1051,21 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
     if ((s = time_total(c, ndm, 5, t_cand)) != PWDF_OK) return s;
     if (t_cand > best_t) cand = best;
   }
+  // 4. the independent launches of a pass overlapping on the internal streams,
+  // or following each other on one stream: timed back to back
   if ((s = setup_device(c, cand)) != PWDF_OK) return s;
+  {
+    double t_fork = 1e300, t_seq = 1e300;
+    for (int f : {1, 0, 0, 1}) {
+      double ms = 0.0;
+      c->tune.fork = f;
+      if ((s = time_total(c, ndm, 5, ms)) != PWDF_OK) return s;
+      double &best_f = f ? t_fork : t_seq;
+      best_f = std::min(best_f, ms);
+    }
+    cand.fork = t_seq < t_fork ? 0 : 1;
+    c->tune.fork = cand.fork;
+  }
   c->prof_on = was_prof;
   save_tune(cache_path, key, cand);
   return PWDF_OK;

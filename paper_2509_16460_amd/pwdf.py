@@ -41,7 +41,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("npairs_by_class", ctypes.c_int64 * 16), ("nG", ctypes.c_int64), ("npairs", ctypes.c_int64),
                 ("nbf", ctypes.c_int64), ("nk", ctypes.c_int64), ("nimg", ctypes.c_int64),
                 ("nblocks", ctypes.c_int64), ("nseg", ctypes.c_int64), ("pairG_evals", ctypes.c_double),
-                ("t_us", ctypes.c_double * 8), ("seg_len", ctypes.c_int64)]
+                ("t_us", ctypes.c_double * 8), ("seg_len", ctypes.c_int64),
+                ("fork", ctypes.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("npairs_by_class", "t_us")}

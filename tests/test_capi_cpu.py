@@ -45,7 +45,8 @@ def test_plan_matches_oracle_enumeration(cfg):
     assert s["nG"] == o["nG"]
     assert 2 * s["npairs"] - n_diag_pairs(prob) == o["npairs"]
     assert s["nbf"] == o["nbf"] and s["nk"] == o["nk"]
-    assert s["seg_len"] == 8  # default line-segment length (last field of pwdf_stats)
+    assert s["seg_len"] == 8  # default line-segment length
+    assert s["fork"] == 1  # default launch fan-out (last field of pwdf_stats)
 
 
 def test_plan_contracted_and_rmax():

@@ -165,3 +165,30 @@ def test_every_segment_length_matches_oracle(prec, segs, tmp_path):
     with pytest.raises(pw().PwdfError) as ei:
         ctx.autotune(1, str(cache))
     assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32_mfma"])
+def test_fork_setting_from_cache(prec, tmp_path):
+    """The launches of a pass overlapping on internal streams (fork 1) or in
+    sequence on the caller's stream (fork 0), set through a tune-cache entry:
+    bit-identical J(k) and E_J, eager and replayed as a graph."""
+    p = problem()
+    D = dev(synth.make_density(p, 650))
+    probe = pw().LongRangeJ(p, precision=prec, max_ndm=1)
+    cache = tmp_path / "tune.txt"
+    probe.autotune(1, str(cache))
+    assert probe.stats()["fork"] in (0, 1)
+    key = cache.read_text().split()[0]
+    ones = " ".join(["1"] * 16)
+    out = {}
+    for fk in (1, 0):
+        cache.write_text(f"{key} 8 {ones} {fk}\n")
+        ctx = pw().LongRangeJ(p, precision=prec, max_ndm=1)
+        ctx.autotune(1, str(cache))
+        assert ctx.stats()["fork"] == fk
+        Je, Ee = ctx.build_j(D)
+        Jg, Eg = ctx.build_j(D, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(Je, Jg) and torch.equal(Ee, Eg)
+        out[fk] = (Je, Ee)
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
