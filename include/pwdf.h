@@ -198,9 +198,9 @@ pwdf_status pwdf_grad(pwdf_ctx *ctx, int ndm, const double *Dk, double *dEdR, do
                       void *stream);
 
 /* Pick launch shapes by timing candidates on the device for ndm densities:
- * first the line-segment length (4, 5, 8 or 16 points; 4 or 8 for the FP32-MFMA
- * form), then a common multiplier (1/2 or 2) of the default number of pair
- * chunks of the rho pass and of segment chunks of the J pass, both by the wall
+ * the line-segment length (4, 5, 8 or 16 points; 4 or 8 for the FP32-MFMA
+ * form) jointly with a common multiplier (1/2, 1 or 2) of the default number of
+ * pair chunks of the rho pass and of segment chunks of the J pass, by the wall
  * time of the transform .. back-transform launches captured as a graph and
  * replayed.  The FP32-MFMA form (one launch per angular class L) then lets each
  * class keep the multiplier (1/4 .. 4) of its shortest launch, and keeps that

@@ -972,47 +972,42 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
     ms = std::min(a, b);
     return r;
   };
-  // 1. segment length: a warm-up, then two passes over the candidates (the
-  // second in reverse order, so that neither end is favoured by clocks still
-  // settling), each candidate keeping its shortest time
+  // 1. segment length and a common multiplier (1/2, 1, 2) of the chunk counts of
+  // the pair-G passes, searched jointly (the best multiplier depends on the
+  // segment length): a warm-up, every pair timed once, then the three best
+  // timed again in reverse order, each keeping its shortest time
   const std::vector<int> segs = seg_lengths(c->prec);
-  std::vector<double> tseg(segs.size(), 1e300);
-  {
+  struct Cand {
     Tune t;
-    t.seg_len = segs.back();
+    double ms;
+  };
+  std::vector<Cand> cands;
+  for (int sl : segs)
+    for (double m : {1.0, 0.5, 2.0}) {
+      Cand k;
+      k.t.seg_len = sl;
+      for (int L = 0; L <= kMaxLsum; ++L) k.t.mrho[L] = k.t.mj[L] = m;
+      k.ms = 1e300;
+      cands.push_back(k);
+    }
+  {
     double ms = 0.0;
-    if ((s = measure(t, ms)) != PWDF_OK) return s;
+    if ((s = measure(cands.back().t, ms)) != PWDF_OK) return s;
   }
-  for (int pass = 0; pass < 2; ++pass)
-    for (size_t i = 0; i < segs.size(); ++i) {
-      const size_t j = pass ? segs.size() - 1 - i : i;
-      Tune t;
-      t.seg_len = segs[j];
-      double ms = 0.0;
-      if ((s = measure(t, ms)) != PWDF_OK) return s;
-      tseg[j] = std::min(tseg[j], ms);
-    }
-  double best_t = 1e300;
-  for (size_t j = 0; j < segs.size(); ++j)
-    if (tseg[j] < best_t) {
-      best_t = tseg[j];
-      best = Tune();
-      best.seg_len = segs[j];
-    }
-  // 2. chunk counts of the pair-G passes scaled together
-  for (double m : {0.5, 2.0}) {
-    Tune t = best;
-    for (int L = 0; L <= kMaxLsum; ++L) t.mrho[L] = t.mj[L] = m;
+  for (Cand &k : cands)
+    if ((s = measure(k.t, k.ms)) != PWDF_OK) return s;
+  std::stable_sort(cands.begin(), cands.end(), [](const Cand &x, const Cand &y) { return x.ms < y.ms; });
+  for (int i = std::min<int>(3, (int)cands.size()) - 1; i >= 0; --i) {
     double ms = 0.0;
-    if ((s = measure(t, ms)) != PWDF_OK) return s;
-    if (ms < best_t) {
-      best_t = ms;
-      best = t;
-    }
+    if ((s = measure(cands[i].t, ms)) != PWDF_OK) return s;
+    cands[i].ms = std::min(cands[i].ms, ms);
   }
+  std::stable_sort(cands.begin(), cands.end(), [](const Cand &x, const Cand &y) { return x.ms < y.ms; });
+  best = cands[0].t;
+  double best_t = cands[0].ms;
   if (best.seg_len != c->plan.seg_len) build_segments(c->plan, best.seg_len);
   Tune cand = best;
-  // 3. FP32-MFMA form (one launch per class): each class keeps the multiplier
+  // 2. FP32-MFMA form (one launch per class): each class keeps the multiplier
   // with its shortest kernel, timed one launch at a time, and the result is kept
   // only if it also wins when the classes overlap
   if (c->prec == PWDF_FP32_MFMA) {
@@ -1051,7 +1046,7 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
     if ((s = time_total(c, ndm, 5, t_cand)) != PWDF_OK) return s;
     if (t_cand > best_t) cand = best;
   }
-  // 4. the independent launches of a pass overlapping on the internal streams,
+  // 3. the independent launches of a pass overlapping on the internal streams,
   // or following each other on one stream: timed back to back
   if ((s = setup_device(c, cand)) != PWDF_OK) return s;
   {
