@@ -37,6 +37,7 @@ struct Dev {
   int ptab_len;
   int kmesh[3];                  // k-point k = (k1 n2 + k2) n3 + k3
   const double *ttab;
+  const double *start_tab;       // 2^(j/32) (32), then (cos, sin)(2 pi j/64), j = -32..32
   int cls_b0[16], cls_b1[16];
   int L_p0[kMaxLsum + 1], L_p1[kMaxLsum + 1];
   int64_t dhat_off[kMaxLsum + 1];

@@ -61,6 +61,70 @@ __device__ __forceinline__ void next_k(int &k1, int &k2, int &k3, int n2, int n3
   }
 }
 
+// ---------------------------------------------------------------------------
+// Segment-start factors of the pair-G passes, table-driven (Tang's method for
+// the exponential):
+//   e^x = 2^m 2^(j/32) e^r,  n = rint(32 x / ln 2) = 32 m + j (0 <= j < 32),
+//   r = x - n ln2/32 (|r| <= ln2/64; ln2/32 split in a head and a tail, two
+//   fma steps), e^r by its Taylor series to r^6 (remainder below 4e-18);
+//   e^{-2 pi i f} for f in [-1/2, 1/2]: the table value e^{-2 pi i j/64}
+//   (j = rint(64 f)) times e^{-i theta}, theta = 2 pi (f - j/64) (the difference
+//   is exact), |theta| <= pi/64, by the Taylor series of cos to theta^8 and of
+//   sin to theta^9 (remainders below 1e-19); e^r - 1 and cos - 1 are carried as
+//   small corrections so that the table values enter with one rounding.
+// No range handling: the arguments are bounded (|x| < 700 for the Gaussian
+// factor and its neighbour ratio; f is reduced mod 1 first).  The tables live
+// in LDS: 2^(j/32) for j = 0..31, (cos, sin)(2 pi j/64) for j = -32..32.
+// ---------------------------------------------------------------------------
+constexpr int kStartTab = 32 + 2 * 65;  // doubles: exp2 table, then cis table
+
+__device__ __forceinline__ double exp_tab(double x, const double *__restrict__ e2) {
+  constexpr double k32_ln2 = 46.16624130844683;
+  constexpr double ln2_32_hi = 0.02166084939249829, ln2_32_lo = 7.247021293269686e-19;
+  const double n = rint(x * k32_ln2);
+  double r = fma(-n, ln2_32_hi, x);
+  r = fma(-n, ln2_32_lo, r);
+  const int ni = (int)n;
+  double p = fma(r, 1.0 / 720.0, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  // 2^(j/32) e^r = T + T (e^r - 1): the table value enters with one rounding
+  const double t = e2[ni & 31];
+  return ldexp(fma(t, p * r, t), ni >> 5);
+}
+
+// (cos 2 pi f, -sin 2 pi f) = e^{-2 pi i f}, f in [-1/2, 1/2]
+__device__ __forceinline__ double2 cis_neg(double f, const double2 *__restrict__ cis) {
+  constexpr double k2pi = 6.283185307179586;
+  const double jd = rint(f * 64.0);
+  const double th = fma(jd, -1.0 / 64.0, f) * k2pi;
+  const double t2 = th * th;
+  double c = fma(t2, 1.0 / 40320.0, -1.0 / 720.0);  // c = cos(theta) - 1
+  c = fma(c, t2, 1.0 / 24.0);
+  c = fma(c, t2, -0.5);
+  c *= t2;
+  double sn = fma(t2, 1.0 / 362880.0, -1.0 / 5040.0);
+  sn = fma(sn, t2, 1.0 / 120.0);
+  sn = fma(sn, t2, -1.0 / 6.0);
+  sn = fma(sn, t2, 1.0);
+  sn *= th;
+  const double2 t = cis[(int)jd + 32];
+  // table value plus small corrections, added last
+  return make_double2(t.x + fma(t.x, c, -t.y * sn), -(t.y + fma(t.y, c, t.x * sn)));
+}
+
+// copies the start tables into LDS (callers synchronise before use)
+__device__ __forceinline__ void load_start_tabs(const double *__restrict__ g, double *e2, double2 *cis) {
+  for (int i = threadIdx.x + threadIdx.y * blockDim.x; i < kStartTab; i += blockDim.x * blockDim.y) {
+    if (i < 32)
+      e2[i] = g[i];
+    else if ((i - 32) % 2 == 0)
+      cis[(i - 32) / 2] = make_double2(g[i], g[i + 1]);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk, int nk, int nbf, int n2, int n3,
                                                  int nsegD, const int *__restrict__ sD_el,
                                                  const int *__restrict__ sD_code, const int *__restrict__ sD_e0,
@@ -191,7 +255,8 @@ struct RhoTile {
 template <int L, int SEG, int NDB>
 __device__ __forceinline__ void rho_pair(const double *__restrict__ r, const SegDesc &sd, const double (&mv)[L + 1],
                                          const double (&mw)[L + 1], double (&accr)[NDB][SEG],
-                                         double (&acci)[NDB][SEG]) {
+                                         double (&acci)[NDB][SEG], const double *__restrict__ e2,
+                                         const double2 *__restrict__ cis) {
   constexpr int NT = nherm(L);
   constexpr Monos<L> MT{};
   const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
@@ -212,28 +277,35 @@ __device__ __forceinline__ void rho_pair(const double *__restrict__ r, const Seg
         cr[b][a] += t;
     }
   }
-  const double e0 = exp(-sd.gq0 * inv4p);
-  const double eR = exp(-sd.dg0 * inv4p);
+  const double e0 = exp_tab(-sd.gq0 * inv4p, e2);
+  const double eR = exp_tab(-sd.dg0 * inv4p, e2);
   double ph = fma(nu0, fu, fma(nv, fv, nw * fw));
   ph -= rint(ph);
-  double sn, cs;
-  sincospi(2.0 * ph, &sn, &cs);
-  double Sr = e0 * cs, Si = -e0 * sn;
+  const double2 w = cis_neg(ph, cis);
+  double Sr = e0 * w.x, Si = e0 * w.y;
   double Rr = eR * r[4], Ri = eR * r[5];
   const double q = r[6];
+  // the degree-L coefficient exists only in the part of parity L (real for even
+  // L, imaginary for odd L): the Horner sums start below it in the other part
+  constexpr int topR = (L & 1) ? L - 1 : L, topI = (L & 1) ? L : L - 1;
 #pragma unroll
   for (int s = 0; s < SEG; ++s) {
     const double n = nu0 + s;
 #pragma unroll
     for (int b = 0; b < NDB; ++b) {
-      double Pr = cr[b][L], Pi = ci[b][L];
+      double Pr = cr[b][topR];
 #pragma unroll
-      for (int a = L - 1; a >= 0; --a) {
-        Pr = fma(Pr, n, cr[b][a]);
-        Pi = fma(Pi, n, ci[b][a]);
+      for (int a = topR - 1; a >= 0; --a) Pr = fma(Pr, n, cr[b][a]);
+      if constexpr (L == 0) {
+        accr[b][s] = fma(Sr, Pr, accr[b][s]);
+        acci[b][s] = fma(Si, Pr, acci[b][s]);
+      } else {
+        double Pi = ci[b][topI];
+#pragma unroll
+        for (int a = topI - 1; a >= 0; --a) Pi = fma(Pi, n, ci[b][a]);
+        accr[b][s] = fma(Sr, Pr, fma(-Si, Pi, accr[b][s]));
+        acci[b][s] = fma(Sr, Pi, fma(Si, Pr, acci[b][s]));
       }
-      accr[b][s] = fma(Sr, Pr, fma(-Si, Pi, accr[b][s]));
-      acci[b][s] = fma(Sr, Pi, fma(Si, Pr, acci[b][s]));
     }
     const double tr = fma(Sr, Rr, -Si * Ri);
     Si = fma(Sr, Ri, Si * Rr);
@@ -245,7 +317,8 @@ __device__ __forceinline__ void rho_pair(const double *__restrict__ r, const Seg
 
 template <int L, int SEG, int W, int NDB>
 __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int db, int ndm, double *__restrict__ sp,
-                                          double2 *__restrict__ red) {
+                                          double2 *__restrict__ red, const double *__restrict__ e2,
+                                          const double2 *__restrict__ cis) {
   constexpr int NT = nherm(L);
   constexpr int REC = 8 + NT * NDB;
   constexpr int TP = RhoTile<L>::TP;
@@ -293,7 +366,7 @@ __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int
       sp[i] = v;
     }
     __syncthreads();
-    for (int j = w; j < nt; j += W) rho_pair<L, SEG, NDB>(sp + j * REC, sd, mv, mw, accr, acci);
+    for (int j = w; j < nt; j += W) rho_pair<L, SEG, NDB>(sp + j * REC, sd, mv, mw, accr, acci, e2, cis);
   }
   // the W waves' partial sums are added in LDS in fixed order, one density at a time
   if (W > 1) {
@@ -418,7 +491,8 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
                                             const PairHot *__restrict__ hot, int Lp0, int Lp1,
                                             double *__restrict__ yhat, int64_t yhat_size, int64_t ycls_off, int pb,
                                             int chunk, int dm0, int ndm, SegDesc *__restrict__ ss,
-                                            double2 *__restrict__ sv) {
+                                            double2 *__restrict__ sv, const double *__restrict__ e2,
+                                            const double2 *__restrict__ cis) {
   constexpr int NT = nherm(L);
   constexpr int TS = kJTile;
   constexpr Monos<L> MT{};
@@ -455,14 +529,13 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
       const SegDesc sd = ss[j];
       const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
       if (!(sd.nv == pnv && sd.nw == pnw && sd.nu0 == pnext)) {
-        const double e0 = exp(-sd.gq0 * h.inv4p);
-        const double eR = exp(-sd.dg0 * h.inv4p);
+        const double e0 = exp_tab(-sd.gq0 * h.inv4p, e2);
+        const double eR = exp_tab(-sd.dg0 * h.inv4p, e2);
         double ph = fma(nu0, h.fu, fma(nv, h.fv, nw * h.fw));
         ph -= rint(ph);
-        double sn, cs;
-        sincospi(2.0 * ph, &sn, &cs);
-        Sr = e0 * cs;
-        Si = -e0 * sn;
+        const double2 w = cis_neg(ph, cis);
+        Sr = e0 * w.x;
+        Si = e0 * w.y;
         Rr = eR * h.cu;
         Ri = eR * h.su;
       }
@@ -1099,6 +1172,10 @@ __global__ __launch_bounds__(256) void k_rho_all(const Dev dv, const ClassTab ta
   constexpr int W = 4;
   __shared__ double sp[rho_sp_max<L0, L1, NDB>()];
   __shared__ double2 red[(W - 1) * 64 * SEG];
+  __shared__ double se2[32];
+  __shared__ double2 scis[65];
+  load_start_tabs(dv.start_tab, se2, scis);
+  __syncthreads();
   const int i = tab_entry(tab, blockIdx.x);
   const int local = blockIdx.x - tab.first[i];
   const int nsg = tab.gx[i];
@@ -1107,7 +1184,7 @@ __global__ __launch_bounds__(256) void k_rho_all(const Dev dv, const ClassTab ta
 #define PWDF_RCASE(LL)                                                                                      \
   case LL:                                                                                                  \
     if (LL >= L0 && LL <= L1)                                                                               \
-      rho_block<(LL >= L0 && LL <= L1 ? LL : L0), SEG, W, NDB>(dv, sgi, chunk, db, ndm, sp, red);           \
+      rho_block<(LL >= L0 && LL <= L1 ? LL : L0), SEG, W, NDB>(dv, sgi, chunk, db, ndm, sp, red, se2, scis); \
     break;
   switch (tab.cls[i]) {
     PWDF_RCASE(0)
@@ -1130,6 +1207,10 @@ template <int SEG, int DEG, int L0, int L1, int NDB>
 __global__ __launch_bounds__(256) void k_jpass_all(const Dev dv, const ClassTab tab, int ndm) {
   __shared__ SegDesc ss[kJTile];
   __shared__ double2 sv[NDB * kJTile * SEG];
+  __shared__ double se2[32];
+  __shared__ double2 scis[65];
+  load_start_tabs(dv.start_tab, se2, scis);
+  __syncthreads();
   const int i = tab_entry(tab, blockIdx.x);
   const int local = blockIdx.x - tab.first[i];
   const int npb = tab.gx[i];
@@ -1144,7 +1225,8 @@ __global__ __launch_bounds__(256) void k_jpass_all(const Dev dv, const ClassTab 
     if (LL >= L0 && LL <= L1)                                                                                  \
       jpass_block<(LL >= L0 && LL <= L1 ? LL + DEG : 0), SEG, NDB>(dv.segs, dv.nseg, dv.j_spc[LL], dv.Vc,      \
                                                                      dv.nslot, dv.hot, dv.L_p0[LL], dv.L_p1[LL], \
-                                                                     y, ysz, yoff, pb, chunk, dm0, ndm, ss, sv); \
+                                                                     y, ysz, yoff, pb, chunk, dm0, ndm, ss, sv,  \
+                                                                     se2, scis);                                 \
     break;
   switch (L) {
     PWDF_JCASE(0)
