@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/pwdf.h"
+#include "kernel_common.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -278,14 +279,8 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   UP(p.eD, eD)
   UP(p.ttab, ttab)
   {
-    // segment-start tables of the pair-G passes (rounded from long double)
-    std::vector<double> st;
-    for (int j = 0; j < 32; ++j) st.push_back((double)std::exp2((long double)j / 32));
-    const long double pi = 3.141592653589793238462643383279502884L;
-    for (int j = -32; j <= 32; ++j) {
-      st.push_back((double)std::cos(2 * pi * j / 64));
-      st.push_back((double)std::sin(2 * pi * j / 64));
-    }
+    std::vector<double> st(kStartTab);
+    start_tables(st.data());
     if ((e = upload(c, st, &d.start_tab)) != hipSuccess) return hip_fail(c, e, "uploading start tables");
   }
 #undef UP

@@ -1,5 +1,7 @@
 // Compile-time index tables shared by the FP64 and FP32 kernels.
 #pragma once
+#include <cmath>
+
 #include "pwdf_internal.h"
 
 namespace pwdf {
@@ -82,6 +84,72 @@ __device__ __forceinline__ void md_axis(double inv2p, double xpa, double xpb,
         E[i][j][t] = v;
       }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Segment-start factors of the pair-G passes, table-driven (Tang's method for
+// the exponential):
+//   e^x = 2^m 2^(j/32) e^r,  n = rint(32 x / ln 2) = 32 m + j (0 <= j < 32),
+//   r = x - n ln2/32 (|r| <= ln2/64; ln2/32 split in a head and a tail, two
+//   fma steps), e^r - 1 by its Taylor series to r^6 (remainder below 4e-18);
+//   e^{-2 pi i f} for f in [-1/2, 1/2]: the table value e^{-2 pi i j/64}
+//   (j = rint(64 f)) times e^{-i theta}, theta = 2 pi (f - j/64) (the difference
+//   is exact), |theta| <= pi/64, by the Taylor series of cos - 1 to theta^8 and
+//   of sin to theta^9 (remainders below 1e-19).
+// The small parts are carried as corrections so that the table values enter
+// with one rounding (about 1 ulp).  No range handling: the arguments are
+// bounded (|x| < 700 for the Gaussian factor and its neighbour ratio; f is
+// reduced mod 1 first).  Tables (kStartTab doubles): 2^(j/32) for j = 0..31,
+// then (cos, sin)(2 pi j/64) for j = -32..32.
+// ---------------------------------------------------------------------------
+constexpr int kStartTab = 32 + 2 * 65;
+
+inline void start_tables(double *t) {
+  for (int j = 0; j < 32; ++j) t[j] = (double)exp2l((long double)j / 32);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int j = -32; j <= 32; ++j) {
+    t[32 + 2 * (j + 32)] = (double)cosl(2 * pi * j / 64);
+    t[33 + 2 * (j + 32)] = (double)sinl(2 * pi * j / 64);
+  }
+}
+
+__host__ __device__ inline double exp_tab(double x, const double *e2) {
+  constexpr double k32_ln2 = 46.16624130844683;
+  constexpr double ln2_32_hi = 0.02166084939249829, ln2_32_lo = 7.247021293269686e-19;
+  const double n = rint(x * k32_ln2);
+  double r = fma(-n, ln2_32_hi, x);
+  r = fma(-n, ln2_32_lo, r);
+  const int ni = (int)n;
+  double p = fma(r, 1.0 / 720.0, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  // 2^(j/32) e^r = T + T (e^r - 1)
+  const double t = e2[ni & 31];
+  return ldexp(fma(t, p * r, t), ni >> 5);
+}
+
+// (c, s) = (cos 2 pi f, -sin 2 pi f) = e^{-2 pi i f}, f in [-1/2, 1/2]; cis is
+// the (cos, sin) table of 65 pairs
+__host__ __device__ inline void cis_neg(double f, const double *cis, double &c, double &s) {
+  constexpr double k2pi = 6.283185307179586;
+  const double jd = rint(f * 64.0);
+  const double th = fma(jd, -1.0 / 64.0, f) * k2pi;
+  const double t2 = th * th;
+  double cm = fma(t2, 1.0 / 40320.0, -1.0 / 720.0);  // cos(theta) - 1
+  cm = fma(cm, t2, 1.0 / 24.0);
+  cm = fma(cm, t2, -0.5);
+  cm *= t2;
+  double sn = fma(t2, 1.0 / 362880.0, -1.0 / 5040.0);
+  sn = fma(sn, t2, 1.0 / 120.0);
+  sn = fma(sn, t2, -1.0 / 6.0);
+  sn = fma(sn, t2, 1.0);
+  sn *= th;
+  const int k = 2 * ((int)jd + 32);
+  const double tc = cis[k], ts = cis[k + 1];
+  c = tc + fma(tc, cm, -ts * sn);
+  s = -(ts + fma(ts, cm, tc * sn));
 }
 
 }  // namespace pwdf

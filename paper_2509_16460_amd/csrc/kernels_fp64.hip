@@ -61,61 +61,7 @@ __device__ __forceinline__ void next_k(int &k1, int &k2, int &k3, int n2, int n3
   }
 }
 
-// ---------------------------------------------------------------------------
-// Segment-start factors of the pair-G passes, table-driven (Tang's method for
-// the exponential):
-//   e^x = 2^m 2^(j/32) e^r,  n = rint(32 x / ln 2) = 32 m + j (0 <= j < 32),
-//   r = x - n ln2/32 (|r| <= ln2/64; ln2/32 split in a head and a tail, two
-//   fma steps), e^r by its Taylor series to r^6 (remainder below 4e-18);
-//   e^{-2 pi i f} for f in [-1/2, 1/2]: the table value e^{-2 pi i j/64}
-//   (j = rint(64 f)) times e^{-i theta}, theta = 2 pi (f - j/64) (the difference
-//   is exact), |theta| <= pi/64, by the Taylor series of cos to theta^8 and of
-//   sin to theta^9 (remainders below 1e-19); e^r - 1 and cos - 1 are carried as
-//   small corrections so that the table values enter with one rounding.
-// No range handling: the arguments are bounded (|x| < 700 for the Gaussian
-// factor and its neighbour ratio; f is reduced mod 1 first).  The tables live
-// in LDS: 2^(j/32) for j = 0..31, (cos, sin)(2 pi j/64) for j = -32..32.
-// ---------------------------------------------------------------------------
-constexpr int kStartTab = 32 + 2 * 65;  // doubles: exp2 table, then cis table
-
-__device__ __forceinline__ double exp_tab(double x, const double *__restrict__ e2) {
-  constexpr double k32_ln2 = 46.16624130844683;
-  constexpr double ln2_32_hi = 0.02166084939249829, ln2_32_lo = 7.247021293269686e-19;
-  const double n = rint(x * k32_ln2);
-  double r = fma(-n, ln2_32_hi, x);
-  r = fma(-n, ln2_32_lo, r);
-  const int ni = (int)n;
-  double p = fma(r, 1.0 / 720.0, 1.0 / 120.0);
-  p = fma(p, r, 1.0 / 24.0);
-  p = fma(p, r, 1.0 / 6.0);
-  p = fma(p, r, 0.5);
-  p = fma(p, r, 1.0);
-  // 2^(j/32) e^r = T + T (e^r - 1): the table value enters with one rounding
-  const double t = e2[ni & 31];
-  return ldexp(fma(t, p * r, t), ni >> 5);
-}
-
-// (cos 2 pi f, -sin 2 pi f) = e^{-2 pi i f}, f in [-1/2, 1/2]
-__device__ __forceinline__ double2 cis_neg(double f, const double2 *__restrict__ cis) {
-  constexpr double k2pi = 6.283185307179586;
-  const double jd = rint(f * 64.0);
-  const double th = fma(jd, -1.0 / 64.0, f) * k2pi;
-  const double t2 = th * th;
-  double c = fma(t2, 1.0 / 40320.0, -1.0 / 720.0);  // c = cos(theta) - 1
-  c = fma(c, t2, 1.0 / 24.0);
-  c = fma(c, t2, -0.5);
-  c *= t2;
-  double sn = fma(t2, 1.0 / 362880.0, -1.0 / 5040.0);
-  sn = fma(sn, t2, 1.0 / 120.0);
-  sn = fma(sn, t2, -1.0 / 6.0);
-  sn = fma(sn, t2, 1.0);
-  sn *= th;
-  const double2 t = cis[(int)jd + 32];
-  // table value plus small corrections, added last
-  return make_double2(t.x + fma(t.x, c, -t.y * sn), -(t.y + fma(t.y, c, t.x * sn)));
-}
-
-// copies the start tables into LDS (callers synchronise before use)
+// copies the segment-start tables into LDS (callers synchronise before use)
 __device__ __forceinline__ void load_start_tabs(const double *__restrict__ g, double *e2, double2 *cis) {
   for (int i = threadIdx.x + threadIdx.y * blockDim.x; i < kStartTab; i += blockDim.x * blockDim.y) {
     if (i < 32)
@@ -123,6 +69,12 @@ __device__ __forceinline__ void load_start_tabs(const double *__restrict__ g, do
     else if ((i - 32) % 2 == 0)
       cis[(i - 32) / 2] = make_double2(g[i], g[i + 1]);
   }
+}
+
+__device__ __forceinline__ double2 cis_neg(double f, const double2 *__restrict__ cis) {
+  double c, s;
+  cis_neg(f, reinterpret_cast<const double *>(cis), c, s);
+  return make_double2(c, s);
 }
 
 __global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk, int nk, int nbf, int n2, int n3,
