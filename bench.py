@@ -13,14 +13,18 @@ torch.cuda.synchronize() on both sides.  A second region of the same steps runs
 with per-launch HIP events (library profiling mode: events on the stream each
 kernel is launched on, launches serialised) and gives each kernel's average
 duration for the roofline entry.  The same line reports the FP32-MFMA form and
-16-density batches of both forms on the same workload, with their errors, and
-the FP64 CPU oracle timed on the host cores as the baseline.
+16-density batches of both forms on the same workload, with their errors
+(measured in a child process, so that a failure there is reported in
+"extras_error" instead of ending the run), and the FP64 CPU oracle timed on the
+host cores as the baseline.
 """
 import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -128,6 +132,47 @@ def timed(torch, fn, steps, warmup):
     return (time.perf_counter() - t0) / steps * 1e3
 
 
+def extras(args):
+    """FP32-MFMA form (one density) and 16-density batches of both forms on the
+    same workload; prints one JSON object, writes the FP32 J(k) to --j32-out."""
+    import numpy as np
+    import torch
+    from paper_2509_16460_amd import pwdf, synth
+
+    torch.cuda.set_device(0)
+    prob = synth.config_problem(2)
+    D = synth.make_density(prob, 2000)
+    Dt = torch.from_numpy(D[None]).cuda()
+    ms = args.fp64_ms
+    c32 = pwdf.LongRangeJ(prob, precision=pwdf.PWDF_FP32_MFMA, max_ndm=1)
+    c32.autotune(1, None)
+    J32 = torch.empty_like(Dt)
+    E32 = torch.empty(1, dtype=torch.float64, device="cuda")
+    ms32 = timed(torch, lambda: c32.build_j(Dt, J32, E32, graph=True), args.steps, args.warmup)
+    fp32 = {"builds_per_s": 1e3 / ms32, "ms_per_build": ms32, "speedup_vs_fp64": ms / ms32,
+            "E_J": float(E32.cpu()[0]), "seg_len": c32.stats()["seg_len"]}
+    np.save(args.j32_out, J32.cpu().numpy()[0])
+    del c32
+    # 16-density batches (distinct densities), per-density throughput
+    ndm = 16
+    Db = torch.from_numpy(synth.make_densities(prob, ndm)).cuda()
+    Jb = torch.empty_like(Db)
+    Eb = torch.empty(ndm, dtype=torch.float64, device="cuda")
+    batched = {}
+    res = {}
+    for name, prec in (("fp64", pwdf.PWDF_FP64), ("fp32_mfma", pwdf.PWDF_FP32_MFMA)):
+        cb = pwdf.LongRangeJ(prob, precision=prec, max_ndm=ndm)
+        cb.autotune(ndm, None)
+        msb = timed(torch, lambda: cb.build_j(Db, Jb, Eb, graph=True), max(5, args.steps // 5), 2)
+        res[name] = (Jb.clone(), Eb.clone())
+        batched[name] = {"ndm": ndm, "ms_per_batch": msb, "density_builds_per_s": ndm * 1e3 / msb,
+                         "speedup_vs_fp64_single": ndm * ms / msb}
+        del cb
+    batched["fp32_mfma"]["max_abs_dJ_vs_fp64_gpu"] = float((res["fp32_mfma"][0] - res["fp64"][0]).abs().max())
+    batched["fp32_mfma"]["max_abs_dE_vs_fp64_gpu"] = float((res["fp32_mfma"][1] - res["fp64"][1]).abs().max())
+    print(json.dumps({"fp32_mfma": fp32, "batched": batched}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,7 +182,13 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32-MFMA and batched measurements")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
+    ap.add_argument("--extras-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--fp64-ms", type=float, default=0.0, help=argparse.SUPPRESS)
+    ap.add_argument("--j32-out", default="", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.extras_only:
+        extras(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; runs on several GPUs are not "
                                    "supported (the long-range J build of one cell runs on one device)"}))
@@ -213,47 +264,35 @@ def main():
         "E_J": E64,
     }
 
+    J32 = None
     if not args.no_extras:
-        # FP32-MFMA form, one density
-        c32 = pwdf.LongRangeJ(prob, precision=pwdf.PWDF_FP32_MFMA, max_ndm=1)
-        c32.autotune(1, None)
-        J32 = torch.empty_like(Dt)
-        E32 = torch.empty(1, dtype=torch.float64, device="cuda")
-        ms32 = timed(torch, lambda: c32.build_j(Dt, J32, E32, graph=True), args.steps, args.warmup)
-        fp32 = {"builds_per_s": 1e3 / ms32, "ms_per_build": ms32, "speedup_vs_fp64": ms / ms32,
-                "E_J": float(E32.cpu()[0]), "seg_len": c32.stats()["seg_len"]}
-        del c32
-        # 16-density batches (distinct densities), per-density throughput
-        ndm = 16
-        Db = torch.from_numpy(synth.make_densities(prob, ndm)).cuda()
-        Jb = torch.empty_like(Db)
-        Eb = torch.empty(ndm, dtype=torch.float64, device="cuda")
-        batched = {}
-        res = {}
-        for name, prec in (("fp64", pwdf.PWDF_FP64), ("fp32_mfma", pwdf.PWDF_FP32_MFMA)):
-            cb = pwdf.LongRangeJ(prob, precision=prec, max_ndm=ndm)
-            cb.autotune(ndm, None)
-            msb = timed(torch, lambda: cb.build_j(Db, Jb, Eb, graph=True), max(5, args.steps // 5), 2)
-            res[name] = (Jb.clone(), Eb.clone())
-            batched[name] = {"ndm": ndm, "ms_per_batch": msb, "density_builds_per_s": ndm * 1e3 / msb,
-                             "speedup_vs_fp64_single": ndm * ms / msb}
-            del cb
-        dJb = float((res["fp32_mfma"][0] - res["fp64"][0]).abs().max())
-        dEb = float((res["fp32_mfma"][1] - res["fp64"][1]).abs().max())
-        batched["fp32_mfma"]["max_abs_dJ_vs_fp64_gpu"] = dJb
-        batched["fp32_mfma"]["max_abs_dE_vs_fp64_gpu"] = dEb
-        out["fp32_mfma"] = fp32
-        out["batched"] = batched
-        del Db, Jb, Eb, res
+        # FP32-MFMA form and 16-density batches in a child process (one more GPU
+        # process for the duration): a failure there is reported, not fatal
+        print("bench: FP32-MFMA and batched measurements (child process)", file=sys.stderr, flush=True)
+        with tempfile.TemporaryDirectory() as td:
+            j32p = os.path.join(td, "j32.npy")
+            cmd = [sys.executable, os.path.abspath(__file__), "--extras-only", "--steps", str(args.steps),
+                   "--warmup", str(args.warmup), "--fp64-ms", repr(ms), "--j32-out", j32p]
+            try:
+                r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+                lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+                if r.returncode == 0 and lines:
+                    out.update(json.loads(lines[-1]))
+                    J32 = np.load(j32p)
+                else:
+                    out["extras_error"] = f"exit status {r.returncode}: {r.stderr[-400:]}"
+            except subprocess.TimeoutExpired:
+                out["extras_error"] = "timed out after 900 s"
+        print("bench: extras done", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         base, ref = cpu_baseline(prob, D)
         out["cpu_baseline"] = base
         out["parity_vs_oracle"] = {"dE_J": abs(E64 - ref["E_G"]),
                                    "max_abs_dJ": float(np.max(np.abs(J64.cpu().numpy()[0] - ref["J"])))}
-        if "fp32_mfma" in out:
+        if "fp32_mfma" in out and J32 is not None:
             out["fp32_mfma"]["dE_J_vs_oracle"] = abs(out["fp32_mfma"]["E_J"] - ref["E_G"])
-            out["fp32_mfma"]["max_abs_dJ_vs_oracle"] = float(np.max(np.abs(J32.cpu().numpy()[0] - ref["J"])))
+            out["fp32_mfma"]["max_abs_dJ_vs_oracle"] = float(np.max(np.abs(J32 - ref["J"])))
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))

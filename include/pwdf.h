@@ -201,10 +201,11 @@ pwdf_status pwdf_grad(pwdf_ctx *ctx, int ndm, const double *Dk, double *dEdR, do
  * the line-segment length (4, 5, 8 or 16 points; 4 or 8 for the FP32-MFMA
  * form) jointly with a common multiplier (1/2, 1 or 2) of the default number of
  * pair chunks of the rho pass and of segment chunks of the J pass, by the wall
- * time of the transform .. back-transform launches captured as a graph and
- * replayed.  The FP32-MFMA form (one launch per angular class L) then lets each
- * class keep the multiplier (1/4 .. 4) of its shortest launch, and keeps that
- * result only if it also wins replayed as a graph.  Last, the independent
+ * time of the transform .. back-transform launches (FP64: captured as a graph
+ * and replayed; FP32-MFMA form: eager launches, segment length first, then the
+ * multiplier).  The FP32-MFMA form (one launch per angular class L) then lets
+ * each class keep the multiplier (1/4 .. 4) of its shortest launch, and keeps
+ * that result only if it also wins overall.  Last, the independent
  * launches of a pass either overlap on the internal streams or follow each
  * other on the caller's stream, whichever replays faster (pwdf_stats.fork).
  * Timing runs on

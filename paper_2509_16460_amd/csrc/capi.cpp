@@ -249,7 +249,7 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
       }
     }
     d.ncolsW = d.ncols32[lmax];
-    d.d32_off[kMaxLsum] = off;
+    d.d32_size = off;
   }
   choose_shapes(p, d, tn, c->max_ndm);
 
@@ -311,10 +311,10 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   d.nblocks = (int)p.blocks.size();
   AL(gblk, M * (size_t)d.nblocks * 6)
   if (d.fp32) {
-    AL(dh32, (size_t)std::max<int64_t>(1, d.d32_off[kMaxLsum]))
+    AL(dh32, (size_t)std::max<int64_t>(1, d.d32_size))
     AL(wre, (size_t)d.nslot * d.ncolsW)
     AL(wim, (size_t)d.nslot * d.ncolsW)
-    if ((e = hipMemset(d.dh32, 0, sizeof(float) * std::max<int64_t>(1, d.d32_off[kMaxLsum]))) != hipSuccess)
+    if ((e = hipMemset(d.dh32, 0, sizeof(float) * std::max<int64_t>(1, d.d32_size))) != hipSuccess)
       return hip_fail(c, e, "clearing operand buffer");
   }
 #undef AL
@@ -899,10 +899,35 @@ static pwdf_status time_tunable(pwdf_ctx *c, int ndm, int reps, std::vector<std:
   return PWDF_OK;
 }
 
+// Wall time per repetition of the tunable part (transform .. back transform)
+// with eager launches on the tuning stream (the FP32-MFMA form's tuner).
+static pwdf_status time_total_eager(pwdf_ctx *c, int ndm, int reps, double &ms_out) {
+  pwdf_status s;
+  hipError_t e;
+  if ((e = hipMemsetAsync(c->dev.Dblk, 0, sizeof(double) * (size_t)ndm * c->plan.nelem, c->cap)) != hipSuccess)
+    return hip_fail(c, e, "tune clear");
+  hipEvent_t a = prof_event(c), b = prof_event(c);
+  if (!a || !b) return fail(c, PWDF_EDEVICE, "tune events");
+  for (int r = -1; r < reps; ++r) {  // r = -1: warm-up
+    if (r == 0 && (e = hipEventRecord(a, c->cap)) != hipSuccess) return hip_fail(c, e, "tune events");
+    if ((s = run_mid_rho(c, ndm, c->Escr, c->cap)) != PWDF_OK) return s;
+    if ((s = run_mid_j(c, ndm, c->cap)) != PWDF_OK) return s;
+  }
+  if ((e = hipEventRecord(b, c->cap)) != hipSuccess || (e = hipEventSynchronize(b)) != hipSuccess)
+    return hip_fail(c, e, "tune events");
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  c->prof_next = 0;
+  ms_out = ms / reps;
+  return PWDF_OK;
+}
+
 // Wall time per repetition of the tunable part (transform .. back transform) as
 // a graph replayed on the tuning stream, the launches of one pass overlapping
-// as the tune's fork setting makes them in a build.
+// as the tune's fork setting makes them in a build.  The FP32-MFMA form times
+// eager launches instead (time_total_eager).
 static pwdf_status time_total(pwdf_ctx *c, int ndm, int reps, double &ms_out) {
+  if (c->prec == PWDF_FP32_MFMA) return time_total_eager(c, ndm, reps, ms_out);
   pwdf_status s;
   hipError_t e;
   if ((e = hipMemsetAsync(c->dev.Dblk, 0, sizeof(double) * (size_t)ndm * c->plan.nelem, c->cap)) != hipSuccess)
@@ -979,36 +1004,51 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
     return r;
   };
   // 1. segment length and a common multiplier (1/2, 1, 2) of the chunk counts of
-  // the pair-G passes, searched jointly (the best multiplier depends on the
-  // segment length): a warm-up, every pair timed once, then the three best
-  // timed again in reverse order, each keeping its shortest time
+  // the pair-G passes: for FP64 searched jointly (the best multiplier depends on
+  // the segment length), for the FP32-MFMA form the segment length at 1 and then
+  // the multipliers for it; a warm-up, every candidate timed once, then the
+  // three best timed again in reverse order, each keeping its shortest time
   const std::vector<int> segs = seg_lengths(c->prec);
   struct Cand {
     Tune t;
     double ms;
   };
   std::vector<Cand> cands;
+  auto add = [&](int sl, double m) {
+    Cand k;
+    k.t.seg_len = sl;
+    for (int L = 0; L <= kMaxLsum; ++L) k.t.mrho[L] = k.t.mj[L] = m;
+    k.ms = 1e300;
+    cands.push_back(k);
+  };
+  auto by_time = [](const Cand &x, const Cand &y) { return x.ms < y.ms; };
+  const bool joint = c->prec == PWDF_FP64;
   for (int sl : segs)
-    for (double m : {1.0, 0.5, 2.0}) {
-      Cand k;
-      k.t.seg_len = sl;
-      for (int L = 0; L <= kMaxLsum; ++L) k.t.mrho[L] = k.t.mj[L] = m;
-      k.ms = 1e300;
-      cands.push_back(k);
-    }
+    for (double m : {1.0, 0.5, 2.0})
+      if (joint || m == 1.0) add(sl, m);
   {
     double ms = 0.0;
     if ((s = measure(cands.back().t, ms)) != PWDF_OK) return s;
   }
   for (Cand &k : cands)
     if ((s = measure(k.t, k.ms)) != PWDF_OK) return s;
-  std::stable_sort(cands.begin(), cands.end(), [](const Cand &x, const Cand &y) { return x.ms < y.ms; });
+  std::stable_sort(cands.begin(), cands.end(), by_time);
+  if (!joint) {
+    // FP32-MFMA form: the multipliers for the fastest segment length only
+    const int sl = cands[0].t.seg_len;
+    const size_t n0 = cands.size();
+    add(sl, 0.5);
+    add(sl, 2.0);
+    for (size_t i = n0; i < cands.size(); ++i)
+      if ((s = measure(cands[i].t, cands[i].ms)) != PWDF_OK) return s;
+    std::stable_sort(cands.begin(), cands.end(), by_time);
+  }
   for (int i = std::min<int>(3, (int)cands.size()) - 1; i >= 0; --i) {
     double ms = 0.0;
     if ((s = measure(cands[i].t, ms)) != PWDF_OK) return s;
     cands[i].ms = std::min(cands[i].ms, ms);
   }
-  std::stable_sort(cands.begin(), cands.end(), [](const Cand &x, const Cand &y) { return x.ms < y.ms; });
+  std::stable_sort(cands.begin(), cands.end(), by_time);
   best = cands[0].t;
   double best_t = cands[0].ms;
   if (best.seg_len != c->plan.seg_len) build_segments(c->plan, best.seg_len);

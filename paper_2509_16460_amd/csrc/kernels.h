@@ -57,6 +57,7 @@ struct Dev {
   int ndmp;
   float *dh32;
   int64_t d32_off[kMaxLsum + 1];
+  int64_t d32_size;  // floats of all classes
   int ncols32[kMaxLsum + 1];
   float *wre, *wim;
   int ncolsW;

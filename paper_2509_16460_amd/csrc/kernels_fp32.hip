@@ -55,11 +55,20 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const SegDesc *__restrict__ se
                                                   const PairHot *__restrict__ hot, int Lp0, int Lp1, int ppc,
                                                   const float *__restrict__ dh32, int64_t d32_off, int ncols,
                                                   int ndmp, int ndm, double2 *__restrict__ part, int row0,
-                                                  int nrows, int nslot) {
+                                                  int nrows, int nslot, const double *__restrict__ start_tab) {
   constexpr int NT = nherm(L);
   constexpr Monos<L> MT{};
   __shared__ PairHot sh[kQTile];
   __shared__ float sc[kQTile * NTG * 16];
+  __shared__ double se2[32];
+  __shared__ double scis[130];
+  for (int i = threadIdx.x; i < kStartTab; i += blockDim.x) {
+    if (i < 32)
+      se2[i] = start_tab[i];
+    else
+      scis[i - 32] = start_tab[i];
+  }
+  __syncthreads();
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, g4 = lane >> 4;
@@ -100,13 +109,13 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const SegDesc *__restrict__ se
         const PairHot h = sh[vq ? q : 0];
         float Sre[T], Sim[T];
         {
-          const double e0 = exp(-sdA.gq0 * h.inv4p);
-          const double eR = exp(-sdA.dg0 * h.inv4p);
+          const double e0 = exp_tab(-sdA.gq0 * h.inv4p, se2);
+          const double eR = exp_tab(-sdA.dg0 * h.inv4p, se2);
           double ph = fma((double)sdA.nu0, h.fu, fma((double)sdA.nv, h.fv, (double)sdA.nw * h.fw));
           ph -= rint(ph);
-          double sn, cs;
-          sincospi(2.0 * ph, &sn, &cs);
-          double Sr = e0 * cs, Si = -e0 * sn;
+          double cs, sn;
+          cis_neg(ph, scis, cs, sn);
+          double Sr = e0 * cs, Si = e0 * sn;
           double Rr = eR * h.cu, Ri = eR * h.su;
 #pragma unroll
           for (int t = 0; t < T; ++t) {
@@ -239,8 +248,18 @@ __global__ __launch_bounds__(256) void k_jpass_mfma(const SegDesc *__restrict__ 
                                                     const float *__restrict__ wre, const float *__restrict__ wim,
                                                     int ncolsW, int ntiles, int ndmp, int ndm,
                                                     const PairHot *__restrict__ hot, int Lp0, int Lp1,
-                                                    double *__restrict__ yhat, int64_t yhat_size, int64_t ycls_off) {
+                                                    double *__restrict__ yhat, int64_t yhat_size, int64_t ycls_off,
+                                                    const double *__restrict__ start_tab) {
   constexpr int NT = nherm(L);
+  __shared__ double se2[32];
+  __shared__ double scis[130];
+  for (int i = threadIdx.x; i < kStartTab; i += blockDim.x) {
+    if (i < 32)
+      se2[i] = start_tab[i];
+    else
+      scis[i - 32] = start_tab[i];
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r16 = lane & 15, g4 = lane >> 4;
   const int np = Lp1 - Lp0;
@@ -257,13 +276,13 @@ __global__ __launch_bounds__(256) void k_jpass_mfma(const SegDesc *__restrict__ 
     const int s = sg0 + g4;
     const bool vs = s < s1;
     const SegDesc sd = segs[vs ? s : s0];
-    const double e0 = exp(-sd.gq0 * h.inv4p);
-    const double eR = exp(-sd.dg0 * h.inv4p);
+    const double e0 = exp_tab(-sd.gq0 * h.inv4p, se2);
+    const double eR = exp_tab(-sd.dg0 * h.inv4p, se2);
     double ph = fma((double)sd.nu0, h.fu, fma((double)sd.nv, h.fv, (double)sd.nw * h.fw));
     ph -= rint(ph);
-    double sn, cs;
-    sincospi(2.0 * ph, &sn, &cs);
-    double Sr = e0 * cs, Si = -e0 * sn;
+    double cs, sn;
+    cis_neg(ph, scis, cs, sn);
+    double Sr = e0 * cs, Si = e0 * sn;
     double Rr = eR * h.cu, Ri = eR * h.su;
     const size_t rowW = (size_t)(vs ? s : s0) * T * ncolsW;
 #pragma unroll
@@ -320,11 +339,11 @@ static hipError_t rho_mfma_one(const Dev &d, int ndm, hipStream_t st) {
   if (d.ncols32[L] == 16)
     hipLaunchKernelGGL((k_rho_mfma<L, T, 1>), grid, dim3(256), 0, st, d.segs, d.nseg, d.hot, d.L_p0[L], d.L_p1[L],
                        d.rho_ppc[L], d.dh32, d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.part, d.rho_row0[L],
-                       d.nrows, d.nslot);
+                       d.nrows, d.nslot, d.start_tab);
   else
     hipLaunchKernelGGL((k_rho_mfma<L, T, (T <= 4 ? 4 : 2)>), grid, dim3(256), 0, st, d.segs, d.nseg, d.hot, d.L_p0[L],
                        d.L_p1[L], d.rho_ppc[L], d.dh32, d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.part,
-                       d.rho_row0[L], d.nrows, d.nslot);
+                       d.rho_row0[L], d.nrows, d.nslot, d.start_tab);
   PWDF_CHECK_LAUNCH32();
   return hipSuccess;
 }
@@ -377,7 +396,7 @@ static hipError_t j_mfma_one(const Dev &d, int ndm, hipStream_t st) {
   dim3 grid((unsigned)((np + 63) / 64), d.j_chunks[L], (unsigned)((ntiles + NTW - 1) / NTW));
   hipLaunchKernelGGL((k_jpass_mfma<L, T, NTW>), grid, dim3(256), 0, st, d.segs, d.nseg, d.j_spc[L], d.wre, d.wim,
                      d.ncolsW, ntiles, d.ndmp, ndm, d.hot, d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size,
-                     d.yhat_off[L]);
+                     d.yhat_off[L], d.start_tab);
   PWDF_CHECK_LAUNCH32();
   return hipSuccess;
 }
