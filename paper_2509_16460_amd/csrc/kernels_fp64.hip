@@ -574,13 +574,26 @@ __device__ __forceinline__ void back_thread(const Dev &dv, int bi, int dm) {
   for (int e = 0; e < NCA * NCB; ++e) J[e] = 0.0;
   for (int q = b.p0; q < b.p1; ++q) {
     const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (q - Lp0);
+    // y_k = sum over the J chunks in chunk order; the loads of four chunks are
+    // issued together (one thread per pair leaves little other parallelism)
     double y[NT];
 #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-      double s = 0.0;
-      for (int c = 0; c < nchunks; ++c) s += ys[((size_t)c * NT + k) * np];
-      y[k] = s;
+    for (int k = 0; k < NT; ++k) y[k] = 0.0;
+    int c = 0;
+    for (; c + 4 <= nchunks; c += 4) {
+      double v[4][NT];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < NT; ++k) v[u][k] = ys[((size_t)(c + u) * NT + k) * np];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < NT; ++k) y[k] += v[u][k];
     }
+    for (; c < nchunks; ++c)
+#pragma unroll
+      for (int k = 0; k < NT; ++k) y[k] += ys[((size_t)c * NT + k) * np];
     double Jt[NT];
 #pragma unroll
     for (int d = 0; d <= L; ++d) {
@@ -839,8 +852,17 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
     __syncthreads();
     const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (q - Lp0);
     for (int k = lane; k < NT; k += 64) {
+      // chunk order kept; four loads in flight
       double s = 0.0;
-      for (int c = 0; c < nchunks; ++c) s += ys[((size_t)c * NT + k) * np];
+      int c = 0;
+      for (; c + 4 <= nchunks; c += 4) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = ys[((size_t)(c + u) * NT + k) * np];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += v[u];
+      }
+      for (; c < nchunks; ++c) s += ys[((size_t)c * NT + k) * np];
       sY[k] = s;
     }
     wave_etabs<LA, LB>(aux + q, sE);
