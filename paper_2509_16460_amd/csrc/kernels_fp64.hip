@@ -806,8 +806,15 @@ __device__ __forceinline__ void transform_wave(const Dev &dv, int bi, int dm, do
       const int nc = ncart(d), r = k - deg_off(d);
       const double *T = ttab + tblk_off(d);
       const double sg = ((d & 3) == 1 || (d & 3) == 2) ? -1.0 : 1.0;
+      // unrolled to the widest degree of the class (predicated) so that the
+      // table loads are issued together instead of one latency after another
+      double tv[ncart(L)];
+#pragma unroll
+      for (int t = 0; t < ncart(L); ++t) tv[t] = t < nc ? T[t * nc + r] : 0.0;
       double s = 0.0;
-      for (int t = 0; t < nc; ++t) s = fma(T[t * nc + r], sH[deg_off(d) + t], s);
+#pragma unroll
+      for (int t = 0; t < ncart(L); ++t)
+        if (t < nc) s = fma(tv[t], sH[deg_off(d) + t], s);
       out[k] = sg * s;
       if (dh32) dh32[d32_off + (size_t)(q - Lp0) * ncols + k * ndmp + dm] = (float)(sg * s);
     }
@@ -873,8 +880,14 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
       const int nc = ncart(d), r = t - deg_off(d);
       const double *T = ttab + tblk_off(d);
       const double sg = ((d & 3) >= 2) ? -1.0 : 1.0;
+      // table loads issued together (see transform_wave)
+      double tv[ncart(L)];
+#pragma unroll
+      for (int k = 0; k < ncart(L); ++k) tv[k] = k < nc ? T[r * nc + k] : 0.0;
       double s = 0.0;
-      for (int k = 0; k < nc; ++k) s = fma(T[r * nc + k], sY[deg_off(d) + k], s);
+#pragma unroll
+      for (int k = 0; k < ncart(L); ++k)
+        if (k < nc) s = fma(tv[k], sY[deg_off(d) + k], s);
       sJ[t] = sg * s;
     }
     __syncthreads();
