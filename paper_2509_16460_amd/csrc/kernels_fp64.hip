@@ -743,13 +743,22 @@ __device__ __forceinline__ void md_axis_lds(double inv2p, double xpa, double xpb
   }
 }
 
+// Wave bodies run four to a workgroup, each on its own pair and LDS slice, so
+// they synchronise their lanes at wavefront scope (LDS writes of the wave
+// visible to its lanes, no wait on the other waves of the workgroup).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Lanes 0..2 build the E table of axis x, y, z (read straight from the pair
 // record in global memory: a lane-indexed field of a local copy would go
 // through scratch).
 template <int LA, int LB>
 __device__ __forceinline__ void wave_etabs(const PairAux *__restrict__ xq, double *sE) {
   using W = WaveTabs<LA, LB>;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   if (lane < 3) md_axis_lds<LA, LB>(0.5 / xq->p, xq->xpa[lane], xq->xpb[lane], sE + lane * W::NE);
 }
 
@@ -770,7 +779,7 @@ __device__ __forceinline__ void transform_wave(const Dev &dv, int bi, int dm, do
   double *sD = sE + 3 * NE;
   double *sH = sD + NCA * NCB;
   int3 *sOff = reinterpret_cast<int3 *>(sH + NT);  // E-table offsets of element (ia, ib) per axis
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const BlockRec b = dv.blocks[bi];
   for (int e = lane; e < NCA * NCB; e += 64) {
     int ax, ay, az, bx, by, bz;
@@ -782,9 +791,9 @@ __device__ __forceinline__ void transform_wave(const Dev &dv, int bi, int dm, do
   double *out_base = dhat + (size_t)dm * dhat_size + cls_off;
   for (int q = b.p0; q < b.p1; ++q) {
     const PairAux x = aux[q];
-    __syncthreads();
+    wave_sync();
     wave_etabs<LA, LB>(aux + q, sE);
-    __syncthreads();
+    wave_sync();
     for (int t = lane; t < NT; t += 64) {
       int tx, ty, tz;
       herm_of(t, tx, ty, tz);
@@ -798,7 +807,7 @@ __device__ __forceinline__ void transform_wave(const Dev &dv, int bi, int dm, do
       }
       sH[t] = s * x.pref_rho;
     }
-    __syncthreads();
+    wave_sync();
     double *out = out_base + (size_t)(q - Lp0) * NT;
     for (int k = lane; k < NT; k += 64) {
       int d = 0;
@@ -837,7 +846,7 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
   double *sY = sE + 3 * NE;
   double *sJ = sY + NT;
   int *sIdx = reinterpret_cast<int *>(sJ + NT);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const BlockRec b = dv.blocks[bi];
   const int np = Lp1 - Lp0;
   for (int t = lane; t < NT; t += 64) {
@@ -856,24 +865,23 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
   }
   for (int q = b.p0; q < b.p1; ++q) {
     const PairAux x = aux[q];
-    __syncthreads();
+    wave_sync();
     const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (q - Lp0);
     for (int k = lane; k < NT; k += 64) {
-      // chunk order kept; four loads in flight
+      // chunk order kept; up to 16 loads in flight
       double s = 0.0;
-      int c = 0;
-      for (; c + 4 <= nchunks; c += 4) {
-        double v[4];
+      for (int c0 = 0; c0 < nchunks; c0 += 16) {
+        double v[16];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = ys[((size_t)(c + u) * NT + k) * np];
+        for (int u = 0; u < 16; ++u) v[u] = c0 + u < nchunks ? ys[((size_t)(c0 + u) * NT + k) * np] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) s += v[u];
+        for (int u = 0; u < 16; ++u)
+          if (c0 + u < nchunks) s += v[u];
       }
-      for (; c < nchunks; ++c) s += ys[((size_t)c * NT + k) * np];
       sY[k] = s;
     }
     wave_etabs<LA, LB>(aux + q, sE);
-    __syncthreads();
+    wave_sync();
     for (int t = lane; t < NT; t += 64) {
       int d = 0;
       while (deg_off(d + 1) <= t) ++d;
@@ -890,7 +898,7 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
         if (k < nc) s = fma(tv[k], sY[deg_off(d) + k], s);
       sJ[t] = sg * s;
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
       if (lane + 64 * r < NEL) {
@@ -1111,31 +1119,43 @@ static bool wave_per_block(int L) { return L >= 3; }
     default: break;                           \
   }
 
-__global__ __launch_bounds__(64) void k_transform_all(const Dev dv, const ClassTab tab) {
-  __shared__ double lds[kWaveLds];
+// Workgroups of 256 threads (many single-wave workgroups launch more slowly than
+// they run): thread mode takes 256 pair blocks per workgroup, wave mode four,
+// one per wave, each wave with its own LDS slice.
+constexpr int kPairWG = 256;
+constexpr int kWavesPerWG = kPairWG / 64;
+
+__global__ __launch_bounds__(kPairWG) void k_transform_all(const Dev dv, const ClassTab tab) {
+  __shared__ double lds[kWavesPerWG * kWaveLds];
   const int i = tab_entry(tab, blockIdx.x);
   const int local = blockIdx.x - tab.first[i];
   const int cl = tab.cls[i];
   const int dm = blockIdx.y;
   if (tab.mode[i]) {
-    PWDF_CLASS_SWITCH_WAVE(transform_wave, dv, dv.cls_b0[cl] + local, dm, lds)
+    const int w = threadIdx.x >> 6;
+    const int bi = dv.cls_b0[cl] + local * kWavesPerWG + w;
+    if (bi >= dv.cls_b1[cl]) return;
+    PWDF_CLASS_SWITCH_WAVE(transform_wave, dv, bi, dm, lds + w * kWaveLds)
   } else {
-    const int bi = dv.cls_b0[cl] + local * 64 + threadIdx.x;
+    const int bi = dv.cls_b0[cl] + local * kPairWG + threadIdx.x;
     if (bi >= dv.cls_b1[cl]) return;
     PWDF_CLASS_SWITCH_THREAD(transform_thread, dv, bi, dm)
   }
 }
 
-__global__ __launch_bounds__(64) void k_back_all(const Dev dv, const ClassTab tab) {
-  __shared__ double lds[kWaveLds];
+__global__ __launch_bounds__(kPairWG) void k_back_all(const Dev dv, const ClassTab tab) {
+  __shared__ double lds[kWavesPerWG * kWaveLds];
   const int i = tab_entry(tab, blockIdx.x);
   const int local = blockIdx.x - tab.first[i];
   const int cl = tab.cls[i];
   const int dm = blockIdx.y;
   if (tab.mode[i]) {
-    PWDF_CLASS_SWITCH_WAVE(back_wave, dv, dv.cls_b0[cl] + local, dm, lds)
+    const int w = threadIdx.x >> 6;
+    const int bi = dv.cls_b0[cl] + local * kWavesPerWG + w;
+    if (bi >= dv.cls_b1[cl]) return;
+    PWDF_CLASS_SWITCH_WAVE(back_wave, dv, bi, dm, lds + w * kWaveLds)
   } else {
-    const int bi = dv.cls_b0[cl] + local * 64 + threadIdx.x;
+    const int bi = dv.cls_b0[cl] + local * kPairWG + threadIdx.x;
     if (bi >= dv.cls_b1[cl]) return;
     PWDF_CLASS_SWITCH_THREAD(back_thread, dv, bi, dm)
   }
@@ -1283,7 +1303,7 @@ static ClassTab pair_class_tab(const Dev &d) {
       const int cl = la * 4 + lb, nb = d.cls_b1[cl] - d.cls_b0[cl];
       if (nb <= 0) continue;
       const int wave = wave_per_block(la + lb) ? 1 : 0;
-      add_entry(t, cl, wave, 0, wave ? nb : (nb + 63) / 64);
+      add_entry(t, cl, wave, 0, wave ? (nb + kWavesPerWG - 1) / kWavesPerWG : (nb + kPairWG - 1) / kPairWG);
     }
   return t;
 }
@@ -1291,7 +1311,7 @@ static ClassTab pair_class_tab(const Dev &d) {
 hipError_t launch_transform_all(const Dev &d, int ndm, hipStream_t st) {
   const ClassTab t = pair_class_tab(d);
   if (t.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_transform_all, dim3((unsigned)t.first[t.n], ndm), dim3(64), 0, st, d, t);
+  hipLaunchKernelGGL(k_transform_all, dim3((unsigned)t.first[t.n], ndm), dim3(kPairWG), 0, st, d, t);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -1299,7 +1319,7 @@ hipError_t launch_transform_all(const Dev &d, int ndm, hipStream_t st) {
 hipError_t launch_back_all(const Dev &d, int ndm, hipStream_t st) {
   const ClassTab t = pair_class_tab(d);
   if (t.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_back_all, dim3((unsigned)t.first[t.n], ndm), dim3(64), 0, st, d, t);
+  hipLaunchKernelGGL(k_back_all, dim3((unsigned)t.first[t.n], ndm), dim3(kPairWG), 0, st, d, t);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }
