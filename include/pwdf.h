@@ -42,9 +42,11 @@
  *   allocated in pwdf_create; pwdf_build_j and pwdf_grad do not allocate.
  *   Device calls only enqueue work on the given HIP stream (NULL: the null
  *   stream); results are valid after the stream is synchronised.  Independent
- *   per-class launches inside one call fan out over internal streams of the
- *   context (default priority) and join back into the given stream before the
- *   next dependent step, so stream order is preserved.  One context must not be
+ *   launches inside one call (the class groups of a pass) either fan out over
+ *   internal streams of the context (default priority) and join back into the
+ *   given stream before the next dependent step, or follow each other on it
+ *   (pwdf_stats.fork, chosen by pwdf_autotune; default: fan out); stream order
+ *   is preserved either way.  One context must not be
  *   used by two streams at once: calls on one context that overlap in time
  *   (different streams, or a graph replay racing an eager call) race on its
  *   workspaces.  Distinct contexts are independent.
@@ -164,8 +166,9 @@ pwdf_status pwdf_build_j(pwdf_ctx *ctx, int ndm, const double *Dk, double *Jk, d
  * (ndm, Dk, Jk, EJ) captures the whole launch sequence (fork/join branches
  * included) on an internal stream, instantiates it and keeps it in the context;
  * this and later calls with the same arguments launch the instantiated graph on
- * `stream` (one launch instead of about a dozen kernel launches).  Results equal those of pwdf_build_j
- * bit for bit (same kernels, same shapes).  A call with other arguments,
+ * `stream` (one launch instead of about a dozen kernel launches).  Results
+ * equal those of pwdf_build_j bit for bit (same kernels, same shapes).  A call
+ * with other arguments,
  * pwdf_autotune or pwdf_destroy drops the cached graph.  The graph holds kernel
  * launches and event dependencies only (no memset or copy nodes).
  * Errors: as pwdf_build_j; PWDF_ESTATE while profiling is enabled.
