@@ -33,8 +33,9 @@
  *             (m1*n2 + m2)*n3 + m3.
  *   D(k),J(k) complex128 interleaved (re, im), [ndm][nk][nbf][nbf] row-major;
  *             D(L) pairs phi_mu in cell 0 with phi_nu in cell L.  Each D(k)
- *             must be Hermitian; the result depends only on its Hermitian
- *             part, and J(k) is Hermitian.
+ *             must be Hermitian: of each pair D_mu,nu(k), D_nu,mu(k) only one
+ *             is read (chosen per shell pair), so a non-Hermitian input gives
+ *             a mix of its two triangles.  J(k) is Hermitian.
  *
  * Ownership and streams
  *   The caller owns every input and output buffer; the library never frees or

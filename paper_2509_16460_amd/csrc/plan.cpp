@@ -9,6 +9,7 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <map>
@@ -475,15 +476,23 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
     p.sD_code.clear();
     p.sD_e0.clear();
     p.eD.clear();
-    std::vector<std::pair<int, int>> ents, dents;  // (code, element offset)
+    std::vector<std::pair<int, int>> ents;  // (code, element offset)
+    // D side: (element of D(k) read, class code, D(L) offset) of every direct
+    // block entry.  The element read is (mu, nu) with the class of m, or, when
+    // shell a has more Cartesian components than shell b, the transposed
+    // element (nu, mu) with the class of -m (Hermitian D(k):
+    // Re e^{ik.m} D_mu,nu(k) = Re e^{-ik.m} D_nu,mu(k)): a row of D(k) then
+    // holds ncart(la) consecutive elements of the block instead of ncart(lb),
+    // so the lines fetched carry more of the support.
+    std::vector<std::array<int, 3>> dtrip;
     for (int mu = 0; mu < nbf; ++mu)
       for (int nu = 0; nu < nbf; ++nu) {
         size_t e = (size_t)mu * nbf + nu;
         p.sJ_off[e] = (int)p.sJ_code.size();
         int sa = p.bf_shell[mu], sb = p.bf_shell[nu];
         int a = p.bf_comp[mu], b = p.bf_comp[nu];
+        const bool dT = ncart(in.sh_l[sa]) > ncart(in.sh_l[sb]);
         ents.clear();
-        dents.clear();
         for (int i = p.sp_off[(size_t)sa * ns + sb]; i < p.sp_off[(size_t)sa * ns + sb + 1]; ++i) {
           const GatherEnt &g = p.sp_ent[i];
           const BlockRec &br = p.blocks[g.blk];
@@ -491,10 +500,10 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
           int64_t joff = br.eoff + (g.tr ? (int64_t)b * ncb + a : (int64_t)a * ncb + b);
           int code = code_of(p.imgs[g.img], g.tr ? -1 : 1);
           ents.push_back({code, (int)joff});
-          if (!g.tr) dents.push_back({code, (int)joff});
+          if (!g.tr)
+            dtrip.push_back({dT ? nu * nbf + mu : (int)e, dT ? code_of(p.imgs[g.img], -1) : code, (int)joff});
         }
         std::sort(ents.begin(), ents.end());
-        std::sort(dents.begin(), dents.end());
         for (size_t i = 0; i < ents.size(); ++i) {
           if (i == 0 || ents[i].first != ents[i - 1].first) {
             p.sJ_code.push_back(ents[i].first);
@@ -502,19 +511,22 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
           }
           p.eJ.push_back(ents[i].second);
         }
-        for (size_t i = 0; i < dents.size(); ++i) {
-          if (i == 0 || dents[i].first != dents[i - 1].first) {
-            p.sD_el.push_back((int)e);
-            p.sD_code.push_back(dents[i].first);
-            p.sD_e0.push_back((int)p.eD.size());
-          }
-          p.eD.push_back(dents[i].second);
-        }
-        if (!dents.empty()) ++p.nD_support;
         if ((int)p.sJ_code.size() - p.sJ_off[e] > kPhaseLight) p.heavyJ.push_back((int)e);
       }
     p.sJ_off[(size_t)nbf * nbf] = (int)p.sJ_code.size();
     p.sJ_e0.push_back((int)p.eJ.size());
+    // D segments: one per (element read, class), ordered by element
+    std::sort(dtrip.begin(), dtrip.end());
+    for (size_t i = 0; i < dtrip.size(); ++i) {
+      const bool new_el = i == 0 || dtrip[i][0] != dtrip[i - 1][0];
+      if (new_el || dtrip[i][1] != dtrip[i - 1][1]) {
+        p.sD_el.push_back(dtrip[i][0]);
+        p.sD_code.push_back(dtrip[i][1]);
+        p.sD_e0.push_back((int)p.eD.size());
+      }
+      if (new_el) ++p.nD_support;
+      p.eD.push_back(dtrip[i][2]);
+    }
     p.sD_e0.push_back((int)p.eD.size());
   }
 
