@@ -421,7 +421,8 @@ double cls_pairs(const Plan &p, int cl) {
   return (double)(p.blocks[p.cls_b1[cl] - 1].p1 - p.blocks[p.cls_b0[cl]].p0);
 }
 
-// transform .. reduce (Dblk already holds D(L)); EJ device [ndm]
+// transform .. reduce (Dblk already holds D(L)); EJ device [ndm], or null to
+// leave the energy partials for the J(k) launch
 pwdf_status run_mid_rho(pwdf_ctx *c, int ndm, double *EJ, hipStream_t st) {
   const Plan &p = c->plan;
   const Dev &d = c->dev;
@@ -513,7 +514,9 @@ pwdf_status run_mid_j(pwdf_ctx *c, int ndm, hipStream_t st) {
   return step(c, "back", total_pairs(p) * ndm, st, [&] { return launch_back_all(d, ndm, st); });
 }
 
-pwdf_status run_from_V(pwdf_ctx *c, int ndm, double *Jk, hipStream_t st) {
+// EJ: device [ndm] summed by the J(k) launch from the energy partials of the
+// preceding reduce (which was given EJ = null), or null
+pwdf_status run_from_V(pwdf_ctx *c, int ndm, double *Jk, double *EJ, hipStream_t st) {
   const Plan &p = c->plan;
   const Dev &d = c->dev;
   pwdf_status s;
@@ -521,13 +524,13 @@ pwdf_status run_from_V(pwdf_ctx *c, int ndm, double *Jk, hipStream_t st) {
   if ((s = step(c, "fold_j", (double)p.eJ.size() * ndm, st, [&] { return launch_fold_j(d, ndm, st); })) != PWDF_OK)
     return s;
   return step(c, "phase_j", (double)p.nk * p.nbf * (double)p.nbf * ndm, st,
-              [&] { return launch_phase_j(d, ndm, Jk, st); });
+              [&] { return launch_phase_j(d, ndm, Jk, EJ, st); });
 }
 
 pwdf_status enqueue_build(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, double *EJ, hipStream_t st) {
   pwdf_status s;
-  if ((s = run_to_rho(c, ndm, Dk, EJ, st)) != PWDF_OK) return s;
-  return run_from_V(c, ndm, Jk, st);
+  if ((s = run_to_rho(c, ndm, Dk, nullptr, st)) != PWDF_OK) return s;
+  return run_from_V(c, ndm, Jk, EJ, st);
 }
 
 }  // namespace

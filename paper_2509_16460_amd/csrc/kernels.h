@@ -91,13 +91,15 @@ hipError_t launch_transform_all(const Dev &d, int ndm, hipStream_t st);
 hipError_t launch_back_all(const Dev &d, int ndm, hipStream_t st);
 // rho of the class group 0 (L <= 2) or 1 (L >= 3)
 hipError_t launch_rho_group(const Dev &d, int group, int ndm, hipStream_t st);
+// EJ null: leave the energy partials for the J(k) launch to sum
 hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st);
 // J moments (force = false) or force moments of degree L+1 (force = true) of the
 // class group 0 (L <= 2) or 1 (L >= 3)
 hipError_t launch_jpass_group(const Dev &d, int group, bool force, int ndm, hipStream_t st);
 bool jpass_group_nonempty(const Dev &d, int group);
 hipError_t launch_fold_j(const Dev &d, int ndm, hipStream_t st);
-hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, hipStream_t st);
+// EJ non-null: one more block per density sums the energy partials into EJ
+hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, double *EJ, hipStream_t st);
 // gradient
 hipError_t launch_force_back_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st);
 hipError_t launch_force_atoms(const Dev &d, int ndm, double *dEdR, hipStream_t st);

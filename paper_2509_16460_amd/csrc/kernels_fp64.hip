@@ -411,12 +411,13 @@ __global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ part
   if (threadIdx.x == 0) Epart[(size_t)dm * gridDim.x + blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
-__global__ __launch_bounds__(256) void k_energy(const double *__restrict__ Epart, int nparts,
-                                                double *__restrict__ EJ) {
-  const int dm = blockIdx.x;
+// E_J of density dm from its energy partials, by one 256-thread block in a fixed
+// order (sh: 256 doubles of LDS).  Shared by k_energy and the extra block of the
+// J(k) launch, so both give the same bits.
+__device__ inline void energy_block(const double *__restrict__ Epart, int nparts, double *__restrict__ EJ, int dm,
+                                    double *sh) {
   double e = 0.0;
   for (int i = threadIdx.x; i < nparts; i += blockDim.x) e += Epart[(size_t)dm * nparts + i];
-  __shared__ double sh[256];
   sh[threadIdx.x] = e;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -424,6 +425,12 @@ __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ Epart
     __syncthreads();
   }
   if (threadIdx.x == 0) EJ[dm] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_energy(const double *__restrict__ Epart, int nparts,
+                                                double *__restrict__ EJ) {
+  __shared__ double sh[256];
+  energy_block(Epart, nparts, EJ, blockIdx.x, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1248,14 +1255,23 @@ __global__ __launch_bounds__(256) void k_jpass_all(const Dev dv, const ClassTab 
 #undef PWDF_JCASE
 }
 
-// J(L) -> J(k): blocks [0, nlight) take 256 elements each (light path), the rest
-// four heavy elements each (one wave per element).
+// J(L) -> J(k): blocks [0, nlight) take 256 elements each (light path), the next
+// ones four heavy elements each (one wave per element).  With EJ non-null the
+// last block of each density sums its energy partials into EJ instead (saves the
+// separate k_energy launch on the J build path).
 __global__ __launch_bounds__(256) void k_phase_j_all(const double *__restrict__ Jfold, int nsegJ,
                                                      const int *__restrict__ sJ_off, const int *__restrict__ sJ_code,
                                                      const int *__restrict__ heavy, int nheavy, int nlight,
                                                      const double2 *__restrict__ ptab, int ptab_len, int nk, int n1,
-                                                     int n2, int n3, int nbf, double2 *__restrict__ Jk) {
+                                                     int n2, int n3, int nbf, double2 *__restrict__ Jk,
+                                                     const double *__restrict__ Epart, int nparts,
+                                                     double *__restrict__ EJ) {
   __shared__ double2 sph[kPtabMax];
+  static_assert(kPtabMax * 2 >= 256, "the energy block reuses the phase table's LDS");
+  if (EJ != nullptr && blockIdx.x == gridDim.x - 1) {
+    energy_block(Epart, nparts, EJ, blockIdx.y, reinterpret_cast<double *>(sph));
+    return;
+  }
   for (int i = threadIdx.x; i < ptab_len; i += blockDim.x) sph[i] = ptab[i];
   __syncthreads();
   const int dm = blockIdx.y;
@@ -1436,15 +1452,15 @@ hipError_t launch_fold_j(const Dev &d, int ndm, hipStream_t st) {
   return hipSuccess;
 }
 
-hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, hipStream_t st) {
+hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, double *EJ, hipStream_t st) {
   if (d.ptab_len > kPtabMax) return hipErrorInvalidValue;
   const int64_t nn = (int64_t)d.nbf * d.nbf;
   const int nlight = (int)((nn + 255) / 256);
   const int nheavy_blocks = (d.nheavyJ + 3) / 4;
-  dim3 grid((unsigned)(nlight + nheavy_blocks), ndm);
+  dim3 grid((unsigned)(nlight + nheavy_blocks + (EJ ? 1 : 0)), ndm);
   hipLaunchKernelGGL(k_phase_j_all, grid, dim3(256), 0, st, d.Jfold, d.nsegJ, d.sJ_off, d.sJ_code, d.heavyJ,
                      d.nheavyJ, nlight, d.ptab, d.ptab_len, d.nk, d.kmesh[0], d.kmesh[1], d.kmesh[2], d.nbf,
-                     (double2 *)Jk);
+                     (double2 *)Jk, d.Epart, d.nred_blocks, EJ);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -1458,6 +1474,7 @@ hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce, g2, dim3(256), 0, st, d.part2, d.ngroups, d.nslot, d.slot_v, d.vol, d.rho, d.Vc,
                      d.Epart);
   PWDF_CHECK_LAUNCH();
+  if (EJ == nullptr) return hipSuccess;  // summed by the J(k) launch
   hipLaunchKernelGGL(k_energy, dim3(ndm), dim3(256), 0, st, d.Epart, d.nred_blocks, EJ);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
