@@ -259,6 +259,8 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   UP(p.segs, segs)
   UP(p.slot_v, slot_v)
   UP(p.hot, hot)
+  UP(p.hot_rho, hot_rho)
+  UP(p.rho_rank, rho_rank)
   UP(p.aux, aux)
   UP(p.blocks, blocks)
   UP(p.elem_blk, elem_blk)

@@ -17,6 +17,8 @@ struct Dev {
   const SegDesc *segs;
   const double *slot_v;
   const PairHot *hot;
+  const PairHot *hot_rho;        // pair records in the rho pass's order (sorted by p for L <= 2)
+  const int *rho_rank;           // pair -> position in that order (where its coefficients go)
   const PairAux *aux;
   const BlockRec *blocks;
   const int *elem_blk;

@@ -165,7 +165,7 @@ __device__ __forceinline__ void transform_thread(const Dev &dv, int bi, int dm) 
             }
           }
       }
-    double *out = out_base + (size_t)(q - Lp0) * NT;
+    double *out = out_base + (size_t)(dv.rho_rank[q] - Lp0) * NT;  // rho's walk order
 #pragma unroll
     for (int d = 0; d <= L; ++d) {
       const int nc = ncart(d);
@@ -208,7 +208,7 @@ template <int L, int SEG, int NDB>
 __device__ __forceinline__ void rho_pair(const double *__restrict__ r, const SegDesc &sd, const double (&mv)[L + 1],
                                          const double (&mw)[L + 1], double (&accr)[NDB][SEG],
                                          double (&acci)[NDB][SEG], const double *__restrict__ e2,
-                                         const double2 *__restrict__ cis) {
+                                         const double2 *__restrict__ cis, double &pc, double &e0, double &eR) {
   constexpr int NT = nherm(L);
   constexpr Monos<L> MT{};
   const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
@@ -229,8 +229,15 @@ __device__ __forceinline__ void rho_pair(const double *__restrict__ r, const Seg
         cr[b][a] += t;
     }
   }
-  const double e0 = exp_tab(-sd.gq0 * inv4p, e2);
-  const double eR = exp_tab(-sd.dg0 * inv4p, e2);
+  // |S| and |R| at the segment start depend on the pair only through p: the low
+  // classes (walked in order of p) keep them from the previous pair of this wave
+  // when its p is the same; the high classes, whose register pressure makes the
+  // branch cost more than the exponentials, always evaluate them
+  if (L > 2 || inv4p != pc) {
+    pc = inv4p;
+    e0 = exp_tab(-sd.gq0 * inv4p, e2);
+    eR = exp_tab(-sd.dg0 * inv4p, e2);
+  }
   double ph = fma(nu0, fu, fma(nv, fv, nw * fw));
   ph -= rint(ph);
   const double2 w = cis_neg(ph, cis);
@@ -275,7 +282,7 @@ __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int
   constexpr int REC = 8 + NT * NDB;
   constexpr int TP = RhoTile<L>::TP;
   const SegDesc *__restrict__ segs = dv.segs;
-  const PairHot *__restrict__ hot = dv.hot;
+  const PairHot *__restrict__ hot = dv.hot_rho;  // walk order, as the coefficients
   const double *__restrict__ dhat = dv.dhat;
   double2 *__restrict__ part = dv.part;
   const int nseg = dv.nseg, Lp0 = dv.L_p0[L], Lp1 = dv.L_p1[L], pairs_per_chunk = dv.rho_ppc[L];
@@ -301,6 +308,7 @@ __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int
 #pragma unroll
     for (int s = 0; s < SEG; ++s) accr[b][s] = acci[b][s] = 0.0;
   const int dm0 = db * NDB;
+  double pc = -1.0, e0 = 0.0, eR = 0.0;  // p-dependent start factors of the last pair (inv4p > 0)
   for (int t0 = p0; t0 < p1; t0 += TP) {
     const int nt = min(TP, p1 - t0);
     __syncthreads();
@@ -318,7 +326,8 @@ __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int
       sp[i] = v;
     }
     __syncthreads();
-    for (int j = w; j < nt; j += W) rho_pair<L, SEG, NDB>(sp + j * REC, sd, mv, mw, accr, acci, e2, cis);
+    for (int j = w; j < nt; j += W)
+      rho_pair<L, SEG, NDB>(sp + j * REC, sd, mv, mw, accr, acci, e2, cis, pc, e0, eR);
   }
   // the W waves' partial sums are added in LDS in fixed order, one density at a time
   if (W > 1) {
@@ -815,7 +824,7 @@ __device__ __forceinline__ void transform_wave(const Dev &dv, int bi, int dm, do
       sH[t] = s * x.pref_rho;
     }
     wave_sync();
-    double *out = out_base + (size_t)(q - Lp0) * NT;
+    double *out = out_base + (size_t)(dv.rho_rank[q] - Lp0) * NT;  // rho's walk order
     for (int k = lane; k < NT; k += 64) {
       int d = 0;
       while (deg_off(d + 1) <= k) ++d;

@@ -389,6 +389,19 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
     p.dhat_off[kMaxLsum] = off;
     p.dhat_size = off;
   }
+  {
+    std::vector<int> order(p.hot.size());
+    for (size_t i = 0; i < p.hot.size(); ++i) order[i] = (int)i;
+    for (int L = 0; L <= 2; ++L)  // the classes whose rho pass reuses p-dependent factors
+      std::stable_sort(order.begin() + p.L_p0[L], order.begin() + p.L_p1[L],
+                       [&](int x, int y) { return p.hot[x].inv4p < p.hot[y].inv4p; });
+    p.rho_rank.resize(p.hot.size());
+    p.hot_rho.resize(p.hot.size());
+    for (size_t r = 0; r < order.size(); ++r) {
+      p.rho_rank[order[r]] = (int)r;
+      p.hot_rho[r] = p.hot[order[r]];
+    }
+  }
   p.elem_blk.resize(p.nelem);
   for (int b = 0; b < (int)p.blocks.size(); ++b) {
     const BlockRec &br = p.blocks[b];

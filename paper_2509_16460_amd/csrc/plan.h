@@ -44,6 +44,13 @@ struct Plan {
   std::vector<PairAux> aux;
   int cls_b0[16], cls_b1[16];  // block range of class (la, lb), index la*4 + lb
   int L_p0[kMaxLsum + 1], L_p1[kMaxLsum + 1];  // pair range of class L
+  // The rho pass walks each class range [L_p0, L_p1) in its own order: sorted by
+  // p (stable) for L <= 2, so that consecutive pairs mostly share e^{-|G|^2/4p},
+  // storage order for L >= 3.  rho_rank[pair] is the pair's position in that walk
+  // (the density transform writes its coefficients there), hot_rho the pair
+  // records in walk order.
+  std::vector<int> rho_rank;
+  std::vector<PairHot> hot_rho;
   int64_t dhat_off[kMaxLsum + 1];             // offset of class L in a per-density coefficient array
   int64_t dhat_size = 0;
   int64_t nelem = 0;                          // sum over blocks of ncart(la) ncart(lb)
