@@ -1265,9 +1265,10 @@ __global__ __launch_bounds__(256) void k_jpass_all(const Dev dv, const ClassTab 
 }
 
 // J(L) -> J(k): blocks [0, nlight) take 256 elements each (light path), the next
-// ones four heavy elements each (one wave per element).  With EJ non-null the
-// last block of each density sums its energy partials into EJ instead (saves the
-// separate k_energy launch on the J build path).
+// ones four heavy elements each (one wave per element).  With EJ non-null one more
+// block of each density, dispatched first so that it overlaps the others, sums
+// its energy partials into EJ (saves the separate k_energy launch on the J build
+// path) and the element blocks follow it.
 __global__ __launch_bounds__(256) void k_phase_j_all(const double *__restrict__ Jfold, int nsegJ,
                                                      const int *__restrict__ sJ_off, const int *__restrict__ sJ_code,
                                                      const int *__restrict__ heavy, int nheavy, int nlight,
@@ -1277,19 +1278,20 @@ __global__ __launch_bounds__(256) void k_phase_j_all(const double *__restrict__ 
                                                      double *__restrict__ EJ) {
   __shared__ double2 sph[kPtabMax];
   static_assert(kPtabMax * 2 >= 256, "the energy block reuses the phase table's LDS");
-  if (EJ != nullptr && blockIdx.x == gridDim.x - 1) {
+  if (EJ != nullptr && blockIdx.x == 0) {
     energy_block(Epart, nparts, EJ, blockIdx.y, reinterpret_cast<double *>(sph));
     return;
   }
+  const int bx = (int)blockIdx.x - (EJ != nullptr ? 1 : 0);
   for (int i = threadIdx.x; i < ptab_len; i += blockDim.x) sph[i] = ptab[i];
   __syncthreads();
   const int dm = blockIdx.y;
-  if ((int)blockIdx.x < nlight)
+  if (bx < nlight)
     phase_j_light(sph, Jfold, nsegJ, sJ_off, sJ_code, nk, n1, n2, n3, nbf, Jk,
-                  (int64_t)blockIdx.x * blockDim.x + threadIdx.x, dm);
+                  (int64_t)bx * blockDim.x + threadIdx.x, dm);
   else
     phase_j_heavy(sph, Jfold, nsegJ, heavy, nheavy, sJ_off, sJ_code, nk, n2, n3, nbf, Jk,
-                  (blockIdx.x - nlight) * 4 + (threadIdx.x >> 6), dm);
+                  (bx - nlight) * 4 + (threadIdx.x >> 6), dm);
 }
 
 // ---------------------------------------------------------------------------
