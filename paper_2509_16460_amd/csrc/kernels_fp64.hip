@@ -1322,16 +1322,18 @@ static void add_entry(ClassTab &t, int cls, int mode, int gx, int nblocks) {
   ++t.n;
 }
 
-// transform / back: one entry per non-empty class (la, lb)
+// transform / back: one entry per non-empty class (la, lb); the wave-mode classes
+// first, so that their long per-pair chains start early and overlap the
+// thread-mode blocks instead of forming the launch's tail
 static ClassTab pair_class_tab(const Dev &d) {
   ClassTab t{};
-  for (int la = 0; la <= kMaxL; ++la)
-    for (int lb = 0; lb <= la; ++lb) {
-      const int cl = la * 4 + lb, nb = d.cls_b1[cl] - d.cls_b0[cl];
-      if (nb <= 0) continue;
-      const int wave = wave_per_block(la + lb) ? 1 : 0;
-      add_entry(t, cl, wave, 0, wave ? (nb + kWavesPerWG - 1) / kWavesPerWG : (nb + kPairWG - 1) / kPairWG);
-    }
+  for (int wave = 1; wave >= 0; --wave)
+    for (int la = 0; la <= kMaxL; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        const int cl = la * 4 + lb, nb = d.cls_b1[cl] - d.cls_b0[cl];
+        if (nb <= 0 || (wave_per_block(la + lb) ? 1 : 0) != wave) continue;
+        add_entry(t, cl, wave, 0, wave ? (nb + kWavesPerWG - 1) / kWavesPerWG : (nb + kPairWG - 1) / kPairWG);
+      }
   return t;
 }
 
