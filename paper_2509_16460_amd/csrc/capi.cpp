@@ -134,6 +134,13 @@ void drop_graph(pwdf_ctx *c) {
 // whether or not all 64 pairs are present, so the J weights count padded lanes.
 // Per pair and point the cost is about 2L + 10 operations plus the segment start
 // (two exponentials, one sincos, the NT coefficients) spread over SEG points.
+// In the FP64 rho pass each class group (L <= 2, L >= 3: its two launches) gets
+// at least kMinGroupWaves of the waves: a group with little work, usually the
+// high classes, would otherwise run as a few long waves, and that latency is its
+// launch time whenever it does not overlap the other group.  (The J pass keeps
+// the plain share: more high-class J chunks cost more in the back-transform,
+// which sums them, than they save.)  A rho chunk holds at least 4 pairs (the 4
+// waves of its blocks share them).
 // The tune multipliers scale the chunk counts per class.
 void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
   const int SEG = p.seg_len;
@@ -155,6 +162,20 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
   const int rho_waves_per_chunk = std::max(4, ((p.nseg() + 63) / 64) * 4);
   wsumR = std::max(wsumR, 1.0);  // no pairs: every class is skipped below
   wsumJ = std::max(wsumJ, 1.0);
+  constexpr double kMinGroupWaves = 1024.0;
+  double gR[2] = {0.0, 0.0}, gJ[2] = {0.0, 0.0};
+  for (int L = 0; L <= kMaxLsum; ++L) {
+    gR[L > 2] += wR[L];
+    gJ[L > 2] += wJ[L];
+  }
+  double tR[2], tJ[2];  // waves of each group
+  for (int g = 0; g < 2; ++g) {
+    tR[g] = target * gR[g] / wsumR;
+    if (!d.fp32) tR[g] = std::max(tR[g], kMinGroupWaves);
+    tJ[g] = target * gJ[g] / wsumJ;
+    gR[g] = std::max(gR[g], 1.0);
+    gJ[g] = std::max(gJ[g], 1.0);
+  }
   int rows = 0;
   int64_t yoff = 0;
   for (int L = 0; L <= kMaxLsum; ++L) {
@@ -168,15 +189,15 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
       d.j_spc[L] = 1;
       continue;
     }
-    int ch = (int)std::lround(target * (wR[L] / wsumR) * tn.mrho[L] / rho_waves_per_chunk);
-    ch = std::max(1, std::min(np, ch));
+    int ch = (int)std::lround(tR[L > 2] * (wR[L] / gR[L > 2]) * tn.mrho[L] / rho_waves_per_chunk);
+    ch = std::max(1, std::min((np + 3) / 4, ch));
     int ppc = (np + ch - 1) / ch;
     ch = (np + ppc - 1) / ppc;
     d.rho_chunks[L] = ch;
     d.rho_ppc[L] = ppc;
     rows += ch;
     const int jw = (np + 63) / 64;  // active waves per segment chunk
-    int jc = (int)std::lround(target * (wJ[L] / wsumJ) * tn.mj[L] / jw);
+    int jc = (int)std::lround(tJ[L > 2] * (wJ[L] / gJ[L > 2]) * tn.mj[L] / jw);
     jc = std::max(1, std::min(p.nseg(), jc));
     int spc = std::max(1, (p.nseg() + jc - 1) / jc);
     jc = (p.nseg() + spc - 1) / spc;  // 0 when the G set is empty
