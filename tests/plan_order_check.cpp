@@ -1,0 +1,79 @@
+// Invariants of the pair order the rho pass walks (plan.cpp), checked on the
+// host: rho_rank is a permutation that maps every class range [L_p0, L_p1) onto
+// itself; hot_rho holds the pair records in that order (bit for bit); the classes
+// L <= 2 are sorted by p (1/(4p) ascending) with ties kept in storage order; the
+// classes L >= 3 keep storage order.  Reads the problem as whitespace-separated
+// text: lattice (9), natm and xyz, nshell and shell atoms, shell l, shell primitive
+// counts, primitive count and exponents, coefficients, kmesh (3), omega, eps_pair,
+// eps_G, r_max.  Prints "pairs <n> classes <m> bad <b>" and exits non-zero on a
+// violation.
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <vector>
+
+#include "plan.h"
+
+using namespace pwdf;
+
+int main(int argc, char **argv) {
+  if (argc < 2) return 2;
+  std::ifstream f(argv[1]);
+  PlanInput in;
+  for (double &x : in.lattice) f >> x;
+  f >> in.natm;
+  in.xyz.resize(3 * in.natm);
+  for (double &x : in.xyz) f >> x;
+  f >> in.nshell;
+  in.sh_atom.resize(in.nshell);
+  in.sh_l.resize(in.nshell);
+  in.sh_nprim.resize(in.nshell);
+  for (int &x : in.sh_atom) f >> x;
+  for (int &x : in.sh_l) f >> x;
+  for (int &x : in.sh_nprim) f >> x;
+  int nprim = 0;
+  f >> nprim;
+  in.exps.resize(nprim);
+  in.coefs.resize(nprim);
+  for (double &x : in.exps) f >> x;
+  for (double &x : in.coefs) f >> x;
+  f >> in.kmesh[0] >> in.kmesh[1] >> in.kmesh[2] >> in.omega >> in.eps_pair >> in.eps_G >> in.r_max;
+  if (!f) return 2;
+  Plan p;
+  const std::string err = build_plan(in, 8, p);
+  if (!err.empty()) {
+    std::printf("plan error: %s\n", err.c_str());
+    return 2;
+  }
+  const int n = (int)p.hot.size();
+  long bad = 0;
+  if ((int)p.rho_rank.size() != n || (int)p.hot_rho.size() != n) {
+    std::printf("pairs %d classes 0 bad 1\n", n);
+    return 1;
+  }
+  std::vector<int> order(n, -1);
+  int classes = 0;
+  for (int L = 0; L <= kMaxLsum; ++L) {
+    const int p0 = p.L_p0[L], p1 = p.L_p1[L];
+    if (p1 > p0) ++classes;
+    for (int q = p0; q < p1; ++q) {
+      const int r = p.rho_rank[q];
+      if (r < p0 || r >= p1 || order[r] != -1) {
+        bad++;
+        continue;
+      }
+      order[r] = q;
+      if (std::memcmp(&p.hot_rho[r], &p.hot[q], sizeof(PairHot)) != 0) bad++;
+      if (L >= 3 && r != q) bad++;
+    }
+    for (int r = p0 + 1; L <= 2 && r < p1; ++r) {
+      const double a = p.hot_rho[r - 1].inv4p, b = p.hot_rho[r].inv4p;
+      if (a > b) bad++;                                   // sorted by p
+      if (a == b && order[r - 1] > order[r]) bad++;       // stable
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    if (order[r] < 0) bad++;
+  std::printf("pairs %d classes %d bad %ld\n", n, classes, bad);
+  return bad != 0;
+}
