@@ -377,7 +377,19 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const double2 *__restrict__
   const int r0 = grp * rows_per_group, r1 = min(nrows, r0 + rows_per_group);
   const double2 *pp = part + (size_t)dm * nrows * nslot + g;
   double r = 0.0, i = 0.0;
-  for (int row = r0; row < r1; ++row) {
+  int row = r0;
+  // rows added in order; the loads of eight rows are issued together
+  for (; row + 8 <= r1; row += 8) {
+    double2 x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = pp[(size_t)(row + u) * nslot];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      r += x[u].x;
+      i += x[u].y;
+    }
+  }
+  for (; row < r1; ++row) {
     const double2 x = pp[(size_t)row * nslot];
     r += x.x;
     i += x.y;
