@@ -8,7 +8,10 @@
   of each density bit for bit (same kernels, same shapes, no memset nodes);
 * pwdf_autotune: the tuned context still meets the FP64 bar against the oracle,
   writes a cache entry, and a second context applies the cached shapes without
-  timing (same segment length, bit-identical results to the first tuned one).
+  timing (same segment length, bit-identical results to the first tuned one);
+* E_J of a J build (summed by an extra block of the J(k) launch) and of the
+  gradient path (its own energy launch) come from the same partials in the same
+  order: bit-identical, eager and graph-replayed, for a batch of two densities.
 """
 import numpy as np
 import pytest
@@ -192,3 +195,25 @@ def test_fork_setting_from_cache(prec, tmp_path):
         assert torch.equal(Je, Jg) and torch.equal(Ee, Eg)
         out[fk] = (Je, Ee)
     assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32_mfma"])
+def test_energy_same_bits_on_every_path(prec):
+    p = problem()
+    D = np.stack([synth.make_density(p, 631), synth.make_density(p, 632)])
+    ctx = pw().LongRangeJ(p, precision=prec, max_ndm=2)
+    Dt = dev(D)
+    _, E_eager = ctx.build_j(Dt)
+    J = torch.empty_like(Dt)
+    E_graph = torch.empty(2, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        ctx.build_j(Dt, J, E_graph, graph=True)
+    _, E_grad = ctx.grad(Dt)
+    torch.cuda.synchronize()
+    a, b, c = (x.cpu().numpy() for x in (E_eager, E_graph, E_grad))
+    print(f"E_J eager {a} graph {b} gradient path {c}", flush=True)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+    for i in range(2):
+        ref = O.build_j(p, D[i], want_J=False, want_rho=False)
+        assert abs(a[i] - ref["E_G"]) <= (1e-10 if prec == 0 else 1e-7)
+
