@@ -93,17 +93,32 @@ __global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk,
   const int c1 = code & 1023, c2 = (code >> 10) & 1023, c3 = code >> 20;
   const double2 *D = Dk + (size_t)dm * nk * nn + sD_el[sg];
   double acc = 0.0;
-  int k1 = 0, k2 = 0, k3 = 0;
+  // the phase of k = (k1, k2, k3) is the table's per-axis steps raised to k1, k2,
+  // k3: it advances by one complex multiplication per k (k3 fastest; the row
+  // starts kept for the wrap-arounds), at most n1 + n2 + n3 products from the
+  // exact table values
+  const double2 o1 = sph[c1], o2 = sph[c2], o3 = sph[c3];
+  double2 w1 = make_double2(1.0, 0.0), w2 = w1, w = w1;
+  int k2 = 0, k3 = 0;
   for (int kb = 0; kb < nk; kb += kU) {
     double2 d[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) d[u] = kb + u < nk ? D[(size_t)(kb + u) * nn] : make_double2(0.0, 0.0);
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      if (kb + u < nk) {
-        const double2 w = sph[k1 * c1 + k2 * c2 + k3 * c3];
-        acc = fma(w.x, d[u].x, fma(-w.y, d[u].y, acc));
-        next_k(k1, k2, k3, n2, n3);
+      acc = fma(w.x, d[u].x, fma(-w.y, d[u].y, acc));  // zero past nk
+      if (++k3 == n3) {
+        k3 = 0;
+        if (++k2 == n2) {
+          k2 = 0;
+          w1 = make_double2(fma(w1.x, o1.x, -w1.y * o1.y), fma(w1.x, o1.y, w1.y * o1.x));
+          w2 = w1;
+        } else {
+          w2 = make_double2(fma(w2.x, o2.x, -w2.y * o2.y), fma(w2.x, o2.y, w2.y * o2.x));
+        }
+        w = w2;
+      } else {
+        w = make_double2(fma(w.x, o3.x, -w.y * o3.y), fma(w.x, o3.y, w.y * o3.x));
       }
     }
   }
