@@ -51,16 +51,6 @@ namespace pwdf {
 // class and is written to each of them.
 constexpr int kU = 8;
 
-__device__ __forceinline__ void next_k(int &k1, int &k2, int &k3, int n2, int n3) {
-  if (++k3 == n3) {
-    k3 = 0;
-    if (++k2 == n2) {
-      k2 = 0;
-      ++k1;
-    }
-  }
-}
-
 // copies the segment-start tables into LDS (callers synchronise before use)
 __device__ __forceinline__ void load_start_tabs(const double *__restrict__ g, double *e2, double2 *cis) {
   for (int i = threadIdx.x + threadIdx.y * blockDim.x; i < kStartTab; i += blockDim.x * blockDim.y) {
