@@ -468,6 +468,13 @@ __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ Epart
 // ---------------------------------------------------------------------------
 constexpr int kJTile = 32;  // segments per LDS tile of the J pass
 
+// binomial coefficient as a double (small arguments, compile-time after unrolling)
+__host__ __device__ constexpr double binom_d(int a, int c) {
+  double r = 1.0;
+  for (int i = 1; i <= c; ++i) r = r * (a - c + i) / i;
+  return r;
+}
+
 // J moments of one pair per lane for NDB densities (dm0 .. dm0+NDB-1, those past
 // ndm skipped): S is generated once per point and shared by the densities.
 template <int L, int SEG, int NDB>
@@ -532,6 +539,9 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
       for (int b = 0; b < NDB; ++b)
 #pragma unroll
         for (int a = 0; a <= L; ++a) mr[b][a] = mi[b][a] = 0.0;
+      // degrees L <= 3 take the moments in the point offset s (powers known at
+      // compile time) and shift them to n_u = nu0 + s once per segment below
+      constexpr bool kShift = L <= 3;
 #pragma unroll
       for (int s = 0; s < SEG; ++s) {
         const double n = nu0 + s;
@@ -540,12 +550,26 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
           const double2 v = sv[b * TS * SEG + j * SEG + s];
           const double Ur = fma(v.x, Sr, -v.y * Si);
           const double Ui = fma(v.x, Si, v.y * Sr);
-          double pw = 1.0;
+          if constexpr (kShift) {
+            mr[b][0] += Ur;
+            mi[b][0] += Ui;
+            double sp = 1.0;
 #pragma unroll
-          for (int a = 0; a <= L; ++a) {
-            mr[b][a] = fma(pw, Ur, mr[b][a]);
-            mi[b][a] = fma(pw, Ui, mi[b][a]);
-            pw *= n;
+            for (int a = 1; a <= L; ++a) {
+              sp *= (double)s;
+              if (s > 0) {
+                mr[b][a] = fma(sp, Ur, mr[b][a]);
+                mi[b][a] = fma(sp, Ui, mi[b][a]);
+              }
+            }
+          } else {
+            double pw = 1.0;
+#pragma unroll
+            for (int a = 0; a <= L; ++a) {
+              mr[b][a] = fma(pw, Ur, mr[b][a]);
+              mi[b][a] = fma(pw, Ui, mi[b][a]);
+              pw *= n;
+            }
           }
         }
         const double tr = fma(Sr, Rr, -Si * Ri);
@@ -553,6 +577,27 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
         Sr = tr;
         Rr *= q;
         Ri *= q;
+      }
+      if constexpr (kShift) {
+        // sum_s (nu0 + s)^a U_s = sum_c C(a, c) nu0^(a - c) sum_s s^c U_s, highest a first
+        double pn[L + 1];
+        pn[0] = 1.0;
+#pragma unroll
+        for (int a = 1; a <= L; ++a) pn[a] = pn[a - 1] * nu0;
+#pragma unroll
+        for (int b = 0; b < NDB; ++b)
+#pragma unroll
+          for (int a = L; a >= 1; --a) {
+            double r = mr[b][a], i = mi[b][a];
+#pragma unroll
+            for (int c = 0; c < a; ++c) {
+              const double w = binom_d(a, c) * pn[a - c];
+              r = fma(w, mr[b][c], r);
+              i = fma(w, mi[b][c], i);
+            }
+            mr[b][a] = r;
+            mi[b][a] = i;
+          }
       }
       double mv[L + 1], mw[L + 1];
       mv[0] = mw[0] = 1.0;
