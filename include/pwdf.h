@@ -209,7 +209,9 @@ pwdf_status pwdf_grad(pwdf_ctx *ctx, int ndm, const double *Dk, double *dEdR, do
  * and replayed; FP32-MFMA form: eager launches, segment length first, then the
  * multiplier).  The FP32-MFMA form (one launch per angular class L) then lets
  * each class keep the multiplier (1/4 .. 4) of its shortest launch, and keeps
- * that result only if it also wins overall.  Last, the independent
+ * that result only if it also wins overall; the FP64 form tries the J pass's
+ * multiplier at 1/2 and 2 and the rho pass's at 3/4 and 3/2 of the chosen one,
+ * each kept only if at least 1 % faster.  Last, the independent
  * launches of a pass either overlap on the internal streams or follow each
  * other on the caller's stream, whichever replays faster (pwdf_stats.fork).
  * Timing runs on

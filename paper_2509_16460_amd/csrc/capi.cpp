@@ -1118,6 +1118,26 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
     if ((s = time_total(c, ndm, 5, t_cand)) != PWDF_OK) return s;
     if (t_cand > best_t) cand = best;
   }
+  // 2b. FP64: the J pass's multiplier apart from rho's (the passes split the work
+  // along different axes: rho chunks the pairs, J the G segments), then rho's
+  // around the joint choice; a variation is kept only when it is at least 1 %
+  // faster than the current choice (two timings each, the shorter kept)
+  if (c->prec == PWDF_FP64) {
+    const double vars[][2] = {{1.0, 0.5}, {1.0, 2.0}, {0.75, 1.0}, {1.5, 1.0}};
+    for (const auto &v : vars) {
+      Tune t = cand;
+      for (int L = 0; L <= kMaxLsum; ++L) {
+        t.mrho[L] *= v[0];
+        t.mj[L] *= v[1];
+      }
+      double ms = 0.0;
+      if ((s = measure(t, ms)) != PWDF_OK) return s;
+      if (ms < 0.99 * best_t) {
+        cand = t;
+        best_t = ms;
+      }
+    }
+  }
   // 3. the independent launches of a pass overlapping on the internal streams,
   // or following each other on one stream: timed back to back
   if ((s = setup_device(c, cand)) != PWDF_OK) return s;
