@@ -319,16 +319,27 @@ __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int
     __syncthreads();
     // pair records: PairHot, then the coefficients of densities dm0 .. dm0+NDB-1
     // (zeros past ndm)
-    for (int i = tid; i < nt * REC; i += 64 * W) {
-      const int pi = i / REC, f = i - pi * REC;
-      double v;
-      if (f < 8) {
-        v = reinterpret_cast<const double *>(hot + t0 + pi)[f];
-      } else {
-        const int b = (f - 8) / NT, k = (f - 8) - b * NT;
-        v = dm0 + b < ndm ? dhat[(size_t)(dm0 + b) * dhat_size + cls_off + (size_t)(t0 + pi - Lp0) * NT + k] : 0.0;
+    // four elements per thread and step, their loads issued before the stores
+    for (int i0 = tid; i0 < nt * REC; i0 += 4 * 64 * W) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * 64 * W;
+        const int pi = i / REC, f = i - pi * REC;
+        const double *src = nullptr;
+        if (i < nt * REC) {
+          if (f < 8) {
+            src = reinterpret_cast<const double *>(hot + t0 + pi) + f;
+          } else {
+            const int b = (f - 8) / NT, k = (f - 8) - b * NT;
+            if (dm0 + b < ndm) src = dhat + (size_t)(dm0 + b) * dhat_size + cls_off + (size_t)(t0 + pi - Lp0) * NT + k;
+          }
+        }
+        v[u] = src ? *src : 0.0;
       }
-      sp[i] = v;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u * 64 * W < nt * REC) sp[i0 + u * 64 * W] = v[u];
     }
     __syncthreads();
     for (int j = w; j < nt; j += W)
