@@ -98,9 +98,18 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const SegDesc *__restrict__ se
       __syncthreads();
       for (int i = tid; i < nq; i += 256) sh[i] = hot[t0 + i];
       // coefficient columns [ng*16, (ng+ntg)*16) of the tile's pairs
-      for (int i = tid; i < nq * NTG * 16; i += 256) {
-        const int q = i / (NTG * 16), c = i - q * (NTG * 16);
-        sc[i] = c < ntg * 16 ? dcls[(size_t)(t0 + q - Lp0) * ncols + ng * 16 + c] : 0.f;
+      // four elements per thread and step, their loads issued before the stores
+      for (int i0 = tid; i0 < nq * NTG * 16; i0 += 4 * 256) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + u * 256;
+          const int q = i / (NTG * 16), c = i - q * (NTG * 16);
+          v[u] = i < nq * NTG * 16 && c < ntg * 16 ? dcls[(size_t)(t0 + q - Lp0) * ncols + ng * 16 + c] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i0 + u * 256 < nq * NTG * 16) sc[i0 + u * 256] = v[u];
       }
       __syncthreads();
       for (int q0 = 0; q0 < nq; q0 += 4) {
