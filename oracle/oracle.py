@@ -45,6 +45,10 @@ def lib():
         L.orc_sizes.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, dp, dp, ip,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ctypes.POINTER(ctypes.c_int64)]
+        L.orc_pairs.restype = ctypes.c_int
+        L.orc_pairs.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, dp, dp, ip,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                ip, ctypes.c_int]
         L.orc_ft_axis.restype = None
         L.orc_ft_axis.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
@@ -87,6 +91,17 @@ def sizes(prob):
     if rc != 0:
         raise ValueError(f"oracle rejected the problem ({rc})")
     return dict(nG=int(out[0]), npairs=int(out[1]), nbf=int(out[2]), nk=int(out[3]))
+
+
+def pairs(prob):
+    """The oracle's screened pair list, int [npairs][7]: sa, sb, ia, ib, m1, m2, m3."""
+    arrs, args = _prob_args(prob)
+    n = lib().orc_pairs(*args, ctypes.POINTER(ctypes.c_int)(), 0)
+    if n < 0:
+        raise ValueError(f"oracle rejected the problem ({n})")
+    out = np.zeros((max(n, 1), 7), dtype=np.int32)
+    lib().orc_pairs(*args, _i(out), n)
+    return out[:n]
 
 
 class OracleResult(dict):

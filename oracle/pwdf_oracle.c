@@ -415,6 +415,34 @@ int orc_sizes(const double *lattice, int natm, const double *xyz, int nshell, co
   return 0;
 }
 
+/* The screened pair list itself (diagnostics): out[q] = (sa, sb, ia, ib, m1, m2, m3)
+ * for q < min(count, maxp), in the order the oracle sums them.  Lets a
+ * finite-difference test confirm that a displaced geometry keeps the same list
+ * (the gradient is defined at a fixed pair list).  Returns the pair count, or
+ * -1 on bad input. */
+int orc_pairs(const double *lattice, int natm, const double *xyz, int nshell, const int *shell_atom,
+              const int *shell_l, const int *shell_nprim, const double *exps, const double *coefs,
+              const int *kmesh, double omega, double eps_pair, double eps_G, double r_max,
+              int *out, int maxp) {
+  orc_sys s;
+  if (sys_setup(&s, lattice, natm, xyz, nshell, shell_atom, shell_l, shell_nprim, exps, coefs,
+                kmesh, omega, eps_pair, eps_G, r_max))
+    return -1;
+  int np;
+  orc_pair *pl = make_pairs(&s, &np);
+  for (int q = 0; q < np && q < maxp; ++q) {
+    int *o = out + 7 * (size_t)q;
+    o[0] = pl[q].sa;
+    o[1] = pl[q].sb;
+    o[2] = pl[q].ia;
+    o[3] = pl[q].ib;
+    for (int c = 0; c < 3; ++c) o[4 + c] = pl[q].m[c];
+  }
+  free(pl);
+  sys_free(&s);
+  return np;
+}
+
 /* Un-normalised 1D pair transform f[i][j] at G (for quadrature pins). */
 void orc_ft_axis(int i, int j, double aa, double Ax, double ab, double Bx, double G, double *out) {
   zd f[ORC_LMAX + 1][ORC_LMAX + 1];

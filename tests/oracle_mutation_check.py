@@ -47,9 +47,19 @@ MUTANTS = {
     "rhoplus": ("zd w = v[ig] * rho[mi[ig]];", "zd w = v[ig] * rho[ig];", "V(G) instead of V(-G) in the J contraction"),
     "dgrad": ("if (a[x] > 0) da -= (double)a[x] * f[x][a[x] - 1][b[x]];",
               "if (a[x] > 0) da += (double)a[x] * f[x][a[x] - 1][b[x]];", "sign of the lowered term of the centre derivative"),
+    "gswap": ("int A_ = shell_atom[P->sa], B_ = shell_atom[P->sb];",
+              "int A_ = shell_atom[P->sb], B_ = shell_atom[P->sa];",
+              "gradient of shell a assigned to the atom of shell b and vice versa"),
+    "grhoplus": ("gA[x] += creal(w * sa_);\n            gB[x] += creal(w * sb_);",
+                 "gA[x] += creal(v[ig] * rho[ig] * sa_);\n            gB[x] += creal(v[ig] * rho[ig] * sb_);",
+                 "rho(G) instead of rho(-G) in the gradient only"),
+    "gnod": ("sa_ += DL[boff[q] + e] * dA[x * n + e];", "sa_ += dA[x * n + e];",
+             "dropped D weight of the shell-a centre derivative"),
+    "gsignb": ("gB[x] += creal(w * sb_);", "gB[x] -= creal(w * sb_);",
+               "sign of the shell-b centre derivative in the gradient"),
 }
 
-TESTS = ["tests/test_oracle_pins.py", "tests/test_oracle_invariants.py"]
+TESTS = ["tests/test_oracle_pins.py", "tests/test_oracle_invariants.py", "tests/test_oracle_grad.py"]
 
 
 def run(name, tmp):
