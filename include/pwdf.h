@@ -87,6 +87,14 @@ typedef enum {
                          transforms and the energy stay FP64 */
 } pwdf_precision;
 
+/* What pwdf_build_j writes into J(k) (pwdf_set_jk_layout). */
+typedef enum {
+  PWDF_JK_FULL = 0,    /* every element of J(k): zeros off the pair support (default) */
+  PWDF_JK_SUPPORT = 1  /* only the elements on the pair support (pwdf_stats.jk_support per k
+                          and density); the others are never written, so the caller clears
+                          J(k) once and keeps the buffer */
+} pwdf_jk_layout;
+
 typedef struct {
   double eps_pair; /* pair screening on exp(-a_a a_b/p |A-B-L|^2); e.g. 1e-12 */
   double eps_G;    /* G cutoff |G| <= 2 omega sqrt(-ln eps_G); e.g. 1e-12 */
@@ -103,6 +111,12 @@ typedef struct {
   int64_t seg_len;    /* line-segment length of the current launch shapes (pwdf_query) */
   int64_t fork;       /* 1: independent launches of a pass overlap on internal streams;
                          0: they follow each other on the caller's stream (pwdf_query) */
+  int64_t jk_support; /* matrix elements (mu,nu) of J(k) on the pair support (both
+                         triangles): what a build writes per k and density in the
+                         PWDF_JK_SUPPORT layout */
+  int64_t dk_support; /* matrix elements of D(k) a build reads per k and density (one
+                         of (mu,nu), (nu,mu) for each support pair of elements) */
+  int64_t jk_layout;  /* current pwdf_jk_layout (pwdf_query) */
 } pwdf_stats;
 
 /*
@@ -126,7 +140,10 @@ typedef struct {
  *   device         HIP device ordinal.
  * On success *out is a new context (free with pwdf_destroy).  PWDF_EINVAL also
  * when no G vector lies in the cutoff sphere (0 < |G| <= Gcut); the screened
- * pair list always holds at least the on-site pairs (K = 1).
+ * pair list always holds at least the on-site pairs (K = 1).  PWDF_EUNSUPPORTED
+ * when a pair is so diffuse (small a_a + a_b = p) that Gcut^2/4p or the step
+ * ratio of the G-line recurrence exceeds 650: its Gaussian factors would
+ * overflow or underflow in FP64 (message names p).
  */
 pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const double *xyz,
                         int nshell, const int *shell_atom, const int *shell_l,
@@ -134,8 +151,32 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
                         const int kmesh[3], double omega, const pwdf_screen *screen,
                         pwdf_precision prec, int max_ndm, int device);
 
-/* Sizes and counts of the plan (host struct, filled). */
+/* Sizes and counts of the plan (host struct, filled).  PWDF_EINVAL for a NULL
+ * ctx (message via pwdf_last_error(NULL)) or a NULL out. */
 pwdf_status pwdf_query(const pwdf_ctx *ctx, pwdf_stats *out);
+
+/*
+ * Choose what later builds write into J(k) (pwdf_jk_layout).  Both layouts hold
+ * the same values on the pair support (eq. "FT of J": J(k) is a sum over the
+ * images of the screened pairs, so elements no pair block touches are exactly
+ * zero).  PWDF_JK_SUPPORT skips those zeros: for a cell whose support is a small
+ * share of nbf^2 (a slab with vacuum) the zero stores would otherwise dominate
+ * the launch.  The caller must then clear J(k) once (the library never writes
+ * the other elements, in any call).  A cached graph is dropped when the layout
+ * changes.  Host only; PWDF_EINVAL for an unknown layout.
+ */
+pwdf_status pwdf_set_jk_layout(pwdf_ctx *ctx, int layout);
+
+/*
+ * Input check of the calls made since the previous check: the D(k) -> D(L)
+ * launch of every build / gradient / rho call sets a device flag when a phase
+ * sum over the D(k) values of a support element is not finite (a NaN or inf in
+ * D(k)).  This call synchronises `stream`, reads and clears the flag, and
+ * returns PWDF_ENONFINITE (with a message) when it was set, else PWDF_OK.  The
+ * enqueueing calls cannot report it themselves: they return before the device
+ * has read D(k).
+ */
+pwdf_status pwdf_check_input(pwdf_ctx *ctx, void *stream);
 
 /* Host-only plan: validates the same arguments as pwdf_create, builds the G set
  * and the unique screened pair list on the host (no device is touched) and
@@ -154,7 +195,8 @@ pwdf_status pwdf_plan_stats(const double lattice[9], int natm, const double *xyz
  * and J(L) -> J(k) (eq. "FT of J").
  *   ndm   1 <= ndm <= max_ndm.
  *   Dk    device, complex128 [ndm][nk][nbf][nbf], Hermitian per k; read only.
- *   Jk    device, same layout; fully written (zeros off the pair support).
+ *   Jk    device, same layout; every element written (zeros off the pair support),
+ *         or only the elements on the pair support (pwdf_set_jk_layout).
  *   EJ    device, double [ndm]; written with E_J of each density.
  *   stream  hipStream_t or NULL.
  * Dk and Jk must not overlap.  Enqueue only.

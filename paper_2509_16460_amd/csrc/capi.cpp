@@ -72,6 +72,7 @@ struct pwdf_ctx {
   int device = 0;
   int max_ndm = 1;
   pwdf_precision prec = PWDF_FP64;
+  int jk_layout = PWDF_JK_FULL;
 };
 
 namespace {
@@ -84,6 +85,11 @@ pwdf_status fail(pwdf_ctx *c, pwdf_status s, const std::string &m) {
   else
     g_create_err = m;
   return s;
+}
+
+// build_plan marks parameters it cannot handle (as opposed to invalid ones)
+pwdf_status plan_status(const std::string &why) {
+  return why.rfind("unsupported:", 0) == 0 ? PWDF_EUNSUPPORTED : PWDF_EINVAL;
 }
 
 pwdf_status hip_fail(pwdf_ctx *c, hipError_t e, const char *where) {
@@ -254,6 +260,8 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   d.nsegD = (int)p.sD_code.size();
   for (int i = 0; i < 3; ++i) d.kmesh[i] = in.kmesh[i];
   d.nheavyJ = (int)p.heavyJ.size();
+  d.nlightJ = (int)p.lightJ.size();
+  d.jk_support = c->jk_layout == PWDF_JK_SUPPORT ? 1 : 0;
   d.fp32 = c->prec == PWDF_FP32_MFMA ? 1 : 0;
   if (d.fp32) {
     d.ndmp = 1;
@@ -297,6 +305,7 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   UP(p.eJ, eJ)
   UP(p.sD_el, sD_el)
   UP(p.heavyJ, heavyJ)
+  UP(p.lightJ, lightJ)
   UP(p.sD_code, sD_code)
   UP(p.sD_e0, sD_e0)
   UP(p.eD, eD)
@@ -358,6 +367,8 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
       return hip_fail(c, e, "uploading atom lists");
   }
   if ((e = alloc(c, M, &c->Escr)) != hipSuccess) return fail(c, PWDF_ENOMEM, "device allocation failed: energies");
+  if ((e = alloc(c, 1, &d.nonfinite)) != hipSuccess) return fail(c, PWDF_ENOMEM, "device allocation failed: flag");
+  if ((e = hipMemset(d.nonfinite, 0, sizeof(int))) != hipSuccess) return hip_fail(c, e, "clearing the input flag");
   return PWDF_OK;
 }
 
@@ -546,7 +557,7 @@ pwdf_status run_from_V(pwdf_ctx *c, int ndm, double *Jk, double *EJ, hipStream_t
   if ((s = run_mid_j(c, ndm, st)) != PWDF_OK) return s;
   if ((s = step(c, "fold_j", (double)p.eJ.size() * ndm, st, [&] { return launch_fold_j(d, ndm, st); })) != PWDF_OK)
     return s;
-  return step(c, "phase_j", (double)p.nk * p.nbf * (double)p.nbf * ndm, st,
+  return step(c, "phase_j", (double)p.nk * (double)(p.lightJ.size() + p.heavyJ.size()) * ndm, st,
               [&] { return launch_phase_j(d, ndm, Jk, EJ, st); });
 }
 
@@ -608,6 +619,9 @@ static void fill_stats(const Plan &p, pwdf_stats *out) {
   out->pairG_evals = 2.0 * (double)p.npairs() * (double)(p.nG_full / 2);
   out->seg_len = p.seg_len;
   out->fork = 1;
+  out->jk_support = (int64_t)(p.lightJ.size() + p.heavyJ.size());
+  out->dk_support = p.nD_support;
+  out->jk_layout = PWDF_JK_FULL;
 }
 
 pwdf_status pwdf_plan_stats(const double lattice[9], int natm, const double *xyz, int nshell, const int *shell_atom,
@@ -625,7 +639,7 @@ pwdf_status pwdf_plan_stats(const double lattice[9], int natm, const double *xyz
   } catch (const std::bad_alloc &) {
     return fail(nullptr, PWDF_ENOMEM, "host allocation failed while building the plan");
   }
-  if (!why.empty()) return fail(nullptr, PWDF_EINVAL, why);
+  if (!why.empty()) return fail(nullptr, plan_status(why), why);
   fill_stats(p, out);
   return PWDF_OK;
 }
@@ -661,7 +675,7 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
   }
   if (!why.empty()) {
     delete c;
-    return fail(nullptr, PWDF_EINVAL, why);
+    return fail(nullptr, plan_status(why), why);
   }
   // the phase kernels stage the (n1+n2+n3) lcm(n1,n2,n3) phases in LDS
   if (c->plan.ptab.size() / 2 > 1024) {
@@ -706,11 +720,40 @@ pwdf_status pwdf_create(pwdf_ctx **out, const double lattice[9], int natm, const
 }
 
 pwdf_status pwdf_query(const pwdf_ctx *c, pwdf_stats *out) {
-  if (!c || !out) return PWDF_EINVAL;
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_query: ctx is NULL");
+  if (!out) return fail(const_cast<pwdf_ctx *>(c), PWDF_EINVAL, "pwdf_query: out is NULL");
   fill_stats(c->plan, out);
   out->seg_len = c->plan.seg_len;
   out->fork = c->tune.fork;
+  out->jk_layout = c->jk_layout;
   return PWDF_OK;
+}
+
+pwdf_status pwdf_set_jk_layout(pwdf_ctx *c, int layout) {
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_set_jk_layout: ctx is NULL");
+  if (layout != PWDF_JK_FULL && layout != PWDF_JK_SUPPORT)
+    return fail(c, PWDF_EINVAL, "layout must be PWDF_JK_FULL or PWDF_JK_SUPPORT");
+  if (layout != c->jk_layout) drop_graph(c);  // the captured J(k) launch has the old shape
+  c->jk_layout = layout;
+  c->dev.jk_support = layout == PWDF_JK_SUPPORT ? 1 : 0;
+  return PWDF_OK;
+}
+
+pwdf_status pwdf_check_input(pwdf_ctx *c, void *stream) {
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_check_input: ctx is NULL");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  int flag = 0;
+  if ((e = hipMemcpyAsync(&flag, c->dev.nonfinite, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return hip_fail(c, e, "reading the input flag");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "sync");
+  if (!flag) return PWDF_OK;
+  if ((e = hipMemsetAsync(c->dev.nonfinite, 0, sizeof(int), st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return hip_fail(c, e, "clearing the input flag");
+  return fail(c, PWDF_ENONFINITE, "a D(k) value on the pair support was not finite (NaN or inf) in a call since "
+                                  "the last check; its results are not usable");
 }
 
 pwdf_status pwdf_build_j(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, double *EJ, void *stream) {

@@ -34,6 +34,10 @@ struct Dev {
   const int *sD_el, *sD_code, *sD_e0, *eD;
   const int *heavyJ;             // elements with more than kPhaseLight J classes
   int nheavyJ;
+  const int *lightJ;             // the other support elements (1 .. kPhaseLight classes), ascending
+  int nlightJ;
+  int jk_support;                // 1: J(k) is written on the pair support only
+  int *nonfinite;                // set to 1 by phase_d when a D(L) phase sum is not finite
   double *Jfold;                 // [ndm][nsegJ]
   const double2 *ptab;           // e^{2 pi i t / N}
   int ptab_len;

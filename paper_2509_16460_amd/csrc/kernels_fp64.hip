@@ -71,7 +71,8 @@ __global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk,
                                                  int nsegD, const int *__restrict__ sD_el,
                                                  const int *__restrict__ sD_code, const int *__restrict__ sD_e0,
                                                  const int *__restrict__ eD, const double2 *__restrict__ ptab,
-                                                 int ptab_len, double wk, double *__restrict__ Dblk, int64_t nelem) {
+                                                 int ptab_len, double wk, double *__restrict__ Dblk, int64_t nelem,
+                                                 int *__restrict__ nonfinite) {
   __shared__ double2 sph[kPtabMax];
   for (int i = threadIdx.x; i < ptab_len; i += blockDim.x) sph[i] = ptab[i];
   __syncthreads();
@@ -113,6 +114,9 @@ __global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk,
     }
   }
   const double v = acc * wk;
+  // a non-finite D(k) value read makes the phase sum non-finite (NaN or inf
+  // propagates through the products); the host reads the flag on request
+  if (!isfinite(v)) *nonfinite = 1;
   double *out = Dblk + (size_t)dm * nelem;
   for (int j = sD_e0[sg]; j < sD_e0[sg + 1]; ++j) out[eD[j]] = v;
 }
@@ -1065,14 +1069,19 @@ __device__ __forceinline__ void phase_j_body(const double2 *__restrict__ sph, co
     }
 }
 
+// i0 indexes the light support list lightJ when it is given (support-only J(k):
+// only elements with 1 .. kPhaseLight classes are visited), else the elements
+// of the whole matrix (zeros written off the support).
 __device__ __forceinline__ void phase_j_light(const double2 *__restrict__ sph, const double *__restrict__ Jfold,
                                               int nsegJ, const int *__restrict__ sJ_off,
                                               const int *__restrict__ sJ_code, int nk, int n1, int n2, int n3,
-                                              int nbf, double2 *__restrict__ Jk, int64_t e0, int dm) {
+                                              int nbf, double2 *__restrict__ Jk, const int *__restrict__ lightJ,
+                                              int64_t nlist, int64_t i0, int dm) {
   const int64_t nn = (int64_t)nbf * nbf;
   // lanes past the end and heavy elements take part with no classes and store nothing
-  const bool inb = e0 < nn;
-  const int64_t e = inb ? e0 : nn - 1;
+  const bool inb = i0 < nlist;
+  const int64_t ii = inb ? i0 : nlist - 1;
+  const int64_t e = lightJ ? (int64_t)lightJ[ii] : ii;
   const int s0 = sJ_off[e];
   int n = sJ_off[e + 1] - s0;
   const bool mine = inb && n <= kPhaseLight;
@@ -1344,7 +1353,8 @@ __global__ __launch_bounds__(256) void k_jpass_all(const Dev dv, const ClassTab 
 // path) and the element blocks follow it.
 __global__ __launch_bounds__(256) void k_phase_j_all(const double *__restrict__ Jfold, int nsegJ,
                                                      const int *__restrict__ sJ_off, const int *__restrict__ sJ_code,
-                                                     const int *__restrict__ heavy, int nheavy, int nlight,
+                                                     const int *__restrict__ heavy, int nheavy,
+                                                     const int *__restrict__ lightJ, int64_t nlist, int nlight,
                                                      const double2 *__restrict__ ptab, int ptab_len, int nk, int n1,
                                                      int n2, int n3, int nbf, double2 *__restrict__ Jk,
                                                      const double *__restrict__ Epart, int nparts,
@@ -1360,7 +1370,7 @@ __global__ __launch_bounds__(256) void k_phase_j_all(const double *__restrict__ 
   __syncthreads();
   const int dm = blockIdx.y;
   if (bx < nlight)
-    phase_j_light(sph, Jfold, nsegJ, sJ_off, sJ_code, nk, n1, n2, n3, nbf, Jk,
+    phase_j_light(sph, Jfold, nsegJ, sJ_off, sJ_code, nk, n1, n2, n3, nbf, Jk, lightJ, nlist,
                   (int64_t)bx * blockDim.x + threadIdx.x, dm);
   else
     phase_j_heavy(sph, Jfold, nsegJ, heavy, nheavy, sJ_off, sJ_code, nk, n2, n3, nbf, Jk,
@@ -1381,7 +1391,8 @@ hipError_t launch_phase_d(const Dev &d, const double *Dk, int ndm, hipStream_t s
   if (d.ptab_len > kPtabMax) return hipErrorInvalidValue;
   dim3 grid((unsigned)((d.nsegD + 255) / 256), ndm);
   hipLaunchKernelGGL(k_phase_d, grid, dim3(256), 0, st, (const double2 *)Dk, d.nk, d.nbf, d.kmesh[1], d.kmesh[2],
-                     d.nsegD, d.sD_el, d.sD_code, d.sD_e0, d.eD, d.ptab, d.ptab_len, 1.0 / d.nk, d.Dblk, d.nelem);
+                     d.nsegD, d.sD_el, d.sD_code, d.sD_e0, d.eD, d.ptab, d.ptab_len, 1.0 / d.nk, d.Dblk, d.nelem,
+                     d.nonfinite);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -1540,13 +1551,16 @@ hipError_t launch_fold_j(const Dev &d, int ndm, hipStream_t st) {
 
 hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, double *EJ, hipStream_t st) {
   if (d.ptab_len > kPtabMax) return hipErrorInvalidValue;
-  const int64_t nn = (int64_t)d.nbf * d.nbf;
-  const int nlight = (int)((nn + 255) / 256);
+  // light path: the support list (support-only J(k)) or every element (zeros off
+  // the support)
+  const int64_t nlist = d.jk_support ? (int64_t)d.nlightJ : (int64_t)d.nbf * d.nbf;
+  const int nlight = (int)((nlist + 255) / 256);
   const int nheavy_blocks = (d.nheavyJ + 3) / 4;
+  if (nlight + nheavy_blocks + (EJ ? 1 : 0) == 0) return hipSuccess;
   dim3 grid((unsigned)(nlight + nheavy_blocks + (EJ ? 1 : 0)), ndm);
   hipLaunchKernelGGL(k_phase_j_all, grid, dim3(256), 0, st, d.Jfold, d.nsegJ, d.sJ_off, d.sJ_code, d.heavyJ,
-                     d.nheavyJ, nlight, d.ptab, d.ptab_len, d.nk, d.kmesh[0], d.kmesh[1], d.kmesh[2], d.nbf,
-                     (double2 *)Jk, d.Epart, d.nred_blocks, EJ);
+                     d.nheavyJ, d.jk_support ? d.lightJ : nullptr, nlist, nlight, d.ptab, d.ptab_len, d.nk,
+                     d.kmesh[0], d.kmesh[1], d.kmesh[2], d.nbf, (double2 *)Jk, d.Epart, d.nred_blocks, EJ);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }

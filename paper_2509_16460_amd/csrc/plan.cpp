@@ -348,6 +348,25 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
     p.blocks.push_back(br);
   }
   p.nelem = eoff;
+  // Bound of the segment-start arguments: |G|^2 / 4p <= Gcut^2 / 4p and the step
+  // ratio (|G(n+1)|^2 - |G(n)|^2) / 4p, |.| <= (2 Gcut |b_u| + |b_u|^2) / 4p, over
+  // the smallest p.  The starts are evaluated without range handling (exp of
+  // arguments up to ~700) and the recurrence multiplies them: a pair so diffuse
+  // that these overflow or underflow is rejected rather than summed as inf / 0.
+  {
+    double pmin = 1e300;
+    for (const PairAux &x : p.aux) pmin = std::min(pmin, x.p);
+    const double gcut2 = 4.0 * in.omega * in.omega * (-std::log(in.eps_G));
+    const double bu2 = p.M[p.ax[0]][p.ax[0]];
+    p.max_start_arg = std::max(gcut2, 2.0 * std::sqrt(gcut2 * bu2) + bu2) / (4.0 * pmin);
+    if (p.max_start_arg > 650.0) {
+      std::snprintf(msg, sizeof msg,
+                    "unsupported: pair exponent sum p = %.3g is too diffuse for the G set (Gcut^2/4p = %.0f > 650); "
+                    "raise the smallest exponent or eps_G (a smaller G cutoff)",
+                    pmin, p.max_start_arg);
+      return msg;
+    }
+  }
   // class ranges (blocks are sorted by (L, la) so classes are contiguous)
   for (int c = 0; c < 16; ++c) {
     p.cls_b0[c] = 0;
@@ -482,6 +501,7 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
     p.sJ_off.assign((size_t)nbf * nbf + 1, 0);
     p.nD_support = 0;
     p.heavyJ.clear();
+    p.lightJ.clear();
     p.sD_el.clear();
     p.sJ_code.clear();
     p.sJ_e0.clear();
@@ -524,7 +544,11 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
           }
           p.eJ.push_back(ents[i].second);
         }
-        if ((int)p.sJ_code.size() - p.sJ_off[e] > kPhaseLight) p.heavyJ.push_back((int)e);
+        const int ncls = (int)p.sJ_code.size() - p.sJ_off[e];
+        if (ncls > kPhaseLight)
+          p.heavyJ.push_back((int)e);
+        else if (ncls > 0)
+          p.lightJ.push_back((int)e);
       }
     p.sJ_off[(size_t)nbf * nbf] = (int)p.sJ_code.size();
     p.sJ_e0.push_back((int)p.eJ.size());

@@ -76,6 +76,13 @@ struct Plan {
   // elements with more than kPhaseLight J classes, summed one wave per element
   // (the others one thread per element)
   std::vector<int> heavyJ;
+  // the other elements of the J(k) support (1 .. kPhaseLight classes), ascending:
+  // the light path of a support-only J(k) launch walks this list instead of every
+  // element of the matrix
+  std::vector<int> lightJ;
+  // largest |G|^2 / 4p and |G(n+1)|^2 - |G(n)|^2 over 4p of any pair and G line
+  // point: the segment-start exponentials are evaluated without range handling
+  double max_start_arg = 0.0;
   std::vector<int> eD;                      // per D entry: element offset in Dblk
   int phN = 1;                        // N
   std::vector<double> ptab;           // e^{2 pi i t / N}, t = 0 .. (n1+n2+n3) N - 1

@@ -22,9 +22,12 @@ PWDF_FP32_MFMA = 1
 _STATUS = {0: "PWDF_OK", -1: "PWDF_EINVAL", -2: "PWDF_ENOMEM", -3: "PWDF_EDEVICE",
            -4: "PWDF_EUNSUPPORTED", -5: "PWDF_ENONFINITE", -6: "PWDF_ESTATE"}
 
+PWDF_JK_FULL = 0
+PWDF_JK_SUPPORT = 1
+
 EXPORTED = ["pwdf_create", "pwdf_query", "pwdf_build_j", "pwdf_build_j_graph", "pwdf_get_rhoG", "pwdf_grad",
             "pwdf_autotune", "pwdf_last_error", "pwdf_destroy", "pwdf_plan_stats",
-            "pwdf_profile_enable", "pwdf_profile_read"]
+            "pwdf_profile_enable", "pwdf_profile_read", "pwdf_set_jk_layout", "pwdf_check_input"]
 
 
 class PwdfError(RuntimeError):
@@ -42,7 +45,8 @@ class Stats(ctypes.Structure):
                 ("nbf", ctypes.c_int64), ("nk", ctypes.c_int64), ("nimg", ctypes.c_int64),
                 ("nblocks", ctypes.c_int64), ("nseg", ctypes.c_int64), ("pairG_evals", ctypes.c_double),
                 ("t_us", ctypes.c_double * 8), ("seg_len", ctypes.c_int64),
-                ("fork", ctypes.c_int64)]
+                ("fork", ctypes.c_int64), ("jk_support", ctypes.c_int64), ("dk_support", ctypes.c_int64),
+                ("jk_layout", ctypes.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("npairs_by_class", "t_us")}
@@ -88,6 +92,10 @@ def lib():
         L.pwdf_profile_enable.argtypes = [vp, ctypes.c_int]
         L.pwdf_profile_read.restype = ctypes.c_int
         L.pwdf_profile_read.argtypes = [vp, ctypes.POINTER(KProf), ctypes.c_int, ip]
+        L.pwdf_set_jk_layout.restype = ctypes.c_int
+        L.pwdf_set_jk_layout.argtypes = [vp, ctypes.c_int]
+        L.pwdf_check_input.restype = ctypes.c_int
+        L.pwdf_check_input.argtypes = [vp, vp]
         L.pwdf_last_error.restype = ctypes.c_char_p
         L.pwdf_last_error.argtypes = [vp]
         L.pwdf_destroy.restype = None
@@ -187,16 +195,32 @@ class LongRangeJ:
             raise ValueError(f"Dk shape {tuple(Dk.shape)} != [ndm, {p.nk}, {p.nbf}, {p.nbf}]")
         return Dk
 
+    def set_jk_layout(self, layout: int):
+        """PWDF_JK_FULL (every element of J(k) written) or PWDF_JK_SUPPORT (only the
+        pair support; a J(k) buffer passed in must have been cleared once)."""
+        rc = lib().pwdf_set_jk_layout(self._h, int(layout))
+        if rc != 0:
+            self._err(rc)
+        self._jk_layout = int(layout)
+
+    def check_input(self, stream=None):
+        """Raises PwdfError(PWDF_ENONFINITE) if a call since the last check read a
+        non-finite D(k) value on the pair support (synchronises the stream)."""
+        rc = lib().pwdf_check_input(self._h, self._stream(stream))
+        if rc != 0:
+            self._err(rc)
+
     def build_j(self, Dk, Jk=None, EJ=None, stream=None, graph=False):
         """Dk: complex128 [ndm][nk][nbf][nbf] (or [nk][nbf][nbf]) on the device.
         Returns (Jk, EJ) device tensors; enqueued on `stream` (default: current).
         graph=True goes through pwdf_build_j_graph (captured once per set of
-        buffers, then replayed): pass the same Jk / EJ tensors on every call."""
+        buffers, then replayed): pass the same Jk / EJ tensors on every call.
+        In the support layout a J(k) allocated here starts as zeros."""
         import torch
         Dk = self._check_D(Dk)
         ndm = Dk.shape[0]
         if Jk is None:
-            Jk = torch.empty_like(Dk)
+            Jk = torch.zeros_like(Dk) if getattr(self, "_jk_layout", 0) == PWDF_JK_SUPPORT else torch.empty_like(Dk)
         if EJ is None:
             EJ = torch.empty(ndm, dtype=torch.float64, device=Dk.device)
         fn = lib().pwdf_build_j_graph if graph else lib().pwdf_build_j

@@ -412,3 +412,41 @@ def small_problem(kind: str = "sp", seed: int = 11, kmesh=(1, 1, 1), omega: floa
     return build_problem(f"small_{kind}", lattice, xyz, [0] * natm, exps, kmesh, omega,
                          eps_pair=eps_pair, eps_G=eps_G, r_max=r_max,
                          nelec=2.0 * natm, seed=seed)
+
+
+
+def make_densities_torch(prob: Problem, ndm: int, base_seed: int, Sk: np.ndarray, device="cuda", which=None):
+    """Random Hermitian PSD D(k) with torch: the time-reversal-symmetric
+    construction of make_density (D(k) = X_k X_k^H, D(-k) = conj D(k), real X at
+    k = -k), each scaled to sum_k w_k Tr(D(k) S(k)) = nelec.  X ~ N(0,1) is drawn
+    on the CPU from a torch generator seeded base_seed + i, so the densities are
+    the same on any machine; the products run on `device` (a GPU for the large
+    batches, "cpu" to rebuild a few of them for reference values).  which: the
+    density indices to build (default range(ndm)).  Returns a complex128 tensor
+    [len(which)][nk][nbf][nbf] on `device`."""
+    import torch
+    nbf, nk = prob.nbf, prob.nk
+    r = density_rank(prob)
+    mk = _minus_k_index(prob.kmesh)
+    which = list(range(ndm)) if which is None else list(which)
+    D = torch.empty((len(which), nk, nbf, nbf), dtype=torch.complex128, device=device)
+    S = torch.from_numpy(np.ascontiguousarray(Sk)).to(device)
+    for j, i in enumerate(which):
+        g = torch.Generator(device="cpu")
+        g.manual_seed(int(base_seed) + int(i))
+        for k in range(nk):
+            if mk[k] < k:
+                continue
+            if mk[k] == k:
+                X = torch.randn((nbf, r), generator=g, dtype=torch.float64).to(device)
+                D[j, k] = (X @ X.T.contiguous()).to(torch.complex128)
+            else:
+                Xr = torch.randn((nbf, r), generator=g, dtype=torch.float64)
+                Xi = torch.randn((nbf, r), generator=g, dtype=torch.float64)
+                X = torch.complex(Xr, Xi).to(device)
+                D[j, k] = X @ X.conj().T.contiguous()
+                D[j, mk[k]] = D[j, k].conj()
+        ne = float((D[j] * S).real.sum()) / nk
+        D[j] *= prob.nelec / ne
+    del S
+    return D

@@ -125,3 +125,42 @@ def test_create_without_device_reports_device_error():
     prob = synth.small_problem(kind="d", seed=4, lmax=1, natm=2)
     with pytest.raises(pwdf.PwdfError, match="PWDF_EDEVICE"):
         pwdf.LongRangeJ(prob)
+
+
+def test_too_diffuse_pair_is_unsupported():
+    # a pair with a_a + a_b = 2e-3 at omega 0.5: Gcut^2/4p ~ 3.5e3, beyond the range
+    # of the unguarded segment-start exponentials -> rejected with a message
+    prob = synth.small_problem(kind="diffuse", seed=4, lmax=1, natm=2)
+    ex = prob.exps.copy()
+    ex[0] = 1e-3
+    with pytest.raises(pwdf.PwdfError, match="PWDF_EUNSUPPORTED.*diffuse"):
+        pwdf.plan_stats(prob.with_(exps=ex))
+    with pytest.raises(pwdf.PwdfError, match="PWDF_EUNSUPPORTED.*diffuse"):
+        pwdf.LongRangeJ(prob.with_(exps=ex))
+
+
+def test_null_context_messages_and_layout():
+    L = pwdf.lib()
+    st = pwdf.Stats()
+    assert L.pwdf_query(None, ctypes.byref(st)) == -1
+    assert b"NULL" in L.pwdf_last_error(None)
+    assert L.pwdf_set_jk_layout(None, 1) == -1
+    assert L.pwdf_check_input(None, None) == -1
+
+
+@pytest.mark.parametrize("cfg", [2, 4, 5])
+def test_support_counts(cfg):
+    # J(k) support: elements (mu, nu) that some screened pair block touches, in
+    # either orientation; D(k) support: at least one of each transposed pair of
+    # them (both for the blocks of a shell with itself at images m and -m)
+    prob = synth.config_problem(cfg)
+    s = pwdf.plan_stats(prob)
+    P = O.pairs(prob)
+    off = prob.shell_offsets()
+    nbf = prob.nbf
+    mask = np.zeros((nbf, nbf), dtype=bool)
+    for sa, sb in {(int(r[0]), int(r[1])) for r in P}:
+        mask[off[sa]:off[sa + 1], off[sb]:off[sb + 1]] = True
+    assert s["jk_support"] == int(mask.sum())
+    assert int(np.triu(mask | mask.T).sum()) <= s["dk_support"] <= int(mask.sum())
+    assert s["jk_layout"] == 0

@@ -1,0 +1,102 @@
+"""Boundary behaviour of the C ABI on the device (needs an MI355X).
+
+* J(k) layouts: PWDF_JK_SUPPORT writes exactly the elements on the pair support
+  (eq. "FT of J" is a sum over the screened pairs' images, so the others are
+  zero) and never touches the rest; PWDF_JK_FULL writes every element.  Checked
+  element by element against the FP64 oracle after builds with two different
+  densities (eager and graph replay), with the off-support elements holding a
+  sentinel the library must leave alone.
+* PWDF_ENONFINITE: a NaN in D(k) on the pair support is reported by
+  pwdf_check_input, once, and a clean build afterwards reports nothing.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_16460_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def pw():
+    from paper_2509_16460_amd import pwdf
+    return pwdf
+
+
+def vacuum_cell():
+    # two atoms 12 Bohr apart along a long axis, compact exponents: many shell
+    # pairs never overlap, so the J(k) support is well below nbf^2
+    lat = np.array([[4.0, 0.0, 0.0], [0.4, 4.3, 0.0], [0.0, 0.0, 24.0]])
+    rng = np.random.default_rng(90)
+    exps = {0: synth.draw_exponents(rng, [2, 2, 1], 0.9, 12.0)}
+    return synth.build_problem("vacuum2", lat, [[0.1, 0.2, 0.3], [1.9, 2.2, 12.3]], [0, 0], exps, (2, 2, 1),
+                               0.5, nelec=4.0, seed=90)
+
+
+def support_mask(prob):
+    P = O.pairs(prob)
+    off = prob.shell_offsets()
+    m = np.zeros((prob.nbf, prob.nbf), dtype=bool)
+    for sa, sb in {(int(r[0]), int(r[1])) for r in P}:
+        m[off[sa]:off[sa + 1], off[sb]:off[sb + 1]] = True
+    return m
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_jk_layouts_against_oracle(precision):
+    pwdf = pw()
+    prob = vacuum_cell()
+    mask = support_mask(prob)
+    st = pwdf.plan_stats(prob)
+    assert st["jk_support"] == int(mask.sum()) < prob.nbf ** 2
+    D1 = synth.make_density(prob, 91)
+    D2 = synth.make_density(prob, 92)
+    ref = O.build_j(prob, D2, want_rho=False)
+    ctx = pwdf.LongRangeJ(prob, precision=precision, max_ndm=1)
+    ctx.set_jk_layout(pwdf.PWDF_JK_SUPPORT)
+    assert ctx.stats()["jk_layout"] == 1
+    sentinel = 7.0 + 7.0j
+    J = torch.full((1, prob.nk, prob.nbf, prob.nbf), sentinel, dtype=torch.complex128, device="cuda")
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+    # layout test: the FP32 form is held to its own rounding level here (its
+    # accuracy targets are tested on the cubic cell in test_gpu_fp32.py)
+    jmax = float(np.max(np.abs(ref["J"])))
+    tolJ, tolE = (1e-11, 1e-10) if precision == 0 else (2e-6 * max(1.0, jmax), 1e-6 * max(1.0, ref["E_G"]))
+    for graph in (False, True):
+        for D in (D1, D2):
+            ctx.build_j(torch.from_numpy(D[None]).cuda(), J, E, graph=graph)
+        torch.cuda.synchronize()
+        Jh = J.cpu().numpy()[0]
+        off = ~mask
+        assert np.all(Jh[:, off] == sentinel), "an element off the pair support was written"
+        dJ = float(np.max(np.abs(Jh[:, mask] - ref["J"][:, mask])))
+        dE = abs(float(E.cpu()[0]) - ref["E_G"])
+        print(f"support layout prec={precision} graph={graph}: dE={dE:.2e} max|dJ|={dJ:.2e}", flush=True)
+        assert dJ <= tolJ and dE <= tolE
+        # the oracle's J(k) is exactly zero off the support
+        assert np.all(ref["J"][:, off] == 0)
+    ctx.set_jk_layout(pwdf.PWDF_JK_FULL)
+    Jf, Ef = ctx.build_j(torch.from_numpy(D2[None]).cuda())
+    torch.cuda.synchronize()
+    Jfh = Jf.cpu().numpy()[0]
+    assert np.all(Jfh[:, ~mask] == 0)
+    assert np.array_equal(Jfh[:, mask], J.cpu().numpy()[0][:, mask])
+
+
+def test_nonfinite_density_is_reported():
+    pwdf = pw()
+    prob = synth.small_problem(kind="nan", seed=93, kmesh=(2, 1, 1), lmax=1, natm=2)
+    D = synth.make_density(prob, 94)
+    ctx = pwdf.LongRangeJ(prob, max_ndm=1)
+    ctx.build_j(torch.from_numpy(D[None]).cuda())
+    ctx.check_input()  # clean input: no error
+    Dbad = D.copy()
+    Dbad[1, 0, 0] = np.nan  # (0, 0) is on the support (on-site pair of the first shell)
+    ctx.build_j(torch.from_numpy(Dbad[None]).cuda())
+    with pytest.raises(pwdf.PwdfError, match="PWDF_ENONFINITE"):
+        ctx.check_input()
+    ctx.check_input()  # the flag was cleared by the failing check
+    _, E = ctx.build_j(torch.from_numpy(D[None]).cuda())
+    ctx.check_input()
+    assert np.isfinite(float(E.cpu()[0]))
