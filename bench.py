@@ -9,8 +9,8 @@ HBM, i.e. the phase sum D(k) -> D(L), per-pair transforms, rho(G), V(G) and
 E_J, J from V, back transform and J(L) -> J(k).  The headline form is the
 FP32-MFMA one (pair-G tiles in FP32 on the matrix cores; phase sums,
 transforms and energies in FP64), launched as the captured graph after an
-untimed autotune, with J(k) written on the pair support only (the buffer is
-cleared once).  `value` is density J builds/s (16 per step) from a region timed
+untimed autotune, with J(k) written on the pair support only, packed (the
+layout PWDF_JK_PACKED: [density][k][support element]).  `value` is density J builds/s (16 per step) from a region timed
 with torch.cuda.synchronize() on both sides.
 
 Beside it, on the same slab and densities: the FP64 form with one density per
@@ -142,11 +142,11 @@ def kernel_table(prof):
 
 
 def single_fp64(torch, pwdf, prob, Dt, steps, warmup):
-    """FP64 form, one density per call, support layout, graph replay, autotuned."""
+    """FP64 form, one density per call, packed J(k), graph replay, autotuned."""
     ctx = pwdf.LongRangeJ(prob, precision=pwdf.PWDF_FP64, max_ndm=1)
-    ctx.set_jk_layout(pwdf.PWDF_JK_SUPPORT)
+    ctx.set_jk_layout(pwdf.PWDF_JK_PACKED)
     ctx.autotune(1, None)
-    J = torch.zeros_like(Dt)
+    J = torch.empty((1, prob.nk, ctx.stats()["jk_support"]), dtype=Dt.dtype, device=Dt.device)
     E = torch.empty(1, dtype=torch.float64, device="cuda")
     ms = timed(torch, lambda: ctx.build_j(Dt, J, E, graph=True), steps, warmup)
     st = ctx.stats()
@@ -208,7 +208,6 @@ def main():
     Sk = synth.overlap_k(prob)
     Db = synth.make_densities_torch(prob, NDM, 1000 * prob.seed, Sk)
     del Sk
-    Jb = torch.zeros_like(Db)
     Eb = torch.empty(NDM, dtype=torch.float64, device="cuda")
 
     if args.calib_copy_mib > 0:
@@ -222,9 +221,11 @@ def main():
     # headline: FP32-MFMA form, 16 densities per call, graph replay
     log("FP32-MFMA batch: autotune")
     c32 = pwdf.LongRangeJ(prob, precision=pwdf.PWDF_FP32_MFMA, max_ndm=NDM)
-    c32.set_jk_layout(pwdf.PWDF_JK_SUPPORT)
+    c32.set_jk_layout(pwdf.PWDF_JK_PACKED)
     c32.autotune(NDM, None)
     st = c32.stats()
+    mu, nu = c32.jk_support()
+    Jb = torch.empty((NDM, prob.nk, st["jk_support"]), dtype=Db.dtype, device="cuda")
     log("FP32-MFMA batch: timed region")
     ms = timed(torch, lambda: c32.build_j(Db, Jb, Eb, graph=True), args.steps, args.warmup)
     J32_0 = Jb[0].clone()
@@ -265,7 +266,7 @@ def main():
         "config": {"workload": WORKLOAD, "atoms": prob.natm, "nbf": prob.nbf, "nk": prob.nk, "omega": prob.omega,
                    "nG": st["nG"], "unique_pairs": st["npairs"], "ndm_per_step": NDM,
                    "precision": "fp32_mfma (pair-G tiles FP32 on MFMA; phase sums, transforms, energy FP64)",
-                   "jk_layout": "support", "jk_support_elements": st["jk_support"],
+                   "jk_layout": "packed support", "jk_support_elements": st["jk_support"],
                    "launch": "graph replay, autotuned", "seg_len": st["seg_len"]},
         "pair_G_evals_per_s": st["pairG_evals"] * dens_per_s,
         "pair_G_evals_per_density_build": st["pairG_evals"],
@@ -305,7 +306,7 @@ def main():
         out["cpu_baseline"] = {"value": 1.0 / el, "unit": "J builds/s", "cores": cores, "kind": "oracle",
                                "sample": f"one full FP64 oracle J build of slab density 0 ({el:.1f} s); "
                                          f"the batch of {NDM} would take {NDM * el:.0f} s"}
-        Jr = ref["J"]
+        Jr = ref["J"][:, mu, nu]  # the packed element order
         out["parity_vs_oracle"] = {
             "fp64_single": {"dE_J": abs(E64 - ref["E_G"]),
                             "max_abs_dJ": float(np.max(np.abs(J64[0].cpu().numpy() - Jr)))},

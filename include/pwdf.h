@@ -90,9 +90,12 @@ typedef enum {
 /* What pwdf_build_j writes into J(k) (pwdf_set_jk_layout). */
 typedef enum {
   PWDF_JK_FULL = 0,    /* every element of J(k): zeros off the pair support (default) */
-  PWDF_JK_SUPPORT = 1  /* only the elements on the pair support (pwdf_stats.jk_support per k
+  PWDF_JK_SUPPORT = 1, /* only the elements on the pair support (pwdf_stats.jk_support per k
                           and density); the others are never written, so the caller clears
                           J(k) once and keeps the buffer */
+  PWDF_JK_PACKED = 2   /* the support elements only, packed: J(k) is complex128
+                          [ndm][nk][jk_support] in the element order of
+                          pwdf_get_jk_support */
 } pwdf_jk_layout;
 
 typedef struct {
@@ -168,6 +171,16 @@ pwdf_status pwdf_query(const pwdf_ctx *ctx, pwdf_stats *out);
 pwdf_status pwdf_set_jk_layout(pwdf_ctx *ctx, int layout);
 
 /*
+ * Element order of the packed J(k) layout: for i < pwdf_stats.jk_support, the
+ * i-th packed value of every (density, k) plane is J_{mu[i], nu[i]}(k).  mu and
+ * nu are host arrays of jk_support ints (either may be NULL).  The elements are
+ * the support of eq. "FT of J" (both triangles); the ones summed by one thread
+ * come first in ascending row-major order, the ones with more than 8 lattice
+ * image classes (summed by one wave each) follow.  Host only.
+ */
+pwdf_status pwdf_get_jk_support(const pwdf_ctx *ctx, int *mu, int *nu);
+
+/*
  * Input check of the calls made since the previous check: the D(k) -> D(L)
  * launch of every build / gradient / rho call sets a device flag when a phase
  * sum over the D(k) values of a support element is not finite (a NaN or inf in
@@ -196,7 +209,8 @@ pwdf_status pwdf_plan_stats(const double lattice[9], int natm, const double *xyz
  *   ndm   1 <= ndm <= max_ndm.
  *   Dk    device, complex128 [ndm][nk][nbf][nbf], Hermitian per k; read only.
  *   Jk    device, same layout; every element written (zeros off the pair support),
- *         or only the elements on the pair support (pwdf_set_jk_layout).
+ *         or only the elements on the pair support (pwdf_set_jk_layout); packed
+ *         layout: complex128 [ndm][nk][jk_support] (pwdf_get_jk_support).
  *   EJ    device, double [ndm]; written with E_J of each density.
  *   stream  hipStream_t or NULL.
  * Dk and Jk must not overlap.  Enqueue only.

@@ -150,22 +150,40 @@ void drop_graph(pwdf_ctx *c) {
 // The tune multipliers scale the chunk counts per class.
 void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
   const int SEG = p.seg_len;
-  const double target = 4096.0;
+  // FP32-MFMA form: one launch per class, the classes overlapping on the
+  // internal streams; its waves hold 90-154 VGPRs (3-5 per SIMD)
+  const double target = d.fp32 ? 8192.0 : 4096.0;
   // the low-L classes share S across d.ndb densities per block (at most 32 / SEG,
   // chosen at launch); chunk counts are those of one density block (a batch
   // adds blocks along the density axis of the grid)
   d.ndb = max_ndm >= 4 ? 4 : (max_ndm >= 2 ? 2 : 1);
   d.rho_bs = 256;  // 64 segments x 4 waves sharing them
   double wsumR = 0.0, wsumJ = 0.0, wR[kMaxLsum + 1], wJ[kMaxLsum + 1];
+  int jzg[kMaxLsum + 1];  // FP32-MFMA J pass: N-tile groups (grid z) per pair block
   for (int L = 0; L <= kMaxLsum; ++L) {
     const int np = p.L_p1[L] - p.L_p0[L];
-    const double cost = 2.0 * L + 10.0 + (70.0 + nherm(L)) / SEG;
-    wR[L] = np > 0 ? (double)np * cost : 0.0;
-    wJ[L] = np > 0 ? (double)((np + 63) / 64) * 64.0 * cost : 0.0;
+    double costR = 2.0 * L + 10.0 + (70.0 + nherm(L)) / SEG, costJ = costR;
+    jzg[L] = 1;
+    if (d.fp32) {
+      // per K-step of a wave (16 G points x 4 pairs): the pair factor is evaluated
+      // once per group of N-tiles (~120 VALU cycles) and each N-tile of 16 (k, dm)
+      // columns costs two MFMAs of 32 cycles; rho groups up to 8 N-tiles, J 4
+      const int nt = std::max(1, d.ncols32[L] / 16);
+      const int ntg = nt <= 1 ? 1 : nt <= 2 ? 2 : nt <= 4 ? 4 : 8;
+      jzg[L] = (nt + 3) / 4;
+      costR = ((nt + ntg - 1) / ntg) * 120.0 + 64.0 * nt;
+      costJ = jzg[L] * 120.0 + 64.0 * nt;
+    }
+    wR[L] = np > 0 ? (double)np * costR : 0.0;
+    wJ[L] = np > 0 ? (double)((np + 63) / 64) * 64.0 * costJ : 0.0;
     wsumR += wR[L];
     wsumJ += wJ[L];
   }
-  const int rho_waves_per_chunk = std::max(4, ((p.nseg() + 63) / 64) * 4);
+  // rho: a chunk spans the G set in groups of 64 segments (FP64) or 64 points
+  // (FP32-MFMA form), four waves each; J: the FP64 form splits the segments
+  // into chunks, the FP32-MFMA form the points
+  const int ngi = d.fp32 ? (int)p.pts.size() : p.nseg();
+  const int rho_waves_per_chunk = std::max(4, ((ngi + 63) / 64) * 4);
   wsumR = std::max(wsumR, 1.0);  // no pairs: every class is skipped below
   wsumJ = std::max(wsumJ, 1.0);
   constexpr double kMinGroupWaves = 1024.0;
@@ -202,11 +220,13 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
     d.rho_chunks[L] = ch;
     d.rho_ppc[L] = ppc;
     rows += ch;
-    const int jw = (np + 63) / 64;  // active waves per segment chunk
+    // active waves per chunk: a pair per lane (FP64), 16 pairs per wave and one
+    // block row per N-tile group (FP32-MFMA)
+    const int jw = d.fp32 ? 4 * ((np + 63) / 64) * jzg[L] : (np + 63) / 64;
     int jc = (int)std::lround(tJ[L > 2] * (wJ[L] / gJ[L > 2]) * tn.mj[L] / jw);
-    jc = std::max(1, std::min(p.nseg(), jc));
-    int spc = std::max(1, (p.nseg() + jc - 1) / jc);
-    jc = (p.nseg() + spc - 1) / spc;  // 0 when the G set is empty
+    jc = std::max(1, std::min(ngi, jc));
+    int spc = std::max(1, (ngi + jc - 1) / jc);
+    jc = (ngi + spc - 1) / spc;  // 0 when the G set is empty
     d.j_chunks[L] = jc;
     d.j_spc[L] = spc;
     yoff += (int64_t)jc * nherm(L) * np;
@@ -243,6 +263,7 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   d.natm = in.natm;
   d.nseg = p.nseg();
   d.nslot = p.nslot();
+  d.npts = (int)p.pts.size();
   d.seg_len = p.seg_len;
   d.nelem = p.nelem;
   d.vol = p.vol;
@@ -261,7 +282,7 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   for (int i = 0; i < 3; ++i) d.kmesh[i] = in.kmesh[i];
   d.nheavyJ = (int)p.heavyJ.size();
   d.nlightJ = (int)p.lightJ.size();
-  d.jk_support = c->jk_layout == PWDF_JK_SUPPORT ? 1 : 0;
+  d.jk_layout = c->jk_layout;
   d.fp32 = c->prec == PWDF_FP32_MFMA ? 1 : 0;
   if (d.fp32) {
     d.ndmp = 1;
@@ -286,6 +307,7 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
 #define UP(vec, field) \
   if ((e = upload(c, vec, &d.field)) != hipSuccess) return hip_fail(c, e, "uploading " #field);
   UP(p.segs, segs)
+  UP(p.pts, pts)
   UP(p.slot_v, slot_v)
   UP(p.hot, hot)
   UP(p.hot_rho, hot_rho)
@@ -731,11 +753,24 @@ pwdf_status pwdf_query(const pwdf_ctx *c, pwdf_stats *out) {
 
 pwdf_status pwdf_set_jk_layout(pwdf_ctx *c, int layout) {
   if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_set_jk_layout: ctx is NULL");
-  if (layout != PWDF_JK_FULL && layout != PWDF_JK_SUPPORT)
-    return fail(c, PWDF_EINVAL, "layout must be PWDF_JK_FULL or PWDF_JK_SUPPORT");
+  if (layout != PWDF_JK_FULL && layout != PWDF_JK_SUPPORT && layout != PWDF_JK_PACKED)
+    return fail(c, PWDF_EINVAL, "layout must be PWDF_JK_FULL, PWDF_JK_SUPPORT or PWDF_JK_PACKED");
   if (layout != c->jk_layout) drop_graph(c);  // the captured J(k) launch has the old shape
   c->jk_layout = layout;
-  c->dev.jk_support = layout == PWDF_JK_SUPPORT ? 1 : 0;
+  c->dev.jk_layout = layout;
+  return PWDF_OK;
+}
+
+pwdf_status pwdf_get_jk_support(const pwdf_ctx *c, int *mu, int *nu) {
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_get_jk_support: ctx is NULL");
+  const Plan &p = c->plan;
+  size_t i = 0;
+  for (const std::vector<int> *v : {&p.lightJ, &p.heavyJ})
+    for (int e : *v) {
+      if (mu) mu[i] = e / p.nbf;
+      if (nu) nu[i] = e % p.nbf;
+      ++i;
+    }
   return PWDF_OK;
 }
 
@@ -877,7 +912,9 @@ static std::string tune_key(const pwdf_ctx *c, int ndm) {
 
 // Segment lengths the kernels are built for, per precision form.
 static std::vector<int> seg_lengths(int prec) {
-  return prec == PWDF_FP32_MFMA ? std::vector<int>{4, 8} : std::vector<int>{4, 5, 8, 16};
+  // the FP32-MFMA pair-G kernels walk the compact point list: the segment length
+  // only sets the slot layout of rho and V there
+  return prec == PWDF_FP32_MFMA ? std::vector<int>{8} : std::vector<int>{4, 5, 8, 16};
 }
 
 static bool load_tune(const char *path, const std::string &key, Tune &t) {

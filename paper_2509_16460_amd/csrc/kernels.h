@@ -15,6 +15,8 @@ struct Dev {
   double vol;
   // static plan data (device)
   const SegDesc *segs;
+  const GPoint *pts;             // the half-space G vectors as a compact list (FP32-MFMA form)
+  int npts;
   const double *slot_v;
   const PairHot *hot;
   const PairHot *hot_rho;        // pair records in the rho pass's order (sorted by p for L <= 2)
@@ -36,7 +38,7 @@ struct Dev {
   int nheavyJ;
   const int *lightJ;             // the other support elements (1 .. kPhaseLight classes), ascending
   int nlightJ;
-  int jk_support;                // 1: J(k) is written on the pair support only
+  int jk_layout;                 // pwdf_jk_layout: 0 every element, 1 the support in place, 2 packed
   int *nonfinite;                // set to 1 by phase_d when a D(L) phase sum is not finite
   double *Jfold;                 // [ndm][nsegJ]
   const double2 *ptab;           // e^{2 pi i t / N}

@@ -442,6 +442,9 @@ __global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ part
     double e = 0.0;
     if (g < nslot) {
       const double v = slot_v[g];
+      // padding slots (v = 0) hold no G vector: the FP32-MFMA rho pass never
+      // writes them, so whatever their partial rows hold is dropped here
+      if (v == 0.0) r = i = 0.0;
       rho[(size_t)dm * nslot + g] = make_double2(r, i);
       Vc[(size_t)dm * nslot + g] = make_double2(v * r, -v * i);
       e = vol * v * (r * r + i * i);
@@ -1071,13 +1074,14 @@ __device__ __forceinline__ void phase_j_body(const double2 *__restrict__ sph, co
 
 // i0 indexes the light support list lightJ when it is given (support-only J(k):
 // only elements with 1 .. kPhaseLight classes are visited), else the elements
-// of the whole matrix (zeros written off the support).
+// of the whole matrix (zeros written off the support).  J(k) of density dm and
+// k-point k starts at Jk + (dm nk + k) kstride; the element goes to offset e (in
+// place) or to its list position i0 (packed).
 __device__ __forceinline__ void phase_j_light(const double2 *__restrict__ sph, const double *__restrict__ Jfold,
                                               int nsegJ, const int *__restrict__ sJ_off,
                                               const int *__restrict__ sJ_code, int nk, int n1, int n2, int n3,
-                                              int nbf, double2 *__restrict__ Jk, const int *__restrict__ lightJ,
-                                              int64_t nlist, int64_t i0, int dm) {
-  const int64_t nn = (int64_t)nbf * nbf;
+                                              double2 *__restrict__ Jk, int64_t kstride, bool packed,
+                                              const int *__restrict__ lightJ, int64_t nlist, int64_t i0, int dm) {
   // lanes past the end and heavy elements take part with no classes and store nothing
   const bool inb = i0 < nlist;
   const int64_t ii = inb ? i0 : nlist - 1;
@@ -1101,35 +1105,35 @@ __device__ __forceinline__ void phase_j_light(const double2 *__restrict__ sph, c
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) nmax = max(nmax, __shfl_xor(nmax, off, 64));
   if (!mine) return;
-  double2 *out = Jk + (size_t)dm * nk * nn + e;
+  double2 *out = Jk + (size_t)dm * nk * kstride + (packed ? ii : e);
   if (nmax == 0) {
-    for (int k = 0; k < nk; ++k) store_jk(out + (size_t)k * nn, 0.0, 0.0);
+    for (int k = 0; k < nk; ++k) store_jk(out + (size_t)k * kstride, 0.0, 0.0);
   } else if (nmax == 1) {
-    phase_j_body<1>(sph, c1, c2, c3, v, n1, n2, n3, (size_t)nn, out);
+    phase_j_body<1>(sph, c1, c2, c3, v, n1, n2, n3, (size_t)kstride, out);
   } else if (nmax == 2) {
-    phase_j_body<2>(sph, c1, c2, c3, v, n1, n2, n3, (size_t)nn, out);
+    phase_j_body<2>(sph, c1, c2, c3, v, n1, n2, n3, (size_t)kstride, out);
   } else if (nmax <= 4) {
-    phase_j_body<4>(sph, c1, c2, c3, v, n1, n2, n3, (size_t)nn, out);
+    phase_j_body<4>(sph, c1, c2, c3, v, n1, n2, n3, (size_t)kstride, out);
   } else {
-    phase_j_body<kPhaseLight>(sph, c1, c2, c3, v, n1, n2, n3, (size_t)nn, out);
+    phase_j_body<kPhaseLight>(sph, c1, c2, c3, v, n1, n2, n3, (size_t)kstride, out);
   }
 }
 
 // Heavy elements: one wave per element, lanes = k-points (64 at a time), the
 // element's classes loaded 64 at a time and broadcast lane by lane, four per
 // step so that their table reads overlap.
+// (packed J(k): heavy element h goes to list position hpos0 + h)
 __device__ __forceinline__ void phase_j_heavy(const double2 *__restrict__ sph, const double *__restrict__ Jfold,
                                               int nsegJ, const int *__restrict__ heavy, int nheavy,
                                               const int *__restrict__ sJ_off, const int *__restrict__ sJ_code,
-                                              int nk, int n2, int n3, int nbf, double2 *__restrict__ Jk, int h,
-                                              int dm) {
+                                              int nk, int n2, int n3, double2 *__restrict__ Jk, int64_t kstride,
+                                              bool packed, int64_t hpos0, int h, int dm) {
   const int lane = threadIdx.x & 63;
   if (h >= nheavy) return;
-  const int64_t nn = (int64_t)nbf * nbf;
   const int64_t e = heavy[h];
   const int s0 = sJ_off[e], s1 = sJ_off[e + 1];
   const double *Jf = Jfold + (size_t)dm * nsegJ;
-  double2 *out = Jk + (size_t)dm * nk * nn + e;
+  double2 *out = Jk + (size_t)dm * nk * kstride + (packed ? hpos0 + h : e);
   const int n23 = n2 * n3;
   for (int kb = 0; kb < nk; kb += 64) {
     const int k = kb + lane;
@@ -1161,7 +1165,7 @@ __device__ __forceinline__ void phase_j_heavy(const double2 *__restrict__ sph, c
         }
       }
     }
-    if (k < nk) store_jk(out + (size_t)k * nn, re, im);
+    if (k < nk) store_jk(out + (size_t)k * kstride, re, im);
   }
 }
 
@@ -1356,7 +1360,8 @@ __global__ __launch_bounds__(256) void k_phase_j_all(const double *__restrict__ 
                                                      const int *__restrict__ heavy, int nheavy,
                                                      const int *__restrict__ lightJ, int64_t nlist, int nlight,
                                                      const double2 *__restrict__ ptab, int ptab_len, int nk, int n1,
-                                                     int n2, int n3, int nbf, double2 *__restrict__ Jk,
+                                                     int n2, int n3, double2 *__restrict__ Jk, int64_t kstride,
+                                                     int packed,
                                                      const double *__restrict__ Epart, int nparts,
                                                      double *__restrict__ EJ) {
   __shared__ double2 sph[kPtabMax];
@@ -1370,10 +1375,10 @@ __global__ __launch_bounds__(256) void k_phase_j_all(const double *__restrict__ 
   __syncthreads();
   const int dm = blockIdx.y;
   if (bx < nlight)
-    phase_j_light(sph, Jfold, nsegJ, sJ_off, sJ_code, nk, n1, n2, n3, nbf, Jk, lightJ, nlist,
+    phase_j_light(sph, Jfold, nsegJ, sJ_off, sJ_code, nk, n1, n2, n3, Jk, kstride, packed != 0, lightJ, nlist,
                   (int64_t)bx * blockDim.x + threadIdx.x, dm);
   else
-    phase_j_heavy(sph, Jfold, nsegJ, heavy, nheavy, sJ_off, sJ_code, nk, n2, n3, nbf, Jk,
+    phase_j_heavy(sph, Jfold, nsegJ, heavy, nheavy, sJ_off, sJ_code, nk, n2, n3, Jk, kstride, packed != 0, nlist,
                   (bx - nlight) * 4 + (threadIdx.x >> 6), dm);
 }
 
@@ -1551,16 +1556,20 @@ hipError_t launch_fold_j(const Dev &d, int ndm, hipStream_t st) {
 
 hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, double *EJ, hipStream_t st) {
   if (d.ptab_len > kPtabMax) return hipErrorInvalidValue;
-  // light path: the support list (support-only J(k)) or every element (zeros off
-  // the support)
-  const int64_t nlist = d.jk_support ? (int64_t)d.nlightJ : (int64_t)d.nbf * d.nbf;
+  // light path: the support list (support-only or packed J(k)) or every element
+  // (zeros off the support); k-planes of nbf^2 elements, or of the support list
+  // (light elements, then heavy ones) when packed
+  const bool list = d.jk_layout != 0, packed = d.jk_layout == 2;
+  const int64_t nn = (int64_t)d.nbf * d.nbf;
+  const int64_t nlist = list ? (int64_t)d.nlightJ : nn;
+  const int64_t kstride = packed ? (int64_t)d.nlightJ + d.nheavyJ : nn;
   const int nlight = (int)((nlist + 255) / 256);
   const int nheavy_blocks = (d.nheavyJ + 3) / 4;
   if (nlight + nheavy_blocks + (EJ ? 1 : 0) == 0) return hipSuccess;
   dim3 grid((unsigned)(nlight + nheavy_blocks + (EJ ? 1 : 0)), ndm);
   hipLaunchKernelGGL(k_phase_j_all, grid, dim3(256), 0, st, d.Jfold, d.nsegJ, d.sJ_off, d.sJ_code, d.heavyJ,
-                     d.nheavyJ, d.jk_support ? d.lightJ : nullptr, nlist, nlight, d.ptab, d.ptab_len, d.nk,
-                     d.kmesh[0], d.kmesh[1], d.kmesh[2], d.nbf, (double2 *)Jk, d.Epart, d.nred_blocks, EJ);
+                     d.nheavyJ, list ? d.lightJ : nullptr, nlist, nlight, d.ptab, d.ptab_len, d.nk, d.kmesh[0],
+                     d.kmesh[1], d.kmesh[2], (double2 *)Jk, kstride, packed ? 1 : 0, d.Epart, d.nred_blocks, EJ);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }

@@ -67,6 +67,7 @@ void build_segments(Plan &p, int seg_len) {
   p.slot_v.clear();
   p.slot_miller.clear();
   p.valid_slots.clear();
+  p.pts.clear();
   const double gcut2 = 4.0 * p.in.omega * p.in.omega * (-std::log(p.in.eps_G));
   const double gcut = std::sqrt(gcut2);
   int nmax[3];
@@ -116,6 +117,7 @@ void build_segments(Plan &p, int seg_len) {
             double g2 = g2_of(p, n);
             vg = 4.0 * kPi * std::exp(-g2 / w4) / g2;
             p.valid_slots.push_back(sidx * seg_len + s);
+            p.pts.push_back({g2, nu0 + s, nv, nw, sidx * seg_len + s});
             ++count;
           }
           p.slot_v.push_back(vg);

@@ -35,6 +35,7 @@ struct Plan {
   std::vector<double> slot_v;       // v(G) per slot, 0 on padding
   std::vector<int> slot_miller;     // [nslot][3] in the original axis order (padding: 0,0,0)
   std::vector<int> valid_slots;     // slots holding a G, in walk order
+  std::vector<GPoint> pts;          // the same G vectors as a compact point list
   int64_t nG_full = 0;              // |G set| including -G
   // lattice images of the pair list
   std::vector<std::array<int, 3>> imgs;

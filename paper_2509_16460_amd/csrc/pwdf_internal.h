@@ -42,6 +42,16 @@ struct SegDesc {
   double dg0;  // |G(nu0+1)|^2 - |G(nu0)|^2
 };
 
+// One G vector of the half space the kernels walk, for the FP32-MFMA form, which
+// evaluates the pair factor at every point directly instead of along lines:
+// |G|^2, the relative coordinates (u, v, w) and the slot of the point in the
+// segment layout (where rho and V live).
+struct GPoint {
+  double g2;
+  int nu, nv, nw;
+  int slot;
+};
+
 // Per primitive pair, read by the pair-G kernels (64 bytes).
 struct PairHot {
   double inv4p;      // 1/(4p)

@@ -24,10 +24,12 @@ _STATUS = {0: "PWDF_OK", -1: "PWDF_EINVAL", -2: "PWDF_ENOMEM", -3: "PWDF_EDEVICE
 
 PWDF_JK_FULL = 0
 PWDF_JK_SUPPORT = 1
+PWDF_JK_PACKED = 2
 
 EXPORTED = ["pwdf_create", "pwdf_query", "pwdf_build_j", "pwdf_build_j_graph", "pwdf_get_rhoG", "pwdf_grad",
             "pwdf_autotune", "pwdf_last_error", "pwdf_destroy", "pwdf_plan_stats",
-            "pwdf_profile_enable", "pwdf_profile_read", "pwdf_set_jk_layout", "pwdf_check_input"]
+            "pwdf_profile_enable", "pwdf_profile_read", "pwdf_set_jk_layout", "pwdf_check_input",
+            "pwdf_get_jk_support"]
 
 
 class PwdfError(RuntimeError):
@@ -94,6 +96,8 @@ def lib():
         L.pwdf_profile_read.argtypes = [vp, ctypes.POINTER(KProf), ctypes.c_int, ip]
         L.pwdf_set_jk_layout.restype = ctypes.c_int
         L.pwdf_set_jk_layout.argtypes = [vp, ctypes.c_int]
+        L.pwdf_get_jk_support.restype = ctypes.c_int
+        L.pwdf_get_jk_support.argtypes = [vp, ip, ip]
         L.pwdf_check_input.restype = ctypes.c_int
         L.pwdf_check_input.argtypes = [vp, vp]
         L.pwdf_last_error.restype = ctypes.c_char_p
@@ -196,12 +200,34 @@ class LongRangeJ:
         return Dk
 
     def set_jk_layout(self, layout: int):
-        """PWDF_JK_FULL (every element of J(k) written) or PWDF_JK_SUPPORT (only the
-        pair support; a J(k) buffer passed in must have been cleared once)."""
+        """PWDF_JK_FULL (every element of J(k) written), PWDF_JK_SUPPORT (only the
+        pair support; a J(k) buffer passed in must have been cleared once) or
+        PWDF_JK_PACKED (J(k) as [ndm][nk][jk_support], element order of
+        jk_support())."""
         rc = lib().pwdf_set_jk_layout(self._h, int(layout))
         if rc != 0:
             self._err(rc)
         self._jk_layout = int(layout)
+
+    def jk_support(self):
+        """(mu, nu) int arrays of the packed J(k) element order."""
+        n = self.stats()["jk_support"]
+        mu = np.zeros(max(n, 1), dtype=np.int32)
+        nu = np.zeros(max(n, 1), dtype=np.int32)
+        rc = lib().pwdf_get_jk_support(self._h, _ip(mu), _ip(nu))
+        if rc != 0:
+            self._err(rc)
+        return mu[:n], nu[:n]
+
+    def unpack_jk(self, Jp):
+        """Dense [ndm][nk][nbf][nbf] J(k) (zeros off the support) from the packed layout."""
+        import torch
+        mu, nu = self.jk_support()
+        p = self.prob
+        idx = torch.from_numpy(mu.astype(np.int64) * p.nbf + nu).to(Jp.device)
+        out = torch.zeros((Jp.shape[0], p.nk, p.nbf * p.nbf), dtype=Jp.dtype, device=Jp.device)
+        out[:, :, idx] = Jp
+        return out.view(Jp.shape[0], p.nk, p.nbf, p.nbf)
 
     def check_input(self, stream=None):
         """Raises PwdfError(PWDF_ENONFINITE) if a call since the last check read a
@@ -220,7 +246,13 @@ class LongRangeJ:
         Dk = self._check_D(Dk)
         ndm = Dk.shape[0]
         if Jk is None:
-            Jk = torch.zeros_like(Dk) if getattr(self, "_jk_layout", 0) == PWDF_JK_SUPPORT else torch.empty_like(Dk)
+            layout = getattr(self, "_jk_layout", PWDF_JK_FULL)
+            if layout == PWDF_JK_PACKED:
+                Jk = torch.empty((ndm, self.prob.nk, self.stats()["jk_support"]), dtype=Dk.dtype, device=Dk.device)
+            elif layout == PWDF_JK_SUPPORT:
+                Jk = torch.zeros_like(Dk)
+            else:
+                Jk = torch.empty_like(Dk)
         if EJ is None:
             EJ = torch.empty(ndm, dtype=torch.float64, device=Dk.device)
         fn = lib().pwdf_build_j_graph if graph else lib().pwdf_build_j
@@ -302,6 +334,8 @@ def _autograd_function():
             if got.shape != ref.shape or not np.array_equal(got, ref):
                 raise ValueError("xyz differs from the geometry of the plan; build a new LongRangeJ")
             Jk, EJ = plan.build_j(Dk)
+            if getattr(plan, "_jk_layout", PWDF_JK_FULL) == PWDF_JK_PACKED:
+                Jk = plan.unpack_jk(Jk)
             ctx.save_for_backward(Dk, Jk)
             ctx.plan = plan
             ctx.xyz_meta = (xyz.device, xyz.dtype)

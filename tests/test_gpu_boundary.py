@@ -2,7 +2,8 @@
 
 * J(k) layouts: PWDF_JK_SUPPORT writes exactly the elements on the pair support
   (eq. "FT of J" is a sum over the screened pairs' images, so the others are
-  zero) and never touches the rest; PWDF_JK_FULL writes every element.  Checked
+  zero) and never touches the rest; PWDF_JK_FULL writes every element;
+  PWDF_JK_PACKED writes the support elements contiguously in the reported order.  Checked
   element by element against the FP64 oracle after builds with two different
   densities (eager and graph replay), with the off-support elements holding a
   sentinel the library must leave alone.
@@ -82,6 +83,19 @@ def test_jk_layouts_against_oracle(precision):
     Jfh = Jf.cpu().numpy()[0]
     assert np.all(Jfh[:, ~mask] == 0)
     assert np.array_equal(Jfh[:, mask], J.cpu().numpy()[0][:, mask])
+    # packed: the support elements in the order pwdf_get_jk_support reports, the
+    # same values as in place; every support element exactly once
+    ctx.set_jk_layout(pwdf.PWDF_JK_PACKED)
+    mu, nu = ctx.jk_support()
+    assert len(mu) == int(mask.sum()) and np.all(mask[mu, nu])
+    assert len(set(zip(mu.tolist(), nu.tolist()))) == len(mu)
+    for graph in (False, True):
+        Jp = torch.empty((1, prob.nk, len(mu)), dtype=torch.complex128, device="cuda")
+        Ep = torch.empty(1, dtype=torch.float64, device="cuda")
+        ctx.build_j(torch.from_numpy(D2[None]).cuda(), Jp, Ep, graph=graph)
+        torch.cuda.synchronize()
+        assert np.array_equal(Jp.cpu().numpy()[0], Jfh[:, mu, nu])
+        assert np.array_equal(ctx.unpack_jk(Jp).cpu().numpy()[0], Jfh)
 
 
 def test_nonfinite_density_is_reported():

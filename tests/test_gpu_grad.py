@@ -6,9 +6,12 @@
   same pair count at the displaced geometries (truncation ~ delta^2 E''' / 6);
 * the autograd Function: xyz.grad = pwdf_grad, and the D(k) gradient
   w_k conj J(k) matches a finite difference along a Hermitian direction;
-* the molecular-crystal workload (48 atoms, 3x3x3 k-mesh) at full size:
-  sum rule and finite differences for two atoms.
+* the molecular-crystal workload (48 atoms, 3x3x3 k-mesh) at full size: E_J,
+  the gradient of all atoms and sampled J(k) against the oracle (stored
+  values), sum rule, finite differences for two atoms in FP64 and FP32-MFMA.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -17,6 +20,8 @@ from paper_2509_16460_amd import synth
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def pw():
@@ -114,12 +119,53 @@ def test_autograd_function():
     assert abs(fd - an) <= 1e-9 * max(1.0, abs(an))
 
 
-def test_molecular_crystal_full_size():
-    """48-atom monoclinic cell, 3x3x3 mesh: sum rule and FD for two atoms."""
+@pytest.fixture(scope="module")
+def crystal():
+    f = np.load(os.path.join(GOLDEN, "molecular_crystal.npz"))
     p = synth.config_problem(5)
-    D = synth.make_density(p, 5000)
+    D = synth.make_density(p, int(f["density_seed"]))
+    return p, D, f
+
+
+def test_molecular_crystal_vs_oracle(crystal):
+    """48-atom monoclinic cell, 3x3x3 mesh, FP64: E_J, the analytic gradient of all
+    48 atoms and J(k) at 12k sampled support elements against the oracle (stored
+    values, tests/golden/molecular_crystal.npz)."""
+    p, D, f = crystal
+    g, E, ctx = grad_gpu(p, D)
+    J, EJ = ctx.build_j(torch.from_numpy(D[None]).cuda())
+    torch.cuda.synchronize()
+    idx = f["idx"]
+    Js = J.cpu().numpy()[0][idx[:, 0], idx[:, 1], idx[:, 2]]
+    scale = float(np.max(np.abs(f["grad"])))
+    dE = abs(E - float(f["E_G"]))
+    dEb = abs(float(EJ.cpu()[0]) - float(f["E_G"]))
+    dg = float(np.max(np.abs(g - f["grad"])))
+    dJ = float(np.max(np.abs(Js - f["J"])))
+    print(f"molecular crystal FP64 vs oracle: E_J={E:.12f} dE={dE:.2e} (build {dEb:.2e}) max|dg|={dg:.2e} "
+          f"(max|g| {scale:.2e}) max|dJ|={dJ:.2e} (max|J| {float(f['maxJ']):.2e})", flush=True)
+    assert dE <= 1e-10 and dEb <= 1e-10
+    assert dg <= 1e-10 * max(1.0, scale)
+    assert dJ <= 1e-11 * max(1.0, float(f["maxJ"]))
+    assert np.max(np.abs(g.sum(0))) <= 1e-10 * max(1.0, scale)
+
+
+def test_molecular_crystal_finite_differences(crystal):
+    """Central differences (delta = 1e-4 Bohr) for two atoms, FP64 and FP32-MFMA.
+    The FP32 form's energies carry rounding of the FP32 tiles; most of it is the
+    same at the displaced geometries (same pairs, same G set), the rest enters the
+    difference quotient divided by 2 delta: its bar is 4 |E32 - E64| / delta on
+    top of the FD truncation, with E32 - E64 measured at the base geometry."""
+    p, D, _ = crystal
     worst, scale, g = fd_check(p, D, atoms=[0, 17])
-    print(f"molecular crystal: max|g|={scale:.3e} worst FD err {worst:.2e} sum={np.max(np.abs(g.sum(0))):.2e}",
-          flush=True)
-    assert np.max(np.abs(g.sum(0))) <= 1e-10 * scale
+    print(f"molecular crystal FP64: max|g|={scale:.3e} worst FD err {worst:.2e}", flush=True)
     assert worst <= 1e-7 * max(1.0, scale)
+    E64, _ = energy_gpu(p, D, 0)
+    E32, _ = energy_gpu(p, D, pw().PWDF_FP32_MFMA)
+    worst32, scale32, g32 = fd_check(p, D, atoms=[0, 17], prec=pw().PWDF_FP32_MFMA)
+    bar = 4 * abs(E32 - E64) / 1e-4 + 1e-7 * max(1.0, scale)
+    rel = np.max(np.abs(g32 - g)) / scale
+    print(f"molecular crystal FP32-MFMA: |E32-E64|={abs(E32 - E64):.2e} worst FD err {worst32:.2e} "
+          f"(bar {bar:.2e}); gradient vs FP64 rel {rel:.2e}", flush=True)
+    assert worst32 <= bar
+    assert rel <= 1e-4

@@ -138,7 +138,9 @@ def test_autotune_full_diamond_cell():
     assert torch.equal(Jg, J1) and torch.equal(Eg, E1)
 
 
-@pytest.mark.parametrize("prec,segs", [(0, (4, 5, 8, 16)), (1, (4, 8))], ids=["fp64", "fp32_mfma"])
+# the FP32-MFMA pair-G kernels walk a compact list of G points; its slot layout
+# uses 8-point segments only
+@pytest.mark.parametrize("prec,segs", [(0, (4, 5, 8, 16)), (1, (8,))], ids=["fp64", "fp32_mfma"])
 def test_every_segment_length_matches_oracle(prec, segs, tmp_path):
     """Each segment length the kernels are built for, forced through a tune-cache
     entry (applied without timing), against the oracle; a length the kernels are
@@ -163,7 +165,7 @@ def test_every_segment_length_matches_oracle(prec, segs, tmp_path):
         dJ = float(np.max(np.abs(J.cpu().numpy()[0] - ref["J"])))
         print(f"prec={prec} seg={seg} nseg={ctx.stats()['nseg']} dE={dE:.2e} dJ={dJ:.2e}", flush=True)
         assert dE <= e_tol and dJ <= j_tol
-    cache.write_text(f"{key} 7 {ones}\n")
+    cache.write_text(f"{key} {7 if prec == 0 else 4} {ones}\n")
     ctx = pw().LongRangeJ(p, precision=prec, max_ndm=1)
     with pytest.raises(pw().PwdfError) as ei:
         ctx.autotune(1, str(cache))
