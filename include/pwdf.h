@@ -234,6 +234,29 @@ pwdf_status pwdf_build_j_graph(pwdf_ctx *ctx, int ndm, const double *Dk, double 
                                void *stream);
 
 /*
+ * pwdf_build_j for callers that cannot allocate device memory at all (code
+ * being captured into a HIP graph, tight serving loops, hosts that forbid
+ * hipMalloc after start-up): the same launch sequence and results as
+ * pwdf_build_j (bit for bit), but every per-call workspace of the build
+ * (D(L) / J(L) blocks, transform coefficients, moment and partial-row arrays,
+ * rho, V, energy partials, folded J, FP32-MFMA operands) lives in one static
+ * device array of the library, 64 MiB per device, held by every device the
+ * library is loaded on until the process ends.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine); the context's own
+ * allocations from pwdf_create (plan tables) are used as they are.
+ *   Arguments, layouts and errors as pwdf_build_j, plus PWDF_EUNSUPPORTED
+ *   (message states the bytes needed) when ndm densities of this plan need
+ *   more workspace than the static array holds.
+ * Every call on one device shares that device's array, whatever the context:
+ * calls that overlap in time on one device (other streams, other threads, a
+ * graph replay racing an eager call) race on it, so order them on one stream.
+ * The array keeps the previous call's contents; the call clears what must
+ * start at zero itself (with a kernel, so the call can be captured).
+ */
+pwdf_status pwdf_build_j_noalloc(pwdf_ctx *ctx, int ndm, const double *Dk, double *Jk, double *EJ,
+                                 void *stream);
+
+/*
  * rho(G) of the last computation path for diagnostics: runs the D(k) -> rho(G)
  * part of pwdf_build_j for ndm densities and writes, for the nG/2 vectors of
  * the half space the kernels walk (rho(-G) = conj rho(G)),

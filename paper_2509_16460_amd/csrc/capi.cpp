@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/pwdf.h"
@@ -837,6 +838,69 @@ pwdf_status pwdf_build_j_graph(pwdf_ctx *c, int ndm, const double *Dk, double *J
   }
   if ((e = hipGraphLaunch(g.exec, st)) != hipSuccess) return hip_fail(c, e, "graph launch");
   return PWDF_OK;
+}
+
+// Byte layout of the per-call workspaces of a J build for ndm densities inside
+// one buffer (each piece 256-byte aligned); fills the pointers of d when base is
+// not null and returns the bytes needed.
+static size_t carve_build_ws(Dev &d, const Plan &p, int ndm, unsigned char *base) {
+  size_t off = 0;
+  auto take = [&](auto *&field, size_t count) {
+    using T = std::remove_pointer_t<std::remove_reference_t<decltype(field)>>;
+    off = (off + 255) / 256 * 256;
+    if (base) field = reinterpret_cast<T *>(base + off);
+    off += std::max<size_t>(1, count) * sizeof(T);
+  };
+  const size_t M = (size_t)ndm;
+  take(d.Dblk, M * p.nelem);
+  take(d.Jblk, M * p.nelem);
+  take(d.dhat, M * d.dhat_size);
+  take(d.yhat, M * d.yhat_size);
+  take(d.part, M * d.nrows * d.nslot);
+  take(d.part2, M * d.ngroups * d.nslot);
+  take(d.rho, M * d.nslot);
+  take(d.Vc, M * d.nslot);
+  take(d.Epart, M * d.nred_blocks);
+  take(d.Jfold, M * (size_t)std::max(1, d.nsegJ));
+  if (d.fp32) {
+    take(d.dh32, (size_t)std::max<int64_t>(1, d.d32_size));
+    take(d.wre, (size_t)d.nslot * d.ncolsW);
+    take(d.wim, (size_t)d.nslot * d.ncolsW);
+  }
+  return off;
+}
+
+pwdf_status pwdf_build_j_noalloc(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, double *EJ, void *stream) {
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_build_j_noalloc: ctx is NULL");
+  pwdf_status s = validate_ndm(c, ndm);
+  if (s != PWDF_OK) return s;
+  if (!Dk || !Jk || !EJ) return fail(c, PWDF_EINVAL, "NULL buffer");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  Dev d = c->dev;
+  const size_t need = carve_build_ws(d, c->plan, ndm, nullptr);
+  if (need > kStaticScratchBytes) {
+    char m[256];
+    std::snprintf(m, sizeof m,
+                  "pwdf_build_j_noalloc: %d densities of this plan need %zu bytes of workspace, the static "
+                  "scratch holds %zu (use pwdf_build_j, or fewer densities per call)",
+                  ndm, need, (size_t)kStaticScratchBytes);
+    return fail(c, PWDF_EUNSUPPORTED, m);
+  }
+  void *base = nullptr;
+  if ((e = static_scratch(c->device, &base)) != hipSuccess) return hip_fail(c, e, "static scratch address");
+  carve_build_ws(d, c->plan, ndm, static_cast<unsigned char *>(base));
+  hipStream_t st = (hipStream_t)stream;
+  // the FP32-MFMA operand columns past the densities must read as zeros: the
+  // scratch holds whatever the previous call on this device left there
+  if (d.fp32 && (e = launch_zero_f32(d.dh32, std::max<int64_t>(1, d.d32_size), st)) != hipSuccess)
+    return hip_fail(c, e, "clearing the operand buffer");
+  // the launch sequence of pwdf_build_j on the scratch-backed workspaces
+  const Dev saved = c->dev;
+  c->dev = d;
+  s = enqueue_build(c, ndm, Dk, Jk, EJ, st);
+  c->dev = saved;
+  return s;
 }
 
 pwdf_status pwdf_get_rhoG(pwdf_ctx *c, int ndm, const double *Dk, double *rhoG, int *miller, void *stream) {

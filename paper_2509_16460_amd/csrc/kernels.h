@@ -89,6 +89,13 @@ struct Dev {
   int nred_blocks;
 };
 
+// Allocation-free J build: the per-call workspaces are carved out of a static
+// device array of this many bytes (one per device, held for the process's life).
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+// device address of that array on `device` (looked up once per device)
+hipError_t static_scratch(int device, void **ptr);
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
+
 // FP32-MFMA form (per class L)
 hipError_t launch_rho_mfma_L(const Dev &d, int L, int ndm, hipStream_t st);
 hipError_t launch_wprep(const Dev &d, int ndm, hipStream_t st);

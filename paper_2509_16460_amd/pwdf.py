@@ -29,7 +29,7 @@ PWDF_JK_PACKED = 2
 EXPORTED = ["pwdf_create", "pwdf_query", "pwdf_build_j", "pwdf_build_j_graph", "pwdf_get_rhoG", "pwdf_grad",
             "pwdf_autotune", "pwdf_last_error", "pwdf_destroy", "pwdf_plan_stats",
             "pwdf_profile_enable", "pwdf_profile_read", "pwdf_set_jk_layout", "pwdf_check_input",
-            "pwdf_get_jk_support"]
+            "pwdf_get_jk_support", "pwdf_build_j_noalloc"]
 
 
 class PwdfError(RuntimeError):
@@ -82,6 +82,8 @@ def lib():
         L.pwdf_query.argtypes = [vp, ctypes.POINTER(Stats)]
         L.pwdf_build_j.restype = ctypes.c_int
         L.pwdf_build_j.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+        L.pwdf_build_j_noalloc.restype = ctypes.c_int
+        L.pwdf_build_j_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
         L.pwdf_build_j_graph.restype = ctypes.c_int
         L.pwdf_build_j_graph.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
         L.pwdf_get_rhoG.restype = ctypes.c_int
@@ -236,12 +238,14 @@ class LongRangeJ:
         if rc != 0:
             self._err(rc)
 
-    def build_j(self, Dk, Jk=None, EJ=None, stream=None, graph=False):
+    def build_j(self, Dk, Jk=None, EJ=None, stream=None, graph=False, noalloc=False):
         """Dk: complex128 [ndm][nk][nbf][nbf] (or [nk][nbf][nbf]) on the device.
         Returns (Jk, EJ) device tensors; enqueued on `stream` (default: current).
         graph=True goes through pwdf_build_j_graph (captured once per set of
         buffers, then replayed): pass the same Jk / EJ tensors on every call.
-        In the support layout a J(k) allocated here starts as zeros."""
+        In the support layout a J(k) allocated here starts as zeros.
+        noalloc=True goes through pwdf_build_j_noalloc (workspaces in the
+        library's static device scratch; pass Jk and EJ to allocate nothing)."""
         import torch
         Dk = self._check_D(Dk)
         ndm = Dk.shape[0]
@@ -256,6 +260,8 @@ class LongRangeJ:
         if EJ is None:
             EJ = torch.empty(ndm, dtype=torch.float64, device=Dk.device)
         fn = lib().pwdf_build_j_graph if graph else lib().pwdf_build_j
+        if noalloc:
+            fn = lib().pwdf_build_j_noalloc
         rc = fn(self._h, ndm, ctypes.c_void_p(Dk.data_ptr()), ctypes.c_void_p(Jk.data_ptr()),
                 ctypes.c_void_p(EJ.data_ptr()), self._stream(stream))
         if rc != 0:
