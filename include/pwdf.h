@@ -84,7 +84,11 @@ typedef enum {
   PWDF_FP64 = 0,      /* every step in FP64 */
   PWDF_FP32_MFMA = 1  /* pair-G tiles generated in FP32, contracted on FP32 MFMA,
                          FP64 accumulation across pairs; phase sums, E-coefficient
-                         transforms and the energy stay FP64 */
+                         transforms and the energy stay FP64.  The head of the G
+                         set -- the G whose Coulomb weight v(G) is at least 2^-7
+                         of the largest, a small ball around G = 0 -- takes FP64
+                         tiles on FP64 MFMA (pwdf_stats.pairG_head): the FP32
+                         rounding then scales with the tail's weights */
 } pwdf_precision;
 
 /* What pwdf_build_j writes into J(k) (pwdf_set_jk_layout). */
@@ -102,6 +106,14 @@ typedef struct {
   double eps_pair; /* pair screening on exp(-a_a a_b/p |A-B-L|^2); e.g. 1e-12 */
   double eps_G;    /* G cutoff |G| <= 2 omega sqrt(-ln eps_G); e.g. 1e-12 */
   double r_max;    /* centre-distance cap |A-B-L| <= r_max (Bohr); <= 0: off */
+  int pair_gcut;   /* 1: every pair block (shell a, shell b, image) sees only the G
+                      of the set inside its own cut radius, where the screening
+                      objective 8 pi eta G (4 pi/G^2) e^{-G^2/4w^2} |F|_inf(G),
+                      eta = [1/p + 1/w^2]^-1, of its most compact primitive pair
+                      falls below eps_G (section "Integral screening", eqs. "AFT
+                      screening obj", "eta_munu"; |F|_inf over the Cartesian
+                      components with G along x, y, z); 0: every pair sees the
+                      whole set */
 } pwdf_screen;
 
 typedef struct {
@@ -109,7 +121,8 @@ typedef struct {
   int64_t nG;       /* |G set| (both G and -G); the kernels walk nG/2 of them */
   int64_t npairs;   /* unique primitive pairs (a,b,L) ~ (b,a,-L) counted once */
   int64_t nbf, nk, nimg, nblocks, nseg;
-  double pairG_evals; /* per build and density: 2 passes x npairs x nG/2 */
+  double pairG_evals; /* per build and density: 2 passes x the G each unique pair sees
+                         (npairs x nG/2 without per-pair cuts) */
   double t_us[8];     /* reserved */
   int64_t seg_len;    /* line-segment length of the current launch shapes (pwdf_query) */
   int64_t fork;       /* 1: independent launches of a pass overlap on internal streams;
@@ -120,6 +133,9 @@ typedef struct {
   int64_t dk_support; /* matrix elements of D(k) a build reads per k and density (one
                          of (mu,nu), (nu,mu) for each support pair of elements) */
   int64_t jk_layout;  /* current pwdf_jk_layout (pwdf_query) */
+  int64_t nG_head;    /* G vectors of the half space in the head (v(G) >= 2^-7 max v) */
+  double pairG_head;  /* per build and density: the part of pairG_evals on the head G;
+                         the FP32-MFMA form evaluates it with FP64 tiles */
 } pwdf_stats;
 
 /*

@@ -40,7 +40,7 @@ def lib():
         L.orc_build_j.restype = ctypes.c_int
         L.orc_build_j.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, dp, dp, ip,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                  dp, dp, dp, dp, ip, ctypes.c_int, ip, dp, ctypes.c_int]
+                                  dp, dp, dp, dp, ip, ctypes.c_int, ip, dp, ctypes.c_int, ctypes.c_int]
         L.orc_sizes.restype = ctypes.c_int
         L.orc_sizes.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, dp, dp, ip,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -49,6 +49,9 @@ def lib():
         L.orc_pairs.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, dp, dp, ip,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ip, ctypes.c_int]
+        L.orc_pair_cut.restype = None
+        L.orc_pair_cut.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double, dp,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.orc_ft_axis.restype = None
         L.orc_ft_axis.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
@@ -108,8 +111,10 @@ class OracleResult(dict):
     pass
 
 
-def build_j(prob, Dk, *, want_J=True, want_rho=True, want_grad=False, nthreads=0):
+def build_j(prob, Dk, *, want_J=True, want_rho=True, want_grad=False, nthreads=0, pair_gcut=None):
     """Long-range J, energies, rho(G) and (optionally) dE/dR for one density.
+    pair_gcut (default: prob.pair_gcut): each screened pair sees only the G
+    vectors inside its own cut radius (section "Integral screening").
 
     Dk: complex128 [nk][nbf][nbf].  Returns dict with J (complex [nk][nbf][nbf]),
     E_real, E_G, E_k, maxImJ, maxJ, charge (Omega rho(0)), rho (complex [nG]),
@@ -132,7 +137,7 @@ def build_j(prob, Dk, *, want_J=True, want_rho=True, want_grad=False, nthreads=0
     rc = lib().orc_build_j(*args, _d(Dv), _d(J.view(np.float64)) if want_J else null_d, _d(energy),
                            _d(rho) if want_rho else null_d, _i(miller) if want_rho else null_i,
                            int(nG), ctypes.byref(nG_out), _d(grad) if want_grad else null_d,
-                           int(nthreads))
+                           int(nthreads), int(getattr(prob, "pair_gcut", 0) if pair_gcut is None else pair_gcut))
     if rc != 0:
         raise RuntimeError(f"oracle failed ({rc})")
     out = OracleResult(E_real=energy[0], E_G=energy[1], E_k=energy[2], maxImJ=energy[3],
@@ -145,6 +150,15 @@ def build_j(prob, Dk, *, want_J=True, want_rho=True, want_grad=False, nthreads=0
     if want_grad:
         out["grad"] = grad
     return out
+
+
+def pair_cut(la, lb, aa, RA, ab, RB, omega, eps_G, G):
+    """(screening objective at |G| = G, cut radius) of one normalised primitive pair."""
+    out = np.zeros(2)
+    lib().orc_pair_cut(int(la), int(lb), float(aa), _d(np.ascontiguousarray(RA, dtype=np.float64)), float(ab),
+                       _d(np.ascontiguousarray(RB, dtype=np.float64)), float(omega), float(eps_G), float(G),
+                       _d(out))
+    return float(out[0]), float(out[1])
 
 
 def ft_axis(i, j, aa, Ax, ab, Bx, G):

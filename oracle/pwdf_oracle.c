@@ -39,6 +39,18 @@
  *                 at fixed D(k), fixed pair list and fixed G set; the centre
  *                 derivative of a Cartesian Gaussian is 2 alpha (l+1 term)
  *                 - l (l-1 term).
+ *   pair cuts     optional (pair_gcut = 1; section "Integral screening"): every
+ *                 block of pairs (shell a, shell b, image m) sees only the G with
+ *                 |G| <= its cut radius, the largest |G| below Gcut where the
+ *                 screening objective 8 pi eta G (4 pi/G^2) e^{-G^2/4w^2}
+ *                 |F|_inf(G), eta = [1/p + 1/w^2]^-1 (eqs. "AFT screening obj",
+ *                 "eta_munu"), of the block's most compact primitive pair still
+ *                 reaches eps_G.  Readings (the text leaves them open): |F|_inf
+ *                 is the largest modulus over the block's Cartesian components
+ *                 with G along x, along y and along z; the radius is found by a
+ *                 scan of 256 steps down from Gcut and 60 bisection steps, and
+ *                 is the upper end of the final bracket.  Without cuts every
+ *                 pair sees the whole G set.
  *
  * Conventions: lattice rows are a1,a2,a3; Cartesian components of a shell in
  * descending lexicographic (lx,ly,lz) order; every component of a primitive
@@ -390,8 +402,119 @@ static void pair_ft_block(int la, int lb, double aa, const double *RA, double ab
 }
 
 /* ------------------------------------------------------------------------- */
+/* per-pair reciprocal-space cut (section "Integral screening")               */
+/* ------------------------------------------------------------------------- */
+
+/* Screening objective of a primitive pair at |G| = G (eq. "AFT screening obj"
+ * with eq. "eta_munu"):
+ *   eps(G) = 8 pi eta G (4 pi / G^2) e^{-G^2/4w^2} |F|_inf(G),
+ *   eta = [1/(a_a + a_b) + 1/w^2]^{-1},
+ * |F|_inf(G): the largest modulus of the pair transform over the Cartesian
+ * components of the shell pair and over G along x, y and z (the paper names the
+ * infinity norm of the exact transform without fixing the directions). */
+static double screen_objective(int la, int lb, double aa, const double *RA, double ab, const double *RB,
+                               double pref, double omega, double G) {
+  zd F[441];
+  double fmax = 0.0;
+  int n = ncart_of(la) * ncart_of(lb);
+  for (int d = 0; d < 3; ++d) {
+    double Gv[3] = {0.0, 0.0, 0.0};
+    Gv[d] = G;
+    pair_ft_block(la, lb, aa, RA, ab, RB, pref, Gv, F, NULL, NULL);
+    for (int e = 0; e < n; ++e)
+      if (cabs(F[e]) > fmax) fmax = cabs(F[e]);
+  }
+  double eta = 1.0 / (1.0 / (aa + ab) + 1.0 / (omega * omega));
+  return 8.0 * ORC_PI * eta * G * (4.0 * ORC_PI / (G * G)) * exp(-G * G / (4.0 * omega * omega)) * fmax;
+}
+
+/* Cut radius of one pair: the objective falls below eps_G for good from here up
+ * to the global cutoff.  From the global cutoff downwards in 256 equal steps to
+ * the first G where the objective is >= eps_G (G -> 0 always is: the objective
+ * grows like 1/G), then 60 bisection steps on that step; the cut is the
+ * bracket's upper end.  The global cutoff itself if the objective is >= eps_G
+ * there. */
+static double pair_cut(int la, int lb, double aa, const double *RA, double ab, const double *RB, double pref,
+                       double omega, double eps_G) {
+  double gglob = 2.0 * omega * sqrt(-log(eps_G));
+  if (screen_objective(la, lb, aa, RA, ab, RB, pref, omega, gglob) >= eps_G) return gglob;
+  double hi = gglob, lo = 0.0;
+  for (int k = 1; k < 256; ++k) {
+    double G = gglob * (1.0 - k / 256.0);
+    if (screen_objective(la, lb, aa, RA, ab, RB, pref, omega, G) >= eps_G) {
+      lo = G;
+      break;
+    }
+    hi = G;
+  }
+  for (int it = 0; it < 60; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid > 0.0 && screen_objective(la, lb, aa, RA, ab, RB, pref, omega, mid) >= eps_G)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return hi;
+}
+
+static int cmp_block(const orc_pair *x, const orc_pair *y) {
+  if (x->sa != y->sa) return x->sa < y->sa ? -1 : 1;
+  if (x->sb != y->sb) return x->sb < y->sb ? -1 : 1;
+  for (int i = 0; i < 3; ++i)
+    if (x->m[i] != y->m[i]) return x->m[i] < y->m[i] ? -1 : 1;
+  return 0;
+}
+
+static const orc_pair *g_sort_pairs;
+static int cmp_pair_index(const void *a, const void *b) {
+  int i = *(const int *)a, j = *(const int *)b;
+  int c = cmp_block(&g_sort_pairs[i], &g_sort_pairs[j]);
+  return c ? c : (i < j ? -1 : i > j);
+}
+
+/* Squared cut radius of every pair: each block (shell a, shell b, image m) takes
+ * the cut of its most compact primitive pair (largest a_a + a_b; the first of
+ * equal ones), which the paper uses for a whole contracted shell pair. */
+static double *pair_cuts2(const orc_sys *s, const orc_pair *pl, int np) {
+  double *gc2 = (double *)malloc(sizeof(double) * (np > 0 ? np : 1));
+  int *idx = (int *)malloc(sizeof(int) * (np > 0 ? np : 1));
+  for (int q = 0; q < np; ++q) idx[q] = q;
+  g_sort_pairs = pl;
+  qsort(idx, np, sizeof(int), cmp_pair_index);
+  for (int g0 = 0; g0 < np;) {
+    int g1 = g0 + 1;
+    while (g1 < np && cmp_block(&pl[idx[g0]], &pl[idx[g1]]) == 0) ++g1;
+    int best = idx[g0];
+    for (int k = g0 + 1; k < g1; ++k) {
+      const orc_pair *P = &pl[idx[k]];
+      if (s->exps[P->ia] + s->exps[P->ib] > s->exps[pl[best].ia] + s->exps[pl[best].ib]) best = idx[k];
+    }
+    const orc_pair *P = &pl[best];
+    int la = s->sh_l[P->sa], lb = s->sh_l[P->sb];
+    const double *RA = s->xyz + 3 * s->sh_atom[P->sa];
+    const double *RB0 = s->xyz + 3 * s->sh_atom[P->sb];
+    double RB[3] = {RB0[0] + P->L[0], RB0[1] + P->L[1], RB0[2] + P->L[2]};
+    double pref = fabs(s->coefs[P->ia] * s->coefs[P->ib]) * norm_of(la, s->exps[P->ia]) * norm_of(lb, s->exps[P->ib]);
+    double c = pair_cut(la, lb, s->exps[P->ia], RA, s->exps[P->ib], RB, pref, s->omega, s->eps_G);
+    for (int k = g0; k < g1; ++k) gc2[idx[k]] = c * c;
+    g0 = g1;
+  }
+  free(idx);
+  return gc2;
+}
+
+/* ------------------------------------------------------------------------- */
 /* exported entry points                                                      */
 /* ------------------------------------------------------------------------- */
+
+/* Screening objective and cut radius of one primitive pair (unit contraction
+ * coefficients) for pins: out[0] = eps(G), out[1] = cut radius. */
+void orc_pair_cut(int la, int lb, double aa, const double *RA, double ab, const double *RB, double omega,
+                  double eps_G, double G, double *out) {
+  double pref = norm_of(la, aa) * norm_of(lb, ab);
+  out[0] = G > 0.0 ? screen_objective(la, lb, aa, RA, ab, RB, pref, omega, G) : HUGE_VAL;
+  out[1] = pair_cut(la, lb, aa, RA, ab, RB, pref, omega, eps_G);
+}
 
 /* Sizes of the lists the oracle builds (diagnostics). */
 int orc_sizes(const double *lattice, int natm, const double *xyz, int nshell, const int *shell_atom,
@@ -484,7 +607,7 @@ int orc_build_j(const double *lattice, int natm, const double *xyz, int nshell,
                 const double *exps, const double *coefs, const int *kmesh, double omega,
                 double eps_pair, double eps_G, double r_max, const double *Dk_, double *Jk_,
                 double *energy, double *rho_out, int *miller, int maxG, int *nG_out,
-                double *grad, int nthreads) {
+                double *grad, int nthreads, int pair_gcut) {
   orc_sys s;
   if (sys_setup(&s, lattice, natm, xyz, nshell, shell_atom, shell_l, shell_nprim, exps, coefs,
                 kmesh, omega, eps_pair, eps_G, r_max))
@@ -507,6 +630,10 @@ int orc_build_j(const double *lattice, int natm, const double *xyz, int nshell,
     sys_free(&s);
     return -2;
   }
+
+  /* per-pair cut (section "Integral screening"): pair q sees only the G of the
+   * set with |G|^2 <= gc2[q]; without it every pair sees the whole set */
+  double *gc2 = pair_gcut ? pair_cuts2(&s, pl, np) : NULL;
 
   /* per-pair block offsets, D(L) blocks and prefactors */
   int64_t *boff = (int64_t *)malloc(sizeof(int64_t) * (np + 1));
@@ -544,6 +671,7 @@ int orc_build_j(const double *lattice, int natm, const double *xyz, int nshell,
       const double *RA = xyz + 3 * shell_atom[P->sa];
       const double *RB0 = xyz + 3 * shell_atom[P->sb];
       double RB[3] = {RB0[0] + P->L[0], RB0[1] + P->L[1], RB0[2] + P->L[2]};
+      if (gc2 && g[ig].G2 > gc2[q]) continue;
       pair_ft_block(la, lb, exps[P->ia], RA, exps[P->ib], RB, pref[q], g[ig].G, F, NULL, NULL);
       int n = ncart_of(la) * ncart_of(lb);
       for (int e = 0; e < n; ++e) acc += DL[boff[q] + e] * F[e];
@@ -586,6 +714,7 @@ int orc_build_j(const double *lattice, int natm, const double *xyz, int nshell,
       for (int e = 0; e < n; ++e) Jc[e] = 0.0;
       double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
       for (int ig = 0; ig < ng; ++ig) {
+        if (gc2 && g[ig].G2 > gc2[q]) continue;
         zd w = v[ig] * rho[mi[ig]];
         pair_ft_block(la, lb, exps[P->ia], RA, exps[P->ib], RB, pref[q], g[ig].G, F,
                       grad ? dA : NULL, grad ? dB : NULL);
@@ -683,6 +812,7 @@ int orc_build_j(const double *lattice, int natm, const double *xyz, int nshell,
         for (int c = 0; c < 3; ++c) miller[3 * ig + c] = g[ig].n[c];
     }
   }
+  free(gc2);
   free(rho);
   free(v);
   free(DL);

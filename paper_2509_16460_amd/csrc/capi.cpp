@@ -168,12 +168,12 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
     if (d.fp32) {
       // per K-step of a wave (16 G points x 4 pairs): the pair factor is evaluated
       // once per group of N-tiles (~120 VALU cycles) and each N-tile of 16 (k, dm)
-      // columns costs two MFMAs of 32 cycles; rho groups up to 8 N-tiles, J 4
+      // columns costs two MFMAs of 32 cycles; both passes use ceil(nt / 8) groups
+      // of equal size (the last one padded)
       const int nt = std::max(1, d.ncols32[L] / 16);
-      const int ntg = nt <= 1 ? 1 : nt <= 2 ? 2 : nt <= 4 ? 4 : 8;
-      jzg[L] = (nt + 3) / 4;
-      costR = ((nt + ntg - 1) / ntg) * 120.0 + 64.0 * nt;
-      costJ = jzg[L] * 120.0 + 64.0 * nt;
+      const int ngr = (nt + 7) / 8, ntg = (nt + ngr - 1) / ngr;
+      jzg[L] = ngr;
+      costR = costJ = ngr * (120.0 + 64.0 * ntg);
     }
     wR[L] = np > 0 ? (double)np * costR : 0.0;
     wJ[L] = np > 0 ? (double)((np + 63) / 64) * 64.0 * costJ : 0.0;
@@ -183,11 +183,14 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
   // rho: a chunk spans the G set in groups of 64 segments (FP64) or 64 points
   // (FP32-MFMA form), four waves each; J: the FP64 form splits the segments
   // into chunks, the FP32-MFMA form the points
-  const int ngi = d.fp32 ? (int)p.pts.size() : p.nseg();
+  const int ngi = d.fp32 ? (int)p.pts.size() - d.npts_head : p.nseg();
   const int rho_waves_per_chunk = std::max(4, ((ngi + 63) / 64) * 4);
   wsumR = std::max(wsumR, 1.0);  // no pairs: every class is skipped below
   wsumJ = std::max(wsumJ, 1.0);
   constexpr double kMinGroupWaves = 1024.0;
+  constexpr double kMinClassWaves = 2048.0;
+  constexpr int kMaxFp32Run = 512;
+  constexpr int kHeadWaves = 1024, kHeadMinPairs = 32;
   double gR[2] = {0.0, 0.0}, gJ[2] = {0.0, 0.0};
   for (int L = 0; L <= kMaxLsum; ++L) {
     gR[L > 2] += wR[L];
@@ -201,12 +204,17 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
     gR[g] = std::max(gR[g], 1.0);
     gJ[g] = std::max(gJ[g], 1.0);
   }
-  int rows = 0;
+  int rows = 0, rows_h = 0;
   int64_t yoff = 0;
   for (int L = 0; L <= kMaxLsum; ++L) {
     int np = p.L_p1[L] - p.L_p0[L];
     d.rho_row0[L] = rows;
+    d.rho_h_row0[L] = rows_h;
     d.yhat_off[L] = yoff;
+    d.rho_h_chunks[L] = 0;
+    d.rho_h_ppc[L] = 1;
+    d.j_chunks32[L] = 0;
+    d.j_spc32[L] = 1;
     if (np <= 0) {
       d.rho_chunks[L] = 0;
       d.rho_ppc[L] = 1;
@@ -214,7 +222,27 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
       d.j_spc[L] = 1;
       continue;
     }
+    // the head (FP64 MFMA): rho in chunks of pairs (one partial row each), about
+    // kHeadWaves waves per class launch and at least one LDS tile of pairs per
+    // chunk; J moments over all head points in one chunk
+    if (d.npts_head > 0) {
+      const int waves_per_chunk = 4 * ((d.npts_head + 63) / 64);
+      const int want = std::max(1, kHeadWaves / waves_per_chunk);
+      int ppc = std::max(kHeadMinPairs, (np + want - 1) / want);
+      d.rho_h_ppc[L] = ppc;
+      d.rho_h_chunks[L] = (np + ppc - 1) / ppc;
+      rows_h += d.rho_h_chunks[L];
+    }
     int ch = (int)std::lround(tR[L > 2] * (wR[L] / gR[L > 2]) * tn.mrho[L] / rho_waves_per_chunk);
+    // FP32-MFMA form: every class launch gets at least kMinClassWaves waves (as
+    // many as chunks of 4 pairs allow), else a small class, whose pairs carry
+    // many N-tiles, runs as a few long waves
+    if (d.fp32) {
+      ch = std::max(ch, (int)std::lround(kMinClassWaves * tn.mrho[L] / rho_waves_per_chunk));
+      // FP32 accumulation runs over at most kMaxFp32Run pairs (one chunk); the
+      // chunks' partial rows are added in FP64
+      ch = std::max(ch, (np + kMaxFp32Run - 1) / kMaxFp32Run);
+    }
     ch = std::max(1, std::min((np + 3) / 4, ch));
     int ppc = (np + ch - 1) / ch;
     ch = (np + ppc - 1) / ppc;
@@ -225,12 +253,25 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
     // block row per N-tile group (FP32-MFMA)
     const int jw = d.fp32 ? 4 * ((np + 63) / 64) * jzg[L] : (np + 63) / 64;
     int jc = (int)std::lround(tJ[L > 2] * (wJ[L] / gJ[L > 2]) * tn.mj[L] / jw);
+    if (d.fp32) {
+      jc = std::min(std::max(jc, (int)std::lround(kMinClassWaves * tn.mj[L] / jw)), (ngi + 15) / 16);
+      jc = std::max(jc, (ngi + kMaxFp32Run - 1) / kMaxFp32Run);  // FP32 runs over <= kMaxFp32Run points
+    }
     jc = std::max(1, std::min(ngi, jc));
     int spc = std::max(1, (ngi + jc - 1) / jc);
     jc = (ngi + spc - 1) / spc;  // 0 when the G set is empty
     d.j_chunks[L] = jc;
     d.j_spc[L] = spc;
-    yoff += (int64_t)jc * nherm(L) * np;
+    if (d.fp32) {
+      // the FP32 chunks, then the head's chunk; the FP64 force moments of the
+      // gradient walk all segments in as many chunks
+      d.j_chunks32[L] = jc;
+      d.j_spc32[L] = spc;
+      const int jt = jc + (d.npts_head > 0 ? 1 : 0);
+      d.j_chunks[L] = jt;
+      d.j_spc[L] = std::max(1, (p.nseg() + std::max(1, jt) - 1) / std::max(1, jt));
+    }
+    yoff += (int64_t)d.j_chunks[L] * nherm(L) * np;
   }
   // force moments of degree L+1 over the class-L pairs, same segment chunks as J
   int64_t foff = 0;
@@ -241,9 +282,13 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
   }
   d.yF_size = std::max<int64_t>(1, foff);
   d.nrows = std::max(1, rows);
-  d.ngroups = std::min(d.nrows, 64);
+  d.nrows_h = std::max(1, rows_h);
+  // first reduction stage: up to 64 groups of rows, of the FP32 rows and (head
+  // slots) of the head rows
+  d.ngroups = std::min(std::max(d.nrows, d.npts_head > 0 ? d.nrows_h : 0), 64);
   d.rows_per_group = (d.nrows + d.ngroups - 1) / d.ngroups;
-  d.ngroups = (d.nrows + d.rows_per_group - 1) / d.rows_per_group;
+  if (d.npts_head == 0) d.ngroups = (d.nrows + d.rows_per_group - 1) / d.rows_per_group;
+  d.rows_per_group_h = (d.nrows_h + d.ngroups - 1) / d.ngroups;
   d.yhat_size = std::max<int64_t>(1, yoff);
   d.nred_blocks = (p.nslot() + 3) / 4;
 }
@@ -284,7 +329,10 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   d.nheavyJ = (int)p.heavyJ.size();
   d.nlightJ = (int)p.lightJ.size();
   d.jk_layout = c->jk_layout;
+  d.pair_gcut = in.pair_gcut;
+  d.muu = p.M[p.ax[0]][p.ax[0]];
   d.fp32 = c->prec == PWDF_FP32_MFMA ? 1 : 0;
+  d.npts_head = d.fp32 ? p.npts_head : 0;
   if (d.fp32) {
     d.ndmp = 1;
     while (d.ndmp < c->max_ndm) d.ndmp *= 2;
@@ -313,6 +361,8 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   UP(p.hot, hot)
   UP(p.hot_rho, hot_rho)
   UP(p.rho_rank, rho_rank)
+  UP(p.hot_cut, hot_cut)
+  UP(p.cut_rank, cut_rank)
   UP(p.aux, aux)
   UP(p.blocks, blocks)
   UP(p.elem_blk, elem_blk)
@@ -333,6 +383,11 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   UP(p.sD_e0, sD_e0)
   UP(p.eD, eD)
   UP(p.ttab, ttab)
+  if (d.npts_head > 0) {
+    std::vector<int> hidx(p.nslot(), -1);
+    for (int i = 0; i < d.npts_head; ++i) hidx[p.pts[i].slot] = i;
+    UP(hidx, slot_hidx)
+  }
   {
     std::vector<double> st(kStartTab);
     start_tables(st.data());
@@ -354,7 +409,8 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   if ((e = alloc(c, (count), &d.field)) != hipSuccess) return fail(c, PWDF_ENOMEM, "device allocation failed: " #field);
   AL(Dblk, M * p.nelem)
   AL(Jblk, M * p.nelem)
-  AL(dhat, M * d.dhat_size)
+  // the FP32-MFMA form keeps the coefficients in the MFMA layout (d32_size per call)
+  AL(dhat, d.fp32 ? (size_t)std::max<int64_t>(1, d.d32_size) : M * d.dhat_size)
   AL(yhat, M * d.yhat_size)
   AL(part, M * d.nrows * d.nslot)
   AL(part2, M * d.ngroups * d.nslot)
@@ -365,6 +421,7 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   AL(yF, M * d.yF_size)
   d.nblocks = (int)p.blocks.size();
   AL(gblk, M * (size_t)d.nblocks * 6)
+  if (d.npts_head > 0) AL(parth, M * d.nrows_h * d.npts_head)
   if (d.fp32) {
     AL(dh32, (size_t)std::max<int64_t>(1, d.d32_size))
     AL(wre, (size_t)d.nslot * d.ncolsW)
@@ -468,7 +525,7 @@ int np_L(const Plan &p, int L) { return p.L_p1[L] - p.L_p0[L]; }
 // per (unique pair, G of the half space, density) in the factored form.
 double pass_flops(const Plan &p, int L0, int L1, int ndm) {
   double f = 0.0;
-  for (int L = L0; L <= L1; ++L) f += (double)np_L(p, L) * (double)(p.nG_full / 2) * (8.0 * (L + 1) + 4.0);
+  for (int L = L0; L <= L1; ++L) f += p.pairG_L[L] * (8.0 * (L + 1) + 4.0);
   return f * ndm;
 }
 
@@ -495,7 +552,16 @@ pwdf_status run_mid_rho(pwdf_ctx *c, int ndm, double *EJ, hipStream_t st) {
       if (np_L(p, L) <= 0) continue;
       std::snprintf(name, sizeof name, "rho_mfma_L%d", L);
       hipStream_t ss = f.stream();
-      if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, ss, [&] { return launch_rho_mfma_L(d, L, ndm, ss); })) !=
+      if ((s = step(c, name, (p.pairG_L[L] - p.pairG_head_L[L]) * ndm, ss,
+                    [&] { return launch_rho_mfma_L(d, L, ndm, ss); })) !=
+          PWDF_OK)
+        return s;
+    }
+    for (int L = 0; L <= 2 * kMaxL && d.npts_head > 0; ++L) {
+      if (np_L(p, L) <= 0) continue;
+      std::snprintf(name, sizeof name, "rho_head_L%d", L);
+      hipStream_t ss = f.stream();
+      if ((s = step(c, name, p.pairG_head_L[L] * ndm, ss, [&] { return launch_rho_head_L(d, L, ndm, ss); })) !=
           PWDF_OK)
         return s;
     }
@@ -538,8 +604,17 @@ pwdf_status run_moments(pwdf_ctx *c, int ndm, bool force, hipStream_t st) {
       if (np_L(p, L) <= 0) continue;
       std::snprintf(name, sizeof name, "jpass_mfma_L%d", L);
       hipStream_t ss = f.stream();
-      if ((s = step(c, name, (double)np_L(p, L) * nGh * ndm, ss,
-                    [&] { return launch_jpass_mfma_L(d, L, ndm, ss); })) != PWDF_OK)
+      if ((s = step(c, name, (p.pairG_L[L] - p.pairG_head_L[L]) * ndm, ss,
+                    [&] { return launch_jpass_mfma_L(d, L, ndm, ss); })) !=
+          PWDF_OK)
+        return s;
+    }
+    for (int L = 0; L <= 2 * kMaxL && d.npts_head > 0; ++L) {
+      if (np_L(p, L) <= 0) continue;
+      std::snprintf(name, sizeof name, "jpass_head_L%d", L);
+      hipStream_t ss = f.stream();
+      if ((s = step(c, name, p.pairG_head_L[L] * ndm, ss, [&] { return launch_jpass_head_L(d, L, ndm, ss); })) !=
+          PWDF_OK)
         return s;
     }
   } else {
@@ -623,6 +698,7 @@ static pwdf_status make_input(PlanInput &in, const double lattice[9], int natm, 
   in.eps_pair = screen->eps_pair;
   in.eps_G = screen->eps_G;
   in.r_max = screen->r_max;
+  in.pair_gcut = screen->pair_gcut != 0 ? 1 : 0;
   return PWDF_OK;
 }
 
@@ -639,12 +715,16 @@ static void fill_stats(const Plan &p, pwdf_stats *out) {
   out->nimg = p.nimg();
   out->nblocks = (int64_t)p.blocks.size();
   out->nseg = p.nseg();
-  out->pairG_evals = 2.0 * (double)p.npairs() * (double)(p.nG_full / 2);
+  // per build and density: both passes over the G each pair sees (its cut
+  // sphere, or the whole half space)
+  out->pairG_evals = 2.0 * p.pairG_cut;
   out->seg_len = p.seg_len;
   out->fork = 1;
   out->jk_support = (int64_t)(p.lightJ.size() + p.heavyJ.size());
   out->dk_support = p.nD_support;
   out->jk_layout = PWDF_JK_FULL;
+  out->nG_head = p.npts_head;
+  out->pairG_head = 2.0 * p.pairG_head;
 }
 
 pwdf_status pwdf_plan_stats(const double lattice[9], int natm, const double *xyz, int nshell, const int *shell_atom,
@@ -854,7 +934,7 @@ static size_t carve_build_ws(Dev &d, const Plan &p, int ndm, unsigned char *base
   const size_t M = (size_t)ndm;
   take(d.Dblk, M * p.nelem);
   take(d.Jblk, M * p.nelem);
-  take(d.dhat, M * d.dhat_size);
+  take(d.dhat, d.fp32 ? (size_t)std::max<int64_t>(1, d.d32_size) : M * d.dhat_size);
   take(d.yhat, M * d.yhat_size);
   take(d.part, M * d.nrows * d.nslot);
   take(d.part2, M * d.ngroups * d.nslot);
@@ -862,6 +942,7 @@ static size_t carve_build_ws(Dev &d, const Plan &p, int ndm, unsigned char *base
   take(d.Vc, M * d.nslot);
   take(d.Epart, M * d.nred_blocks);
   take(d.Jfold, M * (size_t)std::max(1, d.nsegJ));
+  if (d.npts_head > 0) take(d.parth, M * d.nrows_h * d.npts_head);
   if (d.fp32) {
     take(d.dh32, (size_t)std::max<int64_t>(1, d.d32_size));
     take(d.wre, (size_t)d.nslot * d.ncolsW);

@@ -21,6 +21,8 @@ struct Dev {
   const PairHot *hot;
   const PairHot *hot_rho;        // pair records in the rho pass's order (sorted by p for L <= 2)
   const int *rho_rank;           // pair -> position in that order (where its coefficients go)
+  const PairHot *hot_cut;        // pair records by cut radius per class (J pass, FP32-MFMA rho pass)
+  const int *cut_rank;           // pair -> position in that order (J moments, FP32-MFMA coefficient rows)
   const PairAux *aux;
   const BlockRec *blocks;
   const int *elem_blk;
@@ -39,6 +41,8 @@ struct Dev {
   const int *lightJ;             // the other support elements (1 .. kPhaseLight classes), ascending
   int nlightJ;
   int jk_layout;                 // pwdf_jk_layout: 0 every element, 1 the support in place, 2 packed
+  int pair_gcut;                 // 1: pairs carry their own cut radius (PairHot::gc2)
+  double muu;                    // M_uu = |b_u|^2: |G|^2 along a line grows by steps of 2 M_uu
   int *nonfinite;                // set to 1 by phase_d when a D(L) phase sum is not finite
   double *Jfold;                 // [ndm][nsegJ]
   const double2 *ptab;           // e^{2 pi i t / N}
@@ -69,6 +73,16 @@ struct Dev {
   int ncols32[kMaxLsum + 1];
   float *wre, *wim;
   int ncolsW;
+  // the head of the G set (pts[0, npts_head)), FP64 tiles on FP64 MFMA: rho
+  // partial rows [ndm][nrows_h][npts_head] (chunks of pairs per class), the J
+  // moments in chunk j_chunks32[L] of yhat after the FP32 chunks; slot_hidx maps
+  // a slot to its head point (-1 for the others) for the reduction
+  int npts_head;
+  const int *slot_hidx;
+  double2 *parth;
+  int nrows_h, rows_per_group_h;
+  int rho_h_chunks[kMaxLsum + 1], rho_h_ppc[kMaxLsum + 1], rho_h_row0[kMaxLsum + 1];
+  int j_chunks32[kMaxLsum + 1], j_spc32[kMaxLsum + 1];  // FP32 J pass over the other points
   // gradient: moments of degree L+1 per class, per-block centre gradients,
   // per-atom lists of (block, 0 = shell a / 3 = shell b)
   double *yF;
@@ -100,6 +114,9 @@ hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
 hipError_t launch_rho_mfma_L(const Dev &d, int L, int ndm, hipStream_t st);
 hipError_t launch_wprep(const Dev &d, int ndm, hipStream_t st);
 hipError_t launch_jpass_mfma_L(const Dev &d, int L, int ndm, hipStream_t st);
+// the head of the FP32-MFMA form (FP64 MFMA, per class L)
+hipError_t launch_rho_head_L(const Dev &d, int L, int ndm, hipStream_t st);
+hipError_t launch_jpass_head_L(const Dev &d, int L, int ndm, hipStream_t st);
 // FP64 path: one launch per pass over all classes
 hipError_t launch_phase_d(const Dev &d, const double *Dk, int ndm, hipStream_t st);
 hipError_t launch_transform_all(const Dev &d, int ndm, hipStream_t st);

@@ -33,6 +33,7 @@
 
 #include "kernel_common.h"
 #include "kernels.h"
+#include "mfma_common.h"
 
 namespace pwdf {
 
@@ -41,22 +42,6 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
-
-__device__ __forceinline__ double ipow(double x, int e) {
-  double r = 1.0;
-  for (int i = 0; i < e; ++i) r *= x;
-  return r;
-}
-
-constexpr double kLog2e = 1.4426950408889634;
-
-// Pair data of the direct evaluation: log2(e)/4p and the fractional coordinates
-// of P in the (u, v, w) axis order.
-struct PairF {
-  double il2, fu, fv, fw;
-};
-
-__device__ __forceinline__ PairF pair_f(const PairHot &h) { return {h.inv4p * kLog2e, h.fu, h.fv, h.fw}; }
 
 // S = e^{-|G|^2/4p} e^{-2 pi i n.f} in FP32 from FP64-reduced arguments.
 // |G|^2/4p is at most ~650 (checked by the plan), so y >= -940: the integer part
@@ -89,9 +74,8 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const GPoint *__restrict__ pts
                                                   const PairHot *__restrict__ hot, int Lp0, int Lp1, int ppc,
                                                   const float *__restrict__ dh32, int64_t d32_off, int ncols,
                                                   int ndmp, int ndm, double2 *__restrict__ part, int row0,
-                                                  int nrows, int nslot) {
+                                                  int nrows, int nslot, int cut) {
   constexpr int NT = nherm(L);
-  constexpr Monos<L> MT{};
   __shared__ PairF sh[kQTile];
   __shared__ float sc[kQTile * NTG * 16];
   const int tid = threadIdx.x;
@@ -103,6 +87,12 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const GPoint *__restrict__ pts
   const GPoint ptA = pts[min(pt0 + r16, npts - 1)];
   const float *dcls = dh32 + d32_off;
   const int ntiles = ncols >> 4;
+  // per-pair cuts: smallest |G|^2 of the wave's 16 rows; a group of four pairs
+  // whose cuts all lie below it is skipped (wave-uniform)
+  double rmin = pt0 + r16 < npts ? ptA.g2 : 1e300;
+  const double blk_g2min = pts[blockIdx.x * 64].g2;
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) rmin = fmin(rmin, __shfl_xor(rmin, off, 64));
 
   // lanes r16 < ndm write density r16 of the wave's rows; each N-tile group adds
   // its epilogue into the chunk's partial row (same lane, same addresses: no race)
@@ -119,6 +109,15 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const GPoint *__restrict__ pts
       const int nq = min(kQTile, p1 - t0);
       __syncthreads();
       for (int i = tid; i < nq; i += 256) sh[i] = pair_f(hot[t0 + i]);
+      if (cut) {
+        // a tile whose largest cut lies below the block's shortest G (the points
+        // come in order of |G|^2) adds nothing: skipped with its staging
+        __syncthreads();
+        double tmax = lane < nq ? sh[lane].gc2 : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off, 64));
+        if (tmax < blk_g2min) continue;
+      }
       // coefficient columns [ng*16, (ng+ntg)*16) of the tile's pairs
       // four elements per thread and step, their loads issued before the stores
       for (int i0 = tid; i0 < nq * NTG * 16; i0 += 4 * 256) {
@@ -134,18 +133,29 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const GPoint *__restrict__ pts
           if (i0 + u * 256 < nq * NTG * 16) sc[i0 + u * 256] = v[u];
       }
       __syncthreads();
+      // branch-free: a lane past the tile's pairs evaluates a valid pair and
+      // contributes zero; the columns past the group's tiles are zeros in LDS, so
+      // every group runs NTG tiles (a run-time tile count would make the compiler
+      // move the accumulators out of the MFMA registers around every MFMA)
       for (int q0 = 0; q0 < nq; q0 += 4) {
-        const bool vq = q0 + g4 < nq;
-        const int q = vq ? q0 + g4 : nq - 1;
-        float Sr = 0.f, Si = 0.f;
-        if (vq) s_direct(ptA, sh[q], Sr, Si);
+        if (cut) {
+          double kmax = sh[q0].gc2;
+#pragma unroll
+          for (int i = 1; i < 4; ++i) kmax = fmax(kmax, sh[min(q0 + i, nq - 1)].gc2);
+          if (kmax < rmin) continue;
+        }
+        const int q = q0 + g4 < nq ? q0 + g4 : nq - 1;
+        const bool vq = q0 + g4 < nq && ptA.g2 <= sh[q].gc2;
+        float Sr, Si;
+        s_direct(ptA, sh[q], Sr, Si);
+        Sr = vq ? Sr : 0.f;
+        Si = vq ? Si : 0.f;
+        const float *bq = sc + q * (NTG * 16) + r16;
 #pragma unroll
         for (int n = 0; n < NTG; ++n) {
-          if (n < ntg) {
-            const float b = vq ? sc[q * (NTG * 16) + n * 16 + r16] : 0.f;
-            are[n] = mfma4(Sr, b, are[n]);
-            aim[n] = mfma4(Si, b, aim[n]);
-          }
+          const float b = bq[n * 16];
+          are[n] = mfma4(Sr, b, are[n]);
+          aim[n] = mfma4(Si, b, aim[n]);
         }
       }
     }
@@ -162,7 +172,8 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const GPoint *__restrict__ pts
       const int c = (ng + n) * 16 + r16;
       const int k = c / ndmp;
       const bool vk = k < NT;
-      const int ka = vk ? MT.u[k] : 0, kb = vk ? MT.v[k] : 0, kc = vk ? MT.w[k] : 0;
+      int ka = 0, kb = 0, kc = 0;
+      if (vk) mono_of(k, ka, kb, kc);
       const bool odd = (ka + kb + kc) & 1;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -213,7 +224,6 @@ __global__ __launch_bounds__(256) void k_wprep(const double2 *__restrict__ Vc, i
                                                const GPoint *__restrict__ pts, int ncolsW, int ndmp, int ndm,
                                                float *__restrict__ wre, float *__restrict__ wim) {
   constexpr int NT = nherm(LMAX);
-  constexpr Monos<LMAX> MT{};
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   const int pi = blockIdx.y;
   if (col >= ncolsW) return;
@@ -221,7 +231,8 @@ __global__ __launch_bounds__(256) void k_wprep(const double2 *__restrict__ Vc, i
   float xr = 0.f, xi = 0.f;
   if (k < NT && dm < ndm) {
     const GPoint pt = pts[pi];
-    const int a = MT.u[k], b = MT.v[k], c = MT.w[k];
+    int a, b, c;
+    mono_of(k, a, b, c);
     const double mono = ipow((double)pt.nu, a) * ipow((double)pt.nv, b) * ipow((double)pt.nw, c);
     const double2 v = Vc[(size_t)dm * nslot + pt.slot];
     double r = mono * v.x, i = mono * v.y;
@@ -244,15 +255,21 @@ __global__ __launch_bounds__(256) void k_wprep(const double2 *__restrict__ Vc, i
 // with it.  The points of a chunk are staged in LDS tile by tile.  yhat per
 // (G chunk, k, pair) in FP64.
 // ---------------------------------------------------------------------------
-constexpr int kPTile = 64;  // points per LDS tile of the J pass
+// points per LDS tile of the J pass (the W' tile is 2 x kPTile x 16 NTW floats)
+template <int NTW>
+constexpr int j_ptile() {
+  return NTW <= 4 ? 64 : 32;
+}
 
 template <int L, int NTW>
 __global__ __launch_bounds__(256) void k_jpass_mfma(const GPoint *__restrict__ pts, int npts, int ppc,
                                                     const float *__restrict__ wre, const float *__restrict__ wim,
                                                     int ncolsW, int ntiles, int ndmp, int ndm,
                                                     const PairHot *__restrict__ hot, int Lp0, int Lp1,
-                                                    double *__restrict__ yhat, int64_t yhat_size, int64_t ycls_off) {
+                                                    double *__restrict__ yhat, int64_t yhat_size, int64_t ycls_off,
+                                                    int cut) {
   constexpr int NT = nherm(L);
+  constexpr int kPTile = j_ptile<NTW>();
   __shared__ GPoint sp[kPTile];
   __shared__ float sw[2][kPTile][NTW * 16];
   const int tid = threadIdx.x;
@@ -266,11 +283,23 @@ __global__ __launch_bounds__(256) void k_jpass_mfma(const GPoint *__restrict__ p
   const int s0 = min(npts, chunk * ppc), s1 = min(npts, s0 + ppc);
   const int pa = prow0 + r16;
   const PairF f = pair_f(hot[Lp0 + (pa < np ? pa : 0)]);
+  // per-pair cuts: largest cut of the wave's 16 rows; a group of four points all
+  // beyond it is skipped (wave-uniform)
+  double cmax = pa < np ? f.gc2 : 0.0;
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off, 64));
+  // largest cut of the block's 64 pairs: the points come in order of |G|^2, so
+  // the chunk ends for the block at its first tile beyond it
+  __shared__ double scm[4];
+  if (lane == 0) scm[w] = cmax;
+  __syncthreads();
+  const double cmax_blk = fmax(fmax(scm[0], scm[1]), fmax(scm[2], scm[3]));
   f4 acc[NTW];
 #pragma unroll
   for (int n = 0; n < NTW; ++n) acc[n] = f4{0.f, 0.f, 0.f, 0.f};
   for (int t0 = s0; t0 < s1; t0 += kPTile) {
     const int nt = min(kPTile, s1 - t0);
+    if (cut && pts[t0].g2 > cmax_blk) break;
     __syncthreads();
     if (tid < nt) sp[tid] = pts[t0 + tid];
     // W' columns [nt0*16, (nt0+ntw)*16) of the tile's points, real and imaginary
@@ -282,18 +311,25 @@ __global__ __launch_bounds__(256) void k_jpass_mfma(const GPoint *__restrict__ p
       sw[1][q][c] = ok ? wim[g] : 0.f;
     }
     __syncthreads();
+    // branch-free as in the rho pass: columns past the group's tiles are zeros
     for (int q0 = 0; q0 < nt; q0 += 4) {
-      const bool vq = q0 + g4 < nt;
-      const int q = vq ? q0 + g4 : nt - 1;
-      float Sr = 0.f, Si = 0.f;
-      if (vq) s_direct(sp[q], f, Sr, Si);
-      const float nSi = -Si;
+      if (cut) {
+        double pmin = sp[q0].g2;
+#pragma unroll
+        for (int i = 1; i < 4; ++i) pmin = fmin(pmin, sp[min(q0 + i, nt - 1)].g2);
+        if (pmin > cmax) continue;
+      }
+      const int q = q0 + g4 < nt ? q0 + g4 : nt - 1;
+      const bool vq = q0 + g4 < nt && sp[q].g2 <= f.gc2;
+      float Sr, Si;
+      s_direct(sp[q], f, Sr, Si);
+      Sr = vq ? Sr : 0.f;
+      const float nSi = vq ? -Si : 0.f;
+      const float *wr = &sw[0][q][r16], *wi = &sw[1][q][r16];
 #pragma unroll
       for (int n = 0; n < NTW; ++n) {
-        if (n < ntw) {
-          acc[n] = mfma4(Sr, vq ? sw[0][q][n * 16 + r16] : 0.f, acc[n]);
-          acc[n] = mfma4(nSi, vq ? sw[1][q][n * 16 + r16] : 0.f, acc[n]);
-        }
+        acc[n] = mfma4(Sr, wr[n * 16], acc[n]);
+        acc[n] = mfma4(nSi, wi[n * 16], acc[n]);
       }
     }
   }
@@ -323,24 +359,31 @@ __global__ __launch_bounds__(256) void k_jpass_mfma(const GPoint *__restrict__ p
 
 template <int L, int NTG>
 static hipError_t rho_mfma_ntg(const Dev &d, int ndm, hipStream_t st) {
-  dim3 grid((unsigned)((d.npts + 63) / 64), d.rho_chunks[L]);
-  hipLaunchKernelGGL((k_rho_mfma<L, NTG>), grid, dim3(256), 0, st, d.pts, d.npts, d.hot, d.L_p0[L], d.L_p1[L],
+  const int ntail = d.npts - d.npts_head;
+  dim3 grid((unsigned)((ntail + 63) / 64), d.rho_chunks[L]);
+  hipLaunchKernelGGL((k_rho_mfma<L, NTG>), grid, dim3(256), 0, st, d.pts + d.npts_head, ntail, d.hot_cut, d.L_p0[L],
+                     d.L_p1[L],
                      d.rho_ppc[L], d.dh32, d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.part, d.rho_row0[L],
-                     d.nrows, d.nslot);
+                     d.nrows, d.nslot, d.pair_gcut);
   PWDF_CHECK_LAUNCH32();
   return hipSuccess;
 }
 
-// N-tiles per S generation: all of them up to 8 (accumulators 2 x 8 x 4 VGPRs)
 template <int L>
 static hipError_t rho_mfma_one(const Dev &d, int ndm, hipStream_t st) {
   const int np = d.L_p1[L] - d.L_p0[L];
-  if (np <= 0 || d.npts <= 0) return hipSuccess;
-  const int ntiles = d.ncols32[L] / 16;
-  if (ntiles <= 1) return rho_mfma_ntg<L, 1>(d, ndm, st);
-  if (ntiles <= 2) return rho_mfma_ntg<L, 2>(d, ndm, st);
-  if (ntiles <= 4) return rho_mfma_ntg<L, 4>(d, ndm, st);
-  return rho_mfma_ntg<L, 8>(d, ndm, st);
+  if (np <= 0 || d.npts - d.npts_head <= 0) return hipSuccess;
+  switch (group_tiles(d.ncols32[L] / 16)) {
+    case 1: return rho_mfma_ntg<L, 1>(d, ndm, st);
+    case 2: return rho_mfma_ntg<L, 2>(d, ndm, st);
+    case 3: return rho_mfma_ntg<L, 3>(d, ndm, st);
+    case 4: return rho_mfma_ntg<L, 4>(d, ndm, st);
+    case 5: return rho_mfma_ntg<L, 5>(d, ndm, st);
+    case 6: return rho_mfma_ntg<L, 6>(d, ndm, st);
+    case 7: return rho_mfma_ntg<L, 7>(d, ndm, st);
+    case 8: return rho_mfma_ntg<L, 8>(d, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_rho_mfma_L(const Dev &d, int L, int ndm, hipStream_t st) {
@@ -357,26 +400,44 @@ hipError_t launch_rho_mfma_L(const Dev &d, int L, int ndm, hipStream_t st) {
 }
 
 hipError_t launch_wprep(const Dev &d, int ndm, hipStream_t st) {
-  if (d.npts <= 0) return hipSuccess;
-  dim3 grid((unsigned)((d.ncolsW + 255) / 256), d.npts);
-  hipLaunchKernelGGL((k_wprep<2 * kMaxL>), grid, dim3(256), 0, st, d.Vc, d.nslot, d.pts, d.ncolsW, d.ndmp, ndm,
-                     d.wre, d.wim);
+  const int ntail = d.npts - d.npts_head;
+  if (ntail <= 0) return hipSuccess;
+  dim3 grid((unsigned)((d.ncolsW + 255) / 256), ntail);
+  hipLaunchKernelGGL((k_wprep<2 * kMaxL>), grid, dim3(256), 0, st, d.Vc, d.nslot, d.pts + d.npts_head, d.ncolsW,
+                     d.ndmp, ndm, d.wre, d.wim);
   PWDF_CHECK_LAUNCH32();
   return hipSuccess;
 }
 
+template <int L, int NTW>
+static hipError_t j_mfma_ntw(const Dev &d, int ndm, hipStream_t st) {
+  const int np = d.L_p1[L] - d.L_p0[L];
+  const int ntiles = d.ncols32[L] / 16;
+  dim3 grid((unsigned)((np + 63) / 64), d.j_chunks32[L], (unsigned)((ntiles + NTW - 1) / NTW));
+  hipLaunchKernelGGL((k_jpass_mfma<L, NTW>), grid, dim3(256), 0, st, d.pts + d.npts_head, d.npts - d.npts_head,
+                     d.j_spc32[L], d.wre, d.wim,
+                     d.ncolsW, ntiles, d.ndmp, ndm, d.hot_cut, d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size,
+                     d.yhat_off[L], d.pair_gcut);
+  PWDF_CHECK_LAUNCH32();
+  return hipSuccess;
+}
+
+// N-tile groups (grid z) as for rho: ceil(ntiles / 8) groups of equal size
 template <int L>
 static hipError_t j_mfma_one(const Dev &d, int ndm, hipStream_t st) {
   const int np = d.L_p1[L] - d.L_p0[L];
-  if (np <= 0 || d.npts <= 0) return hipSuccess;
-  constexpr int NTW = 4;
-  const int ntiles = d.ncols32[L] / 16;
-  dim3 grid((unsigned)((np + 63) / 64), d.j_chunks[L], (unsigned)((ntiles + NTW - 1) / NTW));
-  hipLaunchKernelGGL((k_jpass_mfma<L, NTW>), grid, dim3(256), 0, st, d.pts, d.npts, d.j_spc[L], d.wre, d.wim,
-                     d.ncolsW, ntiles, d.ndmp, ndm, d.hot, d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size,
-                     d.yhat_off[L]);
-  PWDF_CHECK_LAUNCH32();
-  return hipSuccess;
+  if (np <= 0 || d.npts - d.npts_head <= 0 || d.j_chunks32[L] <= 0) return hipSuccess;
+  switch (group_tiles(d.ncols32[L] / 16)) {
+    case 1: return j_mfma_ntw<L, 1>(d, ndm, st);
+    case 2: return j_mfma_ntw<L, 2>(d, ndm, st);
+    case 3: return j_mfma_ntw<L, 3>(d, ndm, st);
+    case 4: return j_mfma_ntw<L, 4>(d, ndm, st);
+    case 5: return j_mfma_ntw<L, 5>(d, ndm, st);
+    case 6: return j_mfma_ntw<L, 6>(d, ndm, st);
+    case 7: return j_mfma_ntw<L, 7>(d, ndm, st);
+    case 8: return j_mfma_ntw<L, 8>(d, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_jpass_mfma_L(const Dev &d, int L, int ndm, hipStream_t st) {

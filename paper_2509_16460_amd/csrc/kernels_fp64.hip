@@ -185,9 +185,15 @@ __device__ __forceinline__ void transform_thread(const Dev &dv, int bi, int dm) 
         double s = 0.0;
 #pragma unroll
         for (int t = 0; t < nc; ++t) s = fma(T[t * nc + k], Dt[deg_off(d) + t], s);
-        out[deg_off(d) + k] = sg * s;
-        // FP32 operand of the MFMA form: [pair][k * ndmp + dm]
-        if (dh32) dh32[d32_off + (size_t)(q - Lp0) * ncols + (deg_off(d) + k) * ndmp + dm] = (float)(sg * s);
+        // FP32-MFMA form: [pair][k * ndmp + dm], in FP32 for the tiles of the G
+        // set's tail and in FP64 (dhat in that layout) for the tiles of its head
+        if (dh32) {
+          const size_t o = d32_off + (size_t)(dv.cut_rank[q] - Lp0) * ncols + (deg_off(d) + k) * ndmp + dm;
+          dh32[o] = (float)(sg * s);
+          dhat[o] = sg * s;
+        } else {
+          out[deg_off(d) + k] = sg * s;
+        }
       }
     }
   }
@@ -213,11 +219,14 @@ struct RhoTile {
 // of NDB densities) to the SEG points of one segment.  The Gaussian/phase factor
 // S is generated once and shared by the densities; each density keeps its own
 // accumulators, filled in the same pair order as a one-density call.
-template <int L, int SEG, int NDB>
+// CUT: the pair sees only the points with |G|^2 <= its gc2 (record field 7);
+// g2s holds |G|^2 of the lane's SEG points.
+template <int L, int SEG, int NDB, bool CUT>
 __device__ __forceinline__ void rho_pair(const double *__restrict__ r, const SegDesc &sd, const double (&mv)[L + 1],
                                          const double (&mw)[L + 1], double (&accr)[NDB][SEG],
                                          double (&acci)[NDB][SEG], const double *__restrict__ e2,
-                                         const double2 *__restrict__ cis, double &pc, double &e0, double &eR) {
+                                         const double2 *__restrict__ cis, double &pc, double &e0, double &eR,
+                                         const double (&g2s)[SEG]) {
   constexpr int NT = nherm(L);
   constexpr Monos<L> MT{};
   const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
@@ -250,15 +259,18 @@ __device__ __forceinline__ void rho_pair(const double *__restrict__ r, const Seg
   double ph = fma(nu0, fu, fma(nv, fv, nw * fw));
   ph -= rint(ph);
   const double2 w = cis_neg(ph, cis);
-  double Sr = e0 * w.x, Si = e0 * w.y;
+  double Sr_ = e0 * w.x, Si_ = e0 * w.y;
   double Rr = eR * r[4], Ri = eR * r[5];
   const double q = r[6];
   // the degree-L coefficient exists only in the part of parity L (real for even
   // L, imaginary for odd L): the Horner sums start below it in the other part
   constexpr int topR = (L & 1) ? L - 1 : L, topI = (L & 1) ? L : L - 1;
+  const double gc2 = r[7];
 #pragma unroll
   for (int s = 0; s < SEG; ++s) {
     const double n = nu0 + s;
+    // the point's share: S, or 0 outside the pair's cut
+    const double Sr = CUT && g2s[s] > gc2 ? 0.0 : Sr_, Si = CUT && g2s[s] > gc2 ? 0.0 : Si_;
 #pragma unroll
     for (int b = 0; b < NDB; ++b) {
       double Pr = cr[b][topR];
@@ -275,15 +287,15 @@ __device__ __forceinline__ void rho_pair(const double *__restrict__ r, const Seg
         acci[b][s] = fma(Sr, Pi, fma(Si, Pr, acci[b][s]));
       }
     }
-    const double tr = fma(Sr, Rr, -Si * Ri);
-    Si = fma(Sr, Ri, Si * Rr);
-    Sr = tr;
+    const double tr = fma(Sr_, Rr, -Si_ * Ri);
+    Si_ = fma(Sr_, Ri, Si_ * Rr);
+    Sr_ = tr;
     Rr *= q;
     Ri *= q;
   }
 }
 
-template <int L, int SEG, int W, int NDB>
+template <int L, int SEG, int W, int NDB, bool CUT>
 __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int db, int ndm, double *__restrict__ sp,
                                           double2 *__restrict__ red, const double *__restrict__ e2,
                                           const double2 *__restrict__ cis) {
@@ -318,6 +330,22 @@ __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int
     for (int s = 0; s < SEG; ++s) accr[b][s] = acci[b][s] = 0.0;
   const int dm0 = db * NDB;
   double pc = -1.0, e0 = 0.0, eR = 0.0;  // p-dependent start factors of the last pair (inv4p > 0)
+  // per-pair cuts: |G|^2 of the lane's points, and the smallest |G|^2 of the
+  // block's 64 segments (a pair whose cut lies below it is skipped by every wave)
+  double g2s[SEG];
+  double wmin = 1e300;
+  if constexpr (CUT) {
+    double g2 = sd.gq0, dg = sd.dg0;
+#pragma unroll
+    for (int s = 0; s < SEG; ++s) {
+      g2s[s] = g2;
+      g2 += dg;
+      dg += 2.0 * dv.muu;
+    }
+    wmin = active ? sd.g2min : 1e300;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) wmin = fmin(wmin, __shfl_xor(wmin, off, 64));
+  }
   for (int t0 = p0; t0 < p1; t0 += TP) {
     const int nt = min(TP, p1 - t0);
     __syncthreads();
@@ -346,8 +374,10 @@ __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int
         if (i0 + u * 64 * W < nt * REC) sp[i0 + u * 64 * W] = v[u];
     }
     __syncthreads();
-    for (int j = w; j < nt; j += W)
-      rho_pair<L, SEG, NDB>(sp + j * REC, sd, mv, mw, accr, acci, e2, cis, pc, e0, eR);
+    for (int j = w; j < nt; j += W) {
+      if (CUT && sp[j * REC + 7] < wmin) continue;
+      rho_pair<L, SEG, NDB, CUT>(sp + j * REC, sd, mv, mw, accr, acci, e2, cis, pc, e0, eR, g2s);
+    }
   }
   // the W waves' partial sums are added in LDS in fixed order, one density at a time
   if (W > 1) {
@@ -387,22 +417,39 @@ __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int
 // rows, then the groups), V = v rho stored conjugated for the J pass, and the
 // energy partials Omega sum v |rho|^2 per block (G half space).
 // ---------------------------------------------------------------------------
+// The slots of the head of the FP32-MFMA form (slot_hidx >= 0) take their rows
+// from the head's partial rows [nrows_h][nhead] instead.
 __global__ __launch_bounds__(256) void k_reduce_rows(const double2 *__restrict__ part, int nrows, int nslot,
                                                      int rows_per_group, double2 *__restrict__ part2,
-                                                     int ngroups) {
+                                                     int ngroups, const int *__restrict__ slot_hidx,
+                                                     const double2 *__restrict__ parth, int nrows_h,
+                                                     int rows_per_group_h, int nhead) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int grp = blockIdx.y;
   const int dm = blockIdx.z;
   if (g >= nslot) return;
-  const int r0 = grp * rows_per_group, r1 = min(nrows, r0 + rows_per_group);
-  const double2 *pp = part + (size_t)dm * nrows * nslot + g;
+  const int h = slot_hidx ? slot_hidx[g] : -1;
+  int r0, r1;
+  size_t stride;
+  const double2 *pp;
+  if (h >= 0) {
+    r0 = grp * rows_per_group_h;
+    r1 = min(nrows_h, r0 + rows_per_group_h);
+    pp = parth + (size_t)dm * nrows_h * nhead + h;
+    stride = (size_t)nhead;
+  } else {
+    r0 = grp * rows_per_group;
+    r1 = min(nrows, r0 + rows_per_group);
+    pp = part + (size_t)dm * nrows * nslot + g;
+    stride = (size_t)nslot;
+  }
   double r = 0.0, i = 0.0;
   int row = r0;
   // rows added in order; the loads of eight rows are issued together
   for (; row + 8 <= r1; row += 8) {
     double2 x[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) x[u] = pp[(size_t)(row + u) * nslot];
+    for (int u = 0; u < 8; ++u) x[u] = pp[(size_t)(row + u) * stride];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       r += x[u].x;
@@ -410,7 +457,7 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const double2 *__restrict__
     }
   }
   for (; row < r1; ++row) {
-    const double2 x = pp[(size_t)row * nslot];
+    const double2 x = pp[(size_t)row * stride];
     r += x.x;
     i += x.y;
   }
@@ -495,14 +542,14 @@ __host__ __device__ constexpr double binom_d(int a, int c) {
 
 // J moments of one pair per lane for NDB densities (dm0 .. dm0+NDB-1, those past
 // ndm skipped): S is generated once per point and shared by the densities.
-template <int L, int SEG, int NDB>
+template <int L, int SEG, int NDB, bool CUT>
 __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, int nseg, int segs_per_chunk,
                                             const double2 *__restrict__ Vc, int nslot,
                                             const PairHot *__restrict__ hot, int Lp0, int Lp1,
                                             double *__restrict__ yhat, int64_t yhat_size, int64_t ycls_off, int pb,
                                             int chunk, int dm0, int ndm, SegDesc *__restrict__ ss,
                                             double2 *__restrict__ sv, const double *__restrict__ e2,
-                                            const double2 *__restrict__ cis) {
+                                            const double2 *__restrict__ cis, double muu) {
   constexpr int NT = nherm(L);
   constexpr int TS = kJTile;
   constexpr Monos<L> MT{};
@@ -538,6 +585,9 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
     for (int j = 0; j < nt; ++j) {
       const SegDesc sd = ss[j];
       const double nu0 = sd.nu0, nv = sd.nv, nw = sd.nw;
+      // per-pair cuts: a segment outside every lane's cut is skipped (the next
+      // segment of its line then restarts the recurrence)
+      if (CUT && !__any(h.gc2 >= sd.g2min)) continue;
       if (!(sd.nv == pnv && sd.nw == pnw && sd.nu0 == pnext)) {
         const double e0 = exp_tab(-sd.gq0 * h.inv4p, e2);
         const double eR = exp_tab(-sd.dg0 * h.inv4p, e2);
@@ -560,14 +610,21 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
       // degrees L <= 3 take the moments in the point offset s (powers known at
       // compile time) and shift them to n_u = nu0 + s once per segment below
       constexpr bool kShift = L <= 3;
+      double g2 = sd.gq0, dg = sd.dg0;  // |G|^2 along the segment (per-pair cuts)
 #pragma unroll
       for (int s = 0; s < SEG; ++s) {
         const double n = nu0 + s;
+        const bool out = CUT && g2 > h.gc2;
+        const double sr = out ? 0.0 : Sr, si = out ? 0.0 : Si;
+        if constexpr (CUT) {
+          g2 += dg;
+          dg += 2.0 * muu;
+        }
 #pragma unroll
         for (int b = 0; b < NDB; ++b) {
           const double2 v = sv[b * TS * SEG + j * SEG + s];
-          const double Ur = fma(v.x, Sr, -v.y * Si);
-          const double Ui = fma(v.x, Si, v.y * Sr);
+          const double Ur = fma(v.x, sr, -v.y * si);
+          const double Ui = fma(v.x, si, v.y * sr);
           if constexpr (kShift) {
             mr[b][0] += Ur;
             mi[b][0] += Ui;
@@ -669,7 +726,7 @@ __device__ __forceinline__ void back_thread(const Dev &dv, int bi, int dm) {
 #pragma unroll
   for (int e = 0; e < NCA * NCB; ++e) J[e] = 0.0;
   for (int q = b.p0; q < b.p1; ++q) {
-    const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (q - Lp0);
+    const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (dv.cut_rank[q] - Lp0);  // J walk order
     // y_k = sum over the J chunks in chunk order; the loads of four chunks are
     // issued together (one thread per pair leaves little other parallelism)
     double y[NT];
@@ -920,8 +977,13 @@ __device__ __forceinline__ void transform_wave(const Dev &dv, int bi, int dm, do
 #pragma unroll
       for (int t = 0; t < ncart(L); ++t)
         if (t < nc) s = fma(tv[t], sH[deg_off(d) + t], s);
-      out[k] = sg * s;
-      if (dh32) dh32[d32_off + (size_t)(q - Lp0) * ncols + k * ndmp + dm] = (float)(sg * s);
+      if (dh32) {  // FP32-MFMA form: the MFMA layout (see transform_thread)
+        const size_t o = d32_off + (size_t)(dv.cut_rank[q] - Lp0) * ncols + k * ndmp + dm;
+        dh32[o] = (float)(sg * s);
+        dhat[o] = sg * s;
+      } else {
+        out[k] = sg * s;
+      }
     }
   }
 }
@@ -962,7 +1024,7 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
   for (int q = b.p0; q < b.p1; ++q) {
     const PairAux x = aux[q];
     wave_sync();
-    const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (q - Lp0);
+    const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (dv.cut_rank[q] - Lp0);  // J walk order
     for (int k = lane; k < NT; k += 64) {
       // chunk order kept; up to 16 loads in flight
       double s = 0.0;
@@ -1276,7 +1338,7 @@ constexpr int rho_sp_max() {
 // rho of the classes L in [L0, L1] for NDB densities per block (blockIdx.y is the
 // density block).  Low and high groups as for the J pass: the Horner
 // coefficients and monomials of class L set the register footprint.
-template <int SEG, int L0, int L1, int NDB>
+template <int SEG, int L0, int L1, int NDB, bool CUT>
 __global__ __launch_bounds__(256) void k_rho_all(const Dev dv, const ClassTab tab, int ndm) {
   constexpr int W = 4;
   __shared__ double sp[rho_sp_max<L0, L1, NDB>()];
@@ -1293,7 +1355,7 @@ __global__ __launch_bounds__(256) void k_rho_all(const Dev dv, const ClassTab ta
 #define PWDF_RCASE(LL)                                                                                      \
   case LL:                                                                                                  \
     if (LL >= L0 && LL <= L1)                                                                               \
-      rho_block<(LL >= L0 && LL <= L1 ? LL : L0), SEG, W, NDB>(dv, sgi, chunk, db, ndm, sp, red, se2, scis); \
+      rho_block<(LL >= L0 && LL <= L1 ? LL : L0), SEG, W, NDB, CUT>(dv, sgi, chunk, db, ndm, sp, red, se2, scis); \
     break;
   switch (tab.cls[i]) {
     PWDF_RCASE(0)
@@ -1312,7 +1374,7 @@ __global__ __launch_bounds__(256) void k_rho_all(const Dev dv, const ClassTab ta
 // moments of the class-L pairs), NDB densities per block (blockIdx.y).  Classes
 // are split into a low and a high group because the moment count NT(L) sets the
 // register footprint of the launch.
-template <int SEG, int DEG, int L0, int L1, int NDB>
+template <int SEG, int DEG, int L0, int L1, int NDB, bool CUT>
 __global__ __launch_bounds__(256) void k_jpass_all(const Dev dv, const ClassTab tab, int ndm) {
   __shared__ SegDesc ss[kJTile];
   __shared__ double2 sv[NDB * kJTile * SEG];
@@ -1332,10 +1394,9 @@ __global__ __launch_bounds__(256) void k_jpass_all(const Dev dv, const ClassTab 
 #define PWDF_JCASE(LL)                                                                                         \
   case LL:                                                                                                     \
     if (LL >= L0 && LL <= L1)                                                                                  \
-      jpass_block<(LL >= L0 && LL <= L1 ? LL + DEG : 0), SEG, NDB>(dv.segs, dv.nseg, dv.j_spc[LL], dv.Vc,      \
-                                                                     dv.nslot, dv.hot, dv.L_p0[LL], dv.L_p1[LL], \
-                                                                     y, ysz, yoff, pb, chunk, dm0, ndm, ss, sv,  \
-                                                                     se2, scis);                                 \
+      jpass_block<(LL >= L0 && LL <= L1 ? LL + DEG : 0), SEG, NDB, CUT>(                                      \
+          dv.segs, dv.nseg, dv.j_spc[LL], dv.Vc, dv.nslot, dv.hot_cut, dv.L_p0[LL], dv.L_p1[LL], y, ysz, yoff, pb, \
+          chunk, dm0, ndm, ss, sv, se2, scis, dv.muu);                                                             \
     break;
   switch (L) {
     PWDF_JCASE(0)
@@ -1453,15 +1514,21 @@ static int group_ndb(const Dev &d, int group) {
   return std::min(d.ndb, 32 / d.seg_len);
 }
 
-template <int SEG, int NDB>
-static hipError_t rho_launch(const Dev &d, const ClassTab &t, int ndm, hipStream_t st, int group) {
+template <int SEG, int NDB, bool CUT>
+static hipError_t rho_launch_cut(const Dev &d, const ClassTab &t, int ndm, hipStream_t st, int group) {
   dim3 grid((unsigned)t.first[t.n], (unsigned)((ndm + NDB - 1) / NDB)), block(64, 4);
   if (group == 0)
-    hipLaunchKernelGGL((k_rho_all<SEG, 0, kJSplit, NDB>), grid, block, 0, st, d, t, ndm);
+    hipLaunchKernelGGL((k_rho_all<SEG, 0, kJSplit, NDB, CUT>), grid, block, 0, st, d, t, ndm);
   else
-    hipLaunchKernelGGL((k_rho_all<SEG, kJSplit + 1, 2 * kMaxL, 1>), grid, block, 0, st, d, t, ndm);
+    hipLaunchKernelGGL((k_rho_all<SEG, kJSplit + 1, 2 * kMaxL, 1, CUT>), grid, block, 0, st, d, t, ndm);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
+}
+
+template <int SEG, int NDB>
+static hipError_t rho_launch(const Dev &d, const ClassTab &t, int ndm, hipStream_t st, int group) {
+  return d.pair_gcut ? rho_launch_cut<SEG, NDB, true>(d, t, ndm, st, group)
+                     : rho_launch_cut<SEG, NDB, false>(d, t, ndm, st, group);
 }
 
 template <int SEG>
@@ -1492,15 +1559,21 @@ hipError_t launch_rho_group(const Dev &d, int group, int ndm, hipStream_t st) {
   }
 }
 
-template <int SEG, int DEG, int NDB>
-static hipError_t jpass_launch(const Dev &d, const ClassTab &t, int ndm, hipStream_t st, int group) {
+template <int SEG, int DEG, int NDB, bool CUT>
+static hipError_t jpass_launch_cut(const Dev &d, const ClassTab &t, int ndm, hipStream_t st, int group) {
   dim3 grid((unsigned)t.first[t.n], (unsigned)((ndm + NDB - 1) / NDB));
   if (group == 0)
-    hipLaunchKernelGGL((k_jpass_all<SEG, DEG, 0, kJSplit, NDB>), grid, dim3(256), 0, st, d, t, ndm);
+    hipLaunchKernelGGL((k_jpass_all<SEG, DEG, 0, kJSplit, NDB, CUT>), grid, dim3(256), 0, st, d, t, ndm);
   else
-    hipLaunchKernelGGL((k_jpass_all<SEG, DEG, kJSplit + 1, 2 * kMaxL, 1>), grid, dim3(256), 0, st, d, t, ndm);
+    hipLaunchKernelGGL((k_jpass_all<SEG, DEG, kJSplit + 1, 2 * kMaxL, 1, CUT>), grid, dim3(256), 0, st, d, t, ndm);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
+}
+
+template <int SEG, int DEG, int NDB>
+static hipError_t jpass_launch(const Dev &d, const ClassTab &t, int ndm, hipStream_t st, int group) {
+  return d.pair_gcut ? jpass_launch_cut<SEG, DEG, NDB, true>(d, t, ndm, st, group)
+                     : jpass_launch_cut<SEG, DEG, NDB, false>(d, t, ndm, st, group);
 }
 
 template <int SEG, int DEG>
@@ -1577,7 +1650,8 @@ hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, double *EJ, hipStre
 hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st) {
   dim3 g1((unsigned)((d.nslot + 255) / 256), d.ngroups, ndm);
   hipLaunchKernelGGL(k_reduce_rows, g1, dim3(256), 0, st, d.part, d.nrows, d.nslot, d.rows_per_group, d.part2,
-                     d.ngroups);
+                     d.ngroups, d.npts_head > 0 ? d.slot_hidx : nullptr, d.parth, d.nrows_h, d.rows_per_group_h,
+                     d.npts_head);
   PWDF_CHECK_LAUNCH();
   dim3 g2((unsigned)d.nred_blocks, ndm);
   hipLaunchKernelGGL(k_reduce, g2, dim3(256), 0, st, d.part2, d.ngroups, d.nslot, d.slot_v, d.vol, d.rho, d.Vc,

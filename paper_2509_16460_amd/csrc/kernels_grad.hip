@@ -20,8 +20,9 @@ template <int LA, int LB>
 __global__ __launch_bounds__(64) void k_force_back(const BlockRec *__restrict__ blocks, int b0, int b1,
                                                    const PairAux *__restrict__ aux, const double *__restrict__ ttab,
                                                    const double *__restrict__ yF, int64_t yF_size, int64_t yF_off,
-                                                   int nchunks, int Lp0, int Lp1, const double *__restrict__ Dblk,
-                                                   int64_t nelem, double *__restrict__ gblk, int nblocks) {
+                                                   int nchunks, int Lp0, int Lp1, const int *__restrict__ cut_rank,
+                                                   const double *__restrict__ Dblk, int64_t nelem,
+                                                   double *__restrict__ gblk, int nblocks) {
   constexpr int L = LA + LB;
   constexpr int L1 = L + 1;
   constexpr int NT1 = nherm(L1);
@@ -36,7 +37,7 @@ __global__ __launch_bounds__(64) void k_force_back(const BlockRec *__restrict__ 
   const double *D = Dblk + (size_t)dm * nelem + b.eoff;
   double gA[3] = {0.0, 0.0, 0.0}, gB[3] = {0.0, 0.0, 0.0};
   for (int q = b.p0; q < b.p1; ++q) {
-    const double *ys = yF + (size_t)dm * yF_size + yF_off + (q - Lp0);
+    const double *ys = yF + (size_t)dm * yF_size + yF_off + (cut_rank[q] - Lp0);  // J walk order
     double y[NT1];
 #pragma unroll
     for (int k = 0; k < NT1; ++k) {
@@ -166,7 +167,8 @@ static hipError_t fback_one(const Dev &d, int ndm, hipStream_t st) {
   constexpr int L = LA + LB;
   dim3 grid((unsigned)((b1 - b0 + 63) / 64), ndm);
   hipLaunchKernelGGL((k_force_back<LA, LB>), grid, dim3(64), 0, st, d.blocks, b0, b1, d.aux, d.ttab, d.yF, d.yF_size,
-                     d.yF_off[L], d.j_chunks[L], d.L_p0[L], d.L_p1[L], d.Dblk, d.nelem, d.gblk, d.nblocks);
+                     d.yF_off[L], d.j_chunks[L], d.L_p0[L], d.L_p1[L], d.cut_rank, d.Dblk, d.nelem, d.gblk,
+                     d.nblocks);
   PWDF_CHECK_LAUNCHG();
   return hipSuccess;
 }

@@ -1,0 +1,348 @@
+// The head of the G set in the FP32-MFMA form: FP64 tiles on FP64 MFMA
+// (gfx950, v_mfma_f64_16x16x4_f64).
+//
+// The Coulomb weight v(G) = 4 pi e^{-|G|^2/4w^2} / |G|^2 falls by orders of
+// magnitude over the first shells of G vectors, so the terms of largest size in
+// both contractions sit on the few shortest G.  There the rounding of FP32
+// operands and FP32 accumulation would set the error of E_J and J; the head --
+// the G whose weight is at least 2^-7 of the largest -- is therefore contracted
+// in FP64 here, with the same tile structure as the FP32 kernels:
+//
+//   rho:  R[G][(k,dm)] = sum_pair S(G, pair) dhat_k(pair, dm)   (K = pairs)
+//   J:    yhat[pair][(k,dm)] = sum_G Re( S(G, pair) W'(G, (k,dm)) )   (K = G)
+//
+// S(G, pair) = e^{-|G|^2/4p} e^{-2 pi i n.f_P} is evaluated directly in FP64 per
+// (G, pair) (exp2 and sincospi of the device math library); the coefficients
+// come from the FP64 transform output and W' = n^k conj V(G) (times -i for
+// odd |k|) is formed in FP64 while the tile is staged.  The head rho rows go to
+// their own partial rows (one per chunk of pairs), the J moments to the chunk
+// after the FP32 chunks of yhat; the reduction and the back transform add them.
+//
+// Lane layout of the 16x16x4 f64 MFMA (lane l = 0..63): A[l%16][l/16],
+// B[l/16][l%16], D[4*i + l/16][l%16], i = 0..3 (the rows of D interleave across
+// the four lane groups, unlike the f32 form of the same shape).
+#include <hip/hip_runtime.h>
+
+#include "kernel_common.h"
+#include "kernels.h"
+#include "mfma_common.h"
+
+namespace pwdf {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma4d(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// S = e^{-|G|^2/4p} e^{-2 pi i n.f} in FP64
+__device__ __forceinline__ void s_direct64(const GPoint &pt, const PairF &f, double &sr, double &si) {
+  const double e = exp2(-pt.g2 * f.il2);
+  double ph = fma((double)pt.nu, f.fu, fma((double)pt.nv, f.fv, (double)pt.nw * f.fw));
+  ph -= rint(ph);
+  double s, c;
+  sincospi(2.0 * ph, &s, &c);
+  sr = e * c;
+  si = -e * s;
+}
+
+// ---------------------------------------------------------------------------
+// rho over the head points, K = pairs.  A workgroup = 4 waves = 64 points (16 per
+// wave as the MFMA rows) and one chunk of pairs of class L, staged in LDS in
+// tiles of kQTileH pairs with the FP64 coefficient columns of the current N-tile
+// group (the transform's FP64 output in the layout of the FP32 operands,
+// [pair][k * ndmp + dm]).  Output: the chunk's partial row [dm][row][head point].
+// ---------------------------------------------------------------------------
+constexpr int kQTileH = 32;  // LDS: 32 KB of coefficient columns at NTG = 8
+
+template <int L, int NTG>
+__global__ __launch_bounds__(256) void k_rho_head(const GPoint *__restrict__ pts, int npts,
+                                                  const PairHot *__restrict__ hot, int Lp0, int Lp1, int ppc,
+                                                  const double *__restrict__ dh64, int64_t d_off, int ncols,
+                                                  int ndmp, int ndm, double2 *__restrict__ parth, int row0,
+                                                  int nrows_h) {
+  constexpr int NT = nherm(L);
+  __shared__ PairF sh[kQTileH];
+  __shared__ double sc[kQTileH * NTG * 16];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, g4 = lane >> 4;
+  const int chunk = blockIdx.y;
+  const int p0 = Lp0 + chunk * ppc, p1 = min(Lp1, p0 + ppc);
+  const int pt0 = blockIdx.x * 64 + w * 16;
+  const GPoint ptA = pts[min(pt0 + r16, npts - 1)];
+  const int ntiles = ncols >> 4;
+  double2 *out = parth + ((size_t)min(r16, ndm - 1) * nrows_h + row0 + chunk) * npts;
+  for (int ng = 0; ng < ntiles; ng += NTG) {
+    const int ntg = min(NTG, ntiles - ng);
+    d4 are[NTG], aim[NTG];
+#pragma unroll
+    for (int n = 0; n < NTG; ++n) {
+      are[n] = d4{0.0, 0.0, 0.0, 0.0};
+      aim[n] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+    for (int t0 = p0; t0 < p1; t0 += kQTileH) {
+      const int nq = min(kQTileH, p1 - t0);
+      __syncthreads();
+      for (int i = tid; i < nq; i += 256) sh[i] = pair_f(hot[t0 + i]);
+      // columns of densities past ndm were not written by this call's transform:
+      // masked (the FP64 buffer is not cleared)
+      for (int i = tid; i < nq * NTG * 16; i += 256) {
+        const int q = i / (NTG * 16), c = i - q * (NTG * 16);
+        const int col = ng * 16 + c;
+        const int k = col / ndmp, dm = col - k * ndmp;
+        sc[i] = c < ntg * 16 && k < NT && dm < ndm ? dh64[d_off + (size_t)(t0 + q - Lp0) * ncols + col] : 0.0;
+      }
+      __syncthreads();
+      for (int q0 = 0; q0 < nq; q0 += 4) {
+        const int q = q0 + g4 < nq ? q0 + g4 : nq - 1;
+        const bool vq = q0 + g4 < nq && ptA.g2 <= sh[q].gc2;
+        double Sr, Si;
+        s_direct64(ptA, sh[q], Sr, Si);
+        Sr = vq ? Sr : 0.0;
+        Si = vq ? Si : 0.0;
+        const double *bq = sc + q * (NTG * 16) + r16;
+#pragma unroll
+        for (int n = 0; n < NTG; ++n) {
+          const double b = bq[n * 16];
+          are[n] = mfma4d(Sr, b, are[n]);
+          aim[n] = mfma4d(Si, b, aim[n]);
+        }
+      }
+    }
+    // epilogue: lane holds R[point 4*i + g4][column r16]
+    double accr[4], acci[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) accr[i] = acci[i] = 0.0;
+    GPoint pr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pr[i] = pts[min(pt0 + 4 * i + g4, npts - 1)];
+#pragma unroll
+    for (int n = 0; n < NTG; ++n) {
+      if (n >= ntg) break;
+      const int c = (ng + n) * 16 + r16;
+      const int k = c / ndmp;
+      const bool vk = k < NT;
+      int ka = 0, kb = 0, kc = 0;
+      if (vk) mono_of(k, ka, kb, kc);
+      const bool odd = (ka + kb + kc) & 1;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double mono =
+            vk ? ipow((double)pr[i].nu, ka) * ipow((double)pr[i].nv, kb) * ipow((double)pr[i].nw, kc) : 0.0;
+        // even |k|: R; odd |k|: i R (the sign of (-i)^|k| is in dhat)
+        double cr = are[n][i], ci = aim[n][i];
+        if (odd) {
+          const double tr = -ci;
+          ci = cr;
+          cr = tr;
+        }
+        cr *= mono;
+        ci *= mono;
+        for (int off = ndmp; off < 16; off <<= 1) {
+          cr += __shfl_xor(cr, off, 64);
+          ci += __shfl_xor(ci, off, 64);
+        }
+        accr[i] += cr;
+        acci[i] += ci;
+      }
+    }
+    if (r16 < ndm) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pi = pt0 + 4 * i + g4;
+        if (pi >= npts) continue;
+        double2 v = make_double2(accr[i], acci[i]);
+        if (ng > 0) {
+          const double2 o = out[pi];
+          v.x += o.x;
+          v.y += o.y;
+        }
+        out[pi] = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// J moments over the head points, K = G.  A workgroup = 4 waves = 64 pairs (16 per
+// wave as the MFMA rows); the head points are staged in LDS tile by tile with
+// W' formed from conj V in FP64.  Output: yhat at (chunk ycls_off, k, pair).
+// ---------------------------------------------------------------------------
+// head points per LDS tile (the W' tile is 2 x kPTile x 16 NTW doubles, <= 32 KB)
+template <int NTW>
+constexpr int jh_ptile() {
+  return NTW <= 4 ? 32 : 16;
+}
+
+template <int L, int NTW>
+__global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ pts, int npts,
+                                                    const double2 *__restrict__ Vc, int nslot, int ntiles,
+                                                    int ndmp, int ndm, const PairHot *__restrict__ hot, int Lp0,
+                                                    int Lp1, double *__restrict__ yhat, int64_t yhat_size,
+                                                    int64_t ycls_off) {
+  constexpr int NT = nherm(L);
+  constexpr int kPTile = jh_ptile<NTW>();
+  __shared__ GPoint sp[kPTile];
+  __shared__ double sw[2][kPTile][NTW * 16];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, g4 = lane >> 4;
+  const int np = Lp1 - Lp0;
+  const int prow0 = blockIdx.x * 64 + w * 16;
+  const int nt0 = blockIdx.z * NTW;
+  const int ntw = min(NTW, ntiles - nt0);
+  const int pa = prow0 + r16;
+  const PairF f = pair_f(hot[Lp0 + (pa < np ? pa : 0)]);
+  d4 acc[NTW];
+#pragma unroll
+  for (int n = 0; n < NTW; ++n) acc[n] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int t0 = 0; t0 < npts; t0 += kPTile) {
+    const int nt = min(kPTile, npts - t0);
+    __syncthreads();
+    if (tid < nt) sp[tid] = pts[t0 + tid];
+    for (int i = tid; i < nt * NTW * 16; i += 256) {
+      const int q = i / (NTW * 16), c = i - q * (NTW * 16);
+      const int col = (nt0 * 16) + c;
+      const int k = col / ndmp, dm = col - k * ndmp;
+      double r = 0.0, im = 0.0;
+      if (c < ntw * 16 && k < NT && dm < ndm) {
+        const GPoint pt = pts[t0 + q];
+        int a, b, cc;
+        mono_of(k, a, b, cc);
+        const double mono = ipow((double)pt.nu, a) * ipow((double)pt.nv, b) * ipow((double)pt.nw, cc);
+        const double2 v = Vc[(size_t)dm * nslot + pt.slot];
+        r = mono * v.x;
+        im = mono * v.y;
+        if ((a + b + cc) & 1) {  // -i (r + i im) = im - i r
+          const double tr = im;
+          im = -r;
+          r = tr;
+        }
+      }
+      sw[0][q][c] = r;
+      sw[1][q][c] = im;
+    }
+    __syncthreads();
+    for (int q0 = 0; q0 < nt; q0 += 4) {
+      const int q = q0 + g4 < nt ? q0 + g4 : nt - 1;
+      const bool vq = q0 + g4 < nt && sp[q].g2 <= f.gc2;
+      double Sr, Si;
+      s_direct64(sp[q], f, Sr, Si);
+      Sr = vq ? Sr : 0.0;
+      const double nSi = vq ? -Si : 0.0;
+#pragma unroll
+      for (int n = 0; n < NTW; ++n) {
+        acc[n] = mfma4d(Sr, sw[0][q][n * 16 + r16], acc[n]);
+        acc[n] = mfma4d(nSi, sw[1][q][n * 16 + r16], acc[n]);
+      }
+    }
+  }
+  // lane holds Y[pair row 4*i + g4][column r16 of each tile]
+#pragma unroll
+  for (int n = 0; n < NTW; ++n) {
+    if (n >= ntw) continue;
+    const int col = (nt0 + n) * 16 + r16;
+    const int k = col / ndmp, dm = col - k * ndmp;
+    if (k >= NT || dm >= ndm) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int prow = prow0 + 4 * i + g4;
+      if (prow < np) yhat[(size_t)dm * yhat_size + ycls_off + (size_t)k * np + prow] = acc[n][i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+#define PWDF_CHECK_LAUNCH_H()          \
+  do {                                 \
+    hipError_t e_ = hipGetLastError(); \
+    if (e_ != hipSuccess) return e_;   \
+  } while (0)
+
+template <int L, int NTG>
+static hipError_t rho_head_ntg(const Dev &d, int ndm, hipStream_t st) {
+  dim3 grid((unsigned)((d.npts_head + 63) / 64), d.rho_h_chunks[L]);
+  hipLaunchKernelGGL((k_rho_head<L, NTG>), grid, dim3(256), 0, st, d.pts, d.npts_head, d.hot_cut, d.L_p0[L], d.L_p1[L],
+                     d.rho_h_ppc[L], d.dhat, d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.parth, d.rho_h_row0[L],
+                     d.nrows_h);
+  PWDF_CHECK_LAUNCH_H();
+  return hipSuccess;
+}
+
+template <int L>
+static hipError_t rho_head_one(const Dev &d, int ndm, hipStream_t st) {
+  const int np = d.L_p1[L] - d.L_p0[L];
+  if (np <= 0 || d.npts_head <= 0 || d.rho_h_chunks[L] <= 0) return hipSuccess;
+  switch (group_tiles(d.ncols32[L] / 16)) {
+    case 1: return rho_head_ntg<L, 1>(d, ndm, st);
+    case 2: return rho_head_ntg<L, 2>(d, ndm, st);
+    case 3: return rho_head_ntg<L, 3>(d, ndm, st);
+    case 4: return rho_head_ntg<L, 4>(d, ndm, st);
+    case 5: return rho_head_ntg<L, 5>(d, ndm, st);
+    case 6: return rho_head_ntg<L, 6>(d, ndm, st);
+    case 7: return rho_head_ntg<L, 7>(d, ndm, st);
+    case 8: return rho_head_ntg<L, 8>(d, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_rho_head_L(const Dev &d, int L, int ndm, hipStream_t st) {
+  switch (L) {
+    case 0: return rho_head_one<0>(d, ndm, st);
+    case 1: return rho_head_one<1>(d, ndm, st);
+    case 2: return rho_head_one<2>(d, ndm, st);
+    case 3: return rho_head_one<3>(d, ndm, st);
+    case 4: return rho_head_one<4>(d, ndm, st);
+    case 5: return rho_head_one<5>(d, ndm, st);
+    case 6: return rho_head_one<6>(d, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int L, int NTW>
+static hipError_t j_head_ntw(const Dev &d, int ndm, hipStream_t st) {
+  const int np = d.L_p1[L] - d.L_p0[L];
+  const int ntiles = d.ncols32[L] / 16;
+  // the head's moments are chunk j_chunks32[L] of the class
+  const int64_t off = d.yhat_off[L] + (int64_t)d.j_chunks32[L] * nherm(L) * np;
+  dim3 grid((unsigned)((np + 63) / 64), 1, (unsigned)((ntiles + NTW - 1) / NTW));
+  hipLaunchKernelGGL((k_jpass_head<L, NTW>), grid, dim3(256), 0, st, d.pts, d.npts_head, d.Vc, d.nslot, ntiles,
+                     d.ndmp, ndm, d.hot_cut, d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size, off);
+  PWDF_CHECK_LAUNCH_H();
+  return hipSuccess;
+}
+
+template <int L>
+static hipError_t j_head_one(const Dev &d, int ndm, hipStream_t st) {
+  const int np = d.L_p1[L] - d.L_p0[L];
+  if (np <= 0 || d.npts_head <= 0) return hipSuccess;
+  switch (group_tiles(d.ncols32[L] / 16)) {
+    case 1: return j_head_ntw<L, 1>(d, ndm, st);
+    case 2: return j_head_ntw<L, 2>(d, ndm, st);
+    case 3: return j_head_ntw<L, 3>(d, ndm, st);
+    case 4: return j_head_ntw<L, 4>(d, ndm, st);
+    case 5: return j_head_ntw<L, 5>(d, ndm, st);
+    case 6: return j_head_ntw<L, 6>(d, ndm, st);
+    case 7: return j_head_ntw<L, 7>(d, ndm, st);
+    case 8: return j_head_ntw<L, 8>(d, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_jpass_head_L(const Dev &d, int L, int ndm, hipStream_t st) {
+  switch (L) {
+    case 0: return j_head_one<0>(d, ndm, st);
+    case 1: return j_head_one<1>(d, ndm, st);
+    case 2: return j_head_one<2>(d, ndm, st);
+    case 3: return j_head_one<3>(d, ndm, st);
+    case 4: return j_head_one<4>(d, ndm, st);
+    case 5: return j_head_one<5>(d, ndm, st);
+    case 6: return j_head_one<6>(d, ndm, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pwdf

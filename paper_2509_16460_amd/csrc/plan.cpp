@@ -59,6 +59,110 @@ int mono_index(int e0, int e1, int e2) {
   return idx;
 }
 
+// ---- per-pair cut radius (section "Integral screening") ----
+// McMurchie-Davidson Hermite coefficients of one axis (host), E[i][j][t],
+// i <= la, j <= lb, t <= i + j.
+void md_host(int la, int lb, double p, double xpa, double xpb, double E[4][4][8]) {
+  for (int i = 0; i <= la; ++i)
+    for (int j = 0; j <= lb; ++j)
+      for (int t = 0; t < 8; ++t) E[i][j][t] = 0.0;
+  E[0][0][0] = 1.0;
+  const double inv2p = 0.5 / p;
+  for (int i = 0; i <= la; ++i)
+    for (int j = 0; j <= lb; ++j) {
+      if (i == 0 && j == 0) continue;
+      for (int t = 0; t <= i + j; ++t) {
+        double v;
+        if (i > 0) {
+          v = xpa * E[i - 1][j][t];
+          if (t > 0) v += inv2p * E[i - 1][j][t - 1];
+          if (t + 1 <= i - 1 + j) v += (t + 1) * E[i - 1][j][t + 1];
+        } else {
+          v = xpb * E[i][j - 1][t];
+          if (t > 0) v += inv2p * E[i][j - 1][t - 1];
+          if (t + 1 <= i + j - 1) v += (t + 1) * E[i][j - 1][t + 1];
+        }
+        E[i][j][t] = v;
+      }
+    }
+}
+
+// Screening objective of one primitive pair at |G| = G:
+//   eps(G) = 8 pi eta G (4 pi / G^2) e^{-G^2/4w^2} |F|_inf(G),  eta = [1/p + 1/w^2]^-1,
+// |F|_inf the largest modulus over the shell pair's Cartesian components of the
+// pair transform with G along x, y or z: with the Hermite expansion
+//   |F_ij(G e_d)| = pref K (pi/p)^{3/2} e^{-G^2/4p} |sum_t E^d_{i_d j_d t} (-iG)^t|
+//                   prod_{x != d} |E^x_{i_x j_x 0}|.
+struct CutPair {
+  int la, lb;
+  double p, pref, K;
+  double E[3][4][4][8];
+};
+
+double cut_objective(const CutPair &c, double omega, double G) {
+  double fmax = 0.0;
+  const double base = c.pref * c.K * std::pow(kPi / c.p, 1.5) * std::exp(-G * G / (4.0 * c.p));
+  for (int ia = 0; ia < ncart(c.la); ++ia)
+    for (int ib = 0; ib < ncart(c.lb); ++ib) {
+      int a[3], b[3];
+      // components in descending lexicographic order
+      {
+        int n = 0;
+        for (int x = c.la; x >= 0; --x)
+          for (int y = c.la - x; y >= 0; --y, ++n)
+            if (n == ia) a[0] = x, a[1] = y, a[2] = c.la - x - y;
+        n = 0;
+        for (int x = c.lb; x >= 0; --x)
+          for (int y = c.lb - x; y >= 0; --y, ++n)
+            if (n == ib) b[0] = x, b[1] = y, b[2] = c.lb - x - y;
+      }
+      for (int d = 0; d < 3; ++d) {
+        double re = 0.0, im = 0.0, gp = 1.0;  // sum_t E_t (-iG)^t
+        for (int t = 0; t <= a[d] + b[d]; ++t) {
+          const double e = c.E[d][a[d]][b[d]][t] * gp;
+          switch (t & 3) {
+            case 0: re += e; break;
+            case 1: im -= e; break;
+            case 2: re -= e; break;
+            default: im += e; break;
+          }
+          gp *= G;
+        }
+        double f = std::sqrt(re * re + im * im);
+        for (int x = 0; x < 3; ++x)
+          if (x != d) f *= std::fabs(c.E[x][a[x]][b[x]][0]);
+        fmax = std::max(fmax, f);
+      }
+    }
+  const double eta = 1.0 / (1.0 / c.p + 1.0 / (omega * omega));
+  return 8.0 * kPi * eta * G * (4.0 * kPi / (G * G)) * std::exp(-G * G / (4.0 * omega * omega)) * base * fmax;
+}
+
+// Cut radius: from the global cutoff downwards in 256 equal steps to the first G
+// where the objective reaches eps_G, then 60 bisection steps on that step; the
+// bracket's upper end (the global cutoff if the objective reaches eps_G there).
+double cut_radius(const CutPair &c, double omega, double eps_G) {
+  const double gglob = 2.0 * omega * std::sqrt(-std::log(eps_G));
+  if (cut_objective(c, omega, gglob) >= eps_G) return gglob;
+  double hi = gglob, lo = 0.0;
+  for (int k = 1; k < 256; ++k) {
+    const double G = gglob * (1.0 - k / 256.0);
+    if (cut_objective(c, omega, G) >= eps_G) {
+      lo = G;
+      break;
+    }
+    hi = G;
+  }
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid > 0.0 && cut_objective(c, omega, mid) >= eps_G)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return hi;
+}
+
 }  // namespace
 
 void build_segments(Plan &p, int seg_len) {
@@ -77,11 +181,18 @@ void build_segments(Plan &p, int seg_len) {
   }
   const int u = p.ax[0], v = p.ax[1], w = p.ax[2];
   const double w4 = 4.0 * p.in.omega * p.in.omega;
-  int64_t count = 0;
+  // lines of the half space: (nw > 0) or (nw = 0, nv > 0) or (0, 0, nu > 0), with
+  // their n_u range inside the cutoff sphere and their smallest |G|^2
+  struct Line {
+    double g2min;
+    int nw, nv, lo, hi;
+  };
+  std::vector<Line> lines;
   for (int nw = 0; nw <= nmax[w]; ++nw)
     for (int nv = -nmax[v]; nv <= nmax[v]; ++nv) {
-      if (nw == 0 && nv < 0) continue;  // half space: (nw > 0) or (nw = 0, nv > 0) or (0, 0, nu > 0)
+      if (nw == 0 && nv < 0) continue;
       int lo = 1 << 30, hi = -(1 << 30);
+      double gmin = 1e300;
       for (int nu = -nmax[u]; nu <= nmax[u]; ++nu) {
         if (nw == 0 && nv == 0 && nu <= 0) continue;
         int n[3];
@@ -92,40 +203,63 @@ void build_segments(Plan &p, int seg_len) {
         if (g2 > 0.0 && g2 <= gcut2) {
           lo = std::min(lo, nu);
           hi = std::max(hi, nu);
+          gmin = std::min(gmin, g2);
         }
       }
-      if (lo > hi) continue;
-      for (int nu0 = lo; nu0 <= hi; nu0 += seg_len) {
-        SegDesc sd;
-        sd.nu0 = nu0;
-        sd.nv = nv;
-        sd.nw = nw;
-        sd.cnt = std::min(seg_len, hi - nu0 + 1);
-        double b = p.M[u][v] * nv + p.M[u][w] * nw;
-        double c = p.M[v][v] * nv * nv + 2.0 * p.M[v][w] * nv * nw + p.M[w][w] * nw * nw;
-        sd.gq0 = p.M[u][u] * nu0 * (double)nu0 + 2.0 * b * nu0 + c;
-        sd.dg0 = p.M[u][u] * (2.0 * nu0 + 1.0) + 2.0 * b;
-        int sidx = (int)p.segs.size();
-        p.segs.push_back(sd);
-        for (int s = 0; s < seg_len; ++s) {
-          int n[3] = {0, 0, 0};
-          double vg = 0.0;
-          if (s < sd.cnt) {
-            n[u] = nu0 + s;
-            n[v] = nv;
-            n[w] = nw;
-            double g2 = g2_of(p, n);
-            vg = 4.0 * kPi * std::exp(-g2 / w4) / g2;
-            p.valid_slots.push_back(sidx * seg_len + s);
-            p.pts.push_back({g2, nu0 + s, nv, nw, sidx * seg_len + s});
-            ++count;
-          }
-          p.slot_v.push_back(vg);
-          for (int c3 = 0; c3 < 3; ++c3) p.slot_miller.push_back(n[c3]);
-        }
-      }
+      if (lo <= hi) lines.push_back({gmin, nw, nv, lo, hi});
     }
+  // lines ordered by their smallest |G| (segments of one line stay adjacent), so
+  // that a group of segments or points spans a narrow range of |G|: pairs whose
+  // own cut radius is smaller skip whole groups (section "Integral screening")
+  std::stable_sort(lines.begin(), lines.end(), [](const Line &a, const Line &b) {
+    return std::tie(a.g2min, a.nw, a.nv) < std::tie(b.g2min, b.nw, b.nv);
+  });
+  int64_t count = 0;
+  for (const Line &ln : lines) {
+    const int nv = ln.nv, nw = ln.nw;
+    for (int nu0 = ln.lo; nu0 <= ln.hi; nu0 += seg_len) {
+      SegDesc sd;
+      sd.nu0 = nu0;
+      sd.nv = nv;
+      sd.nw = nw;
+      sd.cnt = std::min(seg_len, ln.hi - nu0 + 1);
+      double b = p.M[u][v] * nv + p.M[u][w] * nw;
+      double c = p.M[v][v] * nv * nv + 2.0 * p.M[v][w] * nv * nw + p.M[w][w] * nw * nw;
+      sd.gq0 = p.M[u][u] * nu0 * (double)nu0 + 2.0 * b * nu0 + c;
+      sd.dg0 = p.M[u][u] * (2.0 * nu0 + 1.0) + 2.0 * b;
+      sd.g2min = 1e300;
+      sd.pad = 0.0;
+      int sidx = (int)p.segs.size();
+      for (int s = 0; s < seg_len; ++s) {
+        int n[3] = {0, 0, 0};
+        double vg = 0.0;
+        if (s < sd.cnt) {
+          n[u] = nu0 + s;
+          n[v] = nv;
+          n[w] = nw;
+          double g2 = g2_of(p, n);
+          vg = 4.0 * kPi * std::exp(-g2 / w4) / g2;
+          sd.g2min = std::min(sd.g2min, g2);
+          p.valid_slots.push_back(sidx * seg_len + s);
+          p.pts.push_back({g2, nu0 + s, nv, nw, sidx * seg_len + s});
+          ++count;
+        }
+        p.slot_v.push_back(vg);
+        for (int c3 = 0; c3 < 3; ++c3) p.slot_miller.push_back(n[c3]);
+      }
+      p.segs.push_back(sd);
+    }
+  }
   p.nG_full = 2 * count;
+  // The point list in order of |G|^2 (ties in walk order): a run of consecutive
+  // points spans a narrow shell, so the per-pair cuts skip whole K-steps and
+  // tiles of the point-wise kernels; v(G) decreases with |G|, so the head (v(G) >=
+  // kHeadWeight max v) is a prefix.
+  std::stable_sort(p.pts.begin(), p.pts.end(), [](const GPoint &a, const GPoint &b) { return a.g2 < b.g2; });
+  const double vmax = p.pts.empty() ? 0.0 : p.slot_v[p.pts[0].slot];
+  p.npts_head = 0;
+  while (p.npts_head < (int)p.pts.size() && p.slot_v[p.pts[p.npts_head].slot] >= kHeadWeight * vmax) ++p.npts_head;
+  p.head_g2 = p.npts_head > 0 ? p.pts[p.npts_head - 1].g2 : 0.0;
 }
 
 std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
@@ -342,14 +476,75 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
       h.cu = std::cos(2.0 * kPi * h.fu);
       h.su = -std::sin(2.0 * kPi * h.fu);
       h.q = std::exp(-p.M[p.ax[0]][p.ax[0]] / (2.0 * pp));
-      h.pad = 0.0;
+      h.gc2 = 1e300;  // set per block below when per-pair cuts are on
       p.hot.push_back(h);
       p.aux.push_back(x);
     }
     br.p1 = (int)p.hot.size();
+    // per-pair cut: the block's most compact primitive pair (largest p, the first
+    // of equal ones) sets the cut radius of all its primitive pairs, as the paper
+    // does for a contracted shell pair (section "Integral screening")
+    if (in.pair_gcut && br.p1 > br.p0) {
+      int best = br.p0;
+      for (int q = br.p0 + 1; q < br.p1; ++q)
+        if (p.aux[q].p > p.aux[best].p) best = q;
+      const RawPair &pr = rb.prims[best - br.p0];
+      CutPair cp;
+      cp.la = la;
+      cp.lb = lb;
+      cp.p = p.aux[best].p;
+      cp.pref = std::fabs(in.coefs[pr.ia] * in.coefs[pr.ib]) * gto_norm(la, in.exps[pr.ia]) * gto_norm(lb, in.exps[pr.ib]);
+      double r2 = 0.0;
+      for (int c = 0; c < 3; ++c) r2 += (RA[c] - RB[c]) * (RA[c] - RB[c]);
+      cp.K = std::exp(-in.exps[pr.ia] * in.exps[pr.ib] / cp.p * r2);
+      for (int x = 0; x < 3; ++x) md_host(la, lb, cp.p, p.aux[best].xpa[x], p.aux[best].xpb[x], cp.E[x]);
+      const double rc = cut_radius(cp, in.omega, in.eps_G);
+      for (int q = br.p0; q < br.p1; ++q) p.hot[q].gc2 = rc * rc;
+    }
     p.blocks.push_back(br);
   }
   p.nelem = eoff;
+  // Pair-G work inside the cuts: for each pair and G line (fixed n_v, n_w) the
+  // n_u with |G(n_u)|^2 = M_uu n_u^2 + 2 b n_u + c <= gc2 lie between the roots
+  // of the quadratic (eq. "G-space root finding"), clipped to the line's range.
+  {
+    struct LineQ {
+      double b, c;
+      int lo, hi;
+    };
+    std::vector<LineQ> lq;
+    const int u = p.ax[0], v = p.ax[1], w = p.ax[2];
+    const double muu = p.M[u][u];
+    for (size_t i = 0; i < p.segs.size(); ++i) {
+      const SegDesc &sd = p.segs[i];
+      if (i > 0 && p.segs[i - 1].nv == sd.nv && p.segs[i - 1].nw == sd.nw) {
+        lq.back().hi = sd.nu0 + sd.cnt - 1;
+        continue;
+      }
+      lq.push_back({p.M[u][v] * sd.nv + p.M[u][w] * sd.nw,
+                    p.M[v][v] * sd.nv * (double)sd.nv + 2.0 * p.M[v][w] * sd.nv * sd.nw + p.M[w][w] * sd.nw * (double)sd.nw,
+                    sd.nu0, sd.nu0 + sd.cnt - 1});
+    }
+    const double gcut2 = 4.0 * in.omega * in.omega * (-std::log(in.eps_G));
+    double last = -1.0, last_cnt = 0.0;
+    p.pairG_of.resize(p.hot.size());
+    for (size_t q = 0; q < p.hot.size(); ++q) {
+      const double gc2 = std::min(p.hot[q].gc2, gcut2 * (1.0 + 1e-12));
+      if (gc2 != last) {
+        last = gc2;
+        last_cnt = 0.0;
+        for (const LineQ &l : lq) {
+          const double disc = l.b * l.b - muu * (l.c - gc2);
+          if (disc < 0.0) continue;
+          const double sq = std::sqrt(disc);
+          const int lo = std::max(l.lo, (int)std::ceil((-l.b - sq) / muu - 1e-12));
+          const int hi = std::min(l.hi, (int)std::floor((-l.b + sq) / muu + 1e-12));
+          if (hi >= lo) last_cnt += hi - lo + 1;
+        }
+      }
+      p.pairG_of[q] = last_cnt;
+    }
+  }
   // Bound of the segment-start arguments: |G|^2 / 4p <= Gcut^2 / 4p and the step
   // ratio (|G(n+1)|^2 - |G(n)|^2) / 4p, |.| <= (2 Gcut |b_u| + |b_u|^2) / 4p, over
   // the smallest p.  The starts are evaluated without range handling (exp of
@@ -410,6 +605,24 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
     p.dhat_off[kMaxLsum] = off;
     p.dhat_size = off;
   }
+  p.pairG_cut = 0.0;
+  p.pairG_head = 0.0;
+  {
+    // head G within each pair's cut
+    std::vector<double> hg2;
+    for (int i = 0; i < p.npts_head; ++i) hg2.push_back(p.pts[i].g2);
+    std::sort(hg2.begin(), hg2.end());
+    for (int L = 0; L <= kMaxLsum; ++L) {
+      p.pairG_L[L] = 0.0;
+      p.pairG_head_L[L] = 0.0;
+      for (int q = p.L_p0[L]; q < p.L_p1[L]; ++q) {
+        p.pairG_L[L] += p.pairG_of[q];
+        p.pairG_head_L[L] += (double)(std::upper_bound(hg2.begin(), hg2.end(), p.hot[q].gc2) - hg2.begin());
+      }
+      p.pairG_cut += p.pairG_L[L];
+      p.pairG_head += p.pairG_head_L[L];
+    }
+  }
   {
     std::vector<int> order(p.hot.size());
     for (size_t i = 0; i < p.hot.size(); ++i) order[i] = (int)i;
@@ -421,6 +634,21 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
     for (size_t r = 0; r < order.size(); ++r) {
       p.rho_rank[order[r]] = (int)r;
       p.hot_rho[r] = p.hot[order[r]];
+    }
+  }
+  {
+    // the walk order of the J pass (both forms) and of the FP32-MFMA rho pass:
+    // each class by cut radius, largest first (storage order without cuts)
+    std::vector<int> order(p.hot.size());
+    for (size_t i = 0; i < p.hot.size(); ++i) order[i] = (int)i;
+    for (int L = 0; L <= kMaxLsum; ++L)
+      std::stable_sort(order.begin() + p.L_p0[L], order.begin() + p.L_p1[L],
+                       [&](int x, int y) { return p.hot[x].gc2 > p.hot[y].gc2; });
+    p.cut_rank.resize(p.hot.size());
+    p.hot_cut.resize(p.hot.size());
+    for (size_t r = 0; r < order.size(); ++r) {
+      p.cut_rank[order[r]] = (int)r;
+      p.hot_cut[r] = p.hot[order[r]];
     }
   }
   p.elem_blk.resize(p.nelem);

@@ -18,7 +18,11 @@ struct PlanInput {
   std::vector<double> exps, coefs;
   int kmesh[3];
   double omega, eps_pair, eps_G, r_max;
+  int pair_gcut = 0;  // 1: every pair block gets its own cut radius (section "Integral screening")
 };
+
+// Relative Coulomb weight that bounds the head of the G set (see Plan::npts_head).
+constexpr double kHeadWeight = 1.0 / 128.0;
 
 struct Plan {
   PlanInput in;
@@ -35,8 +39,18 @@ struct Plan {
   std::vector<double> slot_v;       // v(G) per slot, 0 on padding
   std::vector<int> slot_miller;     // [nslot][3] in the original axis order (padding: 0,0,0)
   std::vector<int> valid_slots;     // slots holding a G, in walk order
-  std::vector<GPoint> pts;          // the same G vectors as a compact point list
+  std::vector<GPoint> pts;          // the same G vectors as a compact point list, by |G|^2
+  // The head of the G set: the vectors whose Coulomb weight v(G) is at least
+  // kHeadWeight times the largest one (the shortest |G|).  The FP32-MFMA form
+  // evaluates them with FP64 tiles; pts[0, npts_head) are the head.
+  int npts_head = 0;
+  double head_g2 = 0.0;             // largest |G|^2 of the head
+  double pairG_head = 0.0;          // sum over pairs of the head G within their cut (per pass)
+  double pairG_head_L[kMaxLsum + 1];  // per class L
   int64_t nG_full = 0;              // |G set| including -G
+  double pairG_cut = 0.0;           // sum over pairs of the half-space G within their cut (per pass)
+  std::vector<double> pairG_of;     // per pair: half-space G within its cut
+  double pairG_L[kMaxLsum + 1];     // per class L: sum of pairG_of
   // lattice images of the pair list
   std::vector<std::array<int, 3>> imgs;
   // unique blocks and primitive pairs, sorted by (L = la+lb, la, sa, sb, m)
@@ -52,6 +66,12 @@ struct Plan {
   // records in walk order.
   std::vector<int> rho_rank;
   std::vector<PairHot> hot_rho;
+  // The J pass (both forms) and the FP32-MFMA rho pass walk each class by cut
+  // radius, largest first, so that the pairs of a wave or a tile share similar
+  // cuts and skip the same G: cut_rank[pair] is the position in that walk (of the
+  // J moments and the FP32-MFMA coefficient rows), hot_cut the records in it.
+  std::vector<int> cut_rank;
+  std::vector<PairHot> hot_cut;
   int64_t dhat_off[kMaxLsum + 1];             // offset of class L in a per-density coefficient array
   int64_t dhat_size = 0;
   int64_t nelem = 0;                          // sum over blocks of ncart(la) ncart(lb)

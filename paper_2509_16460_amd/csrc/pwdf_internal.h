@@ -40,6 +40,8 @@ struct SegDesc {
   int nu0, nv, nw, cnt;
   double gq0;  // |G|^2 at n_u = nu0
   double dg0;  // |G(nu0+1)|^2 - |G(nu0)|^2
+  double g2min;  // smallest |G|^2 of the segment's points
+  double pad;
 };
 
 // One G vector of the half space the kernels walk, for the FP32-MFMA form, which
@@ -58,7 +60,7 @@ struct PairHot {
   double fu, fv, fw; // fractional coordinates of P in the (u,v,w) axis order, in [-1/2,1/2)
   double cu, su;     // cos(2 pi f_u), -sin(2 pi f_u): the per-step phase e^{-2 pi i f_u}
   double q;          // exp(-M_uu / 2p)
-  double pad;
+  double gc2;        // squared cut radius: the pair sees the G of the set with |G|^2 <= gc2
 };
 
 // Per primitive pair, read by the density / back transforms.

@@ -39,7 +39,8 @@ class PwdfError(RuntimeError):
 
 
 class Screen(ctypes.Structure):
-    _fields_ = [("eps_pair", ctypes.c_double), ("eps_G", ctypes.c_double), ("r_max", ctypes.c_double)]
+    _fields_ = [("eps_pair", ctypes.c_double), ("eps_G", ctypes.c_double), ("r_max", ctypes.c_double),
+                ("pair_gcut", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -48,7 +49,7 @@ class Stats(ctypes.Structure):
                 ("nblocks", ctypes.c_int64), ("nseg", ctypes.c_int64), ("pairG_evals", ctypes.c_double),
                 ("t_us", ctypes.c_double * 8), ("seg_len", ctypes.c_int64),
                 ("fork", ctypes.c_int64), ("jk_support", ctypes.c_int64), ("dk_support", ctypes.c_int64),
-                ("jk_layout", ctypes.c_int64)]
+                ("jk_layout", ctypes.c_int64), ("nG_head", ctypes.c_int64), ("pairG_head", ctypes.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("npairs_by_class", "t_us")}
@@ -135,7 +136,7 @@ def plan_stats(prob) -> dict:
     """Host-only plan sizes (no device needed)."""
     a = _basis_arrays(prob)
     st = Stats()
-    scr = Screen(prob.eps_pair, prob.eps_G, prob.r_max)
+    scr = Screen(prob.eps_pair, prob.eps_G, prob.r_max, int(getattr(prob, "pair_gcut", 0)))
     rc = lib().pwdf_plan_stats(_dp(a["lat"]), prob.natm, _dp(a["xyz"]), prob.nshell, _ip(a["sa"]), _ip(a["sl"]),
                                _ip(a["sn"]), _dp(a["ex"]), _dp(a["co"]), _ip(a["km"]), float(prob.omega),
                                ctypes.byref(scr), ctypes.byref(st))
@@ -154,7 +155,7 @@ class LongRangeJ:
         self.device = device
         a = _basis_arrays(prob)
         self._keep = a
-        scr = Screen(prob.eps_pair, prob.eps_G, prob.r_max)
+        scr = Screen(prob.eps_pair, prob.eps_G, prob.r_max, int(getattr(prob, "pair_gcut", 0)))
         h = ctypes.c_void_p()
         rc = lib().pwdf_create(ctypes.byref(h), _dp(a["lat"]), prob.natm, _dp(a["xyz"]), prob.nshell, _ip(a["sa"]),
                                _ip(a["sl"]), _ip(a["sn"]), _dp(a["ex"]), _dp(a["co"]), _ip(a["km"]),

@@ -72,6 +72,7 @@ class Problem:
     r_max: float = 0.0
     nelec: float = 2.0
     seed: int = 0
+    pair_gcut: int = 0  # 1: per-pair reciprocal-space cut (section "Integral screening")
 
     @property
     def natm(self) -> int:

@@ -3,8 +3,12 @@
 Targets of the precision form: |E_J - E_J(oracle)| <= 1e-7 Eh and
 max |J(k) - J(k)(oracle)| <= 1e-8 on the cubic Gamma cell (2 atoms, 4s2p per
 atom).  Batched calls must give, density by density, the same result as
-single-density FP32 calls to FP32 rounding, and stay within the relative error
-the FP32 operands allow against the FP64 path on every class up to (3,3).
+single-density FP32 calls up to that form's rounding, and stay within the
+relative error it reaches against the FP64 path on every class up to (3,3).
+The head of the G set (the G whose Coulomb weight is within 2^-7 of the
+largest) is contracted with FP64 tiles, so the FP32 rounding is weighted by the
+tail's small weights: measured ~1e-9 relative in J and below in E_J; the bars
+are 2e-8 (E_J and J, relative) and 1e-8 between batched and single calls.
 """
 import numpy as np
 import pytest
@@ -52,7 +56,7 @@ def test_fp32_vs_fp64_classes(name, lmax, kmesh, natm):
     relE = abs(E32[0] - E64[0]) / abs(E64[0])
     relJ = np.max(np.abs(J32 - J64)) / np.max(np.abs(J64))
     print(f"{name}: relE={relE:.2e} relJ={relJ:.2e}", flush=True)
-    assert relE <= 2e-6 and relJ <= 2e-5
+    assert relE <= 2e-8 and relJ <= 2e-8
 
 
 @pytest.mark.parametrize("ndm", [3, 16])
@@ -63,9 +67,9 @@ def test_fp32_batched_equals_single(ndm):
     J64, E64 = run(p, D, pw().PWDF_FP64)
     for i in (0, ndm - 1):
         Js, Es = run(p, D[i:i + 1], pw().PWDF_FP32_MFMA)
-        assert abs(Eb[i] - Es[0]) <= 1e-6 * abs(Es[0])
-        assert np.max(np.abs(Jb[i] - Js[0])) <= 1e-5 * np.max(np.abs(Js[0]))
+        assert abs(Eb[i] - Es[0]) <= 1e-8 * abs(Es[0])
+        assert np.max(np.abs(Jb[i] - Js[0])) <= 1e-8 * np.max(np.abs(Js[0]))
     relE = np.max(np.abs(Eb - E64) / np.abs(E64))
     relJ = np.max(np.abs(Jb - J64)) / np.max(np.abs(J64))
     print(f"batched ndm={ndm}: relE={relE:.2e} relJ={relJ:.2e}", flush=True)
-    assert relE <= 2e-6 and relJ <= 2e-5
+    assert relE <= 2e-8 and relJ <= 2e-8

@@ -16,12 +16,16 @@ times: autotuned contexts, graph replay, packed J(k).
 Bars.  FP64: 1e-10 Eh and 1e-11 in J(k) where E_J and J are O(1) (diamond);
 on the slab E_J is ~3.4e3 Eh and max|J| ~29, where the FP64 rounding of the
 sums alone is ~1e-13 relative, so the bars there are relative: 1e-13 |E_J| and
-1e-11 max(1, max|J|) (a reading recorded with the other readings of the
-build).  FP32-MFMA: the targets 1e-7 Eh / 1e-8 in J are tested on the cubic
-cell (test_gpu_fp32.py); on the large cells the FP32 form's error grows with
-the size of the sums (FP32 products summed over ~2.5e3 G vectors and ~6e4
-pairs), and the bars are the levels this form reaches, relative: E_J within
-2e-7 |E_J|, J(k) within 2e-6 max|J| (slab); 1e-7 Eh and 1e-7 in J (diamond).
+1e-11 max(1, max|J|) (the absolute bars read as relative ones once E_J and J
+are far from unit size).  FP32-MFMA: the targets 1e-7 Eh / 1e-8 in J are tested on the cubic
+cell (test_gpu_fp32.py).  On the large cells the FP32 tiles carry only the tail
+of the G set (the head, where the Coulomb weight is within 2^-7 of its largest,
+takes FP64 tiles), and the error of the sums of FP32 products scales with the
+tail's weights: measured on the slab 5e-11 to 7e-10 |E_J| and ~1e-8 max|J|
+(~2e-7 absolute in J, ~1e-6 Eh in E_J of ~3.4e3 Eh), on the diamond cell
+~4e-11 Eh and ~5e-10 in J.  The bars are those levels with a margin of about
+ten: slab E_J within 5e-9 |E_J| and J(k) within 5e-8 max|J|; diamond 1e-9 Eh
+and 5e-9 in J.
 """
 import os
 
@@ -105,8 +109,8 @@ def test_slab_batch16_fp32_mfma(slab):
         dJ = float(np.max(np.abs(sampled(J32[i], pos, f[f"idx_{i}"]) - f[f"J_{i}"])))
         print(f"slab FP32-MFMA batch density {i} vs oracle: dE={dE:.2e} ({dE / abs(Eo):.1e} rel) "
               f"max|dJ|={dJ:.2e} ({dJ / jmax:.1e} of max|J|)", flush=True)
-        assert dE <= 2e-7 * abs(Eo)
-        assert dJ <= 2e-6 * jmax
+        assert dE <= 5e-9 * abs(Eo)
+        assert dJ <= 5e-8 * jmax
     c64, pos64 = packed_ctx(p, 0, 16, tune=False)
     assert pos64 == pos
     J64, E64 = run_packed(c64, Db, 16)
@@ -115,7 +119,7 @@ def test_slab_batch16_fp32_mfma(slab):
     jmax = np.max(np.abs(J64))
     print("slab FP32-MFMA vs FP64 batch, per density: relE " + " ".join(f"{x:.1e}" for x in relE) +
           " | max|dJ| " + " ".join(f"{x:.1e}" for x in dJ), flush=True)
-    assert np.all(relE <= 2e-7) and np.all(dJ <= 2e-6 * jmax)
+    assert np.all(relE <= 5e-9) and np.all(dJ <= 5e-8 * jmax)
 
 
 @pytest.fixture(scope="module")
@@ -159,5 +163,5 @@ def test_diamond_batch16_fp32_mfma(diamond_batch):
         dEo = abs(E32[i] - ref["E_G"])
         dJo = float(np.max(np.abs(J32[i] - ref["J"])))
         print(f"diamond batch FP32-MFMA density {i} vs oracle: dE={dEo:.2e} max|dJ|={dJo:.2e}", flush=True)
-        assert dEo <= 1e-7 and dJo <= 1e-7
-    assert dE <= 1e-7 and dJ <= 1e-7
+        assert dEo <= 1e-9 and dJo <= 5e-9
+    assert dE <= 1e-9 and dJ <= 5e-9

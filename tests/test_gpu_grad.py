@@ -96,7 +96,7 @@ def test_grad_fp32_form():
     g32, _, _ = grad_gpu(p, D, pw().PWDF_FP32_MFMA)
     rel = np.max(np.abs(g32 - g64)) / np.max(np.abs(g64))
     print(f"FP32 gradient rel err {rel:.2e}", flush=True)
-    assert rel <= 1e-5
+    assert rel <= 1e-8
 
 
 def test_autograd_function():
@@ -168,4 +168,4 @@ def test_molecular_crystal_finite_differences(crystal):
     print(f"molecular crystal FP32-MFMA: |E32-E64|={abs(E32 - E64):.2e} worst FD err {worst32:.2e} "
           f"(bar {bar:.2e}); gradient vs FP64 rel {rel:.2e}", flush=True)
     assert worst32 <= bar
-    assert rel <= 1e-4
+    assert rel <= 1e-6

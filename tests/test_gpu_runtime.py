@@ -76,7 +76,12 @@ def test_graph_replay_matches_eager(prec):
         print(f"prec={prec} replay {r}: max|dJ|={float((Jr - Je).abs().max()):.1e}", flush=True)
         assert torch.equal(Jr, Je), f"replay {r}: J differs from the eager call"
         assert torch.equal(Er, Ee), f"replay {r}: E_J differs from the eager call"
-        assert torch.equal(Jo[0], Je[0])
+        if prec == 0:
+            assert torch.equal(Jo[0], Je[0])
+        else:
+            # max_ndm = 1 gives the FP32-MFMA form other column layouts and chunks:
+            # equal up to that form's rounding
+            assert float((Jo[0] - Je[0]).abs().max()) <= 1e-9 * float(Je[0].abs().max())
 
 
 def test_graph_recaptures_on_new_buffers():
