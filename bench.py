@@ -4,24 +4,27 @@
 One step = one batched long-range J build of 16 densities on the rock-salt
 slab (32 atoms, a = 7.96 Bohr, 2x2 surface cell, 4 layers, 20 Bohr vacuum;
 8s5p3d1f uncontracted shells per element; 6x6x1 Gamma-centred k-mesh;
-omega 0.4, screening 1e-12): D(k) of every density in HBM -> J(k) and E_J in
-HBM, i.e. the phase sum D(k) -> D(L), per-pair transforms, rho(G), V(G) and
-E_J, J from V, back transform and J(L) -> J(k).  The headline form is the
-FP32-MFMA one (pair-G tiles in FP32 on the matrix cores; phase sums,
+omega 0.4, screening 1e-12 with per-pair G cuts): D(k) of every density in
+HBM -> J(k) and E_J in HBM, i.e. the phase sum D(k) -> D(L), per-pair
+transforms, rho(G), V(G) and E_J, J from V, back transform and J(L) -> J(k).
+The headline form is the FP32-MFMA one (pair-G tiles in FP32 on the matrix
+cores, the head of the G set in FP64 tiles on FP64 MFMA; phase sums,
 transforms and energies in FP64), launched as the captured graph after an
 untimed autotune, with J(k) written on the pair support only, packed (the
-layout PWDF_JK_PACKED: [density][k][support element]).  `value` is density J builds/s (16 per step) from a region timed
-with torch.cuda.synchronize() on both sides.
+layout PWDF_JK_PACKED: [density][k][support element]).  `value` is density J
+builds/s (16 per step) from a region timed with torch.cuda.synchronize() on
+both sides.
 
 Beside it, on the same slab and densities: the FP64 form with one density per
-call (the plain form; the ratio of the two is the batched-FP32 speedup), the
-errors of both against each other and against the FP64 oracle; then (child
-process, so that a failure there is reported in "extras_error" instead of
-ending the run) the FP64 form on the monoclinic molecular crystal and on the
-diamond-like cell.  A second, profiled region of the headline form brackets
-every launch with HIP events on its stream and gives each kernel's average
-duration for the roofline entry.  The FP64 CPU oracle, timed on the host cores
-for one slab density, is the baseline.
+call (the plain form; the ratio of the two is the batched-FP32 speedup) and
+with 16 per call, the FP32-MFMA batch without per-pair cuts, the errors
+against each other and against the FP64 oracle; then (child process, so that a
+failure there is reported in "extras_error" instead of ending the run) the FP64
+form on the monoclinic molecular crystal and on the diamond-like cell.  A
+second, profiled region of the headline form brackets every launch with HIP
+events on its stream and gives each kernel's average duration for the roofline
+entry.  The FP64 CPU oracle, timed on the host cores for one slab density, is
+the baseline.
 """
 import argparse
 import hashlib
@@ -36,9 +39,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "long-range J builds/s + pair-G evals/s, FP32-MFMA vs FP64 at <=1e-7 Eh"
-PEAK = {"fp64_valu_tflops": 78.6, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
+PEAK = {"fp64_valu_tflops": 78.6, "fp64_mfma_tflops": 78.6, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
 CSRC = os.path.join(ROOT, "paper_2509_16460_amd", "csrc")
-WORKLOAD = "rocksalt_slab32_8s5p3d1f_k661_w0.4_ndm16"
+WORKLOAD = "rocksalt_slab32_8s5p3d1f_k661_w0.4_ndm16_paircut"
 NDM = 16
 
 
@@ -58,11 +61,11 @@ def flops_per_unit(name):
     (pair, G of the half space, density) of class L in the factored form (an
     (L+1)-term complex multiply-add along the G line plus the separable
     exponential/phase product).  The FP64 launches rho_lo/hi and jpass_lo/hi
-    count their units in these flops already; the per-class FP32-MFMA launches
-    count pair-G evaluations."""
+    count their units in these flops already; the per-class MFMA launches (FP32
+    tiles, and FP64 tiles of the head of the G set) count pair-G evaluations."""
     if name in ("rho_lo", "rho_hi", "jpass_lo", "jpass_hi"):
         return 1.0
-    for pre in ("rho_mfma_L", "jpass_mfma_L"):
+    for pre in ("rho_mfma_L", "jpass_mfma_L", "rho_head_L", "jpass_head_L"):
         if name.startswith(pre):
             L = int(name[len(pre):])
             return 8 * (L + 1) + 4
@@ -85,8 +88,9 @@ def roofline_entry(name, rec, traffic):
         ent.update(bound="hbm", achieved=ach, peak=PEAK["hbm_gbs"], unit="GB/s", frac=ach / PEAK["hbm_gbs"],
                    traffic=traffic, bytes_per_unit=bpu, algorithmic_bytes_per_launch=units * bpu)
     elif fpu is not None:
-        mfma = "mfma" in name
-        peak = PEAK["fp32_mfma_tflops"] if mfma else PEAK["fp64_valu_tflops"]
+        mfma = "mfma" in name or "head" in name
+        peak = PEAK["fp32_mfma_tflops"] if "mfma" in name else (
+            PEAK["fp64_mfma_tflops"] if "head" in name else PEAK["fp64_valu_tflops"])
         ach = units * fpu / avg_s / 1e12
         ent.update(bound="mfma" if mfma else "alu", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
                    traffic=traffic, flops_per_unit=fpu, algorithmic_flops_per_launch=units * fpu)
@@ -162,8 +166,8 @@ def extras(args):
 
     torch.cuda.set_device(0)
     out = {}
-    for cfg, name in ((5, "molecular_crystal48_k333_w0.5_fp64"), (2, "diamond8_k444_w0.4_fp64")):
-        prob = synth.config_problem(cfg)
+    for cfg, name in ((5, "molecular_crystal48_k333_w0.5_fp64_paircut"), (2, "diamond8_k444_w0.4_fp64_paircut")):
+        prob = synth.config_problem(cfg).with_(pair_gcut=1)
         D = synth.make_density(prob, 1000 * cfg)
         Dt = torch.from_numpy(D[None]).cuda()
         ctx, J, E, ms, st, prof = single_fp64(torch, pwdf, prob, Dt, args.steps, args.warmup)
@@ -178,6 +182,42 @@ def extras(args):
     print(json.dumps(out), flush=True)
 
 
+def rocprof_summary(paths, last):
+    """Markdown table per kernel of rocprofv3 CSV output, over the last `last`
+    dispatches of each kernel (0: all; the timed and profiled regions of a run
+    come after its autotune): from *_kernel_trace.csv the dispatch count and
+    average duration in us; from *_counter_collection.csv the average of every
+    counter per dispatch (FETCH_SIZE / WRITE_SIZE in KiB, as rocprofv3 reports
+    them)."""
+    import csv
+    import re
+    disp = {}
+    for path in paths:
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                name = r.get("Kernel_Name") or ""
+                m = re.search(r"pwdf::(k_\w+)(<[^>]*>)?", name)
+                key = (m.group(1) + (m.group(2) or "")) if m else name[:48]
+                dd = disp.setdefault(key, {})
+                e = dd.setdefault(int(r["Dispatch_Id"]), {})
+                e["dur_us"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+                if "Counter_Name" in r:
+                    e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    rows = {}
+    for key, dd in disp.items():
+        ids = sorted(dd)[-last:] if last else sorted(dd)
+        cols = {c for i in ids for c in dd[i]}
+        rows[key] = {"dispatches": len(ids)}
+        for c in cols:
+            vals = [dd[i][c] for i in ids if c in dd[i]]
+            rows[key][c] = sum(vals) / len(vals)
+    cols = ["dispatches", "dur_us"] + sorted({c for d in rows.values() for c in d} - {"dispatches", "dur_us"})
+    print("| kernel | " + " | ".join(cols) + " |")
+    print("|---" * (len(cols) + 1) + "|")
+    for k in sorted(rows, key=lambda k: -rows[k]["dur_us"] * rows[k]["dispatches"]):
+        print(f"| `{k}` | " + " | ".join(f"{rows[k][c]:.4g}" if c in rows[k] else "" for c in cols) + " |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,9 +226,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the molecular crystal and diamond cell")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="also run one plain device copy of this size (counter calibration)")
+                    help="also run one plain streaming kernel over this size (counter calibration)")
     ap.add_argument("--extras-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--only-headline", action="store_true",
+                    help="run the headline FP32-MFMA batch only (autotune, timed and profiled regions): the "
+                         "command the rocprofv3 summaries under profiles/ are taken with")
+    ap.add_argument("--rocprof-summary", nargs="+", metavar="CSV",
+                    help="print a per-kernel summary of rocprofv3 CSV output (kernel_trace or "
+                         "counter_collection files) instead of benchmarking")
+    ap.add_argument("--last", type=int, default=0, help="with --rocprof-summary: the last N dispatches per kernel")
     args = ap.parse_args()
+    if args.rocprof_summary:
+        rocprof_summary(args.rocprof_summary, args.last)
+        return
     if args.extras_only:
         extras(args)
         return
@@ -203,7 +253,7 @@ def main():
 
     torch.cuda.set_device(0)
     log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)  # noqa: E731
-    prob = synth.config_problem(4)
+    prob = synth.config_problem(4).with_(pair_gcut=1)
     log("slab overlap for the density scale")
     Sk = synth.overlap_k(prob)
     Db = synth.make_densities_torch(prob, NDM, 1000 * prob.seed, Sk)
@@ -211,10 +261,13 @@ def main():
     Eb = torch.empty(NDM, dtype=torch.float64, device="cuda")
 
     if args.calib_copy_mib > 0:
+        # a plain streaming kernel of known traffic (reads and writes the size
+        # given once each; torch's neg kernel, found by name in the counter
+        # output), for the scale of the FETCH_SIZE / WRITE_SIZE counters
         n = args.calib_copy_mib * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.neg(a, out=b)
         torch.cuda.synchronize()
         del a, b
 
@@ -239,6 +292,27 @@ def main():
               if k != dominant and (flops_per_unit(k) or bytes_per_unit(k))][:5]
     del c32
     torch.cuda.empty_cache()
+
+    if args.only_headline:
+        print(json.dumps({"metric": METRIC, "value": NDM * 1e3 / ms, "unit": "J builds/s", "ms_per_step": ms,
+                          "config": {"workload": WORKLOAD}, "roofline": roof, "kernels": kernels}), flush=True)
+        return
+
+    # side legs: the FP32-MFMA batch without per-pair cuts, the FP64 form with 16
+    # densities per call (no autotune, graph replay)
+    def side(pr, prec):
+        c = pwdf.LongRangeJ(pr, precision=prec, max_ndm=NDM)
+        c.set_jk_layout(pwdf.PWDF_JK_PACKED)
+        J = torch.empty((NDM, pr.nk, c.stats()["jk_support"]), dtype=Db.dtype, device="cuda")
+        E = torch.empty(NDM, dtype=torch.float64, device="cuda")
+        t = timed(torch, lambda: c.build_j(Db, J, E, graph=True), max(5, args.steps // 2), args.warmup)
+        r = {"ms_per_step": t, "builds_per_s": NDM * 1e3 / t, "pair_G_evals_per_density_build": c.stats()["pairG_evals"]}
+        del c, J, E
+        torch.cuda.empty_cache()
+        return r
+    log("side legs: FP32-MFMA batch without cuts, FP64 batch")
+    nocut32 = side(prob.with_(pair_gcut=0), pwdf.PWDF_FP32_MFMA)
+    batch64 = side(prob, pwdf.PWDF_FP64)
 
     # the plain form on the same slab: FP64, one density per call
     log("FP64 single density: autotune + timed region")
@@ -265,11 +339,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "atoms": prob.natm, "nbf": prob.nbf, "nk": prob.nk, "omega": prob.omega,
                    "nG": st["nG"], "unique_pairs": st["npairs"], "ndm_per_step": NDM,
-                   "precision": "fp32_mfma (pair-G tiles FP32 on MFMA; phase sums, transforms, energy FP64)",
+                   "precision": "fp32_mfma (pair-G tiles FP32 on MFMA, head of the G set FP64 on MFMA; phase "
+                                "sums, transforms, energy FP64)",
+                   "screening": "eps 1e-12, per-pair G cuts", "nG_head": st["nG_head"],
                    "jk_layout": "packed support", "jk_support_elements": st["jk_support"],
                    "launch": "graph replay, autotuned", "seg_len": st["seg_len"]},
         "pair_G_evals_per_s": st["pairG_evals"] * dens_per_s,
         "pair_G_evals_per_density_build": st["pairG_evals"],
+        "pair_G_fp64_head_fraction": st["pairG_head"] / max(1.0, st["pairG_evals"]),
+        "fp32_batch_without_pair_cuts": nocut32,
+        "fp64_batch16": batch64,
         "roofline": roof,
         "roofline_next": second,
         "kernels": kernels,

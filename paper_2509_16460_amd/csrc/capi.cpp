@@ -190,7 +190,7 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
   constexpr double kMinGroupWaves = 1024.0;
   constexpr double kMinClassWaves = 2048.0;
   constexpr int kMaxFp32Run = 512;
-  constexpr int kHeadWaves = 1024, kHeadMinPairs = 32;
+  constexpr int kHeadWaves = 2048, kHeadMinPairs = 32;
   double gR[2] = {0.0, 0.0}, gJ[2] = {0.0, 0.0};
   for (int L = 0; L <= kMaxLsum; ++L) {
     gR[L > 2] += wR[L];
@@ -226,12 +226,13 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
     // kHeadWaves waves per class launch and at least one LDS tile of pairs per
     // chunk; J moments over all head points in one chunk
     if (d.npts_head > 0) {
-      const int waves_per_chunk = 4 * ((d.npts_head + 63) / 64);
+      const int waves_per_chunk = 4 * ((d.npts_head + 63) / 64) * tile_groups(d.ncols32[L] / 16);
       const int want = std::max(1, kHeadWaves / waves_per_chunk);
       int ppc = std::max(kHeadMinPairs, (np + want - 1) / want);
       d.rho_h_ppc[L] = ppc;
       d.rho_h_chunks[L] = (np + ppc - 1) / ppc;
-      rows_h += d.rho_h_chunks[L];
+      // one partial row per chunk and N-tile group (the groups run as blocks of their own)
+      rows_h += d.rho_h_chunks[L] * tile_groups(d.ncols32[L] / 16);
     }
     int ch = (int)std::lround(tR[L > 2] * (wR[L] / gR[L > 2]) * tn.mrho[L] / rho_waves_per_chunk);
     // FP32-MFMA form: every class launch gets at least kMinClassWaves waves (as

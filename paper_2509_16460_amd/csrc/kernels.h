@@ -81,7 +81,7 @@ struct Dev {
   const int *slot_hidx;
   double2 *parth;
   int nrows_h, rows_per_group_h;
-  int rho_h_chunks[kMaxLsum + 1], rho_h_ppc[kMaxLsum + 1], rho_h_row0[kMaxLsum + 1];
+  int rho_h_chunks[kMaxLsum + 1], rho_h_ppc[kMaxLsum + 1], rho_h_row0[kMaxLsum + 1];  // rows: chunk x tile group
   int j_chunks32[kMaxLsum + 1], j_spc32[kMaxLsum + 1];  // FP32 J pass over the other points
   // gradient: moments of degree L+1 per class, per-block centre gradients,
   // per-atom lists of (block, 0 = shell a / 3 = shell b)
@@ -109,6 +109,18 @@ constexpr size_t kStaticScratchBytes = size_t(64) << 20;
 // device address of that array on `device` (looked up once per device)
 hipError_t static_scratch(int device, void **ptr);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
+
+// MFMA-tile kernels: N-tiles (16 columns of (k, dm)) per S evaluation; ntiles
+// are split into ceil(ntiles / 8) groups of equal size (at most 8 tiles each),
+// the last group's missing tiles being zero columns
+inline int group_tiles(int ntiles) {
+  const int ng = (ntiles + 7) / 8;
+  return (ntiles + ng - 1) / ng;
+}
+inline int tile_groups(int ntiles) {
+  const int g = group_tiles(ntiles);
+  return (ntiles + g - 1) / g;
+}
 
 // FP32-MFMA form (per class L)
 hipError_t launch_rho_mfma_L(const Dev &d, int L, int ndm, hipStream_t st);

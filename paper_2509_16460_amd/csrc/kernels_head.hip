@@ -48,10 +48,11 @@ __device__ __forceinline__ void s_direct64(const GPoint &pt, const PairF &f, dou
 
 // ---------------------------------------------------------------------------
 // rho over the head points, K = pairs.  A workgroup = 4 waves = 64 points (16 per
-// wave as the MFMA rows) and one chunk of pairs of class L, staged in LDS in
-// tiles of kQTileH pairs with the FP64 coefficient columns of the current N-tile
-// group (the transform's FP64 output in the layout of the FP32 operands,
-// [pair][k * ndmp + dm]).  Output: the chunk's partial row [dm][row][head point].
+// wave as the MFMA rows), one chunk of pairs of class L and one group of NTG
+// N-tiles (grid z); the pairs are staged in LDS in tiles of kQTileH with the
+// group's FP64 coefficient columns (the transform's FP64 output in the layout of
+// the FP32 operands, [pair][k * ndmp + dm]).  Output: the partial row of (chunk,
+// group), [dm][row][head point].
 // ---------------------------------------------------------------------------
 constexpr int kQTileH = 32;  // LDS: 32 KB of coefficient columns at NTG = 8
 
@@ -62,104 +63,103 @@ __global__ __launch_bounds__(256) void k_rho_head(const GPoint *__restrict__ pts
                                                   int ndmp, int ndm, double2 *__restrict__ parth, int row0,
                                                   int nrows_h) {
   constexpr int NT = nherm(L);
+  constexpr int PER = kQTileH * NTG * 16 / 256;  // staged columns per thread and tile
+  static_assert(PER * 256 == kQTileH * NTG * 16, "tile size");
   __shared__ PairF sh[kQTileH];
   __shared__ double sc[kQTileH * NTG * 16];
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, g4 = lane >> 4;
-  const int chunk = blockIdx.y;
+  const int chunk = blockIdx.y, grp = blockIdx.z;
   const int p0 = Lp0 + chunk * ppc, p1 = min(Lp1, p0 + ppc);
   const int pt0 = blockIdx.x * 64 + w * 16;
   const GPoint ptA = pts[min(pt0 + r16, npts - 1)];
   const int ntiles = ncols >> 4;
-  double2 *out = parth + ((size_t)min(r16, ndm - 1) * nrows_h + row0 + chunk) * npts;
-  for (int ng = 0; ng < ntiles; ng += NTG) {
-    const int ntg = min(NTG, ntiles - ng);
-    d4 are[NTG], aim[NTG];
+  const int ng = grp * NTG, ntg = min(NTG, ntiles - ng);
+  d4 are[NTG], aim[NTG];
 #pragma unroll
-    for (int n = 0; n < NTG; ++n) {
-      are[n] = d4{0.0, 0.0, 0.0, 0.0};
-      aim[n] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int n = 0; n < NTG; ++n) {
+    are[n] = d4{0.0, 0.0, 0.0, 0.0};
+    aim[n] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  for (int t0 = p0; t0 < p1; t0 += kQTileH) {
+    const int nq = min(kQTileH, p1 - t0);
+    __syncthreads();
+    if (tid < nq) sh[tid] = pair_f(hot[t0 + tid]);
+    // the group's columns of the tile's pairs, loads issued before the stores;
+    // columns of densities past ndm were not written by this call's transform
+    // and are masked (the FP64 buffer is not cleared)
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = tid + u * 256;
+      const int q = i / (NTG * 16), c = i - q * (NTG * 16);
+      const int col = ng * 16 + c;
+      const int k = col / ndmp, dm = col - k * ndmp;
+      v[u] = q < nq && c < ntg * 16 && k < NT && dm < ndm ? dh64[d_off + (size_t)(t0 + q - Lp0) * ncols + col] : 0.0;
     }
-    for (int t0 = p0; t0 < p1; t0 += kQTileH) {
-      const int nq = min(kQTileH, p1 - t0);
-      __syncthreads();
-      for (int i = tid; i < nq; i += 256) sh[i] = pair_f(hot[t0 + i]);
-      // columns of densities past ndm were not written by this call's transform:
-      // masked (the FP64 buffer is not cleared)
-      for (int i = tid; i < nq * NTG * 16; i += 256) {
-        const int q = i / (NTG * 16), c = i - q * (NTG * 16);
-        const int col = ng * 16 + c;
-        const int k = col / ndmp, dm = col - k * ndmp;
-        sc[i] = c < ntg * 16 && k < NT && dm < ndm ? dh64[d_off + (size_t)(t0 + q - Lp0) * ncols + col] : 0.0;
-      }
-      __syncthreads();
-      for (int q0 = 0; q0 < nq; q0 += 4) {
-        const int q = q0 + g4 < nq ? q0 + g4 : nq - 1;
-        const bool vq = q0 + g4 < nq && ptA.g2 <= sh[q].gc2;
-        double Sr, Si;
-        s_direct64(ptA, sh[q], Sr, Si);
-        Sr = vq ? Sr : 0.0;
-        Si = vq ? Si : 0.0;
-        const double *bq = sc + q * (NTG * 16) + r16;
 #pragma unroll
-        for (int n = 0; n < NTG; ++n) {
-          const double b = bq[n * 16];
-          are[n] = mfma4d(Sr, b, are[n]);
-          aim[n] = mfma4d(Si, b, aim[n]);
-        }
-      }
-    }
-    // epilogue: lane holds R[point 4*i + g4][column r16]
-    double accr[4], acci[4];
+    for (int u = 0; u < PER; ++u) sc[tid + u * 256] = v[u];
+    __syncthreads();
+    for (int q0 = 0; q0 < nq; q0 += 4) {
+      const int q = q0 + g4 < nq ? q0 + g4 : nq - 1;
+      const bool vq = q0 + g4 < nq && ptA.g2 <= sh[q].gc2;
+      double Sr, Si;
+      s_direct64(ptA, sh[q], Sr, Si);
+      Sr = vq ? Sr : 0.0;
+      Si = vq ? Si : 0.0;
+      const double *bq = sc + q * (NTG * 16) + r16;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) accr[i] = acci[i] = 0.0;
-    GPoint pr[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) pr[i] = pts[min(pt0 + 4 * i + g4, npts - 1)];
-#pragma unroll
-    for (int n = 0; n < NTG; ++n) {
-      if (n >= ntg) break;
-      const int c = (ng + n) * 16 + r16;
-      const int k = c / ndmp;
-      const bool vk = k < NT;
-      int ka = 0, kb = 0, kc = 0;
-      if (vk) mono_of(k, ka, kb, kc);
-      const bool odd = (ka + kb + kc) & 1;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const double mono =
-            vk ? ipow((double)pr[i].nu, ka) * ipow((double)pr[i].nv, kb) * ipow((double)pr[i].nw, kc) : 0.0;
-        // even |k|: R; odd |k|: i R (the sign of (-i)^|k| is in dhat)
-        double cr = are[n][i], ci = aim[n][i];
-        if (odd) {
-          const double tr = -ci;
-          ci = cr;
-          cr = tr;
-        }
-        cr *= mono;
-        ci *= mono;
-        for (int off = ndmp; off < 16; off <<= 1) {
-          cr += __shfl_xor(cr, off, 64);
-          ci += __shfl_xor(ci, off, 64);
-        }
-        accr[i] += cr;
-        acci[i] += ci;
+      for (int n = 0; n < NTG; ++n) {
+        const double b = bq[n * 16];
+        are[n] = mfma4d(Sr, b, are[n]);
+        aim[n] = mfma4d(Si, b, aim[n]);
       }
     }
-    if (r16 < ndm) {
+  }
+  // epilogue: lane holds R[point 4*i + g4][column r16]
+  double accr[4], acci[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int pi = pt0 + 4 * i + g4;
-        if (pi >= npts) continue;
-        double2 v = make_double2(accr[i], acci[i]);
-        if (ng > 0) {
-          const double2 o = out[pi];
-          v.x += o.x;
-          v.y += o.y;
-        }
-        out[pi] = v;
+  for (int i = 0; i < 4; ++i) accr[i] = acci[i] = 0.0;
+  GPoint pr[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) pr[i] = pts[min(pt0 + 4 * i + g4, npts - 1)];
+#pragma unroll
+  for (int n = 0; n < NTG; ++n) {
+    if (n >= ntg) break;
+    const int c = (ng + n) * 16 + r16;
+    const int k = c / ndmp;
+    const bool vk = k < NT;
+    int ka = 0, kb = 0, kc = 0;
+    if (vk) mono_of(k, ka, kb, kc);
+    const bool odd = (ka + kb + kc) & 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double mono =
+          vk ? ipow((double)pr[i].nu, ka) * ipow((double)pr[i].nv, kb) * ipow((double)pr[i].nw, kc) : 0.0;
+      // even |k|: R; odd |k|: i R (the sign of (-i)^|k| is in the coefficients)
+      double cr = are[n][i], ci = aim[n][i];
+      if (odd) {
+        const double tr = -ci;
+        ci = cr;
+        cr = tr;
       }
+      cr *= mono;
+      ci *= mono;
+      for (int off = ndmp; off < 16; off <<= 1) {
+        cr += __shfl_xor(cr, off, 64);
+        ci += __shfl_xor(ci, off, 64);
+      }
+      accr[i] += cr;
+      acci[i] += ci;
+    }
+  }
+  if (r16 < ndm) {
+    double2 *out = parth + ((size_t)r16 * nrows_h + row0 + chunk * gridDim.z + grp) * npts;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int pi = pt0 + 4 * i + g4;
+      if (pi < npts) out[pi] = make_double2(accr[i], acci[i]);
     }
   }
 }
@@ -197,23 +197,38 @@ __global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ p
   d4 acc[NTW];
 #pragma unroll
   for (int n = 0; n < NTW; ++n) acc[n] = d4{0.0, 0.0, 0.0, 0.0};
+  constexpr int PER = kPTile * NTW * 16 / 256;  // W' elements per thread and tile
+  static_assert(PER * 256 == kPTile * NTW * 16, "tile size");
   for (int t0 = 0; t0 < npts; t0 += kPTile) {
     const int nt = min(kPTile, npts - t0);
     __syncthreads();
     if (tid < nt) sp[tid] = pts[t0 + tid];
-    for (int i = tid; i < nt * NTW * 16; i += 256) {
+    __syncthreads();
+    // V loads of the thread's elements issued together, then W' formed
+    double2 v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = tid + u * 256;
       const int q = i / (NTW * 16), c = i - q * (NTW * 16);
       const int col = (nt0 * 16) + c;
       const int k = col / ndmp, dm = col - k * ndmp;
+      v[u] = q < nt && c < ntw * 16 && k < NT && dm < ndm ? Vc[(size_t)dm * nslot + sp[q].slot]
+                                                           : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = tid + u * 256;
+      const int q = i / (NTW * 16), c = i - q * (NTW * 16);
+      const int col = (nt0 * 16) + c;
+      const int k = col / ndmp;
       double r = 0.0, im = 0.0;
-      if (c < ntw * 16 && k < NT && dm < ndm) {
-        const GPoint pt = pts[t0 + q];
+      if (q < nt && k < NT) {
+        const GPoint pt = sp[q];
         int a, b, cc;
         mono_of(k, a, b, cc);
         const double mono = ipow((double)pt.nu, a) * ipow((double)pt.nv, b) * ipow((double)pt.nw, cc);
-        const double2 v = Vc[(size_t)dm * nslot + pt.slot];
-        r = mono * v.x;
-        im = mono * v.y;
+        r = mono * v[u].x;
+        im = mono * v[u].y;
         if ((a + b + cc) & 1) {  // -i (r + i im) = im - i r
           const double tr = im;
           im = -r;
@@ -264,7 +279,7 @@ __global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ p
 
 template <int L, int NTG>
 static hipError_t rho_head_ntg(const Dev &d, int ndm, hipStream_t st) {
-  dim3 grid((unsigned)((d.npts_head + 63) / 64), d.rho_h_chunks[L]);
+  dim3 grid((unsigned)((d.npts_head + 63) / 64), d.rho_h_chunks[L], (unsigned)tile_groups(d.ncols32[L] / 16));
   hipLaunchKernelGGL((k_rho_head<L, NTG>), grid, dim3(256), 0, st, d.pts, d.npts_head, d.hot_cut, d.L_p0[L], d.L_p1[L],
                      d.rho_h_ppc[L], d.dhat, d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.parth, d.rho_h_row0[L],
                      d.nrows_h);

@@ -41,12 +41,4 @@ struct PairF {
 
 __device__ __forceinline__ PairF pair_f(const PairHot &h) { return {h.inv4p * kLog2e, h.fu, h.fv, h.fw, h.gc2}; }
 
-// N-tiles per S evaluation: ntiles split into ceil(ntiles / 8) groups of equal
-// size (at most 8 tiles, accumulators 2 x 8 x 4 registers); the last group's
-// missing tiles are zero columns
-inline int group_tiles(int ntiles) {
-  const int ng = (ntiles + 7) / 8;
-  return (ntiles + ng - 1) / ng;
-}
-
 }  // namespace pwdf
