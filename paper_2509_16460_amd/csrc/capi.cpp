@@ -149,48 +149,42 @@ void drop_graph(pwdf_ctx *c) {
 // which sums them, than they save.)  A rho chunk holds at least 4 pairs (the 4
 // waves of its blocks share them).
 // The tune multipliers scale the chunk counts per class.
-void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
+// columns of a partial row: slots (FP64 form), points of the tail (FP32-MFMA form)
+size_t part_cols(const Dev &d) { return d.fp32 ? (size_t)std::max(1, d.npts - d.npts_head) : (size_t)d.nslot; }
+
+// Host-side work lists of the FP32-MFMA form (see Dev), uploaded by setup_device.
+struct WorkLists {
+  std::vector<int4> rho_items, j_items;
+  std::vector<int> rows_of_block, jn_of, slot_pidx;
+};
+
+// FP64 form: segment chunks of both passes.  In the FP32-MFMA form these give
+// the segment chunks of the gradient's FP64 force moments; its own passes are
+// laid out by fp32_shapes.
+void choose_shapes_fp64(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
   const int SEG = p.seg_len;
-  // FP32-MFMA form: one launch per class, the classes overlapping on the
-  // internal streams; its waves hold 90-154 VGPRs (3-5 per SIMD)
-  const double target = d.fp32 ? 8192.0 : 4096.0;
+  const double target = 4096.0;
   // the low-L classes share S across d.ndb densities per block (at most 32 / SEG,
   // chosen at launch); chunk counts are those of one density block (a batch
   // adds blocks along the density axis of the grid)
   d.ndb = max_ndm >= 4 ? 4 : (max_ndm >= 2 ? 2 : 1);
   d.rho_bs = 256;  // 64 segments x 4 waves sharing them
   double wsumR = 0.0, wsumJ = 0.0, wR[kMaxLsum + 1], wJ[kMaxLsum + 1];
-  int jzg[kMaxLsum + 1];  // FP32-MFMA J pass: N-tile groups (grid z) per pair block
   for (int L = 0; L <= kMaxLsum; ++L) {
     const int np = p.L_p1[L] - p.L_p0[L];
-    double costR = 2.0 * L + 10.0 + (70.0 + nherm(L)) / SEG, costJ = costR;
-    jzg[L] = 1;
-    if (d.fp32) {
-      // per K-step of a wave (16 G points x 4 pairs): the pair factor is evaluated
-      // once per group of N-tiles (~120 VALU cycles) and each N-tile of 16 (k, dm)
-      // columns costs two MFMAs of 32 cycles; both passes use ceil(nt / 8) groups
-      // of equal size (the last one padded)
-      const int nt = std::max(1, d.ncols32[L] / 16);
-      const int ngr = (nt + 7) / 8, ntg = (nt + ngr - 1) / ngr;
-      jzg[L] = ngr;
-      costR = costJ = ngr * (120.0 + 64.0 * ntg);
-    }
-    wR[L] = np > 0 ? (double)np * costR : 0.0;
-    wJ[L] = np > 0 ? (double)((np + 63) / 64) * 64.0 * costJ : 0.0;
+    const double cost = 2.0 * L + 10.0 + (70.0 + nherm(L)) / SEG;
+    wR[L] = np > 0 ? (double)np * cost : 0.0;
+    wJ[L] = np > 0 ? (double)((np + 63) / 64) * 64.0 * cost : 0.0;
     wsumR += wR[L];
     wsumJ += wJ[L];
   }
-  // rho: a chunk spans the G set in groups of 64 segments (FP64) or 64 points
-  // (FP32-MFMA form), four waves each; J: the FP64 form splits the segments
-  // into chunks, the FP32-MFMA form the points
-  const int ngi = d.fp32 ? (int)p.pts.size() - d.npts_head : p.nseg();
+  // rho: a chunk spans the G set in groups of 64 segments, four waves each; J:
+  // the segments are split into chunks
+  const int ngi = p.nseg();
   const int rho_waves_per_chunk = std::max(4, ((ngi + 63) / 64) * 4);
   wsumR = std::max(wsumR, 1.0);  // no pairs: every class is skipped below
   wsumJ = std::max(wsumJ, 1.0);
   constexpr double kMinGroupWaves = 1024.0;
-  constexpr double kMinClassWaves = 2048.0;
-  constexpr int kMaxFp32Run = 512;
-  constexpr int kHeadWaves = 2048, kHeadMinPairs = 32;
   double gR[2] = {0.0, 0.0}, gJ[2] = {0.0, 0.0};
   for (int L = 0; L <= kMaxLsum; ++L) {
     gR[L > 2] += wR[L];
@@ -198,23 +192,17 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
   }
   double tR[2], tJ[2];  // waves of each group
   for (int g = 0; g < 2; ++g) {
-    tR[g] = target * gR[g] / wsumR;
-    if (!d.fp32) tR[g] = std::max(tR[g], kMinGroupWaves);
+    tR[g] = std::max(target * gR[g] / wsumR, kMinGroupWaves);
     tJ[g] = target * gJ[g] / wsumJ;
     gR[g] = std::max(gR[g], 1.0);
     gJ[g] = std::max(gJ[g], 1.0);
   }
-  int rows = 0, rows_h = 0;
+  int rows = 0;
   int64_t yoff = 0;
   for (int L = 0; L <= kMaxLsum; ++L) {
     int np = p.L_p1[L] - p.L_p0[L];
     d.rho_row0[L] = rows;
-    d.rho_h_row0[L] = rows_h;
     d.yhat_off[L] = yoff;
-    d.rho_h_chunks[L] = 0;
-    d.rho_h_ppc[L] = 1;
-    d.j_chunks32[L] = 0;
-    d.j_spc32[L] = 1;
     if (np <= 0) {
       d.rho_chunks[L] = 0;
       d.rho_ppc[L] = 1;
@@ -222,57 +210,21 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
       d.j_spc[L] = 1;
       continue;
     }
-    // the head (FP64 MFMA): rho in chunks of pairs (one partial row each), about
-    // kHeadWaves waves per class launch and at least one LDS tile of pairs per
-    // chunk; J moments over all head points in one chunk
-    if (d.npts_head > 0) {
-      const int waves_per_chunk = 4 * ((d.npts_head + 63) / 64) * tile_groups(d.ncols32[L] / 16);
-      const int want = std::max(1, kHeadWaves / waves_per_chunk);
-      int ppc = std::max(kHeadMinPairs, (np + want - 1) / want);
-      d.rho_h_ppc[L] = ppc;
-      d.rho_h_chunks[L] = (np + ppc - 1) / ppc;
-      // one partial row per chunk and N-tile group (the groups run as blocks of their own)
-      rows_h += d.rho_h_chunks[L] * tile_groups(d.ncols32[L] / 16);
-    }
     int ch = (int)std::lround(tR[L > 2] * (wR[L] / gR[L > 2]) * tn.mrho[L] / rho_waves_per_chunk);
-    // FP32-MFMA form: every class launch gets at least kMinClassWaves waves (as
-    // many as chunks of 4 pairs allow), else a small class, whose pairs carry
-    // many N-tiles, runs as a few long waves
-    if (d.fp32) {
-      ch = std::max(ch, (int)std::lround(kMinClassWaves * tn.mrho[L] / rho_waves_per_chunk));
-      // FP32 accumulation runs over at most kMaxFp32Run pairs (one chunk); the
-      // chunks' partial rows are added in FP64
-      ch = std::max(ch, (np + kMaxFp32Run - 1) / kMaxFp32Run);
-    }
     ch = std::max(1, std::min((np + 3) / 4, ch));
     int ppc = (np + ch - 1) / ch;
     ch = (np + ppc - 1) / ppc;
     d.rho_chunks[L] = ch;
     d.rho_ppc[L] = ppc;
     rows += ch;
-    // active waves per chunk: a pair per lane (FP64), 16 pairs per wave and one
-    // block row per N-tile group (FP32-MFMA)
-    const int jw = d.fp32 ? 4 * ((np + 63) / 64) * jzg[L] : (np + 63) / 64;
+    const int jw = (np + 63) / 64;  // waves per chunk: a pair per lane
     int jc = (int)std::lround(tJ[L > 2] * (wJ[L] / gJ[L > 2]) * tn.mj[L] / jw);
-    if (d.fp32) {
-      jc = std::min(std::max(jc, (int)std::lround(kMinClassWaves * tn.mj[L] / jw)), (ngi + 15) / 16);
-      jc = std::max(jc, (ngi + kMaxFp32Run - 1) / kMaxFp32Run);  // FP32 runs over <= kMaxFp32Run points
-    }
     jc = std::max(1, std::min(ngi, jc));
     int spc = std::max(1, (ngi + jc - 1) / jc);
     jc = (ngi + spc - 1) / spc;  // 0 when the G set is empty
     d.j_chunks[L] = jc;
     d.j_spc[L] = spc;
-    if (d.fp32) {
-      // the FP32 chunks, then the head's chunk; the FP64 force moments of the
-      // gradient walk all segments in as many chunks
-      d.j_chunks32[L] = jc;
-      d.j_spc32[L] = spc;
-      const int jt = jc + (d.npts_head > 0 ? 1 : 0);
-      d.j_chunks[L] = jt;
-      d.j_spc[L] = std::max(1, (p.nseg() + std::max(1, jt) - 1) / std::max(1, jt));
-    }
-    yoff += (int64_t)d.j_chunks[L] * nherm(L) * np;
+    yoff += (int64_t)jc * nherm(L) * np;
   }
   // force moments of degree L+1 over the class-L pairs, same segment chunks as J
   int64_t foff = 0;
@@ -283,15 +235,131 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm) {
   }
   d.yF_size = std::max<int64_t>(1, foff);
   d.nrows = std::max(1, rows);
-  d.nrows_h = std::max(1, rows_h);
-  // first reduction stage: up to 64 groups of rows, of the FP32 rows and (head
-  // slots) of the head rows
-  d.ngroups = std::min(std::max(d.nrows, d.npts_head > 0 ? d.nrows_h : 0), 64);
+  d.ngroups = std::min(d.nrows, 64);
   d.rows_per_group = (d.nrows + d.ngroups - 1) / d.ngroups;
-  if (d.npts_head == 0) d.ngroups = (d.nrows + d.rows_per_group - 1) / d.rows_per_group;
-  d.rows_per_group_h = (d.nrows_h + d.ngroups - 1) / d.ngroups;
+  d.ngroups = (d.nrows + d.rows_per_group - 1) / d.rows_per_group;
   d.yhat_size = std::max<int64_t>(1, yoff);
   d.nred_blocks = (p.nslot() + 3) / 4;
+}
+
+// FP32-MFMA form: work items of both passes over the tail of the G set and the
+// chunks of the head (see Dev).  Both passes aim at about kItemWaves waves in
+// items of equal cost: per K-step of a wave (4 pairs or points) the pair factor
+// S costs ~120 cycles per group of N-tiles and each N-tile two MFMAs of 32
+// cycles; rho runs a class's ceil(nt / 8) groups one after the other in one item,
+// J one group per workgroup (grid z).  A run of FP32 accumulation covers at most
+// kMaxFp32Run pairs or points (the head, where the largest terms are, is in
+// FP64).  The tune multipliers scale the item counts per class.
+void fp32_shapes(const Plan &p, Dev &d, const Tune &tn, WorkLists &wl) {
+  constexpr double kItemWaves = 8192.0;
+  constexpr int kMaxFp32Run = 1024, kMinRun = 16;
+  constexpr int kHeadWaves = 2048, kHeadMinPairs = 32;
+  const int nh = d.npts_head, npts = (int)p.pts.size(), ntail = npts - nh;
+  const int nb = (ntail + 63) / 64;
+  std::vector<double> tg2(ntail);
+  for (int i = 0; i < ntail; ++i) tg2[i] = p.pts[nh + i].g2;
+  wl = WorkLists();
+  wl.slot_pidx.assign(p.nslot(), -1);
+  for (int i = 0; i < npts; ++i) wl.slot_pidx[p.pts[i].slot] = i;
+  // per class: active pairs of each point block (cut order: gc2 descending) and
+  // active points of each pair block (points: |G|^2 ascending)
+  std::vector<std::vector<int>> nact(kMaxLsum + 1), nactp(kMaxLsum + 1);
+  double WR = 0.0, WJ = 0.0, costR[kMaxLsum + 1], costJ[kMaxLsum + 1];
+  int ngr[kMaxLsum + 1];
+  for (int L = 0; L <= kMaxLsum; ++L) {
+    const int np = p.L_p1[L] - p.L_p0[L];
+    const int nt = std::max(1, d.ncols32[L] / 16);
+    ngr[L] = tile_groups(nt);
+    const int ntg = group_tiles(nt);
+    costR[L] = ngr[L] * (120.0 + 64.0 * ntg);
+    costJ[L] = 120.0 + 64.0 * ntg;
+    if (np <= 0) continue;
+    nact[L].resize(nb);
+    for (int b = 0; b < nb; ++b) {
+      const double g = tg2[64 * b];
+      // first pair (cut order) whose cut lies below the block's shortest G
+      int lo = 0, hi = np;
+      while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (p.hot_cut[p.L_p0[L] + mid].gc2 >= g) lo = mid + 1; else hi = mid;
+      }
+      nact[L][b] = lo;
+      WR += (lo / 4.0) * costR[L];
+    }
+    const int npb = (np + 63) / 64;
+    nactp[L].resize(npb);
+    for (int B = 0; B < npb; ++B) {
+      const double c = p.hot_cut[p.L_p0[L] + 64 * B].gc2;
+      nactp[L][B] = (int)(std::upper_bound(tg2.begin(), tg2.end(), c) - tg2.begin());
+      WJ += ngr[L] * (nactp[L][B] / 4.0) * costJ[L];
+    }
+  }
+  // item cost (cycles of one wave) for about kItemWaves waves, 4 per item
+  const double CR = std::max(1.0, WR / (kItemWaves / 4.0)), CJ = std::max(1.0, WJ / (kItemWaves / 4.0));
+  auto run_len = [&](double C, double cost, double mult) {
+    int r = (int)std::lround(4.0 * C / cost / std::max(mult, 1e-3));
+    r = std::max(kMinRun, std::min(kMaxFp32Run, r));
+    return (r + 3) / 4 * 4;
+  };
+  wl.rows_of_block.assign(std::max(1, nb), 0);
+  const int hc = nh > 0 ? 1 : 0;  // yhat chunk 0 holds the head's J moments
+  wl.jn_of.assign(p.hot.size(), hc);
+  int rows_h = 0;
+  int64_t yoff = 0;
+  for (int L = 0; L <= kMaxLsum; ++L) {
+    const int np = p.L_p1[L] - p.L_p0[L];
+    d.rho_item0[L] = (int)wl.rho_items.size();
+    d.j_item0[L] = (int)wl.j_items.size();
+    d.rho_nitems[L] = d.j_nitems[L] = 0;
+    d.rho_h_row0[L] = rows_h;
+    d.rho_h_chunks[L] = 0;
+    d.rho_h_ppc[L] = 1;
+    d.yhat_off[L] = yoff;
+    if (np <= 0) continue;
+    // rho over the tail
+    const int ppc = run_len(CR, costR[L], tn.mrho[L]);
+    for (int b = 0; b < nb; ++b)
+      for (int q0 = 0; q0 < nact[L][b]; q0 += ppc)
+        wl.rho_items.push_back(make_int4(b, q0, std::min(nact[L][b], q0 + ppc), wl.rows_of_block[b]++));
+    d.rho_nitems[L] = (int)wl.rho_items.size() - d.rho_item0[L];
+    // J over the tail
+    const int spc = run_len(CJ, costJ[L], tn.mj[L]);
+    int maxc = 0;
+    for (int B = 0; B < (int)nactp[L].size(); ++B) {
+      int c = 0;
+      for (int s0 = 0; s0 < nactp[L][B]; s0 += spc, ++c)
+        wl.j_items.push_back(make_int4(B, s0, std::min(nactp[L][B], s0 + spc), c));
+      maxc = std::max(maxc, c);
+      for (int r = 64 * B; r < std::min(np, 64 * B + 64); ++r) wl.jn_of[p.L_p0[L] + r] = hc + c;
+    }
+    d.j_nitems[L] = (int)wl.j_items.size() - d.j_item0[L];
+    yoff += (int64_t)(hc + maxc) * nherm(L) * np;
+    // the head (FP64 MFMA): rho in chunks of pairs x N-tile groups (one partial
+    // row each), about kHeadWaves waves per class launch; J moments over all head
+    // points in one chunk
+    if (nh > 0) {
+      const int waves_per_chunk = 4 * ((nh + 63) / 64) * ngr[L];
+      const int want = std::max(1, kHeadWaves / waves_per_chunk);
+      const int hp = std::max(kHeadMinPairs, (np + want - 1) / want);
+      d.rho_h_ppc[L] = hp;
+      d.rho_h_chunks[L] = (np + hp - 1) / hp;
+      rows_h += d.rho_h_chunks[L] * ngr[L];
+    }
+  }
+  int nrows = 1;
+  for (int r : wl.rows_of_block) nrows = std::max(nrows, r);
+  d.nrows = nrows;
+  d.nrows_h = std::max(1, rows_h);
+  // first reduction stage: up to 64 groups of the tail rows and of the head rows
+  d.ngroups = std::min(std::max(d.nrows, nh > 0 ? d.nrows_h : 0), 64);
+  d.rows_per_group = (d.nrows + d.ngroups - 1) / d.ngroups;
+  d.rows_per_group_h = (d.nrows_h + d.ngroups - 1) / d.ngroups;
+  d.yhat_size = std::max<int64_t>(1, yoff);
+}
+
+void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm, WorkLists &wl) {
+  choose_shapes_fp64(p, d, tn, max_ndm);
+  if (d.fp32) fp32_shapes(p, d, tn, wl);
 }
 
 // (Re)builds the device view of the plan: uploads and workspaces for the current
@@ -351,7 +419,8 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
     d.ncolsW = d.ncols32[lmax];
     d.d32_size = off;
   }
-  choose_shapes(p, d, tn, c->max_ndm);
+  WorkLists wl;
+  choose_shapes(p, d, tn, c->max_ndm, wl);
 
   hipError_t e;
 #define UP(vec, field) \
@@ -384,10 +453,12 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   UP(p.sD_e0, sD_e0)
   UP(p.eD, eD)
   UP(p.ttab, ttab)
-  if (d.npts_head > 0) {
-    std::vector<int> hidx(p.nslot(), -1);
-    for (int i = 0; i < d.npts_head; ++i) hidx[p.pts[i].slot] = i;
-    UP(hidx, slot_hidx)
+  if (d.fp32) {
+    UP(wl.slot_pidx, slot_pidx)
+    UP(wl.rho_items, rho_items)
+    UP(wl.j_items, j_items)
+    UP(wl.rows_of_block, rows_of_block)
+    UP(wl.jn_of, jn_of)
   }
   {
     std::vector<double> st(kStartTab);
@@ -413,7 +484,7 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   // the FP32-MFMA form keeps the coefficients in the MFMA layout (d32_size per call)
   AL(dhat, d.fp32 ? (size_t)std::max<int64_t>(1, d.d32_size) : M * d.dhat_size)
   AL(yhat, M * d.yhat_size)
-  AL(part, M * d.nrows * d.nslot)
+  AL(part, M * d.nrows * part_cols(d))
   AL(part2, M * d.ngroups * d.nslot)
   AL(rho, M * d.nslot)
   AL(Vc, M * d.nslot)
@@ -937,7 +1008,7 @@ static size_t carve_build_ws(Dev &d, const Plan &p, int ndm, unsigned char *base
   take(d.Jblk, M * p.nelem);
   take(d.dhat, d.fp32 ? (size_t)std::max<int64_t>(1, d.d32_size) : M * d.dhat_size);
   take(d.yhat, M * d.yhat_size);
-  take(d.part, M * d.nrows * d.nslot);
+  take(d.part, M * d.nrows * part_cols(d));
   take(d.part2, M * d.ngroups * d.nslot);
   take(d.rho, M * d.nslot);
   take(d.Vc, M * d.nslot);

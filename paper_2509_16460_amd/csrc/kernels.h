@@ -58,7 +58,7 @@ struct Dev {
   double *Dblk, *Jblk;     // [ndm][nelem]
   double *dhat;            // [ndm][dhat_size]
   double *yhat;            // [ndm][yhat_size]
-  double2 *part;           // [ndm][nrows][nslot]
+  double2 *part;           // [ndm][nrows][nslot] (FP64), [ndm][nrows][tail points] (FP32-MFMA)
   double2 *part2;          // [ndm][ngroups][nslot]
   double2 *rho, *Vc;       // [ndm][nslot]
   double *Epart;           // [ndm][nred_blocks]
@@ -73,16 +73,30 @@ struct Dev {
   int ncols32[kMaxLsum + 1];
   float *wre, *wim;
   int ncolsW;
-  // the head of the G set (pts[0, npts_head)), FP64 tiles on FP64 MFMA: rho
-  // partial rows [ndm][nrows_h][npts_head] (chunks of pairs per class), the J
-  // moments in chunk j_chunks32[L] of yhat after the FP32 chunks; slot_hidx maps
-  // a slot to its head point (-1 for the others) for the reduction
+  // The FP32-MFMA form splits the G set into its head, pts[0, npts_head) (FP64
+  // tiles on FP64 MFMA), and the tail (FP32 tiles), both in order of |G|^2, and
+  // runs both passes as lists of work items (int4 per item):
+  //   rho over the tail: (point block b of 64, pair range [q0, q1) of the class
+  //     in cut order, row): the pairs whose cut reaches the block's shortest G;
+  //     partial rows [ndm][nrows][tail point], block b using rows [0,
+  //     rows_of_block[b]);
+  //   J over the tail: (pair block B of 64 in cut order, point range [s0, s1),
+  //     chunk c): the points inside the block's largest cut; the moments of
+  //     chunk c go to yhat chunk 1 + c, the head's to chunk 0, and a pair's
+  //     back transform sums jn_of[cut rank] chunks;
+  //   rho over the head: chunks of pairs x N-tile groups, partial rows
+  //     [ndm][nrows_h][head point].
+  // slot_pidx maps a slot to its point (-1 for padding slots).
   int npts_head;
-  const int *slot_hidx;
+  const int *slot_pidx;
+  const int4 *rho_items, *j_items;
+  int rho_item0[kMaxLsum + 1], rho_nitems[kMaxLsum + 1];
+  int j_item0[kMaxLsum + 1], j_nitems[kMaxLsum + 1];
+  const int *rows_of_block;
+  const int *jn_of;
   double2 *parth;
   int nrows_h, rows_per_group_h;
   int rho_h_chunks[kMaxLsum + 1], rho_h_ppc[kMaxLsum + 1], rho_h_row0[kMaxLsum + 1];  // rows: chunk x tile group
-  int j_chunks32[kMaxLsum + 1], j_spc32[kMaxLsum + 1];  // FP32 J pass over the other points
   // gradient: moments of degree L+1 per class, per-block centre gradients,
   // per-atom lists of (block, 0 = shell a / 3 = shell b)
   double *yF;

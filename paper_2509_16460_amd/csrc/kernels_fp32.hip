@@ -58,45 +58,45 @@ __device__ __forceinline__ void s_direct(const GPoint &pt, const PairF &f, float
 }
 
 // ---------------------------------------------------------------------------
-// rho, K = pairs.  A workgroup = 4 waves = 64 G points (16 per wave as the MFMA
-// rows) and one chunk of pairs of class L, staged in LDS in tiles of kQTile
-// pairs (pair data and the coefficient columns of the current N-tile group).
-// Lane (r16 = l%16, g4 = l/16) evaluates S for point r16 of its wave and pair g4
-// of each group of four, once per N-tile group, and feeds the NTG N-tiles
-// (16 columns of (k, dm) each) of the group with it.  After the chunk the FP64
-// epilogue contracts each column with n^k (times i for odd |k|) and adds the
-// lanes of equal density.
+// rho over the tail of the G set, K = pairs.  A workgroup = 4 waves = one work
+// item: a block of 64 G points (16 per wave as the MFMA rows; points in order of
+// |G|^2) and a range of pairs of class L in cut order whose cuts reach the
+// block's shortest G, staged in LDS in tiles of kQTile pairs (pair data and the
+// coefficient columns of the current N-tile group).  Lane (r16 = l%16, g4 = l/16)
+// evaluates S for point r16 of its wave and pair g4 of each group of four, once
+// per N-tile group, and feeds the NTG N-tiles (16 columns of (k, dm) each) of
+// the group with it; a wave stops at the first group of four whose largest cut
+// lies below its shortest G.  After the range the FP64 epilogue contracts each
+// column with n^k (times i for odd |k|), adds the lanes of equal density and
+// writes the item's partial row.
 // ---------------------------------------------------------------------------
 constexpr int kQTile = 64;  // pairs per LDS tile of the rho pass
 
 template <int L, int NTG>
-__global__ __launch_bounds__(256) void k_rho_mfma(const GPoint *__restrict__ pts, int npts,
-                                                  const PairHot *__restrict__ hot, int Lp0, int Lp1, int ppc,
+__global__ __launch_bounds__(256) void k_rho_mfma(const int4 *__restrict__ items, const GPoint *__restrict__ pts,
+                                                  int npts, const PairHot *__restrict__ hot, int Lp0,
                                                   const float *__restrict__ dh32, int64_t d32_off, int ncols,
-                                                  int ndmp, int ndm, double2 *__restrict__ part, int row0,
-                                                  int nrows, int nslot, int cut) {
+                                                  int ndmp, int ndm, double2 *__restrict__ part, int nrows) {
   constexpr int NT = nherm(L);
   __shared__ PairF sh[kQTile];
   __shared__ float sc[kQTile * NTG * 16];
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, g4 = lane >> 4;
-  const int chunk = blockIdx.y;
-  const int p0 = Lp0 + chunk * ppc, p1 = min(Lp1, p0 + ppc);
-  const int pt0 = blockIdx.x * 64 + w * 16;  // first point of the wave's rows
+  const int4 it = items[blockIdx.x];  // (point block, q0, q1, row)
+  const int p0 = Lp0 + it.y, p1 = Lp0 + it.z;
+  const int pt0 = it.x * 64 + w * 16;  // first point of the wave's rows
   const GPoint ptA = pts[min(pt0 + r16, npts - 1)];
   const float *dcls = dh32 + d32_off;
   const int ntiles = ncols >> 4;
-  // per-pair cuts: smallest |G|^2 of the wave's 16 rows; a group of four pairs
-  // whose cuts all lie below it is skipped (wave-uniform)
+  // smallest |G|^2 of the wave's 16 rows (wave-uniform)
   double rmin = pt0 + r16 < npts ? ptA.g2 : 1e300;
-  const double blk_g2min = pts[blockIdx.x * 64].g2;
 #pragma unroll
   for (int off = 8; off > 0; off >>= 1) rmin = fmin(rmin, __shfl_xor(rmin, off, 64));
 
   // lanes r16 < ndm write density r16 of the wave's rows; each N-tile group adds
-  // its epilogue into the chunk's partial row (same lane, same addresses: no race)
-  double2 *out = part + ((size_t)min(r16, ndm - 1) * nrows + row0 + chunk) * nslot;
+  // its epilogue into the item's partial row (same lane, same addresses: no race)
+  double2 *out = part + ((size_t)min(r16, ndm - 1) * nrows + it.w) * npts;
   for (int ng = 0; ng < ntiles; ng += NTG) {
     const int ntg = min(NTG, ntiles - ng);
     f4 are[NTG], aim[NTG];
@@ -109,15 +109,6 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const GPoint *__restrict__ pts
       const int nq = min(kQTile, p1 - t0);
       __syncthreads();
       for (int i = tid; i < nq; i += 256) sh[i] = pair_f(hot[t0 + i]);
-      if (cut) {
-        // a tile whose largest cut lies below the block's shortest G (the points
-        // come in order of |G|^2) adds nothing: skipped with its staging
-        __syncthreads();
-        double tmax = lane < nq ? sh[lane].gc2 : 0.0;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off, 64));
-        if (tmax < blk_g2min) continue;
-      }
       // coefficient columns [ng*16, (ng+ntg)*16) of the tile's pairs
       // four elements per thread and step, their loads issued before the stores
       for (int i0 = tid; i0 < nq * NTG * 16; i0 += 4 * 256) {
@@ -138,12 +129,8 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const GPoint *__restrict__ pts
       // every group runs NTG tiles (a run-time tile count would make the compiler
       // move the accumulators out of the MFMA registers around every MFMA)
       for (int q0 = 0; q0 < nq; q0 += 4) {
-        if (cut) {
-          double kmax = sh[q0].gc2;
-#pragma unroll
-          for (int i = 1; i < 4; ++i) kmax = fmax(kmax, sh[min(q0 + i, nq - 1)].gc2);
-          if (kmax < rmin) continue;
-        }
+        // pairs in cut order: the first of four has the largest cut
+        if (sh[q0].gc2 < rmin) break;
         const int q = q0 + g4 < nq ? q0 + g4 : nq - 1;
         const bool vq = q0 + g4 < nq && ptA.g2 <= sh[q].gc2;
         float Sr, Si;
@@ -204,11 +191,11 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const GPoint *__restrict__ pts
         if (pi >= npts) continue;
         double2 v = make_double2(accr[i], acci[i]);
         if (ng > 0) {
-          const double2 o = out[pr[i].slot];
+          const double2 o = out[pi];
           v.x += o.x;
           v.y += o.y;
         }
-        out[pr[i].slot] = v;
+        out[pi] = v;
       }
     }
   }
@@ -249,11 +236,14 @@ __global__ __launch_bounds__(256) void k_wprep(const double2 *__restrict__ Vc, i
 }
 
 // ---------------------------------------------------------------------------
-// J moments, K = G.  A workgroup = 4 waves = 64 pairs (16 per wave as the MFMA
-// rows); lane (r16, g4) evaluates S for pair r16 of its wave at point g4 of each
-// group of four (one MFMA K-step per four points) and feeds NTW N-tiles of W'
-// with it.  The points of a chunk are staged in LDS tile by tile.  yhat per
-// (G chunk, k, pair) in FP64.
+// J moments over the tail of the G set, K = G.  A workgroup = 4 waves = one work
+// item (one N-tile group per workgroup, grid z): a block of 64 pairs of class L
+// in cut order (16 per wave as the MFMA rows) and a range of points (in order of
+// |G|^2) inside the block's largest cut.  Lane (r16, g4) evaluates S for pair
+// r16 of its wave at point g4 of each group of four (one MFMA K-step per four
+// points) and feeds NTW N-tiles of W' with it; a wave stops at the first group
+// of four whose shortest G lies beyond its largest cut.  The points are staged
+// in LDS tile by tile.  yhat per (chunk, k, pair) in FP64.
 // ---------------------------------------------------------------------------
 // points per LDS tile of the J pass (the W' tile is 2 x kPTile x 16 NTW floats)
 template <int NTW>
@@ -262,12 +252,12 @@ constexpr int j_ptile() {
 }
 
 template <int L, int NTW>
-__global__ __launch_bounds__(256) void k_jpass_mfma(const GPoint *__restrict__ pts, int npts, int ppc,
+__global__ __launch_bounds__(256) void k_jpass_mfma(const int4 *__restrict__ items, const GPoint *__restrict__ pts,
                                                     const float *__restrict__ wre, const float *__restrict__ wim,
                                                     int ncolsW, int ntiles, int ndmp, int ndm,
                                                     const PairHot *__restrict__ hot, int Lp0, int Lp1,
                                                     double *__restrict__ yhat, int64_t yhat_size, int64_t ycls_off,
-                                                    int cut) {
+                                                    int chunk0) {
   constexpr int NT = nherm(L);
   constexpr int kPTile = j_ptile<NTW>();
   __shared__ GPoint sp[kPTile];
@@ -276,30 +266,23 @@ __global__ __launch_bounds__(256) void k_jpass_mfma(const GPoint *__restrict__ p
   const int lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, g4 = lane >> 4;
   const int np = Lp1 - Lp0;
-  const int prow0 = blockIdx.x * 64 + w * 16;
-  const int chunk = blockIdx.y;
+  const int4 it = items[blockIdx.x];  // (pair block, s0, s1, chunk)
+  const int prow0 = it.x * 64 + w * 16;
+  const int chunk = chunk0 + it.w;
   const int nt0 = blockIdx.z * NTW;
   const int ntw = min(NTW, ntiles - nt0);
-  const int s0 = min(npts, chunk * ppc), s1 = min(npts, s0 + ppc);
+  const int s0 = it.y, s1 = it.z;
   const int pa = prow0 + r16;
   const PairF f = pair_f(hot[Lp0 + (pa < np ? pa : 0)]);
-  // per-pair cuts: largest cut of the wave's 16 rows; a group of four points all
-  // beyond it is skipped (wave-uniform)
+  // largest cut of the wave's 16 rows (wave-uniform)
   double cmax = pa < np ? f.gc2 : 0.0;
 #pragma unroll
   for (int off = 8; off > 0; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off, 64));
-  // largest cut of the block's 64 pairs: the points come in order of |G|^2, so
-  // the chunk ends for the block at its first tile beyond it
-  __shared__ double scm[4];
-  if (lane == 0) scm[w] = cmax;
-  __syncthreads();
-  const double cmax_blk = fmax(fmax(scm[0], scm[1]), fmax(scm[2], scm[3]));
   f4 acc[NTW];
 #pragma unroll
   for (int n = 0; n < NTW; ++n) acc[n] = f4{0.f, 0.f, 0.f, 0.f};
   for (int t0 = s0; t0 < s1; t0 += kPTile) {
     const int nt = min(kPTile, s1 - t0);
-    if (cut && pts[t0].g2 > cmax_blk) break;
     __syncthreads();
     if (tid < nt) sp[tid] = pts[t0 + tid];
     // W' columns [nt0*16, (nt0+ntw)*16) of the tile's points, real and imaginary
@@ -313,12 +296,8 @@ __global__ __launch_bounds__(256) void k_jpass_mfma(const GPoint *__restrict__ p
     __syncthreads();
     // branch-free as in the rho pass: columns past the group's tiles are zeros
     for (int q0 = 0; q0 < nt; q0 += 4) {
-      if (cut) {
-        double pmin = sp[q0].g2;
-#pragma unroll
-        for (int i = 1; i < 4; ++i) pmin = fmin(pmin, sp[min(q0 + i, nt - 1)].g2);
-        if (pmin > cmax) continue;
-      }
+      // points in order of |G|^2: the first of four is the shortest
+      if (sp[q0].g2 > cmax) break;
       const int q = q0 + g4 < nt ? q0 + g4 : nt - 1;
       const bool vq = q0 + g4 < nt && sp[q].g2 <= f.gc2;
       float Sr, Si;
@@ -360,19 +339,16 @@ __global__ __launch_bounds__(256) void k_jpass_mfma(const GPoint *__restrict__ p
 template <int L, int NTG>
 static hipError_t rho_mfma_ntg(const Dev &d, int ndm, hipStream_t st) {
   const int ntail = d.npts - d.npts_head;
-  dim3 grid((unsigned)((ntail + 63) / 64), d.rho_chunks[L]);
-  hipLaunchKernelGGL((k_rho_mfma<L, NTG>), grid, dim3(256), 0, st, d.pts + d.npts_head, ntail, d.hot_cut, d.L_p0[L],
-                     d.L_p1[L],
-                     d.rho_ppc[L], d.dh32, d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.part, d.rho_row0[L],
-                     d.nrows, d.nslot, d.pair_gcut);
+  hipLaunchKernelGGL((k_rho_mfma<L, NTG>), dim3((unsigned)d.rho_nitems[L]), dim3(256), 0, st,
+                     d.rho_items + d.rho_item0[L], d.pts + d.npts_head, ntail, d.hot_cut, d.L_p0[L], d.dh32,
+                     d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.part, d.nrows);
   PWDF_CHECK_LAUNCH32();
   return hipSuccess;
 }
 
 template <int L>
 static hipError_t rho_mfma_one(const Dev &d, int ndm, hipStream_t st) {
-  const int np = d.L_p1[L] - d.L_p0[L];
-  if (np <= 0 || d.npts - d.npts_head <= 0) return hipSuccess;
+  if (d.rho_nitems[L] <= 0) return hipSuccess;
   switch (group_tiles(d.ncols32[L] / 16)) {
     case 1: return rho_mfma_ntg<L, 1>(d, ndm, st);
     case 2: return rho_mfma_ntg<L, 2>(d, ndm, st);
@@ -411,13 +387,12 @@ hipError_t launch_wprep(const Dev &d, int ndm, hipStream_t st) {
 
 template <int L, int NTW>
 static hipError_t j_mfma_ntw(const Dev &d, int ndm, hipStream_t st) {
-  const int np = d.L_p1[L] - d.L_p0[L];
   const int ntiles = d.ncols32[L] / 16;
-  dim3 grid((unsigned)((np + 63) / 64), d.j_chunks32[L], (unsigned)((ntiles + NTW - 1) / NTW));
-  hipLaunchKernelGGL((k_jpass_mfma<L, NTW>), grid, dim3(256), 0, st, d.pts + d.npts_head, d.npts - d.npts_head,
-                     d.j_spc32[L], d.wre, d.wim,
-                     d.ncolsW, ntiles, d.ndmp, ndm, d.hot_cut, d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size,
-                     d.yhat_off[L], d.pair_gcut);
+  // chunk 0 of yhat holds the head's moments when there is a head
+  dim3 grid((unsigned)d.j_nitems[L], 1, (unsigned)((ntiles + NTW - 1) / NTW));
+  hipLaunchKernelGGL((k_jpass_mfma<L, NTW>), grid, dim3(256), 0, st, d.j_items + d.j_item0[L], d.pts + d.npts_head,
+                     d.wre, d.wim, d.ncolsW, ntiles, d.ndmp, ndm, d.hot_cut, d.L_p0[L], d.L_p1[L], d.yhat,
+                     d.yhat_size, d.yhat_off[L], d.npts_head > 0 ? 1 : 0);
   PWDF_CHECK_LAUNCH32();
   return hipSuccess;
 }
@@ -425,8 +400,7 @@ static hipError_t j_mfma_ntw(const Dev &d, int ndm, hipStream_t st) {
 // N-tile groups (grid z) as for rho: ceil(ntiles / 8) groups of equal size
 template <int L>
 static hipError_t j_mfma_one(const Dev &d, int ndm, hipStream_t st) {
-  const int np = d.L_p1[L] - d.L_p0[L];
-  if (np <= 0 || d.npts - d.npts_head <= 0 || d.j_chunks32[L] <= 0) return hipSuccess;
+  if (d.j_nitems[L] <= 0) return hipSuccess;
   switch (group_tiles(d.ncols32[L] / 16)) {
     case 1: return j_mfma_ntw<L, 1>(d, ndm, st);
     case 2: return j_mfma_ntw<L, 2>(d, ndm, st);

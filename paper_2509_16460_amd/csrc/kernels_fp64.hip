@@ -417,31 +417,38 @@ __device__ __forceinline__ void rho_block(const Dev &dv, int sgi, int chunk, int
 // rows, then the groups), V = v rho stored conjugated for the J pass, and the
 // energy partials Omega sum v |rho|^2 per block (G half space).
 // ---------------------------------------------------------------------------
-// The slots of the head of the FP32-MFMA form (slot_hidx >= 0) take their rows
-// from the head's partial rows [nrows_h][nhead] instead.
+// FP32-MFMA form (slot_pidx non-null): a slot's rows are those of its point --
+// the head's partial rows [nrows_h][nhead] for a head point, else the first
+// rows_of_block[b] tail rows [nrows][ntail] of its point block b; padding slots
+// sum nothing.
 __global__ __launch_bounds__(256) void k_reduce_rows(const double2 *__restrict__ part, int nrows, int nslot,
                                                      int rows_per_group, double2 *__restrict__ part2,
-                                                     int ngroups, const int *__restrict__ slot_hidx,
+                                                     int ngroups, const int *__restrict__ slot_pidx,
                                                      const double2 *__restrict__ parth, int nrows_h,
-                                                     int rows_per_group_h, int nhead) {
+                                                     int rows_per_group_h, int nhead, int ntail,
+                                                     const int *__restrict__ rows_of_block) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int grp = blockIdx.y;
   const int dm = blockIdx.z;
   if (g >= nslot) return;
-  const int h = slot_hidx ? slot_hidx[g] : -1;
-  int r0, r1;
-  size_t stride;
-  const double2 *pp;
-  if (h >= 0) {
-    r0 = grp * rows_per_group_h;
-    r1 = min(nrows_h, r0 + rows_per_group_h);
-    pp = parth + (size_t)dm * nrows_h * nhead + h;
-    stride = (size_t)nhead;
-  } else {
-    r0 = grp * rows_per_group;
-    r1 = min(nrows, r0 + rows_per_group);
-    pp = part + (size_t)dm * nrows * nslot + g;
-    stride = (size_t)nslot;
+  int r0 = grp * rows_per_group, r1 = min(nrows, r0 + rows_per_group);
+  size_t stride = (size_t)nslot;
+  const double2 *pp = part + (size_t)dm * nrows * nslot + g;
+  if (slot_pidx) {
+    const int pi = slot_pidx[g];
+    if (pi < 0) {
+      r1 = r0;
+    } else if (pi < nhead) {
+      r0 = grp * rows_per_group_h;
+      r1 = min(nrows_h, r0 + rows_per_group_h);
+      pp = parth + (size_t)dm * nrows_h * nhead + pi;
+      stride = (size_t)nhead;
+    } else {
+      const int tp = pi - nhead;
+      r1 = min(rows_of_block[tp >> 6], r0 + rows_per_group);
+      pp = part + (size_t)dm * nrows * ntail + tp;
+      stride = (size_t)ntail;
+    }
   }
   double r = 0.0, i = 0.0;
   int row = r0;
@@ -719,14 +726,17 @@ __device__ __forceinline__ void back_thread(const Dev &dv, int bi, int dm) {
   const double *__restrict__ yhat = dv.yhat;
   double *__restrict__ Jblk = dv.Jblk;
   const int64_t yhat_size = dv.yhat_size, ycls_off = dv.yhat_off[L], nelem = dv.nelem;
-  const int nchunks = dv.j_chunks[L], Lp0 = dv.L_p0[L], Lp1 = dv.L_p1[L];
+  const int nchunks_L = dv.j_chunks[L], Lp0 = dv.L_p0[L], Lp1 = dv.L_p1[L];
   const BlockRec b = dv.blocks[bi];
   const int np = Lp1 - Lp0;
   double J[NCA * NCB];
 #pragma unroll
   for (int e = 0; e < NCA * NCB; ++e) J[e] = 0.0;
   for (int q = b.p0; q < b.p1; ++q) {
-    const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (dv.cut_rank[q] - Lp0);  // J walk order
+    const int rq = dv.cut_rank[q];  // J walk order
+    const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (rq - Lp0);
+    // FP32-MFMA form: the chunks the pair's block of the J pass wrote
+    const int nchunks = dv.jn_of ? dv.jn_of[rq] : nchunks_L;
     // y_k = sum over the J chunks in chunk order; the loads of four chunks are
     // issued together (one thread per pair leaves little other parallelism)
     double y[NT];
@@ -999,7 +1009,7 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
   const double *__restrict__ yhat = dv.yhat;
   double *__restrict__ Jblk = dv.Jblk;
   const int64_t yhat_size = dv.yhat_size, ycls_off = dv.yhat_off[L], nelem = dv.nelem;
-  const int nchunks = dv.j_chunks[L], Lp0 = dv.L_p0[L], Lp1 = dv.L_p1[L];
+  const int nchunks_L = dv.j_chunks[L], Lp0 = dv.L_p0[L], Lp1 = dv.L_p1[L];
   double *sE = lds;
   double *sY = sE + 3 * NE;
   double *sJ = sY + NT;
@@ -1024,7 +1034,10 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
   for (int q = b.p0; q < b.p1; ++q) {
     const PairAux x = aux[q];
     wave_sync();
-    const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (dv.cut_rank[q] - Lp0);  // J walk order
+    const int rq = dv.cut_rank[q];  // J walk order
+    const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (rq - Lp0);
+    // FP32-MFMA form: the chunks the pair's block of the J pass wrote
+    const int nchunks = dv.jn_of ? dv.jn_of[rq] : nchunks_L;
     for (int k = lane; k < NT; k += 64) {
       // chunk order kept; up to 16 loads in flight
       double s = 0.0;
@@ -1650,8 +1663,8 @@ hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, double *EJ, hipStre
 hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st) {
   dim3 g1((unsigned)((d.nslot + 255) / 256), d.ngroups, ndm);
   hipLaunchKernelGGL(k_reduce_rows, g1, dim3(256), 0, st, d.part, d.nrows, d.nslot, d.rows_per_group, d.part2,
-                     d.ngroups, d.npts_head > 0 ? d.slot_hidx : nullptr, d.parth, d.nrows_h, d.rows_per_group_h,
-                     d.npts_head);
+                     d.ngroups, d.fp32 ? d.slot_pidx : nullptr, d.parth, d.nrows_h, d.rows_per_group_h, d.npts_head,
+                     d.npts - d.npts_head, d.rows_of_block);
   PWDF_CHECK_LAUNCH();
   dim3 g2((unsigned)d.nred_blocks, ndm);
   hipLaunchKernelGGL(k_reduce, g2, dim3(256), 0, st, d.part2, d.ngroups, d.nslot, d.slot_v, d.vol, d.rho, d.Vc,

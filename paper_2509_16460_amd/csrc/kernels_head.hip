@@ -15,8 +15,8 @@
 // (G, pair) (exp2 and sincospi of the device math library); the coefficients
 // come from the FP64 transform output and W' = n^k conj V(G) (times -i for
 // odd |k|) is formed in FP64 while the tile is staged.  The head rho rows go to
-// their own partial rows (one per chunk of pairs), the J moments to the chunk
-// after the FP32 chunks of yhat; the reduction and the back transform add them.
+// their own partial rows (one per chunk of pairs and N-tile group), the J
+// moments to chunk 0 of yhat; the reduction and the back transform add them.
 //
 // Lane layout of the 16x16x4 f64 MFMA (lane l = 0..63): A[l%16][l/16],
 // B[l/16][l%16], D[4*i + l/16][l%16], i = 0..3 (the rows of D interleave across
@@ -321,8 +321,8 @@ template <int L, int NTW>
 static hipError_t j_head_ntw(const Dev &d, int ndm, hipStream_t st) {
   const int np = d.L_p1[L] - d.L_p0[L];
   const int ntiles = d.ncols32[L] / 16;
-  // the head's moments are chunk j_chunks32[L] of the class
-  const int64_t off = d.yhat_off[L] + (int64_t)d.j_chunks32[L] * nherm(L) * np;
+  // the head's moments are chunk 0 of the class
+  const int64_t off = d.yhat_off[L];
   dim3 grid((unsigned)((np + 63) / 64), 1, (unsigned)((ntiles + NTW - 1) / NTW));
   hipLaunchKernelGGL((k_jpass_head<L, NTW>), grid, dim3(256), 0, st, d.pts, d.npts_head, d.Vc, d.nslot, ntiles,
                      d.ndmp, ndm, d.hot_cut, d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size, off);
