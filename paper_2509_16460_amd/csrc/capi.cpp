@@ -296,9 +296,9 @@ void fp32_shapes(const Plan &p, Dev &d, const Tune &tn, WorkLists &wl) {
   }
   // item cost (cycles of one wave) for about kItemWaves waves, 4 per item
   const double CR = std::max(1.0, WR / (kItemWaves / 4.0)), CJ = std::max(1.0, WJ / (kItemWaves / 4.0));
-  auto run_len = [&](double C, double cost, double mult) {
+  auto run_len = [&](double C, double cost, double mult, int cap) {
     int r = (int)std::lround(4.0 * C / cost / std::max(mult, 1e-3));
-    r = std::max(kMinRun, std::min(kMaxFp32Run, r));
+    r = std::max(kMinRun, std::min(cap, r));
     return (r + 3) / 4 * 4;
   };
   wl.rows_of_block.assign(std::max(1, nb), 0);
@@ -317,13 +317,13 @@ void fp32_shapes(const Plan &p, Dev &d, const Tune &tn, WorkLists &wl) {
     d.yhat_off[L] = yoff;
     if (np <= 0) continue;
     // rho over the tail
-    const int ppc = run_len(CR, costR[L], tn.mrho[L]);
+    const int ppc = run_len(CR, costR[L], tn.mrho[L], kMaxFp32Run);
     for (int b = 0; b < nb; ++b)
       for (int q0 = 0; q0 < nact[L][b]; q0 += ppc)
         wl.rho_items.push_back(make_int4(b, q0, std::min(nact[L][b], q0 + ppc), wl.rows_of_block[b]++));
     d.rho_nitems[L] = (int)wl.rho_items.size() - d.rho_item0[L];
     // J over the tail
-    const int spc = run_len(CJ, costJ[L], tn.mj[L]);
+    const int spc = run_len(CJ, costJ[L], tn.mj[L], kMaxFp32Run);
     int maxc = 0;
     for (int B = 0; B < (int)nactp[L].size(); ++B) {
       int c = 0;
@@ -433,6 +433,7 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   UP(p.rho_rank, rho_rank)
   UP(p.hot_cut, hot_cut)
   UP(p.cut_rank, cut_rank)
+  UP(p.blk_cut, blk_cut)
   UP(p.aux, aux)
   UP(p.blocks, blocks)
   UP(p.elem_blk, elem_blk)

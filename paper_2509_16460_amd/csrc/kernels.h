@@ -23,6 +23,8 @@ struct Dev {
   const int *rho_rank;           // pair -> position in that order (where its coefficients go)
   const PairHot *hot_cut;        // pair records by cut radius per class (J pass, FP32-MFMA rho pass)
   const int *cut_rank;           // pair -> position in that order (J moments, FP32-MFMA coefficient rows)
+  const int *blk_cut;            // blocks of each (la, lb) class in that order: neighbouring lanes / waves
+                                 // of the back transform read neighbouring moments
   const PairAux *aux;
   const BlockRec *blocks;
   const int *elem_blk;

@@ -1302,6 +1302,9 @@ static bool wave_per_block(int L) { return L >= 3; }
 constexpr int kPairWG = 256;
 constexpr int kWavesPerWG = kPairWG / 64;
 
+// The transform takes the blocks in storage order (neighbouring lanes read
+// neighbouring D(L) blocks); the back transform takes them in the J walk order
+// (blk_cut), in which it reads the moments.
 __global__ __launch_bounds__(kPairWG) void k_transform_all(const Dev dv, const ClassTab tab) {
   __shared__ double lds[kWavesPerWG * kWaveLds];
   const int i = tab_entry(tab, blockIdx.x);
@@ -1328,13 +1331,13 @@ __global__ __launch_bounds__(kPairWG) void k_back_all(const Dev dv, const ClassT
   const int dm = blockIdx.y;
   if (tab.mode[i]) {
     const int w = threadIdx.x >> 6;
-    const int bi = dv.cls_b0[cl] + local * kWavesPerWG + w;
-    if (bi >= dv.cls_b1[cl]) return;
-    PWDF_CLASS_SWITCH_WAVE(back_wave, dv, bi, dm, lds + w * kWaveLds)
+    const int j = dv.cls_b0[cl] + local * kWavesPerWG + w;
+    if (j >= dv.cls_b1[cl]) return;
+    PWDF_CLASS_SWITCH_WAVE(back_wave, dv, dv.blk_cut[j], dm, lds + w * kWaveLds)
   } else {
-    const int bi = dv.cls_b0[cl] + local * kPairWG + threadIdx.x;
-    if (bi >= dv.cls_b1[cl]) return;
-    PWDF_CLASS_SWITCH_THREAD(back_thread, dv, bi, dm)
+    const int j = dv.cls_b0[cl] + local * kPairWG + threadIdx.x;
+    if (j >= dv.cls_b1[cl]) return;
+    PWDF_CLASS_SWITCH_THREAD(back_thread, dv, dv.blk_cut[j], dm)
   }
 }
 

@@ -650,6 +650,12 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
       p.cut_rank[order[r]] = (int)r;
       p.hot_cut[r] = p.hot[order[r]];
     }
+    // blocks of each (la, lb) class in the same walk (by the rank of their first pair)
+    p.blk_cut.resize(p.blocks.size());
+    for (size_t b = 0; b < p.blocks.size(); ++b) p.blk_cut[b] = (int)b;
+    for (int c = 0; c < 16; ++c)
+      std::stable_sort(p.blk_cut.begin() + p.cls_b0[c], p.blk_cut.begin() + p.cls_b1[c],
+                       [&](int x, int y) { return p.cut_rank[p.blocks[x].p0] < p.cut_rank[p.blocks[y].p0]; });
   }
   p.elem_blk.resize(p.nelem);
   for (int b = 0; b < (int)p.blocks.size(); ++b) {

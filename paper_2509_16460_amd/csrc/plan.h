@@ -72,6 +72,7 @@ struct Plan {
   // J moments and the FP32-MFMA coefficient rows), hot_cut the records in it.
   std::vector<int> cut_rank;
   std::vector<PairHot> hot_cut;
+  std::vector<int> blk_cut;  // blocks of each (la, lb) class in that walk (back transform)
   int64_t dhat_off[kMaxLsum + 1];             // offset of class L in a per-density coefficient array
   int64_t dhat_size = 0;
   int64_t nelem = 0;                          // sum over blocks of ncart(la) ncart(lb)
