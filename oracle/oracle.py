@@ -40,7 +40,8 @@ def lib():
         L.orc_build_j.restype = ctypes.c_int
         L.orc_build_j.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, dp, dp, ip,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                  dp, dp, dp, dp, ip, ctypes.c_int, ip, dp, ctypes.c_int, ctypes.c_int]
+                                  dp, dp, dp, dp, ip, ctypes.c_int, ip, dp, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_double]
         L.orc_sizes.restype = ctypes.c_int
         L.orc_sizes.argtypes = [dp, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, dp, dp, ip,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -111,10 +112,15 @@ class OracleResult(dict):
     pass
 
 
-def build_j(prob, Dk, *, want_J=True, want_rho=True, want_grad=False, nthreads=0, pair_gcut=None):
+def build_j(prob, Dk, *, want_J=True, want_rho=True, want_grad=False, nthreads=0, pair_gcut=None,
+            alpha_cut=None):
     """Long-range J, energies, rho(G) and (optionally) dE/dR for one density.
     pair_gcut (default: prob.pair_gcut): each screened pair sees only the G
     vectors inside its own cut radius (section "Integral screening").
+    alpha_cut (default: prob.alpha_cut; <= 0 off): compact/diffuse classification
+    (section "Density classification: compact and diffuse"): pairs of two
+    primitives with exponents below alpha_cut interact in full (4 pi/G^2), the
+    others keep the long-range kernel among themselves; rho is then rho_C + rho_D.
 
     Dk: complex128 [nk][nbf][nbf].  Returns dict with J (complex [nk][nbf][nbf]),
     E_real, E_G, E_k, maxImJ, maxJ, charge (Omega rho(0)), rho (complex [nG]),
@@ -137,7 +143,8 @@ def build_j(prob, Dk, *, want_J=True, want_rho=True, want_grad=False, nthreads=0
     rc = lib().orc_build_j(*args, _d(Dv), _d(J.view(np.float64)) if want_J else null_d, _d(energy),
                            _d(rho) if want_rho else null_d, _i(miller) if want_rho else null_i,
                            int(nG), ctypes.byref(nG_out), _d(grad) if want_grad else null_d,
-                           int(nthreads), int(getattr(prob, "pair_gcut", 0) if pair_gcut is None else pair_gcut))
+                           int(nthreads), int(getattr(prob, "pair_gcut", 0) if pair_gcut is None else pair_gcut),
+                           float(getattr(prob, "alpha_cut", 0.0) if alpha_cut is None else alpha_cut))
     if rc != 0:
         raise RuntimeError(f"oracle failed ({rc})")
     out = OracleResult(E_real=energy[0], E_G=energy[1], E_k=energy[2], maxImJ=energy[3],

@@ -51,6 +51,26 @@
  *                 scan of 256 steps down from Gcut and 60 bisection steps, and
  *                 is the upper end of the final bracket.  Without cuts every
  *                 pair sees the whole G set.
+ *   classification optional (alpha_cut > 0; section "Density classification:
+ *                 compact and diffuse", eq. "cd cutoff" gives alpha_cut =
+ *                 w^2/2): a primitive function is diffuse when its exponent is
+ *                 below alpha_cut, and a primitive pair is a diffuse (DD) pair
+ *                 when both of its functions are; every other pair is compact
+ *                 (CC or CD).  rho = rho_C + rho_D splits by pair class.  When
+ *                 both sides of an interaction are compact it keeps the
+ *                 long-range kernel; otherwise the interaction is taken in full
+ *                 in reciprocal space, v_full(G) = 4 pi / G^2 (G != 0), so the
+ *                 two potentials are
+ *                   V_C(G) = v(G) rho_C(G) + v_full(G) rho_D(G)   (compact pairs)
+ *                   V_D(G) = v_full(G) (rho_C(G) + rho_D(G))       (DD pairs)
+ *                 J_ab(L) = sum_G V_class(-G) F_abL(G) with the pair's own
+ *                 class, E_J = 1/2 Omega sum_G [rho_C(G) V_C(-G) + rho_D(G)
+ *                 V_D(-G)] (the same three routes), and the gradient takes the
+ *                 same V.  Readings: a pair whose exponents equal alpha_cut is
+ *                 compact; DD pairs see the whole G set even with per-pair
+ *                 cuts (the cut objective is the long-range one); the G set
+ *                 stays the long-range one (a DD pair density decays as
+ *                 e^{-G^2/4p}, p < w^2, faster than the long-range kernel).
  *
  * Conventions: lattice rows are a1,a2,a3; Cartesian components of a shell in
  * descending lexicographic (lx,ly,lz) order; every component of a primitive
@@ -600,6 +620,8 @@ void orc_pair_ft(int la, int lb, double aa, const double *RA, double ab, const d
  *           max|Im J(L)|, max|J(L)|, Omega*rho(0)  (rho(0) from F at G = 0)
  *   rho     out [maxG][2] and miller [maxG][3] (NULL: skip); nG_out gets |G set|
  *   grad    out [natm][3] (NULL: skip)
+ *   pair_gcut  1: per-pair G cuts;  alpha_cut  > 0: compact/diffuse classification
+ *   (rho out is then rho_C + rho_D)
  * Returns 0, or -1 on bad input, -2 when maxG is too small.
  */
 int orc_build_j(const double *lattice, int natm, const double *xyz, int nshell,
@@ -607,7 +629,7 @@ int orc_build_j(const double *lattice, int natm, const double *xyz, int nshell,
                 const double *exps, const double *coefs, const int *kmesh, double omega,
                 double eps_pair, double eps_G, double r_max, const double *Dk_, double *Jk_,
                 double *energy, double *rho_out, int *miller, int maxG, int *nG_out,
-                double *grad, int nthreads, int pair_gcut) {
+                double *grad, int nthreads, int pair_gcut, double alpha_cut) {
   orc_sys s;
   if (sys_setup(&s, lattice, natm, xyz, nshell, shell_atom, shell_l, shell_nprim, exps, coefs,
                 kmesh, omega, eps_pair, eps_G, r_max))
@@ -635,6 +657,14 @@ int orc_build_j(const double *lattice, int natm, const double *xyz, int nshell,
    * set with |G|^2 <= gc2[q]; without it every pair sees the whole set */
   double *gc2 = pair_gcut ? pair_cuts2(&s, pl, np) : NULL;
 
+  /* compact/diffuse classification: dd[q] = 1 for a pair of two diffuse
+   * primitives (exponents below alpha_cut); DD pairs see the whole G set */
+  char *dd = (char *)calloc(np > 0 ? np : 1, 1);
+  for (int q = 0; q < np; ++q) {
+    dd[q] = alpha_cut > 0.0 && exps[pl[q].ia] < alpha_cut && exps[pl[q].ib] < alpha_cut;
+    if (gc2 && dd[q]) gc2[q] = HUGE_VAL;
+  }
+
   /* per-pair block offsets, D(L) blocks and prefactors */
   int64_t *boff = (int64_t *)malloc(sizeof(int64_t) * (np + 1));
   boff[0] = 0;
@@ -659,12 +689,14 @@ int orc_build_j(const double *lattice, int natm, const double *xyz, int nshell,
       }
   }
 
-  /* rho(G) = (1/Omega) sum_pairs D_ab(L) F_abL(G) */
+  /* rho(G) = (1/Omega) sum_pairs D_ab(L) F_abL(G), split by pair class:
+   * rho holds the compact pairs' part, rhoD the DD pairs' part */
   zd *rho = (zd *)malloc(sizeof(zd) * ng);
+  zd *rhoD = (zd *)malloc(sizeof(zd) * ng);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int ig = 0; ig < ng; ++ig) {
     zd F[441];
-    zd acc = 0.0;
+    zd acc = 0.0, accD = 0.0;
     for (int q = 0; q < np; ++q) {
       const orc_pair *P = &pl[q];
       int la = shell_l[P->sa], lb = shell_l[P->sb];
@@ -674,17 +706,23 @@ int orc_build_j(const double *lattice, int natm, const double *xyz, int nshell,
       if (gc2 && g[ig].G2 > gc2[q]) continue;
       pair_ft_block(la, lb, exps[P->ia], RA, exps[P->ib], RB, pref[q], g[ig].G, F, NULL, NULL);
       int n = ncart_of(la) * ncart_of(lb);
-      for (int e = 0; e < n; ++e) acc += DL[boff[q] + e] * F[e];
+      zd *a = dd[q] ? &accD : &acc;
+      for (int e = 0; e < n; ++e) *a += DL[boff[q] + e] * F[e];
     }
     rho[ig] = acc / s.omega_vol;
+    rhoD[ig] = accD / s.omega_vol;
   }
 
-  /* v(G) and the G-space energy */
+  /* v(G) (long range), vf(G) (full range) and the G-space energy */
   double *v = (double *)malloc(sizeof(double) * ng);
+  double *vf = (double *)malloc(sizeof(double) * ng);
   double e_g = 0.0;
   for (int ig = 0; ig < ng; ++ig) {
     v[ig] = 4.0 * ORC_PI * exp(-g[ig].G2 / (4.0 * omega * omega)) / g[ig].G2;
+    vf[ig] = 4.0 * ORC_PI / g[ig].G2;
     e_g += v[ig] * creal(rho[ig] * rho[mi[ig]]);
+    /* interactions with a DD side, in full */
+    e_g += vf[ig] * creal(rho[ig] * rhoD[mi[ig]] + rhoD[ig] * rho[mi[ig]] + rhoD[ig] * rhoD[mi[ig]]);
   }
   e_g *= 0.5 * s.omega_vol;
 
@@ -715,7 +753,8 @@ int orc_build_j(const double *lattice, int natm, const double *xyz, int nshell,
       double gA[3] = {0, 0, 0}, gB[3] = {0, 0, 0};
       for (int ig = 0; ig < ng; ++ig) {
         if (gc2 && g[ig].G2 > gc2[q]) continue;
-        zd w = v[ig] * rho[mi[ig]];
+        /* V(-G) of the pair's class: V_C for compact pairs, V_D for DD pairs */
+        zd w = dd[q] ? vf[ig] * (rho[mi[ig]] + rhoD[mi[ig]]) : v[ig] * rho[mi[ig]] + vf[ig] * rhoD[mi[ig]];
         pair_ft_block(la, lb, exps[P->ia], RA, exps[P->ib], RB, pref[q], g[ig].G, F,
                       grad ? dA : NULL, grad ? dB : NULL);
         for (int e = 0; e < n; ++e) Jc[e] += w * F[e];
@@ -806,15 +845,18 @@ int orc_build_j(const double *lattice, int natm, const double *xyz, int nshell,
   }
   if (rho_out) {
     for (int ig = 0; ig < ng; ++ig) {
-      rho_out[2 * ig] = creal(rho[ig]);
-      rho_out[2 * ig + 1] = cimag(rho[ig]);
+      rho_out[2 * ig] = creal(rho[ig] + rhoD[ig]);
+      rho_out[2 * ig + 1] = cimag(rho[ig] + rhoD[ig]);
       if (miller)
         for (int c = 0; c < 3; ++c) miller[3 * ig + c] = g[ig].n[c];
     }
   }
   free(gc2);
+  free(dd);
   free(rho);
+  free(rhoD);
   free(v);
+  free(vf);
   free(DL);
   free(JL);
   free(pref);

@@ -73,6 +73,9 @@ class Problem:
     nelec: float = 2.0
     seed: int = 0
     pair_gcut: int = 0  # 1: per-pair reciprocal-space cut (section "Integral screening")
+    # > 0: compact/diffuse classification with this cutoff exponent (section
+    # "Density classification: compact and diffuse"; the paper's default is omega^2/2)
+    alpha_cut: float = 0.0
 
     @property
     def natm(self) -> int:

@@ -44,7 +44,17 @@ MUTANTS = {
     "omega": ("exp(-g[ig].G2 / (4.0 * omega * omega))", "exp(-g[ig].G2 / (2.0 * omega * omega))",
               "wrong range-separation exponent"),
     "ehalf": ("e_g *= 0.5 * s.omega_vol;", "e_g *= s.omega_vol;", "dropped 1/2 in the G-space energy"),
-    "rhoplus": ("zd w = v[ig] * rho[mi[ig]];", "zd w = v[ig] * rho[ig];", "V(G) instead of V(-G) in the J contraction"),
+    "rhoplus": (": v[ig] * rho[mi[ig]] + vf[ig] * rhoD[mi[ig]];", ": v[ig] * rho[ig] + vf[ig] * rhoD[mi[ig]];",
+                "V(G) instead of V(-G) in the J contraction"),
+    "cdjv": ("zd w = dd[q] ? vf[ig] * (rho[mi[ig]] + rhoD[mi[ig]])", "zd w = dd[q] ? v[ig] * rho[mi[ig]] + vf[ig] * rhoD[mi[ig]]",
+             "DD pairs contracted with the compact pairs' potential V_C"),
+    "cdcross": ("e_g += vf[ig] * creal(rho[ig] * rhoD[mi[ig]] + rhoD[ig] * rho[mi[ig]]",
+                "e_g += vf[ig] * creal(rho[ig] * rhoD[mi[ig]]",
+                "one of the two compact-diffuse cross terms dropped from the G-space energy"),
+    "cdvf": ("vf[ig] = 4.0 * ORC_PI / g[ig].G2;", "vf[ig] = v[ig];",
+             "long-range kernel kept for the interactions with a DD side"),
+    "cdle": ("exps[pl[q].ia] < alpha_cut && exps[pl[q].ib] < alpha_cut", "exps[pl[q].ia] < alpha_cut || exps[pl[q].ib] < alpha_cut",
+             "CD pairs classified as diffuse"),
     "dgrad": ("if (a[x] > 0) da -= (double)a[x] * f[x][a[x] - 1][b[x]];",
               "if (a[x] > 0) da += (double)a[x] * f[x][a[x] - 1][b[x]];", "sign of the lowered term of the centre derivative"),
     "gswap": ("int A_ = shell_atom[P->sa], B_ = shell_atom[P->sb];",
@@ -59,7 +69,8 @@ MUTANTS = {
                "sign of the shell-b centre derivative in the gradient"),
 }
 
-TESTS = ["tests/test_oracle_pins.py", "tests/test_oracle_invariants.py", "tests/test_oracle_grad.py"]
+TESTS = ["tests/test_oracle_pins.py", "tests/test_oracle_invariants.py", "tests/test_oracle_grad.py",
+         "tests/test_oracle_cd.py"]
 
 
 def run(name, tmp):
