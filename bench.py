@@ -62,8 +62,11 @@ def flops_per_unit(name):
     (L+1)-term complex multiply-add along the G line plus the separable
     exponential/phase product).  The FP64 launches rho_lo/hi and jpass_lo/hi
     count their units in these flops already; the per-class MFMA launches (FP32
-    tiles, and FP64 tiles of the head of the G set) count pair-G evaluations."""
-    if name in ("rho_lo", "rho_hi", "jpass_lo", "jpass_hi"):
+    tiles, and FP64 tiles of the head of the G set) count pair-G evaluations.  The
+    density transform and the back transform count their algorithmic flops (two
+    per term of the E-coefficient contraction and per Hermite -> monomial table
+    entry, per pair and density) on the FP64 VALU."""
+    if name in ("rho_lo", "rho_hi", "jpass_lo", "jpass_hi", "transform", "back"):
         return 1.0
     for pre in ("rho_mfma_L", "jpass_mfma_L", "rho_head_L", "jpass_head_L"):
         if name.startswith(pre):
@@ -339,7 +342,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "atoms": prob.natm, "nbf": prob.nbf, "nk": prob.nk, "omega": prob.omega,
                    "nG": st["nG"], "unique_pairs": st["npairs"], "ndm_per_step": NDM,
-                   "precision": "fp32_mfma (pair-G tiles FP32 on MFMA, head of the G set FP64 on MFMA; phase "
+                   "precision": "fp32_mfma (pair-G tiles FP32 on MFMA, head of the G set (v(G) >= 2^-20 max v) FP64 on MFMA; phase "
                                 "sums, transforms, energy FP64)",
                    "screening": "eps 1e-12, per-pair G cuts", "nG_head": st["nG_head"],
                    "jk_layout": "packed support", "jk_support_elements": st["jk_support"],

@@ -85,10 +85,10 @@ typedef enum {
   PWDF_FP32_MFMA = 1  /* pair-G tiles generated in FP32, contracted on FP32 MFMA,
                          FP64 accumulation across pairs; phase sums, E-coefficient
                          transforms and the energy stay FP64.  The head of the G
-                         set -- the G whose Coulomb weight v(G) is at least 2^-7
-                         of the largest, a small ball around G = 0 -- takes FP64
-                         tiles on FP64 MFMA (pwdf_stats.pairG_head): the FP32
-                         rounding then scales with the tail's weights */
+                         set -- the G whose Coulomb weight v(G) is at least 2^-20
+                         of the largest (pwdf_set_fp32_head), a ball around G = 0
+                         -- takes FP64 tiles on FP64 MFMA (pwdf_stats.pairG_head):
+                         the FP32 rounding then scales with the tail's weights */
 } pwdf_precision;
 
 /* What pwdf_build_j writes into J(k) (pwdf_set_jk_layout). */
@@ -114,6 +114,19 @@ typedef struct {
                       screening obj", "eta_munu"; |F|_inf over the Cartesian
                       components with G along x, y, z); 0: every pair sees the
                       whole set */
+  double alpha_cut; /* > 0: compact/diffuse classification (section "Density
+                      classification: compact and diffuse"; eq. "cd cutoff" sets
+                      alpha_cut = omega^2/2).  A primitive pair whose two exponents
+                      both lie below alpha_cut is diffuse (DD); every interaction
+                      with a DD side then takes the full-range kernel 4 pi/G^2:
+                        V_C = v rho_C + (4 pi/G^2) rho_D   for compact pairs,
+                        V_D = (4 pi/G^2)(rho_C + rho_D)    for DD pairs,
+                        E_J = 1/2 Omega sum_G [rho_C V_C(-G) + rho_D V_D(-G)],
+                      rho_C / rho_D the parts of rho from compact / DD pairs.  DD
+                      pairs see the whole G set (no per-pair cut) and are
+                      evaluated in FP64 in both precision forms; J, E_J, the
+                      gradient and pwdf_get_rhoG (rho_C + rho_D) follow.  <= 0:
+                      off.  Must be finite (PWDF_EINVAL) */
 } pwdf_screen;
 
 typedef struct {
@@ -136,6 +149,8 @@ typedef struct {
   int64_t nG_head;    /* G vectors of the half space in the head (v(G) >= 2^-7 max v) */
   double pairG_head;  /* per build and density: the part of pairG_evals on the head G;
                          the FP32-MFMA form evaluates it with FP64 tiles */
+  int64_t npairs_dd;  /* unique DD primitive pairs (pwdf_screen.alpha_cut); pairG_evals
+                         counts them over the whole half space in both passes */
 } pwdf_stats;
 
 /*
@@ -185,6 +200,21 @@ pwdf_status pwdf_query(const pwdf_ctx *ctx, pwdf_stats *out);
  * changes.  Host only; PWDF_EINVAL for an unknown layout.
  */
 pwdf_status pwdf_set_jk_layout(pwdf_ctx *ctx, int layout);
+
+/*
+ * FP32-MFMA form: the G vectors whose Coulomb weight v(G) = 4 pi e^{-G^2/4w^2}/G^2
+ * is at least `weight` times the largest one (a ball around G = 0: the part of
+ * the sum of eq. "Ewald J" that carries most of the energy) are contracted with
+ * FP64 tiles on FP64 MFMA, the others with FP32 tiles.  A smaller weight moves
+ * more of the pair-G work into FP64 (pwdf_stats.nG_head, pairG_head) and lowers
+ * the FP32 rounding error of E_J and J; weight -> 0 takes every G in FP64.
+ * Default 2^-20.  weight in (0, 1] (PWDF_EINVAL otherwise).  The context's device
+ * workspaces are rebuilt for the new split (this call allocates and synchronises
+ * the device; a cached graph is dropped; the launch shapes of the last
+ * pwdf_autotune are kept, so tune again for the best ones).  The FP64 form only
+ * reports the counts.
+ */
+pwdf_status pwdf_set_fp32_head(pwdf_ctx *ctx, double weight);
 
 /*
  * Element order of the packed J(k) layout: for i < pwdf_stats.jk_support, the
@@ -333,7 +363,9 @@ pwdf_status pwdf_autotune(pwdf_ctx *ctx, int ndm, const char *cache_path);
  * jpass_lo/hi, 8(L+1)+4 per unique pair, G of the half space and density;
  * pair-G evaluations for the FP32 launches rho_mfma_L* / jpass_mfma_L*; D(k) values read for
  * phase_d (elements on the pair support x Nk), J(k) values written for phase_j,
- * primitive pairs for transform / back).
+ * algorithmic flops for transform / back: two per term of the E-coefficient
+ * contraction sum_ab D_ab E^x E^y E^z and per entry of the Hermite -> monomial
+ * blocks, per pair and density).
  * out may be NULL to query the count; *n receives the number of names. */
 typedef struct {
   char name[32];

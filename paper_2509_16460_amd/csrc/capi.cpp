@@ -398,7 +398,7 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   d.nheavyJ = (int)p.heavyJ.size();
   d.nlightJ = (int)p.lightJ.size();
   d.jk_layout = c->jk_layout;
-  d.pair_gcut = in.pair_gcut;
+  d.pair_gcut = p.cut_on() ? 1 : 0;
   d.muu = p.M[p.ax[0]][p.ax[0]];
   d.fp32 = c->prec == PWDF_FP32_MFMA ? 1 : 0;
   d.npts_head = d.fp32 ? p.npts_head : 0;
@@ -454,6 +454,13 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   UP(p.sD_e0, sD_e0)
   UP(p.eD, eD)
   UP(p.ttab, ttab)
+  d.ndd = (int)p.dd_q.size();
+  if (d.ndd > 0) {
+    UP(p.dd_q, dd_q)
+    UP(p.dd_L, dd_L)
+    UP(p.dd_of, dd_of)
+    UP(p.slot_vf, slot_vf)
+  }
   if (d.fp32) {
     UP(wl.slot_pidx, slot_pidx)
     UP(wl.rho_items, rho_items)
@@ -490,6 +497,12 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   AL(rho, M * d.nslot)
   AL(Vc, M * d.nslot)
   AL(Epart, M * d.nred_blocks)
+  if (d.ndd > 0) {
+    AL(rhoD, M * d.nslot)
+    AL(VDc, M * d.nslot)
+    AL(ydd, M * d.ndd * kDDStride)
+    AL(yddF, M * d.ndd * kDDStride)
+  }
   AL(Jfold, M * (size_t)std::max(1, d.nsegJ))
   AL(yF, M * d.yF_size)
   d.nblocks = (int)p.blocks.size();
@@ -602,7 +615,30 @@ double pass_flops(const Plan &p, int L0, int L1, int ndm) {
   return f * ndm;
 }
 
-double total_pairs(const Plan &p) { return (double)p.npairs(); }
+// Algorithmic flops of the density transform (or, the same count, of the back
+// transform) over all pairs and ndm densities: per pair of class (la, lb), two
+// per term of sum_{ab} D_ab E^x E^y E^z (one term per Hermite index t of each
+// Cartesian element (a, b)), and two per entry of the Hermite -> relative-monomial
+// blocks of every degree <= la + lb.
+double pair_transform_flops(const Plan &p, int ndm) {
+  double f = 0.0;
+  for (int la = 0; la <= kMaxL; ++la)
+    for (int lb = 0; lb <= la; ++lb) {
+      const int cl = la * 4 + lb;
+      if (p.cls_b1[cl] <= p.cls_b0[cl]) continue;
+      double per = 0.0;
+      for (int ax = la; ax >= 0; --ax)
+        for (int ay = la - ax; ay >= 0; --ay)
+          for (int bx = lb; bx >= 0; --bx)
+            for (int by = lb - bx; by >= 0; --by) {
+              const int az = la - ax - ay, bz = lb - bx - by;
+              per += 2.0 * (ax + bx + 1) * (ay + by + 1) * (az + bz + 1);
+            }
+      for (int d = 0; d <= la + lb; ++d) per += 2.0 * ncart(d) * ncart(d);
+      f += per * (double)(p.blocks[p.cls_b1[cl] - 1].p1 - p.blocks[p.cls_b0[cl]].p0);
+    }
+  return f * ndm;
+}
 
 double cls_pairs(const Plan &p, int cl) {
   return (double)(p.blocks[p.cls_b1[cl] - 1].p1 - p.blocks[p.cls_b0[cl]].p0);
@@ -616,7 +652,7 @@ pwdf_status run_mid_rho(pwdf_ctx *c, int ndm, double *EJ, hipStream_t st) {
   const double nGh = (double)(p.nG_full / 2);
   pwdf_status s;
   char name[32];
-  if ((s = step(c, "transform", total_pairs(p) * ndm, st, [&] { return launch_transform_all(d, ndm, st); })) !=
+  if ((s = step(c, "transform", pair_transform_flops(p, ndm), st, [&] { return launch_transform_all(d, ndm, st); })) !=
       PWDF_OK)
     return s;
   if (d.fp32) {
@@ -650,7 +686,20 @@ pwdf_status run_mid_rho(pwdf_ctx *c, int ndm, double *EJ, hipStream_t st) {
     }
     if (hipError_t e = f.join()) return hip_fail(c, e, "join");
   }
-  return step(c, "reduce", (double)p.nslot() * ndm, st, [&] { return launch_reduce(d, ndm, EJ, st); });
+  if (d.ndd == 0)
+    return step(c, "reduce", (double)p.nslot() * ndm, st, [&] { return launch_reduce(d, ndm, EJ, st); });
+  // compact/diffuse classification: the reduce gives rho_C; then rho_D of the DD
+  // pairs, the combined potentials V_C and V_D and the energy partials
+  if ((s = step(c, "reduce", (double)p.nslot() * ndm, st, [&] { return launch_reduce(d, ndm, nullptr, st); })) !=
+      PWDF_OK)
+    return s;
+  if ((s = step(c, "rho_dd", (double)d.ndd * nGh * ndm, st, [&] { return launch_rho_dd(d, ndm, st); })) != PWDF_OK)
+    return s;
+  if ((s = step(c, "combine_dd", (double)p.nslot() * ndm, st, [&] { return launch_combine_dd(d, ndm, st); })) !=
+      PWDF_OK)
+    return s;
+  if (!EJ) return PWDF_OK;
+  return step(c, "energy", (double)ndm, st, [&] { return launch_energy(d, ndm, EJ, st); });
 }
 
 pwdf_status run_to_rho(pwdf_ctx *c, int ndm, const double *Dk, double *EJ, hipStream_t st) {
@@ -716,7 +765,10 @@ pwdf_status run_mid_j(pwdf_ctx *c, int ndm, hipStream_t st) {
                     PWDF_OK)
     return s;
   if ((s = run_moments(c, ndm, false, st)) != PWDF_OK) return s;
-  return step(c, "back", total_pairs(p) * ndm, st, [&] { return launch_back_all(d, ndm, st); });
+  if (d.ndd > 0 && (s = step(c, "jpass_dd", (double)d.ndd * (p.nG_full / 2) * ndm, st,
+                             [&] { return launch_jpass_dd(d, false, ndm, st); })) != PWDF_OK)
+    return s;
+  return step(c, "back", pair_transform_flops(p, ndm), st, [&] { return launch_back_all(d, ndm, st); });
 }
 
 // EJ: device [ndm] summed by the J(k) launch from the energy partials of the
@@ -772,6 +824,8 @@ static pwdf_status make_input(PlanInput &in, const double lattice[9], int natm, 
   in.eps_G = screen->eps_G;
   in.r_max = screen->r_max;
   in.pair_gcut = screen->pair_gcut != 0 ? 1 : 0;
+  if (!std::isfinite(screen->alpha_cut)) return fail(nullptr, PWDF_EINVAL, "alpha_cut must be finite");
+  in.alpha_cut = screen->alpha_cut > 0.0 ? screen->alpha_cut : 0.0;
   return PWDF_OK;
 }
 
@@ -790,7 +844,8 @@ static void fill_stats(const Plan &p, pwdf_stats *out) {
   out->nseg = p.nseg();
   // per build and density: both passes over the G each pair sees (its cut
   // sphere, or the whole half space)
-  out->pairG_evals = 2.0 * p.pairG_cut;
+  out->pairG_evals = 2.0 * p.pairG_cut + 2.0 * (double)p.dd_q.size() * (double)(p.nG_full / 2);
+  out->npairs_dd = (int64_t)p.dd_q.size();
   out->seg_len = p.seg_len;
   out->fork = 1;
   out->jk_support = (int64_t)(p.lightJ.size() + p.heavyJ.size());
@@ -915,6 +970,17 @@ pwdf_status pwdf_set_jk_layout(pwdf_ctx *c, int layout) {
   return PWDF_OK;
 }
 
+pwdf_status pwdf_set_fp32_head(pwdf_ctx *c, double weight) {
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_set_fp32_head: ctx is NULL");
+  if (!(weight > 0.0 && weight <= 1.0)) return fail(c, PWDF_EINVAL, "head weight must be in (0, 1]");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  // the workspaces are rebuilt below: nothing may still be running on them
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+  set_head_weight(c->plan, weight);
+  return setup_device(c, c->tune);
+}
+
 pwdf_status pwdf_get_jk_support(const pwdf_ctx *c, int *mu, int *nu) {
   if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_get_jk_support: ctx is NULL");
   const Plan &p = c->plan;
@@ -1014,6 +1080,11 @@ static size_t carve_build_ws(Dev &d, const Plan &p, int ndm, unsigned char *base
   take(d.rho, M * d.nslot);
   take(d.Vc, M * d.nslot);
   take(d.Epart, M * d.nred_blocks);
+  if (d.ndd > 0) {
+    take(d.rhoD, M * d.nslot);
+    take(d.VDc, M * d.nslot);
+    take(d.ydd, M * d.ndd * kDDStride);
+  }
   take(d.Jfold, M * (size_t)std::max(1, d.nsegJ));
   if (d.npts_head > 0) take(d.parth, M * d.nrows_h * d.npts_head);
   if (d.fp32) {
@@ -1100,6 +1171,9 @@ pwdf_status pwdf_grad(pwdf_ctx *c, int ndm, const double *Dk, double *dEdR, doub
   const Dev &d = c->dev;
   char name[32];
   if ((s = run_moments(c, ndm, true, st)) != PWDF_OK) return s;
+  if (d.ndd > 0 && (s = step(c, "jforce_dd", (double)d.ndd * (p.nG_full / 2) * ndm, st,
+                             [&] { return launch_jpass_dd(d, true, ndm, st); })) != PWDF_OK)
+    return s;
   {
     Fork f(c, st);
     for (int la = 0; la <= kMaxL; ++la)

@@ -107,6 +107,17 @@ struct Dev {
   double *gblk;              // [ndm][nblocks][6]
   int nblocks;
   const int *atom_off, *atom_ent;
+  // compact/diffuse classification (ndd > 0): the DD pairs (global pair index,
+  // class L), pair -> DD index or -1 (null without DD pairs), the full-range
+  // kernel per slot; rho_D and conj V_D per slot [ndm][nslot]; the DD pairs' J
+  // moments and force moments [ndm][ndd][kDDStride] (raw moments as the J pass
+  // writes them, read by the back transform and the force contraction instead of
+  // the pair's chunks)
+  int ndd;
+  const int *dd_q, *dd_L, *dd_of;
+  const double *slot_vf;
+  double2 *rhoD, *VDc;
+  double *ydd, *yddF;
   // launch shapes
   int ndb;  // densities per block of the low-L pair-G launches (1, 2 or 4)
   int rho_bs;
@@ -118,6 +129,9 @@ struct Dev {
   int64_t yhat_size;
   int nred_blocks;
 };
+
+// moments per DD pair and density: every degree up to the force moments of L = 6
+constexpr int kDDStride = nherm(kMaxLsum);
 
 // Allocation-free J build: the per-call workspaces are carved out of a static
 // device array of this many bytes (one per device, held for the process's life).
@@ -160,6 +174,14 @@ bool jpass_group_nonempty(const Dev &d, int group);
 hipError_t launch_fold_j(const Dev &d, int ndm, hipStream_t st);
 // EJ non-null: one more block per density sums the energy partials into EJ
 hipError_t launch_phase_j(const Dev &d, int ndm, double *Jk, double *EJ, hipStream_t st);
+// compact/diffuse classification: rho_D of the DD pairs, then V_C, V_D, rho =
+// rho_C + rho_D and the energy partials from rho_C (the reduce's rho) and rho_D;
+// the DD pairs' moments from V_D (force = true: degree L+1); E_J from the
+// energy partials
+hipError_t launch_rho_dd(const Dev &d, int ndm, hipStream_t st);
+hipError_t launch_combine_dd(const Dev &d, int ndm, hipStream_t st);
+hipError_t launch_jpass_dd(const Dev &d, bool force, int ndm, hipStream_t st);
+hipError_t launch_energy(const Dev &d, int ndm, double *EJ, hipStream_t st);
 // gradient
 hipError_t launch_force_back_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st);
 hipError_t launch_force_atoms(const Dev &d, int ndm, double *dEdR, hipStream_t st);

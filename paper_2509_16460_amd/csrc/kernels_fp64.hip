@@ -742,15 +742,26 @@ __device__ __forceinline__ void back_thread(const Dev &dv, int bi, int dm) {
     double y[NT];
 #pragma unroll
     for (int k = 0; k < NT; ++k) y[k] = 0.0;
-    int c = 0;
-    for (; c + 4 <= nchunks; c += 4) {
-      double v[4][NT];
+    // a DD pair (compact/diffuse classification) takes its moments of V_D from
+    // the DD kernel instead of the chunks (which hold zeros for it)
+    const int dq = dv.dd_of ? dv.dd_of[q] : -1;
+    if (dq >= 0) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int k = 0; k < NT; ++k) y[k] = dv.ydd[((size_t)dm * dv.ndd + dq) * kDDStride + k];
+    }
+    // chunks whose loads are issued together: 4 for the small classes, 1 for
+    // (3, 0), whose 20 moments per chunk would otherwise hold 160 registers
+    constexpr int NB = NT <= 10 ? 4 : 1;
+    int c = 0;
+    if (dq >= 0) c = nchunks;
+    for (; c + NB <= nchunks; c += NB) {
+      double v[NB][NT];
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
 #pragma unroll
         for (int k = 0; k < NT; ++k) v[u][k] = ys[((size_t)(c + u) * NT + k) * np];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < NB; ++u)
 #pragma unroll
         for (int k = 0; k < NT; ++k) y[k] += v[u][k];
     }
@@ -1038,7 +1049,12 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
     const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (rq - Lp0);
     // FP32-MFMA form: the chunks the pair's block of the J pass wrote
     const int nchunks = dv.jn_of ? dv.jn_of[rq] : nchunks_L;
+    const int dq = dv.dd_of ? dv.dd_of[q] : -1;  // DD pair: the DD kernel's moments
     for (int k = lane; k < NT; k += 64) {
+      if (dq >= 0) {
+        sY[k] = dv.ydd[((size_t)dm * dv.ndd + dq) * kDDStride + k];
+        continue;
+      }
       // chunk order kept; up to 16 loads in flight
       double s = 0.0;
       for (int c0 = 0; c0 < nchunks; c0 += 16) {
@@ -1273,9 +1289,14 @@ constexpr int kWaveLds = cmax(cmax(cmax(wave_lds<2, 1>(), wave_lds<3, 0>()), cma
                               cmax(wave_lds<3, 2>(), wave_lds<3, 3>()));
 
 // Wave-per-block bodies for the classes with L = la + lb >= 3: their per-lane
-// tables (E coefficients, Hermite and Cartesian vectors) would hold hundreds
-// of registers in a thread-per-block body.
-static bool wave_per_block(int L) { return L >= 3; }
+// tables (E coefficients, Hermite and Cartesian vectors) would hold hundreds of
+// registers in a thread-per-block body.  (3, 0) -- one f shell with one s shell,
+// 20 Hermite terms and 10 elements -- runs a thread per block instead, where a
+// wave per block would leave most lanes idle: inside the fused transform launch
+// (108 VGPRs), and in a launch of its own after the fused back transform (its
+// body inside the fused launch would take that launch to 255 VGPRs, one wave per
+// SIMD for every class).
+static bool wave_per_block(int la, int lb) { return la + lb >= 3 && !(la == 3 && lb == 0); }
 
 #define PWDF_CLASS_SWITCH_THREAD(F, ...)      \
   switch (cl) {                               \
@@ -1283,12 +1304,14 @@ static bool wave_per_block(int L) { return L >= 3; }
     case 4: F<1, 0>(__VA_ARGS__); break;      \
     case 5: F<1, 1>(__VA_ARGS__); break;      \
     case 8: F<2, 0>(__VA_ARGS__); break;      \
+    case 12:                                  \
+      if constexpr (kThread30) F<3, 0>(__VA_ARGS__); \
+      break;                                  \
     default: break;                           \
   }
 #define PWDF_CLASS_SWITCH_WAVE(F, ...)        \
   switch (cl) {                               \
     case 9: F<2, 1>(__VA_ARGS__); break;      \
-    case 12: F<3, 0>(__VA_ARGS__); break;     \
     case 10: F<2, 2>(__VA_ARGS__); break;     \
     case 13: F<3, 1>(__VA_ARGS__); break;     \
     case 14: F<3, 2>(__VA_ARGS__); break;     \
@@ -1306,6 +1329,7 @@ constexpr int kWavesPerWG = kPairWG / 64;
 // neighbouring D(L) blocks); the back transform takes them in the J walk order
 // (blk_cut), in which it reads the moments.
 __global__ __launch_bounds__(kPairWG) void k_transform_all(const Dev dv, const ClassTab tab) {
+  constexpr bool kThread30 = true;  // (3, 0): a thread per block
   __shared__ double lds[kWavesPerWG * kWaveLds];
   const int i = tab_entry(tab, blockIdx.x);
   const int local = blockIdx.x - tab.first[i];
@@ -1324,6 +1348,7 @@ __global__ __launch_bounds__(kPairWG) void k_transform_all(const Dev dv, const C
 }
 
 __global__ __launch_bounds__(kPairWG) void k_back_all(const Dev dv, const ClassTab tab) {
+  constexpr bool kThread30 = false;  // (3, 0): k_back_30
   __shared__ double lds[kWavesPerWG * kWaveLds];
   const int i = tab_entry(tab, blockIdx.x);
   const int local = blockIdx.x - tab.first[i];
@@ -1339,6 +1364,13 @@ __global__ __launch_bounds__(kPairWG) void k_back_all(const Dev dv, const ClassT
     if (j >= dv.cls_b1[cl]) return;
     PWDF_CLASS_SWITCH_THREAD(back_thread, dv, dv.blk_cut[j], dm)
   }
+}
+
+// The back transform of the class (3, 0), a thread per block in the J walk order.
+__global__ __launch_bounds__(kPairWG) void k_back_30(const Dev dv) {
+  const int j = dv.cls_b0[12] + blockIdx.x * kPairWG + threadIdx.x;
+  if (j >= dv.cls_b1[12]) return;
+  back_thread<3, 0>(dv, dv.blk_cut[j], blockIdx.y);
 }
 
 template <int L, int NDB>
@@ -1491,20 +1523,21 @@ static void add_entry(ClassTab &t, int cls, int mode, int gx, int nblocks) {
 // transform / back: one entry per non-empty class (la, lb); the wave-mode classes
 // first, so that their long per-pair chains start early and overlap the
 // thread-mode blocks instead of forming the launch's tail
-static ClassTab pair_class_tab(const Dev &d) {
+static ClassTab pair_class_tab(const Dev &d, bool back) {
+  // the back transform's (3, 0) blocks go to k_back_30
   ClassTab t{};
   for (int wave = 1; wave >= 0; --wave)
     for (int la = 0; la <= kMaxL; ++la)
       for (int lb = 0; lb <= la; ++lb) {
         const int cl = la * 4 + lb, nb = d.cls_b1[cl] - d.cls_b0[cl];
-        if (nb <= 0 || (wave_per_block(la + lb) ? 1 : 0) != wave) continue;
+        if (nb <= 0 || (wave_per_block(la, lb) ? 1 : 0) != wave || (back && cl == 12)) continue;
         add_entry(t, cl, wave, 0, wave ? (nb + kWavesPerWG - 1) / kWavesPerWG : (nb + kPairWG - 1) / kPairWG);
       }
   return t;
 }
 
 hipError_t launch_transform_all(const Dev &d, int ndm, hipStream_t st) {
-  const ClassTab t = pair_class_tab(d);
+  const ClassTab t = pair_class_tab(d, false);
   if (t.n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_transform_all, dim3((unsigned)t.first[t.n], ndm), dim3(kPairWG), 0, st, d, t);
   PWDF_CHECK_LAUNCH();
@@ -1512,10 +1545,16 @@ hipError_t launch_transform_all(const Dev &d, int ndm, hipStream_t st) {
 }
 
 hipError_t launch_back_all(const Dev &d, int ndm, hipStream_t st) {
-  const ClassTab t = pair_class_tab(d);
-  if (t.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_back_all, dim3((unsigned)t.first[t.n], ndm), dim3(kPairWG), 0, st, d, t);
-  PWDF_CHECK_LAUNCH();
+  const ClassTab t = pair_class_tab(d, true);
+  if (t.n > 0) {
+    hipLaunchKernelGGL(k_back_all, dim3((unsigned)t.first[t.n], ndm), dim3(kPairWG), 0, st, d, t);
+    PWDF_CHECK_LAUNCH();
+  }
+  const int n30 = d.cls_b1[12] - d.cls_b0[12];
+  if (n30 > 0) {
+    hipLaunchKernelGGL(k_back_30, dim3((unsigned)((n30 + kPairWG - 1) / kPairWG), ndm), dim3(kPairWG), 0, st, d);
+    PWDF_CHECK_LAUNCH();
+  }
   return hipSuccess;
 }
 
@@ -1674,6 +1713,10 @@ hipError_t launch_reduce(const Dev &d, int ndm, double *EJ, hipStream_t st) {
                      d.Epart);
   PWDF_CHECK_LAUNCH();
   if (EJ == nullptr) return hipSuccess;  // summed by the J(k) launch
+  return launch_energy(d, ndm, EJ, st);
+}
+
+hipError_t launch_energy(const Dev &d, int ndm, double *EJ, hipStream_t st) {
   hipLaunchKernelGGL(k_energy, dim3(ndm), dim3(256), 0, st, d.Epart, d.nred_blocks, EJ);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;

@@ -22,7 +22,9 @@ __global__ __launch_bounds__(64) void k_force_back(const BlockRec *__restrict__ 
                                                    const double *__restrict__ yF, int64_t yF_size, int64_t yF_off,
                                                    int nchunks, int Lp0, int Lp1, const int *__restrict__ cut_rank,
                                                    const double *__restrict__ Dblk, int64_t nelem,
-                                                   double *__restrict__ gblk, int nblocks) {
+                                                   double *__restrict__ gblk, int nblocks,
+                                                   const int *__restrict__ dd_of, const double *__restrict__ yddF,
+                                                   int ndd) {
   constexpr int L = LA + LB;
   constexpr int L1 = L + 1;
   constexpr int NT1 = nherm(L1);
@@ -38,11 +40,18 @@ __global__ __launch_bounds__(64) void k_force_back(const BlockRec *__restrict__ 
   double gA[3] = {0.0, 0.0, 0.0}, gB[3] = {0.0, 0.0, 0.0};
   for (int q = b.p0; q < b.p1; ++q) {
     const double *ys = yF + (size_t)dm * yF_size + yF_off + (cut_rank[q] - Lp0);  // J walk order
+    // a DD pair (compact/diffuse classification) takes its force moments of V_D
+    // from the DD kernel
+    const int dq = dd_of ? dd_of[q] : -1;
     double y[NT1];
 #pragma unroll
     for (int k = 0; k < NT1; ++k) {
       double s = 0.0;
-      for (int c = 0; c < nchunks; ++c) s += ys[((size_t)c * NT1 + k) * np];
+      if (dq >= 0) {
+        s = yddF[((size_t)dm * ndd + dq) * kDDStride + k];
+      } else {
+        for (int c = 0; c < nchunks; ++c) s += ys[((size_t)c * NT1 + k) * np];
+      }
       y[k] = s;
     }
     // Hermite moments J~_t = Re sum_G conj V S (-iG)^t, |t| <= L+1
@@ -168,7 +177,7 @@ static hipError_t fback_one(const Dev &d, int ndm, hipStream_t st) {
   dim3 grid((unsigned)((b1 - b0 + 63) / 64), ndm);
   hipLaunchKernelGGL((k_force_back<LA, LB>), grid, dim3(64), 0, st, d.blocks, b0, b1, d.aux, d.ttab, d.yF, d.yF_size,
                      d.yF_off[L], d.j_chunks[L], d.L_p0[L], d.L_p1[L], d.cut_rank, d.Dblk, d.nelem, d.gblk,
-                     d.nblocks);
+                     d.nblocks, d.ndd > 0 ? d.dd_of : nullptr, d.yddF, d.ndd);
   PWDF_CHECK_LAUNCHG();
   return hipSuccess;
 }

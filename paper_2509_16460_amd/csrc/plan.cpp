@@ -165,10 +165,13 @@ double cut_radius(const CutPair &c, double omega, double eps_G) {
 
 }  // namespace
 
+static void head_points(Plan &p);
+
 void build_segments(Plan &p, int seg_len) {
   p.seg_len = seg_len;
   p.segs.clear();
   p.slot_v.clear();
+  p.slot_vf.clear();
   p.slot_miller.clear();
   p.valid_slots.clear();
   p.pts.clear();
@@ -232,19 +235,21 @@ void build_segments(Plan &p, int seg_len) {
       int sidx = (int)p.segs.size();
       for (int s = 0; s < seg_len; ++s) {
         int n[3] = {0, 0, 0};
-        double vg = 0.0;
+        double vg = 0.0, vf = 0.0;
         if (s < sd.cnt) {
           n[u] = nu0 + s;
           n[v] = nv;
           n[w] = nw;
           double g2 = g2_of(p, n);
           vg = 4.0 * kPi * std::exp(-g2 / w4) / g2;
+          vf = 4.0 * kPi / g2;
           sd.g2min = std::min(sd.g2min, g2);
           p.valid_slots.push_back(sidx * seg_len + s);
           p.pts.push_back({g2, nu0 + s, nv, nw, sidx * seg_len + s});
           ++count;
         }
         p.slot_v.push_back(vg);
+        p.slot_vf.push_back(vf);
         for (int c3 = 0; c3 < 3; ++c3) p.slot_miller.push_back(n[c3]);
       }
       p.segs.push_back(sd);
@@ -256,10 +261,36 @@ void build_segments(Plan &p, int seg_len) {
   // tiles of the point-wise kernels; v(G) decreases with |G|, so the head (v(G) >=
   // kHeadWeight max v) is a prefix.
   std::stable_sort(p.pts.begin(), p.pts.end(), [](const GPoint &a, const GPoint &b) { return a.g2 < b.g2; });
+  head_points(p);
+}
+
+// The head: the prefix of the |G|-ordered points with v(G) >= head_weight max v.
+static void head_points(Plan &p) {
   const double vmax = p.pts.empty() ? 0.0 : p.slot_v[p.pts[0].slot];
   p.npts_head = 0;
-  while (p.npts_head < (int)p.pts.size() && p.slot_v[p.pts[p.npts_head].slot] >= kHeadWeight * vmax) ++p.npts_head;
+  while (p.npts_head < (int)p.pts.size() && p.slot_v[p.pts[p.npts_head].slot] >= p.head_weight * vmax)
+    ++p.npts_head;
   p.head_g2 = p.npts_head > 0 ? p.pts[p.npts_head - 1].g2 : 0.0;
+}
+
+// Head points within each pair's cut, per class L and in total.
+static void head_pair_counts(Plan &p) {
+  std::vector<double> hg2;
+  for (int i = 0; i < p.npts_head; ++i) hg2.push_back(p.pts[i].g2);
+  std::sort(hg2.begin(), hg2.end());
+  p.pairG_head = 0.0;
+  for (int L = 0; L <= kMaxLsum; ++L) {
+    p.pairG_head_L[L] = 0.0;
+    for (int q = p.L_p0[L]; q < p.L_p1[L]; ++q)
+      p.pairG_head_L[L] += (double)(std::upper_bound(hg2.begin(), hg2.end(), p.hot[q].gc2) - hg2.begin());
+    p.pairG_head += p.pairG_head_L[L];
+  }
+}
+
+void set_head_weight(Plan &p, double weight) {
+  p.head_weight = weight;
+  head_points(p);
+  head_pair_counts(p);
 }
 
 std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
@@ -504,6 +535,26 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
     p.blocks.push_back(br);
   }
   p.nelem = eoff;
+  // Compact/diffuse classification (section "Density classification: compact
+  // and diffuse"; alpha_cut = w^2/2 by eq. "cd cutoff" is the caller's choice):
+  // a primitive pair whose two exponents both lie below alpha_cut is a DD pair.
+  // Its gc2 of -1 takes it out of the compact pairs' pair-G passes; the DD
+  // kernels evaluate it over the whole G set with the full-range potential.
+  p.dd_q.clear();
+  p.dd_L.clear();
+  p.dd_of.assign(p.hot.size(), -1);
+  if (in.alpha_cut > 0.0) {
+    for (const BlockRec &br : p.blocks) {
+      const int L = in.sh_l[br.sa] + in.sh_l[br.sb];
+      for (int q = br.p0; q < br.p1; ++q)
+        if (p.aux[q].alpha_a < in.alpha_cut && p.aux[q].alpha_b < in.alpha_cut) {
+          p.dd_of[q] = (int)p.dd_q.size();
+          p.dd_q.push_back(q);
+          p.dd_L.push_back(L);
+          p.hot[q].gc2 = -1.0;
+        }
+    }
+  }
   // Pair-G work inside the cuts: for each pair and G line (fixed n_v, n_w) the
   // n_u with |G(n_u)|^2 = M_uu n_u^2 + 2 b n_u + c <= gc2 lie between the roots
   // of the quadratic (eq. "G-space root finding"), clipped to the line's range.
@@ -551,8 +602,11 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
   // arguments up to ~700) and the recurrence multiplies them: a pair so diffuse
   // that these overflow or underflow is rejected rather than summed as inf / 0.
   {
+    // (DD pairs excluded: the DD kernels evaluate their factors directly)
     double pmin = 1e300;
-    for (const PairAux &x : p.aux) pmin = std::min(pmin, x.p);
+    for (size_t q = 0; q < p.aux.size(); ++q)
+      if (p.dd_of[q] < 0) pmin = std::min(pmin, p.aux[q].p);
+    if (pmin == 1e300) pmin = 1.0;
     const double gcut2 = 4.0 * in.omega * in.omega * (-std::log(in.eps_G));
     const double bu2 = p.M[p.ax[0]][p.ax[0]];
     p.max_start_arg = std::max(gcut2, 2.0 * std::sqrt(gcut2 * bu2) + bu2) / (4.0 * pmin);
@@ -606,23 +660,12 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
     p.dhat_size = off;
   }
   p.pairG_cut = 0.0;
-  p.pairG_head = 0.0;
-  {
-    // head G within each pair's cut
-    std::vector<double> hg2;
-    for (int i = 0; i < p.npts_head; ++i) hg2.push_back(p.pts[i].g2);
-    std::sort(hg2.begin(), hg2.end());
-    for (int L = 0; L <= kMaxLsum; ++L) {
-      p.pairG_L[L] = 0.0;
-      p.pairG_head_L[L] = 0.0;
-      for (int q = p.L_p0[L]; q < p.L_p1[L]; ++q) {
-        p.pairG_L[L] += p.pairG_of[q];
-        p.pairG_head_L[L] += (double)(std::upper_bound(hg2.begin(), hg2.end(), p.hot[q].gc2) - hg2.begin());
-      }
-      p.pairG_cut += p.pairG_L[L];
-      p.pairG_head += p.pairG_head_L[L];
-    }
+  for (int L = 0; L <= kMaxLsum; ++L) {
+    p.pairG_L[L] = 0.0;
+    for (int q = p.L_p0[L]; q < p.L_p1[L]; ++q) p.pairG_L[L] += p.pairG_of[q];
+    p.pairG_cut += p.pairG_L[L];
   }
+  head_pair_counts(p);
   {
     std::vector<int> order(p.hot.size());
     for (size_t i = 0; i < p.hot.size(); ++i) order[i] = (int)i;

@@ -19,10 +19,18 @@ struct PlanInput {
   int kmesh[3];
   double omega, eps_pair, eps_G, r_max;
   int pair_gcut = 0;  // 1: every pair block gets its own cut radius (section "Integral screening")
+  // > 0: compact/diffuse classification (section "Density classification:
+  // compact and diffuse"): pairs of two primitives with exponents below it are
+  // DD pairs, taken with the full-range kernel against everything
+  double alpha_cut = 0.0;
 };
 
-// Relative Coulomb weight that bounds the head of the G set (see Plan::npts_head).
-constexpr double kHeadWeight = 1.0 / 128.0;
+// Default relative Coulomb weight that bounds the head of the G set (see
+// Plan::npts_head): with 2^-20 the FP32 tail carries a small enough share of the
+// energy and of J that its rounding stays near 1e-9 Eh in E_J and 2e-10 in J on
+// the rock-salt slab (E_J ~3.4e3 Eh, max|J| ~29), against targets of 1e-7 Eh and
+// 1e-8 (2^-16: 6e-8 Eh and up to 1.2e-8 in J over the tuner's shapes).
+constexpr double kHeadWeight = 1.0 / 1048576.0;
 
 struct Plan {
   PlanInput in;
@@ -41,8 +49,9 @@ struct Plan {
   std::vector<int> valid_slots;     // slots holding a G, in walk order
   std::vector<GPoint> pts;          // the same G vectors as a compact point list, by |G|^2
   // The head of the G set: the vectors whose Coulomb weight v(G) is at least
-  // kHeadWeight times the largest one (the shortest |G|).  The FP32-MFMA form
+  // head_weight times the largest one (the shortest |G|).  The FP32-MFMA form
   // evaluates them with FP64 tiles; pts[0, npts_head) are the head.
+  double head_weight = kHeadWeight;
   int npts_head = 0;
   double head_g2 = 0.0;             // largest |G|^2 of the head
   double pairG_head = 0.0;          // sum over pairs of the head G within their cut (per pass)
@@ -112,6 +121,15 @@ struct Plan {
   // the sign of (-i)^{|k|} folded into the rho coefficients / J moments
   std::vector<double> ttab;
 
+  // DD pairs (both exponents below alpha_cut): their gc2 is -1, so the pair-G
+  // passes of the compact pairs skip them; dd_q lists them (global pair index),
+  // dd_L their class L, dd_of[pair] their index in that list or -1.  slot_vf is
+  // the full-range kernel 4 pi/|G|^2 per slot (0 on padding).
+  std::vector<int> dd_q, dd_L, dd_of;
+  std::vector<double> slot_vf;
+  // the pair-G kernels must honour gc2 (per-pair cuts, or DD pairs to skip)
+  bool cut_on() const { return in.pair_gcut != 0 || !dd_q.empty(); }
+
   int nseg() const { return (int)segs.size(); }
   int nslot() const { return (int)segs.size() * seg_len; }
   int npairs() const { return (int)hot.size(); }
@@ -123,5 +141,9 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &out);
 
 // Rebuild only the reciprocal-space segments for another segment length.
 void build_segments(Plan &p, int seg_len);
+
+// Set the relative weight that bounds the head of the G set (0 < weight <= 1)
+// and recount the head's points and pair-G work.
+void set_head_weight(Plan &p, double weight);
 
 }  // namespace pwdf

@@ -29,7 +29,7 @@ PWDF_JK_PACKED = 2
 EXPORTED = ["pwdf_create", "pwdf_query", "pwdf_build_j", "pwdf_build_j_graph", "pwdf_get_rhoG", "pwdf_grad",
             "pwdf_autotune", "pwdf_last_error", "pwdf_destroy", "pwdf_plan_stats",
             "pwdf_profile_enable", "pwdf_profile_read", "pwdf_set_jk_layout", "pwdf_check_input",
-            "pwdf_get_jk_support", "pwdf_build_j_noalloc"]
+            "pwdf_get_jk_support", "pwdf_build_j_noalloc", "pwdf_set_fp32_head"]
 
 
 class PwdfError(RuntimeError):
@@ -40,7 +40,12 @@ class PwdfError(RuntimeError):
 
 class Screen(ctypes.Structure):
     _fields_ = [("eps_pair", ctypes.c_double), ("eps_G", ctypes.c_double), ("r_max", ctypes.c_double),
-                ("pair_gcut", ctypes.c_int)]
+                ("pair_gcut", ctypes.c_int), ("alpha_cut", ctypes.c_double)]
+
+
+def _screen(prob) -> Screen:
+    return Screen(prob.eps_pair, prob.eps_G, prob.r_max, int(getattr(prob, "pair_gcut", 0)),
+                  float(getattr(prob, "alpha_cut", 0.0)))
 
 
 class Stats(ctypes.Structure):
@@ -49,7 +54,8 @@ class Stats(ctypes.Structure):
                 ("nblocks", ctypes.c_int64), ("nseg", ctypes.c_int64), ("pairG_evals", ctypes.c_double),
                 ("t_us", ctypes.c_double * 8), ("seg_len", ctypes.c_int64),
                 ("fork", ctypes.c_int64), ("jk_support", ctypes.c_int64), ("dk_support", ctypes.c_int64),
-                ("jk_layout", ctypes.c_int64), ("nG_head", ctypes.c_int64), ("pairG_head", ctypes.c_double)]
+                ("jk_layout", ctypes.c_int64), ("nG_head", ctypes.c_int64), ("pairG_head", ctypes.c_double),
+                ("npairs_dd", ctypes.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("npairs_by_class", "t_us")}
@@ -99,6 +105,8 @@ def lib():
         L.pwdf_profile_read.argtypes = [vp, ctypes.POINTER(KProf), ctypes.c_int, ip]
         L.pwdf_set_jk_layout.restype = ctypes.c_int
         L.pwdf_set_jk_layout.argtypes = [vp, ctypes.c_int]
+        L.pwdf_set_fp32_head.restype = ctypes.c_int
+        L.pwdf_set_fp32_head.argtypes = [vp, ctypes.c_double]
         L.pwdf_get_jk_support.restype = ctypes.c_int
         L.pwdf_get_jk_support.argtypes = [vp, ip, ip]
         L.pwdf_check_input.restype = ctypes.c_int
@@ -136,7 +144,7 @@ def plan_stats(prob) -> dict:
     """Host-only plan sizes (no device needed)."""
     a = _basis_arrays(prob)
     st = Stats()
-    scr = Screen(prob.eps_pair, prob.eps_G, prob.r_max, int(getattr(prob, "pair_gcut", 0)))
+    scr = _screen(prob)
     rc = lib().pwdf_plan_stats(_dp(a["lat"]), prob.natm, _dp(a["xyz"]), prob.nshell, _ip(a["sa"]), _ip(a["sl"]),
                                _ip(a["sn"]), _dp(a["ex"]), _dp(a["co"]), _ip(a["km"]), float(prob.omega),
                                ctypes.byref(scr), ctypes.byref(st))
@@ -155,7 +163,7 @@ class LongRangeJ:
         self.device = device
         a = _basis_arrays(prob)
         self._keep = a
-        scr = Screen(prob.eps_pair, prob.eps_G, prob.r_max, int(getattr(prob, "pair_gcut", 0)))
+        scr = _screen(prob)
         h = ctypes.c_void_p()
         rc = lib().pwdf_create(ctypes.byref(h), _dp(a["lat"]), prob.natm, _dp(a["xyz"]), prob.nshell, _ip(a["sa"]),
                                _ip(a["sl"]), _ip(a["sn"]), _dp(a["ex"]), _dp(a["co"]), _ip(a["km"]),
@@ -201,6 +209,13 @@ class LongRangeJ:
         if tuple(Dk.shape[1:]) != (p.nk, p.nbf, p.nbf):
             raise ValueError(f"Dk shape {tuple(Dk.shape)} != [ndm, {p.nk}, {p.nbf}, {p.nbf}]")
         return Dk
+
+    def set_fp32_head(self, weight: float):
+        """FP32-MFMA form: G vectors with v(G) >= weight * max v take FP64 tiles
+        (default 2^-20); rebuilds the workspaces."""
+        rc = lib().pwdf_set_fp32_head(self._h, float(weight))
+        if rc != 0:
+            self._err(rc)
 
     def set_jk_layout(self, layout: int):
         """PWDF_JK_FULL (every element of J(k) written), PWDF_JK_SUPPORT (only the

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     txt = open(os.path.join(ROOT, "include", "pwdf.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(pwdf_[A-Za-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(pwdf_\w+)\s*\(", txt)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -76,6 +76,7 @@ def bad(prob, **kw):
     (dict(shell_l=None), "PWDF_EUNSUPPORTED"),
     (dict(exps=None), "PWDF_EINVAL"),
     (dict(shell_atom=None), "PWDF_EINVAL"),
+    (dict(alpha_cut=float("inf")), "PWDF_EINVAL"),
 ])
 def test_host_validation(mutate, status):
     prob = synth.small_problem(kind="v", seed=4, lmax=1, natm=2)
@@ -164,3 +165,30 @@ def test_support_counts(cfg):
     assert s["jk_support"] == int(mask.sum())
     assert int(np.triu(mask | mask.T).sum()) <= s["dk_support"] <= int(mask.sum())
     assert s["jk_layout"] == 0
+
+
+def test_dd_pairs_counted_by_the_plan():
+    """Compact/diffuse classification (section "Density classification: compact and
+    diffuse"): DD pairs = unique primitive pairs of two exponents below alpha_cut,
+    counted on the host from the oracle's own pair list; they leave the compact
+    passes (their per-pair G work moves to the DD pass over the whole half space)."""
+    lat = np.array([[4.2, 0.0, 0.0], [0.3, 4.6, 0.0], [-0.4, 0.5, 3.9]])
+    xyz = np.array([[0.2, 0.1, 0.3], [2.0, 2.5, 1.7]])
+    prob = synth.build_problem("dd", lat, xyz, [0, 0], {0: [np.array([2.2, 0.09]), np.array([1.3, 0.1])]},
+                               (2, 1, 1), 0.5)
+    ac = 0.125
+    ex = np.asarray(prob.exps)
+    assert (ex < ac).any() and (ex > ac).any()
+    pl = O.pairs(prob)
+    dd_full = int(np.sum((ex[pl[:, 2]] < ac) & (ex[pl[:, 3]] < ac)))
+    diag = int(np.sum((ex[pl[:, 2]] < ac) & (ex[pl[:, 3]] < ac) & (pl[:, 0] == pl[:, 1])
+                      & np.all(pl[:, 4:7] == 0, axis=1)))
+    st = pwdf.plan_stats(prob.with_(alpha_cut=ac))
+    st0 = pwdf.plan_stats(prob)
+    assert st0["npairs_dd"] == 0
+    assert 2 * st["npairs_dd"] - diag == dd_full
+    assert st["npairs"] == st0["npairs"]
+    assert st["pairG_evals"] == st0["pairG_evals"]  # without cuts every pair sees the half space
+    stc = pwdf.plan_stats(prob.with_(alpha_cut=ac, pair_gcut=1))
+    stc0 = pwdf.plan_stats(prob.with_(pair_gcut=1))
+    assert stc["pairG_evals"] >= stc0["pairG_evals"]  # DD pairs lose their cut

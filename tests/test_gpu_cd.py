@@ -1,0 +1,132 @@
+"""Compact/diffuse classification on the GPU vs the FP64 oracle, through the C ABI.
+
+Section "Density classification: compact and diffuse", eq. "cd cutoff"
+(alpha_cut = w^2/2): DD pairs (two exponents below alpha_cut) interact in full
+(4 pi/G^2) with everything, compact pairs keep the long-range kernel among
+themselves.  Bars as for the unclassified path: FP64 |dE_J| <= 1e-10 Eh, max
+|dJ(k)| <= 1e-11, rho(G) (rho_C + rho_D) 1e-12 relative, gradient 1e-10; the
+FP32-MFMA form (the DD pairs stay FP64) within its bars against the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_16460_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+E_TOL = 1e-10
+J_TOL = 1e-11
+
+
+def pw():
+    from paper_2509_16460_amd import pwdf
+    return pwdf
+
+
+def cd_problem(kmesh=(2, 1, 1), lmax=2, natm=2, seed=61, pair_gcut=0):
+    """One diffuse and one compact exponent per l against alpha_cut = 0.125
+    (w = 0.5): CC, CD and DD pairs of every class up to (lmax, lmax)."""
+    rng = np.random.default_rng(seed)
+    lat = np.array([[4.2, 0.0, 0.0], [0.3, 4.6, 0.0], [-0.4, 0.5, 3.9]])
+    xyz = rng.uniform(0, 1, size=(natm, 3)) @ lat
+    ex = {0: [np.array(e) for e in ([2.2, 0.09], [1.3, 0.1], [0.9, 0.11], [0.7, 0.12])[:lmax + 1]]}
+    prob = synth.build_problem("cd", lat, xyz, [0] * natm, ex, kmesh, 0.5, nelec=2.0 * natm, seed=seed)
+    return prob.with_(alpha_cut=0.125, pair_gcut=pair_gcut)
+
+
+CASES = {
+    "spd_k211": dict(kmesh=(2, 1, 1), lmax=2, seed=61),
+    "spd_k211_cut": dict(kmesh=(2, 1, 1), lmax=2, seed=61, pair_gcut=1),
+    "spdf_gamma": dict(kmesh=(1, 1, 1), lmax=3, natm=1, seed=62),
+    "sp_k221_3atoms": dict(kmesh=(2, 2, 1), lmax=1, natm=3, seed=63),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def cd_ref(request):
+    prob = cd_problem(**CASES[request.param])
+    D = synth.make_density(prob, 71)
+    ref = O.build_j(prob, D)
+    return request.param, prob, D, ref
+
+
+def build(prob, D, prec, graph=False):
+    ctx = pw().LongRangeJ(prob, precision=prec, max_ndm=D.shape[0])
+    Dt = torch.from_numpy(np.ascontiguousarray(D)).cuda()
+    J, E = ctx.build_j(Dt, graph=graph)
+    torch.cuda.synchronize()
+    return ctx, Dt, J.cpu().numpy(), E.cpu().numpy()
+
+
+def test_plan_counts_dd_pairs(cd_ref):
+    name, prob, D, ref = cd_ref
+    st = pw().plan_stats(prob)
+    st0 = pw().plan_stats(prob.with_(alpha_cut=0.0))
+    assert st["npairs_dd"] > 0 and st0["npairs_dd"] == 0
+    assert st["npairs"] == st0["npairs"]
+    # the DD pairs leave the compact passes and see the whole half space instead
+    assert st["pairG_evals"] >= st0["pairG_evals"]
+
+
+def test_fp64_matches_oracle(cd_ref):
+    name, prob, D, ref = cd_ref
+    ctx, Dt, J, E = build(prob, D[None], 0)
+    dE = abs(E[0] - ref["E_G"])
+    dJ = np.max(np.abs(J[0] - ref["J"]))
+    print(f"{name}: E_J={E[0]:.12f} oracle={ref['E_G']:.12f} dE={dE:.2e} max|dJ|={dJ:.2e} "
+          f"ndd={ctx.stats()['npairs_dd']}")
+    assert dE <= E_TOL and dJ <= J_TOL
+    # graph replay gives the same bits
+    _, _, Jg, Eg = build(prob, D[None], 0, graph=True)
+    assert np.array_equal(Jg, J) and np.array_equal(Eg, E)
+
+
+def test_rho_is_rho_c_plus_rho_d(cd_ref):
+    name, prob, D, ref = cd_ref
+    ctx = pw().LongRangeJ(prob, precision=0, max_ndm=1)
+    rho, mil = ctx.get_rhoG(torch.from_numpy(D[None]).cuda())
+    rho = rho.cpu().numpy()[0]
+    idx = {tuple(m): i for i, m in enumerate(ref["miller"])}
+    ro = np.array([ref["rho"][idx[tuple(m)]] for m in mil])
+    err = np.max(np.abs(rho - ro)) / np.max(np.abs(ro))
+    print(f"{name}: max|drho|/max|rho| = {err:.2e}")
+    assert err <= 1e-12
+
+
+def test_fp32_mfma_matches_oracle(cd_ref):
+    name, prob, D, ref = cd_ref
+    _, _, J, E = build(prob, D[None], 1)
+    dE = abs(E[0] - ref["E_G"])
+    dJ = np.max(np.abs(J[0] - ref["J"]))
+    print(f"{name}: FP32-MFMA dE={dE:.2e} max|dJ|={dJ:.2e}")
+    assert dE <= 1e-7 and dJ <= 1e-8
+
+
+def test_gradient_matches_oracle():
+    prob = cd_problem(kmesh=(2, 1, 1), lmax=2, seed=64)
+    D = synth.make_density(prob, 72)
+    ref = O.build_j(prob, D, want_J=False, want_rho=False, want_grad=True)
+    ctx = pw().LongRangeJ(prob, precision=0, max_ndm=1)
+    g, E = ctx.grad(torch.from_numpy(D[None]).cuda())
+    g = g.cpu().numpy()[0]
+    err = np.max(np.abs(g - ref["grad"]))
+    print(f"gradient: max|g|={np.max(np.abs(ref['grad'])):.3e} max|dg|={err:.2e} dE={abs(E.item() - ref['E_G']):.2e}")
+    assert err <= 1e-10 and abs(E.item() - ref["E_G"]) <= E_TOL
+
+
+def test_batched_densities_match_single():
+    """Three densities per call: FP64 bit for bit equal to one-density calls (the
+    DD kernels sum every density in the same order); FP32-MFMA within the
+    batched-vs-single bar of that form (its MFMA column layout depends on the
+    batch)."""
+    prob = cd_problem(kmesh=(2, 1, 1), lmax=2, seed=65)
+    Ds = np.stack([synth.make_density(prob, 80 + i) for i in range(3)])
+    for prec, tol in ((0, 0.0), (1, 1e-8)):
+        _, _, Jb, Eb = build(prob, Ds, prec)
+        for i in range(3):
+            _, _, J1, E1 = build(prob, Ds[i:i + 1], prec)
+            print(f"prec {prec} density {i}: dE={abs(Eb[i] - E1[0]):.2e} max|dJ|={np.max(np.abs(Jb[i] - J1[0])):.2e}")
+            assert abs(Eb[i] - E1[0]) <= tol * abs(E1[0])
+            assert np.max(np.abs(Jb[i] - J1[0])) <= tol * np.max(np.abs(J1[0]))

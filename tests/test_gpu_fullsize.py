@@ -17,15 +17,13 @@ Bars.  FP64: 1e-10 Eh and 1e-11 in J(k) where E_J and J are O(1) (diamond);
 on the slab E_J is ~3.4e3 Eh and max|J| ~29, where the FP64 rounding of the
 sums alone is ~1e-13 relative, so the bars there are relative: 1e-13 |E_J| and
 1e-11 max(1, max|J|) (the absolute bars read as relative ones once E_J and J
-are far from unit size).  FP32-MFMA: the targets 1e-7 Eh / 1e-8 in J are tested on the cubic
-cell (test_gpu_fp32.py).  On the large cells the FP32 tiles carry only the tail
-of the G set (the head, where the Coulomb weight is within 2^-7 of its largest,
-takes FP64 tiles), and the error of the sums of FP32 products scales with the
-tail's weights: measured on the slab 5e-11 to 7e-10 |E_J| and ~1e-8 max|J|
-(~2e-7 absolute in J, ~1e-6 Eh in E_J of ~3.4e3 Eh), on the diamond cell
-~4e-11 Eh and ~5e-10 in J.  The bars are those levels with a margin of about
-ten: slab E_J within 5e-9 |E_J| and J(k) within 5e-8 max|J|; diamond 1e-9 Eh
-and 5e-9 in J.
+are far from unit size).  FP32-MFMA: the FP32 tiles carry only the tail of the G
+set (the head, where the Coulomb weight is within 2^-20 of its largest, takes
+FP64 tiles), and the error of the sums of FP32 products scales with the tail's
+share of the energy; the bars are the targets themselves, 1e-7 Eh in E_J and
+1e-8 in J(k), absolute, on the slab (E_J ~3.4e3 Eh; measured ~1e-9 Eh and
+~2e-10 over the 16 densities) and the diamond cell (tighter there: 1e-9 Eh and
+5e-9).
 """
 import os
 
@@ -109,17 +107,16 @@ def test_slab_batch16_fp32_mfma(slab):
         dJ = float(np.max(np.abs(sampled(J32[i], pos, f[f"idx_{i}"]) - f[f"J_{i}"])))
         print(f"slab FP32-MFMA batch density {i} vs oracle: dE={dE:.2e} ({dE / abs(Eo):.1e} rel) "
               f"max|dJ|={dJ:.2e} ({dJ / jmax:.1e} of max|J|)", flush=True)
-        assert dE <= 5e-9 * abs(Eo)
-        assert dJ <= 5e-8 * jmax
+        assert dE <= 1e-7
+        assert dJ <= 1e-8
     c64, pos64 = packed_ctx(p, 0, 16, tune=False)
     assert pos64 == pos
     J64, E64 = run_packed(c64, Db, 16)
-    relE = np.abs(E32 - E64) / np.abs(E64)
+    dE = np.abs(E32 - E64)
     dJ = np.max(np.abs(J32 - J64), axis=(1, 2))
-    jmax = np.max(np.abs(J64))
-    print("slab FP32-MFMA vs FP64 batch, per density: relE " + " ".join(f"{x:.1e}" for x in relE) +
+    print("slab FP32-MFMA vs FP64 batch, per density: dE " + " ".join(f"{x:.1e}" for x in dE) +
           " | max|dJ| " + " ".join(f"{x:.1e}" for x in dJ), flush=True)
-    assert np.all(relE <= 5e-9) and np.all(dJ <= 5e-8 * jmax)
+    assert np.all(dE <= 1e-7) and np.all(dJ <= 1e-8)
 
 
 @pytest.fixture(scope="module")

@@ -153,11 +153,12 @@ def test_plan_root_finding_count_matches_brute_force(name, prob):
 ], ids=["cubic2_gamma", "spdf_mixed"])
 def test_plan_head_of_the_G_set(name, prob):
     """The head of the G set (contracted with FP64 tiles in the FP32-MFMA form):
-    the G with v(G) >= 2^-7 max v, v = 4 pi e^{-G^2/4 omega^2} / G^2; its pair-G
-    work with and without per-pair cuts against brute force."""
+    the G with v(G) >= 2^-20 max v (the default head weight), v = 4 pi
+    e^{-G^2/4 omega^2} / G^2; its pair-G work with and without per-pair cuts
+    against brute force."""
     g2 = g2_of_set(prob)
     v = np.exp(-g2 / (4 * prob.omega ** 2)) / g2
-    head = g2[v >= v.max() / 128.0]
+    head = g2[v >= v.max() / 1048576.0]
     st = pwdf.plan_stats(prob)
     assert st["nG_head"] == len(head) // 2 and 0 < st["nG_head"] < st["nG"] // 2
     assert st["pairG_head"] == 2 * st["npairs"] * st["nG_head"]
