@@ -254,6 +254,7 @@ void fp32_shapes(const Plan &p, Dev &d, const Tune &tn, WorkLists &wl) {
   constexpr double kItemWaves = 8192.0;
   constexpr int kMaxFp32Run = 1024, kMinRun = 16;
   constexpr int kHeadWaves = 2048, kHeadMinPairs = 32;
+  constexpr int kHeadJBlocks = 512, kHeadJMinPts = 32;
   const int nh = d.npts_head, npts = (int)p.pts.size(), ntail = npts - nh;
   const int nb = (ntail + 63) / 64;
   std::vector<double> tg2(ntail);
@@ -302,8 +303,7 @@ void fp32_shapes(const Plan &p, Dev &d, const Tune &tn, WorkLists &wl) {
     return (r + 3) / 4 * 4;
   };
   wl.rows_of_block.assign(std::max(1, nb), 0);
-  const int hc = nh > 0 ? 1 : 0;  // yhat chunk 0 holds the head's J moments
-  wl.jn_of.assign(p.hot.size(), hc);
+  wl.jn_of.assign(p.hot.size(), 0);
   int rows_h = 0;
   int64_t yoff = 0;
   for (int L = 0; L <= kMaxLsum; ++L) {
@@ -315,7 +315,20 @@ void fp32_shapes(const Plan &p, Dev &d, const Tune &tn, WorkLists &wl) {
     d.rho_h_chunks[L] = 0;
     d.rho_h_ppc[L] = 1;
     d.yhat_off[L] = yoff;
+    d.jh_chunks[L] = 0;
+    d.jh_ppc[L] = 1;
     if (np <= 0) continue;
+    // J over the head (FP64 MFMA): split over the head points into yhat chunks
+    // [0, hc) so that a class of few pairs still fills about kHeadJBlocks
+    // workgroups (each chunk at least kHeadJMinPts points)
+    int hc = 0;
+    if (nh > 0) {
+      const int blocks = ((np + 63) / 64) * ngr[L];
+      hc = std::max(1, std::min((kHeadJBlocks + blocks - 1) / blocks, (nh + kHeadJMinPts - 1) / kHeadJMinPts));
+      d.jh_ppc[L] = (nh + hc - 1) / hc;
+      hc = (nh + d.jh_ppc[L] - 1) / d.jh_ppc[L];
+      d.jh_chunks[L] = hc;
+    }
     // rho over the tail
     const int ppc = run_len(CR, costR[L], tn.mrho[L], kMaxFp32Run);
     for (int b = 0; b < nb; ++b)

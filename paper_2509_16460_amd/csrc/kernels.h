@@ -84,8 +84,8 @@ struct Dev {
   //     rows_of_block[b]);
   //   J over the tail: (pair block B of 64 in cut order, point range [s0, s1),
   //     chunk c): the points inside the block's largest cut; the moments of
-  //     chunk c go to yhat chunk 1 + c, the head's to chunk 0, and a pair's
-  //     back transform sums jn_of[cut rank] chunks;
+  //     chunk c go to yhat chunk jh_chunks[L] + c, the head's chunks come first,
+  //     and a pair's back transform sums jn_of[cut rank] chunks;
   //   rho over the head: chunks of pairs x N-tile groups, partial rows
   //     [ndm][nrows_h][head point].
   // slot_pidx maps a slot to its point (-1 for padding slots).
@@ -99,6 +99,9 @@ struct Dev {
   double2 *parth;
   int nrows_h, rows_per_group_h;
   int rho_h_chunks[kMaxLsum + 1], rho_h_ppc[kMaxLsum + 1], rho_h_row0[kMaxLsum + 1];  // rows: chunk x tile group
+  // J over the head: jh_chunks[L] chunks of jh_ppc[L] head points each, yhat
+  // chunks [0, jh_chunks[L]) of the class; the tail's chunks follow them
+  int jh_chunks[kMaxLsum + 1], jh_ppc[kMaxLsum + 1];
   // gradient: moments of degree L+1 per class, per-block centre gradients,
   // per-atom lists of (block, 0 = shell a / 3 = shell b)
   double *yF;

@@ -388,11 +388,11 @@ hipError_t launch_wprep(const Dev &d, int ndm, hipStream_t st) {
 template <int L, int NTW>
 static hipError_t j_mfma_ntw(const Dev &d, int ndm, hipStream_t st) {
   const int ntiles = d.ncols32[L] / 16;
-  // chunk 0 of yhat holds the head's moments when there is a head
+  // yhat chunks [0, jh_chunks[L]) hold the head's moments
   dim3 grid((unsigned)d.j_nitems[L], 1, (unsigned)((ntiles + NTW - 1) / NTW));
   hipLaunchKernelGGL((k_jpass_mfma<L, NTW>), grid, dim3(256), 0, st, d.j_items + d.j_item0[L], d.pts + d.npts_head,
                      d.wre, d.wim, d.ncolsW, ntiles, d.ndmp, ndm, d.hot_cut, d.L_p0[L], d.L_p1[L], d.yhat,
-                     d.yhat_size, d.yhat_off[L], d.npts_head > 0 ? 1 : 0);
+                     d.yhat_size, d.yhat_off[L], d.jh_chunks[L]);
   PWDF_CHECK_LAUNCH32();
   return hipSuccess;
 }

@@ -167,7 +167,8 @@ __global__ __launch_bounds__(256) void k_rho_head(const GPoint *__restrict__ pts
 // ---------------------------------------------------------------------------
 // J moments over the head points, K = G.  A workgroup = 4 waves = 64 pairs (16 per
 // wave as the MFMA rows); the head points are staged in LDS tile by tile with
-// W' formed from conj V in FP64.  Output: yhat at (chunk ycls_off, k, pair).
+// W' formed from conj V in FP64; grid y splits the head points into chunks.
+// Output: yhat chunk blockIdx.y of the class, (k, pair).
 // ---------------------------------------------------------------------------
 // head points per LDS tile (the W' tile is 2 x kPTile x 16 NTW doubles, <= 32 KB)
 template <int NTW>
@@ -176,7 +177,7 @@ constexpr int jh_ptile() {
 }
 
 template <int L, int NTW>
-__global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ pts, int npts,
+__global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ pts, int npts, int ppc,
                                                     const double2 *__restrict__ Vc, int nslot, int ntiles,
                                                     int ndmp, int ndm, const PairHot *__restrict__ hot, int Lp0,
                                                     int Lp1, double *__restrict__ yhat, int64_t yhat_size,
@@ -199,8 +200,10 @@ __global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ p
   for (int n = 0; n < NTW; ++n) acc[n] = d4{0.0, 0.0, 0.0, 0.0};
   constexpr int PER = kPTile * NTW * 16 / 256;  // W' elements per thread and tile
   static_assert(PER * 256 == kPTile * NTW * 16, "tile size");
-  for (int t0 = 0; t0 < npts; t0 += kPTile) {
-    const int nt = min(kPTile, npts - t0);
+  // chunk blockIdx.y: head points [c ppc, (c + 1) ppc), moments to yhat chunk c
+  const int pend = min(npts, (int)(blockIdx.y + 1) * ppc);
+  for (int t0 = blockIdx.y * ppc; t0 < pend; t0 += kPTile) {
+    const int nt = min(kPTile, pend - t0);
     __syncthreads();
     if (tid < nt) sp[tid] = pts[t0 + tid];
     __syncthreads();
@@ -263,7 +266,8 @@ __global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ p
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int prow = prow0 + 4 * i + g4;
-      if (prow < np) yhat[(size_t)dm * yhat_size + ycls_off + (size_t)k * np + prow] = acc[n][i];
+      if (prow < np)
+        yhat[(size_t)dm * yhat_size + ycls_off + ((size_t)blockIdx.y * NT + k) * np + prow] = acc[n][i];
     }
   }
 }
@@ -321,11 +325,11 @@ template <int L, int NTW>
 static hipError_t j_head_ntw(const Dev &d, int ndm, hipStream_t st) {
   const int np = d.L_p1[L] - d.L_p0[L];
   const int ntiles = d.ncols32[L] / 16;
-  // the head's moments are chunk 0 of the class
+  // the head's moments are chunks [0, jh_chunks[L]) of the class
   const int64_t off = d.yhat_off[L];
-  dim3 grid((unsigned)((np + 63) / 64), 1, (unsigned)((ntiles + NTW - 1) / NTW));
-  hipLaunchKernelGGL((k_jpass_head<L, NTW>), grid, dim3(256), 0, st, d.pts, d.npts_head, d.Vc, d.nslot, ntiles,
-                     d.ndmp, ndm, d.hot_cut, d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size, off);
+  dim3 grid((unsigned)((np + 63) / 64), (unsigned)d.jh_chunks[L], (unsigned)((ntiles + NTW - 1) / NTW));
+  hipLaunchKernelGGL((k_jpass_head<L, NTW>), grid, dim3(256), 0, st, d.pts, d.npts_head, d.jh_ppc[L], d.Vc, d.nslot,
+                     ntiles, d.ndmp, ndm, d.hot_cut, d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size, off);
   PWDF_CHECK_LAUNCH_H();
   return hipSuccess;
 }
@@ -333,7 +337,7 @@ static hipError_t j_head_ntw(const Dev &d, int ndm, hipStream_t st) {
 template <int L>
 static hipError_t j_head_one(const Dev &d, int ndm, hipStream_t st) {
   const int np = d.L_p1[L] - d.L_p0[L];
-  if (np <= 0 || d.npts_head <= 0) return hipSuccess;
+  if (np <= 0 || d.npts_head <= 0 || d.jh_chunks[L] <= 0) return hipSuccess;
   switch (group_tiles(d.ncols32[L] / 16)) {
     case 1: return j_head_ntw<L, 1>(d, ndm, st);
     case 2: return j_head_ntw<L, 2>(d, ndm, st);
