@@ -127,6 +127,16 @@ typedef struct {
                       evaluated in FP64 in both precision forms; J, E_J, the
                       gradient and pwdf_get_rhoG (rho_C + rho_D) follow.  <= 0:
                       off.  Must be finite (PWDF_EINVAL) */
+  int dd_gpw;       /* with alpha_cut > 0: 1 takes the DD pairs' density and J through
+                      a real-space grid (GPW, appendix "Evaluation of density on
+                      real space grid (GPW)"): rho_D(r) collocated on N1 x N2 x N3
+                      points along the lattice vectors, N_i = 2 ceil(1.25 M_i) + 1
+                      for the largest |n_i| = M_i of the G set, transformed onto
+                      the G set by separable sums; V_D(G) back onto the grid and
+                      integrated against each DD pair density into J(L).  Equal to
+                      the analytic route up to the grid's aliasing (vectors beyond
+                      the cutoff sphere).  The gradient keeps the analytic DD
+                      moments.  0: analytic transforms of the DD pairs */
 } pwdf_screen;
 
 typedef struct {
@@ -151,6 +161,8 @@ typedef struct {
                          the FP32-MFMA form evaluates it with FP64 tiles */
   int64_t npairs_dd;  /* unique DD primitive pairs (pwdf_screen.alpha_cut); pairG_evals
                          counts them over the whole half space in both passes */
+  int64_t gpw_grid[3]; /* GPW route (pwdf_screen.dd_gpw): grid points along a1, a2, a3
+                          (0 when the DD pairs take the analytic route) */
 } pwdf_stats;
 
 /*

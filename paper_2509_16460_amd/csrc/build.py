@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libpwdf.so")
-SOURCES = ["capi.cpp", "plan.cpp", "kernels_fp64.hip", "kernels_fp32.hip", "kernels_head.hip", "kernels_grad.hip", "kernels_cd.hip", "static_ws.hip"]
+SOURCES = ["capi.cpp", "plan.cpp", "kernels_fp64.hip", "kernels_fp32.hip", "kernels_head.hip", "kernels_grad.hip", "kernels_cd.hip", "kernels_gpw.hip", "static_ws.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -150,6 +150,11 @@ void drop_graph(pwdf_ctx *c) {
 // waves of its blocks share them).
 // The tune multipliers scale the chunk counts per class.
 // columns of a partial row: slots (FP64 form), points of the tail (FP32-MFMA form)
+// complex intermediates of the GPW transforms, per density
+size_t gpw_a_size(const Dev &d) { return (size_t)d.gN[2] * d.gN[1] * (2 * d.gM[0] + 1); }
+size_t gpw_b_size(const Dev &d) { return (size_t)d.gN[2] * (2 * d.gM[1] + 1) * (2 * d.gM[0] + 1); }
+size_t gpw_c_size(const Dev &d) { return (size_t)(2 * d.gM[2] + 1) * (2 * d.gM[1] + 1) * (2 * d.gM[0] + 1); }
+
 size_t part_cols(const Dev &d) { return d.fp32 ? (size_t)std::max(1, d.npts - d.npts_head) : (size_t)d.nslot; }
 
 // Host-side work lists of the FP32-MFMA form (see Dev), uploaded by setup_device.
@@ -474,6 +479,25 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
     UP(p.dd_of, dd_of)
     UP(p.slot_vf, slot_vf)
   }
+  d.gpw = (d.ndd > 0 && in.dd_gpw) ? 1 : 0;
+  if (d.gpw) {
+    for (int i = 0; i < 3; ++i) {
+      d.gN[i] = p.gN[i];
+      d.gM[i] = p.gM[i];
+      d.gtiles[i] = p.gtiles[i];
+    }
+    d.gpts = (int64_t)p.gN[0] * p.gN[1] * p.gN[2];
+    for (int c = 0; c < 3; ++c)
+      for (int i = 0; i < 3; ++i) d.lat[c * 3 + i] = p.A[c][i];
+    UP(p.dd_blk, dd_blk)
+    UP(p.gP, gP)
+    UP(p.gimg, gimg)
+    UP(p.gimg_box, gimg_box)
+    UP(p.gimg_off, gimg_off)
+    UP(p.gtile_off, gtile_off)
+    UP(p.gtile_ent, gtile_ent)
+    UP(p.slot_miller, slot_miller)
+  }
   if (d.fp32) {
     UP(wl.slot_pidx, slot_pidx)
     UP(wl.rho_items, rho_items)
@@ -515,6 +539,13 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
     AL(VDc, M * d.nslot)
     AL(ydd, M * d.ndd * kDDStride)
     AL(yddF, M * d.ndd * kDDStride)
+  }
+  if (d.gpw) {
+    AL(grid_r, M * d.gpts)
+    AL(grid_a, M * gpw_a_size(d))
+    AL(grid_b, M * gpw_b_size(d))
+    AL(grid_c, M * gpw_c_size(d))
+    AL(gpw_part, M * d.ndd * kGpwEl)
   }
   AL(Jfold, M * (size_t)std::max(1, d.nsegJ))
   AL(yF, M * d.yF_size)
@@ -706,8 +737,13 @@ pwdf_status run_mid_rho(pwdf_ctx *c, int ndm, double *EJ, hipStream_t st) {
   if ((s = step(c, "reduce", (double)p.nslot() * ndm, st, [&] { return launch_reduce(d, ndm, nullptr, st); })) !=
       PWDF_OK)
     return s;
-  if ((s = step(c, "rho_dd", (double)d.ndd * nGh * ndm, st, [&] { return launch_rho_dd(d, ndm, st); })) != PWDF_OK)
+  if (d.gpw) {
+    if ((s = step(c, "gpw_rho", (double)d.gpts * ndm, st, [&] { return launch_gpw_rho(d, ndm, st); })) != PWDF_OK)
+      return s;
+  } else if ((s = step(c, "rho_dd", (double)d.ndd * nGh * ndm, st, [&] { return launch_rho_dd(d, ndm, st); })) !=
+             PWDF_OK) {
     return s;
+  }
   if ((s = step(c, "combine_dd", (double)p.nslot() * ndm, st, [&] { return launch_combine_dd(d, ndm, st); })) !=
       PWDF_OK)
     return s;
@@ -778,10 +814,19 @@ pwdf_status run_mid_j(pwdf_ctx *c, int ndm, hipStream_t st) {
                     PWDF_OK)
     return s;
   if ((s = run_moments(c, ndm, false, st)) != PWDF_OK) return s;
-  if (d.ndd > 0 && (s = step(c, "jpass_dd", (double)d.ndd * (p.nG_full / 2) * ndm, st,
-                             [&] { return launch_jpass_dd(d, false, ndm, st); })) != PWDF_OK)
+  if (d.gpw) {
+    if ((s = step(c, "gpw_j", (double)d.gpts * ndm, st, [&] { return launch_gpw_j(d, ndm, st); })) != PWDF_OK)
+      return s;
+  } else if (d.ndd > 0 && (s = step(c, "jpass_dd", (double)d.ndd * (p.nG_full / 2) * ndm, st,
+                                    [&] { return launch_jpass_dd(d, false, ndm, st); })) != PWDF_OK) {
     return s;
-  return step(c, "back", pair_transform_flops(p, ndm), st, [&] { return launch_back_all(d, ndm, st); });
+  }
+  if ((s = step(c, "back", pair_transform_flops(p, ndm), st, [&] { return launch_back_all(d, ndm, st); })) !=
+      PWDF_OK)
+    return s;
+  if (!d.gpw) return PWDF_OK;
+  // GPW route: the DD pairs' J blocks, integrated on the grid, join J(L)
+  return step(c, "gpw_add", (double)d.ndd * ndm, st, [&] { return launch_gpw_add(d, ndm, st); });
 }
 
 // EJ: device [ndm] summed by the J(k) launch from the energy partials of the
@@ -839,6 +884,7 @@ static pwdf_status make_input(PlanInput &in, const double lattice[9], int natm, 
   in.pair_gcut = screen->pair_gcut != 0 ? 1 : 0;
   if (!std::isfinite(screen->alpha_cut)) return fail(nullptr, PWDF_EINVAL, "alpha_cut must be finite");
   in.alpha_cut = screen->alpha_cut > 0.0 ? screen->alpha_cut : 0.0;
+  in.dd_gpw = screen->dd_gpw != 0 ? 1 : 0;
   return PWDF_OK;
 }
 
@@ -859,6 +905,7 @@ static void fill_stats(const Plan &p, pwdf_stats *out) {
   // sphere, or the whole half space)
   out->pairG_evals = 2.0 * p.pairG_cut + 2.0 * (double)p.dd_q.size() * (double)(p.nG_full / 2);
   out->npairs_dd = (int64_t)p.dd_q.size();
+  for (int i = 0; i < 3; ++i) out->gpw_grid[i] = p.gN[i];
   out->seg_len = p.seg_len;
   out->fork = 1;
   out->jk_support = (int64_t)(p.lightJ.size() + p.heavyJ.size());
@@ -1097,6 +1144,13 @@ static size_t carve_build_ws(Dev &d, const Plan &p, int ndm, unsigned char *base
     take(d.rhoD, M * d.nslot);
     take(d.VDc, M * d.nslot);
     take(d.ydd, M * d.ndd * kDDStride);
+  }
+  if (d.gpw) {
+    take(d.grid_r, M * d.gpts);
+    take(d.grid_a, M * gpw_a_size(d));
+    take(d.grid_b, M * gpw_b_size(d));
+    take(d.grid_c, M * gpw_c_size(d));
+    take(d.gpw_part, M * d.ndd * kGpwEl);
   }
   take(d.Jfold, M * (size_t)std::max(1, d.nsegJ));
   if (d.npts_head > 0) take(d.parth, M * d.nrows_h * d.npts_head);

@@ -121,6 +121,24 @@ struct Dev {
   const double *slot_vf;
   double2 *rhoD, *VDc;
   double *ydd, *yddF;
+  // GPW route of the DD pairs (gpw = 1; see Plan::gN): grid sizes, the DD pairs'
+  // blocks, centres and cut radii, image entries and their grid boxes, tile
+  // lists; the lattice (lat[c * 3 + i] = component c of a_i); the slot Miller
+  // indices; workspaces: a real grid [ndm][gpts] (density, then V(r)), complex
+  // intermediates of the separable transforms ([ndm][N2][N1][K0],
+  // [ndm][N2][K1][K0], [ndm][K2][K1][K0], K_i = 2 gM_i + 1) and the DD pairs'
+  // J partials [ndm][ndd][kGpwEl]
+  int gpw;
+  int gN[3], gM[3], gtiles[3];
+  int64_t gpts;
+  double lat[9];
+  const int *dd_blk;
+  const double *gP;
+  const int *gimg, *gimg_box, *gimg_off, *gtile_off, *gtile_ent;
+  const int *slot_miller;
+  double *grid_r;
+  double2 *grid_a, *grid_b, *grid_c;
+  double *gpw_part;
   // launch shapes
   int ndb;  // densities per block of the low-L pair-G launches (1, 2 or 4)
   int rho_bs;
@@ -135,6 +153,8 @@ struct Dev {
 
 // moments per DD pair and density: every degree up to the force moments of L = 6
 constexpr int kDDStride = nherm(kMaxLsum);
+// Cartesian elements of a pair block, at most (3,3)
+constexpr int kGpwEl = 100;
 
 // Allocation-free J build: the per-call workspaces are carved out of a static
 // device array of this many bytes (one per device, held for the process's life).
@@ -185,6 +205,12 @@ hipError_t launch_rho_dd(const Dev &d, int ndm, hipStream_t st);
 hipError_t launch_combine_dd(const Dev &d, int ndm, hipStream_t st);
 hipError_t launch_jpass_dd(const Dev &d, bool force, int ndm, hipStream_t st);
 hipError_t launch_energy(const Dev &d, int ndm, double *EJ, hipStream_t st);
+// GPW route: rho_D from the DD pairs' density on the grid (collocation and a
+// separable transform onto the G set); V_D onto the grid and the DD pairs' J
+// blocks by integration, added to J(L) after the back transform
+hipError_t launch_gpw_rho(const Dev &d, int ndm, hipStream_t st);
+hipError_t launch_gpw_j(const Dev &d, int ndm, hipStream_t st);
+hipError_t launch_gpw_add(const Dev &d, int ndm, hipStream_t st);
 // gradient
 hipError_t launch_force_back_cls(const Dev &d, int la, int lb, int ndm, hipStream_t st);
 hipError_t launch_force_atoms(const Dev &d, int ndm, double *dEdR, hipStream_t st);

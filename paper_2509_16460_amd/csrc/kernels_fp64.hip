@@ -745,7 +745,7 @@ __device__ __forceinline__ void back_thread(const Dev &dv, int bi, int dm) {
     // a DD pair (compact/diffuse classification) takes its moments of V_D from
     // the DD kernel instead of the chunks (which hold zeros for it)
     const int dq = dv.dd_of ? dv.dd_of[q] : -1;
-    if (dq >= 0) {
+    if (dq >= 0 && !dv.gpw) {  // (GPW route: the DD pairs' J is added to J(L) afterwards)
 #pragma unroll
       for (int k = 0; k < NT; ++k) y[k] = dv.ydd[((size_t)dm * dv.ndd + dq) * kDDStride + k];
     }
@@ -1052,7 +1052,7 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
     const int dq = dv.dd_of ? dv.dd_of[q] : -1;  // DD pair: the DD kernel's moments
     for (int k = lane; k < NT; k += 64) {
       if (dq >= 0) {
-        sY[k] = dv.ydd[((size_t)dm * dv.ndd + dq) * kDDStride + k];
+        sY[k] = dv.gpw ? 0.0 : dv.ydd[((size_t)dm * dv.ndd + dq) * kDDStride + k];
         continue;
       }
       // chunk order kept; up to 16 loads in flight

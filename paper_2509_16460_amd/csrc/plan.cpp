@@ -167,6 +167,97 @@ double cut_radius(const CutPair &c, double omega, double eps_G) {
 
 static void head_points(Plan &p);
 
+// GPW grid and lists of the DD pairs (see Plan::gN).  The ball of a pair density
+// is cut at e^{-p r^2} = e^{-50}: with its polynomial factor of degree <= 6 the
+// dropped tail stays below ~1e-15 of the pair's values.  Returns a reason when
+// the grid work (image boxes x their grid points, collocation and integration
+// alike) would exceed kGpwMaxWork: GPW pays off when the cell is large against
+// the diffuse Gaussians; for a small cell the analytic route is the one to use.
+constexpr double kGpwMaxWork = 3e9;
+
+static std::string build_gpw(Plan &p) {
+  for (int i = 0; i < 3; ++i) p.gM[i] = 0;
+  for (size_t s = 0; s < p.slot_miller.size() / 3; ++s)
+    for (int i = 0; i < 3; ++i) p.gM[i] = std::max(p.gM[i], std::abs(p.slot_miller[3 * s + i]));
+  for (int i = 0; i < 3; ++i) {
+    p.gN[i] = 2 * (int)std::ceil(1.25 * p.gM[i]) + 1;
+    p.gtiles[i] = (p.gN[i] + 7) / 8;
+  }
+  const int ndd = (int)p.dd_q.size();
+  p.gP.assign(4 * (size_t)ndd, 0.0);
+  p.gimg.clear();
+  p.gimg_box.clear();
+  p.gimg_off.assign(ndd + 1, 0);
+  double work = 0.0;
+  double blen[3];
+  for (int i = 0; i < 3; ++i)
+    blen[i] = std::sqrt(p.B[0][i] * p.B[0][i] + p.B[1][i] * p.B[1][i] + p.B[2][i] * p.B[2][i]);
+  for (int k = 0; k < ndd; ++k) {
+    const int q = p.dd_q[k];
+    const BlockRec &br = p.blocks[p.dd_blk[k]];
+    const PairAux &x = p.aux[q];
+    const double *RA = &p.in.xyz[3 * p.in.sh_atom[br.sa]];
+    double P[3], f[3], rf[3];
+    for (int c = 0; c < 3; ++c) P[c] = RA[c] + x.xpa[c];
+    const double rc2 = 50.0 / x.p, rc = std::sqrt(rc2);
+    for (int c = 0; c < 3; ++c) p.gP[4 * k + c] = P[c];
+    p.gP[4 * k + 3] = rc2;
+    for (int i = 0; i < 3; ++i) {
+      f[i] = (p.B[0][i] * P[0] + p.B[1][i] * P[1] + p.B[2][i] * P[2]) / (2.0 * kPi);
+      rf[i] = rc * blen[i] / (2.0 * kPi);  // fractional half-width of the ball along a_i
+    }
+    int mlo[3], mhi[3];
+    for (int i = 0; i < 3; ++i) {
+      mlo[i] = (int)std::ceil(-rf[i] - f[i]);
+      mhi[i] = (int)std::floor(1.0 + rf[i] - f[i]);
+    }
+    for (int m0 = mlo[0]; m0 <= mhi[0]; ++m0)
+      for (int m1 = mlo[1]; m1 <= mhi[1]; ++m1)
+        for (int m2 = mlo[2]; m2 <= mhi[2]; ++m2) {
+          const int m[3] = {m0, m1, m2};
+          int box[6];
+          bool empty = false;
+          for (int i = 0; i < 3; ++i) {
+            const double c0 = f[i] + m[i];
+            box[2 * i] = std::max(0, (int)std::ceil((c0 - rf[i]) * p.gN[i]));
+            box[2 * i + 1] = std::min(p.gN[i] - 1, (int)std::floor((c0 + rf[i]) * p.gN[i]));
+            empty = empty || box[2 * i] > box[2 * i + 1];
+          }
+          if (empty) continue;
+          work += (double)(box[1] - box[0] + 1) * (box[3] - box[2] + 1) * (box[5] - box[4] + 1);
+          if (work > kGpwMaxWork) {
+            char msg[256];
+            std::snprintf(msg, sizeof msg,
+                          "unsupported: the GPW route of the DD pairs would evaluate more than %.0e grid points "
+                          "(diffuse Gaussians much wider than the cell); use the analytic route (dd_gpw = 0)",
+                          kGpwMaxWork);
+            return msg;
+          }
+          p.gimg.insert(p.gimg.end(), {k, m0, m1, m2});
+          p.gimg_box.insert(p.gimg_box.end(), box, box + 6);
+        }
+    p.gimg_off[k + 1] = (int)(p.gimg.size() / 4);
+  }
+  // tiles of 8^3 grid points: the image entries whose box meets each tile
+  const int nt = p.gtiles[0] * p.gtiles[1] * p.gtiles[2];
+  std::vector<std::vector<int>> per(nt);
+  const int ne = (int)(p.gimg.size() / 4);
+  for (int e = 0; e < ne; ++e) {
+    const int *b = &p.gimg_box[6 * (size_t)e];
+    for (int t2 = b[4] / 8; t2 <= b[5] / 8; ++t2)
+      for (int t1 = b[2] / 8; t1 <= b[3] / 8; ++t1)
+        for (int t0 = b[0] / 8; t0 <= b[1] / 8; ++t0) per[(t2 * p.gtiles[1] + t1) * p.gtiles[0] + t0].push_back(e);
+  }
+  p.gtile_off.assign(nt + 1, 0);
+  p.gtile_ent.clear();
+  for (int t = 0; t < nt; ++t) {
+    p.gtile_off[t] = (int)p.gtile_ent.size();
+    p.gtile_ent.insert(p.gtile_ent.end(), per[t].begin(), per[t].end());
+  }
+  p.gtile_off[nt] = (int)p.gtile_ent.size();
+  return std::string();
+}
+
 void build_segments(Plan &p, int seg_len) {
   p.seg_len = seg_len;
   p.segs.clear();
@@ -543,17 +634,24 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
   p.dd_q.clear();
   p.dd_L.clear();
   p.dd_of.assign(p.hot.size(), -1);
+  p.dd_blk.clear();
   if (in.alpha_cut > 0.0) {
-    for (const BlockRec &br : p.blocks) {
+    for (size_t bi = 0; bi < p.blocks.size(); ++bi) {
+      const BlockRec &br = p.blocks[bi];
       const int L = in.sh_l[br.sa] + in.sh_l[br.sb];
       for (int q = br.p0; q < br.p1; ++q)
         if (p.aux[q].alpha_a < in.alpha_cut && p.aux[q].alpha_b < in.alpha_cut) {
           p.dd_of[q] = (int)p.dd_q.size();
           p.dd_q.push_back(q);
           p.dd_L.push_back(L);
+          p.dd_blk.push_back((int)bi);
           p.hot[q].gc2 = -1.0;
         }
     }
+  }
+  if (in.dd_gpw && !p.dd_q.empty()) {
+    const std::string why = build_gpw(p);
+    if (!why.empty()) return why;
   }
   // Pair-G work inside the cuts: for each pair and G line (fixed n_v, n_w) the
   // n_u with |G(n_u)|^2 = M_uu n_u^2 + 2 b n_u + c <= gc2 lie between the roots

@@ -23,6 +23,10 @@ struct PlanInput {
   // compact and diffuse"): pairs of two primitives with exponents below it are
   // DD pairs, taken with the full-range kernel against everything
   double alpha_cut = 0.0;
+  // 1: the DD pairs' density and J go through a real-space grid (GPW, appendix
+  // "Evaluation of density on real space grid (GPW)") instead of their analytic
+  // transforms
+  int dd_gpw = 0;
 };
 
 // Default relative Coulomb weight that bounds the head of the G set (see
@@ -127,6 +131,20 @@ struct Plan {
   // the full-range kernel 4 pi/|G|^2 per slot (0 on padding).
   std::vector<int> dd_q, dd_L, dd_of;
   std::vector<double> slot_vf;
+  // GPW route of the DD pairs (in.dd_gpw): a grid of gN[i] points along a_i
+  // (original axis order), gN[i] = 2 ceil(1.25 gM[i]) + 1 with gM[i] the largest
+  // |n_i| of the G set, so that every G of the set aliases only onto |G'| beyond
+  // the cutoff sphere.  Per DD pair: its block, centre P and squared cut radius
+  // (gP: x, y, z, rc^2); its lattice images whose ball reaches the cell (gimg:
+  // dd index, m0, m1, m2; gimg_box: grid index box lo0 hi0 lo1 hi1 lo2 hi2 inside
+  // the cell; gimg_off[dd] first entry), and per tile of 8^3 grid points the image
+  // entries whose box meets it (gtile_off, gtile_ent).
+  int gN[3] = {0, 0, 0}, gM[3] = {0, 0, 0};
+  int gtiles[3] = {0, 0, 0};
+  std::vector<int> dd_blk;
+  std::vector<double> gP;
+  std::vector<int> gimg, gimg_box, gimg_off, gtile_off, gtile_ent;
+
   // the pair-G kernels must honour gc2 (per-pair cuts, or DD pairs to skip)
   bool cut_on() const { return in.pair_gcut != 0 || !dd_q.empty(); }
 

@@ -40,12 +40,12 @@ class PwdfError(RuntimeError):
 
 class Screen(ctypes.Structure):
     _fields_ = [("eps_pair", ctypes.c_double), ("eps_G", ctypes.c_double), ("r_max", ctypes.c_double),
-                ("pair_gcut", ctypes.c_int), ("alpha_cut", ctypes.c_double)]
+                ("pair_gcut", ctypes.c_int), ("alpha_cut", ctypes.c_double), ("dd_gpw", ctypes.c_int)]
 
 
 def _screen(prob) -> Screen:
     return Screen(prob.eps_pair, prob.eps_G, prob.r_max, int(getattr(prob, "pair_gcut", 0)),
-                  float(getattr(prob, "alpha_cut", 0.0)))
+                  float(getattr(prob, "alpha_cut", 0.0)), int(getattr(prob, "dd_gpw", 0)))
 
 
 class Stats(ctypes.Structure):
@@ -55,10 +55,11 @@ class Stats(ctypes.Structure):
                 ("t_us", ctypes.c_double * 8), ("seg_len", ctypes.c_int64),
                 ("fork", ctypes.c_int64), ("jk_support", ctypes.c_int64), ("dk_support", ctypes.c_int64),
                 ("jk_layout", ctypes.c_int64), ("nG_head", ctypes.c_int64), ("pairG_head", ctypes.c_double),
-                ("npairs_dd", ctypes.c_int64)]
+                ("npairs_dd", ctypes.c_int64), ("gpw_grid", ctypes.c_int64 * 3)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("npairs_by_class", "t_us")}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("npairs_by_class", "t_us", "gpw_grid")}
+        d["gpw_grid"] = tuple(int(x) for x in self.gpw_grid)
         d["npairs_by_class"] = {f"{c // 4}{c % 4}": int(self.npairs_by_class[c]) for c in range(16)
                                 if self.npairs_by_class[c]}
         return d

@@ -76,6 +76,7 @@ class Problem:
     # > 0: compact/diffuse classification with this cutoff exponent (section
     # "Density classification: compact and diffuse"; the paper's default is omega^2/2)
     alpha_cut: float = 0.0
+    dd_gpw: int = 0  # 1: the diffuse pairs through a real-space grid (GPW)
 
     @property
     def natm(self) -> int:

@@ -5,6 +5,7 @@ and of the full pair list (every (a,b,L) and its mirror (b,a,-L)); the
 library keeps one representative per mirror pair, so full = 2 unique - diag.
 """
 import ctypes
+import math
 import os
 import re
 
@@ -192,3 +193,32 @@ def test_dd_pairs_counted_by_the_plan():
     stc = pwdf.plan_stats(prob.with_(alpha_cut=ac, pair_gcut=1))
     stc0 = pwdf.plan_stats(prob.with_(pair_gcut=1))
     assert stc["pairG_evals"] >= stc0["pairG_evals"]  # DD pairs lose their cut
+
+
+def test_gpw_grid_of_the_plan():
+    """GPW route of the DD pairs (appendix "Evaluation of density on real space grid
+    (GPW)"): the plan's grid takes N_i = 2 ceil(1.25 M_i) + 1 points along a_i, M_i
+    the largest |n_i| of the G set (the oracle's own G set here), so that every G
+    of the set aliases only onto vectors outside the cutoff sphere."""
+    lat = np.array([[4.2, 0.0, 0.0], [0.3, 4.6, 0.0], [-0.4, 0.5, 3.9]])
+    xyz = np.array([[0.2, 0.1, 0.3], [2.0, 2.5, 1.7]])
+    prob = synth.build_problem("gpw", lat, xyz, [0, 0], {0: [np.array([2.2, 0.09]), np.array([1.3, 0.1])]},
+                               (2, 1, 1), 0.5).with_(alpha_cut=0.125, dd_gpw=1)
+    st = pwdf.plan_stats(prob)
+    mil = O.build_j(prob, synth.make_density(prob, 3), want_J=False)["miller"]
+    M = np.max(np.abs(mil), axis=0)
+    assert st["gpw_grid"] == tuple(int(2 * math.ceil(1.25 * m) + 1) for m in M)
+    assert pwdf.plan_stats(prob.with_(dd_gpw=0))["gpw_grid"] == (0, 0, 0)
+
+
+def test_gpw_refuses_a_cell_far_smaller_than_its_diffuse_gaussians():
+    """GPW pays off when the cell is large against the diffuse Gaussians: a 4.2
+    Bohr cell with exponents ~0.1 would need ~1e10 grid evaluations per build, and
+    the plan refuses it (PWDF_EUNSUPPORTED) instead of running for seconds."""
+    lat = np.array([[4.2, 0.0, 0.0], [0.3, 4.6, 0.0], [-0.4, 0.5, 3.9]])
+    xyz = np.array([[0.2, 0.1, 0.3], [2.0, 2.5, 1.7]])
+    ex = {0: [np.array([2.2, 0.09]), np.array([1.3, 0.1]), np.array([0.9, 0.11])]}
+    prob = synth.build_problem("gpw_small", lat, xyz, [0, 0], ex, (2, 1, 1), 0.5).with_(alpha_cut=0.125, dd_gpw=1)
+    with pytest.raises(pwdf.PwdfError, match="PWDF_EUNSUPPORTED"):
+        pwdf.plan_stats(prob)
+    assert pwdf.plan_stats(prob.with_(dd_gpw=0))["npairs_dd"] > 0

@@ -6,6 +6,12 @@ Section "Density classification: compact and diffuse", eq. "cd cutoff"
 themselves.  Bars as for the unclassified path: FP64 |dE_J| <= 1e-10 Eh, max
 |dJ(k)| <= 1e-11, rho(G) (rho_C + rho_D) 1e-12 relative, gradient 1e-10; the
 FP32-MFMA form (the DD pairs stay FP64) within its bars against the oracle.
+
+Both routes of the DD pairs are tested against the same (analytic) oracle: their
+analytic transforms, and GPW (appendix "Evaluation of density on real space grid
+(GPW)": density collocated on a real-space grid and transformed onto the G set,
+J integrated on the grid), which equals the analytic result up to the grid's
+aliasing onto vectors beyond the cutoff sphere.
 """
 import numpy as np
 import pytest
@@ -36,20 +42,34 @@ def cd_problem(kmesh=(2, 1, 1), lmax=2, natm=2, seed=61, pair_gcut=0):
     return prob.with_(alpha_cut=0.125, pair_gcut=pair_gcut)
 
 
+def gpw_problem(kmesh=(2, 1, 1), lmax=2, natm=2, seed=61, pair_gcut=0):
+    """A cell of ~7.5 Bohr with diffuse exponents just below alpha_cut = 0.125:
+    the GPW route's grid work stays modest (its cost grows with the number of
+    cells a diffuse Gaussian spans)."""
+    rng = np.random.default_rng(seed)
+    lat = np.array([[7.5, 0.0, 0.0], [0.4, 7.8, 0.0], [-0.5, 0.6, 7.1]])
+    xyz = rng.uniform(0, 1, size=(natm, 3)) @ lat
+    ex = {0: [np.array(e) for e in ([2.2, 0.11], [1.3, 0.115], [0.9, 0.12], [0.7, 0.122])[:lmax + 1]]}
+    prob = synth.build_problem("gpw", lat, xyz, [0] * natm, ex, kmesh, 0.5, nelec=2.0 * natm, seed=seed)
+    return prob.with_(alpha_cut=0.125, pair_gcut=pair_gcut, dd_gpw=1)
+
+
 CASES = {
-    "spd_k211": dict(kmesh=(2, 1, 1), lmax=2, seed=61),
-    "spd_k211_cut": dict(kmesh=(2, 1, 1), lmax=2, seed=61, pair_gcut=1),
-    "spdf_gamma": dict(kmesh=(1, 1, 1), lmax=3, natm=1, seed=62),
-    "sp_k221_3atoms": dict(kmesh=(2, 2, 1), lmax=1, natm=3, seed=63),
+    "spd_k211-aft": lambda: cd_problem(kmesh=(2, 1, 1), lmax=2, seed=61),
+    "spd_k211_cut-aft": lambda: cd_problem(kmesh=(2, 1, 1), lmax=2, seed=61, pair_gcut=1),
+    "spdf_gamma-aft": lambda: cd_problem(kmesh=(1, 1, 1), lmax=3, natm=1, seed=62),
+    "sp_k221_3atoms-aft": lambda: cd_problem(kmesh=(2, 2, 1), lmax=1, natm=3, seed=63),
+    "spd_k211-gpw": lambda: gpw_problem(kmesh=(2, 1, 1), lmax=2, seed=64),
+    "spd_k211_cut-gpw": lambda: gpw_problem(kmesh=(2, 1, 1), lmax=2, seed=64, pair_gcut=1),
+    "spdf_gamma-gpw": lambda: gpw_problem(kmesh=(1, 1, 1), lmax=3, natm=1, seed=65),
 }
 
 
 @pytest.fixture(scope="module", params=list(CASES))
 def cd_ref(request):
-    prob = cd_problem(**CASES[request.param])
+    prob = CASES[request.param]()
     D = synth.make_density(prob, 71)
-    ref = O.build_j(prob, D)
-    return request.param, prob, D, ref
+    return request.param, prob, D, O.build_j(prob, D)
 
 
 def build(prob, D, prec, graph=False):
@@ -65,6 +85,7 @@ def test_plan_counts_dd_pairs(cd_ref):
     st = pw().plan_stats(prob)
     st0 = pw().plan_stats(prob.with_(alpha_cut=0.0))
     assert st["npairs_dd"] > 0 and st0["npairs_dd"] == 0
+    assert (min(st["gpw_grid"]) > 0) == bool(prob.dd_gpw)
     assert st["npairs"] == st0["npairs"]
     # the DD pairs leave the compact passes and see the whole half space instead
     assert st["pairG_evals"] >= st0["pairG_evals"]
@@ -104,8 +125,9 @@ def test_fp32_mfma_matches_oracle(cd_ref):
     assert dE <= 1e-7 and dJ <= 1e-8
 
 
-def test_gradient_matches_oracle():
-    prob = cd_problem(kmesh=(2, 1, 1), lmax=2, seed=64)
+@pytest.mark.parametrize("gpw", [0, 1], ids=["aft", "gpw"])
+def test_gradient_matches_oracle(gpw):
+    prob = gpw_problem(kmesh=(2, 1, 1), lmax=2, seed=66) if gpw else cd_problem(kmesh=(2, 1, 1), lmax=2, seed=64)
     D = synth.make_density(prob, 72)
     ref = O.build_j(prob, D, want_J=False, want_rho=False, want_grad=True)
     ctx = pw().LongRangeJ(prob, precision=0, max_ndm=1)
@@ -130,3 +152,18 @@ def test_batched_densities_match_single():
             print(f"prec {prec} density {i}: dE={abs(Eb[i] - E1[0]):.2e} max|dJ|={np.max(np.abs(Jb[i] - J1[0])):.2e}")
             assert abs(Eb[i] - E1[0]) <= tol * abs(E1[0])
             assert np.max(np.abs(Jb[i] - J1[0])) <= tol * np.max(np.abs(J1[0]))
+
+
+def test_gpw_batch_and_noalloc_match_single():
+    """GPW route with three densities per call equals one-density calls bit for
+    bit (every grid sum per density in a fixed order), and the allocation-free
+    entry point gives the same bits."""
+    prob = gpw_problem(kmesh=(2, 1, 1), lmax=1, seed=67)
+    Ds = np.stack([synth.make_density(prob, 90 + i) for i in range(3)])
+    ctx, Dt, Jb, Eb = build(prob, Ds, 0)
+    for i in range(3):
+        _, _, J1, E1 = build(prob, Ds[i:i + 1], 0)
+        assert np.array_equal(Jb[i], J1[0]) and Eb[i] == E1[0]
+    J, E = ctx.build_j(Dt, noalloc=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(J.cpu().numpy(), Jb) and np.array_equal(E.cpu().numpy(), Eb)
