@@ -20,7 +20,9 @@ call (the plain form; the ratio of the two is the batched-FP32 speedup) and
 with 16 per call, the FP32-MFMA batch without per-pair cuts, the errors
 against each other and against the FP64 oracle; then (child process, so that a
 failure there is reported in "extras_error" instead of ending the run) the FP64
-form on the monoclinic molecular crystal and on the diamond-like cell.  A
+form on the monoclinic molecular crystal and on the diamond-like cell, and the
+compact/diffuse classification on a cell with diffuse shells (the diffuse pairs
+by their analytic transforms and by GPW).  A
 second, profiled region of the headline form brackets every launch with HIP
 events on its stream and gives each kernel's average duration for the roofline
 entry.  The FP64 CPU oracle, timed on the host cores for one slab density, is
@@ -163,13 +165,16 @@ def single_fp64(torch, pwdf, prob, Dt, steps, warmup):
 
 def extras(args):
     """FP64 single-density builds of the molecular crystal and the diamond-like
-    cell; prints one JSON object."""
+    cell, and of a cell with diffuse shells under the compact/diffuse
+    classification (the DD pairs by their analytic transforms and by GPW);
+    prints one JSON object."""
     import torch
     from paper_2509_16460_amd import pwdf, synth
 
     torch.cuda.set_device(0)
     out = {}
     for cfg, name in ((5, "molecular_crystal48_k333_w0.5_fp64_paircut"), (2, "diamond8_k444_w0.4_fp64_paircut")):
+        print(f"bench: extras {name}: autotune + timed region", file=sys.stderr, flush=True)
         prob = synth.config_problem(cfg).with_(pair_gcut=1)
         D = synth.make_density(prob, 1000 * cfg)
         Dt = torch.from_numpy(D[None]).cuda()
@@ -182,6 +187,37 @@ def extras(args):
         del ctx, J, E, Dt
         torch.cuda.empty_cache()
         print(f"bench: extras {name} {ms:.3f} ms", file=sys.stderr, flush=True)
+    # compact/diffuse classification on a cell with diffuse shells: the DD pairs by
+    # their analytic transforms and by GPW (real-space grid), FP64, one density
+    prob = synth.diffuse_problem(a=11.0, natm=2)
+    D = synth.make_density(prob, 7000)
+    Dt = torch.from_numpy(D[None]).cuda()
+    res, Js = {}, {}
+    for route in (0, 1):
+        pr = prob.with_(dd_gpw=route)
+        print(f"bench: extras classification, {'GPW' if route else 'analytic'} route", file=sys.stderr, flush=True)
+        # default launch shapes (no autotune), graph replay
+        ctx = pwdf.LongRangeJ(pr, precision=pwdf.PWDF_FP64, max_ndm=1)
+        ctx.set_jk_layout(pwdf.PWDF_JK_PACKED)
+        J = torch.empty((1, pr.nk, ctx.stats()["jk_support"]), dtype=Dt.dtype, device=Dt.device)
+        E = torch.empty(1, dtype=torch.float64, device="cuda")
+        ms = timed(torch, lambda: ctx.build_j(Dt, J, E, graph=True), min(args.steps, 10), 2)
+        st = ctx.stats()
+        prof = profile_kernels(torch, ctx, lambda: ctx.build_j(Dt, J, E), 3)
+        kt = kernel_table(prof)
+        dd = {k: v["avg_us"] for k, v in kt.items() if k in ("rho_dd", "jpass_dd", "combine_dd", "gpw_rho", "gpw_j",
+                                                              "gpw_add")}
+        res["gpw" if route else "analytic"] = {"ms_per_build": ms, "builds_per_s": 1e3 / ms, "dd_kernels_us": dd,
+                                               "E_J": float(E.cpu()[0]), "gpw_grid": list(st["gpw_grid"])}
+        Js[route] = J.clone()
+        del ctx, J, E
+        torch.cuda.empty_cache()
+    res["workload"] = prob.name + "_k222_w0.5_fp64_cd (default launch shapes)"
+    res.update(natm=prob.natm, nbf=prob.nbf, nk=prob.nk, unique_pairs=st["npairs"], dd_pairs=st["npairs_dd"],
+               nG=st["nG"], max_abs_dJ_gpw_vs_analytic=float((Js[0] - Js[1]).abs().max()))
+    out["classification"] = res
+    print(f"bench: extras classification {res['analytic']['ms_per_build']:.3f} / {res['gpw']['ms_per_build']:.3f} ms",
+          file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 
@@ -368,12 +404,13 @@ def main():
         cmd = [sys.executable, os.path.abspath(__file__), "--extras-only", "--steps", str(args.steps),
                "--warmup", str(args.warmup)]
         try:
-            r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+            # the child's progress lines go straight to this process's stderr
+            r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=600)
             lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
             if r.returncode == 0 and lines:
                 out["other_workloads"] = json.loads(lines[-1])
             else:
-                out["extras_error"] = f"exit status {r.returncode}: {r.stderr[-400:]}"
+                out["extras_error"] = f"exit status {r.returncode}"
         except subprocess.TimeoutExpired:
             out["extras_error"] = "timed out after 600 s"
 

@@ -479,6 +479,14 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
     UP(p.dd_of, dd_of)
     UP(p.slot_vf, slot_vf)
   }
+  if (d.ndd > 0) {
+    // rho_D of the analytic route: about 2048 workgroups over (slot blocks x
+    // chunks of DD pairs), at least 8 pairs per chunk
+    const int bx = (d.nslot + 255) / 256;
+    int nc = std::max(1, std::min((2048 + bx - 1) / bx, (d.ndd + 7) / 8));
+    d.dd_ppc = (d.ndd + nc - 1) / nc;
+    d.dd_chunks = (d.ndd + d.dd_ppc - 1) / d.dd_ppc;
+  }
   d.gpw = (d.ndd > 0 && in.dd_gpw) ? 1 : 0;
   if (d.gpw) {
     for (int i = 0; i < 3; ++i) {
@@ -536,6 +544,7 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   AL(Epart, M * d.nred_blocks)
   if (d.ndd > 0) {
     AL(rhoD, M * d.nslot)
+    AL(rhoDp, M * d.dd_chunks * d.nslot)
     AL(VDc, M * d.nslot)
     AL(ydd, M * d.ndd * kDDStride)
     AL(yddF, M * d.ndd * kDDStride)
@@ -1142,6 +1151,7 @@ static size_t carve_build_ws(Dev &d, const Plan &p, int ndm, unsigned char *base
   take(d.Epart, M * d.nred_blocks);
   if (d.ndd > 0) {
     take(d.rhoD, M * d.nslot);
+    take(d.rhoDp, M * d.dd_chunks * d.nslot);
     take(d.VDc, M * d.nslot);
     take(d.ydd, M * d.ndd * kDDStride);
   }

@@ -117,6 +117,8 @@ struct Dev {
   // writes them, read by the back transform and the force contraction instead of
   // the pair's chunks)
   int ndd;
+  int dd_chunks, dd_ppc;  // rho_D: chunks of dd_ppc DD pairs, partial rows rhoDp [ndm][dd_chunks][nslot]
+  double2 *rhoDp;
   const int *dd_q, *dd_L, *dd_of;
   const double *slot_vf;
   double2 *rhoD, *VDc;

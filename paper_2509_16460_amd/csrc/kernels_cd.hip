@@ -64,15 +64,18 @@ __device__ __forceinline__ double dd_coef(const Dev &d, int q, int L, int k, int
 }
 
 // rho_D(G) = sum_{DD pairs} S P, P = sum_k d_k n^k (real part from even |k|,
-// imaginary from odd |k|): one thread per slot, the DD pairs in list order
+// imaginary from odd |k|): one thread per slot and chunk of DD pairs (grid y),
+// the chunk's pairs in list order into its partial row; k_rho_dd_sum adds the
+// rows in chunk order
 __global__ __launch_bounds__(256) void k_rho_dd(const Dev d) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  const int dm = blockIdx.y;
+  const int chunk = blockIdx.y, dm = blockIdx.z;
   if (slot >= d.nslot) return;
   double n[3], g2;
   double rr = 0.0, ri = 0.0;
+  const int i1 = min(d.ndd, (chunk + 1) * d.dd_ppc);
   if (slot_point(d, slot, n, g2)) {
-    for (int i = 0; i < d.ndd; ++i) {
+    for (int i = chunk * d.dd_ppc; i < i1; ++i) {
       const int q = d.dd_q[i], L = d.dd_L[i];
       const double2 S = pair_factor(d.hot[q], n, g2);
       double pr = 0.0, pi = 0.0;
@@ -91,6 +94,18 @@ __global__ __launch_bounds__(256) void k_rho_dd(const Dev d) {
       rr = fma(S.x, pr, fma(-S.y, pi, rr));
       ri = fma(S.x, pi, fma(S.y, pr, ri));
     }
+  }
+  d.rhoDp[((size_t)dm * d.dd_chunks + chunk) * d.nslot + slot] = make_double2(rr, ri);
+}
+
+__global__ __launch_bounds__(256) void k_rho_dd_sum(const Dev d) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x, dm = blockIdx.y;
+  if (slot >= d.nslot) return;
+  double rr = 0.0, ri = 0.0;
+  for (int c = 0; c < d.dd_chunks; ++c) {
+    const double2 v = d.rhoDp[((size_t)dm * d.dd_chunks + c) * d.nslot + slot];
+    rr += v.x;
+    ri += v.y;
   }
   d.rhoD[(size_t)dm * d.nslot + slot] = make_double2(rr, ri);
 }
@@ -180,7 +195,10 @@ __global__ __launch_bounds__(256) void k_jpass_dd(const Dev d, int deg, double *
   } while (0)
 
 hipError_t launch_rho_dd(const Dev &d, int ndm, hipStream_t st) {
-  hipLaunchKernelGGL(k_rho_dd, dim3((unsigned)((d.nslot + 255) / 256), ndm), dim3(256), 0, st, d);
+  const unsigned bx = (unsigned)((d.nslot + 255) / 256);
+  hipLaunchKernelGGL(k_rho_dd, dim3(bx, d.dd_chunks, ndm), dim3(256), 0, st, d);
+  PWDF_CHECK_LAUNCH_DD();
+  hipLaunchKernelGGL(k_rho_dd_sum, dim3(bx, ndm), dim3(256), 0, st, d);
   PWDF_CHECK_LAUNCH_DD();
   return hipSuccess;
 }

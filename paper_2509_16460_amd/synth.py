@@ -420,6 +420,21 @@ def small_problem(kind: str = "sp", seed: int = 11, kmesh=(1, 1, 1), omega: floa
 
 
 
+def diffuse_problem(seed: int = 7, a: float = 8.0, natm: int = 4, kmesh=(2, 2, 2), omega: float = 0.5) -> Problem:
+    """A cell with diffuse shells for the compact/diffuse classification: natm
+    atoms at seeded positions in a slightly skewed cell of side ~a Bohr, per atom
+    s, p, d shells with one compact exponent each (2.2, 1.3, 0.9) and one just
+    below alpha_cut = omega^2/2 (0.11, 0.115, 0.12 at omega = 0.5), so CC, CD and
+    DD pairs of every class up to (2, 2) occur; alpha_cut is set."""
+    rng = np.random.default_rng(seed)
+    lat = np.array([[a, 0.0, 0.0], [0.05 * a, 1.04 * a, 0.0], [-0.07 * a, 0.08 * a, 0.95 * a]])
+    xyz = rng.uniform(0, 1, size=(natm, 3)) @ lat
+    ex = {0: [np.array([2.2, 0.11]), np.array([1.3, 0.115]), np.array([0.9, 0.12])]}
+    prob = build_problem(f"diffuse{natm}_spd_a{a:g}", lat, xyz, [0] * natm, ex, kmesh, omega,
+                         nelec=2.0 * natm, seed=seed)
+    return prob.with_(alpha_cut=omega ** 2 / 2)
+
+
 def make_densities_torch(prob: Problem, ndm: int, base_seed: int, Sk: np.ndarray, device="cuda", which=None):
     """Random Hermitian PSD D(k) with torch: the time-reversal-symmetric
     construction of make_density (D(k) = X_k X_k^H, D(-k) = conj D(k), real X at
