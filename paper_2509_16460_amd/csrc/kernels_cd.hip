@@ -141,22 +141,23 @@ __global__ __launch_bounds__(64) void k_combine_dd(const Dev d) {
 
 // Moments of one DD pair for one density, y_k = sum_G n^k (Re U if |k| even,
 // else Im U), U = conj V_D(G) S(G), over the half space (the J pass's moments,
-// with V_D for V_C): the workgroup stages U and n of 256 slots in LDS, then
-// thread k adds its moment over them in slot order.  Degree L (J) or L+1
+// with V_D for V_C): the workgroup stages U and the powers n_u^e, n_v^e, n_w^e of
+// 256 slots in LDS; the 256 threads form 256 / NT groups of NT, thread (g, k)
+// adding moment k over the slots g, g + groups, ... of the tile; at the end the
+// groups' sums of each moment are added in group order.  Degree L (J) or L+1
 // (force moments).
 __global__ __launch_bounds__(256) void k_jpass_dd(const Dev d, int deg, double *__restrict__ out) {
   __shared__ double2 sU[256];
-  __shared__ double sn[3][256];
+  __shared__ double spw[3][kMaxLsum + 1][256];
+  __shared__ double red[256];
   const int i = blockIdx.x, dm = blockIdx.y, t = threadIdx.x;
   const int q = d.dd_q[i];
   const int NT = nherm(d.dd_L[i] + deg);
+  const int groups = 256 / NT;
+  const int k = t % NT, g = t / NT;
+  const bool active = g < groups;
   const PairHot h = d.hot[q];
-  int a = 0, b = 0, c = 0;
-  if (t < NT) {
-    a = kMonoDD.u[t];
-    b = kMonoDD.v[t];
-    c = kMonoDD.w[t];
-  }
+  const int a = kMonoDD.u[k], b = kMonoDD.v[k], c = kMonoDD.w[k];
   const bool odd = (a + b + c) & 1;
   double acc = 0.0;
   for (int base = 0; base < d.nslot; base += 256) {
@@ -170,22 +171,32 @@ __global__ __launch_bounds__(256) void k_jpass_dd(const Dev d, int deg, double *
     }
     __syncthreads();
     sU[t] = U;
-    sn[0][t] = n[0];
-    sn[1][t] = n[1];
-    sn[2][t] = n[2];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+      double pw = 1.0;
+#pragma unroll
+      for (int e = 0; e <= kMaxLsum; ++e) {
+        spw[x][e][t] = pw;
+        pw *= n[x];
+      }
+    }
     __syncthreads();
-    if (t < NT) {
+    if (active) {
       const int m = min(256, d.nslot - base);
-      for (int j = 0; j < m; ++j) {
-        double mono = 1.0;
-        for (int e = 0; e < a; ++e) mono *= sn[0][j];
-        for (int e = 0; e < b; ++e) mono *= sn[1][j];
-        for (int e = 0; e < c; ++e) mono *= sn[2][j];
+      for (int j = g; j < m; j += groups) {
+        const double mono = spw[0][a][j] * spw[1][b][j] * spw[2][c][j];
         acc = fma(mono, odd ? sU[j].y : sU[j].x, acc);
       }
     }
   }
-  if (t < NT) out[((size_t)dm * d.ndd + i) * kDDStride + t] = acc;
+  __syncthreads();
+  red[t] = active ? acc : 0.0;
+  __syncthreads();
+  if (t < NT) {
+    double s = 0.0;
+    for (int gg = 0; gg < groups; ++gg) s += red[gg * NT + t];
+    out[((size_t)dm * d.ndd + i) * kDDStride + t] = s;
+  }
 }
 
 #define PWDF_CHECK_LAUNCH_DD()          \

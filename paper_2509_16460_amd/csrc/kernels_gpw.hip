@@ -60,62 +60,110 @@ __device__ __forceinline__ double gpw_pref(const PairAux &x) {
   return 0.5 * x.pref_j / (s * sqrt(s));
 }
 
-// rho_D on the grid: one workgroup per tile of 8^3 points (two points per thread),
-// the tile's image entries in list order
+// One image entry of a DD pair as the collocation reads it: the Gaussian's centre
+// P + T, its squared cut radius and exponent, the pair's weight w c c N N K, the
+// offsets P - A and P - B, the grid box, the shells' l and the D(L) block offset.
+struct GpwEnt {
+  double cx, cy, cz, rc2, p, coef;
+  double xpa[3], xpb[3];
+  int box[6];
+  int la, lb;
+  int64_t eoff;
+};
+
+constexpr int kGpwBatch = 64;  // image entries staged in LDS at a time
+
+// rho_D on the grid: one workgroup per tile of 8^3 points (two points per thread);
+// the tile's image entries are staged in LDS in batches (one thread per entry
+// gathers its pair data), then every thread adds the batch's entries to its
+// points in list order
 __global__ __launch_bounds__(256) void k_gpw_collocate(const Dev d) {
+  __shared__ GpwEnt se[kGpwBatch];
   const int t = blockIdx.x, dm = blockIdx.y;
   const int t0 = t % d.gtiles[0], t1 = (t / d.gtiles[0]) % d.gtiles[1], t2 = t / (d.gtiles[0] * d.gtiles[1]);
   const int e0 = d.gtile_off[t], e1 = d.gtile_off[t + 1];
   const double *Dblk = d.Dblk + (size_t)dm * d.nelem;
-  for (int u = threadIdx.x; u < 512; u += blockDim.x) {
-    const int j0 = t0 * 8 + (u & 7), j1 = t1 * 8 + ((u >> 3) & 7), j2 = t2 * 8 + (u >> 6);
-    if (j0 >= d.gN[0] || j1 >= d.gN[1] || j2 >= d.gN[2]) continue;
-    double r[3];
-    gpw_point(d, j0, j1, j2, r);
-    double rho = 0.0;
-    for (int e = e0; e < e1; ++e) {
-      const int ent = d.gtile_ent[e];
-      const int *box = d.gimg_box + 6 * (size_t)ent;
-      if (j0 < box[0] || j0 > box[1] || j1 < box[2] || j1 > box[3] || j2 < box[4] || j2 > box[5]) continue;
-      const int k = d.gimg[4 * ent], m0 = d.gimg[4 * ent + 1], m1 = d.gimg[4 * ent + 2], m2 = d.gimg[4 * ent + 3];
-      double X[3], x2 = 0.0;
+  int jj[2][3];
+  double r[2][3], rho[2] = {0.0, 0.0};
+  bool in[2];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double T = d.lat[c * 3 + 0] * m0 + d.lat[c * 3 + 1] * m1 + d.lat[c * 3 + 2] * m2;
-        X[c] = r[c] - d.gP[4 * k + c] - T;
-        x2 += X[c] * X[c];
-      }
-      if (x2 > d.gP[4 * k + 3]) continue;
+  for (int v = 0; v < 2; ++v) {
+    const int u = threadIdx.x + 256 * v;
+    jj[v][0] = t0 * 8 + (u & 7);
+    jj[v][1] = t1 * 8 + ((u >> 3) & 7);
+    jj[v][2] = t2 * 8 + (u >> 6);
+    in[v] = jj[v][0] < d.gN[0] && jj[v][1] < d.gN[1] && jj[v][2] < d.gN[2];
+    gpw_point(d, jj[v][0], jj[v][1], jj[v][2], r[v]);
+  }
+  for (int b0 = e0; b0 < e1; b0 += kGpwBatch) {
+    const int nb = min(kGpwBatch, e1 - b0);
+    __syncthreads();
+    if ((int)threadIdx.x < nb) {
+      const int ent = d.gtile_ent[b0 + threadIdx.x];
+      const int k = d.gimg[4 * ent], m0 = d.gimg[4 * ent + 1], m1 = d.gimg[4 * ent + 2], m2 = d.gimg[4 * ent + 3];
       const int q = d.dd_q[k];
       const BlockRec b = d.blocks[d.dd_blk[k]];
-      const int la = d.sh_l[b.sa], lb = d.sh_l[b.sb];
-      const int ncb = ncart(lb);
       const PairAux x = d.aux[q];
-      double pa[3][kMaxL + 1], pb[3][kMaxL + 1];
+      GpwEnt g;
+      g.cx = d.gP[4 * k + 0] + d.lat[0] * m0 + d.lat[1] * m1 + d.lat[2] * m2;
+      g.cy = d.gP[4 * k + 1] + d.lat[3] * m0 + d.lat[4] * m1 + d.lat[5] * m2;
+      g.cz = d.gP[4 * k + 2] + d.lat[6] * m0 + d.lat[7] * m1 + d.lat[8] * m2;
+      g.rc2 = d.gP[4 * k + 3];
+      g.p = x.p;
+      g.coef = x.w * gpw_pref(x);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        pa[c][0] = pb[c][0] = 1.0;
+        g.xpa[c] = x.xpa[c];
+        g.xpb[c] = x.xpb[c];
+      }
 #pragma unroll
-        for (int i = 1; i <= kMaxL; ++i) {
-          pa[c][i] = pa[c][i - 1] * (X[c] + x.xpa[c]);
-          pb[c][i] = pb[c][i - 1] * (X[c] + x.xpb[c]);
-        }
-      }
-      double s = 0.0;
-      for (int ia = 0; ia < ncart(la); ++ia) {
-        int ax, ay, az;
-        gpw_cart(la, ia, ax, ay, az);
-        const double fa = pa[0][ax] * pa[1][ay] * pa[2][az];
-        for (int ib = 0; ib < ncb; ++ib) {
-          int bx, by, bz;
-          gpw_cart(lb, ib, bx, by, bz);
-          s = fma(Dblk[b.eoff + ia * ncb + ib] * fa, pb[0][bx] * pb[1][by] * pb[2][bz], s);
-        }
-      }
-      rho = fma(x.w * gpw_pref(x) * exp(-x.p * x2), s, rho);
+      for (int c = 0; c < 6; ++c) g.box[c] = d.gimg_box[6 * (size_t)ent + c];
+      g.la = d.sh_l[b.sa];
+      g.lb = d.sh_l[b.sb];
+      g.eoff = b.eoff;
+      se[threadIdx.x] = g;
     }
-    d.grid_r[(size_t)dm * d.gpts + ((size_t)j2 * d.gN[1] + j1) * d.gN[0] + j0] = rho;
+    __syncthreads();
+    for (int e = 0; e < nb; ++e) {
+      const GpwEnt &g = se[e];
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        if (!in[v] || jj[v][0] < g.box[0] || jj[v][0] > g.box[1] || jj[v][1] < g.box[2] || jj[v][1] > g.box[3] ||
+            jj[v][2] < g.box[4] || jj[v][2] > g.box[5])
+          continue;
+        const double X[3] = {r[v][0] - g.cx, r[v][1] - g.cy, r[v][2] - g.cz};
+        const double x2 = X[0] * X[0] + X[1] * X[1] + X[2] * X[2];
+        if (x2 > g.rc2) continue;
+        double pa[3][kMaxL + 1], pb[3][kMaxL + 1];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          pa[c][0] = pb[c][0] = 1.0;
+#pragma unroll
+          for (int l = 1; l <= kMaxL; ++l) {
+            pa[c][l] = pa[c][l - 1] * (X[c] + g.xpa[c]);
+            pb[c][l] = pb[c][l - 1] * (X[c] + g.xpb[c]);
+          }
+        }
+        const int ncb = ncart(g.lb);
+        double sum = 0.0;
+        for (int ia = 0; ia < ncart(g.la); ++ia) {
+          int ax, ay, az;
+          gpw_cart(g.la, ia, ax, ay, az);
+          const double fa = pa[0][ax] * pa[1][ay] * pa[2][az];
+          for (int ib = 0; ib < ncb; ++ib) {
+            int bx, by, bz;
+            gpw_cart(g.lb, ib, bx, by, bz);
+            sum = fma(Dblk[g.eoff + ia * ncb + ib] * fa, pb[0][bx] * pb[1][by] * pb[2][bz], sum);
+          }
+        }
+        rho[v] = fma(g.coef * exp(-g.p * x2), sum, rho[v]);
+      }
+    }
   }
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+    if (in[v])
+      d.grid_r[(size_t)dm * d.gpts + ((size_t)jj[v][2] * d.gN[1] + jj[v][1]) * d.gN[0] + jj[v][0]] = rho[v];
 }
 
 // One pass of the separable transform along axis a: out[o2][o1][o0] (dims d0, d1,
