@@ -327,6 +327,23 @@ pwdf_status pwdf_get_rhoG(pwdf_ctx *ctx, int ndm, const double *Dk, double *rhoG
                           void *stream);
 
 /*
+ * Real-space form of the energy, E_J^(R) = 1/2 sum over (a, b, L) of D_ab(L) J_ab(L)
+ * (section "Long-range contributions": the energy as the contraction of the
+ * real-space density and Coulomb blocks), from the D(L) and J(L) blocks that the
+ * last pwdf_build_j or pwdf_build_j_graph call on ctx left in its workspace.  It
+ * equals the E_J of that call (the G-space sum 1/2 Omega sum_G v |rho|^2, and its
+ * compact/diffuse form) up to rounding, in either precision form: a cross-check
+ * of the whole path rather than a second result.
+ *   ndm  1 .. the ndm of that call: the first ndm densities.
+ *   ER   device, double [ndm], written.
+ * Same stream as the build (or ordered after it).  PWDF_ESTATE when the
+ * workspace holds no such blocks: no build yet, fewer densities, or another call
+ * since (pwdf_build_j_noalloc, pwdf_get_rhoG, pwdf_grad, pwdf_autotune,
+ * pwdf_set_fp32_head replace them).
+ */
+pwdf_status pwdf_energy_real(pwdf_ctx *ctx, int ndm, double *ER, void *stream);
+
+/*
  * Nuclear gradient dE_J/dR_A at fixed D(k), fixed pair list and fixed G set
  * (derivative of the pair transform with respect to the Gaussian centres,
  * eq. "cart gaussian function" and eq. "FT of cart Gaussians").

@@ -65,6 +65,8 @@ struct pwdf_ctx {
   Dev dev;
   std::vector<void *> owned;  // device allocations of the current setup
   double *Escr = nullptr;     // [max_ndm] energies of diagnostic calls
+  double *ERpart = nullptr;   // [max_ndm][256] partials of the real-space energy
+  int blocks_ndm = 0;         // densities whose D(L) / J(L) blocks the workspace holds
   hipStream_t aux[kAux] = {};
   hipStream_t cap = nullptr;  // capture / tuning stream
   hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
@@ -383,6 +385,7 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm, WorkLists
 // (Re)builds the device view of the plan: uploads and workspaces for the current
 // segment length and tune.  Frees the previous setup first.
 pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
+  c->blocks_ndm = 0;
   drop_graph(c);
   free_device(c);
   c->tune = tn;
@@ -502,8 +505,10 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
     UP(p.gimg, gimg)
     UP(p.gimg_box, gimg_box)
     UP(p.gimg_off, gimg_off)
-    UP(p.gtile_off, gtile_off)
     UP(p.gtile_ent, gtile_ent)
+    UP(p.gitem, gitem)
+    UP(p.gitem_off, gitem_off)
+    d.ngitems = (int)(p.gitem.size() / 3);
     UP(p.slot_miller, slot_miller)
   }
   if (d.fp32) {
@@ -551,6 +556,7 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   }
   if (d.gpw) {
     AL(grid_r, M * d.gpts)
+    AL(grid_p, M * d.ngitems * 512)
     AL(grid_a, M * gpw_a_size(d))
     AL(grid_b, M * gpw_b_size(d))
     AL(grid_c, M * gpw_c_size(d))
@@ -586,6 +592,8 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
       return hip_fail(c, e, "uploading atom lists");
   }
   if ((e = alloc(c, M, &c->Escr)) != hipSuccess) return fail(c, PWDF_ENOMEM, "device allocation failed: energies");
+  if ((e = alloc(c, M * 256, &c->ERpart)) != hipSuccess)
+    return fail(c, PWDF_ENOMEM, "device allocation failed: energy partials");
   if ((e = alloc(c, 1, &d.nonfinite)) != hipSuccess) return fail(c, PWDF_ENOMEM, "device allocation failed: flag");
   if ((e = hipMemset(d.nonfinite, 0, sizeof(int))) != hipSuccess) return hip_fail(c, e, "clearing the input flag");
   return PWDF_OK;
@@ -1087,7 +1095,10 @@ pwdf_status pwdf_build_j(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, dou
   if (!Dk || !Jk || !EJ) return fail(c, PWDF_EINVAL, "NULL buffer");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-  return enqueue_build(c, ndm, Dk, Jk, EJ, (hipStream_t)stream);
+  c->blocks_ndm = 0;
+  if ((s = enqueue_build(c, ndm, Dk, Jk, EJ, (hipStream_t)stream)) != PWDF_OK) return s;
+  c->blocks_ndm = ndm;
+  return PWDF_OK;
 }
 
 pwdf_status pwdf_build_j_graph(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, double *EJ, void *stream) {
@@ -1124,7 +1135,9 @@ pwdf_status pwdf_build_j_graph(pwdf_ctx *c, int ndm, const double *Dk, double *J
     g.Jk = Jk;
     g.EJ = EJ;
   }
+  c->blocks_ndm = 0;
   if ((e = hipGraphLaunch(g.exec, st)) != hipSuccess) return hip_fail(c, e, "graph launch");
+  c->blocks_ndm = ndm;
   return PWDF_OK;
 }
 
@@ -1157,6 +1170,7 @@ static size_t carve_build_ws(Dev &d, const Plan &p, int ndm, unsigned char *base
   }
   if (d.gpw) {
     take(d.grid_r, M * d.gpts);
+    take(d.grid_p, M * d.ngitems * 512);
     take(d.grid_a, M * gpw_a_size(d));
     take(d.grid_b, M * gpw_b_size(d));
     take(d.grid_c, M * gpw_c_size(d));
@@ -1202,7 +1216,26 @@ pwdf_status pwdf_build_j_noalloc(pwdf_ctx *c, int ndm, const double *Dk, double 
   c->dev = d;
   s = enqueue_build(c, ndm, Dk, Jk, EJ, st);
   c->dev = saved;
+  c->blocks_ndm = 0;  // the blocks went to the shared scratch
   return s;
+}
+
+pwdf_status pwdf_energy_real(pwdf_ctx *c, int ndm, double *ER, void *stream) {
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_energy_real: ctx is NULL");
+  if (!ER) return fail(c, PWDF_EINVAL, "NULL buffer");
+  if (ndm < 1 || ndm > c->blocks_ndm) {
+    char m[256];
+    std::snprintf(m, sizeof m,
+                  "pwdf_energy_real: the workspace holds the D(L) and J(L) blocks of %d densities (those of the "
+                  "last pwdf_build_j or pwdf_build_j_graph call; any other call replaces them), %d asked",
+                  c->blocks_ndm, ndm);
+    return fail(c, PWDF_ESTATE, m);
+  }
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  if ((e = launch_energy_real(c->dev, ndm, c->ERpart, ER, (hipStream_t)stream)) != hipSuccess)
+    return hip_fail(c, e, "real-space energy");
+  return PWDF_OK;
 }
 
 pwdf_status pwdf_get_rhoG(pwdf_ctx *c, int ndm, const double *Dk, double *rhoG, int *miller, void *stream) {
@@ -1213,6 +1246,7 @@ pwdf_status pwdf_get_rhoG(pwdf_ctx *c, int ndm, const double *Dk, double *rhoG, 
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  c->blocks_ndm = 0;
   if ((s = run_to_rho(c, ndm, Dk, c->Escr, st)) != PWDF_OK) return s;
   // gather the valid slots on the host side of the copy (small: nG/2 complex per density)
   const Plan &p = c->plan;
@@ -1243,6 +1277,7 @@ pwdf_status pwdf_grad(pwdf_ctx *c, int ndm, const double *Dk, double *dEdR, doub
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   // energy path (rho, V) in the context's precision; the adjoint moments and the
   // centre-derivative contraction run in FP64
+  c->blocks_ndm = 0;
   if ((s = run_to_rho(c, ndm, Dk, EJ ? EJ : c->Escr, st)) != PWDF_OK) return s;
   const Plan &p = c->plan;
   const Dev &d = c->dev;
@@ -1456,6 +1491,7 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   // the workspaces are rebuilt below: nothing may still be running on them
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+  c->blocks_ndm = 0;
   const std::string key = tune_key(c, ndm);
   Tune best;
   if (load_tune(cache_path, key, best)) {

@@ -129,14 +129,17 @@ struct Dev {
   // indices; workspaces: a real grid [ndm][gpts] (density, then V(r)), complex
   // intermediates of the separable transforms ([ndm][N2][N1][K0],
   // [ndm][N2][K1][K0], [ndm][K2][K1][K0], K_i = 2 gM_i + 1) and the DD pairs'
-  // J partials [ndm][ndd][kGpwEl]
+  // J partials [ndm][ndd][kGpwEl]; the collocation's work items (gitem,
+  // gitem_off) and their partial tiles grid_p [ndm][ngitems][512]
   int gpw;
   int gN[3], gM[3], gtiles[3];
   int64_t gpts;
   double lat[9];
   const int *dd_blk;
   const double *gP;
-  const int *gimg, *gimg_box, *gimg_off, *gtile_off, *gtile_ent;
+  const int *gimg, *gimg_box, *gimg_off, *gtile_ent, *gitem, *gitem_off;
+  int ngitems;
+  double *grid_p;
   const int *slot_miller;
   double *grid_r;
   double2 *grid_a, *grid_b, *grid_c;
@@ -207,6 +210,8 @@ hipError_t launch_rho_dd(const Dev &d, int ndm, hipStream_t st);
 hipError_t launch_combine_dd(const Dev &d, int ndm, hipStream_t st);
 hipError_t launch_jpass_dd(const Dev &d, bool force, int ndm, hipStream_t st);
 hipError_t launch_energy(const Dev &d, int ndm, double *EJ, hipStream_t st);
+// E_J from the D(L) and J(L) blocks; part holds 256 doubles per density
+hipError_t launch_energy_real(const Dev &d, int ndm, double *part, double *ER, hipStream_t st);
 // GPW route: rho_D from the DD pairs' density on the grid (collocation and a
 // separable transform onto the G set); V_D onto the grid and the DD pairs' J
 // blocks by integration, added to J(L) after the back transform

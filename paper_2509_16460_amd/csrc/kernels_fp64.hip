@@ -1722,4 +1722,48 @@ hipError_t launch_energy(const Dev &d, int ndm, double *EJ, hipStream_t st) {
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// E_J in real space, (1/2) sum over (a, b, L) of D_ab(L) J_ab(L), from the D(L)
+// and J(L) blocks of a build: a block with its mirror (b, a, -L) folded in counts
+// twice (D and J are real and the mirror's values equal the block's).  A wave per
+// block at a time (blocks strided over the kERBlocks x 4 waves), partials per workgroup in
+// a fixed order, then one fixed-order sum per density.
+// ---------------------------------------------------------------------------
+constexpr int kERBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_energy_real_part(const Dev d, double *__restrict__ part) {
+  __shared__ double sh[256];
+  const int dm = blockIdx.y, lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * 4 + (threadIdx.x >> 6), nw = kERBlocks * 4;
+  const double *D = d.Dblk + (size_t)dm * d.nelem, *J = d.Jblk + (size_t)dm * d.nelem;
+  double acc = 0.0;
+  for (int b = gw; b < d.nblocks; b += nw) {
+    const BlockRec r = d.blocks[b];
+    const int n = ncart(d.sh_l[r.sa]) * ncart(d.sh_l[r.sb]);
+    double s = 0.0;
+    for (int e = lane; e < n; e += 64) s = fma(D[r.eoff + e], J[r.eoff + e], s);
+    acc += r.w2 ? 2.0 * s : s;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)dm * kERBlocks + blockIdx.x] = 0.5 * sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_energy_real_sum(const double *__restrict__ part, double *__restrict__ ER) {
+  __shared__ double sh[256];
+  energy_block(part, kERBlocks, ER, blockIdx.x, sh);
+}
+
+hipError_t launch_energy_real(const Dev &d, int ndm, double *part, double *ER, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_real_part, dim3(kERBlocks, ndm), dim3(256), 0, st, d, part);
+  PWDF_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_energy_real_sum, dim3(ndm), dim3(256), 0, st, part, ER);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
 }  // namespace pwdf

@@ -73,15 +73,16 @@ struct GpwEnt {
 
 constexpr int kGpwBatch = 64;  // image entries staged in LDS at a time
 
-// rho_D on the grid: one workgroup per tile of 8^3 points (two points per thread);
-// the tile's image entries are staged in LDS in batches (one thread per entry
-// gathers its pair data), then every thread adds the batch's entries to its
-// points in list order
+// rho_D on the grid, one workgroup per work item (a run of one tile's image
+// entries; 8^3 points, two per thread): the entries are staged in LDS in batches
+// (one thread per entry gathers its pair data), then every thread adds the
+// batch's entries to its points in list order.  The item's partial tile goes to
+// grid_p; k_gpw_collect sums a tile's items in order.
 __global__ __launch_bounds__(256) void k_gpw_collocate(const Dev d) {
   __shared__ GpwEnt se[kGpwBatch];
-  const int t = blockIdx.x, dm = blockIdx.y;
+  const int item = blockIdx.x, dm = blockIdx.y;
+  const int t = d.gitem[3 * item], e0 = d.gitem[3 * item + 1], e1 = d.gitem[3 * item + 2];
   const int t0 = t % d.gtiles[0], t1 = (t / d.gtiles[0]) % d.gtiles[1], t2 = t / (d.gtiles[0] * d.gtiles[1]);
-  const int e0 = d.gtile_off[t], e1 = d.gtile_off[t + 1];
   const double *Dblk = d.Dblk + (size_t)dm * d.nelem;
   int jj[2][3];
   double r[2][3], rho[2] = {0.0, 0.0};
@@ -160,10 +161,23 @@ __global__ __launch_bounds__(256) void k_gpw_collocate(const Dev d) {
       }
     }
   }
-#pragma unroll
-  for (int v = 0; v < 2; ++v)
-    if (in[v])
-      d.grid_r[(size_t)dm * d.gpts + ((size_t)jj[v][2] * d.gN[1] + jj[v][1]) * d.gN[0] + jj[v][0]] = rho[v];
+  double *out = d.grid_p + ((size_t)dm * d.ngitems + item) * 512;
+  out[threadIdx.x] = rho[0];
+  out[threadIdx.x + 256] = rho[1];
+}
+
+// rho_D of a tile: its work items' partial tiles summed in item order
+__global__ __launch_bounds__(256) void k_gpw_collect(const Dev d) {
+  const int t = blockIdx.x, dm = blockIdx.y;
+  const int t0 = t % d.gtiles[0], t1 = (t / d.gtiles[0]) % d.gtiles[1], t2 = t / (d.gtiles[0] * d.gtiles[1]);
+  const int i0 = d.gitem_off[t], i1 = d.gitem_off[t + 1];
+  for (int u = threadIdx.x; u < 512; u += 256) {
+    const int j0 = t0 * 8 + (u & 7), j1 = t1 * 8 + ((u >> 3) & 7), j2 = t2 * 8 + (u >> 6);
+    if (j0 >= d.gN[0] || j1 >= d.gN[1] || j2 >= d.gN[2]) continue;
+    double s = 0.0;
+    for (int i = i0; i < i1; ++i) s += d.grid_p[((size_t)dm * d.ngitems + i) * 512 + u];
+    d.grid_r[(size_t)dm * d.gpts + ((size_t)j2 * d.gN[1] + j1) * d.gN[0] + j0] = s;
+  }
 }
 
 // One pass of the separable transform along axis a: out[o2][o1][o0] (dims d0, d1,
@@ -365,7 +379,9 @@ hipError_t launch_gpw_rho(const Dev &d, int ndm, hipStream_t st) {
   const int N0 = d.gN[0], N1 = d.gN[1], N2 = d.gN[2];
   const int K0 = 2 * d.gM[0] + 1, K1 = 2 * d.gM[1] + 1, K2 = 2 * d.gM[2] + 1;
   const int ntiles = d.gtiles[0] * d.gtiles[1] * d.gtiles[2];
-  hipLaunchKernelGGL(k_gpw_collocate, dim3((unsigned)ntiles, ndm), dim3(256), 0, st, d);
+  hipLaunchKernelGGL(k_gpw_collocate, dim3((unsigned)d.ngitems, ndm), dim3(256), 0, st, d);
+  PWDF_CHECK_LAUNCH_GPW();
+  hipLaunchKernelGGL(k_gpw_collect, dim3((unsigned)ntiles, ndm), dim3(256), 0, st, d);
   PWDF_CHECK_LAUNCH_GPW();
   hipError_t e;
   if ((e = gpw_axis(d, nullptr, d.grid_r, d.grid_a, nullptr, K0, N1, N2, 0, N0, -1, 1, ndm, st)) != hipSuccess) return e;

@@ -174,6 +174,7 @@ static void head_points(Plan &p);
 // alike) would exceed kGpwMaxWork: GPW pays off when the cell is large against
 // the diffuse Gaussians; for a small cell the analytic route is the one to use.
 constexpr double kGpwMaxWork = 3e9;
+constexpr int kGpwItems = 2048;
 
 static std::string build_gpw(Plan &p) {
   for (int i = 0; i < 3; ++i) p.gM[i] = 0;
@@ -255,6 +256,20 @@ static std::string build_gpw(Plan &p) {
     p.gtile_ent.insert(p.gtile_ent.end(), per[t].begin(), per[t].end());
   }
   p.gtile_off[nt] = (int)p.gtile_ent.size();
+  // about kGpwItems work items over the whole grid, at least 32 entries each
+  p.glen = (int)std::max<int64_t>(32, ((int64_t)p.gtile_ent.size() + kGpwItems - 1) / kGpwItems);
+  p.gitem.clear();
+  p.gitem_off.assign(nt + 1, 0);
+  for (int t = 0; t < nt; ++t) {
+    p.gitem_off[t] = (int)(p.gitem.size() / 3);
+    int a = p.gtile_off[t];
+    do {
+      const int b = std::min(p.gtile_off[t + 1], a + p.glen);
+      p.gitem.insert(p.gitem.end(), {t, a, b});
+      a = b;
+    } while (a < p.gtile_off[t + 1]);
+  }
+  p.gitem_off[nt] = (int)(p.gitem.size() / 3);
   return std::string();
 }
 

@@ -138,12 +138,16 @@ struct Plan {
   // (gP: x, y, z, rc^2); its lattice images whose ball reaches the cell (gimg:
   // dd index, m0, m1, m2; gimg_box: grid index box lo0 hi0 lo1 hi1 lo2 hi2 inside
   // the cell; gimg_off[dd] first entry), and per tile of 8^3 grid points the image
-  // entries whose box meets it (gtile_off, gtile_ent).
+  // entries whose box meets it (gtile_off, gtile_ent).  The collocation's work
+  // items cut each tile's list into runs of at most glen entries (gitem: tile,
+  // first entry, end entry; gitem_off[tile] its first item), so that a small grid
+  // still spreads over enough workgroups.
   int gN[3] = {0, 0, 0}, gM[3] = {0, 0, 0};
   int gtiles[3] = {0, 0, 0};
+  int glen = 0;
   std::vector<int> dd_blk;
   std::vector<double> gP;
-  std::vector<int> gimg, gimg_box, gimg_off, gtile_off, gtile_ent;
+  std::vector<int> gimg, gimg_box, gimg_off, gtile_off, gtile_ent, gitem, gitem_off;
 
   // the pair-G kernels must honour gc2 (per-pair cuts, or DD pairs to skip)
   bool cut_on() const { return in.pair_gcut != 0 || !dd_q.empty(); }

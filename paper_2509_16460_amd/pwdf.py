@@ -29,7 +29,7 @@ PWDF_JK_PACKED = 2
 EXPORTED = ["pwdf_create", "pwdf_query", "pwdf_build_j", "pwdf_build_j_graph", "pwdf_get_rhoG", "pwdf_grad",
             "pwdf_autotune", "pwdf_last_error", "pwdf_destroy", "pwdf_plan_stats",
             "pwdf_profile_enable", "pwdf_profile_read", "pwdf_set_jk_layout", "pwdf_check_input",
-            "pwdf_get_jk_support", "pwdf_build_j_noalloc", "pwdf_set_fp32_head"]
+            "pwdf_get_jk_support", "pwdf_build_j_noalloc", "pwdf_set_fp32_head", "pwdf_energy_real"]
 
 
 class PwdfError(RuntimeError):
@@ -108,6 +108,8 @@ def lib():
         L.pwdf_set_jk_layout.argtypes = [vp, ctypes.c_int]
         L.pwdf_set_fp32_head.restype = ctypes.c_int
         L.pwdf_set_fp32_head.argtypes = [vp, ctypes.c_double]
+        L.pwdf_energy_real.restype = ctypes.c_int
+        L.pwdf_energy_real.argtypes = [vp, ctypes.c_int, vp, vp]
         L.pwdf_get_jk_support.restype = ctypes.c_int
         L.pwdf_get_jk_support.argtypes = [vp, ip, ip]
         L.pwdf_check_input.restype = ctypes.c_int
@@ -162,6 +164,7 @@ class LongRangeJ:
         self.precision = precision
         self.max_ndm = max_ndm
         self.device = device
+        self._last_ndm = 0
         a = _basis_arrays(prob)
         self._keep = a
         scr = _screen(prob)
@@ -283,7 +286,19 @@ class LongRangeJ:
                 ctypes.c_void_p(EJ.data_ptr()), self._stream(stream))
         if rc != 0:
             self._err(rc)
+        self._last_ndm = ndm
         return Jk, EJ
+
+    def energy_real(self, ndm=None, stream=None):
+        """E_J^(R) = 1/2 sum D(L) J(L) of the last build_j (eager or graph) on this
+        context, [ndm] device tensor; ndm defaults to that build's."""
+        import torch
+        n = self._last_ndm if ndm is None else ndm
+        ER = torch.empty(max(1, n), dtype=torch.float64, device=torch.device("cuda", self.device))
+        rc = lib().pwdf_energy_real(self._h, n, ctypes.c_void_p(ER.data_ptr()), self._stream(stream))
+        if rc != 0:
+            self._err(rc)
+        return ER
 
     def get_rhoG(self, Dk, stream=None):
         """rho(G) on the half space the kernels walk, and the Miller indices (host)."""
