@@ -411,6 +411,22 @@ const char *pwdf_last_error(const pwdf_ctx *ctx);
 /* Free the plan and all device workspaces; NULL is a no-op. */
 void pwdf_destroy(pwdf_ctx *ctx);
 
+/*
+ * Test hooks of the library's device allocations (every plan upload and
+ * workspace of every context goes through one allocator; the static scratch of
+ * pwdf_build_j_noalloc is not an allocation).
+ * pwdf_debug_fail_alloc(after): after >= 0 lets that many further allocations
+ * succeed and fails every one after them with an out-of-memory error until the
+ * next call; after < 0 turns the failures off (the default).  A setup that fails
+ * returns PWDF_ENOMEM and releases what it had allocated: pwdf_create then
+ * returns no context; a context whose re-setup failed (pwdf_autotune,
+ * pwdf_set_fp32_head) answers PWDF_ESTATE to device work until pwdf_destroy.
+ * pwdf_debug_live_allocs(): device allocations currently held by all contexts.
+ * Process-wide; not for use while other threads create or tune contexts.
+ */
+void pwdf_debug_fail_alloc(int after);
+int64_t pwdf_debug_live_allocs(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -67,6 +68,7 @@ struct pwdf_ctx {
   double *Escr = nullptr;     // [max_ndm] energies of diagnostic calls
   double *ERpart = nullptr;   // [max_ndm][256] partials of the real-space energy
   int blocks_ndm = 0;         // densities whose D(L) / J(L) blocks the workspace holds
+  bool ready = false;         // the device setup is complete (false after a failed one)
   hipStream_t aux[kAux] = {};
   hipStream_t cap = nullptr;  // capture / tuning stream
   hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
@@ -97,14 +99,35 @@ pwdf_status plan_status(const std::string &why) {
 
 pwdf_status hip_fail(pwdf_ctx *c, hipError_t e, const char *where) {
   std::string m = std::string(where) + ": " + hipGetErrorString(e);
-  return fail(c, PWDF_EDEVICE, m);
+  return fail(c, e == hipErrorOutOfMemory ? PWDF_ENOMEM : PWDF_EDEVICE, m);
+}
+
+// Every device allocation of the library goes through dev_malloc / dev_free:
+// g_live counts the allocations held (all contexts), g_alloc_budget >= 0 makes
+// every allocation after that many more fail (pwdf_debug_fail_alloc).
+std::atomic<int64_t> g_live{0};
+std::atomic<int> g_alloc_budget{-1};
+
+hipError_t dev_malloc(void **p, size_t n) {
+  int b = g_alloc_budget.load();
+  while (b >= 0) {
+    if (b == 0) return hipErrorOutOfMemory;
+    if (g_alloc_budget.compare_exchange_weak(b, b - 1)) break;
+  }
+  const hipError_t e = hipMalloc(p, n);
+  if (e == hipSuccess) ++g_live;
+  return e;
+}
+
+void dev_free(void *p) {
+  if (p && hipFree(p) == hipSuccess) --g_live;
 }
 
 template <class T>
 hipError_t upload(pwdf_ctx *c, const std::vector<T> &v, const T **out) {
   void *p = nullptr;
   size_t n = std::max<size_t>(1, v.size()) * sizeof(T);
-  hipError_t e = hipMalloc(&p, n);
+  hipError_t e = dev_malloc(&p, n);
   if (e != hipSuccess) return e;
   c->owned.push_back(p);
   if (!v.empty()) {
@@ -118,7 +141,7 @@ hipError_t upload(pwdf_ctx *c, const std::vector<T> &v, const T **out) {
 template <class T>
 hipError_t alloc(pwdf_ctx *c, size_t count, T **out) {
   void *p = nullptr;
-  hipError_t e = hipMalloc(&p, std::max<size_t>(1, count) * sizeof(T));
+  hipError_t e = dev_malloc(&p, std::max<size_t>(1, count) * sizeof(T));
   if (e != hipSuccess) return e;
   c->owned.push_back(p);
   *out = (T *)p;
@@ -126,7 +149,7 @@ hipError_t alloc(pwdf_ctx *c, size_t count, T **out) {
 }
 
 void free_device(pwdf_ctx *c) {
-  for (void *p : c->owned) (void)hipFree(p);
+  for (void *p : c->owned) dev_free(p);
   c->owned.clear();
 }
 
@@ -384,7 +407,7 @@ void choose_shapes(const Plan &p, Dev &d, const Tune &tn, int max_ndm, WorkLists
 
 // (Re)builds the device view of the plan: uploads and workspaces for the current
 // segment length and tune.  Frees the previous setup first.
-pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
+pwdf_status setup_device_impl(pwdf_ctx *c, const Tune &tn) {
   c->blocks_ndm = 0;
   drop_graph(c);
   free_device(c);
@@ -599,7 +622,28 @@ pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
   return PWDF_OK;
 }
 
+// A failed setup releases what it had allocated and leaves the context unusable
+// for device work (PWDF_ESTATE) until pwdf_destroy.
+pwdf_status setup_device(pwdf_ctx *c, const Tune &tn) {
+  c->ready = false;
+  const pwdf_status s = setup_device_impl(c, tn);
+  if (s != PWDF_OK) {
+    free_device(c);
+    std::memset(&c->dev, 0, sizeof(c->dev));
+    c->Escr = c->ERpart = nullptr;
+    return s;
+  }
+  c->ready = true;
+  return PWDF_OK;
+}
+
+pwdf_status not_ready(pwdf_ctx *c) {
+  return fail(c, PWDF_ESTATE,
+              "the context's device setup failed (" + c->err + "); it takes no further device work: destroy it");
+}
+
 pwdf_status validate_ndm(pwdf_ctx *c, int ndm) {
+  if (!c->ready) return not_ready(c);
   if (ndm < 1) return fail(c, PWDF_EINVAL, "ndm must be >= 1");
   if (ndm > c->max_ndm) return fail(c, PWDF_EUNSUPPORTED, "ndm exceeds max_ndm given to pwdf_create");
   return PWDF_OK;
@@ -1050,6 +1094,7 @@ pwdf_status pwdf_set_jk_layout(pwdf_ctx *c, int layout) {
 pwdf_status pwdf_set_fp32_head(pwdf_ctx *c, double weight) {
   if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_set_fp32_head: ctx is NULL");
   if (!(weight > 0.0 && weight <= 1.0)) return fail(c, PWDF_EINVAL, "head weight must be in (0, 1]");
+  if (!c->ready) return not_ready(c);
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   // the workspaces are rebuilt below: nothing may still be running on them
@@ -1073,6 +1118,7 @@ pwdf_status pwdf_get_jk_support(const pwdf_ctx *c, int *mu, int *nu) {
 
 pwdf_status pwdf_check_input(pwdf_ctx *c, void *stream) {
   if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_check_input: ctx is NULL");
+  if (!c->ready) return not_ready(c);
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
@@ -1685,6 +1731,10 @@ pwdf_status pwdf_profile_read(pwdf_ctx *c, pwdf_kprof *out, int max, int *n) {
 }
 
 const char *pwdf_last_error(const pwdf_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+void pwdf_debug_fail_alloc(int after) { g_alloc_budget.store(after < 0 ? -1 : after); }
+
+int64_t pwdf_debug_live_allocs(void) { return g_live.load(); }
 
 void pwdf_destroy(pwdf_ctx *c) {
   if (!c) return;

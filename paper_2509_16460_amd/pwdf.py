@@ -29,7 +29,8 @@ PWDF_JK_PACKED = 2
 EXPORTED = ["pwdf_create", "pwdf_query", "pwdf_build_j", "pwdf_build_j_graph", "pwdf_get_rhoG", "pwdf_grad",
             "pwdf_autotune", "pwdf_last_error", "pwdf_destroy", "pwdf_plan_stats",
             "pwdf_profile_enable", "pwdf_profile_read", "pwdf_set_jk_layout", "pwdf_check_input",
-            "pwdf_get_jk_support", "pwdf_build_j_noalloc", "pwdf_set_fp32_head", "pwdf_energy_real"]
+            "pwdf_get_jk_support", "pwdf_build_j_noalloc", "pwdf_set_fp32_head", "pwdf_energy_real",
+            "pwdf_debug_fail_alloc", "pwdf_debug_live_allocs"]
 
 
 class PwdfError(RuntimeError):
@@ -110,6 +111,10 @@ def lib():
         L.pwdf_set_fp32_head.argtypes = [vp, ctypes.c_double]
         L.pwdf_energy_real.restype = ctypes.c_int
         L.pwdf_energy_real.argtypes = [vp, ctypes.c_int, vp, vp]
+        L.pwdf_debug_fail_alloc.restype = None
+        L.pwdf_debug_fail_alloc.argtypes = [ctypes.c_int]
+        L.pwdf_debug_live_allocs.restype = ctypes.c_int64
+        L.pwdf_debug_live_allocs.argtypes = []
         L.pwdf_get_jk_support.restype = ctypes.c_int
         L.pwdf_get_jk_support.argtypes = [vp, ip, ip]
         L.pwdf_check_input.restype = ctypes.c_int

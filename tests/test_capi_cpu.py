@@ -222,3 +222,13 @@ def test_gpw_refuses_a_cell_far_smaller_than_its_diffuse_gaussians():
     with pytest.raises(pwdf.PwdfError, match="PWDF_EUNSUPPORTED"):
         pwdf.plan_stats(prob)
     assert pwdf.plan_stats(prob.with_(dd_gpw=0))["npairs_dd"] > 0
+
+
+def test_allocation_hooks_without_a_context():
+    """The allocation test hooks need no device: no allocation is held before
+    any context exists, and the failure budget can be set and cleared."""
+    L = pwdf.lib()
+    assert L.pwdf_debug_live_allocs() == 0
+    L.pwdf_debug_fail_alloc(3)
+    L.pwdf_debug_fail_alloc(-1)
+    assert L.pwdf_debug_live_allocs() == 0
