@@ -5,11 +5,21 @@
 // classes L >= 3 keep storage order.  Reads the problem as whitespace-separated
 // text: lattice (9), natm and xyz, nshell and shell atoms, shell l, shell primitive
 // counts, primitive count and exponents, coefficients, kmesh (3), omega, eps_pair,
-// eps_G, r_max.  Prints "pairs <n> classes <m> bad <b>" and exits non-zero on a
-// violation.
+// eps_G, r_max, and optionally pair_gcut, alpha_cut, dd_gpw.  Prints "pairs <n>
+// classes <m> bad <b>" and exits non-zero on a violation.
+//
+// With a second argument "sweep" it then rebuilds the segments for every segment
+// length the tuner can pick (4, 5, 8, 16) and recounts the head of the G set for
+// several weights, checking that the valid slots hold the same G vectors each
+// time (same count, each Miller index once, padding at (0,0,0) with v = 0) and
+// that the head grows with a smaller weight.  Built with the address and
+// undefined-behaviour sanitizers, this runs the host planning code over cells with
+// per-pair cuts, DD pairs and the GPW lists.
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <set>
+#include <tuple>
 #include <vector>
 
 #include "plan.h"
@@ -39,6 +49,13 @@ int main(int argc, char **argv) {
   for (double &x : in.coefs) f >> x;
   f >> in.kmesh[0] >> in.kmesh[1] >> in.kmesh[2] >> in.omega >> in.eps_pair >> in.eps_G >> in.r_max;
   if (!f) return 2;
+  int gcut = 0, gpw = 0;
+  double acut = 0.0;
+  if (f >> gcut >> acut >> gpw) {
+    in.pair_gcut = gcut;
+    in.alpha_cut = acut;
+    in.dd_gpw = gpw;
+  }
   Plan p;
   const std::string err = build_plan(in, 8, p);
   if (!err.empty()) {
@@ -74,6 +91,38 @@ int main(int argc, char **argv) {
   }
   for (int r = 0; r < n; ++r)
     if (order[r] < 0) bad++;
+  if (argc > 2 && std::strcmp(argv[2], "sweep") == 0) {
+    std::set<std::tuple<int, int, int>> ref;
+    long nvalid = -1;
+    for (int seg : {4, 5, 8, 16, 8}) {
+      build_segments(p, seg);
+      std::set<std::tuple<int, int, int>> got;
+      for (int s : p.valid_slots) {
+        const int *m = &p.slot_miller[3 * (size_t)s];
+        if (!got.insert({m[0], m[1], m[2]}).second) bad++;  // each G once
+      }
+      std::vector<char> valid(p.nslot(), 0);
+      for (int s : p.valid_slots) valid[s] = 1;
+      for (int s = 0; s < p.nslot(); ++s)
+        if (!valid[s] && (p.slot_v[s] != 0.0 || p.slot_miller[3 * (size_t)s] != 0 ||
+                          p.slot_miller[3 * (size_t)s + 1] != 0 || p.slot_miller[3 * (size_t)s + 2] != 0))
+          bad++;
+      if (nvalid < 0) {
+        nvalid = (long)p.valid_slots.size();
+        ref = got;
+      } else if ((long)p.valid_slots.size() != nvalid || got != ref) {
+        bad++;
+      }
+    }
+    int prev = -1;
+    for (double w : {1.0, 1.0 / 1024, 1.0 / 65536, 1.0 / 1048576}) {
+      set_head_weight(p, w);
+      if (p.npts_head < prev || p.npts_head > (int)p.pts.size()) bad++;
+      prev = p.npts_head;
+    }
+    std::printf("sweep: G %ld head %d dd %zu gpw %d x %d x %d\n", nvalid, prev, p.dd_q.size(), p.gN[0], p.gN[1],
+                p.gN[2]);
+  }
   std::printf("pairs %d classes %d bad %ld\n", n, classes, bad);
   return bad != 0;
 }
