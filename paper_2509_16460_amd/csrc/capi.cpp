@@ -1651,7 +1651,9 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
   }
   // 2b. FP64: the J pass's multiplier apart from rho's (the passes split the work
   // along different axes: rho chunks the pairs, J the G segments), then rho's
-  // around the joint choice; a variation is kept only when it is at least 1 %
+  // around the joint choice, then both passes' multipliers of the classes L >= 3
+  // (their own launches, wave-per-pair bodies of a larger register footprint)
+  // apart from those of L <= 2; a variation is kept only when it is at least 1 %
   // faster than the current choice (two timings each, the shorter kept)
   if (c->prec == PWDF_FP64) {
     const double vars[][2] = {{1.0, 0.5}, {1.0, 2.0}, {0.75, 1.0}, {1.5, 1.0}};
@@ -1660,6 +1662,22 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
       for (int L = 0; L <= kMaxLsum; ++L) {
         t.mrho[L] *= v[0];
         t.mj[L] *= v[1];
+      }
+      double ms = 0.0;
+      if ((s = measure(t, ms)) != PWDF_OK) return s;
+      if (ms < 0.99 * best_t) {
+        cand = t;
+        best_t = ms;
+      }
+    }
+    bool high = false;
+    for (int L = 3; L <= kMaxLsum; ++L) high = high || np_L(c->plan, L) > 0;
+    for (double m : {0.5, 2.0}) {
+      if (!high) break;
+      Tune t = cand;
+      for (int L = 3; L <= kMaxLsum; ++L) {
+        t.mrho[L] *= m;
+        t.mj[L] *= m;
       }
       double ms = 0.0;
       if ((s = measure(t, ms)) != PWDF_OK) return s;
