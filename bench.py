@@ -274,6 +274,9 @@ def main():
                     help="print a per-kernel summary of rocprofv3 CSV output (kernel_trace or "
                          "counter_collection files) instead of benchmarking")
     ap.add_argument("--last", type=int, default=0, help="with --rocprof-summary: the last N dispatches per kernel")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tune cache file of the headline's autotune (a profiling run can reuse the launch shapes "
+                         "an earlier run chose instead of timing candidates under the profiler)")
     args = ap.parse_args()
     if args.rocprof_summary:
         rocprof_summary(args.rocprof_summary, args.last)
@@ -314,7 +317,7 @@ def main():
     log("FP32-MFMA batch: autotune")
     c32 = pwdf.LongRangeJ(prob, precision=pwdf.PWDF_FP32_MFMA, max_ndm=NDM)
     c32.set_jk_layout(pwdf.PWDF_JK_PACKED)
-    c32.autotune(NDM, None)
+    c32.autotune(NDM, args.tune_cache)
     st = c32.stats()
     mu, nu = c32.jk_support()
     Jb = torch.empty((NDM, prob.nk, st["jk_support"]), dtype=Db.dtype, device="cuda")

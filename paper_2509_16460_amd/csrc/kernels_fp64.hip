@@ -1328,20 +1328,41 @@ constexpr int kWavesPerWG = kPairWG / 64;
 // The transform takes the blocks in storage order (neighbouring lanes read
 // neighbouring D(L) blocks); the back transform takes them in the J walk order
 // (blk_cut), in which it reads the moments.
-__global__ __launch_bounds__(kPairWG) void k_transform_all(const Dev dv, const ClassTab tab) {
+//
+// fold (FP32-MFMA form): the densities of the call are folded into the x
+// dimension instead of y, so that the ndmp consecutive operand columns of one
+// (pair, k) -- [pair][k * ndmp + dm] -- are written by neighbouring lanes (thread
+// mode: lane = (block, density), density fastest) or by consecutive workgroups
+// (wave mode: workgroup = (group of four blocks, density), density fastest)
+// rather than by workgroups far apart in the dispatch order, each filling a few
+// bytes of every line.
+template <bool FOLD>
+__global__ __launch_bounds__(kPairWG) void k_transform_all(const Dev dv, const ClassTab tab, int ndm) {
   constexpr bool kThread30 = true;  // (3, 0): a thread per block
   __shared__ double lds[kWavesPerWG * kWaveLds];
   const int i = tab_entry(tab, blockIdx.x);
-  const int local = blockIdx.x - tab.first[i];
+  int local = blockIdx.x - tab.first[i];
   const int cl = tab.cls[i];
-  const int dm = blockIdx.y;
+  int dm = blockIdx.y;
   if (tab.mode[i]) {
+    if (FOLD) {
+      dm = local % ndm;
+      local /= ndm;
+    }
     const int w = threadIdx.x >> 6;
     const int bi = dv.cls_b0[cl] + local * kWavesPerWG + w;
     if (bi >= dv.cls_b1[cl]) return;
     PWDF_CLASS_SWITCH_WAVE(transform_wave, dv, bi, dm, lds + w * kWaveLds)
   } else {
-    const int bi = dv.cls_b0[cl] + local * kPairWG + threadIdx.x;
+    int bi;
+    if (FOLD) {
+      const int dpt = dv.ndmp;  // a power of two <= 16
+      dm = threadIdx.x & (dpt - 1);
+      bi = dv.cls_b0[cl] + local * (kPairWG / dpt) + threadIdx.x / dpt;
+      if (dm >= ndm) return;
+    } else {
+      bi = dv.cls_b0[cl] + local * kPairWG + threadIdx.x;
+    }
     if (bi >= dv.cls_b1[cl]) return;
     PWDF_CLASS_SWITCH_THREAD(transform_thread, dv, bi, dm)
   }
@@ -1523,7 +1544,10 @@ static void add_entry(ClassTab &t, int cls, int mode, int gx, int nblocks) {
 // transform / back: one entry per non-empty class (la, lb); the wave-mode classes
 // first, so that their long per-pair chains start early and overlap the
 // thread-mode blocks instead of forming the launch's tail
-static ClassTab pair_class_tab(const Dev &d, bool back) {
+// fold: the transform of the FP32-MFMA form (densities in x, see k_transform_all):
+// thread-mode entries take kPairWG / ndmp blocks per workgroup, wave-mode entries
+// ndm workgroups per group of four blocks
+static ClassTab pair_class_tab(const Dev &d, bool back, bool fold = false, int ndm = 1) {
   // the back transform's (3, 0) blocks go to k_back_30
   ClassTab t{};
   for (int wave = 1; wave >= 0; --wave)
@@ -1531,15 +1555,23 @@ static ClassTab pair_class_tab(const Dev &d, bool back) {
       for (int lb = 0; lb <= la; ++lb) {
         const int cl = la * 4 + lb, nb = d.cls_b1[cl] - d.cls_b0[cl];
         if (nb <= 0 || (wave_per_block(la, lb) ? 1 : 0) != wave || (back && cl == 12)) continue;
-        add_entry(t, cl, wave, 0, wave ? (nb + kWavesPerWG - 1) / kWavesPerWG : (nb + kPairWG - 1) / kPairWG);
+        const int bpw = fold ? kPairWG / d.ndmp : kPairWG;
+        add_entry(t, cl, wave, 0,
+                  wave ? (nb + kWavesPerWG - 1) / kWavesPerWG * (fold ? ndm : 1) : (nb + bpw - 1) / bpw);
       }
   return t;
 }
 
 hipError_t launch_transform_all(const Dev &d, int ndm, hipStream_t st) {
-  const ClassTab t = pair_class_tab(d, false);
+  const bool fold = d.dh32 != nullptr;
+  if (fold && (d.ndmp < 1 || d.ndmp > 16 || (d.ndmp & (d.ndmp - 1)) != 0 || ndm > d.ndmp))
+    return hipErrorInvalidValue;
+  const ClassTab t = pair_class_tab(d, false, fold, ndm);
   if (t.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_transform_all, dim3((unsigned)t.first[t.n], ndm), dim3(kPairWG), 0, st, d, t);
+  if (fold)
+    hipLaunchKernelGGL(k_transform_all<true>, dim3((unsigned)t.first[t.n], 1), dim3(kPairWG), 0, st, d, t, ndm);
+  else
+    hipLaunchKernelGGL(k_transform_all<false>, dim3((unsigned)t.first[t.n], ndm), dim3(kPairWG), 0, st, d, t, ndm);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }
