@@ -365,16 +365,21 @@ pwdf_status pwdf_grad(pwdf_ctx *ctx, int ndm, const double *Dk, double *dEdR, do
  * each class keep the multiplier (1/4 .. 4) of its shortest launch, and keeps
  * that result only if it also wins overall; the FP64 form tries the J pass's
  * multiplier at 1/2 and 2 and the rho pass's at 3/4 and 3/2 of the chosen one,
- * each kept only if at least 1 % faster.  Last, the independent
- * launches of a pass either overlap on the internal streams or follow each
- * other on the caller's stream, whichever replays faster (pwdf_stats.fork).
+ * each kept only if at least 1 % faster, then the classes L >= 3 apart from
+ * L <= 2 at 1/2 and 2.  Last, the independent launches of a pass either overlap
+ * on the internal streams or follow each other on the caller's stream,
+ * whichever replays faster (pwdf_stats.fork); the FP32-MFMA form first times
+ * its per-class launches one at a time and also tries them overlapping in the
+ * order of those times (longest first, each onto the least-loaded stream).
  * Timing runs on
  * an internal stream over zero D(L) and does not touch caller buffers.  The
  * device workspaces are rebuilt for the chosen shapes (this call allocates),
  * a cached graph is dropped and profiling counters are reset.  Results of later
  * calls agree with the untuned ones to rounding (summation order changes).
- * cache_path: text file of "key seg_len mrho[0..7] mj[0..7] fork" lines (fork
- * may be absent: 1) keyed by
+ * cache_path: text file of "key seg_len mrho[0..7] mj[0..7] fork lpt
+ * cost[4][0..7]" lines (fork may be absent: 1; lpt and the launch times in ms
+ * of the FP32-MFMA form's rho tail, rho head, J tail and J head launches may be
+ * absent: class order) keyed by
  * arch, precision, nG, pair count, nbf, nk and ndm; an entry found there is
  * applied without timing (PWDF_EINVAL if its segment length is not one listed
  * above for the context's form), a new result is appended.  NULL: no

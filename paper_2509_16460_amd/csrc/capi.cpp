@@ -38,8 +38,16 @@ struct Tune {
   double mrho[kMaxLsum + 1];
   double mj[kMaxLsum + 1];
   int fork = 1;
+  // FP32-MFMA form: measured milliseconds of the per-class launches (rho tail,
+  // rho head, J tail, J head) and whether the passes order their launches by
+  // them (see class_schedule)
+  double cost[4][kMaxLsum + 1];
+  int lpt = 0;
   Tune() {
-    for (int L = 0; L <= kMaxLsum; ++L) mrho[L] = mj[L] = 1.0;
+    for (int L = 0; L <= kMaxLsum; ++L) {
+      mrho[L] = mj[L] = 1.0;
+      for (int i = 0; i < 4; ++i) cost[i][L] = 0.0;
+    }
   }
 };
 
@@ -699,6 +707,7 @@ struct Fork {
     for (int i = 0; i < kAux; ++i) (void)hipStreamWaitEvent(c->aux[i], c->ev_fork, 0);
   }
   hipStream_t stream() { return on ? c->aux[next++ % kAux] : st; }
+  hipStream_t stream_at(int i) { return on ? c->aux[i % kAux] : st; }
   hipError_t join() {
     if (!on) return hipSuccess;
     hipError_t e = hipSuccess;
@@ -711,6 +720,41 @@ struct Fork {
 };
 
 int np_L(const Plan &p, int L) { return p.L_p1[L] - p.L_p0[L]; }
+
+// FP32-MFMA form: the per-class launches of one pass (pass 0: rho, 1: J) -- the
+// tail (FP32 MFMA) of every class, then the head (FP64 MFMA) -- with the internal
+// stream each goes to.  Default: that order, round robin over the streams.  With
+// measured launch times (Tune::lpt): longest first, each onto the stream whose
+// launches so far add up to the least time, so that no long launch starts last
+// and runs alone at the end of the pass.
+struct ClassLaunch {
+  int head, L, stream;
+};
+
+std::vector<ClassLaunch> class_schedule(const Plan &p, const Dev &d, const Tune &t, int pass) {
+  std::vector<ClassLaunch> v;
+  std::vector<double> cost;
+  for (int head = 0; head < 2; ++head)
+    for (int L = 0; L <= 2 * kMaxL; ++L) {
+      if (np_L(p, L) <= 0 || (head && d.npts_head <= 0)) continue;
+      v.push_back({head, L, (int)v.size() % kAux});
+      cost.push_back(t.cost[2 * pass + head][L]);
+    }
+  if (!t.lpt) return v;
+  std::vector<int> idx(v.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  double load[kAux] = {};
+  std::vector<ClassLaunch> out;
+  for (int i : idx) {
+    int s = 0;
+    for (int k = 1; k < kAux; ++k)
+      if (load[k] < load[s]) s = k;
+    load[s] += cost[i];
+    out.push_back({v[i].head, v[i].L, s});
+  }
+  return out;
+}
 
 // Algorithmic flops of one pair-G pass over the classes L in [L0, L1]: 8(L+1)+4
 // per (unique pair, G of the half space, density) in the factored form.
@@ -762,22 +806,16 @@ pwdf_status run_mid_rho(pwdf_ctx *c, int ndm, double *EJ, hipStream_t st) {
     return s;
   if (d.fp32) {
     Fork f(c, st);
-    for (int L = 0; L <= 2 * kMaxL; ++L) {
-      if (np_L(p, L) <= 0) continue;
-      std::snprintf(name, sizeof name, "rho_mfma_L%d", L);
-      hipStream_t ss = f.stream();
-      if ((s = step(c, name, (p.pairG_L[L] - p.pairG_head_L[L]) * ndm, ss,
-                    [&] { return launch_rho_mfma_L(d, L, ndm, ss); })) !=
-          PWDF_OK)
-        return s;
-    }
-    for (int L = 0; L <= 2 * kMaxL && d.npts_head > 0; ++L) {
-      if (np_L(p, L) <= 0) continue;
-      std::snprintf(name, sizeof name, "rho_head_L%d", L);
-      hipStream_t ss = f.stream();
-      if ((s = step(c, name, p.pairG_head_L[L] * ndm, ss, [&] { return launch_rho_head_L(d, L, ndm, ss); })) !=
-          PWDF_OK)
-        return s;
+    for (const ClassLaunch &cl : class_schedule(p, d, c->tune, 0)) {
+      const int L = cl.L;
+      hipStream_t ss = f.stream_at(cl.stream);
+      std::snprintf(name, sizeof name, cl.head ? "rho_head_L%d" : "rho_mfma_L%d", L);
+      if (cl.head)
+        s = step(c, name, p.pairG_head_L[L] * ndm, ss, [&] { return launch_rho_head_L(d, L, ndm, ss); });
+      else
+        s = step(c, name, (p.pairG_L[L] - p.pairG_head_L[L]) * ndm, ss,
+                 [&] { return launch_rho_mfma_L(d, L, ndm, ss); });
+      if (s != PWDF_OK) return s;
     }
     if (hipError_t e = f.join()) return hip_fail(c, e, "join");
   } else {
@@ -832,22 +870,16 @@ pwdf_status run_moments(pwdf_ctx *c, int ndm, bool force, hipStream_t st) {
   char name[32];
   Fork f(c, st);
   if (d.fp32 && !force) {
-    for (int L = 0; L <= 2 * kMaxL; ++L) {
-      if (np_L(p, L) <= 0) continue;
-      std::snprintf(name, sizeof name, "jpass_mfma_L%d", L);
-      hipStream_t ss = f.stream();
-      if ((s = step(c, name, (p.pairG_L[L] - p.pairG_head_L[L]) * ndm, ss,
-                    [&] { return launch_jpass_mfma_L(d, L, ndm, ss); })) !=
-          PWDF_OK)
-        return s;
-    }
-    for (int L = 0; L <= 2 * kMaxL && d.npts_head > 0; ++L) {
-      if (np_L(p, L) <= 0) continue;
-      std::snprintf(name, sizeof name, "jpass_head_L%d", L);
-      hipStream_t ss = f.stream();
-      if ((s = step(c, name, p.pairG_head_L[L] * ndm, ss, [&] { return launch_jpass_head_L(d, L, ndm, ss); })) !=
-          PWDF_OK)
-        return s;
+    for (const ClassLaunch &cl : class_schedule(p, d, c->tune, 1)) {
+      const int L = cl.L;
+      hipStream_t ss = f.stream_at(cl.stream);
+      std::snprintf(name, sizeof name, cl.head ? "jpass_head_L%d" : "jpass_mfma_L%d", L);
+      if (cl.head)
+        s = step(c, name, p.pairG_head_L[L] * ndm, ss, [&] { return launch_jpass_head_L(d, L, ndm, ss); });
+      else
+        s = step(c, name, (p.pairG_L[L] - p.pairG_head_L[L]) * ndm, ss,
+                 [&] { return launch_jpass_mfma_L(d, L, ndm, ss); });
+      if (s != PWDF_OK) return s;
     }
   } else {
     for (int g = 0; g < 2; ++g) {
@@ -1393,8 +1425,25 @@ static bool load_tune(const char *path, const std::string &key, Tune &t) {
       q += m;
     }
     if (good) {
-      int f = 1;
-      if (std::sscanf(q, "%d", &f) == 1) u.fork = f != 0;
+      int f = 1, m = 0;
+      if (std::sscanf(q, "%d%n", &f, &m) == 1) {
+        u.fork = f != 0;
+        q += m;
+        // optional: the launch order flag and the measured per-class launch times
+        Tune w = u;
+        int lpt = 0;
+        bool more = std::sscanf(q, "%d%n", &lpt, &m) == 1;
+        if (more) q += m;
+        for (int i = 0; i < 4 && more; ++i)
+          for (int L = 0; L <= kMaxLsum && more; ++L) {
+            more = std::sscanf(q, "%lf%n", &w.cost[i][L], &m) == 1;
+            q += m;
+          }
+        if (more) {
+          w.lpt = lpt != 0;
+          u = w;
+        }
+      }
       t = u;
       found = true;
     }
@@ -1410,7 +1459,10 @@ static void save_tune(const char *path, const std::string &key, const Tune &t) {
   std::fprintf(f, "%s %d", key.c_str(), t.seg_len);
   for (int L = 0; L <= kMaxLsum; ++L) std::fprintf(f, " %.6g", t.mrho[L]);
   for (int L = 0; L <= kMaxLsum; ++L) std::fprintf(f, " %.6g", t.mj[L]);
-  std::fprintf(f, " %d\n", t.fork);
+  std::fprintf(f, " %d %d", t.fork, t.lpt);
+  for (int i = 0; i < 4; ++i)
+    for (int L = 0; L <= kMaxLsum; ++L) std::fprintf(f, " %.6g", t.cost[i][L]);
+  std::fprintf(f, "\n");
   std::fclose(f);
 }
 
@@ -1688,19 +1740,45 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
     }
   }
   // 3. the independent launches of a pass overlapping on the internal streams,
-  // or following each other on one stream: timed back to back
+  // or following each other on one stream: timed back to back.  The FP32-MFMA
+  // form first measures its per-class launch times (one launch at a time) and
+  // also times the overlapping launches ordered by them (class_schedule)
   if ((s = setup_device(c, cand)) != PWDF_OK) return s;
+  if (c->prec == PWDF_FP32_MFMA) {
+    std::vector<std::pair<std::string, double>> per;
+    double tot = 0.0;
+    if ((s = time_tunable(c, ndm, 3, per, tot)) != PWDF_OK) return s;
+    char name[32];
+    const char *fmt[4] = {"rho_mfma_L%d", "rho_head_L%d", "jpass_mfma_L%d", "jpass_head_L%d"};
+    for (int i = 0; i < 4; ++i)
+      for (int L = 0; L <= kMaxLsum; ++L) {
+        std::snprintf(name, sizeof name, fmt[i], L);
+        cand.cost[i][L] = kernel_ms(per, name);
+      }
+    c->tune = cand;
+  }
   {
-    double t_fork = 1e300, t_seq = 1e300;
-    for (int f : {1, 0, 0, 1}) {
-      double ms = 0.0;
-      c->tune.fork = f;
-      if ((s = time_total(c, ndm, 5, ms)) != PWDF_OK) return s;
-      double &best_f = f ? t_fork : t_seq;
-      best_f = std::min(best_f, ms);
-    }
-    cand.fork = t_seq < t_fork ? 0 : 1;
+    // variants (fork, lpt): overlapping in class order, overlapping longest
+    // first (FP32-MFMA form), in order; each timed twice, in both orders
+    std::vector<std::pair<int, int>> vars = {{1, 0}, {0, 0}};
+    if (c->prec == PWDF_FP32_MFMA) vars.push_back({1, 1});
+    std::vector<double> best_v(vars.size(), 1e300);
+    for (int rep = 0; rep < 2; ++rep)
+      for (size_t k = 0; k < vars.size(); ++k) {
+        const size_t i = rep ? vars.size() - 1 - k : k;
+        c->tune.fork = vars[i].first;
+        c->tune.lpt = vars[i].second;
+        double ms = 0.0;
+        if ((s = time_total(c, ndm, 5, ms)) != PWDF_OK) return s;
+        best_v[i] = std::min(best_v[i], ms);
+      }
+    size_t b = 0;
+    for (size_t i = 1; i < vars.size(); ++i)
+      if (best_v[i] < best_v[b]) b = i;
+    cand.fork = vars[b].first;
+    cand.lpt = vars[b].second;
     c->tune.fork = cand.fork;
+    c->tune.lpt = cand.lpt;
   }
   c->prof_on = was_prof;
   save_tune(cache_path, key, cand);

@@ -180,8 +180,9 @@ def test_every_segment_length_matches_oracle(prec, segs, tmp_path):
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32_mfma"])
 def test_fork_setting_from_cache(prec, tmp_path):
     """The launches of a pass overlapping on internal streams (fork 1) or in
-    sequence on the caller's stream (fork 0), set through a tune-cache entry:
-    bit-identical J(k) and E_J, eager and replayed as a graph."""
+    sequence on the caller's stream (fork 0), and for the FP32-MFMA form in the
+    order of given launch times, set through a tune-cache entry: bit-identical
+    J(k) and E_J, eager and replayed as a graph."""
     p = problem()
     D = dev(synth.make_density(p, 650))
     probe = pw().LongRangeJ(p, precision=prec, max_ndm=1)
@@ -191,8 +192,12 @@ def test_fork_setting_from_cache(prec, tmp_path):
     key = cache.read_text().split()[0]
     ones = " ".join(["1"] * 16)
     out = {}
-    for fk in (1, 0):
-        cache.write_text(f"{key} 8 {ones} {fk}\n")
+    # FP32-MFMA form: also the per-class launches ordered by (made-up) launch times,
+    # longest first onto the least-loaded stream ("1 1 <costs>")
+    costs = " ".join(f"{(7 * i) % 11 + 0.5:g}" for i in range(32))
+    variants = [("1", 1), ("0", 0)] + ([(f"1 1 {costs}", 1)] if prec == 1 else [])
+    for tail, fk in variants:
+        cache.write_text(f"{key} 8 {ones} {tail}\n")
         ctx = pw().LongRangeJ(p, precision=prec, max_ndm=1)
         ctx.autotune(1, str(cache))
         assert ctx.stats()["fork"] == fk
@@ -200,8 +205,9 @@ def test_fork_setting_from_cache(prec, tmp_path):
         Jg, Eg = ctx.build_j(D, graph=True)
         torch.cuda.synchronize()
         assert torch.equal(Je, Jg) and torch.equal(Ee, Eg)
-        out[fk] = (Je, Ee)
-    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+        out[tail] = (Je, Ee)
+    for tail, _ in variants[1:]:
+        assert torch.equal(out[tail][0], out["1"][0]) and torch.equal(out[tail][1], out["1"][1])
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32_mfma"])
