@@ -543,6 +543,23 @@ pwdf_status setup_device_impl(pwdf_ctx *c, const Tune &tn) {
     UP(p.slot_miller, slot_miller)
   }
   if (d.fp32) {
+    // n^k of every point: the products the epilogues formed on the device
+    // (repeated multiplications, u then v then w; integers, exact while
+    // |n|^(2 kMaxL) < 2^53)
+    {
+      constexpr Monos<2 * kMaxL> MT{};
+      std::vector<double> pm(std::max<size_t>(1, p.pts.size() * (size_t)kMonoStride), 0.0);
+      auto pw = [](double x, int e) {
+        double r = 1.0;
+        for (int i = 0; i < e; ++i) r *= x;
+        return r;
+      };
+      for (size_t i = 0; i < p.pts.size(); ++i)
+        for (int k = 0; k < kMonoStride; ++k)
+          pm[i * kMonoStride + k] =
+              pw(p.pts[i].nu, MT.u[k]) * pw(p.pts[i].nv, MT.v[k]) * pw(p.pts[i].nw, MT.w[k]);
+      UP(pm, ptmono)
+    }
     UP(wl.slot_pidx, slot_pidx)
     UP(wl.rho_items, rho_items)
     UP(wl.j_items, j_items)

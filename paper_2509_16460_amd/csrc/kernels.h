@@ -95,6 +95,9 @@ struct Dev {
   int rho_item0[kMaxLsum + 1], rho_nitems[kMaxLsum + 1];
   int j_item0[kMaxLsum + 1], j_nitems[kMaxLsum + 1];
   const int *rows_of_block;
+  // FP32-MFMA form: the relative monomials n_u^a n_v^b n_w^c of every point of
+  // pts, [point][kMonoStride] in the order of Monos
+  const double *ptmono;
   const int *jn_of;
   double2 *parth;
   int nrows_h, rows_per_group_h;
@@ -171,6 +174,9 @@ hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
 // MFMA-tile kernels: N-tiles (16 columns of (k, dm)) per S evaluation; ntiles
 // are split into ceil(ntiles / 8) groups of equal size (at most 8 tiles each),
 // the last group's missing tiles being zero columns
+// monomials per point in Dev::ptmono (every degree up to 2 kMaxL)
+constexpr int kMonoStride = nherm(2 * kMaxL);
+
 inline int group_tiles(int ntiles) {
   const int ng = (ntiles + 7) / 8;
   return (ntiles + ng - 1) / ng;

@@ -76,7 +76,8 @@ template <int L, int NTG>
 __global__ __launch_bounds__(256) void k_rho_mfma(const int4 *__restrict__ items, const GPoint *__restrict__ pts,
                                                   int npts, const PairHot *__restrict__ hot, int Lp0,
                                                   const float *__restrict__ dh32, int64_t d32_off, int ncols,
-                                                  int ndmp, int ndm, double2 *__restrict__ part, int nrows) {
+                                                  int ndmp, int ndm, double2 *__restrict__ part, int nrows,
+                                                  const double *__restrict__ pmono) {
   constexpr int NT = nherm(L);
   __shared__ PairF sh[kQTile];
   __shared__ float sc[kQTile * NTG * 16];
@@ -150,22 +151,19 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const int4 *__restrict__ items
     double accr[4], acci[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) accr[i] = acci[i] = 0.0;
-    GPoint pr[4];
+    const double *pm[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) pr[i] = pts[min(pt0 + 4 * g4 + i, npts - 1)];
+    for (int i = 0; i < 4; ++i) pm[i] = pmono + (size_t)min(pt0 + 4 * g4 + i, npts - 1) * kMonoStride;
 #pragma unroll
     for (int n = 0; n < NTG; ++n) {
       if (n >= ntg) break;
       const int c = (ng + n) * 16 + r16;
       const int k = c / ndmp;
       const bool vk = k < NT;
-      int ka = 0, kb = 0, kc = 0;
-      if (vk) mono_of(k, ka, kb, kc);
-      const bool odd = (ka + kb + kc) & 1;
+      const bool odd = vk && (mono_degree(k) & 1);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const double mono =
-            vk ? ipow((double)pr[i].nu, ka) * ipow((double)pr[i].nv, kb) * ipow((double)pr[i].nw, kc) : 0.0;
+        const double mono = vk ? pm[i][k] : 0.0;
         // d_k carries sigma_|k| already (real part from even |k|, imaginary from odd):
         // the column contributes R for even |k| and i R for odd |k|
         double cr = (double)are[n][i], ci = (double)aim[n][i];
@@ -209,7 +207,8 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const int4 *__restrict__ items
 template <int LMAX>
 __global__ __launch_bounds__(256) void k_wprep(const double2 *__restrict__ Vc, int nslot,
                                                const GPoint *__restrict__ pts, int ncolsW, int ndmp, int ndm,
-                                               float *__restrict__ wre, float *__restrict__ wim) {
+                                               float *__restrict__ wre, float *__restrict__ wim,
+                                               const double *__restrict__ pmono) {
   constexpr int NT = nherm(LMAX);
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   const int pi = blockIdx.y;
@@ -218,12 +217,10 @@ __global__ __launch_bounds__(256) void k_wprep(const double2 *__restrict__ Vc, i
   float xr = 0.f, xi = 0.f;
   if (k < NT && dm < ndm) {
     const GPoint pt = pts[pi];
-    int a, b, c;
-    mono_of(k, a, b, c);
-    const double mono = ipow((double)pt.nu, a) * ipow((double)pt.nv, b) * ipow((double)pt.nw, c);
+    const double mono = pmono[(size_t)pi * kMonoStride + k];
     const double2 v = Vc[(size_t)dm * nslot + pt.slot];
     double r = mono * v.x, i = mono * v.y;
-    if ((a + b + c) & 1) {  // -i (r + i i) = i - i r
+    if (mono_degree(k) & 1) {  // -i (r + i i) = i - i r
       const double tr = i;
       i = -r;
       r = tr;
@@ -341,7 +338,8 @@ static hipError_t rho_mfma_ntg(const Dev &d, int ndm, hipStream_t st) {
   const int ntail = d.npts - d.npts_head;
   hipLaunchKernelGGL((k_rho_mfma<L, NTG>), dim3((unsigned)d.rho_nitems[L]), dim3(256), 0, st,
                      d.rho_items + d.rho_item0[L], d.pts + d.npts_head, ntail, d.hot_cut, d.L_p0[L], d.dh32,
-                     d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.part, d.nrows);
+                     d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.part, d.nrows,
+                     d.ptmono + (size_t)d.npts_head * kMonoStride);
   PWDF_CHECK_LAUNCH32();
   return hipSuccess;
 }
@@ -380,7 +378,7 @@ hipError_t launch_wprep(const Dev &d, int ndm, hipStream_t st) {
   if (ntail <= 0) return hipSuccess;
   dim3 grid((unsigned)((d.ncolsW + 255) / 256), ntail);
   hipLaunchKernelGGL((k_wprep<2 * kMaxL>), grid, dim3(256), 0, st, d.Vc, d.nslot, d.pts + d.npts_head, d.ncolsW,
-                     d.ndmp, ndm, d.wre, d.wim);
+                     d.ndmp, ndm, d.wre, d.wim, d.ptmono + (size_t)d.npts_head * kMonoStride);
   PWDF_CHECK_LAUNCH32();
   return hipSuccess;
 }

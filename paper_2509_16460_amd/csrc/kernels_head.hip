@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void k_rho_head(const GPoint *__restrict__ pts
                                                   const PairHot *__restrict__ hot, int Lp0, int Lp1, int ppc,
                                                   const double *__restrict__ dh64, int64_t d_off, int ncols,
                                                   int ndmp, int ndm, double2 *__restrict__ parth, int row0,
-                                                  int nrows_h) {
+                                                  int nrows_h, const double *__restrict__ pmono) {
   constexpr int NT = nherm(L);
   constexpr int PER = kQTileH * NTG * 16 / 256;  // staged columns per thread and tile
   static_assert(PER * 256 == kQTileH * NTG * 16, "tile size");
@@ -121,22 +121,19 @@ __global__ __launch_bounds__(256) void k_rho_head(const GPoint *__restrict__ pts
   double accr[4], acci[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) accr[i] = acci[i] = 0.0;
-  GPoint pr[4];
+  const double *pm[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) pr[i] = pts[min(pt0 + 4 * i + g4, npts - 1)];
+  for (int i = 0; i < 4; ++i) pm[i] = pmono + (size_t)min(pt0 + 4 * i + g4, npts - 1) * kMonoStride;
 #pragma unroll
   for (int n = 0; n < NTG; ++n) {
     if (n >= ntg) break;
     const int c = (ng + n) * 16 + r16;
     const int k = c / ndmp;
     const bool vk = k < NT;
-    int ka = 0, kb = 0, kc = 0;
-    if (vk) mono_of(k, ka, kb, kc);
-    const bool odd = (ka + kb + kc) & 1;
+    const bool odd = vk && (mono_degree(k) & 1);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const double mono =
-          vk ? ipow((double)pr[i].nu, ka) * ipow((double)pr[i].nv, kb) * ipow((double)pr[i].nw, kc) : 0.0;
+      const double mono = vk ? pm[i][k] : 0.0;
       // even |k|: R; odd |k|: i R (the sign of (-i)^|k| is in the coefficients)
       double cr = are[n][i], ci = aim[n][i];
       if (odd) {
@@ -181,7 +178,7 @@ __global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ p
                                                     const double2 *__restrict__ Vc, int nslot, int ntiles,
                                                     int ndmp, int ndm, const PairHot *__restrict__ hot, int Lp0,
                                                     int Lp1, double *__restrict__ yhat, int64_t yhat_size,
-                                                    int64_t ycls_off) {
+                                                    int64_t ycls_off, const double *__restrict__ pmono) {
   constexpr int NT = nherm(L);
   constexpr int kPTile = jh_ptile<NTW>();
   __shared__ GPoint sp[kPTile];
@@ -226,13 +223,10 @@ __global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ p
       const int k = col / ndmp;
       double r = 0.0, im = 0.0;
       if (q < nt && k < NT) {
-        const GPoint pt = sp[q];
-        int a, b, cc;
-        mono_of(k, a, b, cc);
-        const double mono = ipow((double)pt.nu, a) * ipow((double)pt.nv, b) * ipow((double)pt.nw, cc);
+        const double mono = pmono[(size_t)(t0 + q) * kMonoStride + k];
         r = mono * v[u].x;
         im = mono * v[u].y;
-        if ((a + b + cc) & 1) {  // -i (r + i im) = im - i r
+        if (mono_degree(k) & 1) {  // -i (r + i im) = im - i r
           const double tr = im;
           im = -r;
           r = tr;
@@ -286,7 +280,7 @@ static hipError_t rho_head_ntg(const Dev &d, int ndm, hipStream_t st) {
   dim3 grid((unsigned)((d.npts_head + 63) / 64), d.rho_h_chunks[L], (unsigned)tile_groups(d.ncols32[L] / 16));
   hipLaunchKernelGGL((k_rho_head<L, NTG>), grid, dim3(256), 0, st, d.pts, d.npts_head, d.hot_cut, d.L_p0[L], d.L_p1[L],
                      d.rho_h_ppc[L], d.dhat, d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.parth, d.rho_h_row0[L],
-                     d.nrows_h);
+                     d.nrows_h, d.ptmono);
   PWDF_CHECK_LAUNCH_H();
   return hipSuccess;
 }
@@ -329,7 +323,7 @@ static hipError_t j_head_ntw(const Dev &d, int ndm, hipStream_t st) {
   const int64_t off = d.yhat_off[L];
   dim3 grid((unsigned)((np + 63) / 64), (unsigned)d.jh_chunks[L], (unsigned)((ntiles + NTW - 1) / NTW));
   hipLaunchKernelGGL((k_jpass_head<L, NTW>), grid, dim3(256), 0, st, d.pts, d.npts_head, d.jh_ppc[L], d.Vc, d.nslot,
-                     ntiles, d.ndmp, ndm, d.hot_cut, d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size, off);
+                     ntiles, d.ndmp, ndm, d.hot_cut, d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size, off, d.ptmono);
   PWDF_CHECK_LAUNCH_H();
   return hipSuccess;
 }

@@ -32,6 +32,13 @@ __device__ __forceinline__ void mono_of(int k, int &a, int &b, int &c) {
   c = d - a - b;
 }
 
+// Degree a + b + c of the k-th relative monomial.
+__device__ __forceinline__ int mono_degree(int k) {
+  int d = 0;
+  while (deg_off(d + 1) <= k) ++d;
+  return d;
+}
+
 // Pair data of the direct evaluation: log2(e)/4p, the fractional coordinates
 // of P in the (u, v, w) axis order, and the squared cut radius (a pair sees the
 // G with |G|^2 <= gc2; 1e300 without per-pair cuts).
