@@ -619,6 +619,10 @@ pwdf_status setup_device_impl(pwdf_ctx *c, const Tune &tn) {
     AL(dh32, (size_t)std::max<int64_t>(1, d.d32_size))
     AL(wre, (size_t)d.nslot * d.ncolsW)
     AL(wim, (size_t)d.nslot * d.ncolsW)
+    if (d.npts_head > 0) {
+      AL(wre64, (size_t)d.npts_head * d.ncolsW)
+      AL(wim64, (size_t)d.npts_head * d.ncolsW)
+    }
     if ((e = hipMemset(d.dh32, 0, sizeof(float) * std::max<int64_t>(1, d.d32_size))) != hipSuccess)
       return hip_fail(c, e, "clearing operand buffer");
   }
@@ -1277,6 +1281,10 @@ static size_t carve_build_ws(Dev &d, const Plan &p, int ndm, unsigned char *base
     take(d.dh32, (size_t)std::max<int64_t>(1, d.d32_size));
     take(d.wre, (size_t)d.nslot * d.ncolsW);
     take(d.wim, (size_t)d.nslot * d.ncolsW);
+    if (d.npts_head > 0) {
+      take(d.wre64, (size_t)d.npts_head * d.ncolsW);
+      take(d.wim64, (size_t)d.npts_head * d.ncolsW);
+    }
   }
   return off;
 }

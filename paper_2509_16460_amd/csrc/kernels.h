@@ -74,6 +74,7 @@ struct Dev {
   int64_t d32_size;  // floats of all classes
   int ncols32[kMaxLsum + 1];
   float *wre, *wim;
+  double *wre64, *wim64;  // W' of the head points in FP64, [head point][k * ndmp + dm]
   int ncolsW;
   // The FP32-MFMA form splits the G set into its head, pts[0, npts_head) (FP64
   // tiles on FP64 MFMA), and the tail (FP32 tiles), both in order of |G|^2, and

@@ -202,19 +202,20 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const int4 *__restrict__ items
 // ---------------------------------------------------------------------------
 // W'[point][k * ndmp + dm] = n^k conj V(slot of the point, dm) (times -i for odd
 // |k|), so that Re(S W') is the parity-selected moment term of the J pass.
-// Columns past NT * ndm carry zeros.
+// Columns past NT * ndm carry zeros.  T = float for the tail's points (FP32
+// MFMA operands), double for the head's (FP64 MFMA, kernels_head.hip).
 // ---------------------------------------------------------------------------
-template <int LMAX>
+template <int LMAX, typename T>
 __global__ __launch_bounds__(256) void k_wprep(const double2 *__restrict__ Vc, int nslot,
                                                const GPoint *__restrict__ pts, int ncolsW, int ndmp, int ndm,
-                                               float *__restrict__ wre, float *__restrict__ wim,
+                                               T *__restrict__ wre, T *__restrict__ wim,
                                                const double *__restrict__ pmono) {
   constexpr int NT = nherm(LMAX);
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   const int pi = blockIdx.y;
   if (col >= ncolsW) return;
   const int k = col / ndmp, dm = col - k * ndmp;
-  float xr = 0.f, xi = 0.f;
+  T xr = 0, xi = 0;
   if (k < NT && dm < ndm) {
     const GPoint pt = pts[pi];
     const double mono = pmono[(size_t)pi * kMonoStride + k];
@@ -225,8 +226,8 @@ __global__ __launch_bounds__(256) void k_wprep(const double2 *__restrict__ Vc, i
       i = -r;
       r = tr;
     }
-    xr = (float)r;
-    xi = (float)i;
+    xr = (T)r;
+    xi = (T)i;
   }
   wre[(size_t)pi * ncolsW + col] = xr;
   wim[(size_t)pi * ncolsW + col] = xi;
@@ -375,11 +376,18 @@ hipError_t launch_rho_mfma_L(const Dev &d, int L, int ndm, hipStream_t st) {
 
 hipError_t launch_wprep(const Dev &d, int ndm, hipStream_t st) {
   const int ntail = d.npts - d.npts_head;
-  if (ntail <= 0) return hipSuccess;
-  dim3 grid((unsigned)((d.ncolsW + 255) / 256), ntail);
-  hipLaunchKernelGGL((k_wprep<2 * kMaxL>), grid, dim3(256), 0, st, d.Vc, d.nslot, d.pts + d.npts_head, d.ncolsW,
-                     d.ndmp, ndm, d.wre, d.wim, d.ptmono + (size_t)d.npts_head * kMonoStride);
-  PWDF_CHECK_LAUNCH32();
+  if (ntail > 0) {
+    dim3 grid((unsigned)((d.ncolsW + 255) / 256), ntail);
+    hipLaunchKernelGGL((k_wprep<2 * kMaxL, float>), grid, dim3(256), 0, st, d.Vc, d.nslot, d.pts + d.npts_head,
+                       d.ncolsW, d.ndmp, ndm, d.wre, d.wim, d.ptmono + (size_t)d.npts_head * kMonoStride);
+    PWDF_CHECK_LAUNCH32();
+  }
+  if (d.npts_head > 0) {
+    dim3 grid((unsigned)((d.ncolsW + 255) / 256), d.npts_head);
+    hipLaunchKernelGGL((k_wprep<2 * kMaxL, double>), grid, dim3(256), 0, st, d.Vc, d.nslot, d.pts, d.ncolsW, d.ndmp,
+                       ndm, d.wre64, d.wim64, d.ptmono);
+    PWDF_CHECK_LAUNCH32();
+  }
   return hipSuccess;
 }
 

@@ -163,9 +163,10 @@ __global__ __launch_bounds__(256) void k_rho_head(const GPoint *__restrict__ pts
 
 // ---------------------------------------------------------------------------
 // J moments over the head points, K = G.  A workgroup = 4 waves = 64 pairs (16 per
-// wave as the MFMA rows); the head points are staged in LDS tile by tile with
-// W' formed from conj V in FP64; grid y splits the head points into chunks.
-// Output: yhat chunk blockIdx.y of the class, (k, pair).
+// wave as the MFMA rows); the head points and their W' columns (formed once per
+// build in FP64 by k_wprep) are staged in LDS tile by tile, the next tile's
+// loads issued before the barrier that ends the current one; grid y splits the
+// head points into chunks.  Output: yhat chunk blockIdx.y of the class, (k, pair).
 // ---------------------------------------------------------------------------
 // head points per LDS tile (the W' tile is 2 x kPTile x 16 NTW doubles, <= 32 KB)
 template <int NTW>
@@ -175,10 +176,11 @@ constexpr int jh_ptile() {
 
 template <int L, int NTW>
 __global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ pts, int npts, int ppc,
-                                                    const double2 *__restrict__ Vc, int nslot, int ntiles,
-                                                    int ndmp, int ndm, const PairHot *__restrict__ hot, int Lp0,
-                                                    int Lp1, double *__restrict__ yhat, int64_t yhat_size,
-                                                    int64_t ycls_off, const double *__restrict__ pmono) {
+                                                    const double *__restrict__ wre, const double *__restrict__ wim,
+                                                    int ncolsW, int ntiles, int ndmp,
+                                                    const PairHot *__restrict__ hot, int Lp0, int Lp1,
+                                                    double *__restrict__ yhat, int64_t yhat_size, int64_t ycls_off,
+                                                    int ndm) {
   constexpr int NT = nherm(L);
   constexpr int kPTile = jh_ptile<NTW>();
   __shared__ GPoint sp[kPTile];
@@ -201,39 +203,36 @@ __global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ p
   const int pend = min(npts, (int)(blockIdx.y + 1) * ppc);
   for (int t0 = blockIdx.y * ppc; t0 < pend; t0 += kPTile) {
     const int nt = min(kPTile, pend - t0);
-    __syncthreads();
-    if (tid < nt) sp[tid] = pts[t0 + tid];
-    __syncthreads();
-    // V loads of the thread's elements issued together, then W' formed
-    double2 v[PER];
+    // the tile's point records and W' elements (columns of k >= NT, densities
+    // past ndm and points past the tile read as zeros), loaded before the barrier
+    const GPoint *pp = pts + t0 + min(tid, nt - 1);
+    const double pg2 = pp->g2;
+    const int pnu = pp->nu, pnv = pp->nv, pnw = pp->nw, pslot = pp->slot;
+    double2 x[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int i = tid + u * 256;
       const int q = i / (NTW * 16), c = i - q * (NTW * 16);
       const int col = (nt0 * 16) + c;
-      const int k = col / ndmp, dm = col - k * ndmp;
-      v[u] = q < nt && c < ntw * 16 && k < NT && dm < ndm ? Vc[(size_t)dm * nslot + sp[q].slot]
-                                                           : make_double2(0.0, 0.0);
+      const bool ok = q < nt && c < ntw * 16 && col / ndmp < NT;
+      const size_t o = ok ? (size_t)(t0 + q) * ncolsW + col : 0;
+      x[u] = make_double2(wre[o], wim[o]);
+      if (!ok) x[u] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();  // the previous tile's MFMA reads are done
+    if (tid < nt) {
+      sp[tid].g2 = pg2;
+      sp[tid].nu = pnu;
+      sp[tid].nv = pnv;
+      sp[tid].nw = pnw;
+      sp[tid].slot = pslot;
     }
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int i = tid + u * 256;
       const int q = i / (NTW * 16), c = i - q * (NTW * 16);
-      const int col = (nt0 * 16) + c;
-      const int k = col / ndmp;
-      double r = 0.0, im = 0.0;
-      if (q < nt && k < NT) {
-        const double mono = pmono[(size_t)(t0 + q) * kMonoStride + k];
-        r = mono * v[u].x;
-        im = mono * v[u].y;
-        if (mono_degree(k) & 1) {  // -i (r + i im) = im - i r
-          const double tr = im;
-          im = -r;
-          r = tr;
-        }
-      }
-      sw[0][q][c] = r;
-      sw[1][q][c] = im;
+      sw[0][q][c] = x[u].x;
+      sw[1][q][c] = x[u].y;
     }
     __syncthreads();
     for (int q0 = 0; q0 < nt; q0 += 4) {
@@ -322,8 +321,9 @@ static hipError_t j_head_ntw(const Dev &d, int ndm, hipStream_t st) {
   // the head's moments are chunks [0, jh_chunks[L]) of the class
   const int64_t off = d.yhat_off[L];
   dim3 grid((unsigned)((np + 63) / 64), (unsigned)d.jh_chunks[L], (unsigned)((ntiles + NTW - 1) / NTW));
-  hipLaunchKernelGGL((k_jpass_head<L, NTW>), grid, dim3(256), 0, st, d.pts, d.npts_head, d.jh_ppc[L], d.Vc, d.nslot,
-                     ntiles, d.ndmp, ndm, d.hot_cut, d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size, off, d.ptmono);
+  hipLaunchKernelGGL((k_jpass_head<L, NTW>), grid, dim3(256), 0, st, d.pts, d.npts_head, d.jh_ppc[L], d.wre64,
+                     d.wim64, d.ncolsW, ntiles, d.ndmp, d.hot_cut, d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size, off,
+                     ndm);
   PWDF_CHECK_LAUNCH_H();
   return hipSuccess;
 }
