@@ -257,6 +257,71 @@ def rocprof_summary(paths, last):
         print(f"| `{k}` | " + " | ".join(f"{rows[k][c]:.4g}" if c in rows[k] else "" for c in cols) + " |")
 
 
+def profile_name(kernel):
+    """The bench's profile name (pwdf_profile_*) of a device kernel, or None."""
+    import re
+    m = re.search(r"pwdf::(k_\w+)(?:<(\d+)[^>]*>)?", kernel)
+    if not m:
+        return None
+    k, L = m.group(1), m.group(2)
+    fixed = {"k_phase_j_all": "phase_j", "k_phase_d": "phase_d", "k_back_all": "back", "k_back_30": "back",
+             "k_transform_all": "transform", "k_reduce_rows": "reduce", "k_reduce": "reduce", "k_fold_j": "fold_j",
+             "k_wprep": "wprep"}
+    if k in fixed:
+        return fixed[k]
+    per_class = {"k_rho_mfma": "rho_mfma_L", "k_rho_head": "rho_head_L", "k_jpass_mfma": "jpass_mfma_L",
+                 "k_jpass_head": "jpass_head_L"}
+    return per_class[k] + L if k in per_class and L is not None else None
+
+
+def traffic_json(fetch_csv, write_csv, last):
+    """profiles/traffic_counters.json from two rocprofv3 counter runs of the
+    headline leg (FETCH_SIZE, then WRITE_SIZE, both with --calib-copy-mib): each
+    counter scaled by what it reads for the calibration kernel (torch's neg over
+    the given size, reading and writing it once), HBM bytes per launch of each
+    profile kernel = the sum over its device kernels of their average over the
+    last `last` dispatches."""
+    import csv
+    per = {}
+    calib = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        disp = {}
+        neg = 0.0
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") != counter:
+                    continue
+                name, v = r["Kernel_Name"], float(r["Counter_Value"])
+                if "neg_kernel" in name:
+                    neg = max(neg, v)
+                disp.setdefault(name, {})[int(r["Dispatch_Id"])] = v
+        calib[counter] = neg
+        for name, dd in disp.items():
+            pn = profile_name(name)
+            if pn is None:
+                continue
+            ids = sorted(dd)[-last:]
+            per.setdefault(pn, {}).setdefault(counter, 0.0)
+            per[pn][counter] += sum(dd[i] for i in ids) / len(ids)
+    if not calib.get("FETCH_SIZE") or not calib.get("WRITE_SIZE"):
+        raise SystemExit("no calibration kernel found (run the counter passes with --calib-copy-mib)")
+    # the calibration kernel moves the size once each way; KiB per dispatch
+    size_kib = max(calib["WRITE_SIZE"], calib["FETCH_SIZE"])
+    f_fetch, f_write = size_kib / calib["FETCH_SIZE"], size_kib / calib["WRITE_SIZE"]
+    out = {"source_hash": kernel_source_hash(), "workloads": {WORKLOAD: {}},
+           "calibration": {"fetch_factor": f_fetch, "write_factor": f_write, "calib_kib": size_kib},
+           "note": "HBM bytes per launch = (FETCH_SIZE x fetch_factor + WRITE_SIZE x write_factor) KiB x 1024, "
+                   f"average of the last {last} dispatches of each device kernel, summed per profile kernel"}
+    for pn, c in sorted(per.items()):
+        out["workloads"][WORKLOAD][pn] = {
+            "fetch_kib_raw": c.get("FETCH_SIZE", 0.0), "write_kib_raw": c.get("WRITE_SIZE", 0.0),
+            "hbm_bytes_per_launch": 1024.0 * (c.get("FETCH_SIZE", 0.0) * f_fetch + c.get("WRITE_SIZE", 0.0) * f_write)}
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(f"wrote {path}: fetch x{f_fetch:.4f}, write x{f_write:.4f}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,7 +342,12 @@ def main():
     ap.add_argument("--tune-cache", default=None,
                     help="tune cache file of the headline's autotune (a profiling run can reuse the launch shapes "
                          "an earlier run chose instead of timing candidates under the profiler)")
+    ap.add_argument("--traffic-json", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_counters.json from the two counter runs (with --last N)")
     args = ap.parse_args()
+    if args.traffic_json:
+        traffic_json(args.traffic_json[0], args.traffic_json[1], args.last or 3)
+        return
     if args.rocprof_summary:
         rocprof_summary(args.rocprof_summary, args.last)
         return
