@@ -128,12 +128,21 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const int4 *__restrict__ items
       // branch-free: a lane past the tile's pairs evaluates a valid pair and
       // contributes zero; the columns past the group's tiles are zeros in LDS, so
       // every group runs NTG tiles (a run-time tile count would make the compiler
-      // move the accumulators out of the MFMA registers around every MFMA)
-      for (int q0 = 0; q0 < nq; q0 += 4) {
-        // pairs in cut order: the first of four has the largest cut
-        if (sh[q0].gc2 < rmin) break;
+      // move the accumulators out of the MFMA registers around every MFMA).  The
+      // wave stops at the first group of four pairs (cut order: the first has the
+      // largest cut) whose cut lies below its shortest G; that count is found
+      // first, so that the MFMA loop has one exit and a wave-uniform trip count
+      // (an exit inside it has the same effect on the accumulators).
+      int qend = nq;
+      for (int q0 = 0; q0 < nq; q0 += 4)
+        if (sh[q0].gc2 < rmin) {
+          qend = q0;
+          break;
+        }
+      qend = __builtin_amdgcn_readfirstlane(qend);
+      for (int q0 = 0; q0 < qend; q0 += 4) {
         const int q = q0 + g4 < nq ? q0 + g4 : nq - 1;
-        const bool vq = q0 + g4 < nq && ptA.g2 <= sh[q].gc2;
+        const bool vq = (q0 + g4 < nq) & (ptA.g2 <= sh[q].gc2);  // no branch: q is in range
         float Sr, Si;
         s_direct(ptA, sh[q], Sr, Si);
         Sr = vq ? Sr : 0.f;
@@ -292,12 +301,19 @@ __global__ __launch_bounds__(256) void k_jpass_mfma(const int4 *__restrict__ ite
       sw[1][q][c] = ok ? wim[g] : 0.f;
     }
     __syncthreads();
-    // branch-free as in the rho pass: columns past the group's tiles are zeros
-    for (int q0 = 0; q0 < nt; q0 += 4) {
-      // points in order of |G|^2: the first of four is the shortest
-      if (sp[q0].g2 > cmax) break;
+    // branch-free as in the rho pass: columns past the group's tiles are zeros;
+    // the wave stops at the first group of four points (in order of |G|^2: the
+    // first is the shortest) beyond its largest cut, counted first (see rho)
+    int qend = nt;
+    for (int q0 = 0; q0 < nt; q0 += 4)
+      if (sp[q0].g2 > cmax) {
+        qend = q0;
+        break;
+      }
+    qend = __builtin_amdgcn_readfirstlane(qend);
+    for (int q0 = 0; q0 < qend; q0 += 4) {
       const int q = q0 + g4 < nt ? q0 + g4 : nt - 1;
-      const bool vq = q0 + g4 < nt && sp[q].g2 <= f.gc2;
+      const bool vq = (q0 + g4 < nt) & (sp[q].g2 <= f.gc2);
       float Sr, Si;
       s_direct(sp[q], f, Sr, Si);
       Sr = vq ? Sr : 0.f;

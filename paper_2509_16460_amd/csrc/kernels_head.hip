@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_rho_head(const GPoint *__restrict__ pts
     __syncthreads();
     for (int q0 = 0; q0 < nq; q0 += 4) {
       const int q = q0 + g4 < nq ? q0 + g4 : nq - 1;
-      const bool vq = q0 + g4 < nq && ptA.g2 <= sh[q].gc2;
+      const bool vq = (q0 + g4 < nq) & (ptA.g2 <= sh[q].gc2);  // no branch: q is in range
       double Sr, Si;
       s_direct64(ptA, sh[q], Sr, Si);
       Sr = vq ? Sr : 0.0;
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ p
     __syncthreads();
     for (int q0 = 0; q0 < nt; q0 += 4) {
       const int q = q0 + g4 < nt ? q0 + g4 : nt - 1;
-      const bool vq = q0 + g4 < nt && sp[q].g2 <= f.gc2;
+      const bool vq = (q0 + g4 < nt) & (sp[q].g2 <= f.gc2);
       double Sr, Si;
       s_direct64(sp[q], f, Sr, Si);
       Sr = vq ? Sr : 0.0;
