@@ -5,18 +5,20 @@
 // magnitude over the first shells of G vectors, so the terms of largest size in
 // both contractions sit on the few shortest G.  There the rounding of FP32
 // operands and FP32 accumulation would set the error of E_J and J; the head --
-// the G whose weight is at least 2^-7 of the largest -- is therefore contracted
-// in FP64 here, with the same tile structure as the FP32 kernels:
+// the G whose weight is at least a set fraction of the largest (2^-20 by
+// default) -- is therefore contracted in FP64 here, with the same tile structure
+// as the FP32 kernels:
 //
 //   rho:  R[G][(k,dm)] = sum_pair S(G, pair) dhat_k(pair, dm)   (K = pairs)
 //   J:    yhat[pair][(k,dm)] = sum_G Re( S(G, pair) W'(G, (k,dm)) )   (K = G)
 //
 // S(G, pair) = e^{-|G|^2/4p} e^{-2 pi i n.f_P} is evaluated directly in FP64 per
-// (G, pair) (exp2 and sincospi of the device math library); the coefficients
-// come from the FP64 transform output and W' = n^k conj V(G) (times -i for
-// odd |k|) is formed in FP64 while the tile is staged.  The head rho rows go to
-// their own partial rows (one per chunk of pairs and N-tile group), the J
-// moments to chunk 0 of yhat; the reduction and the back transform add them.
+// (G, pair) (the table-driven exponential and phase factor of the FP64 passes,
+// tables in LDS); the coefficients come from the FP64 transform output and
+// W' = n^k conj V(G) (times -i for odd |k|) is formed once per build in FP64
+// (k_wprep).  The head rho rows go to their own partial rows (one per chunk of
+// pairs and N-tile group), the J moments to the first jh_chunks chunks of yhat;
+// the reduction and the back transform add them.
 //
 // Lane layout of the 16x16x4 f64 MFMA (lane l = 0..63): A[l%16][l/16],
 // B[l/16][l%16], D[4*i + l/16][l%16], i = 0..3 (the rows of D interleave across
@@ -35,15 +37,36 @@ __device__ __forceinline__ d4 mfma4d(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// S = e^{-|G|^2/4p} e^{-2 pi i n.f} in FP64
-__device__ __forceinline__ void s_direct64(const GPoint &pt, const PairF &f, double &sr, double &si) {
-  const double e = exp2(-pt.g2 * f.il2);
+// Pair data of the FP64 evaluation: 1/4p, the fractional coordinates of P in
+// the (u, v, w) axis order, the squared cut radius.
+struct PairD {
+  double inv4p, fu, fv, fw, gc2;
+};
+
+__device__ __forceinline__ PairD pair_d(const PairHot &h) { return {h.inv4p, h.fu, h.fv, h.fw, h.gc2}; }
+
+// the segment-start tables (2^(j/32); e^{2 pi i j/64}) copied into LDS
+__device__ __forceinline__ void head_tables(const double *__restrict__ g, double *e2, double *cis) {
+  for (int i = threadIdx.x; i < kStartTab; i += blockDim.x) {
+    if (i < 32)
+      e2[i] = g[i];
+    else
+      cis[i - 32] = g[i];
+  }
+}
+
+// S = e^{-|G|^2/4p} e^{-2 pi i n.f} in FP64, by the table-driven exponential and
+// phase factor of the FP64 passes (about 1 ulp each; |G|^2/4p is bounded by the
+// plan, the phase is reduced mod 1 first)
+__device__ __forceinline__ void s_direct64(const GPoint &pt, const PairD &f, const double *e2, const double *cis,
+                                           double &sr, double &si) {
+  const double e = exp_tab(-pt.g2 * f.inv4p, e2);
   double ph = fma((double)pt.nu, f.fu, fma((double)pt.nv, f.fv, (double)pt.nw * f.fw));
   ph -= rint(ph);
-  double s, c;
-  sincospi(2.0 * ph, &s, &c);
+  double c, s;
+  cis_neg(ph, cis, c, s);
   sr = e * c;
-  si = -e * s;
+  si = e * s;
 }
 
 // ---------------------------------------------------------------------------
@@ -61,12 +84,15 @@ __global__ __launch_bounds__(256) void k_rho_head(const GPoint *__restrict__ pts
                                                   const PairHot *__restrict__ hot, int Lp0, int Lp1, int ppc,
                                                   const double *__restrict__ dh64, int64_t d_off, int ncols,
                                                   int ndmp, int ndm, double2 *__restrict__ parth, int row0,
-                                                  int nrows_h, const double *__restrict__ pmono) {
+                                                  int nrows_h, const double *__restrict__ pmono,
+                                                  const double *__restrict__ start_tab) {
   constexpr int NT = nherm(L);
   constexpr int PER = kQTileH * NTG * 16 / 256;  // staged columns per thread and tile
   static_assert(PER * 256 == kQTileH * NTG * 16, "tile size");
-  __shared__ PairF sh[kQTileH];
+  __shared__ PairD sh[kQTileH];
   __shared__ double sc[kQTileH * NTG * 16];
+  __shared__ double se2[32], scis[2 * 65];
+  head_tables(start_tab, se2, scis);  // (the tile loop's first barrier orders it)
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, g4 = lane >> 4;
@@ -85,7 +111,7 @@ __global__ __launch_bounds__(256) void k_rho_head(const GPoint *__restrict__ pts
   for (int t0 = p0; t0 < p1; t0 += kQTileH) {
     const int nq = min(kQTileH, p1 - t0);
     __syncthreads();
-    if (tid < nq) sh[tid] = pair_f(hot[t0 + tid]);
+    if (tid < nq) sh[tid] = pair_d(hot[t0 + tid]);
     // the group's columns of the tile's pairs, loads issued before the stores;
     // columns of densities past ndm were not written by this call's transform
     // and are masked (the FP64 buffer is not cleared)
@@ -105,7 +131,7 @@ __global__ __launch_bounds__(256) void k_rho_head(const GPoint *__restrict__ pts
       const int q = q0 + g4 < nq ? q0 + g4 : nq - 1;
       const bool vq = (q0 + g4 < nq) & (ptA.g2 <= sh[q].gc2);  // no branch: q is in range
       double Sr, Si;
-      s_direct64(ptA, sh[q], Sr, Si);
+      s_direct64(ptA, sh[q], se2, scis, Sr, Si);
       Sr = vq ? Sr : 0.0;
       Si = vq ? Si : 0.0;
       const double *bq = sc + q * (NTG * 16) + r16;
@@ -180,11 +206,13 @@ __global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ p
                                                     int ncolsW, int ntiles, int ndmp,
                                                     const PairHot *__restrict__ hot, int Lp0, int Lp1,
                                                     double *__restrict__ yhat, int64_t yhat_size, int64_t ycls_off,
-                                                    int ndm) {
+                                                    int ndm, const double *__restrict__ start_tab) {
   constexpr int NT = nherm(L);
   constexpr int kPTile = jh_ptile<NTW>();
   __shared__ GPoint sp[kPTile];
   __shared__ double sw[2][kPTile][NTW * 16];
+  __shared__ double se2[32], scis[2 * 65];
+  head_tables(start_tab, se2, scis);  // (the tile loop's barriers order it)
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, g4 = lane >> 4;
@@ -193,7 +221,7 @@ __global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ p
   const int nt0 = blockIdx.z * NTW;
   const int ntw = min(NTW, ntiles - nt0);
   const int pa = prow0 + r16;
-  const PairF f = pair_f(hot[Lp0 + (pa < np ? pa : 0)]);
+  const PairD f = pair_d(hot[Lp0 + (pa < np ? pa : 0)]);
   d4 acc[NTW];
 #pragma unroll
   for (int n = 0; n < NTW; ++n) acc[n] = d4{0.0, 0.0, 0.0, 0.0};
@@ -239,7 +267,7 @@ __global__ __launch_bounds__(256) void k_jpass_head(const GPoint *__restrict__ p
       const int q = q0 + g4 < nt ? q0 + g4 : nt - 1;
       const bool vq = (q0 + g4 < nt) & (sp[q].g2 <= f.gc2);
       double Sr, Si;
-      s_direct64(sp[q], f, Sr, Si);
+      s_direct64(sp[q], f, se2, scis, Sr, Si);
       Sr = vq ? Sr : 0.0;
       const double nSi = vq ? -Si : 0.0;
 #pragma unroll
@@ -279,7 +307,7 @@ static hipError_t rho_head_ntg(const Dev &d, int ndm, hipStream_t st) {
   dim3 grid((unsigned)((d.npts_head + 63) / 64), d.rho_h_chunks[L], (unsigned)tile_groups(d.ncols32[L] / 16));
   hipLaunchKernelGGL((k_rho_head<L, NTG>), grid, dim3(256), 0, st, d.pts, d.npts_head, d.hot_cut, d.L_p0[L], d.L_p1[L],
                      d.rho_h_ppc[L], d.dhat, d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.parth, d.rho_h_row0[L],
-                     d.nrows_h, d.ptmono);
+                     d.nrows_h, d.ptmono, d.start_tab);
   PWDF_CHECK_LAUNCH_H();
   return hipSuccess;
 }
@@ -323,7 +351,7 @@ static hipError_t j_head_ntw(const Dev &d, int ndm, hipStream_t st) {
   dim3 grid((unsigned)((np + 63) / 64), (unsigned)d.jh_chunks[L], (unsigned)((ntiles + NTW - 1) / NTW));
   hipLaunchKernelGGL((k_jpass_head<L, NTW>), grid, dim3(256), 0, st, d.pts, d.npts_head, d.jh_ppc[L], d.wre64,
                      d.wim64, d.ncolsW, ntiles, d.ndmp, d.hot_cut, d.L_p0[L], d.L_p1[L], d.yhat, d.yhat_size, off,
-                     ndm);
+                     ndm, d.start_tab);
   PWDF_CHECK_LAUNCH_H();
   return hipSuccess;
 }
