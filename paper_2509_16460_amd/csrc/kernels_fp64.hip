@@ -714,8 +714,12 @@ __device__ __forceinline__ void jpass_block(const SegDesc *__restrict__ segs, in
 //   J~_t = sum_{|k| = |t|} T[t][k] y_k
 //   J_ab += pref_j sum_t E^{ab}_t J~_t
 // ---------------------------------------------------------------------------
+// classes whose J moments k_ysum sums over the chunks before the back transform
+// (FP32-MFMA form): L >= 3 holds every wave-per-pair class
+constexpr int kYsumL0 = 3;
+
 template <int LA, int LB>
-__device__ __forceinline__ void back_thread(const Dev &dv, int bi, int dm) {
+__device__ __forceinline__ void back_thread(const Dev &dv, int bi, int dm, int jsum) {
   constexpr int L = LA + LB;
   constexpr int NT = nherm(L);
   constexpr Carts<LA> CA{};
@@ -735,8 +739,10 @@ __device__ __forceinline__ void back_thread(const Dev &dv, int bi, int dm) {
   for (int q = b.p0; q < b.p1; ++q) {
     const int rq = dv.cut_rank[q];  // J walk order
     const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (rq - Lp0);
-    // FP32-MFMA form: the chunks the pair's block of the J pass wrote
-    const int nchunks = dv.jn_of ? dv.jn_of[rq] : nchunks_L;
+    // FP32-MFMA form: the chunks the pair's block of the J pass wrote (for the
+    // classes L >= kYsumL0 summed into chunk 0 by k_ysum when jsum is set)
+    int nchunks = dv.jn_of ? dv.jn_of[rq] : nchunks_L;
+    if (jsum && L >= kYsumL0) nchunks = min(nchunks, 1);
     // y_k = sum over the J chunks in chunk order; the loads of four chunks are
     // issued together (one thread per pair leaves little other parallelism)
     double y[NT];
@@ -1010,7 +1016,7 @@ __device__ __forceinline__ void transform_wave(const Dev &dv, int bi, int dm, do
 }
 
 template <int LA, int LB>
-__device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double *__restrict__ lds) {
+__device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double *__restrict__ lds, int jsum) {
   using W = WaveTabs<LA, LB>;
   constexpr int L = W::L, NT = W::NT, NCA = W::NCA, NCB = W::NCB, NE = W::NE;
   constexpr int NEL = NCA * NCB;
@@ -1047,8 +1053,11 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
     wave_sync();
     const int rq = dv.cut_rank[q];  // J walk order
     const double *ys = yhat + (size_t)dm * yhat_size + ycls_off + (rq - Lp0);
-    // FP32-MFMA form: the chunks the pair's block of the J pass wrote
-    const int nchunks = dv.jn_of ? dv.jn_of[rq] : nchunks_L;
+    // FP32-MFMA form: the chunks the pair's block of the J pass wrote (summed
+    // into chunk 0 by k_ysum when jsum is set: every wave-per-pair class has
+    // L >= kYsumL0)
+    int nchunks = dv.jn_of ? dv.jn_of[rq] : nchunks_L;
+    if (jsum && L >= kYsumL0) nchunks = min(nchunks, 1);
     const int dq = dv.dd_of ? dv.dd_of[q] : -1;  // DD pair: the DD kernel's moments
     for (int k = lane; k < NT; k += 64) {
       if (dq >= 0) {
@@ -1368,7 +1377,43 @@ __global__ __launch_bounds__(kPairWG) void k_transform_all(const Dev dv, const C
   }
 }
 
-__global__ __launch_bounds__(kPairWG) void k_back_all(const Dev dv, const ClassTab tab) {
+// FP32-MFMA form, before the back transform: the J moments of the pairs of the
+// classes L >= kYsumL0 summed over the chunks their block of the J pass wrote,
+// in chunk order, into chunk 0.  One thread per (class, moment k, pair):
+// neighbouring lanes read neighbouring pairs of a chunk, where the wave-per-pair
+// back transform of those classes would read each moment of each chunk from a
+// line of its own.  The sums are the ones the back transform formed itself,
+// term for term.
+struct YsumTab {
+  int64_t start[kMaxLsum + 2];  // first thread of class L (0 below kYsumL0); start[kMaxLsum + 1] = total
+};
+
+__global__ __launch_bounds__(256) void k_ysum(const Dev dv, const YsumTab t) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= t.start[kMaxLsum + 1]) return;
+  const int dm = blockIdx.y;
+  int L = kYsumL0;
+  while (i >= t.start[L + 1]) ++L;
+  const int np = dv.L_p1[L] - dv.L_p0[L], NT = nherm(L);
+  const int64_t j = i - t.start[L];
+  const int k = (int)(j / np), r = (int)(j - (int64_t)k * np);
+  const int n = dv.jn_of[dv.L_p0[L] + r];
+  if (n <= 0) return;  // no chunk: the back transform reads none either
+  double *ys = dv.yhat + (size_t)dm * dv.yhat_size + dv.yhat_off[L] + (size_t)k * np + r;
+  const size_t cs = (size_t)NT * np;
+  double s = 0.0;
+  for (int c0 = 0; c0 < n; c0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = c0 + u < n ? ys[(size_t)(c0 + u) * cs] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (c0 + u < n) s += v[u];
+  }
+  ys[0] = s;
+}
+
+__global__ __launch_bounds__(kPairWG) void k_back_all(const Dev dv, const ClassTab tab, int jsum) {
   constexpr bool kThread30 = false;  // (3, 0): k_back_30
   __shared__ double lds[kWavesPerWG * kWaveLds];
   const int i = tab_entry(tab, blockIdx.x);
@@ -1379,19 +1424,19 @@ __global__ __launch_bounds__(kPairWG) void k_back_all(const Dev dv, const ClassT
     const int w = threadIdx.x >> 6;
     const int j = dv.cls_b0[cl] + local * kWavesPerWG + w;
     if (j >= dv.cls_b1[cl]) return;
-    PWDF_CLASS_SWITCH_WAVE(back_wave, dv, dv.blk_cut[j], dm, lds + w * kWaveLds)
+    PWDF_CLASS_SWITCH_WAVE(back_wave, dv, dv.blk_cut[j], dm, lds + w * kWaveLds, jsum)
   } else {
     const int j = dv.cls_b0[cl] + local * kPairWG + threadIdx.x;
     if (j >= dv.cls_b1[cl]) return;
-    PWDF_CLASS_SWITCH_THREAD(back_thread, dv, dv.blk_cut[j], dm)
+    PWDF_CLASS_SWITCH_THREAD(back_thread, dv, dv.blk_cut[j], dm, jsum)
   }
 }
 
 // The back transform of the class (3, 0), a thread per block in the J walk order.
-__global__ __launch_bounds__(kPairWG) void k_back_30(const Dev dv) {
+__global__ __launch_bounds__(kPairWG) void k_back_30(const Dev dv, int jsum) {
   const int j = dv.cls_b0[12] + blockIdx.x * kPairWG + threadIdx.x;
   if (j >= dv.cls_b1[12]) return;
-  back_thread<3, 0>(dv, dv.blk_cut[j], blockIdx.y);
+  back_thread<3, 0>(dv, dv.blk_cut[j], blockIdx.y, jsum);
 }
 
 template <int L, int NDB>
@@ -1577,14 +1622,30 @@ hipError_t launch_transform_all(const Dev &d, int ndm, hipStream_t st) {
 }
 
 hipError_t launch_back_all(const Dev &d, int ndm, hipStream_t st) {
+  // FP32-MFMA form: the chunk sums of the classes L >= kYsumL0 first
+  const int jsum = d.jn_of != nullptr ? 1 : 0;
+  if (jsum) {
+    YsumTab y{};
+    int64_t n = 0;
+    for (int L = 0; L <= kMaxLsum; ++L) {
+      y.start[L] = n;
+      if (L >= kYsumL0) n += (int64_t)nherm(L) * (d.L_p1[L] - d.L_p0[L]);
+    }
+    y.start[kMaxLsum + 1] = n;
+    if (n > 0) {
+      hipLaunchKernelGGL(k_ysum, dim3((unsigned)((n + 255) / 256), ndm), dim3(256), 0, st, d, y);
+      PWDF_CHECK_LAUNCH();
+    }
+  }
   const ClassTab t = pair_class_tab(d, true);
   if (t.n > 0) {
-    hipLaunchKernelGGL(k_back_all, dim3((unsigned)t.first[t.n], ndm), dim3(kPairWG), 0, st, d, t);
+    hipLaunchKernelGGL(k_back_all, dim3((unsigned)t.first[t.n], ndm), dim3(kPairWG), 0, st, d, t, jsum);
     PWDF_CHECK_LAUNCH();
   }
   const int n30 = d.cls_b1[12] - d.cls_b0[12];
   if (n30 > 0) {
-    hipLaunchKernelGGL(k_back_30, dim3((unsigned)((n30 + kPairWG - 1) / kPairWG), ndm), dim3(kPairWG), 0, st, d);
+    hipLaunchKernelGGL(k_back_30, dim3((unsigned)((n30 + kPairWG - 1) / kPairWG), ndm), dim3(kPairWG), 0, st, d,
+                       jsum);
     PWDF_CHECK_LAUNCH();
   }
   return hipSuccess;
