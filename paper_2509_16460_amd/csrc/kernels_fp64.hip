@@ -838,7 +838,7 @@ struct WaveTabs {
   static constexpr int eidx(int i, int j, int t) { return (i * (LB + 1) + j) * (L + 1) + t; }
   // LDS doubles of the wave-per-block transform and back-transform
   static constexpr int kTransformLds = 3 * NE + NCA * NCB + NT + (3 * NCA * NCB + 1) / 2;
-  static constexpr int kBackLds = 3 * NE + 2 * NT + ((L + 1) * (L + 1) * (L + 1) + 1) / 2;
+  static constexpr int kBackLds = 3 * NE + NT + (L + 1) * (L + 1) * (L + 1);
 };
 
 // (tx, ty, tz) of Hermite index t in the degree-ordered list (runtime inverse).
@@ -1027,18 +1027,14 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
   double *__restrict__ Jblk = dv.Jblk;
   const int64_t yhat_size = dv.yhat_size, ycls_off = dv.yhat_off[L], nelem = dv.nelem;
   const int nchunks_L = dv.j_chunks[L], Lp0 = dv.L_p0[L], Lp1 = dv.L_p1[L];
+  // sJ3: the Hermite-basis J moments at their (tx, ty, tz), so that the
+  // contraction reads them by position (one LDS read, no index table)
   double *sE = lds;
   double *sY = sE + 3 * NE;
-  double *sJ = sY + NT;
-  int *sIdx = reinterpret_cast<int *>(sJ + NT);
+  double *sJ3 = sY + NT;
   const int lane = threadIdx.x & 63;
   const BlockRec b = dv.blocks[bi];
   const int np = Lp1 - Lp0;
-  for (int t = lane; t < NT; t += 64) {
-    int tx, ty, tz;
-    herm_of(t, tx, ty, tz);
-    sIdx[(tx * (L + 1) + ty) * (L + 1) + tz] = t;
-  }
   double acc[ROUNDS];
   int ax[ROUNDS], ay[ROUNDS], az[ROUNDS], bx[ROUNDS], by[ROUNDS], bz[ROUNDS];
 #pragma unroll
@@ -1092,7 +1088,9 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
 #pragma unroll
       for (int k = 0; k < ncart(L); ++k)
         if (k < nc) s = fma(tv[k], sY[deg_off(d) + k], s);
-      sJ[t] = sg * s;
+      int tx, ty, tz;
+      herm_of(t, tx, ty, tz);
+      sJ3[(tx * (L + 1) + ty) * (L + 1) + tz] = sg * s;
     }
     wave_sync();
 #pragma unroll
@@ -1103,8 +1101,9 @@ __device__ __forceinline__ void back_wave(const Dev &dv, int bi, int dm, double 
           const double ex = sE[W::eidx(ax[r], bx[r], tx)];
           for (int ty = 0; ty <= ay[r] + by[r]; ++ty) {
             const double exy = ex * sE[NE + W::eidx(ay[r], by[r], ty)];
+            const double *jz = sJ3 + (tx * (L + 1) + ty) * (L + 1);
             for (int tz = 0; tz <= az[r] + bz[r]; ++tz)
-              s = fma(exy * sE[2 * NE + W::eidx(az[r], bz[r], tz)], sJ[sIdx[(tx * (L + 1) + ty) * (L + 1) + tz]], s);
+              s = fma(exy * sE[2 * NE + W::eidx(az[r], bz[r], tz)], jz[tz], s);
           }
         }
         acc[r] = fma(x.pref_j, s, acc[r]);
