@@ -265,7 +265,7 @@ def profile_name(kernel):
         return None
     k, L = m.group(1), m.group(2)
     fixed = {"k_phase_j_all": "phase_j", "k_phase_d": "phase_d", "k_back_all": "back", "k_back_30": "back",
-             "k_transform_all": "transform", "k_reduce_rows": "reduce", "k_reduce": "reduce", "k_fold_j": "fold_j",
+             "k_transform_all": "transform", "k_ysum": "back", "k_reduce_rows": "reduce", "k_reduce": "reduce", "k_fold_j": "fold_j",
              "k_wprep": "wprep"}
     if k in fixed:
         return fixed[k]
