@@ -56,8 +56,9 @@
  *   Every call returns a pwdf_status; nothing aborts.  Arguments are validated
  *   on the host before anything is enqueued; on failure nothing is enqueued and
  *   pwdf_last_error(ctx) describes the problem (pwdf_last_error(NULL) reports
- *   the last failed pwdf_create of the calling thread).  HIP runtime failures
- *   map to PWDF_EDEVICE with the HIP error string.
+ *   the last failure of the calling thread that had no context: a failed
+ *   pwdf_create, or a call given a NULL ctx).  HIP runtime failures map to
+ *   PWDF_EDEVICE with the HIP error string (PWDF_ENOMEM for an allocation).
  */
 #ifndef PWDF_H
 #define PWDF_H
@@ -320,8 +321,8 @@ pwdf_status pwdf_build_j_noalloc(pwdf_ctx *ctx, int ndm, const double *Dk, doubl
  * the half space the kernels walk (rho(-G) = conj rho(G)),
  *   rhoG    device, complex128 [ndm][nG/2]
  *   miller  host, int [nG/2][3] Miller indices n (G = B n) in the same order
- *           (may be NULL).
- * Synchronises the stream before returning (miller is filled on the host).
+ *           (may be NULL; filled from the plan before the call returns).
+ * rhoG is written on the stream (asynchronous, like pwdf_build_j).
  */
 pwdf_status pwdf_get_rhoG(pwdf_ctx *ctx, int ndm, const double *Dk, double *rhoG, int *miller,
                           void *stream);
@@ -410,7 +411,7 @@ typedef struct {
 pwdf_status pwdf_profile_enable(pwdf_ctx *ctx, int on);
 pwdf_status pwdf_profile_read(pwdf_ctx *ctx, pwdf_kprof *out, int max, int *n);
 
-/* Message of the last failure on ctx (NULL: last failed pwdf_create of this thread). */
+/* Message of the last failure on ctx (NULL: the last failure of this thread without a context). */
 const char *pwdf_last_error(const pwdf_ctx *ctx);
 
 /* Free the plan and all device workspaces; NULL is a no-op. */

@@ -479,6 +479,8 @@ pwdf_status setup_device_impl(pwdf_ctx *c, const Tune &tn) {
   if ((e = upload(c, vec, &d.field)) != hipSuccess) return hip_fail(c, e, "uploading " #field);
   UP(p.segs, segs)
   UP(p.pts, pts)
+  UP(p.valid_slots, valid_slots)
+  d.nvalid = (int)p.valid_slots.size();
   UP(p.slot_v, slot_v)
   UP(p.hot, hot)
   UP(p.hot_rho, hot_rho)
@@ -1188,7 +1190,7 @@ pwdf_status pwdf_check_input(pwdf_ctx *c, void *stream) {
 }
 
 pwdf_status pwdf_build_j(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, double *EJ, void *stream) {
-  if (!c) return PWDF_EINVAL;
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_build_j: ctx is NULL");
   pwdf_status s = validate_ndm(c, ndm);
   if (s != PWDF_OK) return s;
   if (!Dk || !Jk || !EJ) return fail(c, PWDF_EINVAL, "NULL buffer");
@@ -1201,7 +1203,7 @@ pwdf_status pwdf_build_j(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, dou
 }
 
 pwdf_status pwdf_build_j_graph(pwdf_ctx *c, int ndm, const double *Dk, double *Jk, double *EJ, void *stream) {
-  if (!c) return PWDF_EINVAL;
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_build_j_graph: ctx is NULL");
   pwdf_status s = validate_ndm(c, ndm);
   if (s != PWDF_OK) return s;
   if (!Dk || !Jk || !EJ) return fail(c, PWDF_EINVAL, "NULL buffer");
@@ -1342,7 +1344,7 @@ pwdf_status pwdf_energy_real(pwdf_ctx *c, int ndm, double *ER, void *stream) {
 }
 
 pwdf_status pwdf_get_rhoG(pwdf_ctx *c, int ndm, const double *Dk, double *rhoG, int *miller, void *stream) {
-  if (!c) return PWDF_EINVAL;
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_get_rhoG: ctx is NULL");
   pwdf_status s = validate_ndm(c, ndm);
   if (s != PWDF_OK) return s;
   if (!Dk || !rhoG) return fail(c, PWDF_EINVAL, "NULL buffer");
@@ -1351,27 +1353,18 @@ pwdf_status pwdf_get_rhoG(pwdf_ctx *c, int ndm, const double *Dk, double *rhoG, 
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   c->blocks_ndm = 0;
   if ((s = run_to_rho(c, ndm, Dk, c->Escr, st)) != PWDF_OK) return s;
-  // gather the valid slots on the host side of the copy (small: nG/2 complex per density)
+  // the valid slots gathered on the device, on the caller's stream
+  if ((e = launch_gather_rho(c->dev, ndm, reinterpret_cast<double2 *>(rhoG), st)) != hipSuccess)
+    return hip_fail(c, e, "gathering rho");
   const Plan &p = c->plan;
-  const size_t nv = p.valid_slots.size();
-  std::vector<double2> full((size_t)ndm * p.nslot());
-  if ((e = hipMemcpyAsync(full.data(), c->dev.rho, full.size() * sizeof(double2), hipMemcpyDeviceToHost, st)) !=
-      hipSuccess)
-    return hip_fail(c, e, "copy rho");
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "sync");
-  std::vector<double2> comp((size_t)ndm * nv);
-  for (int dm = 0; dm < ndm; ++dm)
-    for (size_t i = 0; i < nv; ++i) comp[dm * nv + i] = full[(size_t)dm * p.nslot() + p.valid_slots[i]];
-  if ((e = hipMemcpy(rhoG, comp.data(), comp.size() * sizeof(double2), hipMemcpyHostToDevice)) != hipSuccess)
-    return hip_fail(c, e, "copy rhoG");
   if (miller)
-    for (size_t i = 0; i < nv; ++i)
+    for (size_t i = 0; i < p.valid_slots.size(); ++i)
       for (int x = 0; x < 3; ++x) miller[3 * i + x] = p.slot_miller[3 * (size_t)p.valid_slots[i] + x];
   return PWDF_OK;
 }
 
 pwdf_status pwdf_grad(pwdf_ctx *c, int ndm, const double *Dk, double *dEdR, double *EJ, void *stream) {
-  if (!c) return PWDF_EINVAL;
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_grad: ctx is NULL");
   pwdf_status s = validate_ndm(c, ndm);
   if (s != PWDF_OK) return s;
   if (!Dk || !dEdR) return fail(c, PWDF_EINVAL, "NULL buffer");
@@ -1607,7 +1600,7 @@ static double kernel_ms(const std::vector<std::pair<std::string, double>> &v, co
 }
 
 pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
-  if (!c) return PWDF_EINVAL;
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_autotune: ctx is NULL");
   pwdf_status s = validate_ndm(c, ndm);
   if (s != PWDF_OK) return s;
   hipError_t e = hipSetDevice(c->device);
@@ -1811,7 +1804,7 @@ pwdf_status pwdf_autotune(pwdf_ctx *c, int ndm, const char *cache_path) {
 }
 
 pwdf_status pwdf_profile_enable(pwdf_ctx *c, int on) {
-  if (!c) return PWDF_EINVAL;
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_profile_enable: ctx is NULL");
   c->prof_on = on != 0;
   c->prof_recs.clear();
   c->prof_next = 0;
@@ -1820,7 +1813,8 @@ pwdf_status pwdf_profile_enable(pwdf_ctx *c, int on) {
 }
 
 pwdf_status pwdf_profile_read(pwdf_ctx *c, pwdf_kprof *out, int max, int *n) {
-  if (!c || !n) return PWDF_EINVAL;
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_profile_read: ctx is NULL");
+  if (!n) return fail(c, PWDF_EINVAL, "pwdf_profile_read: n is NULL");
   (void)hipSetDevice(c->device);
   for (const ProfRec &r : c->prof_recs) {
     hipError_t e = hipEventSynchronize(r.b);

@@ -99,6 +99,9 @@ struct Dev {
   // FP32-MFMA form: the relative monomials n_u^a n_v^b n_w^c of every point of
   // pts, [point][kMonoStride] in the order of Monos
   const double *ptmono;
+  // the slots holding a G of the half space, in walk order (pwdf_get_rhoG)
+  const int *valid_slots;
+  int nvalid;
   const int *jn_of;
   double2 *parth;
   int nrows_h, rows_per_group_h;
@@ -219,6 +222,8 @@ hipError_t launch_jpass_dd(const Dev &d, bool force, int ndm, hipStream_t st);
 hipError_t launch_energy(const Dev &d, int ndm, double *EJ, hipStream_t st);
 // E_J from the D(L) and J(L) blocks; part holds 256 doubles per density
 hipError_t launch_energy_real(const Dev &d, int ndm, double *part, double *ER, hipStream_t st);
+// rho of the valid slots, [ndm][nvalid], gathered from Dev::rho
+hipError_t launch_gather_rho(const Dev &d, int ndm, double2 *out, hipStream_t st);
 // GPW route: rho_D from the DD pairs' density on the grid (collocation and a
 // separable transform onto the G set); V_D onto the grid and the DD pairs' J
 // blocks by integration, added to J(L) after the back transform

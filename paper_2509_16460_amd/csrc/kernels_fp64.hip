@@ -1850,6 +1850,21 @@ __global__ __launch_bounds__(256) void k_energy_real_sum(const double *__restric
   energy_block(part, kERBlocks, ER, blockIdx.x, sh);
 }
 
+__global__ __launch_bounds__(256) void k_gather_rho(const double2 *__restrict__ rho, int nslot,
+                                                    const int *__restrict__ slots, int nvalid,
+                                                    double2 *__restrict__ out) {
+  const int i = blockIdx.x * 256 + threadIdx.x, dm = blockIdx.y;
+  if (i < nvalid) out[(size_t)dm * nvalid + i] = rho[(size_t)dm * nslot + slots[i]];
+}
+
+hipError_t launch_gather_rho(const Dev &d, int ndm, double2 *out, hipStream_t st) {
+  if (d.nvalid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rho, dim3((unsigned)((d.nvalid + 255) / 256), ndm), dim3(256), 0, st, d.rho, d.nslot,
+                     d.valid_slots, d.nvalid, out);
+  PWDF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
 hipError_t launch_energy_real(const Dev &d, int ndm, double *part, double *ER, hipStream_t st) {
   hipLaunchKernelGGL(k_energy_real_part, dim3(kERBlocks, ndm), dim3(256), 0, st, d, part);
   PWDF_CHECK_LAUNCH();

@@ -232,3 +232,27 @@ def test_allocation_hooks_without_a_context():
     L.pwdf_debug_fail_alloc(3)
     L.pwdf_debug_fail_alloc(-1)
     assert L.pwdf_debug_live_allocs() == 0
+
+
+def test_null_context_calls_report_a_message():
+    """Every entry point given a NULL context returns PWDF_EINVAL and leaves a
+    message for pwdf_last_error(NULL); none of these calls touches a device."""
+    L = pwdf.lib()
+    nul = ctypes.c_void_p()
+    calls = {
+        "pwdf_build_j": lambda: L.pwdf_build_j(nul, 1, None, None, None, None),
+        "pwdf_build_j_graph": lambda: L.pwdf_build_j_graph(nul, 1, None, None, None, None),
+        "pwdf_build_j_noalloc": lambda: L.pwdf_build_j_noalloc(nul, 1, None, None, None, None),
+        "pwdf_get_rhoG": lambda: L.pwdf_get_rhoG(nul, 1, None, None, None, None),
+        "pwdf_grad": lambda: L.pwdf_grad(nul, 1, None, None, None, None),
+        "pwdf_autotune": lambda: L.pwdf_autotune(nul, 1, None),
+        "pwdf_energy_real": lambda: L.pwdf_energy_real(nul, 1, None, None),
+        "pwdf_profile_enable": lambda: L.pwdf_profile_enable(nul, 1),
+        "pwdf_set_jk_layout": lambda: L.pwdf_set_jk_layout(nul, 0),
+        "pwdf_set_fp32_head": lambda: L.pwdf_set_fp32_head(nul, 0.5),
+        "pwdf_query": lambda: L.pwdf_query(nul, None),
+    }
+    for name, call in calls.items():
+        assert call() == -1, name
+        msg = L.pwdf_last_error(None).decode()
+        assert name in msg and "NULL" in msg, (name, msg)
