@@ -293,6 +293,7 @@ void fp32_shapes(const Plan &p, Dev &d, const Tune &tn, WorkLists &wl) {
   constexpr int kMaxFp32Run = 1024, kMinRun = 16;
   constexpr int kHeadWaves = 2048, kHeadMinPairs = 32;
   constexpr int kHeadJBlocks = 512, kHeadJMinPts = 32;
+  constexpr int kRhoZWaves = 2048;  // tail rho: spread a class's N-tile groups below this many waves
   const int nh = d.npts_head, npts = (int)p.pts.size(), ntail = npts - nh;
   const int nb = (ntail + 63) / 64;
   std::vector<double> tg2(ntail);
@@ -367,11 +368,25 @@ void fp32_shapes(const Plan &p, Dev &d, const Tune &tn, WorkLists &wl) {
       hc = (nh + d.jh_ppc[L] - 1) / d.jh_ppc[L];
       d.jh_chunks[L] = hc;
     }
-    // rho over the tail
+    // rho over the tail; a class of few items (the high classes, whose items walk
+    // many N-tile groups) spreads its groups over grid z in slices, each slice
+    // adding into a partial row of its own
     const int ppc = run_len(CR, costR[L], tn.mrho[L], kMaxFp32Run);
+    int nit = 0;
+    for (int b = 0; b < nb; ++b) nit += (nact[L][b] + ppc - 1) / ppc;
+    int gps = ngr[L];
+    if (nit > 0 && 4 * nit < kRhoZWaves) {
+      const int want = std::min(ngr[L], (kRhoZWaves + 4 * nit - 1) / (4 * nit));
+      gps = (ngr[L] + want - 1) / want;
+    }
+    const int zs = (ngr[L] + gps - 1) / gps;  // every slice holds at least one group
+    d.rho_gps[L] = gps;
+    d.rho_zs[L] = zs;
     for (int b = 0; b < nb; ++b)
-      for (int q0 = 0; q0 < nact[L][b]; q0 += ppc)
-        wl.rho_items.push_back(make_int4(b, q0, std::min(nact[L][b], q0 + ppc), wl.rows_of_block[b]++));
+      for (int q0 = 0; q0 < nact[L][b]; q0 += ppc) {
+        wl.rho_items.push_back(make_int4(b, q0, std::min(nact[L][b], q0 + ppc), wl.rows_of_block[b]));
+        wl.rows_of_block[b] += zs;
+      }
     d.rho_nitems[L] = (int)wl.rho_items.size() - d.rho_item0[L];
     // J over the tail
     const int spc = run_len(CJ, costJ[L], tn.mj[L], kMaxFp32Run);

@@ -94,6 +94,9 @@ struct Dev {
   const int *slot_pidx;
   const int4 *rho_items, *j_items;
   int rho_item0[kMaxLsum + 1], rho_nitems[kMaxLsum + 1];
+  // rho over the tail: N-tile groups per slice of grid z (each slice with a
+  // partial row of its own: rows [row, row + slices) of an item) and slices
+  int rho_gps[kMaxLsum + 1], rho_zs[kMaxLsum + 1];
   int j_item0[kMaxLsum + 1], j_nitems[kMaxLsum + 1];
   const int *rows_of_block;
   // FP32-MFMA form: the relative monomials n_u^a n_v^b n_w^c of every point of

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const int4 *__restrict__ items
                                                   int npts, const PairHot *__restrict__ hot, int Lp0,
                                                   const float *__restrict__ dh32, int64_t d32_off, int ncols,
                                                   int ndmp, int ndm, double2 *__restrict__ part, int nrows,
-                                                  const double *__restrict__ pmono) {
+                                                  const double *__restrict__ pmono, int gps) {
   constexpr int NT = nherm(L);
   __shared__ PairF sh[kQTile];
   __shared__ float sc[kQTile * NTG * 16];
@@ -95,10 +95,13 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const int4 *__restrict__ items
 #pragma unroll
   for (int off = 8; off > 0; off >>= 1) rmin = fmin(rmin, __shfl_xor(rmin, off, 64));
 
-  // lanes r16 < ndm write density r16 of the wave's rows; each N-tile group adds
-  // its epilogue into the item's partial row (same lane, same addresses: no race)
-  double2 *out = part + ((size_t)min(r16, ndm - 1) * nrows + it.w) * npts;
-  for (int ng = 0; ng < ntiles; ng += NTG) {
+  // slice blockIdx.z of the N-tile groups: gps groups of NTG tiles, into the
+  // item's partial row it.w + z; lanes r16 < ndm write density r16 of the wave's
+  // rows; each group of the slice adds its epilogue into that row (same lane,
+  // same addresses: no race)
+  const int ng0 = blockIdx.z * gps * NTG, ng1 = min(ntiles, ng0 + gps * NTG);
+  double2 *out = part + ((size_t)min(r16, ndm - 1) * nrows + it.w + blockIdx.z) * npts;
+  for (int ng = ng0; ng < ng1; ng += NTG) {
     const int ntg = min(NTG, ntiles - ng);
     f4 are[NTG], aim[NTG];
 #pragma unroll
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(256) void k_rho_mfma(const int4 *__restrict__ items
         const int pi = pt0 + 4 * g4 + i;
         if (pi >= npts) continue;
         double2 v = make_double2(accr[i], acci[i]);
-        if (ng > 0) {
+        if (ng > ng0) {
           const double2 o = out[pi];
           v.x += o.x;
           v.y += o.y;
@@ -353,10 +356,10 @@ __global__ __launch_bounds__(256) void k_jpass_mfma(const int4 *__restrict__ ite
 template <int L, int NTG>
 static hipError_t rho_mfma_ntg(const Dev &d, int ndm, hipStream_t st) {
   const int ntail = d.npts - d.npts_head;
-  hipLaunchKernelGGL((k_rho_mfma<L, NTG>), dim3((unsigned)d.rho_nitems[L]), dim3(256), 0, st,
+  hipLaunchKernelGGL((k_rho_mfma<L, NTG>), dim3((unsigned)d.rho_nitems[L], 1, (unsigned)d.rho_zs[L]), dim3(256), 0, st,
                      d.rho_items + d.rho_item0[L], d.pts + d.npts_head, ntail, d.hot_cut, d.L_p0[L], d.dh32,
                      d.d32_off[L], d.ncols32[L], d.ndmp, ndm, d.part, d.nrows,
-                     d.ptmono + (size_t)d.npts_head * kMonoStride);
+                     d.ptmono + (size_t)d.npts_head * kMonoStride, d.rho_gps[L]);
   PWDF_CHECK_LAUNCH32();
   return hipSuccess;
 }
