@@ -15,6 +15,13 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include")]
 
+# The MFMA kernels keep their accumulators in VGPRs (the MFMA's C/D operands in
+# the VGPR form): with AGPR operands the register allocator moved every
+# accumulator between a single AGPR tile and VGPRs around each MFMA in several of
+# their instances, which also exposed each MFMA's full latency.
+MFMA_FLAGS = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+MFMA_SOURCES = {"kernels_fp32.hip", "kernels_head.hip"}
+
 
 def build(jobs: int = 8) -> str:
     objdir = os.path.join(PKG, "_build")
@@ -23,7 +30,7 @@ def build(jobs: int = 8) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
-        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(HERE, src), "-o", obj]
+        cmd = [HIPCC] + FLAGS + (MFMA_FLAGS if src in MFMA_SOURCES else []) + ["-c", os.path.join(HERE, src), "-o", obj]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
     for src, pr in procs:
