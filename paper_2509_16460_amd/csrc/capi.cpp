@@ -388,8 +388,19 @@ void fp32_shapes(const Plan &p, Dev &d, const Tune &tn, WorkLists &wl) {
         wl.rows_of_block[b] += zs;
       }
     d.rho_nitems[L] = (int)wl.rho_items.size() - d.rho_item0[L];
-    // J over the tail
-    const int spc = run_len(CJ, costJ[L], tn.mj[L], kMaxFp32Run);
+    // J over the tail; a class of few pair blocks (the high classes) takes shorter
+    // point runs, so that its launch still spreads over about kRhoZWaves waves
+    // (more chunks of moments, which the back transform's chunk sum reads)
+    int spc = run_len(CJ, costJ[L], tn.mj[L], kMaxFp32Run);
+    {
+      int nit = 0;
+      for (int B = 0; B < (int)nactp[L].size(); ++B) nit += (nactp[L][B] + spc - 1) / spc;
+      const int waves = 4 * nit * ngr[L];
+      if (nit > 0 && waves < kRhoZWaves) {
+        const int r = (int)((int64_t)spc * waves / kRhoZWaves);
+        spc = std::max(kMinRun, (r + 3) / 4 * 4);
+      }
+    }
     int maxc = 0;
     for (int B = 0; B < (int)nactp[L].size(); ++B) {
       int c = 0;
