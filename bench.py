@@ -10,10 +10,12 @@ transforms, rho(G), V(G) and E_J, J from V, back transform and J(L) -> J(k).
 The headline form is the FP32-MFMA one (pair-G tiles in FP32 on the matrix
 cores, the head of the G set in FP64 tiles on FP64 MFMA; phase sums,
 transforms and energies in FP64), launched as the captured graph after an
-untimed autotune, with J(k) written on the pair support only, packed (the
-layout PWDF_JK_PACKED: [density][k][support element]).  `value` is density J
-builds/s (16 per step) from a region timed with torch.cuda.synchronize() on
-both sides.
+untimed autotune, with D(k) read and J(k) written on the pair support only,
+packed (the layouts PWDF_DK_PACKED and PWDF_JK_PACKED: [density][k][support
+element]; the dense D(k) is gathered into that layout before the timed
+region).  `value` is density J builds/s (16 per step) from a region timed with
+torch.cuda.synchronize() on both sides; the same build reading the dense
+[density][k][nbf][nbf] D(k) is timed after it ("dense_dk_input").
 
 Beside it, on the same slab and densities: the FP64 form with one density per
 call (the plain form; the ratio of the two is the batched-FP32 speedup) and
@@ -151,9 +153,11 @@ def kernel_table(prof):
 
 
 def single_fp64(torch, pwdf, prob, Dt, steps, warmup):
-    """FP64 form, one density per call, packed J(k), graph replay, autotuned."""
+    """FP64 form, one density per call, packed D(k) and J(k), graph replay, autotuned."""
     ctx = pwdf.LongRangeJ(prob, precision=pwdf.PWDF_FP64, max_ndm=1)
     ctx.set_jk_layout(pwdf.PWDF_JK_PACKED)
+    ctx.set_dk_layout(pwdf.PWDF_DK_PACKED)
+    Dt = ctx.pack_dk(Dt)
     ctx.autotune(1, None)
     J = torch.empty((1, prob.nk, ctx.stats()["jk_support"]), dtype=Dt.dtype, device=Dt.device)
     E = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -199,11 +203,13 @@ def extras(args):
         # default launch shapes (no autotune), graph replay
         ctx = pwdf.LongRangeJ(pr, precision=pwdf.PWDF_FP64, max_ndm=1)
         ctx.set_jk_layout(pwdf.PWDF_JK_PACKED)
+        ctx.set_dk_layout(pwdf.PWDF_DK_PACKED)
+        Dp = ctx.pack_dk(Dt)
         J = torch.empty((1, pr.nk, ctx.stats()["jk_support"]), dtype=Dt.dtype, device=Dt.device)
         E = torch.empty(1, dtype=torch.float64, device="cuda")
-        ms = timed(torch, lambda: ctx.build_j(Dt, J, E, graph=True), min(args.steps, 10), 2)
+        ms = timed(torch, lambda: ctx.build_j(Dp, J, E, graph=True), min(args.steps, 10), 2)
         st = ctx.stats()
-        prof = profile_kernels(torch, ctx, lambda: ctx.build_j(Dt, J, E), 3)
+        prof = profile_kernels(torch, ctx, lambda: ctx.build_j(Dp, J, E), 3)
         kt = kernel_table(prof)
         dd = {k: v["avg_us"] for k, v in kt.items() if k in ("rho_dd", "jpass_dd", "combine_dd", "gpw_rho", "gpw_j",
                                                               "gpw_add")}
@@ -387,16 +393,27 @@ def main():
     log("FP32-MFMA batch: autotune")
     c32 = pwdf.LongRangeJ(prob, precision=pwdf.PWDF_FP32_MFMA, max_ndm=NDM)
     c32.set_jk_layout(pwdf.PWDF_JK_PACKED)
+    c32.set_dk_layout(pwdf.PWDF_DK_PACKED)
     c32.autotune(NDM, args.tune_cache)
     st = c32.stats()
     mu, nu = c32.jk_support()
+    Dp = c32.pack_dk(Db)  # outside the timed region: the density as the caller holds it
     Jb = torch.empty((NDM, prob.nk, st["jk_support"]), dtype=Db.dtype, device="cuda")
     log("FP32-MFMA batch: timed region")
-    ms = timed(torch, lambda: c32.build_j(Db, Jb, Eb, graph=True), args.steps, args.warmup)
+    ms = timed(torch, lambda: c32.build_j(Dp, Jb, Eb, graph=True), args.steps, args.warmup)
     J32_0 = Jb[0].clone()
     E32 = Eb.cpu().numpy().copy()
-    prof = profile_kernels(torch, c32, lambda: c32.build_j(Db, Jb, Eb), max(3, args.steps // 4))
+    prof = profile_kernels(torch, c32, lambda: c32.build_j(Dp, Jb, Eb), max(3, args.steps // 4))
     c32.check_input()
+    # the same build reading the dense D(k)
+    c32.set_dk_layout(pwdf.PWDF_DK_FULL)
+    log("FP32-MFMA batch, dense D(k): timed region")
+    ms_dense = timed(torch, lambda: c32.build_j(Db, Jb, Eb, graph=True), args.steps, args.warmup)
+    dense_dk = {"ms_per_step": ms_dense, "builds_per_s": NDM * 1e3 / ms_dense,
+                "max_abs_dJ_vs_packed": float((Jb[0] - J32_0).abs().max()),
+                "dk_support_elements": c32.stats()["dk_support"]}
+    c32.check_input()
+    del Dp
     dominant = max(prof, key=lambda k: prof[k]["ms"] / prof[k]["launches"])
     roof = roofline_entry(dominant, prof[dominant], load_traffic(WORKLOAD, dominant))
     kernels = kernel_table(prof)
@@ -407,7 +424,8 @@ def main():
 
     if args.only_headline:
         print(json.dumps({"metric": METRIC, "value": NDM * 1e3 / ms, "unit": "J builds/s", "ms_per_step": ms,
-                          "config": {"workload": WORKLOAD}, "roofline": roof, "kernels": kernels}), flush=True)
+                          "config": {"workload": WORKLOAD}, "roofline": roof, "kernels": kernels,
+                          "dense_dk_input": dense_dk}), flush=True)
         return
 
     # side legs: the FP32-MFMA batch without per-pair cuts, the FP64 form with 16
@@ -415,9 +433,12 @@ def main():
     def side(pr, prec):
         c = pwdf.LongRangeJ(pr, precision=prec, max_ndm=NDM)
         c.set_jk_layout(pwdf.PWDF_JK_PACKED)
+        c.set_dk_layout(pwdf.PWDF_DK_PACKED)
+        Dq = c.pack_dk(Db)
         J = torch.empty((NDM, pr.nk, c.stats()["jk_support"]), dtype=Db.dtype, device="cuda")
         E = torch.empty(NDM, dtype=torch.float64, device="cuda")
-        t = timed(torch, lambda: c.build_j(Db, J, E, graph=True), max(5, args.steps // 2), args.warmup)
+        t = timed(torch, lambda: c.build_j(Dq, J, E, graph=True), max(5, args.steps // 2), args.warmup)
+        del Dq
         r = {"ms_per_step": t, "builds_per_s": NDM * 1e3 / t, "pair_G_evals_per_density_build": c.stats()["pairG_evals"]}
         del c, J, E
         torch.cuda.empty_cache()
@@ -455,10 +476,12 @@ def main():
                                 "sums, transforms, energy FP64)",
                    "screening": "eps 1e-12, per-pair G cuts", "nG_head": st["nG_head"],
                    "jk_layout": "packed support", "jk_support_elements": st["jk_support"],
+                   "dk_layout": "packed support", "dk_support_elements_read": st["dk_support"],
                    "launch": "graph replay, autotuned", "seg_len": st["seg_len"]},
         "pair_G_evals_per_s": st["pairG_evals"] * dens_per_s,
         "pair_G_evals_per_density_build": st["pairG_evals"],
         "pair_G_fp64_head_fraction": st["pairG_head"] / max(1.0, st["pairG_evals"]),
+        "dense_dk_input": dense_dk,
         "fp32_batch_without_pair_cuts": nocut32,
         "fp64_batch16": batch64,
         "roofline": roof,

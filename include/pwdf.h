@@ -103,6 +103,15 @@ typedef enum {
                           pwdf_get_jk_support */
 } pwdf_jk_layout;
 
+/* How the D(k) of pwdf_build_j / _graph / _noalloc, pwdf_get_rhoG and pwdf_grad
+ * is laid out (pwdf_set_dk_layout). */
+typedef enum {
+  PWDF_DK_FULL = 0,  /* complex128 [ndm][nk][nbf][nbf], every element present (default) */
+  PWDF_DK_PACKED = 1 /* complex128 [ndm][nk][jk_support]: only the elements of the J(k)
+                        support, in the packed order of pwdf_get_jk_support (both
+                        triangles; the packed J(k) of a build has this layout) */
+} pwdf_dk_layout;
+
 typedef struct {
   double eps_pair; /* pair screening on exp(-a_a a_b/p |A-B-L|^2); e.g. 1e-12 */
   double eps_G;    /* G cutoff |G| <= 2 omega sqrt(-ln eps_G); e.g. 1e-12 */
@@ -155,7 +164,8 @@ typedef struct {
                          triangles): what a build writes per k and density in the
                          PWDF_JK_SUPPORT layout */
   int64_t dk_support; /* matrix elements of D(k) a build reads per k and density (one
-                         of (mu,nu), (nu,mu) for each support pair of elements) */
+                         of (mu,nu), (nu,mu) for each support pair of elements; in
+                         the packed D(k) layout, pwdf_query: the packed ones) */
   int64_t jk_layout;  /* current pwdf_jk_layout (pwdf_query) */
   int64_t nG_head;    /* G vectors of the half space in the head (v(G) >= 2^-7 max v) */
   double pairG_head;  /* per build and density: the part of pairG_evals on the head G;
@@ -230,6 +240,21 @@ pwdf_status pwdf_set_jk_layout(pwdf_ctx *ctx, int layout);
 pwdf_status pwdf_set_fp32_head(pwdf_ctx *ctx, double weight);
 
 /*
+ * D(k) layout of the calls that read a density (pwdf_dk_layout; default
+ * PWDF_DK_FULL).  With PWDF_DK_PACKED a density is passed as the values of
+ * D(k) on the J(k) support only, in the packed element order of
+ * pwdf_get_jk_support: the D(k) -> D(L) phase sums (eq. "FT for D") then read
+ * whole runs of each packed row (of the two Hermitian partners (mu, nu) and
+ * (nu, mu) the one with shell(mu) <= shell(nu)) instead of a few elements per
+ * row of the dense matrix.  Every D(L) value a build forms lies on that support,
+ * so both layouts give the same J(k) and E_J up to rounding (the two read
+ * opposite partners of some pairs: D(k) is taken as Hermitian).  A cached graph
+ * is dropped when the layout changes.  Errors: PWDF_EINVAL (NULL ctx, unknown
+ * layout).  Host only.
+ */
+pwdf_status pwdf_set_dk_layout(pwdf_ctx *ctx, int layout);
+
+/*
  * Element order of the packed J(k) layout: for i < pwdf_stats.jk_support, the
  * i-th packed value of every (density, k) plane is J_{mu[i], nu[i]}(k).  mu and
  * nu are host arrays of jk_support ints (either may be NULL).  The elements are
@@ -266,7 +291,8 @@ pwdf_status pwdf_plan_stats(const double lattice[9], int natm, const double *xyz
  * "non-ortho J eval"), back transform (algorithm "J matrix transformation")
  * and J(L) -> J(k) (eq. "FT of J").
  *   ndm   1 <= ndm <= max_ndm.
- *   Dk    device, complex128 [ndm][nk][nbf][nbf], Hermitian per k; read only.
+ *   Dk    device, complex128 [ndm][nk][nbf][nbf], Hermitian per k; read only;
+ *         or [ndm][nk][jk_support] in the packed D(k) layout (pwdf_set_dk_layout).
  *   Jk    device, same layout; every element written (zeros off the pair support),
  *         or only the elements on the pair support (pwdf_set_jk_layout); packed
  *         layout: complex128 [ndm][nk][jk_support] (pwdf_get_jk_support).

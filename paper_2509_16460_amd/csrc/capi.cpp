@@ -86,6 +86,7 @@ struct pwdf_ctx {
   int max_ndm = 1;
   pwdf_precision prec = PWDF_FP64;
   int jk_layout = PWDF_JK_FULL;
+  int dk_layout = PWDF_DK_FULL;
 };
 
 namespace {
@@ -472,10 +473,12 @@ pwdf_status setup_device_impl(pwdf_ctx *c, const Tune &tn) {
   d.dhat_size = std::max<int64_t>(1, p.dhat_size);
   d.nsegJ = (int)p.sJ_code.size();
   d.nsegD = (int)p.sD_code.size();
+  d.nsegDp = (int)p.sDp_code.size();
   for (int i = 0; i < 3; ++i) d.kmesh[i] = in.kmesh[i];
   d.nheavyJ = (int)p.heavyJ.size();
   d.nlightJ = (int)p.lightJ.size();
   d.jk_layout = c->jk_layout;
+  d.dk_layout = c->dk_layout;
   d.pair_gcut = p.cut_on() ? 1 : 0;
   d.muu = p.M[p.ax[0]][p.ax[0]];
   d.fp32 = c->prec == PWDF_FP32_MFMA ? 1 : 0;
@@ -533,6 +536,10 @@ pwdf_status setup_device_impl(pwdf_ctx *c, const Tune &tn) {
   UP(p.sD_code, sD_code)
   UP(p.sD_e0, sD_e0)
   UP(p.eD, eD)
+  UP(p.sDp_el, sDp_el)
+  UP(p.sDp_code, sDp_code)
+  UP(p.sDp_e0, sDp_e0)
+  UP(p.eDp, eDp)
   UP(p.ttab, ttab)
   d.ndd = (int)p.dd_q.size();
   if (d.ndd > 0) {
@@ -903,7 +910,8 @@ pwdf_status run_to_rho(pwdf_ctx *c, int ndm, const double *Dk, double *EJ, hipSt
   const Plan &p = c->plan;
   const Dev &d = c->dev;
   pwdf_status s;
-  if ((s = step(c, "phase_d", (double)p.nD_support * p.nk * ndm, st,
+  const double nsup = (double)(c->dk_layout == PWDF_DK_PACKED ? p.nDp_support : p.nD_support);
+  if ((s = step(c, "phase_d", nsup * p.nk * ndm, st,
                 [&] { return launch_phase_d(d, Dk, ndm, st); })) != PWDF_OK)
     return s;
   return run_mid_rho(c, ndm, EJ, st);
@@ -1159,6 +1167,7 @@ pwdf_status pwdf_query(const pwdf_ctx *c, pwdf_stats *out) {
   out->seg_len = c->plan.seg_len;
   out->fork = c->tune.fork;
   out->jk_layout = c->jk_layout;
+  if (c->dk_layout == PWDF_DK_PACKED) out->dk_support = c->plan.nDp_support;
   return PWDF_OK;
 }
 
@@ -1169,6 +1178,16 @@ pwdf_status pwdf_set_jk_layout(pwdf_ctx *c, int layout) {
   if (layout != c->jk_layout) drop_graph(c);  // the captured J(k) launch has the old shape
   c->jk_layout = layout;
   c->dev.jk_layout = layout;
+  return PWDF_OK;
+}
+
+pwdf_status pwdf_set_dk_layout(pwdf_ctx *c, int layout) {
+  if (!c) return fail(nullptr, PWDF_EINVAL, "pwdf_set_dk_layout: ctx is NULL");
+  if (layout != PWDF_DK_FULL && layout != PWDF_DK_PACKED)
+    return fail(c, PWDF_EINVAL, "layout must be PWDF_DK_FULL or PWDF_DK_PACKED");
+  if (layout != c->dk_layout) drop_graph(c);  // the captured D(k) launch reads the old layout
+  c->dk_layout = layout;
+  c->dev.dk_layout = layout;
   return PWDF_OK;
 }
 

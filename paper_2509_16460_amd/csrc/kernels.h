@@ -35,14 +35,16 @@ struct Dev {
   const GatherEnt *sp_ent;
   const int *bf_shell, *bf_comp;
   // phase sums by Born-von Karman class (see plan.h)
-  int nsegJ, nsegD;
+  int nsegJ, nsegD, nsegDp;
   const int *sJ_off, *sJ_code, *sJ_e0, *eJ;
   const int *sD_el, *sD_code, *sD_e0, *eD;
+  const int *sDp_el, *sDp_code, *sDp_e0, *eDp;  // the same for a packed D(k)
   const int *heavyJ;             // elements with more than kPhaseLight J classes
   int nheavyJ;
   const int *lightJ;             // the other support elements (1 .. kPhaseLight classes), ascending
   int nlightJ;
   int jk_layout;                 // pwdf_jk_layout: 0 every element, 1 the support in place, 2 packed
+  int dk_layout;                 // pwdf_dk_layout: 0 dense D(k), 1 packed on the J(k) support
   int pair_gcut;                 // 1: pairs carry their own cut radius (PairHot::gc2)
   double muu;                    // M_uu = |b_u|^2: |G|^2 along a line grows by steps of 2 M_uu
   int *nonfinite;                // set to 1 by phase_d when a D(L) phase sum is not finite

@@ -67,7 +67,7 @@ __device__ __forceinline__ double2 cis_neg(double f, const double2 *__restrict__
   return make_double2(c, s);
 }
 
-__global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk, int nk, int nbf, int n2, int n3,
+__global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk, int nk, int64_t nn, int n2, int n3,
                                                  int nsegD, const int *__restrict__ sD_el,
                                                  const int *__restrict__ sD_code, const int *__restrict__ sD_e0,
                                                  const int *__restrict__ eD, const double2 *__restrict__ ptab,
@@ -79,7 +79,6 @@ __global__ __launch_bounds__(256) void k_phase_d(const double2 *__restrict__ Dk,
   const int sg = blockIdx.x * blockDim.x + threadIdx.x;
   const int dm = blockIdx.y;
   if (sg >= nsegD) return;
-  const int64_t nn = (int64_t)nbf * nbf;
   const int code = sD_code[sg];
   const int c1 = code & 1023, c2 = (code >> 10) & 1023, c3 = code >> 20;
   const double2 *D = Dk + (size_t)dm * nk * nn + sD_el[sg];
@@ -1566,12 +1565,16 @@ __global__ __launch_bounds__(256) void k_phase_j_all(const double *__restrict__ 
   } while (0)
 
 hipError_t launch_phase_d(const Dev &d, const double *Dk, int ndm, hipStream_t st) {
-  if (d.nsegD <= 0) return hipSuccess;
+  const bool packed = d.dk_layout == 1;
+  const int nseg = packed ? d.nsegDp : d.nsegD;
+  if (nseg <= 0) return hipSuccess;
   if (d.ptab_len > kPtabMax) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((d.nsegD + 255) / 256), ndm);
-  hipLaunchKernelGGL(k_phase_d, grid, dim3(256), 0, st, (const double2 *)Dk, d.nk, d.nbf, d.kmesh[1], d.kmesh[2],
-                     d.nsegD, d.sD_el, d.sD_code, d.sD_e0, d.eD, d.ptab, d.ptab_len, 1.0 / d.nk, d.Dblk, d.nelem,
-                     d.nonfinite);
+  // a plane of D(k): the dense matrix, or the J(k) support in its packed order
+  const int64_t nn = packed ? (int64_t)d.nlightJ + d.nheavyJ : (int64_t)d.nbf * d.nbf;
+  dim3 grid((unsigned)((nseg + 255) / 256), ndm);
+  hipLaunchKernelGGL(k_phase_d, grid, dim3(256), 0, st, (const double2 *)Dk, d.nk, nn, d.kmesh[1], d.kmesh[2], nseg,
+                     packed ? d.sDp_el : d.sD_el, packed ? d.sDp_code : d.sD_code, packed ? d.sDp_e0 : d.sD_e0,
+                     packed ? d.eDp : d.eD, d.ptab, d.ptab_len, 1.0 / d.nk, d.Dblk, d.nelem, d.nonfinite);
   PWDF_CHECK_LAUNCH();
   return hipSuccess;
 }

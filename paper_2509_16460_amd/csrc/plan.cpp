@@ -910,6 +910,9 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
     // holds ncart(la) consecutive elements of the block instead of ncart(lb),
     // so the lines fetched carry more of the support.
     std::vector<std::array<int, 3>> dtrip;
+    // packed layout candidates: (element, class code, D(L) offset, transposed
+    // element, its class code), the transposed one taken when shell(mu) > shell(nu)
+    std::vector<std::array<int, 5>> ptrip;
     for (int mu = 0; mu < nbf; ++mu)
       for (int nu = 0; nu < nbf; ++nu) {
         size_t e = (size_t)mu * nbf + nu;
@@ -925,8 +928,11 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
           int64_t joff = br.eoff + (g.tr ? (int64_t)b * ncb + a : (int64_t)a * ncb + b);
           int code = code_of(p.imgs[g.img], g.tr ? -1 : 1);
           ents.push_back({code, (int)joff});
-          if (!g.tr)
-            dtrip.push_back({dT ? nu * nbf + mu : (int)e, dT ? code_of(p.imgs[g.img], -1) : code, (int)joff});
+          if (!g.tr) {
+            const int codeT = code_of(p.imgs[g.img], -1);
+            dtrip.push_back({dT ? nu * nbf + mu : (int)e, dT ? codeT : code, (int)joff});
+            ptrip.push_back({(int)e, code, (int)joff, sa > sb ? nu * nbf + mu : -1, codeT});
+          }
         }
         std::sort(ents.begin(), ents.end());
         for (size_t i = 0; i < ents.size(); ++i) {
@@ -957,6 +963,32 @@ std::string build_plan(const PlanInput &in, int seg_len, Plan &p) {
       p.eD.push_back(dtrip[i][2]);
     }
     p.sD_e0.push_back((int)p.eD.size());
+    // packed D segments: element = index in the packed order (lightJ, then heavyJ)
+    std::vector<int> pidx((size_t)nbf * nbf, -1);
+    int np = 0;
+    for (const std::vector<int> *v : {&p.lightJ, &p.heavyJ})
+      for (int e : *v) pidx[e] = np++;
+    for (auto &t : ptrip) {
+      const bool tr = t[3] >= 0 && pidx[t[3]] >= 0;
+      t = {pidx[tr ? t[3] : t[0]], tr ? t[4] : t[1], t[2], 0, 0};
+      if (t[0] < 0) return "internal: a D(L) entry outside the J(k) support";
+    }
+    std::sort(ptrip.begin(), ptrip.end());
+    p.sDp_el.clear();
+    p.sDp_code.clear();
+    p.sDp_e0.clear();
+    p.eDp.clear();
+    p.nDp_support = 0;
+    for (size_t i = 0; i < ptrip.size(); ++i) {
+      if (i == 0 || ptrip[i][0] != ptrip[i - 1][0]) ++p.nDp_support;
+      if (i == 0 || ptrip[i][0] != ptrip[i - 1][0] || ptrip[i][1] != ptrip[i - 1][1]) {
+        p.sDp_el.push_back(ptrip[i][0]);
+        p.sDp_code.push_back(ptrip[i][1]);
+        p.sDp_e0.push_back((int)p.eDp.size());
+      }
+      p.eDp.push_back(ptrip[i][2]);
+    }
+    p.sDp_e0.push_back((int)p.eDp.size());
   }
 
   // ---- Hermite -> relative monomial transform per degree:

@@ -108,6 +108,11 @@ struct Plan {
   std::vector<int> eJ;              // per J entry: element offset in Jblk
   std::vector<int> sD_el, sD_code, sD_e0;  // per D segment: element, class code, first entry
   int64_t nD_support = 0;                  // elements with at least one D segment
+  // D side for a packed D(k) (the J(k) support in the packed element order):
+  // the same entries, each read at (mu, nu) with shell(mu) <= shell(nu) so that
+  // the values read from a row are one run at its end; element = packed index
+  std::vector<int> sDp_el, sDp_code, sDp_e0, eDp;
+  int64_t nDp_support = 0;  // packed elements read
   // elements with more than kPhaseLight J classes, summed one wave per element
   // (the others one thread per element)
   std::vector<int> heavyJ;

@@ -26,11 +26,14 @@ PWDF_JK_FULL = 0
 PWDF_JK_SUPPORT = 1
 PWDF_JK_PACKED = 2
 
+PWDF_DK_FULL = 0
+PWDF_DK_PACKED = 1
+
 EXPORTED = ["pwdf_create", "pwdf_query", "pwdf_build_j", "pwdf_build_j_graph", "pwdf_get_rhoG", "pwdf_grad",
             "pwdf_autotune", "pwdf_last_error", "pwdf_destroy", "pwdf_plan_stats",
             "pwdf_profile_enable", "pwdf_profile_read", "pwdf_set_jk_layout", "pwdf_check_input",
             "pwdf_get_jk_support", "pwdf_build_j_noalloc", "pwdf_set_fp32_head", "pwdf_energy_real",
-            "pwdf_debug_fail_alloc", "pwdf_debug_live_allocs"]
+            "pwdf_debug_fail_alloc", "pwdf_debug_live_allocs", "pwdf_set_dk_layout"]
 
 
 class PwdfError(RuntimeError):
@@ -107,6 +110,8 @@ def lib():
         L.pwdf_profile_read.argtypes = [vp, ctypes.POINTER(KProf), ctypes.c_int, ip]
         L.pwdf_set_jk_layout.restype = ctypes.c_int
         L.pwdf_set_jk_layout.argtypes = [vp, ctypes.c_int]
+        L.pwdf_set_dk_layout.restype = ctypes.c_int
+        L.pwdf_set_dk_layout.argtypes = [vp, ctypes.c_int]
         L.pwdf_set_fp32_head.restype = ctypes.c_int
         L.pwdf_set_fp32_head.argtypes = [vp, ctypes.c_double]
         L.pwdf_energy_real.restype = ctypes.c_int
@@ -213,6 +218,13 @@ class LongRangeJ:
         p = self.prob
         if Dk.dtype != torch.complex128 or not Dk.is_cuda or not Dk.is_contiguous():
             raise ValueError("Dk must be a contiguous complex128 CUDA tensor")
+        if getattr(self, "_dk_layout", PWDF_DK_FULL) == PWDF_DK_PACKED:
+            if Dk.dim() == 2:
+                Dk = Dk.unsqueeze(0)
+            ns = self.stats()["jk_support"]
+            if tuple(Dk.shape[1:]) != (p.nk, ns):
+                raise ValueError(f"packed Dk shape {tuple(Dk.shape)} != [ndm, {p.nk}, {ns}]")
+            return Dk
         if Dk.dim() == 3:
             Dk = Dk.unsqueeze(0)
         if tuple(Dk.shape[1:]) != (p.nk, p.nbf, p.nbf):
@@ -235,6 +247,24 @@ class LongRangeJ:
         if rc != 0:
             self._err(rc)
         self._jk_layout = int(layout)
+
+    def set_dk_layout(self, layout: int):
+        """PWDF_DK_FULL (D(k) as [ndm][nk][nbf][nbf]) or PWDF_DK_PACKED (D(k) as
+        [ndm][nk][jk_support], the element order of jk_support(); pack_dk makes it)."""
+        rc = lib().pwdf_set_dk_layout(self._h, int(layout))
+        if rc != 0:
+            self._err(rc)
+        self._dk_layout = int(layout)
+
+    def pack_dk(self, Dk):
+        """[ndm][nk][jk_support] values of a dense [ndm][nk][nbf][nbf] D(k) (a gather
+        on the device, outside the library)."""
+        import torch
+        mu, nu = self.jk_support()
+        p = self.prob
+        idx = torch.from_numpy(mu.astype(np.int64) * p.nbf + nu).to(Dk.device)
+        D = Dk if Dk.dim() == 4 else Dk.unsqueeze(0)
+        return D.reshape(D.shape[0], p.nk, p.nbf * p.nbf).index_select(2, idx).contiguous()
 
     def jk_support(self):
         """(mu, nu) int arrays of the packed J(k) element order."""
@@ -279,9 +309,11 @@ class LongRangeJ:
             if layout == PWDF_JK_PACKED:
                 Jk = torch.empty((ndm, self.prob.nk, self.stats()["jk_support"]), dtype=Dk.dtype, device=Dk.device)
             elif layout == PWDF_JK_SUPPORT:
-                Jk = torch.zeros_like(Dk)
+                Jk = torch.zeros((ndm, self.prob.nk, self.prob.nbf, self.prob.nbf), dtype=Dk.dtype,
+                                 device=Dk.device)
             else:
-                Jk = torch.empty_like(Dk)
+                Jk = torch.empty((ndm, self.prob.nk, self.prob.nbf, self.prob.nbf), dtype=Dk.dtype,
+                                 device=Dk.device)
         if EJ is None:
             EJ = torch.empty(ndm, dtype=torch.float64, device=Dk.device)
         fn = lib().pwdf_build_j_graph if graph else lib().pwdf_build_j
@@ -376,6 +408,8 @@ def _autograd_function():
             got = xyz.detach().to("cpu", torch.float64).numpy()
             if got.shape != ref.shape or not np.array_equal(got, ref):
                 raise ValueError("xyz differs from the geometry of the plan; build a new LongRangeJ")
+            if getattr(plan, "_dk_layout", PWDF_DK_FULL) != PWDF_DK_FULL:
+                raise ValueError("long_range_energy takes a dense D(k): set PWDF_DK_FULL")
             Jk, EJ = plan.build_j(Dk)
             if getattr(plan, "_jk_layout", PWDF_JK_FULL) == PWDF_JK_PACKED:
                 Jk = plan.unpack_jk(Jk)

@@ -2,7 +2,10 @@
 // host: rho_rank is a permutation that maps every class range [L_p0, L_p1) onto
 // itself; hot_rho holds the pair records in that order (bit for bit); the classes
 // L <= 2 are sorted by p (1/(4p) ascending) with ties kept in storage order; the
-// classes L >= 3 keep storage order.  Reads the problem as whitespace-separated
+// classes L >= 3 keep storage order.  The D segments of the packed D(k) layout
+// read every D(L) entry once, as the dense ones do, from the same element or its
+// Hermitian partner with the negated class, always at shell(mu) <= shell(nu), in
+// ascending packed order.  Reads the problem as whitespace-separated
 // text: lattice (9), natm and xyz, nshell and shell atoms, shell l, shell primitive
 // counts, primitive count and exponents, coefficients, kmesh (3), omega, eps_pair,
 // eps_G, r_max, and optionally pair_gcut, alpha_cut, dd_gpw.  Prints "pairs <n>
@@ -91,6 +94,48 @@ int main(int argc, char **argv) {
   }
   for (int r = 0; r < n; ++r)
     if (order[r] < 0) bad++;
+  {
+    // D(L) entry -> (dense element read, class code), for both layouts
+    std::vector<int> pel;
+    for (const std::vector<int> *v : {&p.lightJ, &p.heavyJ}) pel.insert(pel.end(), v->begin(), v->end());
+    const size_t ne = p.eD.size();
+    std::vector<std::pair<int, int>> dn(p.nelem, {-1, -1}), pk(p.nelem, {-1, -1});
+    if (p.eDp.size() != ne || p.sDp_e0.size() != p.sDp_el.size() + 1) bad++;
+    for (size_t s = 0; s + 1 < p.sD_e0.size(); ++s)
+      for (int j = p.sD_e0[s]; j < p.sD_e0[s + 1]; ++j) {
+        if (dn[p.eD[j]].first >= 0) bad++;
+        dn[p.eD[j]] = {p.sD_el[s], p.sD_code[s]};
+      }
+    for (size_t s = 0; s + 1 < p.sDp_e0.size(); ++s) {
+      const int el = p.sDp_el[s];
+      if (el < 0 || el >= (int)pel.size() || (s > 0 && el < p.sDp_el[s - 1])) {
+        bad++;
+        continue;
+      }
+      const int e = pel[el];
+      if (p.bf_shell[e / p.nbf] > p.bf_shell[e % p.nbf]) bad++;
+      for (int j = p.sDp_e0[s]; j < p.sDp_e0[s + 1]; ++j) {
+        if (pk[p.eDp[j]].first >= 0) bad++;
+        pk[p.eDp[j]] = {e, p.sDp_code[s]};
+      }
+    }
+    const int N = p.phN;
+    auto neg = [N](int c) {
+      int r = 0;
+      for (int i = 0; i < 3; ++i) r |= ((N - ((c >> (10 * i)) & 1023)) % N) << (10 * i);
+      return r;
+    };
+    for (int64_t j = 0; j < p.nelem; ++j) {
+      if ((dn[j].first < 0) != (pk[j].first < 0)) {
+        bad++;
+        continue;
+      }
+      if (dn[j].first < 0) continue;
+      const int a = dn[j].first, b = pk[j].first;
+      const int aT = (a % p.nbf) * p.nbf + a / p.nbf;
+      if (!((a == b && dn[j].second == pk[j].second) || (aT == b && neg(dn[j].second) == pk[j].second))) bad++;
+    }
+  }
   if (argc > 2 && std::strcmp(argv[2], "sweep") == 0) {
     std::set<std::tuple<int, int, int>> ref;
     long nvalid = -1;
